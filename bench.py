@@ -1,0 +1,267 @@
+#!/usr/bin/env python3
+"""Benchmark: queries/sec at recall@10 >= 0.9 on one MI355X.
+
+One step = one pass of the whole query path (pad, project + hash, probe,
+schedule, de-duplicated candidate union, exact verification, top-K) over the
+full query workload, with the index built and the queries already resident in
+HBM.  The headline configuration is the 1M-point uint8 workload: n=1,000,000,
+d=128 Gaussian mixture (1,000 components, sigma 20), Q=10,000 noisy data
+points, L=20 layers of k=10 functions, K=10.  Its stated bucket width w=400
+reaches recall@10 of only ~0.13, so the benchmark runs at w_0.9: the smallest w
+on the grid {1, 1.5, 2, 2.5, 3, 4, 6, 8} x 400 whose measured recall@10 (against
+GPU brute force over all points) is >= 0.9; L and k are unchanged.
+
+Reported: the fast form (FP16 MFMA + FP64 guard band, bucket grouping,
+learned-count binning, persistent verify, HIP graph) as `value`; the plain FP32
+form beside it; the verify kernel's achieved HBM bandwidth against the 8 TB/s
+peak; and the CPU oracle timed on a bounded query sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+W_GRID = [1, 1.5, 2, 2.5, 3, 4, 6, 8]
+METRIC = "queries/sec at recall@10>=0.9, BF16+learned vs plain FP32 on 1 MI355X"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def recall_at_10(ids_lsh, ids_true, dist_lsh, dist_true):
+    """Tie-tolerant recall@10: a returned id counts when it is one of the exact
+    top-10 ids or its distance is <= the exact 10th distance."""
+    import numpy as np
+    K = 10
+    hits = 0
+    for q in range(ids_lsh.shape[0]):
+        truth = set(ids_true[q, :K].tolist())
+        d10 = dist_true[q, K - 1]
+        for r in range(K):
+            i = int(ids_lsh[q, r])
+            if i < 0:
+                continue
+            if i in truth or dist_lsh[q, r] <= d10:
+                hits += 1
+    return hits / (K * ids_lsh.shape[0])
+
+
+def verify_source_hash():
+    h = hashlib.sha256()
+    for f in ("qw_verify.hip", "qw_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_1907_11803_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4])
+    ap.add_argument("--w", type=float, default=None, help="bucket width (default: search w_0.9)")
+    ap.add_argument("--train-queries", type=int, default=50_000)
+    ap.add_argument("--cpu-sample", type=int, default=1000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="only the fast-form timed loop (for rocprofv3 runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this engine has no multi-GPU path (queries or data "
+              "would be sharded across GPUs with one gather of Q x K results; see DESIGN.md).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1907_11803_amd import lib, synth
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    lib.load()
+    t0 = time.time()
+    spec = synth.CONFIGS[args.config]
+    wl = synth.make_config(args.config)
+    log(f"[bench] cfg{args.config}: n={wl.n} d={wl.d} Q={wl.Q} L={wl.params.L} "
+        f"k={wl.params.k} generated in {time.time() - t0:.1f}s")
+    data_d = torch.from_numpy(wl.data).to(dev)
+    q_d = torch.from_numpy(wl.queries).to(dev)
+    a_d = torch.from_numpy(wl.params.a).to(dev)
+    K = wl.K
+    is_u8 = wl.data.dtype == np.uint8
+
+    # ---- choose w_0.9 (recall measured on every query against GPU brute force)
+    grid = [args.w] if args.w else [m * spec["w"] for m in W_GRID]
+    truth = None
+    chosen = None
+    tried = []
+    for w in grid:
+        b_d = torch.from_numpy(wl.params.b(w)).to(dev)
+        t1 = time.time()
+        ix = lib.Index(data_d, a_d, b_d, w, form=lib.QW_FORM_FAST)
+        build_s = time.time() - t1
+        if truth is None:
+            t1 = time.time()
+            ti, td = ix.bruteforce(q_d, K)
+            torch.cuda.synchronize()
+            truth = (ti.cpu().numpy(), td.cpu().numpy())
+            log(f"[bench] brute-force ground truth in {time.time() - t1:.1f}s")
+        ids, dist, st = ix.query(q_d, K, lib.make_opts(sched=lib.QW_SCHED_SUM, graph=0), stats=True)
+        rec = recall_at_10(ids.cpu().numpy(), truth[0], dist.cpu().numpy(), truth[1])
+        tried.append({"w": w, "recall_at_10": round(rec, 4),
+                      "mean_unique_candidates": st["cand_unique"] / wl.Q})
+        log(f"[bench] w={w}: recall@10={rec:.4f} unique/q={st['cand_unique'] / wl.Q:.0f} "
+            f"sum/q={st['cand_total'] / wl.Q:.0f} build {build_s:.1f}s")
+        if rec >= 0.9 or w == grid[-1]:
+            chosen = (w, ix, b_d, rec, st)
+            break
+        ix.close()
+    w, ix, b_d, rec, st0 = chosen
+
+    # ---- learned count model, trained on the engine's own features
+    t1 = time.time()
+    train = synth.training_queries(args.config, args.train_queries)
+    train_d = torch.from_numpy(train).to(dev)
+    train_loss = ix.train_count_model(train_d, epochs=8, batch=1024, lr=2e-3, seed=1)
+    del train_d
+    log(f"[bench] count model trained on {args.train_queries} queries, loss {train_loss:.4f} "
+        f"in {time.time() - t1:.1f}s")
+
+    out_ids = torch.empty((wl.Q, K), dtype=torch.int32, device=dev)
+    out_dist = torch.empty((wl.Q, K), dtype=torch.int32 if is_u8 else torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def timed(opts, steps, warmup):
+        for _ in range(warmup):
+            ix.query(q_d, K, opts, out_ids=out_ids, out_dist=out_dist)
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for _ in range(steps):
+            ix.query(q_d, K, opts, out_ids=out_ids, out_dist=out_dist)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        return start.elapsed_time(stop) / steps
+
+    fast_opts = lib.make_opts(form=lib.QW_FORM_FAST, sched=lib.QW_SCHED_LEARNED, group=1, graph=1)
+    if args.profile:
+        ms = timed(fast_opts, args.steps, args.warmup)
+        log(f"[bench] profile loop: {ms:.3f} ms/step")
+        return
+
+    # exactness of the timed forms against each other and the brute-force recall
+    ref_ids, ref_dist = ix.query(q_d, K, lib.make_opts(form=lib.QW_FORM_PLAIN_FP32))
+    ref_ids, ref_dist = ref_ids.cpu().numpy(), ref_dist.cpu().numpy()
+    f_ids, f_dist = ix.query(q_d, K, fast_opts)
+    identical = bool(np.array_equal(f_ids.cpu().numpy(), ref_ids) and
+                     np.array_equal(f_dist.cpu().numpy(), ref_dist))
+
+    # ---- timed regions
+    ms_fast = timed(fast_opts, args.steps, args.warmup)
+    ms_plain = timed(lib.make_opts(form=lib.QW_FORM_PLAIN_FP32), args.steps, args.warmup)
+    sched_ms = {}
+    for name, sc in (("sum", lib.QW_SCHED_SUM), ("actual", lib.QW_SCHED_ACTUAL),
+                     ("none", lib.QW_SCHED_NONE), ("learned", lib.QW_SCHED_LEARNED)):
+        sched_ms[name] = round(timed(lib.make_opts(sched=sc), max(5, args.steps // 2), 2), 4)
+    log(f"[bench] fast {ms_fast:.3f} ms/step, plain {ms_plain:.3f} ms/step, scheds {sched_ms}")
+
+    # ---- per-stage timing of the fast pipeline (events inside the library)
+    stage = np.zeros(8)
+    nrep = 5
+    for _ in range(nrep):
+        _, _, s = ix.query(q_d, K, lib.make_opts(sched=lib.QW_SCHED_LEARNED, timing=1, graph=0),
+                           out_ids=out_ids, out_dist=out_dist, stats=True)
+        stage += np.array(s["ms_stage"])
+    stage /= nrep
+    st = s
+    elem = 1 if is_u8 else 4
+    L = wl.params.L
+    alg_bytes = (wl.Q * wl.d * elem + 8 * L * wl.Q + 4 * st["cand_total"] +
+                 st["cand_unique"] * wl.d * elem + 8 * K * wl.Q)
+    verify_ms = float(stage[3])
+    achieved = alg_bytes / (verify_ms * 1e-3) / 1e9 if verify_ms > 0 else None
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"verify_cfg{args.config}_traffic.json")
+    if os.path.exists(tfile):
+        tj = json.load(open(tfile))
+        if tj.get("verify_source") == verify_source_hash() and abs(tj.get("w", -1) - w) < 1e-9:
+            traffic = tj.get("bytes_per_step")
+
+    # ---- CPU oracle on a bounded sample
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        nthreads = max(1, min(16, os.cpu_count() or 1))
+        t1 = time.time()
+        bi = oracle.BuiltIndex(wl.data, wl.params.a, wl.params.b(w), w, nthreads=nthreads)
+        build_cpu = time.time() - t1
+        rng = np.random.default_rng(7)
+        sample = np.sort(rng.choice(wl.Q, size=min(args.cpu_sample, wl.Q), replace=False))
+        t1 = time.time()
+        o_ids, o_dist, _ = bi.query(wl.queries[sample], K)
+        q_cpu = time.time() - t1
+        bi.close()
+        cpu_match = bool(np.array_equal(o_ids, ref_ids[sample]))
+        cpu = {"value": round(len(sample) / q_cpu, 2), "unit": "queries/s", "cores": nthreads,
+               "kind": "oracle",
+               "sample": f"{len(sample)} of {wl.Q} queries against the full {wl.n}-point index; "
+                         f"oracle index build {build_cpu:.1f}s excluded, query phase {q_cpu:.2f}s",
+               "matches_gpu": cpu_match}
+        log(f"[bench] oracle: {cpu['value']} q/s on {nthreads} threads (build {build_cpu:.1f}s)")
+
+    qps = wl.Q / (ms_fast * 1e-3)
+    line = {
+        "metric": METRIC,
+        "value": round(qps, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_fast, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8" if is_u8 else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"cfg{args.config}: n={wl.n} d={wl.d} {'u8' if is_u8 else 'f32'}, "
+                         f"Q={wl.Q} queries, L={L} k={wl.params.k} w={w} (w_0.9), K={K}"),
+            "n": wl.n, "d": wl.d, "Q": wl.Q, "L": L, "k": wl.params.k, "w": w, "K": K,
+            "projection": "fp16-mfma+fp64-guard" if is_u8 else "fp32-mfma+fp64-guard",
+            "w_search": tried,
+        },
+        "recall_at_10": round(rec, 4),
+        "plain_fp32_qps": round(wl.Q / (ms_plain * 1e-3), 1),
+        "speedup_vs_plain_fp32": round(ms_plain / ms_fast, 3),
+        "forms_identical": identical,
+        "sched_ms_per_step": sched_ms,
+        "stage_ms": {"hash": round(stage[0], 4), "probe": round(stage[1], 4),
+                     "schedule": round(stage[2], 4), "verify": round(stage[3], 4),
+                     "overflow": round(stage[4], 4), "total": round(stage[5], 4)},
+        "recompute_frac": st["recompute_frac"],
+        "cand_per_query": {"sum_of_buckets": st["cand_total"] / wl.Q,
+                           "unique": st["cand_unique"] / wl.Q},
+        "overflow_queries": st["overflow"],
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                     "traffic": traffic, "kernel": "verify_kernel (all size classes of one step)",
+                     "algorithmic_bytes_per_step": int(alg_bytes)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    ix.close()
+
+
+if __name__ == "__main__":
+    main()

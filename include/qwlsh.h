@@ -1,0 +1,246 @@
+/*
+ * qwlsh.h -- C ABI of the MI355X (gfx950) engine for p-stable LSH query
+ * workloads.
+ *
+ * The engine answers a whole workload of Q similarity queries against an index
+ * of L hash layers, each keyed by k concatenated p-stable functions
+ *     h_{a,b}(v) = floor((a.v + b) / w)                  (Section 3; the floor is
+ *                                                          that of the cited
+ *                                                          scheme of Datar et al.)
+ * combined conjunctively inside a layer and disjunctively across layers
+ * (Section 1.1).  Per query it projects and hashes, probes every layer's bucket,
+ * forms the de-duplicated union of the bucket members (the candidates found by
+ * accessing the index, Section 1.2), removes false positives by exact distance
+ * and returns the top-K (the c-k-ANN output of Section 3).  The workload is
+ * processed as a whole (Sections 4 and 5.1): queries that share buckets are
+ * scheduled together so a bucket's ids and points are fetched once and reused.
+ *
+ * Conventions for every entry point:
+ *  - Pointers documented "device" must point to memory of the current HIP
+ *    device; "host" pointers to host memory.  No pointer may be NULL unless
+ *    documented "nullable".
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work is
+ *    enqueued on it; unless documented otherwise, calls return before the GPU
+ *    finishes and outputs are valid once the stream reaches that point.
+ *  - Errors are returned as qw_status; on error, output buffers are left
+ *    untouched and no work is enqueued.  No C++ exception crosses the ABI.
+ *  - An index is not thread-safe: calls on one index must be serialised by the
+ *    caller.  Distinct indexes may be used concurrently.
+ *  - Vectors are row-major, dtype QW_U8 (uint8) or QW_F32 (float32).
+ *  - Distances are SQUARED Euclidean: int32 exact for QW_U8 data, float32 for
+ *    QW_F32 data (the float64 distance of the index-order sum, rounded once).
+ *  - Results are sorted by (distance ascending, id ascending); rows with fewer
+ *    than K candidates are padded with id -1 and distance INT32_MAX (QW_U8) or
+ *    +infinity (QW_F32).
+ */
+#ifndef QWLSH_H
+#define QWLSH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QW_OK = 0,
+    QW_EINVAL = 1,        /* invalid argument (null pointer, bad size, out-of-range value) */
+    QW_ENOMEM = 2,        /* device or host allocation failed */
+    QW_EDEVICE = 3,       /* a HIP runtime call failed */
+    QW_EUNSUPPORTED = 4,  /* valid request the engine cannot serve (e.g. keys wider than 128 bits) */
+    QW_EINTERNAL = 5      /* internal invariant violated */
+} qw_status;
+
+typedef enum { QW_U8 = 0, QW_F32 = 1 } qw_dtype;
+
+/* Execution form.  Both forms return identical results. */
+typedef enum {
+    /* FP32 projections (guard band + FP64 recompute keeps bucket ids exact), one
+     * workgroup per query in workload order, one hash-set size for the whole
+     * workload. */
+    QW_FORM_PLAIN_FP32 = 0,
+    /* FP16 (uint8 data) or FP32 (float data) MFMA projections with an FP64 guard
+     * band; queries grouped by bucket, binned by predicted candidate count and
+     * served by a persistent verify kernel; replayed from a HIP graph. */
+    QW_FORM_FAST = 1
+} qw_form;
+
+/* Where the fast form takes each query's predicted candidate count from. */
+typedef enum {
+    QW_SCHED_SUM = 0,     /* sum of the query's bucket sizes (an upper bound, never overflows) */
+    QW_SCHED_LEARNED = 1, /* the count model (qw_train_count_model / qw_set_count_model) */
+    QW_SCHED_ACTUAL = 2,  /* an extra counting pass gives the exact count */
+    QW_SCHED_NONE = 3     /* no binning: one hash-set size for the whole workload */
+} qw_sched;
+
+typedef struct {
+    int32_t form;      /* qw_form */
+    int32_t sched;     /* qw_sched (fast form only) */
+    int32_t group;     /* fast form: 1 = order queries by bucket key (default), 0 = workload order */
+    int32_t graph;     /* fast form: 1 = capture/replay the query pipeline as a HIP graph */
+    int32_t timing;    /* 1 = record per-stage HIP events and report them in qw_stats (syncs) */
+    int32_t reserved[3];
+} qw_opts;
+
+/* Filled (host memory) by qw_query_workload when non-NULL; the call then
+ * synchronises `stream` before returning. */
+typedef struct {
+    int64_t projections;   /* (query, function) projections computed */
+    int64_t recomputed;    /* of which recomputed in FP64 inside the guard band */
+    double recompute_frac; /* recomputed / projections */
+    int64_t probes_hit;    /* (query, layer) probes that found a bucket */
+    int64_t cand_total;    /* sum over queries and layers of the bucket sizes */
+    int64_t cand_unique;   /* sum over queries of |C(q)| */
+    int64_t overflow;      /* queries re-run because their hash set was sized too small */
+    int64_t bins[8];       /* queries per hash-set size class (fast form) */
+    float ms_stage[8];     /* timing=1: hash, probe, schedule, verify, overflow, total, -, - */
+} qw_stats;
+
+typedef struct {
+    int64_t n;
+    int32_t d, dtype, L, k;
+    float w;
+    int32_t key_bits[64];  /* packed key width of each layer (first min(L,64) layers) */
+    int64_t buckets;       /* total buckets over all layers */
+    int64_t max_bucket;    /* largest bucket size */
+    int64_t device_bytes;  /* device memory held by the index */
+    int32_t has_count_model;
+} qw_index_info;
+
+typedef struct qw_index qw_index;
+
+/* Default options: fast form, learned schedule when a model is loaded (else
+ * the bucket-size sum), grouping on, graph on, timing off. */
+void qw_default_opts(qw_opts *o);
+
+/*
+ * Build the index (Sections 1.1 and 3: L layers of k p-stable functions).
+ *  data  device, n x d row-major, dtype `dtype`; copied into the index, so the
+ *        caller may free it after the call returns.
+ *  a     device, float32 [L][k][d]: the projection vectors a_{l,j}.
+ *  b     device, float32 [L][k]: offsets b_{l,j}, expected in [0, w).
+ *  w     bucket width, finite and > 0.
+ *  o     nullable; selects the projection form used to hash the data (results
+ *        are identical either way).
+ *  out   host; receives the new index (owned by the library; free with
+ *        qw_free_index).
+ * Limits: 1 <= n <= 2^31-1, 1 <= d <= 8192, 1 <= L <= 64, 1 <= k <= 32.
+ * Errors: QW_EINVAL on bad arguments or when |a.v + b| / w can exceed 2^30
+ * (hash values would leave int32); QW_EUNSUPPORTED when a layer's packed key
+ * needs more than 128 bits; QW_ENOMEM; QW_EDEVICE.
+ * Synchronises `stream` before returning.
+ */
+qw_status qw_build_index(const void *data, int64_t n, int32_t d, int32_t dtype,
+                         const float *a, const float *b, float w, int32_t L, int32_t k,
+                         const qw_opts *o, void *stream, qw_index **out);
+
+/*
+ * Answer a query workload: for each of the Q queries, the K nearest candidates.
+ *  queries   device, Q x d row-major, same dtype as the data.
+ *  K         1 <= K <= 1024.
+ *  o         nullable (defaults of qw_default_opts).
+ *  out_ids   device int32 [Q][K].
+ *  out_dist  device [Q][K]: int32 (QW_U8) or float32 (QW_F32).
+ *  st        host, nullable.
+ * Q = 0 is valid and does nothing.  Workspace is owned by the index and grown
+ * on demand (the first call at a new size allocates).
+ */
+qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_t K,
+                            const qw_opts *o, void *stream, int32_t *out_ids, void *out_dist,
+                            qw_stats *st);
+
+/* Release the index and all device memory it holds (NULL is a no-op). */
+void qw_free_index(qw_index *ix);
+
+/* Static string naming a status code. */
+const char *qw_status_string(qw_status s);
+
+/* Index description (host `info`). */
+qw_status qw_get_index_info(const qw_index *ix, qw_index_info *info);
+
+/* ---- introspection (tests and measurements; same ownership rules) ---------- */
+
+/*
+ * Hash values of m vectors: out_h device int32 [m][L*k], function order
+ * (layer, function).  `form` selects the projection path (qw_form).
+ * out_recomputed: host, nullable; receives the number of guard-band recomputes
+ * (the call then synchronises `stream`).
+ */
+qw_status qw_hash(qw_index *ix, const void *x, int64_t m, int32_t form, void *stream,
+                  int32_t *out_h, int64_t *out_recomputed);
+
+/* Bucket size of each (query, layer): out_sizes device int32 [Q][L] (0 = miss). */
+qw_status qw_bucket_sizes(qw_index *ix, const void *queries, int64_t Q, void *stream,
+                          int32_t *out_sizes);
+
+/* |C(q)| of each query: out_counts device int32 [Q]. */
+qw_status qw_candidate_counts(qw_index *ix, const void *queries, int64_t Q, void *stream,
+                              int32_t *out_counts);
+
+/*
+ * Candidate ids of each query, in unspecified order within a query: offsets
+ * device int64 [Q+1] (exclusive prefix sums of qw_candidate_counts), out_ids
+ * device int32 [offsets[Q]].
+ */
+qw_status qw_candidate_lists(qw_index *ix, const void *queries, int64_t Q,
+                             const int64_t *offsets, void *stream, int32_t *out_ids);
+
+/*
+ * Exact kNN of Q queries (device, Q x d) over all n indexed points -- the c-k-ANN
+ * problem with every point a candidate (Section 3); the recall ground truth.
+ * Same output conventions as qw_query_workload; 1 <= K <= 1024.
+ */
+qw_status qw_bruteforce_knn(qw_index *ix, const void *queries, int64_t Q, int32_t K,
+                            void *stream, int32_t *out_ids, void *out_dist);
+
+/* ---- candidate-count model (steers scheduling only, never results) --------
+ *
+ * A two-layer perceptron y = W2 relu(W1 f + b1) + b2 over f_l = log(1 + s_l)
+ * (s_l = the query's bucket size in layer l) predicting log(1 + |C(q)|).  It
+ * plays the part of the paper's offline-trained model that sets resources
+ * from data characteristics (Sections 5.2-5.3).  Parameters are packed float32:
+ * W1 [H][L], b1 [H], W2 [H], b2 [1]  (H*L + 2H + 1 values, H = 64).
+ */
+#define QW_MLP_HIDDEN 64
+
+/* Number of packed parameters for L inputs. */
+int32_t qw_mlp_param_count(int32_t L);
+
+/*
+ * Loss and gradient of one minibatch (mean squared error), FP32 on the GPU.
+ *  params device [P]; feats device float32 [B][L]; targets device float32 [B];
+ *  grad device [P] (overwritten); loss device float32 [1] (overwritten).
+ */
+qw_status qw_mlp_loss_grad(const float *params, int32_t L, const float *feats,
+                           const float *targets, int32_t B, void *stream,
+                           float *grad, float *loss);
+
+/* One Adam step (bias-corrected, step >= 1) on device params / moments m, v. */
+qw_status qw_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t P,
+                      int32_t step, float lr, float beta1, float beta2, float eps,
+                      void *stream);
+
+/* BF16 inference: out device float32 [B] = predicted log(1 + |C(q)|). */
+qw_status qw_mlp_predict_bf16(const float *params, int32_t L, const float *feats, int32_t B,
+                              void *stream, float *out);
+
+/*
+ * Train the index's count model on m training queries (device, m x d): the
+ * engine computes features (bucket sizes) and labels (exact |C(q)|) itself and
+ * runs `epochs` passes of minibatch Adam.  final_loss: host, nullable.
+ * Synchronises `stream`.
+ */
+qw_status qw_train_count_model(qw_index *ix, const void *train_queries, int64_t m,
+                               int32_t epochs, int32_t batch, float lr, uint64_t seed,
+                               void *stream, float *final_loss);
+
+/* Install / read the count model parameters (host float32 [P]). */
+qw_status qw_set_count_model(qw_index *ix, const float *params, int32_t P);
+qw_status qw_get_count_model(const qw_index *ix, float *params, int32_t P);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QWLSH_H */

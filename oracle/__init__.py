@@ -52,7 +52,13 @@ def _load():
         lib.orc_lsh_candidates.argtypes = [P, i64, i32, i32, P, i64, P, P, i32, i32, f64, i32,
                                            P, P, P]
         lib.orc_bruteforce.argtypes = [P, i64, i32, i32, P, i64, i32, i32, P, P, P]
-        for f in (lib.orc_hash, lib.orc_lsh_query, lib.orc_lsh_candidates, lib.orc_bruteforce):
+        lib.orc_lsh_build.argtypes = [P, i64, i32, i32, P, P, i32, i32, f64, i32]
+        lib.orc_lsh_build.restype = ctypes.c_void_p
+        lib.orc_lsh_query_built.argtypes = [P, P, i64, i32, i32, P, P, P, P]
+        lib.orc_lsh_free.argtypes = [P]
+        lib.orc_lsh_free.restype = None
+        for f in (lib.orc_hash, lib.orc_lsh_query, lib.orc_lsh_candidates, lib.orc_bruteforce,
+                  lib.orc_lsh_query_built):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -165,3 +171,49 @@ def bruteforce(data: np.ndarray, queries: np.ndarray, K: int,
     if rc:
         raise ValueError("orc_bruteforce failed (%d)" % rc)
     return ids, dist
+
+
+class BuiltIndex:
+    """The oracle's index built once (hash + per-layer buckets) and queried later;
+    lets the build and query phases be timed separately.  Keeps references to
+    the arrays it was built from."""
+
+    def __init__(self, data, a, b, w, nthreads=None):
+        self.data = np.ascontiguousarray(data)
+        L, k, d = a.shape
+        self.a = np.ascontiguousarray(a, dtype=np.float32)
+        self.b = np.ascontiguousarray(b, dtype=np.float32)
+        self.nthreads = _threads(nthreads)
+        self.h = _load().orc_lsh_build(_ptr(self.data), self.data.shape[0], d,
+                                       _dtype_code(self.data), _ptr(self.a), _ptr(self.b), L, k,
+                                       float(np.float32(w)), self.nthreads)
+        if not self.h:
+            raise ValueError("orc_lsh_build failed")
+
+    def query(self, queries, K):
+        queries = np.ascontiguousarray(queries)
+        Q = queries.shape[0]
+        ids = np.empty((Q, K), dtype=np.int32)
+        cnt = np.empty((Q,), dtype=np.int64)
+        if _dtype_code(self.data) == U8:
+            dist = np.empty((Q, K), dtype=np.int64)
+            pi, pf = _ptr(dist), None
+        else:
+            dist = np.empty((Q, K), dtype=np.float64)
+            pi, pf = None, _ptr(dist)
+        rc = _load().orc_lsh_query_built(ctypes.c_void_p(self.h), _ptr(queries), Q, int(K),
+                                         self.nthreads, _ptr(ids), pi, pf, _ptr(cnt))
+        if rc:
+            raise ValueError("orc_lsh_query_built failed (%d)" % rc)
+        return ids, dist, cnt
+
+    def close(self):
+        if self.h:
+            _load().orc_lsh_free(ctypes.c_void_p(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

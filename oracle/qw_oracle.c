@@ -367,6 +367,57 @@ int orc_lsh_candidates(const void *data, int64_t n, int32_t d, int32_t dtype,
     return rc;
 }
 
+/*
+ * The same workload split into its two phases so they can be timed apart:
+ * orc_lsh_build hashes the data and builds the per-layer buckets (steps 1-3),
+ * orc_lsh_query_built answers queries against it (steps 1 and 4-6).
+ */
+typedef struct {
+    orc_index ix; int32_t *hd; const void *data; int64_t n; int32_t d, dtype, L, k;
+    const float *a, *b; double w;
+} orc_built;
+
+void *orc_lsh_build(const void *data, int64_t n, int32_t d, int32_t dtype, const float *a,
+                    const float *b, int32_t L, int32_t k, double w, int32_t nthreads)
+{
+    if (check_common(data, n, d, data, 0, a, b, L, k, w)) return NULL;
+    orc_built *o = (orc_built *)calloc(1, sizeof(orc_built));
+    if (!o) return NULL;
+    o->hd = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1) * L * k);
+    if (!o->hd || orc_hash(data, n, d, dtype, a, b, L * k, w, nthreads, o->hd) ||
+        index_build(&o->ix, o->hd, n, L, k)) {
+        free(o->hd); free(o->ix.order); free(o);
+        return NULL;
+    }
+    o->data = data; o->n = n; o->d = d; o->dtype = dtype; o->L = L; o->k = k;
+    o->a = a; o->b = b; o->w = w;
+    return o;
+}
+
+int orc_lsh_query_built(void *h, const void *q, int64_t Q, int32_t K, int32_t nthreads,
+                        int32_t *out_ids, int64_t *out_di, double *out_df, int64_t *out_cnt)
+{
+    orc_built *o = (orc_built *)h;
+    if (!o || !q || Q < 0 || K <= 0 || !out_ids) return -1;
+    int32_t *hq = (int32_t *)malloc(sizeof(int32_t) * (size_t)(Q > 0 ? Q : 1) * o->L * o->k);
+    if (!hq) return -5;
+    int rc = orc_hash(q, Q, o->d, o->dtype, o->a, o->b, o->L * o->k, o->w, nthreads, hq);
+    if (!rc) {
+        query_job t = {&o->ix, hq, o->data, q, o->dtype, o->d, Q, K, out_ids, out_di, out_df,
+                       out_cnt, NULL, NULL, 0, 1, 0};
+        rc = run_queries(&t, nthreads);
+    }
+    free(hq);
+    return rc;
+}
+
+void orc_lsh_free(void *h)
+{
+    orc_built *o = (orc_built *)h;
+    if (!o) return;
+    free(o->ix.order); free(o->hd); free(o);
+}
+
 /* Exact kNN over all n points (step 7). */
 int orc_bruteforce(const void *data, int64_t n, int32_t d, int32_t dtype,
                    const void *q, int64_t Q, int32_t K, int32_t nthreads,

@@ -1,0 +1,728 @@
+// C ABI of libqwlsh: argument validation, workspace, and the two execution forms
+// of the query-workload pipeline (hash -> probe -> schedule -> verify/top-K).
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <new>
+#include <random>
+#include <vector>
+
+#include "qw_internal.h"
+
+using namespace qw;
+
+namespace {
+
+// counters buffer: u64 [kC64] then u32 [kC32]
+enum {
+    C_RECOMP = 0, C_UNIQUE, C_PROBEHIT, C_CANDTOT, C_CLASS /* .. C_CLASS+15 */, kC64 = 24
+};
+enum { W_WORK = 0 /* .. 15 */, W_OVFWORK = 16, W_OVF = 17, W_MAX = 18, kC32 = 32 };
+constexpr int kCmin = 10;
+constexpr int kMaxClasses = 16;
+constexpr float kMargin = 1.25f;  // learned schedule: slack on the predicted count
+
+
+inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline unsigned long long *c64(qw_index *ix) { return ix->ws.counters.as<unsigned long long>(); }
+inline uint32_t *c32(qw_index *ix) { return reinterpret_cast<uint32_t *>(c64(ix) + kC64); }
+
+int pow2_at_least(int v)
+{
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+void drop_graphs(qw_index *ix)
+{
+    for (auto &g : ix->graphs) (void)hipGraphExecDestroy(g.second);
+    ix->graphs.clear();
+}
+
+Plan make_plan(qw_index *ix, int K)
+{
+    auto hit = ix->plans.find(K);
+    if (hit != ix->plans.end()) return hit->second;
+    Plan p;
+    p.buf = pow2_at_least(std::max(64, 2 * (K + verify_per_iter(ix->dp, ix->dtype))));
+    int c = kCmin;
+    while (c + 1 < 30 && (int)(c + 1 - kCmin) < kMaxClasses - 1 &&
+           verify_lds_bytes(c + 1, p.buf, 0, ix->L, ix->dp, ix->dtype) <= ix->lds_max)
+        ++c;
+    p.cmax = c;
+    p.ncls = (p.cmax - kCmin + 1) + 1;
+    for (int i = 0; i + 1 < p.ncls; ++i) {
+        const size_t lds = verify_lds_bytes(kCmin + i, p.buf, 0, ix->L, ix->dp, ix->dtype);
+        p.grid[i] = verify_blocks_per_cu(ix->dp, ix->dtype, lds) * ix->cus;
+    }
+    const uint64_t bound = std::min<uint64_t>((uint64_t)ix->L * (uint64_t)std::max<int64_t>(1, ix->max_bucket),
+                                              (uint64_t)ix->n);
+    p.cap_g = std::max(p.cmax + 1, ceil_log2(2 * bound));
+    const double per_wg = 1.5 * std::ldexp(4.0, p.cap_g);
+    const double budget = 2.0 * 1024 * 1024 * 1024;
+    p.grid_g = (int)std::max(1.0, std::min((double)ix->cus, std::floor(budget / per_wg)));
+    p.grid[p.ncls - 1] = p.grid_g;
+    ix->plans[K] = p;
+    return p;
+}
+
+// Grow the query workspace for Q queries; drops captured graphs when any
+// buffer moves.
+qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan)
+{
+    Workspace &w = ix->ws;
+    std::vector<void *> before = {w.qpad.p, w.h.p, w.bstart.p, w.bsize.p, w.qsum.p, w.pred.p,
+                                  w.feats.p, w.keys.p, w.keys2.p, w.vals.p, w.vals2.p,
+                                  w.binoff.p, w.counters.p, w.ovf.p, w.gscratch.p, w.mlpout.p,
+                                  w.hist.p};
+    const size_t elem = ix->dtype == QW_U8 ? 1 : 4;
+    const int64_t q = std::max<int64_t>(Q, 1);
+    QW_TRY(w.qpad.ensure(elem * (size_t)q * ix->dp));
+    QW_TRY(w.h.ensure(sizeof(int32_t) * (size_t)q * ix->nf));
+    QW_TRY(w.bstart.ensure(sizeof(uint32_t) * (size_t)q * ix->L));
+    QW_TRY(w.bsize.ensure(sizeof(uint32_t) * (size_t)q * ix->L));
+    QW_TRY(w.qsum.ensure(sizeof(uint32_t) * q));
+    QW_TRY(w.pred.ensure(sizeof(int32_t) * q));
+    QW_TRY(w.feats.ensure(sizeof(float) * (size_t)q * ix->L));
+    QW_TRY(w.mlpout.ensure(sizeof(float) * q));
+    QW_TRY(w.keys.ensure(sizeof(unsigned long long) * q));
+    QW_TRY(w.keys2.ensure(sizeof(unsigned long long) * q));
+    QW_TRY(w.vals.ensure(sizeof(int32_t) * q));
+    QW_TRY(w.vals2.ensure(sizeof(int32_t) * q));
+    QW_TRY(w.ovf.ensure(sizeof(int32_t) * q));
+    QW_TRY(w.binoff.ensure(sizeof(unsigned long long) * 2 * kMaxClasses));
+    QW_TRY(w.counters.ensure(sizeof(unsigned long long) * kC64 + sizeof(uint32_t) * kC32));
+    QW_TRY(w.hist.ensure(radix_sort_scratch_bytes(q)));
+    if (plan) {
+        const size_t g = (size_t)plan->grid_g * ((size_t(1) << plan->cap_g) * 3 / 2) * 4;
+        QW_TRY(w.gscratch.ensure(g));
+    }
+    std::vector<void *> after = {w.qpad.p, w.h.p, w.bstart.p, w.bsize.p, w.qsum.p, w.pred.p,
+                                 w.feats.p, w.keys.p, w.keys2.p, w.vals.p, w.vals2.p,
+                                 w.binoff.p, w.counters.p, w.ovf.p, w.gscratch.p, w.mlpout.p,
+                                 w.hist.p};
+    if (before != after) drop_graphs(ix);
+    return QW_OK;
+}
+
+VerifyArgs base_args(qw_index *ix, int K, int mode)
+{
+    VerifyArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.bstart = ix->ws.bstart.as<uint32_t>();
+    a.bsize = ix->ws.bsize.as<uint32_t>();
+    a.ids = ix->ids.as<int32_t>();
+    a.n = ix->n;
+    a.L = ix->L;
+    a.d = ix->d;
+    a.dp = ix->dp;
+    a.dtype = ix->dtype;
+    a.K = K;
+    a.mode = mode;
+    a.data = ix->data.p;
+    a.queries = ix->ws.qpad.p;
+    a.ovf_count = c32(ix) + W_OVF;
+    a.ovf_list = ix->ws.ovf.as<int32_t>();
+    return a;
+}
+
+// pad -> hash -> probe for Q queries (counters must already be cleared)
+qw_status front(qw_index *ix, const void *queries, int64_t Q, int form, hipStream_t s,
+                hipEvent_t *ev = nullptr)
+{
+    QW_TRY(launch_pad_rows(queries, Q, ix->d, ix->dp, ix->dtype, ix->ws.qpad.p, s));
+    QW_TRY(launch_hash(ix, ix->ws.qpad.p, Q, 0, ix->nf, form, ix->ws.h.as<int32_t>(), ix->nf,
+                       c64(ix) + C_RECOMP, s));
+    if (ev) QW_HIP(hipEventRecord(ev[1], s));
+    QW_TRY(launch_fill_u32(ix->ws.qsum.as<uint32_t>(), 0u, Q, s));
+    QW_TRY(launch_probe(ix, ix->ws.h.as<int32_t>(), Q, ix->ws.bstart.as<uint32_t>(),
+                        ix->ws.bsize.as<uint32_t>(), ix->ws.qsum.as<uint32_t>(), s));
+    return QW_OK;
+}
+
+qw_status clear_counters(qw_index *ix, hipStream_t s)
+{
+    const int64_t words = (int64_t)(sizeof(unsigned long long) * kC64 + sizeof(uint32_t) * kC32) / 4;
+    return launch_fill_u32(ix->ws.counters.as<uint32_t>(), 0u, words, s);
+}
+
+// One hash-set size for all queries (from the largest bound), one workgroup per
+// query.  Used by the plain form and by the introspection calls.  Syncs.
+qw_status verify_simple(qw_index *ix, int64_t Q, int K, int mode, hipStream_t s,
+                        int32_t *out_ids, void *out_dist, int32_t *out_counts,
+                        const long long *offsets, hipEvent_t ev_sched = nullptr)
+{
+    uint32_t *mx = c32(ix) + W_MAX;
+    QW_TRY(launch_fill_u32(mx, 0u, 1, s));
+    QW_TRY(launch_max_u32(ix->ws.qsum.as<uint32_t>(), Q, mx, s));
+    uint32_t maxsum = 0;
+    QW_HIP(hipMemcpyAsync(&maxsum, mx, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    QW_HIP(hipStreamSynchronize(s));
+    if (ev_sched) QW_HIP(hipEventRecord(ev_sched, s));
+    const uint64_t bound = std::min<uint64_t>(maxsum, (uint64_t)ix->n);
+    int cap = std::max(kCmin, ceil_log2(2 * std::max<uint64_t>(bound, 1)));
+    VerifyArgs a = base_args(ix, K, mode);
+    const int buf = pow2_at_least(std::max(64, 2 * (K + verify_per_iter(ix->dp, ix->dtype))));
+    a.buf = (uint32_t)buf;
+    a.nitems = Q;
+    a.out_ids = out_ids;
+    a.out_dist = out_dist;
+    a.out_counts = out_counts;
+    a.offsets = offsets;
+    a.unique_total = c64(ix) + C_UNIQUE;
+    if (verify_lds_bytes(cap, buf, 0, ix->L, ix->dp, ix->dtype) <= ix->lds_max) {
+        a.cap_log2 = (uint32_t)cap;
+        a.limit = 1u << (cap - 1);
+        return launch_verify(a, (int)Q, s);
+    }
+    // very large candidate sets: hash sets in global scratch, persistent workgroups
+    const int grid = (int)std::min<int64_t>(Q, ix->cus);
+    void *old = ix->ws.gscratch.p;
+    QW_TRY(ix->ws.gscratch.ensure((size_t)grid * ((size_t(1) << cap) * 3 / 2) * 4));
+    if (ix->ws.gscratch.p != old) drop_graphs(ix);  // captured graphs hold the old pointer
+    a.cap_log2 = (uint32_t)cap;
+    a.limit = 1u << (cap - 1);
+    a.global_tab = 1;
+    a.gscratch = ix->ws.gscratch.as<uint32_t>();
+    a.counter = c32(ix) + W_OVFWORK;
+    QW_TRY(launch_fill_u32(a.counter, 0u, 1, s));
+    return launch_verify(a, grid, s);
+}
+
+qw_status check_index(const qw_index *ix)
+{
+    if (!ix) return QW_EINVAL;
+    int dev = -1;
+    QW_HIP(hipGetDevice(&dev));
+    if (dev != ix->device) return QW_EINVAL;
+    return QW_OK;
+}
+
+qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int64_t Q, int K,
+                       const qw_opts &o, hipStream_t s, int32_t *out_ids, void *out_dist,
+                       hipEvent_t *ev)
+{
+    Workspace &w = ix->ws;
+    if (ev) QW_HIP(hipEventRecord(ev[0], s));
+    QW_TRY(clear_counters(ix, s));
+    QW_TRY(front(ix, queries, Q, QW_FORM_FAST, s, ev));
+    if (ev) QW_HIP(hipEventRecord(ev[2], s));
+    const bool learned = o.sched == QW_SCHED_LEARNED && !ix->mlp.empty();
+    const int32_t *exact = nullptr;
+    const float *pred_log = nullptr;
+    unsigned long long *seg = w.binoff.as<unsigned long long>();
+    unsigned long long *ccount = c64(ix) + C_CLASS;
+    auto schedule = [&](const int32_t *ex, const float *pl, int force_max,
+                        const int32_t **order) -> qw_status {
+        QW_TRY(launch_classify(Q, ix->L, ix->n, w.qsum.as<uint32_t>(), w.bstart.as<uint32_t>(),
+                               w.bsize.as<uint32_t>(), ex, pl, kMargin, force_max, kCmin,
+                               plan.cmax, plan.ncls, o.group, w.keys.as<unsigned long long>(),
+                               w.vals.as<int32_t>(), ccount, s));
+        bool alt = false;
+        QW_TRY(radix_sort_pairs(w.keys.as<unsigned long long>(), w.vals.as<int32_t>(), Q,
+                                o.group ? 0 : 24, 32, w.keys2.as<unsigned long long>(),
+                                w.vals2.as<int32_t>(), w.hist, s, &alt));
+        *order = alt ? w.vals2.as<int32_t>() : w.vals.as<int32_t>();
+        QW_TRY(launch_segments(ccount, plan.ncls, seg, s));
+        return QW_OK;
+    };
+    auto run_classes = [&](const int32_t *order, int mode, int32_t *counts) -> qw_status {
+        // global class first (largest queries), then LDS classes from large to small
+        for (int i = plan.ncls - 1; i >= 0; --i) {
+            VerifyArgs a = base_args(ix, K, mode);
+            a.order = order;
+            a.seg = seg + 2 * i;
+            a.counter = c32(ix) + W_WORK + i;
+            a.buf = (uint32_t)plan.buf;
+            a.out_ids = out_ids;
+            a.out_dist = out_dist;
+            a.out_counts = counts;
+            a.unique_total = mode == VM_TOPK ? c64(ix) + C_UNIQUE : nullptr;
+            if (i == plan.ncls - 1) {
+                a.cap_log2 = (uint32_t)plan.cap_g;
+                a.limit = 1u << (plan.cap_g - 1);
+                a.global_tab = 1;
+                a.gscratch = w.gscratch.as<uint32_t>();
+            } else {
+                a.cap_log2 = (uint32_t)(kCmin + i);
+                a.limit = 1u << (kCmin + i - 1);
+            }
+            QW_TRY(launch_verify(a, plan.grid[i], s));
+        }
+        return QW_OK;
+    };
+    const int32_t *order = nullptr;
+    if (o.sched == QW_SCHED_ACTUAL) {
+        QW_TRY(schedule(nullptr, nullptr, 0, &order));
+        QW_TRY(run_classes(order, VM_COUNT, w.pred.as<int32_t>()));
+        QW_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(ccount), 0u, 2 * kMaxClasses, s));
+        QW_TRY(launch_fill_u32(c32(ix) + W_WORK, 0u, kMaxClasses, s));
+        exact = w.pred.as<int32_t>();
+    } else if (learned) {
+        QW_TRY(launch_mlp_features(w.bsize.as<uint32_t>(), Q, ix->L, w.feats.as<float>(), s));
+        QW_TRY(launch_mlp_predict_bf16(ix->mlp_dev.as<float>(), ix->L, w.feats.as<float>(), Q,
+                                       w.mlpout.as<float>(), s));
+        pred_log = w.mlpout.as<float>();
+    }
+    QW_TRY(schedule(exact, pred_log, o.sched == QW_SCHED_NONE, &order));
+    if (ev) QW_HIP(hipEventRecord(ev[3], s));
+    QW_TRY(run_classes(order, VM_TOPK, nullptr));
+    if (ev) QW_HIP(hipEventRecord(ev[4], s));
+    // queries whose hash set was sized too small by the prediction
+    VerifyArgs a = base_args(ix, K, VM_TOPK);
+    a.order = w.ovf.as<int32_t>();
+    a.nitems_dev = c32(ix) + W_OVF;
+    a.counter = c32(ix) + W_OVFWORK;
+    a.buf = (uint32_t)plan.buf;
+    a.cap_log2 = (uint32_t)plan.cap_g;
+    a.limit = 1u << (plan.cap_g - 1);
+    a.global_tab = 1;
+    a.gscratch = w.gscratch.as<uint32_t>();
+    a.out_ids = out_ids;
+    a.out_dist = out_dist;
+    a.unique_total = c64(ix) + C_UNIQUE;
+    a.ovf_count = c32(ix) + W_MAX;  // never used: global sets cannot overflow
+    QW_TRY(launch_verify(a, plan.grid_g, s));
+    if (ev) QW_HIP(hipEventRecord(ev[5], s));
+    return QW_OK;
+}
+
+qw_status fill_stats(qw_index *ix, int64_t Q, hipStream_t s, qw_stats *st, hipEvent_t *ev,
+                     bool fast)
+{
+    std::memset(st, 0, sizeof(*st));
+    if (Q <= 0) return QW_OK;
+    QW_TRY(launch_probe_stats(ix->ws.bsize.as<uint32_t>(), Q * ix->L, c64(ix) + C_PROBEHIT,
+                              c64(ix) + C_CANDTOT, s));
+    unsigned long long h64[kC64];
+    uint32_t h32[kC32];
+    QW_HIP(hipMemcpyAsync(h64, c64(ix), sizeof(h64), hipMemcpyDeviceToHost, s));
+    QW_HIP(hipMemcpyAsync(h32, c32(ix), sizeof(h32), hipMemcpyDeviceToHost, s));
+    QW_HIP(hipStreamSynchronize(s));
+    st->projections = Q * ix->nf;
+    st->recomputed = (int64_t)h64[C_RECOMP];
+    st->recompute_frac = (double)st->recomputed / (double)st->projections;
+    st->probes_hit = (int64_t)h64[C_PROBEHIT];
+    st->cand_total = (int64_t)h64[C_CANDTOT];
+    st->cand_unique = (int64_t)h64[C_UNIQUE];
+    st->overflow = fast ? (int64_t)h32[W_OVF] : 0;
+    if (fast)
+        for (int i = 0; i < 8; ++i) st->bins[i] = (int64_t)h64[C_CLASS + i];
+    if (ev) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) st->ms_stage[0] = ms;
+        if (hipEventElapsedTime(&ms, ev[1], ev[2]) == hipSuccess) st->ms_stage[1] = ms;
+        if (hipEventElapsedTime(&ms, ev[2], ev[3]) == hipSuccess) st->ms_stage[2] = ms;
+        if (hipEventElapsedTime(&ms, ev[3], ev[4]) == hipSuccess) st->ms_stage[3] = ms;
+        if (hipEventElapsedTime(&ms, ev[4], ev[5]) == hipSuccess) st->ms_stage[4] = ms;
+        if (hipEventElapsedTime(&ms, ev[0], ev[5]) == hipSuccess) st->ms_stage[5] = ms;
+        (void)hipGetLastError();
+    }
+    return QW_OK;
+}
+
+qw_status ensure_events(qw_index *ix)
+{
+    if (ix->ev_init) return QW_OK;
+    for (auto &e : ix->ev) QW_HIP(hipEventCreate(&e));
+    ix->ev_init = true;
+    return QW_OK;
+}
+
+qw_status check_vectors(const qw_index *ix, const void *x, int64_t m)
+{
+    if (m < 0 || (m > 0 && !x)) return QW_EINVAL;
+    if (m > INT32_MAX) return QW_EINVAL;
+    (void)ix;
+    return QW_OK;
+}
+
+}  // namespace
+
+// ============================================================================ ABI
+
+extern "C" {
+
+void qw_default_opts(qw_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->form = QW_FORM_FAST;
+    o->sched = QW_SCHED_LEARNED;
+    o->group = 1;
+    o->graph = 1;
+    o->timing = 0;
+}
+
+const char *qw_status_string(qw_status s)
+{
+    switch (s) {
+    case QW_OK: return "ok";
+    case QW_EINVAL: return "invalid argument";
+    case QW_ENOMEM: return "out of memory";
+    case QW_EDEVICE: return "HIP device error";
+    case QW_EUNSUPPORTED: return "unsupported request";
+    case QW_EINTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+qw_status qw_build_index(const void *data, int64_t n, int32_t d, int32_t dtype, const float *a,
+                         const float *b, float w, int32_t L, int32_t k, const qw_opts *o,
+                         void *stream, qw_index **out)
+{
+    if (!data || !a || !b || !out) return QW_EINVAL;
+    if (n < 1 || n > INT32_MAX || d < 1 || d > kMaxD || L < 1 || L > kMaxL || k < 1 || k > kMaxK)
+        return QW_EINVAL;
+    if (dtype != QW_U8 && dtype != QW_F32) return QW_EINVAL;
+    if (!std::isfinite(w) || !(w > 0.f)) return QW_EINVAL;
+    if ((uint64_t)n * (uint64_t)L >= (1ull << 31)) return QW_EUNSUPPORTED;
+    const int form = o ? o->form : QW_FORM_FAST;
+    if (form != QW_FORM_PLAIN_FP32 && form != QW_FORM_FAST) return QW_EINVAL;
+    try {
+        return build_index(data, n, d, dtype, a, b, w, L, k, form, S(stream), out);
+    } catch (const std::bad_alloc &) {
+        return QW_ENOMEM;
+    } catch (...) {
+        return QW_EINTERNAL;
+    }
+}
+
+void qw_free_index(qw_index *ix)
+{
+    if (!ix) return;
+    (void)hipDeviceSynchronize();
+    drop_graphs(ix);
+    if (ix->ev_init)
+        for (auto &e : ix->ev) (void)hipEventDestroy(e);
+    delete ix;
+}
+
+qw_status qw_get_index_info(const qw_index *ix, qw_index_info *info)
+{
+    if (!ix || !info) return QW_EINVAL;
+    std::memset(info, 0, sizeof(*info));
+    info->n = ix->n;
+    info->d = ix->d;
+    info->dtype = ix->dtype;
+    info->L = ix->L;
+    info->k = ix->k;
+    info->w = ix->w;
+    for (int l = 0; l < ix->L && l < 64; ++l) info->key_bits[l] = ix->key_bits[l];
+    info->buckets = ix->buckets;
+    info->max_bucket = ix->max_bucket;
+    const DevBuf *bufs[] = {&ix->a32, &ix->b32, &ix->a_hi, &ix->a_lo, &ix->gb_plain,
+                            &ix->gb_fast, &ix->data, &ix->hmin, &ix->hmax, &ix->shift,
+                            &ix->ids, &ix->tab, &ix->tab_off, &ix->tab_mask, &ix->mlp_dev};
+    for (const DevBuf *b : bufs) info->device_bytes += (int64_t)b->bytes;
+    info->has_count_model = ix->mlp.empty() ? 0 : 1;
+    return QW_OK;
+}
+
+qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_t K,
+                            const qw_opts *o, void *stream, int32_t *out_ids, void *out_dist,
+                            qw_stats *st)
+{
+    QW_TRY(check_index(ix));
+    QW_TRY(check_vectors(ix, queries, Q));
+    if (K < 1 || K > kMaxTopK || (Q > 0 && (!out_ids || !out_dist))) return QW_EINVAL;
+    qw_opts opt;
+    if (o) opt = *o; else qw_default_opts(&opt);
+    if (opt.form != QW_FORM_PLAIN_FP32 && opt.form != QW_FORM_FAST) return QW_EINVAL;
+    if (opt.sched < QW_SCHED_SUM || opt.sched > QW_SCHED_NONE) return QW_EINVAL;
+    if (Q == 0) {
+        if (st) std::memset(st, 0, sizeof(*st));
+        return QW_OK;
+    }
+    hipStream_t s = S(stream);
+    try {
+        if (opt.timing) QW_TRY(ensure_events(ix));
+        if (opt.form == QW_FORM_PLAIN_FP32) {
+            QW_TRY(ensure_ws(ix, Q, nullptr));
+            hipEvent_t *ev = opt.timing ? ix->ev : nullptr;
+            if (ev) QW_HIP(hipEventRecord(ev[0], s));
+            QW_TRY(clear_counters(ix, s));
+            QW_TRY(front(ix, queries, Q, QW_FORM_PLAIN_FP32, s, ev));
+            if (ev) QW_HIP(hipEventRecord(ev[2], s));
+            QW_TRY(verify_simple(ix, Q, K, VM_TOPK, s, out_ids, out_dist, nullptr, nullptr,
+                                 ev ? ev[3] : nullptr));
+            if (ev) {
+                QW_HIP(hipEventRecord(ev[4], s));
+                QW_HIP(hipEventRecord(ev[5], s));
+            }
+            if (st) QW_TRY(fill_stats(ix, Q, s, st, ev, false));
+            return QW_OK;
+        }
+        const Plan plan = make_plan(ix, K);
+        QW_TRY(ensure_ws(ix, Q, &plan));
+        const bool learned = opt.sched == QW_SCHED_LEARNED && !ix->mlp.empty();
+        const int sched = opt.sched == QW_SCHED_LEARNED && !learned ? QW_SCHED_SUM : opt.sched;
+        qw_opts eff = opt;
+        eff.sched = sched;
+        if (opt.timing || !opt.graph) {
+            QW_TRY(enqueue_fast(ix, plan, queries, Q, K, eff, s, out_ids, out_dist,
+                                opt.timing ? ix->ev : nullptr));
+        } else {
+            GraphKey key;
+            std::memset(&key, 0, sizeof(key));
+            key.q = queries; key.Q = Q; key.K = K; key.ids = out_ids; key.dist = out_dist;
+            key.form = eff.form; key.sched = eff.sched; key.group = eff.group;
+            auto it = ix->graphs.find(key);
+            if (it == ix->graphs.end()) {
+                hipStream_t cs;
+                QW_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+                hipGraph_t g = nullptr;
+                qw_status rc = QW_OK;
+                if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+                    (void)hipStreamDestroy(cs);
+                    return QW_EDEVICE;
+                }
+                rc = enqueue_fast(ix, plan, queries, Q, K, eff, cs, out_ids, out_dist, nullptr);
+                hipError_t ec = hipStreamEndCapture(cs, &g);
+                (void)hipStreamDestroy(cs);
+                if (rc != QW_OK) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return rc;
+                }
+                if (ec != hipSuccess || !g) return QW_EDEVICE;
+                hipGraphExec_t ex = nullptr;
+                hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (ei != hipSuccess) return QW_EDEVICE;
+                it = ix->graphs.emplace(key, ex).first;
+            }
+            QW_HIP(hipGraphLaunch(it->second, s));
+        }
+        if (st) QW_TRY(fill_stats(ix, Q, s, st, opt.timing ? ix->ev : nullptr, true));
+        return QW_OK;
+    } catch (const std::bad_alloc &) {
+        return QW_ENOMEM;
+    } catch (...) {
+        return QW_EINTERNAL;
+    }
+}
+
+qw_status qw_hash(qw_index *ix, const void *x, int64_t m, int32_t form, void *stream,
+                  int32_t *out_h, int64_t *out_recomputed)
+{
+    QW_TRY(check_index(ix));
+    QW_TRY(check_vectors(ix, x, m));
+    if (form != QW_FORM_PLAIN_FP32 && form != QW_FORM_FAST) return QW_EINVAL;
+    if (m > 0 && !out_h) return QW_EINVAL;
+    if (m == 0) {
+        if (out_recomputed) *out_recomputed = 0;
+        return QW_OK;
+    }
+    hipStream_t s = S(stream);
+    QW_TRY(ensure_ws(ix, m, nullptr));
+    QW_TRY(clear_counters(ix, s));
+    QW_TRY(launch_pad_rows(x, m, ix->d, ix->dp, ix->dtype, ix->ws.qpad.p, s));
+    QW_TRY(launch_hash(ix, ix->ws.qpad.p, m, 0, ix->nf, form, out_h, ix->nf, c64(ix) + C_RECOMP, s));
+    if (out_recomputed) {
+        unsigned long long r = 0;
+        QW_HIP(hipMemcpyAsync(&r, c64(ix) + C_RECOMP, sizeof(r), hipMemcpyDeviceToHost, s));
+        QW_HIP(hipStreamSynchronize(s));
+        *out_recomputed = (int64_t)r;
+    }
+    return QW_OK;
+}
+
+qw_status qw_bucket_sizes(qw_index *ix, const void *queries, int64_t Q, void *stream,
+                          int32_t *out_sizes)
+{
+    QW_TRY(check_index(ix));
+    QW_TRY(check_vectors(ix, queries, Q));
+    if (Q > 0 && !out_sizes) return QW_EINVAL;
+    if (Q == 0) return QW_OK;
+    hipStream_t s = S(stream);
+    QW_TRY(ensure_ws(ix, Q, nullptr));
+    QW_TRY(clear_counters(ix, s));
+    QW_TRY(front(ix, queries, Q, QW_FORM_FAST, s));
+    QW_HIP(hipMemcpyAsync(out_sizes, ix->ws.bsize.p, sizeof(int32_t) * Q * ix->L,
+                          hipMemcpyDeviceToDevice, s));
+    return QW_OK;
+}
+
+qw_status qw_candidate_counts(qw_index *ix, const void *queries, int64_t Q, void *stream,
+                              int32_t *out_counts)
+{
+    QW_TRY(check_index(ix));
+    QW_TRY(check_vectors(ix, queries, Q));
+    if (Q > 0 && !out_counts) return QW_EINVAL;
+    if (Q == 0) return QW_OK;
+    hipStream_t s = S(stream);
+    QW_TRY(ensure_ws(ix, Q, nullptr));
+    QW_TRY(clear_counters(ix, s));
+    QW_TRY(front(ix, queries, Q, QW_FORM_FAST, s));
+    return verify_simple(ix, Q, 1, VM_COUNT, s, nullptr, nullptr, out_counts, nullptr);
+}
+
+qw_status qw_candidate_lists(qw_index *ix, const void *queries, int64_t Q, const int64_t *offsets,
+                             void *stream, int32_t *out_ids)
+{
+    QW_TRY(check_index(ix));
+    QW_TRY(check_vectors(ix, queries, Q));
+    if (Q > 0 && (!offsets || !out_ids)) return QW_EINVAL;
+    if (Q == 0) return QW_OK;
+    hipStream_t s = S(stream);
+    QW_TRY(ensure_ws(ix, Q, nullptr));
+    QW_TRY(clear_counters(ix, s));
+    QW_TRY(front(ix, queries, Q, QW_FORM_FAST, s));
+    return verify_simple(ix, Q, 1, VM_LIST, s, out_ids, nullptr, nullptr,
+                         reinterpret_cast<const long long *>(offsets));
+}
+
+qw_status qw_bruteforce_knn(qw_index *ix, const void *queries, int64_t Q, int32_t K,
+                            void *stream, int32_t *out_ids, void *out_dist)
+{
+    QW_TRY(check_index(ix));
+    QW_TRY(check_vectors(ix, queries, Q));
+    if (K < 1 || K > kMaxTopK || (Q > 0 && (!out_ids || !out_dist))) return QW_EINVAL;
+    if (Q == 0) return QW_OK;
+    hipStream_t s = S(stream);
+    QW_TRY(ensure_ws(ix, Q, nullptr));
+    QW_TRY(launch_pad_rows(queries, Q, ix->d, ix->dp, ix->dtype, ix->ws.qpad.p, s));
+    VerifyArgs a = base_args(ix, K, VM_ALL);
+    a.L = 0;
+    a.nitems = Q;
+    a.cap_log2 = 1;
+    a.limit = 1;
+    a.buf = (uint32_t)pow2_at_least(std::max(64, 2 * (K + verify_per_iter(ix->dp, ix->dtype))));
+    a.out_ids = out_ids;
+    a.out_dist = out_dist;
+    return launch_verify(a, (int)Q, s);
+}
+
+// ---------------------------------------------------------------- count model
+
+int32_t qw_mlp_param_count(int32_t L) { return QW_MLP_HIDDEN * L + 2 * QW_MLP_HIDDEN + 1; }
+
+qw_status qw_mlp_loss_grad(const float *params, int32_t L, const float *feats,
+                           const float *targets, int32_t B, void *stream, float *grad,
+                           float *loss)
+{
+    if (!params || !feats || !targets || !grad || !loss || L < 1 || L > kMaxL || B < 1)
+        return QW_EINVAL;
+    return launch_mlp_loss_grad(params, L, feats, targets, B, grad, loss, S(stream));
+}
+
+qw_status qw_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t P,
+                      int32_t step, float lr, float beta1, float beta2, float eps, void *stream)
+{
+    if (!params || !grad || !m || !v || P < 1 || step < 1) return QW_EINVAL;
+    if (!(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+        return QW_EINVAL;
+    return launch_mlp_adam(params, grad, m, v, P, step, lr, beta1, beta2, eps, S(stream));
+}
+
+qw_status qw_mlp_predict_bf16(const float *params, int32_t L, const float *feats, int32_t B,
+                              void *stream, float *out)
+{
+    if (!params || !feats || !out || L < 1 || L > kMaxL || B < 0) return QW_EINVAL;
+    return launch_mlp_predict_bf16(params, L, feats, B, out, S(stream));
+}
+
+qw_status qw_set_count_model(qw_index *ix, const float *params, int32_t P)
+{
+    if (!ix || !params || P != qw_mlp_param_count(ix->L)) return QW_EINVAL;
+    for (int32_t i = 0; i < P; ++i)
+        if (!std::isfinite(params[i])) return QW_EINVAL;
+    QW_TRY(ix->mlp_dev.ensure(sizeof(float) * P));
+    QW_HIP(hipMemcpy(ix->mlp_dev.p, params, sizeof(float) * P, hipMemcpyHostToDevice));
+    ix->mlp.assign(params, params + P);
+    drop_graphs(ix);
+    return QW_OK;
+}
+
+qw_status qw_get_count_model(const qw_index *ix, float *params, int32_t P)
+{
+    if (!ix || !params || ix->mlp.empty() || P != (int32_t)ix->mlp.size()) return QW_EINVAL;
+    std::memcpy(params, ix->mlp.data(), sizeof(float) * P);
+    return QW_OK;
+}
+
+qw_status qw_train_count_model(qw_index *ix, const void *train_queries, int64_t m, int32_t epochs,
+                               int32_t batch, float lr, uint64_t seed, void *stream,
+                               float *final_loss)
+{
+    QW_TRY(check_index(ix));
+    QW_TRY(check_vectors(ix, train_queries, m));
+    if (m < 1 || epochs < 1 || batch < 1 || !(lr > 0.f)) return QW_EINVAL;
+    hipStream_t s = S(stream);
+    const int32_t L = ix->L, P = qw_mlp_param_count(L);
+    const int32_t B = (int32_t)std::min<int64_t>(batch, m);
+    try {
+        // features and labels computed by the engine itself
+        QW_TRY(ensure_ws(ix, m, nullptr));
+        QW_TRY(clear_counters(ix, s));
+        QW_TRY(front(ix, train_queries, m, QW_FORM_FAST, s));
+        QW_TRY(verify_simple(ix, m, 1, VM_COUNT, s, nullptr, nullptr, ix->ws.pred.as<int32_t>(),
+                             nullptr));
+        DevBuf feats, labels, perm, fb, tb, params, grad, mom, vel, loss;
+        QW_TRY(feats.ensure(sizeof(float) * (size_t)m * L));
+        QW_TRY(labels.ensure(sizeof(float) * m));
+        QW_TRY(perm.ensure(sizeof(int32_t) * m));
+        QW_TRY(fb.ensure(sizeof(float) * (size_t)B * L));
+        QW_TRY(tb.ensure(sizeof(float) * B));
+        QW_TRY(params.ensure(sizeof(float) * P));
+        QW_TRY(grad.ensure(sizeof(float) * P));
+        QW_TRY(mom.ensure(sizeof(float) * P));
+        QW_TRY(vel.ensure(sizeof(float) * P));
+        const int64_t steps_per_epoch = (m + B - 1) / B;
+        QW_TRY(loss.ensure(sizeof(float) * steps_per_epoch));
+        QW_TRY(launch_mlp_features(ix->ws.bsize.as<uint32_t>(), m, L, feats.as<float>(), s));
+        QW_TRY(launch_labels(ix->ws.pred.as<int32_t>(), m, labels.as<float>(), s));
+        std::vector<float> hl(m);
+        QW_HIP(hipMemcpyAsync(hl.data(), labels.p, sizeof(float) * m, hipMemcpyDeviceToHost, s));
+        QW_HIP(hipStreamSynchronize(s));
+        double mean = 0.0;
+        for (float v : hl) mean += v;
+        mean /= (double)m;
+        // He-style initialisation from the seed
+        std::mt19937_64 rng(seed);
+        std::normal_distribution<double> nd(0.0, 1.0);
+        std::vector<float> p0(P, 0.f);
+        const int H = QW_MLP_HIDDEN;
+        for (int i = 0; i < H * L; ++i) p0[i] = (float)(nd(rng) * std::sqrt(2.0 / L));
+        for (int i = 0; i < H; ++i) p0[H * L + i] = 0.01f;
+        for (int i = 0; i < H; ++i) p0[H * L + H + i] = (float)(nd(rng) * std::sqrt(1.0 / H));
+        p0[P - 1] = (float)mean;
+        QW_HIP(hipMemcpyAsync(params.p, p0.data(), sizeof(float) * P, hipMemcpyHostToDevice, s));
+        QW_TRY(launch_fill_u32(mom.as<uint32_t>(), 0u, P, s));
+        QW_TRY(launch_fill_u32(vel.as<uint32_t>(), 0u, P, s));
+        std::vector<int32_t> order(m);
+        for (int64_t i = 0; i < m; ++i) order[i] = (int32_t)i;
+        int32_t step = 0;
+        std::vector<float> hloss(steps_per_epoch);
+        for (int32_t e = 0; e < epochs; ++e) {
+            std::shuffle(order.begin(), order.end(), rng);
+            QW_HIP(hipMemcpyAsync(perm.p, order.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, s));
+            int64_t st_i = 0;
+            for (int64_t off = 0; off + B <= m; off += B, ++st_i) {
+                QW_TRY(launch_gather_batch(feats.as<float>(), labels.as<float>(),
+                                           perm.as<int32_t>() + off, L, B, fb.as<float>(),
+                                           tb.as<float>(), s));
+                QW_TRY(launch_mlp_loss_grad(params.as<float>(), L, fb.as<float>(), tb.as<float>(),
+                                            B, grad.as<float>(), loss.as<float>() + st_i, s));
+                QW_TRY(launch_mlp_adam(params.as<float>(), grad.as<float>(), mom.as<float>(),
+                                       vel.as<float>(), P, ++step, lr, 0.9f, 0.999f, 1e-8f, s));
+            }
+            QW_HIP(hipStreamSynchronize(s));  // the host permutation buffer is reused
+            if (e == epochs - 1 && st_i > 0) {
+                QW_HIP(hipMemcpy(hloss.data(), loss.p, sizeof(float) * st_i, hipMemcpyDeviceToHost));
+                double acc = 0.0;
+                for (int64_t i = 0; i < st_i; ++i) acc += hloss[i];
+                if (final_loss) *final_loss = (float)(acc / (double)st_i);
+            }
+        }
+        std::vector<float> hp(P);
+        QW_HIP(hipMemcpy(hp.data(), params.p, sizeof(float) * P, hipMemcpyDeviceToHost));
+        return qw_set_count_model(ix, hp.data(), P);
+    } catch (const std::bad_alloc &) {
+        return QW_ENOMEM;
+    }
+}
+
+}  // extern "C"

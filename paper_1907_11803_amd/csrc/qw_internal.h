@@ -1,0 +1,237 @@
+// Internal declarations shared by the HIP translation units of libqwlsh.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/qwlsh.h"
+
+namespace qw {
+
+constexpr int kBlock = 256;              // threads per workgroup for every kernel here
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // empty hash-set slot
+constexpr int kMaxL = 64;
+constexpr int kMaxK = 32;
+constexpr int kMaxTopK = 1024;
+constexpr int kMaxD = 8192;
+
+// ---------------------------------------------------------------- status plumbing
+#define QW_TRY(expr)                          \
+    do {                                      \
+        qw_status s_ = (expr);                \
+        if (s_ != QW_OK) return s_;           \
+    } while (0)
+
+#define QW_HIP(expr)                                          \
+    do {                                                      \
+        hipError_t e_ = (expr);                               \
+        if (e_ != hipSuccess) {                               \
+            ::qw::note_hip_error(e_, #expr, __FILE__, __LINE__); \
+            return QW_EDEVICE;                                \
+        }                                                     \
+    } while (0)
+
+void note_hip_error(hipError_t e, const char *what, const char *file, int line);
+
+// ---------------------------------------------------------------- device buffers
+// A device allocation owned by the library.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    ~DevBuf() { release(); }
+    qw_status ensure(size_t want);  // grows (contents discarded); never shrinks
+    void release();
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// ---------------------------------------------------------------- index
+// Probe-table entry: a bucket of one layer, keyed by its packed k-tuple.
+struct TabEntry {
+    uint64_t klo, khi;
+    uint32_t start, size;  // CSR range of the bucket; size == 0 marks an empty slot
+};
+
+struct Workspace {
+    DevBuf qpad, h, bstart, bsize, qsum, pred, feats, keys, keys2, vals, vals2, hist,
+        order, binoff, counters, ovf, gscratch, mlpout, scan;
+};
+
+// Launch plan of the fast form for one top-K size: hash-set size classes and
+// persistent grid sizes.
+struct Plan {
+    int buf = 64;
+    int cmax = 10;      // largest LDS class (log2 capacity)
+    int ncls = 2;       // LDS classes + 1 global class
+    int grid[16] = {};
+    int cap_g = 20, grid_g = 1;
+};
+
+struct GraphKey {
+    const void *q; int64_t Q; int32_t K; int32_t *ids; void *dist;
+    int32_t form, sched, group;
+    bool operator<(const GraphKey &o) const {
+        return std::memcmp(this, &o, sizeof(GraphKey)) < 0;
+    }
+};
+
+}  // namespace qw
+
+struct qw_index {
+    int device = 0;
+    int cus = 256;
+    size_t lds_max = 65536;
+    int64_t n = 0;
+    int32_t d = 0, dp = 0, dtype = 0, L = 0, k = 0, nf = 0, nf_pad = 0;
+    float w = 0.f;
+    // hash parameters (device)
+    qw::DevBuf a32;      // float [nf_pad][dp], zero padded
+    qw::DevBuf b32;      // float [nf]
+    qw::DevBuf a_hi;     // _Float16 [nf_pad][dp]  (uint8 data, MFMA path)
+    qw::DevBuf a_lo;     // _Float16 [nf_pad][dp]
+    qw::DevBuf gb_plain; // double [nf]: guard-band coefficient of the FP32 VALU path
+    qw::DevBuf gb_fast;  // double [nf]: guard-band coefficient of the MFMA path
+    bool fast_f16 = true;  // uint8 data with |a| < 2^15 uses the FP16 hi/lo split
+    // data copy, rows padded to dp elements
+    qw::DevBuf data;
+    // key packing per function
+    qw::DevBuf hmin, hmax, shift;  // int32 [nf]
+    std::vector<int32_t> key_bits;  // per layer
+    // CSR ids [L][n] and probe tables
+    qw::DevBuf ids;
+    qw::DevBuf tab;        // TabEntry, all layers concatenated
+    qw::DevBuf tab_off;    // int64 [L] first entry of each layer
+    qw::DevBuf tab_mask;   // uint32 [L]
+    int64_t buckets = 0, max_bucket = 0;
+    // count model
+    std::vector<float> mlp;  // packed host copy (empty = none)
+    qw::DevBuf mlp_dev;
+    // query workspace and captured graphs
+    qw::Workspace ws;
+    std::map<qw::GraphKey, hipGraphExec_t> graphs;
+    std::map<int, qw::Plan> plans;  // by K
+    hipEvent_t ev[8] = {};
+    bool ev_init = false;
+};
+
+namespace qw {
+
+// ---------------------------------------------------------------- kernels (launch wrappers)
+// Copy m rows of d elements into rows of dp elements (zero padding).
+qw_status launch_pad_rows(const void *src, int64_t m, int32_t d, int32_t dp, int32_t dtype,
+                          void *dst, hipStream_t s);
+
+// Hash m padded rows for functions [f0, f0+nfun): out[row][f - f0] (row stride out_ld).
+// form 0: FP32 VALU, form 1: MFMA.  recomputed: device counter (nullable).
+qw_status launch_hash(const qw_index *ix, const void *xpad, int64_t m, int32_t f0, int32_t nfun,
+                      int32_t form, int32_t *out, int32_t out_ld,
+                      unsigned long long *recomputed, hipStream_t s);
+
+// Probe every (query, layer): bstart/bsize [Q][L] (bsize 0 = miss); qsum[q] = sum of sizes.
+qw_status launch_probe(const qw_index *ix, const int32_t *h, int64_t Q, uint32_t *bstart,
+                       uint32_t *bsize, uint32_t *qsum, hipStream_t s);
+
+// Generic fills.
+qw_status launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s);
+qw_status launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t count,
+                          hipStream_t s);
+qw_status launch_iota(int32_t *p, int64_t count, hipStream_t s);
+
+// Exclusive prefix sum of count uint32 values into uint64 out (out has count+1 entries).
+qw_status launch_scan_u32_to_u64(const uint32_t *in, int64_t count, unsigned long long *out,
+                                 DevBuf &scratch, hipStream_t s);
+
+// Scratch bytes radix_sort_pairs needs for `count` pairs.
+size_t radix_sort_scratch_bytes(int64_t count);
+// Stable LSD radix sort of (key, value) pairs on key bits [bit_lo, bits).
+qw_status radix_sort_pairs(unsigned long long *keys, int32_t *vals, int64_t count, int bit_lo,
+                           int bits,
+                           unsigned long long *keys_alt, int32_t *vals_alt, DevBuf &hist,
+                           hipStream_t s, bool *result_in_alt);
+
+// ---------------------------------------------------------------- verify kernel
+// TOPK: top-K of the LSH candidates; COUNT: |C(q)| only; LIST: the candidate ids;
+// ALL: top-K over every indexed point (exact kNN, no dedup phase).
+enum VerifyMode { VM_TOPK = 0, VM_COUNT = 1, VM_LIST = 2, VM_ALL = 3 };
+
+struct VerifyArgs {
+    const int32_t *order;        // item -> query (nullable: identity)
+    const unsigned long long *seg;  // nullable: {begin, end} of the items this launch serves
+    int64_t nitems;              // used when seg == nullptr and nitems_dev == nullptr
+    const uint32_t *nitems_dev;  // nullable: item count read from device memory
+    uint32_t *counter;           // persistent work counter (nullable = one item per workgroup)
+    const uint32_t *bstart, *bsize;
+    const int32_t *ids;
+    int64_t n;
+    int32_t L, d, dp, dtype, K, mode;
+    const void *data, *queries;
+    uint32_t cap_log2;           // hash-set capacity 2^cap_log2
+    uint32_t limit;              // abort when more unique ids than this (overflow)
+    uint32_t buf;                // top-K buffer entries (power of two)
+    int32_t global_tab;          // 1: hash set in global scratch
+    uint32_t *gscratch;          // global scratch (global_tab)
+    uint32_t *ovf_count;         // overflow queue
+    int32_t *ovf_list;
+    int32_t *out_ids;            // TOPK: [Q][K]; LIST: concatenated lists
+    void *out_dist;              // TOPK
+    int32_t *out_counts;         // COUNT
+    const long long *offsets;    // LIST
+    unsigned long long *unique_total;  // nullable stats counter
+};
+
+size_t verify_lds_bytes(int cap_log2, int buf, int global_tab, int L, int dp, int dtype);
+qw_status launch_verify(const VerifyArgs &a, int grid, hipStream_t s);
+// Candidates processed per workgroup iteration (sizes the top-K buffer).
+int verify_per_iter(int dp, int dtype);
+// Resident workgroups per CU of the verify kernel with `lds` bytes of LDS.
+int verify_blocks_per_cu(int dp, int dtype, size_t lds);
+
+// ---------------------------------------------------------------- scheduling
+qw_status launch_classify(int64_t Q, int32_t L, int64_t n, const uint32_t *qsum,
+                          const uint32_t *bstart, const uint32_t *bsize, const int32_t *exact,
+                          const float *pred_log, float margin, int32_t force_max, int32_t cmin,
+                          int32_t cmax, int32_t ncls, int32_t group, unsigned long long *keys,
+                          int32_t *vals, unsigned long long *class_count, hipStream_t s);
+qw_status launch_segments(const unsigned long long *class_count, int32_t ncls,
+                          unsigned long long *seg, hipStream_t s);
+qw_status launch_max_u32(const uint32_t *v, int64_t count, uint32_t *out, hipStream_t s);
+qw_status launch_probe_stats(const uint32_t *bsize, int64_t count, unsigned long long *hits,
+                             unsigned long long *total, hipStream_t s);
+qw_status launch_gather_batch(const float *feats, const float *labels, const int32_t *perm,
+                              int32_t L, int32_t B, float *fb, float *tb, hipStream_t s);
+qw_status launch_labels(const int32_t *counts, int64_t m, float *out, hipStream_t s);
+
+// ---------------------------------------------------------------- build
+qw_status build_index(const void *data, int64_t n, int32_t d, int32_t dtype, const float *a,
+                      const float *b, float w, int32_t L, int32_t k, int32_t form,
+                      hipStream_t s, qw_index **out);
+
+// ---------------------------------------------------------------- model
+qw_status launch_mlp_features(const uint32_t *bsize, int64_t Q, int32_t L, float *feats,
+                              hipStream_t s);
+qw_status launch_mlp_predict_bf16(const float *params, int32_t L, const float *feats,
+                                  int64_t B, float *out, hipStream_t s);
+qw_status launch_mlp_loss_grad(const float *params, int32_t L, const float *feats,
+                               const float *targets, int32_t B, float *grad, float *loss,
+                               hipStream_t s);
+qw_status launch_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t P,
+                          int32_t step, float lr, float b1, float b2, float eps,
+                          hipStream_t s);
+
+// ---------------------------------------------------------------- misc
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int ceil_log2(uint64_t v) {
+    int r = 0;
+    while ((1ull << r) < v) ++r;
+    return r;
+}
+
+}  // namespace qw

@@ -1,0 +1,188 @@
+// Workload scheduling kernels: hash-set size classes, bucket grouping keys,
+// class segments and statistics.
+//
+// Queries of a workload that fall in the same bucket are processed back to
+// back (the sort key groups them by the bucket of their first non-empty
+// layer), so the bucket's ids and points are fetched from HBM once and then
+// served from L2 / the Infinity Cache -- the GPU counterpart of keeping reused
+// index files and data objects in the cache (Sections 4 and 5.1).
+#include "qw_internal.h"
+
+namespace qw {
+
+__device__ inline uint32_t mix32(uint64_t x)
+{
+    x ^= x >> 33;
+    x *= 0xFF51AFD7ED558CCDull;
+    x ^= x >> 33;
+    x *= 0xC4CEB9FE1A85EC53ull;
+    x ^= x >> 33;
+    return (uint32_t)x;
+}
+
+// Size class of every query from its predicted number of unique candidates:
+// 2^c >= 2 * need, c >= cmin.  Classes 0 .. ncls-2 are LDS classes
+// (c = cmin + class), class ncls-1 holds the hash set in global memory.
+__global__ void classify_kernel(int64_t Q, int32_t L, int64_t n, const uint32_t *__restrict__ qsum,
+                                const uint32_t *__restrict__ bstart,
+                                const uint32_t *__restrict__ bsize,
+                                const int32_t *__restrict__ exact, const float *__restrict__ pred_log,
+                                float margin, int32_t force_max, int32_t cmin, int32_t cmax,
+                                int32_t ncls, int32_t group, unsigned long long *__restrict__ keys,
+                                int32_t *__restrict__ vals, unsigned long long *class_count)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < Q;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t bound = min((uint64_t)qsum[q], (uint64_t)n);
+        uint64_t need = bound;
+        if (exact) {
+            need = min(need, (uint64_t)exact[q]);
+        } else if (pred_log) {
+            const float p = expm1f(pred_log[q]) * margin + 32.f;
+            if (p == p && p < (float)need) need = p > 0.f ? (uint64_t)ceilf(p) : 0;
+        }
+        int c = cmin;
+        while (c < 40 && (1ull << c) < 2 * need) ++c;
+        if (force_max && c <= cmax) c = cmax;
+        const int cls = c <= cmax ? c - cmin : ncls - 1;
+        uint32_t g = 0;
+        if (group) {
+            for (int32_t l = 0; l < L; ++l) {
+                const uint32_t sz = bsize[q * L + l];
+                if (sz) {
+                    g = mix32(((uint64_t)l << 32) | bstart[q * L + l]) & 0xFFFFFFu;
+                    break;
+                }
+            }
+        }
+        keys[q] = ((unsigned long long)cls << 24) | g;
+        vals[q] = (int32_t)q;
+        atomicAdd(&class_count[cls], 1ull);
+    }
+}
+
+qw_status launch_classify(int64_t Q, int32_t L, int64_t n, const uint32_t *qsum,
+                          const uint32_t *bstart, const uint32_t *bsize, const int32_t *exact,
+                          const float *pred_log, float margin, int32_t force_max, int32_t cmin,
+                          int32_t cmax, int32_t ncls, int32_t group, unsigned long long *keys,
+                          int32_t *vals, unsigned long long *class_count, hipStream_t s)
+{
+    if (Q <= 0) return QW_OK;
+    int g = (int)std::min<int64_t>(4096, ceil_div(Q, kBlock));
+    classify_kernel<<<g, kBlock, 0, s>>>(Q, L, n, qsum, bstart, bsize, exact, pred_log, margin,
+                                         force_max, cmin, cmax, ncls, group, keys, vals,
+                                         class_count);
+    QW_HIP(hipGetLastError());
+    return QW_OK;
+}
+
+// seg[2c], seg[2c+1] = [begin, end) of class c in the class-sorted order.
+__global__ void segments_kernel(const unsigned long long *class_count, int32_t ncls,
+                                unsigned long long *seg)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    unsigned long long off = 0;
+    for (int c = 0; c < ncls; ++c) {
+        seg[2 * c] = off;
+        off += class_count[c];
+        seg[2 * c + 1] = off;
+    }
+}
+
+qw_status launch_segments(const unsigned long long *class_count, int32_t ncls,
+                          unsigned long long *seg, hipStream_t s)
+{
+    segments_kernel<<<1, 64, 0, s>>>(class_count, ncls, seg);
+    QW_HIP(hipGetLastError());
+    return QW_OK;
+}
+
+__global__ void max_u32_kernel(const uint32_t *__restrict__ v, int64_t count, uint32_t *out)
+{
+    uint32_t m = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, v[i]);
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+}
+
+qw_status launch_max_u32(const uint32_t *v, int64_t count, uint32_t *out, hipStream_t s)
+{
+    if (count <= 0) return QW_OK;
+    int g = (int)std::min<int64_t>(1024, ceil_div(count, kBlock));
+    max_u32_kernel<<<g, kBlock, 0, s>>>(v, count, out);
+    QW_HIP(hipGetLastError());
+    return QW_OK;
+}
+
+// probes that hit a bucket, and the total of the bucket sizes
+__global__ void probe_stats_kernel(const uint32_t *__restrict__ bsize, int64_t count,
+                                   unsigned long long *hits, unsigned long long *total)
+{
+    unsigned long long h = 0, t = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = bsize[i];
+        h += v ? 1 : 0;
+        t += v;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        h += __shfl_xor(h, off);
+        t += __shfl_xor(t, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(hits, h);
+        atomicAdd(total, t);
+    }
+}
+
+qw_status launch_probe_stats(const uint32_t *bsize, int64_t count, unsigned long long *hits,
+                             unsigned long long *total, hipStream_t s)
+{
+    if (count <= 0) return QW_OK;
+    int g = (int)std::min<int64_t>(1024, ceil_div(count, kBlock));
+    probe_stats_kernel<<<g, kBlock, 0, s>>>(bsize, count, hits, total);
+    QW_HIP(hipGetLastError());
+    return QW_OK;
+}
+
+// Training minibatch gather and labels.
+__global__ void gather_batch_kernel(const float *__restrict__ feats, const float *__restrict__ labels,
+                                    const int32_t *__restrict__ perm, int32_t L, int32_t B,
+                                    float *__restrict__ fb, float *__restrict__ tb)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < B * L; i += gridDim.x * blockDim.x) {
+        const int s = i / L, l = i - s * L;
+        fb[i] = feats[(int64_t)perm[s] * L + l];
+        if (l == 0) tb[s] = labels[perm[s]];
+    }
+}
+
+qw_status launch_gather_batch(const float *feats, const float *labels, const int32_t *perm,
+                              int32_t L, int32_t B, float *fb, float *tb, hipStream_t s)
+{
+    if (B <= 0) return QW_OK;
+    gather_batch_kernel<<<(unsigned)ceil_div((int64_t)B * L, kBlock), kBlock, 0, s>>>(
+        feats, labels, perm, L, B, fb, tb);
+    QW_HIP(hipGetLastError());
+    return QW_OK;
+}
+
+__global__ void labels_kernel(const int32_t *__restrict__ counts, int64_t m, float *__restrict__ out)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = log1pf((float)counts[i]);
+}
+
+qw_status launch_labels(const int32_t *counts, int64_t m, float *out, hipStream_t s)
+{
+    if (m <= 0) return QW_OK;
+    int g = (int)std::min<int64_t>(4096, ceil_div(m, kBlock));
+    labels_kernel<<<g, kBlock, 0, s>>>(counts, m, out);
+    QW_HIP(hipGetLastError());
+    return QW_OK;
+}
+
+}  // namespace qw

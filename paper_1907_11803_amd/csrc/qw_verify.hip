@@ -1,0 +1,488 @@
+// Candidate union, verification and top-K for one query per workgroup.
+//
+// For query q the candidates are C(q) = the union over layers l of the bucket
+// members ids_l[start_{q,l} .. start_{q,l} + s_{q,l}) (the index accessed to find
+// candidates, Sections 1.2 and 5.1).  Each candidate is verified by its exact
+// squared Euclidean distance (the false-positive removal of Section 1.2) and the
+// K smallest by (distance, id) are returned (the c-k-ANN output, Section 3).
+//
+// Phase 1 (dedup): the workgroup streams the concatenated bucket id lists
+//   (coalesced) and inserts every id into an open-addressing hash set (LDS, or
+//   global scratch for very large queries).  The lane that claims a slot owns a
+//   new candidate; a wavefront ballot compacts new ids into a dense list with
+//   one LDS atomic per wave.
+// Phase 2 (verify): groups of G lanes gather candidate rows (16 bytes per lane
+//   per load, several candidates in flight per lane) and reduce the distance
+//   across the group.  uint8 rows: exact int32 via dot4 (|x|^2 - 2 x.q + |q|^2).
+//   float rows: FP32 with a proven relative error bound eps.
+// Phase 3 (top-K): group leaders append (distance, id) entries under a
+//   threshold to an LDS buffer; a bitonic sort keeps the K best whenever it
+//   fills.  For float data every entry kept is first re-ranked by its FP64
+//   index-order distance, and the admission threshold is the K-th FP64 distance
+//   times (1 + eps), so no candidate of the exact top-K is ever rejected.
+#include "qw_internal.h"
+
+namespace qw {
+
+struct TopEntry {
+    unsigned long long pri;  // u8: distance; f32: FP32 bits (unranked) / FP64 bits (ranked)
+    uint32_t id;
+    uint32_t flag;           // 1 = unranked FP32 entry
+};
+
+enum { S_ITEM = 0, S_UCOUNT, S_OVF, S_BUFCOUNT, S_THR, S_QQ, S_T, S_CAP, S_NSCAL = 16 };
+
+__host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
+
+struct LdsLayout {
+    size_t buf, q, tab, list, lpref, lstart, scal, total;
+};
+
+__host__ __device__ inline LdsLayout lds_layout(int cap_log2, int buf, int global_tab, int L,
+                                                int dp, int dtype)
+{
+    LdsLayout o;
+    const size_t cap = size_t(1) << cap_log2;
+    o.buf = 0;
+    o.q = o.buf + align16(size_t(buf) * sizeof(TopEntry));
+    o.tab = o.q + align16(size_t(dp) * (dtype == QW_U8 ? 1 : 4));
+    o.list = o.tab + (global_tab ? 0 : cap * 4);
+    o.lpref = o.list + (global_tab ? 0 : (cap / 2) * 4);
+    o.lstart = o.lpref + align16(size_t(L + 1) * 4);
+    o.scal = o.lstart + align16(size_t(L) * 4);
+    o.total = o.scal + S_NSCAL * 4;
+    return o;
+}
+
+size_t verify_lds_bytes(int cap_log2, int buf, int global_tab, int L, int dp, int dtype)
+{
+    return lds_layout(cap_log2, buf, global_tab, L, dp, dtype).total;
+}
+
+__device__ inline bool entry_less(const TopEntry &a, const TopEntry &b)
+{
+    return a.pri < b.pri || (a.pri == b.pri && a.id < b.id);
+}
+
+// FP64 index-order squared distance (the reference sequence; no contraction).
+__device__ __noinline__ double exact_dist_f32(const float *__restrict__ x, const float *q, int32_t d)
+{
+    double acc = 0.0;
+    for (int32_t i = 0; i < d; ++i) {
+        double t = __dsub_rn((double)x[i], (double)q[i]);
+        acc = __dadd_rn(acc, __dmul_rn(t, t));
+    }
+    return acc;
+}
+
+__device__ inline uint32_t hash_id(uint32_t id, int cap_log2)
+{
+    return (id * 0x9E3779B1u) >> (32 - cap_log2);
+}
+
+enum { INS_NEW = 0, INS_DUP = 1, INS_FULL = 2 };
+
+__device__ inline int set_insert(uint32_t *tab, int cap_log2, uint32_t id)
+{
+    const uint32_t mask = (1u << cap_log2) - 1u;
+    uint32_t slot = cap_log2 ? hash_id(id, cap_log2) : 0u;
+    for (uint32_t it = 0; it <= mask; ++it) {
+        uint32_t old = atomicCAS(&tab[slot], kEmpty, id);
+        if (old == kEmpty) return INS_NEW;
+        if (old == id) return INS_DUP;
+        slot = (slot + 1) & mask;
+    }
+    return INS_FULL;
+}
+
+// Compact the top-K buffer: rank unranked float entries in FP64, sort, keep K,
+// update the admission threshold.  Called by the whole workgroup.
+template <int DT>
+__device__ void topk_compact(TopEntry *buf, uint32_t *scal, int nbuf, int K,
+                             const void *data, int32_t dp, int32_t d, const float *qrow, float eps)
+{
+    __syncthreads();
+    const int n_e = (int)scal[S_BUFCOUNT];
+    if (DT == QW_F32) {
+        for (int e = threadIdx.x; e < n_e; e += kBlock) {
+            if (buf[e].flag) {
+                const float *x = (const float *)data + (int64_t)buf[e].id * dp;
+                double D = exact_dist_f32(x, qrow, d);
+                buf[e].pri = (unsigned long long)__double_as_longlong(D);
+                buf[e].flag = 0;
+            }
+        }
+    }
+    for (int e = n_e + threadIdx.x; e < nbuf; e += kBlock) {
+        buf[e].pri = ~0ull;
+        buf[e].id = 0xFFFFFFFFu;
+        buf[e].flag = 0;
+    }
+    __syncthreads();
+    for (int size = 2; size <= nbuf; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < nbuf / 2; i += kBlock) {
+                const int lo = 2 * i - (i & (stride - 1));
+                const int hi = lo + stride;
+                const bool asc = (lo & size) == 0;
+                TopEntry a = buf[lo], b = buf[hi];
+                if (entry_less(b, a) == asc) {
+                    buf[lo] = b;
+                    buf[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) {
+        const int keep = n_e < K ? n_e : K;
+        scal[S_BUFCOUNT] = (uint32_t)keep;
+        if (keep == K) {
+            if (DT == QW_U8) {
+                scal[S_THR] = (uint32_t)buf[K - 1].pri;
+            } else {
+                const double DK = __longlong_as_double((long long)buf[K - 1].pri);
+                const double t = DK * (1.0 + (double)eps) + (d + 1) * 0x1p-100;
+                float f = (float)t;
+                if ((double)f < t) f = nextafterf(f, INFINITY);
+                scal[S_THR] = __float_as_uint(f);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <int DT, int UN, int PM>
+__global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int glob = A.global_tab;
+    const LdsLayout lay = lds_layout((int)A.cap_log2, (int)A.buf, glob, A.L, A.dp, A.dtype);
+    TopEntry *buf = reinterpret_cast<TopEntry *>(smem + lay.buf);
+    uint32_t *lpref = reinterpret_cast<uint32_t *>(smem + lay.lpref);
+    uint32_t *lstart = reinterpret_cast<uint32_t *>(smem + lay.lstart);
+    uint32_t *scal = reinterpret_cast<uint32_t *>(smem + lay.scal);
+    const size_t gcap = size_t(1) << A.cap_log2;
+    uint32_t *tab = glob ? A.gscratch + (size_t)blockIdx.x * (gcap + gcap / 2)
+                         : reinterpret_cast<uint32_t *>(smem + lay.tab);
+    uint32_t *list = glob ? tab + gcap : reinterpret_cast<uint32_t *>(smem + lay.list);
+
+    const int elem = DT == QW_U8 ? 1 : 4;
+    const int row_bytes = A.dp * elem;
+    const int parts = row_bytes / 16;  // 16-byte parts per row
+    int G = 1;
+    while (G < parts && G < 64) G <<= 1;
+    const int P = (parts + G - 1) / G;  // parts per lane
+    const int NG = kBlock / G;
+    const int per_iter = NG * UN;
+    const int grp = tid / G, j = tid % G;
+    const unsigned long long lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+    // relative error bound of the FP32 distance: term rounding (2u), 4P sequential
+    // adds per lane, log2(G) <= 6 tree levels; plus the FP64 reference's own error
+    const float eps = (float)((4 * P + 16) * 0x1p-24 + (A.d + 2) * 0x1p-52);
+
+    int64_t begin = 0, end = A.nitems;
+    if (A.seg) {
+        begin = (int64_t)A.seg[0];
+        end = (int64_t)A.seg[1];
+    } else if (A.nitems_dev) {
+        end = (int64_t)*A.nitems_dev;
+    }
+    int64_t first = A.counter ? -1 : begin + blockIdx.x;
+
+    while (true) {
+        if (tid == 0) {
+            int64_t it = A.counter ? begin + (int64_t)atomicAdd(A.counter, 1u) : first;
+            scal[S_ITEM] = it < end ? (uint32_t)(it - begin) : 0xFFFFFFFFu;
+        }
+        __syncthreads();
+        if (scal[S_ITEM] == 0xFFFFFFFFu) break;
+        const int64_t item = begin + scal[S_ITEM];
+        first = end;  // non-persistent launches serve one item
+        const int64_t q = A.order ? (int64_t)A.order[item] : item;
+
+        // ---- per-query setup
+        int cap_log2 = (int)A.cap_log2;
+        if (tid < A.L) {
+            lstart[tid] = A.bstart[q * A.L + tid];
+            lpref[tid + 1] = A.bsize[q * A.L + tid];
+        }
+        if (tid == 0) {
+            lpref[0] = 0;
+            scal[S_UCOUNT] = 0;
+            scal[S_OVF] = 0;
+            scal[S_BUFCOUNT] = 0;
+            scal[S_THR] = DT == QW_U8 ? 0xFFFFFFFFu : __float_as_uint(INFINITY);
+            scal[S_QQ] = 0;
+        }
+        {  // query row into LDS (+ |q|^2 for uint8)
+            const uint4 *src = reinterpret_cast<const uint4 *>((const unsigned char *)A.queries +
+                                                               q * (int64_t)row_bytes);
+            uint4 *dst = reinterpret_cast<uint4 *>(smem + lay.q);
+            uint32_t qq = 0;
+            for (int i = tid; i < parts; i += kBlock) {
+                uint4 v = src[i];
+                dst[i] = v;
+                if (DT == QW_U8) {
+                    qq = __builtin_amdgcn_udot4(v.x, v.x, qq, false);
+                    qq = __builtin_amdgcn_udot4(v.y, v.y, qq, false);
+                    qq = __builtin_amdgcn_udot4(v.z, v.z, qq, false);
+                    qq = __builtin_amdgcn_udot4(v.w, v.w, qq, false);
+                }
+            }
+            __syncthreads();
+            if (DT == QW_U8 && qq) atomicAdd(&scal[S_QQ], qq);
+        }
+        if (tid == 0) {
+            uint32_t run = 0;
+            for (int l = 0; l < A.L; ++l) {
+                run += lpref[l + 1];
+                lpref[l + 1] = run;
+            }
+            scal[S_T] = run;
+            int c = cap_log2;
+            if (glob) {  // hash set sized from the exact bound min(sum_l s_{q,l}, n)
+                const uint64_t bound = min((uint64_t)run, (uint64_t)A.n);
+                c = 10;
+                while (c < (int)A.cap_log2 && (1ull << c) < 2 * bound) ++c;
+            }
+            scal[S_CAP] = (uint32_t)c;
+        }
+        __syncthreads();
+        cap_log2 = (int)scal[S_CAP];
+        const uint32_t cap = 1u << cap_log2;
+        const uint32_t limit = glob ? cap / 2 : (A.limit < cap / 2 ? A.limit : cap / 2);
+        for (uint32_t i = tid; i < cap; i += kBlock) tab[i] = kEmpty;
+        if (glob) __threadfence();
+        __syncthreads();
+
+        // ---- phase 1: de-duplicated union of the L bucket lists
+        const uint32_t T = A.mode == VM_ALL ? 0u : scal[S_T];
+        for (uint32_t base = 0; base < T; base += kBlock) {
+            const uint32_t pos = base + tid;
+            bool isnew = false;
+            uint32_t id = 0;
+            if (pos < T && !scal[S_OVF]) {
+                int lo = 0, hi = A.L;  // lpref[lo] <= pos < lpref[hi]
+                while (hi - lo > 1) {
+                    int mid = (lo + hi) >> 1;
+                    if (lpref[mid] <= pos) lo = mid; else hi = mid;
+                }
+                id = (uint32_t)A.ids[(int64_t)lo * A.n + lstart[lo] + (pos - lpref[lo])];
+                int r = set_insert(tab, cap_log2, id);
+                isnew = r == INS_NEW;
+                if (r == INS_FULL) scal[S_OVF] = 1;
+            }
+            const unsigned long long m = __ballot(isnew);
+            const uint32_t cnt = (uint32_t)__popcll(m);
+            uint32_t wbase = 0;
+            if (lane == 0 && cnt) wbase = atomicAdd(&scal[S_UCOUNT], cnt);
+            wbase = (uint32_t)__shfl((int)wbase, 0);
+            if (isnew) {
+                const uint32_t idx = wbase + (uint32_t)__popcll(m & lt_mask);
+                if (idx < limit) list[idx] = id; else scal[S_OVF] = 1;
+            }
+        }
+        if (glob) __threadfence();
+        __syncthreads();
+        const uint32_t U = A.mode == VM_ALL ? (uint32_t)A.n : scal[S_UCOUNT];
+        if (A.mode != VM_ALL && (scal[S_OVF] || U > limit)) {
+            if (tid == 0) {
+                uint32_t o = atomicAdd(A.ovf_count, 1u);
+                A.ovf_list[o] = (int32_t)q;
+            }
+            __syncthreads();
+            continue;
+        }
+        if (tid == 0 && A.unique_total && A.mode != VM_ALL) atomicAdd(A.unique_total, (unsigned long long)U);
+        if (A.mode == VM_COUNT) {
+            if (tid == 0) A.out_counts[q] = (int32_t)U;
+            __syncthreads();
+            continue;
+        }
+        if (A.mode == VM_LIST) {
+            const long long o = A.offsets[q];
+            for (uint32_t i = tid; i < U; i += kBlock) A.out_ids[o + i] = (int32_t)list[i];
+            __syncthreads();
+            continue;
+        }
+
+        // ---- phase 2: gather and verify
+        const uint32_t qq = scal[S_QQ];
+        const unsigned char *qrow_b = smem + lay.q;
+        for (uint32_t c0 = 0; c0 < U; c0 += (uint32_t)per_iter) {
+            // every thread snapshots the buffer count between two barriers, so
+            // the compaction decision is uniform even though leaders append to
+            // the buffer later in this iteration
+            __syncthreads();
+            const int bufcount = (int)scal[S_BUFCOUNT];
+            __syncthreads();
+            if (bufcount > (int)A.buf - per_iter)
+                topk_compact<DT>(buf, scal, (int)A.buf, A.K, A.data, A.dp, A.d,
+                                 reinterpret_cast<const float *>(qrow_b), eps);
+            const uint32_t thr = scal[S_THR];
+            uint32_t cid[UN];
+            bool cv[UN];
+            for (int u = 0; u < UN; ++u) {
+                const uint32_t c = c0 + grp + (uint32_t)(NG * u);
+                cv[u] = c < U;
+                cid[u] = cv[u] ? (A.mode == VM_ALL ? c : list[c]) : 0u;
+            }
+            uint32_t accu[UN];
+            float accf[UN];
+            for (int u = 0; u < UN; ++u) {
+                accu[u] = 0;
+                accf[u] = 0.f;
+            }
+            for (int p0 = 0; p0 < P; p0 += PM) {
+                uint4 xv[UN][PM];
+                for (int u = 0; u < UN; ++u)
+                    for (int pp = 0; pp < PM; ++pp) {
+                        const int part = j + G * (p0 + pp);
+                        if (cv[u] && p0 + pp < P && part < parts) {
+                            const uint4 *row = reinterpret_cast<const uint4 *>(
+                                (const unsigned char *)A.data + (int64_t)cid[u] * row_bytes);
+                            xv[u][pp] = row[part];
+                        } else {
+                            xv[u][pp] = make_uint4(0, 0, 0, 0);
+                        }
+                    }
+                for (int pp = 0; pp < PM; ++pp) {
+                    const int part = j + G * (p0 + pp);
+                    if (p0 + pp >= P || part >= parts) continue;
+                    const uint4 qv = reinterpret_cast<const uint4 *>(qrow_b)[part];
+                    for (int u = 0; u < UN; ++u) {
+                        const uint4 x = xv[u][pp];
+                        if (DT == QW_U8) {
+                            uint32_t xx = 0, xq = 0;
+                            xx = __builtin_amdgcn_udot4(x.x, x.x, xx, false);
+                            xx = __builtin_amdgcn_udot4(x.y, x.y, xx, false);
+                            xx = __builtin_amdgcn_udot4(x.z, x.z, xx, false);
+                            xx = __builtin_amdgcn_udot4(x.w, x.w, xx, false);
+                            xq = __builtin_amdgcn_udot4(x.x, qv.x, xq, false);
+                            xq = __builtin_amdgcn_udot4(x.y, qv.y, xq, false);
+                            xq = __builtin_amdgcn_udot4(x.z, qv.z, xq, false);
+                            xq = __builtin_amdgcn_udot4(x.w, qv.w, xq, false);
+                            accu[u] += xx - 2u * xq;
+                        } else {
+                            float d0 = __uint_as_float(x.x) - __uint_as_float(qv.x);
+                            float d1 = __uint_as_float(x.y) - __uint_as_float(qv.y);
+                            float d2 = __uint_as_float(x.z) - __uint_as_float(qv.z);
+                            float d3 = __uint_as_float(x.w) - __uint_as_float(qv.w);
+                            float s = accf[u];
+                            s = fmaf(d0, d0, s);
+                            s = fmaf(d1, d1, s);
+                            s = fmaf(d2, d2, s);
+                            s = fmaf(d3, d3, s);
+                            accf[u] = s;
+                        }
+                    }
+                }
+            }
+            for (int u = 0; u < UN; ++u) {
+                for (int off = G >> 1; off > 0; off >>= 1) {
+                    if (DT == QW_U8)
+                        accu[u] += (uint32_t)__shfl_xor((int)accu[u], off);
+                    else
+                        accf[u] += __shfl_xor(accf[u], off);
+                }
+            }
+            if (j == 0) {
+                for (int u = 0; u < UN; ++u) {
+                    if (!cv[u]) continue;
+                    bool admit;
+                    unsigned long long pri;
+                    uint32_t flag;
+                    if (DT == QW_U8) {
+                        const uint32_t dist = accu[u] + qq;
+                        admit = dist <= thr;
+                        pri = dist;
+                        flag = 0;
+                    } else {
+                        admit = accf[u] <= __uint_as_float(thr);
+                        pri = __float_as_uint(accf[u]);
+                        flag = 1;
+                    }
+                    if (admit) {
+                        const uint32_t e = atomicAdd(&scal[S_BUFCOUNT], 1u);
+                        buf[e].pri = pri;
+                        buf[e].id = cid[u];
+                        buf[e].flag = flag;
+                    }
+                }
+            }
+        }
+        topk_compact<DT>(buf, scal, (int)A.buf, A.K, A.data, A.dp, A.d,
+                         reinterpret_cast<const float *>(qrow_b), eps);
+        const int keep = (int)scal[S_BUFCOUNT];
+        for (int r = tid; r < A.K; r += kBlock) {
+            const int64_t o = q * A.K + r;
+            if (r < keep) {
+                A.out_ids[o] = (int32_t)buf[r].id;
+                if (DT == QW_U8)
+                    reinterpret_cast<int32_t *>(A.out_dist)[o] = (int32_t)buf[r].pri;
+                else
+                    reinterpret_cast<float *>(A.out_dist)[o] =
+                        (float)__longlong_as_double((long long)buf[r].pri);
+            } else {
+                A.out_ids[o] = -1;
+                if (DT == QW_U8)
+                    reinterpret_cast<int32_t *>(A.out_dist)[o] = INT32_MAX;
+                else
+                    reinterpret_cast<float *>(A.out_dist)[o] = INFINITY;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+int verify_per_iter(int dp, int dtype)
+{
+    const int parts = dp * (dtype == QW_U8 ? 1 : 4) / 16;
+    int G = 1;
+    while (G < parts && G < 64) G <<= 1;
+    return (kBlock / G) * (parts <= 64 ? 4 : 2);
+}
+
+int verify_blocks_per_cu(int dp, int dtype, size_t lds)
+{
+    const int parts = dp * (dtype == QW_U8 ? 1 : 4) / 16;
+    const bool small = parts <= 64;
+    const void *fn;
+    if (dtype == QW_U8)
+        fn = small ? (const void *)verify_kernel<QW_U8, 4, 1> : (const void *)verify_kernel<QW_U8, 2, 4>;
+    else
+        fn = small ? (const void *)verify_kernel<QW_F32, 4, 1> : (const void *)verify_kernel<QW_F32, 2, 4>;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        nb = 1;
+    }
+    return nb > 0 ? nb : 1;
+}
+
+qw_status launch_verify(const VerifyArgs &a, int grid, hipStream_t s)
+{
+    if (grid <= 0) return QW_OK;
+    const size_t lds = verify_lds_bytes((int)a.cap_log2, (int)a.buf, a.global_tab, a.L, a.dp,
+                                        a.dtype);
+    const int row_bytes = a.dp * (a.dtype == QW_U8 ? 1 : 4);
+    const int parts = row_bytes / 16;
+    const bool small = parts <= 64;  // one part per lane
+    if (a.dtype == QW_U8) {
+        if (small)
+            verify_kernel<QW_U8, 4, 1><<<grid, kBlock, lds, s>>>(a);
+        else
+            verify_kernel<QW_U8, 2, 4><<<grid, kBlock, lds, s>>>(a);
+    } else {
+        if (small)
+            verify_kernel<QW_F32, 4, 1><<<grid, kBlock, lds, s>>>(a);
+        else
+            verify_kernel<QW_F32, 2, 4><<<grid, kBlock, lds, s>>>(a);
+    }
+    QW_HIP(hipGetLastError());
+    return QW_OK;
+}
+
+}  // namespace qw

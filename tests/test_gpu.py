@@ -1,0 +1,306 @@
+"""GPU parity tests: the HIP path (through the C ABI) against the CPU oracle.
+
+Bucket ids, candidate sets and top-K ids must be bit-exact; uint8 distances are
+exact int32; float distances must lie within 1e-5 relative of the FP64 oracle
+(the library returns the FP64 index-order distance rounded once to float32).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1907_11803_amd import lib, synth
+
+pytestmark = pytest.mark.gpu
+
+I32MAX = np.iinfo(np.int32).max
+FORMS = [lib.QW_FORM_PLAIN_FP32, lib.QW_FORM_FAST]
+SCHEDS = [lib.QW_SCHED_SUM, lib.QW_SCHED_ACTUAL, lib.QW_SCHED_NONE, lib.QW_SCHED_LEARNED]
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def build(wl_data, a, b, w, form=lib.QW_FORM_FAST):
+    return lib.Index(dev(wl_data), dev(a), dev(b), w, form=form)
+
+
+def check_topk(ids_g, dist_g, ids_o, dist_o, is_u8):
+    ids_g = ids_g.cpu().numpy()
+    dist_g = dist_g.cpu().numpy()
+    assert np.array_equal(ids_g, ids_o), np.argwhere(ids_g != ids_o)[:5]
+    if is_u8:
+        want = np.where(dist_o == np.iinfo(np.int64).max, I32MAX, dist_o).astype(np.int64)
+        assert np.array_equal(dist_g.astype(np.int64), want)
+    else:
+        fin = np.isfinite(dist_o)
+        assert np.array_equal(np.isfinite(dist_g), fin)
+        np.testing.assert_allclose(dist_g[fin], dist_o[fin], rtol=1e-5, atol=0)
+        # the library rounds the FP64 distance once
+        assert np.array_equal(dist_g[fin], dist_o[fin].astype(np.float32))
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return synth.make_config(1)
+
+
+# ---------------------------------------------------------------- hashing
+
+@pytest.mark.parametrize("form", FORMS)
+def test_hash_bit_exact_cfg1(cfg1, form):
+    p = cfg1.params
+    ix = build(cfg1.data, p.a, p.b(), p.w, form)
+    for x in (cfg1.data[:3001], cfg1.queries):
+        h, rec = ix.hash(dev(x), form)
+        want = oracle.hash_points(x, p.a, p.b(), p.w)
+        assert np.array_equal(h.cpu().numpy(), want)
+        assert 0 <= rec < 0.05 * want.size
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_hash_boundary_cases(form):
+    """Projections exactly on bucket boundaries or one ulp of b beside them."""
+    L, k, d = 3, 5, 48
+    a, b, w = synth.boundary_params(17, L, k, d, w=4.0)
+    rng = np.random.default_rng(18)
+    x = rng.integers(0, 256, size=(777, d), dtype=np.uint8)
+    ix = build(x, a, b, w, form)
+    h, rec = ix.hash(dev(x), form)
+    assert np.array_equal(h.cpu().numpy(), oracle.hash_points(x, a, b, w))
+    assert rec > 0  # exact boundary hits must take the FP64 path
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_hash_float_data_ragged_d(form):
+    wl = synth.random_small(23, n=1500, d=37, Q=70, L=3, k=7, w=0.7, dtype="f32")
+    p = wl.params
+    ix = build(wl.data, p.a, p.b(), p.w, form)
+    h, _ = ix.hash(dev(wl.queries), form)
+    assert np.array_equal(h.cpu().numpy(), oracle.hash_points(wl.queries, p.a, p.b(), p.w))
+
+
+# ---------------------------------------------------------------- candidates
+
+@pytest.mark.parametrize("w", [400.0, 1200.0])
+def test_candidate_sets_cfg1(cfg1, w):
+    p = cfg1.params
+    ix = build(cfg1.data, p.a, p.b(w), w)
+    q = cfg1.queries
+    got = ix.candidate_lists(dev(q))
+    want = oracle.lsh_candidates(cfg1.data, q, p.a, p.b(w), w)
+    for g, o in zip(got, want):
+        assert np.array_equal(g, o)
+    cnt = ix.candidate_counts(dev(q)).cpu().numpy()
+    assert cnt.tolist() == [len(o) for o in want]
+    sizes = ix.bucket_sizes(dev(q)).cpu().numpy()
+    assert sizes.shape == (q.shape[0], p.L)
+    assert np.all(sizes.sum(axis=1) >= cnt)
+
+
+# ---------------------------------------------------------------- top-K, uint8
+
+@pytest.mark.parametrize("w", [400.0, 1200.0])
+@pytest.mark.parametrize("form", FORMS)
+def test_topk_cfg1(cfg1, w, form):
+    p = cfg1.params
+    ix = build(cfg1.data, p.a, p.b(w), w)
+    ids_o, dist_o, cnt_o = oracle.lsh_query(cfg1.data, cfg1.queries, p.a, p.b(w), w, cfg1.K)
+    opts = lib.make_opts(form=form, sched=lib.QW_SCHED_SUM)
+    ids, dist, st = ix.query(dev(cfg1.queries), cfg1.K, opts, stats=True)
+    check_topk(ids, dist, ids_o, dist_o, True)
+    assert st["cand_unique"] == int(cnt_o.sum())
+    assert st["overflow"] == 0
+
+
+@pytest.mark.parametrize("sched", SCHEDS)
+@pytest.mark.parametrize("group", [0, 1])
+def test_fast_form_schedules_identical(cfg1, sched, group):
+    p = cfg1.params
+    w = 1200.0
+    ix = build(cfg1.data, p.a, p.b(w), w)
+    ids_o, dist_o, _ = oracle.lsh_query(cfg1.data, cfg1.queries, p.a, p.b(w), w, cfg1.K)
+    opts = lib.make_opts(form=lib.QW_FORM_FAST, sched=sched, group=group)
+    for rep in range(3):  # graph replays, with eager work in between
+        ids, dist = ix.query(dev(cfg1.queries), cfg1.K, opts)
+        torch.cuda.synchronize()
+        check_topk(ids, dist, ids_o, dist_o, True)
+        _ = (torch.arange(1000, device="cuda") * 2).sum().item()
+
+
+def test_ragged_u8_and_topk_sizes():
+    """d not a multiple of 16, n and Q not multiples of the tile sizes, several K."""
+    wl = synth.random_small(31, n=2345, d=53, Q=77, L=4, k=3, w=700.0, dtype="u8")
+    p = wl.params
+    ix = build(wl.data, p.a, p.b(), p.w)
+    for K in (1, 7, 33, 300):
+        ids_o, dist_o, _ = oracle.lsh_query(wl.data, wl.queries, p.a, p.b(), p.w, K)
+        for form in FORMS:
+            ids, dist = ix.query(dev(wl.queries), K, lib.make_opts(form=form, sched=lib.QW_SCHED_SUM))
+            check_topk(ids, dist, ids_o, dist_o, True)
+
+
+def test_padding_and_empty_workload():
+    wl = synth.random_small(41, n=500, d=16, Q=20, L=2, k=6, w=50.0, dtype="u8")
+    p = wl.params
+    ix = build(wl.data, p.a, p.b(), p.w)
+    ids_o, dist_o, cnt = oracle.lsh_query(wl.data, wl.queries, p.a, p.b(), p.w, 10)
+    assert (cnt < 10).any()  # small w: most queries have few candidates
+    ids, dist = ix.query(dev(wl.queries), 10)
+    check_topk(ids, dist, ids_o, dist_o, True)
+    e_ids, e_dist = ix.query(dev(wl.queries[:0]), 10)
+    assert e_ids.shape == (0, 10)
+
+
+def test_duplicates_tie_break():
+    rng = np.random.default_rng(5)
+    base = rng.integers(0, 256, size=(300, 24), dtype=np.uint8)
+    data = np.concatenate([base, base[:100], base[:50]])  # ids 300.. duplicate 0..
+    q = base[:40].copy()
+    L, k, w = 3, 2, 2000.0
+    a = rng.standard_normal((L, k, 24)).astype(np.float32)
+    b = (rng.random((L, k)) * w).astype(np.float32)
+    ix = build(data, a, b, w)
+    ids_o, dist_o, _ = oracle.lsh_query(data, q, a, b, w, 5)
+    for form in FORMS:
+        ids, dist = ix.query(dev(q), 5, lib.make_opts(form=form, sched=lib.QW_SCHED_SUM))
+        check_topk(ids, dist, ids_o, dist_o, True)
+    assert ids_o[0, :3].tolist() == [0, 300, 400]
+
+
+# ---------------------------------------------------------------- float data
+
+@pytest.fixture(scope="module")
+def cfg3_small():
+    return synth.make_config(3, n=6000, Q=60, ncomp=30, w=8.0)
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_topk_float_cfg3_small(cfg3_small, form):
+    wl = cfg3_small
+    p = wl.params
+    ix = build(wl.data, p.a, p.b(), p.w)
+    ids_o, dist_o, cnt = oracle.lsh_query(wl.data, wl.queries, p.a, p.b(), p.w, wl.K)
+    assert cnt.mean() > 50
+    ids, dist = ix.query(dev(wl.queries), wl.K, lib.make_opts(form=form, sched=lib.QW_SCHED_SUM))
+    check_topk(ids, dist, ids_o, dist_o, False)
+
+
+# ---------------------------------------------------------------- brute force
+
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_bruteforce_matches_oracle(dtype):
+    wl = synth.random_small(51, n=3000, d=40, Q=30, L=1, k=1, w=10.0, dtype=dtype)
+    p = wl.params
+    ix = build(wl.data, p.a, p.b(), p.w)
+    ids_o, dist_o = oracle.bruteforce(wl.data, wl.queries, 12)
+    ids, dist = ix.bruteforce(dev(wl.queries), 12)
+    check_topk(ids, dist, ids_o, dist_o, dtype == "u8")
+
+
+def test_huge_w_equals_bruteforce():
+    """Every point in one bucket per layer: LSH top-K equals exact kNN."""
+    rng = np.random.default_rng(61)
+    data = rng.integers(0, 256, size=(4000, 32), dtype=np.uint8)
+    q = rng.integers(0, 256, size=(25, 32), dtype=np.uint8)
+    L, k, w = 2, 3, 1.0e7
+    a = rng.standard_normal((L, k, 32)).astype(np.float32)
+    b = np.full((L, k), w / 2, np.float32)
+    ix = build(data, a, b, w)
+    ids_o, dist_o = oracle.bruteforce(data, q, 10)
+    for form in FORMS:
+        ids, dist = ix.query(dev(q), 10, lib.make_opts(form=form, sched=lib.QW_SCHED_SUM))
+        check_topk(ids, dist, ids_o, dist_o, True)
+
+
+# ---------------------------------------------------------------- count model
+
+def test_mlp_gradient_matches_oracle():
+    from oracle import mlp
+    rng = np.random.default_rng(71)
+    L, H, B = 16, 64, 300
+    P = lib.qw_mlp_param_count(L)
+    params = (rng.standard_normal(P) * 0.2).astype(np.float32)
+    feats = np.log1p(rng.integers(0, 800, size=(B, L))).astype(np.float32)
+    targets = np.log1p(rng.integers(1, 4000, size=B)).astype(np.float32)
+    grad, loss = lib.qw_mlp_loss_grad(dev(params), L, dev(feats), dev(targets))
+    W1 = params[:H * L].reshape(H, L).astype(np.float64)
+    b1 = params[H * L:H * L + H].astype(np.float64)
+    W2 = params[H * L + H:H * L + 2 * H].astype(np.float64)
+    b2 = float(params[-1])
+    lo, (dW1, db1, dW2, db2) = mlp.loss_and_grad(W1, b1, W2, b2, feats.astype(np.float64), targets)
+    want = np.concatenate([dW1.ravel(), db1, dW2, [db2]])
+    g = grad.cpu().numpy().astype(np.float64)
+    assert abs(float(loss.item()) - lo) <= 1e-4 * abs(lo)
+    np.testing.assert_allclose(g, want, rtol=1e-4, atol=1e-4 * np.abs(want).max())
+
+
+def test_adam_matches_oracle():
+    from oracle import mlp
+    rng = np.random.default_rng(72)
+    P = 500
+    p = rng.standard_normal(P).astype(np.float32)
+    g = rng.standard_normal(P).astype(np.float32)
+    pt, gt = dev(p), dev(g)
+    m, v = torch.zeros_like(pt), torch.zeros_like(pt)
+    pm, mm, vm = p.astype(np.float64), np.zeros(P), np.zeros(P)
+    for step in (1, 2, 3):
+        lib.qw_mlp_adam(pt, gt, m, v, step, 1e-2)
+        pm, mm, vm = mlp.adam_step(pm, g.astype(np.float64), mm, vm, step, 1e-2)
+    np.testing.assert_allclose(pt.cpu().numpy(), pm, rtol=1e-5, atol=1e-6)
+
+
+def test_mlp_bf16_prediction_close_to_fp64():
+    from oracle import mlp
+    rng = np.random.default_rng(73)
+    L, H, B = 12, 64, 200
+    P = lib.qw_mlp_param_count(L)
+    params = (rng.standard_normal(P) * 0.2).astype(np.float32)
+    feats = np.log1p(rng.integers(0, 800, size=(B, L))).astype(np.float32)
+    out = lib.qw_mlp_predict_bf16(dev(params), L, dev(feats)).cpu().numpy()
+    W1 = params[:H * L].reshape(H, L)
+    y, _ = mlp.forward(W1, params[H * L:H * L + H], params[H * L + H:H * L + 2 * H], params[-1], feats)
+    # bf16 operands: 8-bit mantissa, relative error ~2^-8 per operand
+    assert np.max(np.abs(out - y)) <= 0.05 * (np.max(np.abs(y)) + 1)
+
+
+def test_learned_schedule_trains_and_keeps_results(cfg1):
+    p = cfg1.params
+    w = 1200.0
+    ix = build(cfg1.data, p.a, p.b(w), w)
+    train = synth.training_queries(1, 3000)
+    loss = ix.train_count_model(dev(train), epochs=4, batch=256, lr=3e-3, seed=1)
+    assert math.isfinite(loss)
+    assert ix.info()["has_count_model"] == 1
+    ids_o, dist_o, _ = oracle.lsh_query(cfg1.data, cfg1.queries, p.a, p.b(w), w, cfg1.K)
+    ids, dist, st = ix.query(dev(cfg1.queries), cfg1.K,
+                             lib.make_opts(sched=lib.QW_SCHED_LEARNED), stats=True)
+    check_topk(ids, dist, ids_o, dist_o, True)
+    # a sabotaged model (predicts 0 candidates) forces the overflow path
+    P = lib.qw_mlp_param_count(p.L)
+    bad = np.zeros(P, np.float32)
+    bad[-1] = -5.0
+    ix.set_count_model(bad)
+    ids, dist, st = ix.query(dev(cfg1.queries), cfg1.K,
+                             lib.make_opts(sched=lib.QW_SCHED_LEARNED), stats=True)
+    check_topk(ids, dist, ids_o, dist_o, True)
+
+
+# ---------------------------------------------------------------- errors
+
+def test_error_paths(cfg1):
+    p = cfg1.params
+    ix = build(cfg1.data[:1000], p.a, p.b(), p.w)
+    q = dev(cfg1.queries)
+    with pytest.raises(lib.QwError) as e:
+        ix.query(q, 0)
+    assert e.value.status == lib.QW_EINVAL
+    with pytest.raises(lib.QwError):
+        ix.query(q, 5000)
+    with pytest.raises(lib.QwError):  # w <= 0
+        lib.Index(dev(cfg1.data[:100]), dev(p.a), dev(p.b()), 0.0)
+    with pytest.raises(lib.QwError):  # keys wider than 128 bits: tiny w, k = 8, huge ranges
+        lib.Index(dev(cfg1.data[:2000]), dev(p.a), dev(p.b(0.001)), 0.001)

@@ -375,3 +375,13 @@ def test_adam_first_step_is_lr_times_sign():
     g = np.array([0.3, -2.0, 1e-3])
     p, m, v = mlp.adam_step(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, 0.01)
     np.testing.assert_allclose(p, -0.01 * np.sign(g), rtol=1e-4)
+
+
+def test_built_index_matches_one_shot_query():
+    wl = synth.make_config(1, n=2000, Q=30, w=1000.0)
+    a, b, w = wl.params.a, wl.params.b(), wl.params.w
+    ids1, d1, c1 = oracle.lsh_query(wl.data, wl.queries, a, b, w, 10)
+    bi = oracle.BuiltIndex(wl.data, a, b, w)
+    ids2, d2, c2 = bi.query(wl.queries, 10)
+    bi.close()
+    assert np.array_equal(ids1, ids2) and np.array_equal(d1, d2) and np.array_equal(c1, c2)
