@@ -70,7 +70,7 @@ def main():
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4])
     ap.add_argument("--w", type=float, default=None, help="bucket width (default: search w_0.9)")
     ap.add_argument("--train-queries", type=int, default=50_000)
-    ap.add_argument("--cpu-sample", type=int, default=1000)
+    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle query sample (0 = all)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="only the fast-form timed loop (for rocprofv3 runs)")
@@ -206,7 +206,8 @@ def main():
         bi = oracle.BuiltIndex(wl.data, wl.params.a, wl.params.b(w), w, nthreads=nthreads)
         build_cpu = time.time() - t1
         rng = np.random.default_rng(7)
-        sample = np.sort(rng.choice(wl.Q, size=min(args.cpu_sample, wl.Q), replace=False))
+        ns = wl.Q if args.cpu_sample <= 0 else min(args.cpu_sample, wl.Q)
+        sample = np.sort(rng.choice(wl.Q, size=ns, replace=False))
         t1 = time.time()
         o_ids, o_dist, _ = bi.query(wl.queries[sample], K)
         q_cpu = time.time() - t1

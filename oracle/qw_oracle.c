@@ -147,18 +147,33 @@ typedef struct {
     int64_t n; int32_t L, k;
 } orc_index;
 
-static int index_build(orc_index *ix, const int32_t *h, int64_t n, int32_t L, int32_t k)
+typedef struct { orc_index *ix; int tid, nthreads; } build_job;
+
+static void *build_worker(void *p)
+{
+    build_job *j = (build_job *)p;
+    orc_index *ix = j->ix;
+    for (int32_t l = j->tid; l < ix->L; l += j->nthreads) {
+        int32_t *o = ix->order + (int64_t)l * ix->n;
+        for (int64_t i = 0; i < ix->n; ++i) o[i] = (int32_t)i;
+        tuple_ctx c = {ix->h, ix->L * ix->k, ix->k, l * ix->k};
+        qsort_r(o, (size_t)ix->n, sizeof(int32_t), cmp_ids, &c);
+    }
+    return NULL;
+}
+
+/* one sorted id list per layer; layers are independent and sorted in parallel */
+static int index_build(orc_index *ix, const int32_t *h, int64_t n, int32_t L, int32_t k,
+                       int nthreads)
 {
     ix->h = h; ix->n = n; ix->L = L; ix->k = k;
     ix->order = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1) * L);
     if (!ix->order) return -1;
-    for (int32_t l = 0; l < L; ++l) {
-        int32_t *o = ix->order + (int64_t)l * n;
-        for (int64_t i = 0; i < n; ++i) o[i] = (int32_t)i;
-        tuple_ctx c = {h, L * k, k, l * k};
-        qsort_r(o, (size_t)n, sizeof(int32_t), cmp_ids, &c);
-    }
-    return 0;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    build_job jobs[256];
+    for (int t = 0; t < nthreads; ++t) jobs[t] = (build_job){ix, t, nthreads};
+    return run_threads(build_worker, jobs, sizeof(build_job), nthreads) ? -2 : 0;
 }
 
 /* first position in layer l whose tuple is >= t; sets *cnt to the run length of t */
@@ -328,7 +343,7 @@ int orc_lsh_query(const void *data, int64_t n, int32_t d, int32_t dtype,
     int rc = orc_hash(data, n, d, dtype, a, b, nf, w, nthreads, hd);
     if (!rc) rc = orc_hash(q, Q, d, dtype, a, b, nf, w, nthreads, hq);
     orc_index ix = {0};
-    if (!rc) rc = index_build(&ix, hd, n, L, k);
+    if (!rc) rc = index_build(&ix, hd, n, L, k, nthreads);
     if (!rc) {
         query_job t = {&ix, hq, data, q, dtype, d, Q, K, out_ids, out_di, out_df, out_cnt,
                        NULL, NULL, 0, 1, 0};
@@ -357,7 +372,7 @@ int orc_lsh_candidates(const void *data, int64_t n, int32_t d, int32_t dtype,
     int rc = orc_hash(data, n, d, dtype, a, b, nf, w, nthreads, hd);
     if (!rc) rc = orc_hash(q, Q, d, dtype, a, b, nf, w, nthreads, hq);
     orc_index ix = {0};
-    if (!rc) rc = index_build(&ix, hd, n, L, k);
+    if (!rc) rc = index_build(&ix, hd, n, L, k, nthreads);
     if (!rc) {
         query_job t = {&ix, hq, data, q, dtype, d, Q, 0, NULL, NULL, NULL, out_cnt,
                        (int64_t *)cand_off, cand_ids, 0, 1, 0};
@@ -385,7 +400,7 @@ void *orc_lsh_build(const void *data, int64_t n, int32_t d, int32_t dtype, const
     if (!o) return NULL;
     o->hd = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1) * L * k);
     if (!o->hd || orc_hash(data, n, d, dtype, a, b, L * k, w, nthreads, o->hd) ||
-        index_build(&o->ix, o->hd, n, L, k)) {
+        index_build(&o->ix, o->hd, n, L, k, nthreads)) {
         free(o->hd); free(o->ix.order); free(o);
         return NULL;
     }

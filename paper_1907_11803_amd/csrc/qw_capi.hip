@@ -17,7 +17,10 @@ namespace {
 enum {
     C_RECOMP = 0, C_UNIQUE, C_PROBEHIT, C_CANDTOT, C_CLASS /* .. C_CLASS+15 */, kC64 = 24
 };
-enum { W_WORK = 0 /* .. 15 */, W_OVFWORK = 16, W_OVF = 17, W_MAX = 18, kC32 = 32 };
+// u32: persistent work counters per class, overflow-queue lengths per class
+// (queue i holds queries that overflowed class i-1), misc
+enum { W_WORK = 0 /* .. 15 */, W_QCNT = 16 /* .. 32 */, W_SIMPLE = 33, W_MAX = 34, W_DUMMY = 35,
+       kC32 = 40 };
 constexpr int kCmin = 10;
 constexpr int kMaxClasses = 16;
 constexpr float kMargin = 1.25f;  // learned schedule: slack on the predicted count
@@ -59,8 +62,9 @@ Plan make_plan(qw_index *ix, int K)
     }
     const uint64_t bound = std::min<uint64_t>((uint64_t)ix->L * (uint64_t)std::max<int64_t>(1, ix->max_bucket),
                                               (uint64_t)ix->n);
-    p.cap_g = std::max(p.cmax + 1, ceil_log2(2 * bound));
-    const double per_wg = 1.5 * std::ldexp(4.0, p.cap_g);
+    p.cap_g = p.cmax + 1;
+    while ((3ull << p.cap_g) < 4 * bound) ++p.cap_g;  // load factor <= 3/4
+    const double per_wg = std::ldexp(4.0, p.cap_g);
     const double budget = 2.0 * 1024 * 1024 * 1024;
     p.grid_g = (int)std::max(1.0, std::min((double)ix->cus, std::floor(budget / per_wg)));
     p.grid[p.ncls - 1] = p.grid_g;
@@ -91,12 +95,12 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan)
     QW_TRY(w.keys2.ensure(sizeof(unsigned long long) * q));
     QW_TRY(w.vals.ensure(sizeof(int32_t) * q));
     QW_TRY(w.vals2.ensure(sizeof(int32_t) * q));
-    QW_TRY(w.ovf.ensure(sizeof(int32_t) * q));
+    QW_TRY(w.ovf.ensure(sizeof(int32_t) * q * (kMaxClasses + 1)));  // one queue per class
     QW_TRY(w.binoff.ensure(sizeof(unsigned long long) * 2 * kMaxClasses));
     QW_TRY(w.counters.ensure(sizeof(unsigned long long) * kC64 + sizeof(uint32_t) * kC32));
     QW_TRY(w.hist.ensure(radix_sort_scratch_bytes(q)));
     if (plan) {
-        const size_t g = (size_t)plan->grid_g * ((size_t(1) << plan->cap_g) * 3 / 2) * 4;
+        const size_t g = (size_t)plan->grid_g * (size_t(1) << plan->cap_g) * 4;
         QW_TRY(w.gscratch.ensure(g));
     }
     std::vector<void *> after = {w.qpad.p, w.h.p, w.bstart.p, w.bsize.p, w.qsum.p, w.pred.p,
@@ -123,7 +127,7 @@ VerifyArgs base_args(qw_index *ix, int K, int mode)
     a.mode = mode;
     a.data = ix->data.p;
     a.queries = ix->ws.qpad.p;
-    a.ovf_count = c32(ix) + W_OVF;
+    a.ovf_count = c32(ix) + W_DUMMY;  // callers that can overflow set a real queue
     a.ovf_list = ix->ws.ovf.as<int32_t>();
     return a;
 }
@@ -162,7 +166,8 @@ qw_status verify_simple(qw_index *ix, int64_t Q, int K, int mode, hipStream_t s,
     QW_HIP(hipStreamSynchronize(s));
     if (ev_sched) QW_HIP(hipEventRecord(ev_sched, s));
     const uint64_t bound = std::min<uint64_t>(maxsum, (uint64_t)ix->n);
-    int cap = std::max(kCmin, ceil_log2(2 * std::max<uint64_t>(bound, 1)));
+    int cap = kCmin;
+    while ((3ull << cap) < 4 * bound) ++cap;  // load factor <= 3/4: never overflows
     VerifyArgs a = base_args(ix, K, mode);
     const int buf = pow2_at_least(std::max(64, 2 * (K + verify_per_iter(ix->dp, ix->dtype))));
     a.buf = (uint32_t)buf;
@@ -174,19 +179,19 @@ qw_status verify_simple(qw_index *ix, int64_t Q, int K, int mode, hipStream_t s,
     a.unique_total = c64(ix) + C_UNIQUE;
     if (verify_lds_bytes(cap, buf, 0, ix->L, ix->dp, ix->dtype) <= ix->lds_max) {
         a.cap_log2 = (uint32_t)cap;
-        a.limit = 1u << (cap - 1);
+        a.limit = (1u << cap) / 4 * 3;
         return launch_verify(a, (int)Q, s);
     }
     // very large candidate sets: hash sets in global scratch, persistent workgroups
     const int grid = (int)std::min<int64_t>(Q, ix->cus);
     void *old = ix->ws.gscratch.p;
-    QW_TRY(ix->ws.gscratch.ensure((size_t)grid * ((size_t(1) << cap) * 3 / 2) * 4));
+    QW_TRY(ix->ws.gscratch.ensure((size_t)grid * (size_t(1) << cap) * 4));
     if (ix->ws.gscratch.p != old) drop_graphs(ix);  // captured graphs hold the old pointer
     a.cap_log2 = (uint32_t)cap;
-    a.limit = 1u << (cap - 1);
+    a.limit = (1u << cap) / 4 * 3;
     a.global_tab = 1;
     a.gscratch = ix->ws.gscratch.as<uint32_t>();
-    a.counter = c32(ix) + W_OVFWORK;
+    a.counter = c32(ix) + W_SIMPLE;
     QW_TRY(launch_fill_u32(a.counter, 0u, 1, s));
     return launch_verify(a, grid, s);
 }
@@ -222,19 +227,26 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
                                w.vals.as<int32_t>(), ccount, s));
         bool alt = false;
         QW_TRY(radix_sort_pairs(w.keys.as<unsigned long long>(), w.vals.as<int32_t>(), Q,
-                                o.group ? 0 : 24, 32, w.keys2.as<unsigned long long>(),
+                                o.group ? 0 : 16, 24, w.keys2.as<unsigned long long>(),
                                 w.vals2.as<int32_t>(), w.hist, s, &alt));
         *order = alt ? w.vals2.as<int32_t>() : w.vals.as<int32_t>();
         QW_TRY(launch_segments(ccount, plan.ncls, seg, s));
         return QW_OK;
     };
+    // Classes run from the smallest hash set to the global one.  Each launch
+    // serves its segment of the order, then the queue of queries that
+    // overflowed the previous class; its own overflows go to the next queue.
+    int32_t *queues = w.ovf.as<int32_t>();
     auto run_classes = [&](const int32_t *order, int mode, int32_t *counts) -> qw_status {
-        // global class first (largest queries), then LDS classes from large to small
-        for (int i = plan.ncls - 1; i >= 0; --i) {
+        for (int i = 0; i < plan.ncls; ++i) {
             VerifyArgs a = base_args(ix, K, mode);
             a.order = order;
             a.seg = seg + 2 * i;
             a.counter = c32(ix) + W_WORK + i;
+            a.in_list = i > 0 ? queues + (int64_t)i * Q : nullptr;
+            a.in_count = i > 0 ? c32(ix) + W_QCNT + i : nullptr;
+            a.ovf_list = queues + (int64_t)(i + 1) * Q;
+            a.ovf_count = c32(ix) + W_QCNT + i + 1;
             a.buf = (uint32_t)plan.buf;
             a.out_ids = out_ids;
             a.out_dist = out_dist;
@@ -242,12 +254,12 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
             a.unique_total = mode == VM_TOPK ? c64(ix) + C_UNIQUE : nullptr;
             if (i == plan.ncls - 1) {
                 a.cap_log2 = (uint32_t)plan.cap_g;
-                a.limit = 1u << (plan.cap_g - 1);
+                a.limit = (1u << plan.cap_g) / 4 * 3;
                 a.global_tab = 1;
                 a.gscratch = w.gscratch.as<uint32_t>();
             } else {
                 a.cap_log2 = (uint32_t)(kCmin + i);
-                a.limit = 1u << (kCmin + i - 1);
+                a.limit = (1u << (kCmin + i)) / 4 * 3;
             }
             QW_TRY(launch_verify(a, plan.grid[i], s));
         }
@@ -258,7 +270,7 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
         QW_TRY(schedule(nullptr, nullptr, 0, &order));
         QW_TRY(run_classes(order, VM_COUNT, w.pred.as<int32_t>()));
         QW_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(ccount), 0u, 2 * kMaxClasses, s));
-        QW_TRY(launch_fill_u32(c32(ix) + W_WORK, 0u, kMaxClasses, s));
+        QW_TRY(launch_fill_u32(c32(ix) + W_WORK, 0u, W_SIMPLE - W_WORK, s));
         exact = w.pred.as<int32_t>();
     } else if (learned) {
         QW_TRY(launch_mlp_features(w.bsize.as<uint32_t>(), Q, ix->L, w.feats.as<float>(), s));
@@ -270,21 +282,6 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     if (ev) QW_HIP(hipEventRecord(ev[3], s));
     QW_TRY(run_classes(order, VM_TOPK, nullptr));
     if (ev) QW_HIP(hipEventRecord(ev[4], s));
-    // queries whose hash set was sized too small by the prediction
-    VerifyArgs a = base_args(ix, K, VM_TOPK);
-    a.order = w.ovf.as<int32_t>();
-    a.nitems_dev = c32(ix) + W_OVF;
-    a.counter = c32(ix) + W_OVFWORK;
-    a.buf = (uint32_t)plan.buf;
-    a.cap_log2 = (uint32_t)plan.cap_g;
-    a.limit = 1u << (plan.cap_g - 1);
-    a.global_tab = 1;
-    a.gscratch = w.gscratch.as<uint32_t>();
-    a.out_ids = out_ids;
-    a.out_dist = out_dist;
-    a.unique_total = c64(ix) + C_UNIQUE;
-    a.ovf_count = c32(ix) + W_MAX;  // never used: global sets cannot overflow
-    QW_TRY(launch_verify(a, plan.grid_g, s));
     if (ev) QW_HIP(hipEventRecord(ev[5], s));
     return QW_OK;
 }
@@ -307,7 +304,9 @@ qw_status fill_stats(qw_index *ix, int64_t Q, hipStream_t s, qw_stats *st, hipEv
     st->probes_hit = (int64_t)h64[C_PROBEHIT];
     st->cand_total = (int64_t)h64[C_CANDTOT];
     st->cand_unique = (int64_t)h64[C_UNIQUE];
-    st->overflow = fast ? (int64_t)h32[W_OVF] : 0;
+    st->overflow = 0;
+    if (fast)
+        for (int i = 1; i <= kMaxClasses; ++i) st->overflow += (int64_t)h32[W_QCNT + i];
     if (fast)
         for (int i = 0; i < 8; ++i) st->bins[i] = (int64_t)h64[C_CLASS + i];
     if (ev) {

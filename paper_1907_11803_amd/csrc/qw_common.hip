@@ -217,6 +217,30 @@ __global__ __launch_bounds__(kBlock) void scan_tile_apply(const uint32_t *__rest
     if (blockIdx.x == ntiles - 1 && threadIdx.x == 0) out[count] = sums[ntiles];
 }
 
+// Whole scan in one workgroup when count <= kScanTile.
+__global__ __launch_bounds__(kBlock) void scan_small_kernel(const uint32_t *__restrict__ in,
+                                                            int64_t count,
+                                                            unsigned long long *__restrict__ out)
+{
+    __shared__ unsigned long long lds[4];
+    const int64_t base = (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    unsigned long long loc = 0;
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t i = base + j;
+        v[j] = i < count ? in[i] : 0u;
+        loc += v[j];
+    }
+    unsigned long long tot;
+    unsigned long long run = block_exclusive_scan<unsigned long long>(loc, lds, &tot);
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t i = base + j;
+        if (i < count) out[i] = run;
+        run += v[j];
+    }
+    if (threadIdx.x == 0) out[count] = tot;
+}
+
 qw_status launch_scan_u32_to_u64(const uint32_t *in, int64_t count, unsigned long long *out,
                                  DevBuf &scratch, hipStream_t s)
 {
@@ -335,12 +359,17 @@ qw_status radix_sort_pairs(unsigned long long *keys, int32_t *vals, int64_t coun
     for (int shift = bit_lo; shift < bits; shift += 8) {
         rs_hist_kernel<<<(unsigned)ntiles, kBlock, 0, s>>>(kin, count, shift, h32, ntiles);
         QW_HIP(hipGetLastError());
-        scan_tile_sums<<<(unsigned)scan_tiles, kBlock, 0, s>>>(h32, nh, sums);
-        QW_HIP(hipGetLastError());
-        scan_sums_single<<<1, kBlock, 0, s>>>(sums, scan_tiles);
-        QW_HIP(hipGetLastError());
-        scan_tile_apply<<<(unsigned)scan_tiles, kBlock, 0, s>>>(h32, nh, sums, off64, scan_tiles);
-        QW_HIP(hipGetLastError());
+        if (scan_tiles == 1) {
+            scan_small_kernel<<<1, kBlock, 0, s>>>(h32, nh, off64);
+            QW_HIP(hipGetLastError());
+        } else {
+            scan_tile_sums<<<(unsigned)scan_tiles, kBlock, 0, s>>>(h32, nh, sums);
+            QW_HIP(hipGetLastError());
+            scan_sums_single<<<1, kBlock, 0, s>>>(sums, scan_tiles);
+            QW_HIP(hipGetLastError());
+            scan_tile_apply<<<(unsigned)scan_tiles, kBlock, 0, s>>>(h32, nh, sums, off64, scan_tiles);
+            QW_HIP(hipGetLastError());
+        }
         rs_scatter_kernel<<<(unsigned)ntiles, kBlock, 0, s>>>(kin, vin, count, shift, off64,
                                                               ntiles, kout, vout);
         QW_HIP(hipGetLastError());

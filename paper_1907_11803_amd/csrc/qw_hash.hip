@@ -14,15 +14,44 @@ namespace qw {
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
-// FP64, index order, correctly rounded steps: the reference sequence.
+// FP64, index order, correctly rounded steps: the reference sequence.  Rows
+// are padded to a multiple of 16 elements, so the inputs are read 16 at a time
+// with 16-byte loads; the summation still runs i = 0..d-1 in order.
+__device__ inline void load16(const uint8_t *p, float *v)
+{
+    const uint4 w = *reinterpret_cast<const uint4 *>(p);
+    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int t = 0; t < 16; ++t) v[t] = (float)((ws[t >> 2] >> (8 * (t & 3))) & 255u);
+}
+
+__device__ inline void load16(const float *p, float *v)
+{
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const float4 f = reinterpret_cast<const float4 *>(p)[t];
+        v[4 * t] = f.x;
+        v[4 * t + 1] = f.y;
+        v[4 * t + 2] = f.z;
+        v[4 * t + 3] = f.w;
+    }
+}
+
 template <typename T>
 __device__ __noinline__ int32_t hash_exact(const T *__restrict__ xrow,
                                            const float *__restrict__ arow, int32_t d, float bf,
                                            double w)
 {
     double acc = 0.0;
-    for (int32_t i = 0; i < d; ++i)
-        acc = __dadd_rn(acc, __dmul_rn((double)arow[i], (double)xrow[i]));
+    for (int32_t i0 = 0; i0 < d; i0 += 16) {
+        float xv[16], av[16];
+        load16(xrow + i0, xv);
+        load16(arow + i0, av);
+        const int32_t lim = d - i0 < 16 ? d - i0 : 16;
+#pragma unroll
+        for (int t = 0; t < 16; ++t)
+            if (t < lim) acc = __dadd_rn(acc, __dmul_rn((double)av[t], (double)xv[t]));
+    }
     double t = __dadd_rn(acc, (double)bf);
     double y = __ddiv_rn(t, w);
     return floor_to_i32(y);

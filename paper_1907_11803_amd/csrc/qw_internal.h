@@ -174,12 +174,14 @@ struct VerifyArgs {
     int32_t L, d, dp, dtype, K, mode;
     const void *data, *queries;
     uint32_t cap_log2;           // hash-set capacity 2^cap_log2
-    uint32_t limit;              // abort when more unique ids than this (overflow)
+    uint32_t limit;              // abort when more unique ids than this (overflow); <= 3/4 capacity
     uint32_t buf;                // top-K buffer entries (power of two)
     int32_t global_tab;          // 1: hash set in global scratch
-    uint32_t *gscratch;          // global scratch (global_tab)
-    uint32_t *ovf_count;         // overflow queue
+    uint32_t *gscratch;          // global scratch (global_tab): 2^cap_log2 words per workgroup
+    uint32_t *ovf_count;         // queue receiving queries whose set overflowed
     int32_t *ovf_list;
+    const uint32_t *in_count;    // nullable: queue of queries this launch serves after its segment
+    const int32_t *in_list;
     int32_t *out_ids;            // TOPK: [Q][K]; LIST: concatenated lists
     void *out_dist;              // TOPK
     int32_t *out_counts;         // COUNT

@@ -42,6 +42,8 @@ __device__ inline float bf16_round(float x)
     return __uint_as_float(u & 0xFFFF0000u);
 }
 
+// One thread per query; the H hidden pre-activations live in registers (static
+// indices) while the L inputs stream in.
 __global__ __launch_bounds__(kBlock) void mlp_predict_bf16_kernel(const float *__restrict__ params,
                                                                   int32_t L,
                                                                   const float *__restrict__ feats,
@@ -58,15 +60,19 @@ __global__ __launch_bounds__(kBlock) void mlp_predict_bf16_kernel(const float *_
     const float b2 = sw[P - 1];
     for (int64_t q = blockIdx.x * (int64_t)kBlock + threadIdx.x; q < B;
          q += (int64_t)gridDim.x * kBlock) {
-        float f[kMaxL];
-        for (int l = 0; l < L; ++l) f[l] = bf16_round(feats[q * L + l]);
+        float z[H];
+#pragma unroll
+        for (int h = 0; h < H; ++h) z[h] = 0.f;
+        for (int l = 0; l < L; ++l) {
+            const float f = bf16_round(feats[q * L + l]);
+#pragma unroll
+            for (int h = 0; h < H; ++h) z[h] = fmaf(W1[h * L + l], f, z[h]);
+        }
         float y = 0.f;
+#pragma unroll
         for (int h = 0; h < H; ++h) {
-            float z = 0.f;
-            for (int l = 0; l < L; ++l) z = fmaf(W1[h * L + l], f[l], z);
-            z += b1[h];
-            const float a = bf16_round(z > 0.f ? z : 0.f);
-            y = fmaf(W2[h], a, y);
+            const float zz = z[h] + b1[h];
+            y = fmaf(W2[h], bf16_round(zz > 0.f ? zz : 0.f), y);
         }
         out[q] = y + b2;
     }

@@ -20,17 +20,21 @@ __device__ inline uint32_t mix32(uint64_t x)
     return (uint32_t)x;
 }
 
-// Size class of every query from its predicted number of unique candidates:
-// 2^c >= 2 * need, c >= cmin.  Classes 0 .. ncls-2 are LDS classes
-// (c = cmin + class), class ncls-1 holds the hash set in global memory.
-__global__ void classify_kernel(int64_t Q, int32_t L, int64_t n, const uint32_t *__restrict__ qsum,
-                                const uint32_t *__restrict__ bstart,
-                                const uint32_t *__restrict__ bsize,
-                                const int32_t *__restrict__ exact, const float *__restrict__ pred_log,
-                                float margin, int32_t force_max, int32_t cmin, int32_t cmax,
-                                int32_t ncls, int32_t group, unsigned long long *__restrict__ keys,
-                                int32_t *__restrict__ vals, unsigned long long *class_count)
+// Size class of every query from its predicted number of unique candidates
+// `need`: the smallest c >= cmin with 3/4 * 2^c >= need (hash-set load factor
+// <= 3/4).  Classes 0 .. ncls-2 are LDS classes (c = cmin + class), class
+// ncls-1 keeps its set in global memory.  Key = class << 16 | 16-bit group.
+__global__ __launch_bounds__(kBlock) void classify_kernel(
+    int64_t Q, int32_t L, int64_t n, const uint32_t *__restrict__ qsum,
+    const uint32_t *__restrict__ bstart, const uint32_t *__restrict__ bsize,
+    const int32_t *__restrict__ exact, const float *__restrict__ pred_log, float margin,
+    int32_t force_max, int32_t cmin, int32_t cmax, int32_t ncls, int32_t group,
+    unsigned long long *__restrict__ keys, int32_t *__restrict__ vals,
+    unsigned long long *class_count)
 {
+    __shared__ uint32_t hist[32];
+    if (threadIdx.x < 32) hist[threadIdx.x] = 0;
+    __syncthreads();
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < Q;
          q += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t bound = min((uint64_t)qsum[q], (uint64_t)n);
@@ -42,23 +46,25 @@ __global__ void classify_kernel(int64_t Q, int32_t L, int64_t n, const uint32_t 
             if (p == p && p < (float)need) need = p > 0.f ? (uint64_t)ceilf(p) : 0;
         }
         int c = cmin;
-        while (c < 40 && (1ull << c) < 2 * need) ++c;
+        while (c < 40 && (3ull << c) < 4 * need) ++c;
         if (force_max && c <= cmax) c = cmax;
         const int cls = c <= cmax ? c - cmin : ncls - 1;
         uint32_t g = 0;
         if (group) {
             for (int32_t l = 0; l < L; ++l) {
-                const uint32_t sz = bsize[q * L + l];
-                if (sz) {
-                    g = mix32(((uint64_t)l << 32) | bstart[q * L + l]) & 0xFFFFFFu;
+                if (bsize[q * L + l]) {
+                    g = mix32(((uint64_t)l << 32) | bstart[q * L + l]) & 0xFFFFu;
                     break;
                 }
             }
         }
-        keys[q] = ((unsigned long long)cls << 24) | g;
+        keys[q] = ((unsigned long long)cls << 16) | g;
         vals[q] = (int32_t)q;
-        atomicAdd(&class_count[cls], 1ull);
+        atomicAdd(&hist[cls], 1u);
     }
+    __syncthreads();
+    if (threadIdx.x < ncls && hist[threadIdx.x])
+        atomicAdd(&class_count[threadIdx.x], (unsigned long long)hist[threadIdx.x]);
 }
 
 qw_status launch_classify(int64_t Q, int32_t L, int64_t n, const uint32_t *qsum,
@@ -68,7 +74,7 @@ qw_status launch_classify(int64_t Q, int32_t L, int64_t n, const uint32_t *qsum,
                           int32_t *vals, unsigned long long *class_count, hipStream_t s)
 {
     if (Q <= 0) return QW_OK;
-    int g = (int)std::min<int64_t>(4096, ceil_div(Q, kBlock));
+    int g = (int)std::min<int64_t>(1024, ceil_div(Q, kBlock));
     classify_kernel<<<g, kBlock, 0, s>>>(Q, L, n, qsum, bstart, bsize, exact, pred_log, margin,
                                          force_max, cmin, cmax, ncls, group, keys, vals,
                                          class_count);

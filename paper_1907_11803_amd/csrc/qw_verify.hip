@@ -7,35 +7,44 @@
 // K smallest by (distance, id) are returned (the c-k-ANN output, Section 3).
 //
 // Phase 1 (dedup): the workgroup streams the concatenated bucket id lists
-//   (coalesced) and inserts every id into an open-addressing hash set (LDS, or
-//   global scratch for very large queries).  The lane that claims a slot owns a
-//   new candidate; a wavefront ballot compacts new ids into a dense list with
-//   one LDS atomic per wave.
+//   (coalesced, four positions per thread in flight) and inserts every id into
+//   an open-addressing hash set (LDS, load factor <= 3/4, or global scratch for
+//   very large queries).  Wavefront reductions count the new ids with one LDS
+//   atomic per wave.  The set is then compacted in place into a dense list with
+//   wavefront ballots.
 // Phase 2 (verify): groups of G lanes gather candidate rows (16 bytes per lane
-//   per load, several candidates in flight per lane) and reduce the distance
+//   per load, up to eight candidates in flight per lane) and reduce the distance
 //   across the group.  uint8 rows: exact int32 via dot4 (|x|^2 - 2 x.q + |q|^2).
 //   float rows: FP32 with a proven relative error bound eps.
-// Phase 3 (top-K): group leaders append (distance, id) entries under a
-//   threshold to an LDS buffer; a bitonic sort keeps the K best whenever it
-//   fills.  For float data every entry kept is first re-ranked by its FP64
-//   index-order distance, and the admission threshold is the K-th FP64 distance
-//   times (1 + eps), so no candidate of the exact top-K is ever rejected.
+// Phase 3 (top-K): group leaders append entries under a threshold to an LDS
+//   buffer; a bitonic sort keeps the K best whenever it fills.  For float data
+//   every kept entry is first re-ranked by its FP64 index-order distance, and the
+//   admission threshold is the K-th FP64 distance times (1 + eps), so no member
+//   of the exact top-K is ever rejected.
+//
+// Work items: a launch serves a segment of the scheduled order plus a queue of
+// queries that overflowed a smaller hash set; a query whose unique candidates
+// exceed this launch's set is appended to the next launch's queue.
 #include "qw_internal.h"
 
 namespace qw {
 
-struct TopEntry {
-    unsigned long long pri;  // u8: distance; f32: FP32 bits (unranked) / FP64 bits (ranked)
+struct TopF {  // float data entry
+    unsigned long long pri;  // FP32 bits (unranked) or FP64 bits (ranked)
     uint32_t id;
-    uint32_t flag;           // 1 = unranked FP32 entry
+    uint32_t flag;           // 1 = unranked
 };
 
-enum { S_ITEM = 0, S_UCOUNT, S_OVF, S_BUFCOUNT, S_THR, S_QQ, S_T, S_CAP, S_NSCAL = 16 };
+template <int DT> struct TopT;
+template <> struct TopT<QW_U8> { using type = unsigned long long; };  // (dist << 32) | id
+template <> struct TopT<QW_F32> { using type = TopF; };
+
+enum { S_ITEM = 0, S_UCOUNT, S_OVF, S_BUFCOUNT, S_THR, S_QQ, S_T, S_CAP, S_CPOS, S_NSCAL = 16 };
 
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
 
 struct LdsLayout {
-    size_t buf, q, tab, list, lpref, lstart, scal, total;
+    size_t buf, q, tab, lpref, lstart, scal, total;
 };
 
 __host__ __device__ inline LdsLayout lds_layout(int cap_log2, int buf, int global_tab, int L,
@@ -43,11 +52,11 @@ __host__ __device__ inline LdsLayout lds_layout(int cap_log2, int buf, int globa
 {
     LdsLayout o;
     const size_t cap = size_t(1) << cap_log2;
+    const size_t esz = dtype == QW_U8 ? 8 : 16;
     o.buf = 0;
-    o.q = o.buf + align16(size_t(buf) * sizeof(TopEntry));
+    o.q = o.buf + align16(size_t(buf) * esz);
     o.tab = o.q + align16(size_t(dp) * (dtype == QW_U8 ? 1 : 4));
-    o.list = o.tab + (global_tab ? 0 : cap * 4);
-    o.lpref = o.list + (global_tab ? 0 : (cap / 2) * 4);
+    o.lpref = o.tab + (global_tab ? 0 : cap * 4);
     o.lstart = o.lpref + align16(size_t(L + 1) * 4);
     o.scal = o.lstart + align16(size_t(L) * 4);
     o.total = o.scal + S_NSCAL * 4;
@@ -59,9 +68,17 @@ size_t verify_lds_bytes(int cap_log2, int buf, int global_tab, int L, int dp, in
     return lds_layout(cap_log2, buf, global_tab, L, dp, dtype).total;
 }
 
-__device__ inline bool entry_less(const TopEntry &a, const TopEntry &b)
+__device__ inline bool entry_less(unsigned long long a, unsigned long long b) { return a < b; }
+__device__ inline bool entry_less(const TopF &a, const TopF &b)
 {
     return a.pri < b.pri || (a.pri == b.pri && a.id < b.id);
+}
+__device__ inline void entry_sentinel(unsigned long long &e) { e = ~0ull; }
+__device__ inline void entry_sentinel(TopF &e)
+{
+    e.pri = ~0ull;
+    e.id = 0xFFFFFFFFu;
+    e.flag = 0;
 }
 
 // FP64 index-order squared distance (the reference sequence; no contraction).
@@ -85,7 +102,7 @@ enum { INS_NEW = 0, INS_DUP = 1, INS_FULL = 2 };
 __device__ inline int set_insert(uint32_t *tab, int cap_log2, uint32_t id)
 {
     const uint32_t mask = (1u << cap_log2) - 1u;
-    uint32_t slot = cap_log2 ? hash_id(id, cap_log2) : 0u;
+    uint32_t slot = hash_id(id, cap_log2);
     for (uint32_t it = 0; it <= mask; ++it) {
         uint32_t old = atomicCAS(&tab[slot], kEmpty, id);
         if (old == kEmpty) return INS_NEW;
@@ -95,15 +112,16 @@ __device__ inline int set_insert(uint32_t *tab, int cap_log2, uint32_t id)
     return INS_FULL;
 }
 
-// Compact the top-K buffer: rank unranked float entries in FP64, sort, keep K,
-// update the admission threshold.  Called by the whole workgroup.
+// Compact the top-K buffer: rank unranked float entries in FP64, sort the live
+// entries, keep K, update the admission threshold.  Whole workgroup.
 template <int DT>
-__device__ void topk_compact(TopEntry *buf, uint32_t *scal, int nbuf, int K,
+__device__ void topk_compact(typename TopT<DT>::type *buf, uint32_t *scal, int nbuf, int K,
                              const void *data, int32_t dp, int32_t d, const float *qrow, float eps)
 {
+    using E = typename TopT<DT>::type;
     __syncthreads();
     const int n_e = (int)scal[S_BUFCOUNT];
-    if (DT == QW_F32) {
+    if constexpr (DT == QW_F32) {
         for (int e = threadIdx.x; e < n_e; e += kBlock) {
             if (buf[e].flag) {
                 const float *x = (const float *)data + (int64_t)buf[e].id * dp;
@@ -113,19 +131,18 @@ __device__ void topk_compact(TopEntry *buf, uint32_t *scal, int nbuf, int K,
             }
         }
     }
-    for (int e = n_e + threadIdx.x; e < nbuf; e += kBlock) {
-        buf[e].pri = ~0ull;
-        buf[e].id = 0xFFFFFFFFu;
-        buf[e].flag = 0;
-    }
+    int nsort = 2;
+    while (nsort < n_e) nsort <<= 1;
+    if (nsort > nbuf) nsort = nbuf;
+    for (int e = n_e + threadIdx.x; e < nsort; e += kBlock) entry_sentinel(buf[e]);
     __syncthreads();
-    for (int size = 2; size <= nbuf; size <<= 1) {
+    for (int size = 2; size <= nsort; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = threadIdx.x; i < nbuf / 2; i += kBlock) {
+            for (int i = threadIdx.x; i < nsort / 2; i += kBlock) {
                 const int lo = 2 * i - (i & (stride - 1));
                 const int hi = lo + stride;
                 const bool asc = (lo & size) == 0;
-                TopEntry a = buf[lo], b = buf[hi];
+                E a = buf[lo], b = buf[hi];
                 if (entry_less(b, a) == asc) {
                     buf[lo] = b;
                     buf[hi] = a;
@@ -138,8 +155,8 @@ __device__ void topk_compact(TopEntry *buf, uint32_t *scal, int nbuf, int K,
         const int keep = n_e < K ? n_e : K;
         scal[S_BUFCOUNT] = (uint32_t)keep;
         if (keep == K) {
-            if (DT == QW_U8) {
-                scal[S_THR] = (uint32_t)buf[K - 1].pri;
+            if constexpr (DT == QW_U8) {
+                scal[S_THR] = (uint32_t)(buf[K - 1] >> 32);
             } else {
                 const double DK = __longlong_as_double((long long)buf[K - 1].pri);
                 const double t = DK * (1.0 + (double)eps) + (d + 1) * 0x1p-100;
@@ -155,18 +172,18 @@ __device__ void topk_compact(TopEntry *buf, uint32_t *scal, int nbuf, int K,
 template <int DT, int UN, int PM>
 __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
 {
+    using E = typename TopT<DT>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x, lane = tid & 63;
     const int glob = A.global_tab;
     const LdsLayout lay = lds_layout((int)A.cap_log2, (int)A.buf, glob, A.L, A.dp, A.dtype);
-    TopEntry *buf = reinterpret_cast<TopEntry *>(smem + lay.buf);
+    E *buf = reinterpret_cast<E *>(smem + lay.buf);
     uint32_t *lpref = reinterpret_cast<uint32_t *>(smem + lay.lpref);
     uint32_t *lstart = reinterpret_cast<uint32_t *>(smem + lay.lstart);
     uint32_t *scal = reinterpret_cast<uint32_t *>(smem + lay.scal);
     const size_t gcap = size_t(1) << A.cap_log2;
-    uint32_t *tab = glob ? A.gscratch + (size_t)blockIdx.x * (gcap + gcap / 2)
+    uint32_t *tab = glob ? A.gscratch + (size_t)blockIdx.x * gcap
                          : reinterpret_cast<uint32_t *>(smem + lay.tab);
-    uint32_t *list = glob ? tab + gcap : reinterpret_cast<uint32_t *>(smem + lay.list);
 
     const int elem = DT == QW_U8 ? 1 : 4;
     const int row_bytes = A.dp * elem;
@@ -182,28 +199,37 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
     // adds per lane, log2(G) <= 6 tree levels; plus the FP64 reference's own error
     const float eps = (float)((4 * P + 16) * 0x1p-24 + (A.d + 2) * 0x1p-52);
 
-    int64_t begin = 0, end = A.nitems;
+    // item space: [0, nseg) from the scheduled order, then [nseg, nseg + nin)
+    // from the queue of queries that overflowed a smaller set
+    int64_t sbeg = 0, nseg = A.nitems;
     if (A.seg) {
-        begin = (int64_t)A.seg[0];
-        end = (int64_t)A.seg[1];
+        sbeg = (int64_t)A.seg[0];
+        nseg = (int64_t)A.seg[1] - sbeg;
     } else if (A.nitems_dev) {
-        end = (int64_t)*A.nitems_dev;
+        nseg = (int64_t)*A.nitems_dev;
     }
-    int64_t first = A.counter ? -1 : begin + blockIdx.x;
+    const int64_t nin = A.in_count ? (int64_t)*A.in_count : 0;
+    const int64_t nall = nseg + nin;
+    int64_t first = A.counter ? -1 : (int64_t)blockIdx.x;
 
     while (true) {
         if (tid == 0) {
-            int64_t it = A.counter ? begin + (int64_t)atomicAdd(A.counter, 1u) : first;
-            scal[S_ITEM] = it < end ? (uint32_t)(it - begin) : 0xFFFFFFFFu;
+            int64_t it = A.counter ? (int64_t)atomicAdd(A.counter, 1u) : first;
+            scal[S_ITEM] = it < nall ? (uint32_t)it : 0xFFFFFFFFu;
         }
         __syncthreads();
         if (scal[S_ITEM] == 0xFFFFFFFFu) break;
-        const int64_t item = begin + scal[S_ITEM];
-        first = end;  // non-persistent launches serve one item
-        const int64_t q = A.order ? (int64_t)A.order[item] : item;
+        const int64_t item = scal[S_ITEM];
+        first = nall;  // non-persistent launches serve one item
+        int64_t q;
+        if (item < nseg) {
+            const int64_t o = sbeg + item;
+            q = A.order ? (int64_t)A.order[o] : o;
+        } else {
+            q = (int64_t)A.in_list[item - nseg];
+        }
 
         // ---- per-query setup
-        int cap_log2 = (int)A.cap_log2;
         if (tid < A.L) {
             lstart[tid] = A.bstart[q * A.L + tid];
             lpref[tid + 1] = A.bsize[q * A.L + tid];
@@ -215,6 +241,7 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
             scal[S_BUFCOUNT] = 0;
             scal[S_THR] = DT == QW_U8 ? 0xFFFFFFFFu : __float_as_uint(INFINITY);
             scal[S_QQ] = 0;
+            scal[S_CPOS] = 0;
         }
         {  // query row into LDS (+ |q|^2 for uint8)
             const uint4 *src = reinterpret_cast<const uint4 *>((const unsigned char *)A.queries +
@@ -241,61 +268,93 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
                 lpref[l + 1] = run;
             }
             scal[S_T] = run;
-            int c = cap_log2;
-            if (glob) {  // hash set sized from the exact bound min(sum_l s_{q,l}, n)
+            int c = (int)A.cap_log2;
+            if (glob) {  // set sized from the exact bound min(sum_l s_{q,l}, n)
                 const uint64_t bound = min((uint64_t)run, (uint64_t)A.n);
                 c = 10;
-                while (c < (int)A.cap_log2 && (1ull << c) < 2 * bound) ++c;
+                while (c < (int)A.cap_log2 && (3ull << c) < 4 * bound) ++c;
             }
             scal[S_CAP] = (uint32_t)c;
         }
         __syncthreads();
-        cap_log2 = (int)scal[S_CAP];
+        const int cap_log2 = (int)scal[S_CAP];
         const uint32_t cap = 1u << cap_log2;
-        const uint32_t limit = glob ? cap / 2 : (A.limit < cap / 2 ? A.limit : cap / 2);
-        for (uint32_t i = tid; i < cap; i += kBlock) tab[i] = kEmpty;
+        const uint32_t set_limit = (cap >> 2) * 3;  // load factor <= 3/4
+        const uint32_t limit = glob ? set_limit : (A.limit < set_limit ? A.limit : set_limit);
+        const uint32_t T = A.mode == VM_ALL ? 0u : scal[S_T];
+        if (A.mode != VM_ALL)
+            for (uint32_t i = tid; i < cap; i += kBlock) tab[i] = kEmpty;
         if (glob) __threadfence();
         __syncthreads();
 
         // ---- phase 1: de-duplicated union of the L bucket lists
-        const uint32_t T = A.mode == VM_ALL ? 0u : scal[S_T];
-        for (uint32_t base = 0; base < T; base += kBlock) {
-            const uint32_t pos = base + tid;
-            bool isnew = false;
-            uint32_t id = 0;
-            if (pos < T && !scal[S_OVF]) {
-                int lo = 0, hi = A.L;  // lpref[lo] <= pos < lpref[hi]
-                while (hi - lo > 1) {
-                    int mid = (lo + hi) >> 1;
-                    if (lpref[mid] <= pos) lo = mid; else hi = mid;
+        for (uint32_t base = 0; base < T; base += 4 * kBlock) {
+            // every thread reads the flag before any thread of this pass can set
+            // it, so the early exit is uniform
+            const bool stop = scal[S_OVF] != 0;
+            __syncthreads();
+            if (stop) break;
+            uint32_t ids4[4];
+            bool ok4[4];
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t pos = base + (uint32_t)(r * kBlock + tid);
+                ok4[r] = pos < T;
+                ids4[r] = 0;
+                if (ok4[r]) {
+                    int lo = 0, hi = A.L;  // lpref[lo] <= pos < lpref[hi]
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (lpref[mid] <= pos) lo = mid; else hi = mid;
+                    }
+                    ids4[r] = (uint32_t)A.ids[(int64_t)lo * A.n + lstart[lo] + (pos - lpref[lo])];
                 }
-                id = (uint32_t)A.ids[(int64_t)lo * A.n + lstart[lo] + (pos - lpref[lo])];
-                int r = set_insert(tab, cap_log2, id);
-                isnew = r == INS_NEW;
-                if (r == INS_FULL) scal[S_OVF] = 1;
             }
-            const unsigned long long m = __ballot(isnew);
-            const uint32_t cnt = (uint32_t)__popcll(m);
-            uint32_t wbase = 0;
-            if (lane == 0 && cnt) wbase = atomicAdd(&scal[S_UCOUNT], cnt);
-            wbase = (uint32_t)__shfl((int)wbase, 0);
-            if (isnew) {
-                const uint32_t idx = wbase + (uint32_t)__popcll(m & lt_mask);
-                if (idx < limit) list[idx] = id; else scal[S_OVF] = 1;
+            uint32_t nnew = 0;
+            bool full = false;
+            for (int r = 0; r < 4; ++r) {
+                if (!ok4[r]) continue;
+                const int res = set_insert(tab, cap_log2, ids4[r]);
+                nnew += res == INS_NEW;
+                full |= res == INS_FULL;
             }
+            // one LDS atomic per wave for the unique count
+            for (int off = 32; off > 0; off >>= 1) nnew += (uint32_t)__shfl_xor((int)nnew, off);
+            const bool anyfull = __ballot(full) != 0ull;
+            if (lane == 0 && (nnew || anyfull)) {
+                const uint32_t tot = atomicAdd(&scal[S_UCOUNT], nnew) + nnew;
+                if (tot > limit || anyfull) scal[S_OVF] = 1;
+            }
+            if (glob) __threadfence();
+            __syncthreads();
         }
-        if (glob) __threadfence();
-        __syncthreads();
         const uint32_t U = A.mode == VM_ALL ? (uint32_t)A.n : scal[S_UCOUNT];
         if (A.mode != VM_ALL && (scal[S_OVF] || U > limit)) {
             if (tid == 0) {
-                uint32_t o = atomicAdd(A.ovf_count, 1u);
+                const uint32_t o = atomicAdd(A.ovf_count, 1u);
                 A.ovf_list[o] = (int32_t)q;
             }
             __syncthreads();
             continue;
         }
-        if (tid == 0 && A.unique_total && A.mode != VM_ALL) atomicAdd(A.unique_total, (unsigned long long)U);
+        // compact the set in place: contents move only to lower positions that
+        // were read in this or an earlier round
+        if (A.mode != VM_ALL) {
+            for (uint32_t base = 0; base < cap; base += kBlock) {
+                const uint32_t v = tab[base + tid];
+                const bool occ = v != kEmpty;
+                if (glob) __threadfence();
+                __syncthreads();
+                const unsigned long long m = __ballot(occ);
+                uint32_t wb = 0;
+                if (lane == 0 && m) wb = atomicAdd(&scal[S_CPOS], (uint32_t)__popcll(m));
+                wb = (uint32_t)__shfl((int)wb, 0);
+                if (occ) tab[wb + (uint32_t)__popcll(m & lt_mask)] = v;
+            }
+            if (glob) __threadfence();
+            __syncthreads();
+        }
+        if (tid == 0 && A.unique_total && A.mode != VM_ALL)
+            atomicAdd(A.unique_total, (unsigned long long)U);
         if (A.mode == VM_COUNT) {
             if (tid == 0) A.out_counts[q] = (int32_t)U;
             __syncthreads();
@@ -303,7 +362,7 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
         }
         if (A.mode == VM_LIST) {
             const long long o = A.offsets[q];
-            for (uint32_t i = tid; i < U; i += kBlock) A.out_ids[o + i] = (int32_t)list[i];
+            for (uint32_t i = tid; i < U; i += kBlock) A.out_ids[o + i] = (int32_t)tab[i];
             __syncthreads();
             continue;
         }
@@ -327,7 +386,7 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
             for (int u = 0; u < UN; ++u) {
                 const uint32_t c = c0 + grp + (uint32_t)(NG * u);
                 cv[u] = c < U;
-                cid[u] = cv[u] ? (A.mode == VM_ALL ? c : list[c]) : 0u;
+                cid[u] = cv[u] ? (A.mode == VM_ALL ? c : tab[c]) : 0u;
             }
             uint32_t accu[UN];
             float accf[UN];
@@ -391,24 +450,19 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
             if (j == 0) {
                 for (int u = 0; u < UN; ++u) {
                     if (!cv[u]) continue;
-                    bool admit;
-                    unsigned long long pri;
-                    uint32_t flag;
-                    if (DT == QW_U8) {
+                    if constexpr (DT == QW_U8) {
                         const uint32_t dist = accu[u] + qq;
-                        admit = dist <= thr;
-                        pri = dist;
-                        flag = 0;
+                        if (dist <= thr) {
+                            const uint32_t e = atomicAdd(&scal[S_BUFCOUNT], 1u);
+                            buf[e] = ((unsigned long long)dist << 32) | cid[u];
+                        }
                     } else {
-                        admit = accf[u] <= __uint_as_float(thr);
-                        pri = __float_as_uint(accf[u]);
-                        flag = 1;
-                    }
-                    if (admit) {
-                        const uint32_t e = atomicAdd(&scal[S_BUFCOUNT], 1u);
-                        buf[e].pri = pri;
-                        buf[e].id = cid[u];
-                        buf[e].flag = flag;
+                        if (accf[u] <= __uint_as_float(thr)) {
+                            const uint32_t e = atomicAdd(&scal[S_BUFCOUNT], 1u);
+                            buf[e].pri = __float_as_uint(accf[u]);
+                            buf[e].id = cid[u];
+                            buf[e].flag = 1;
+                        }
                     }
                 }
             }
@@ -419,12 +473,14 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
         for (int r = tid; r < A.K; r += kBlock) {
             const int64_t o = q * A.K + r;
             if (r < keep) {
-                A.out_ids[o] = (int32_t)buf[r].id;
-                if (DT == QW_U8)
-                    reinterpret_cast<int32_t *>(A.out_dist)[o] = (int32_t)buf[r].pri;
-                else
+                if constexpr (DT == QW_U8) {
+                    A.out_ids[o] = (int32_t)(uint32_t)buf[r];
+                    reinterpret_cast<int32_t *>(A.out_dist)[o] = (int32_t)(buf[r] >> 32);
+                } else {
+                    A.out_ids[o] = (int32_t)buf[r].id;
                     reinterpret_cast<float *>(A.out_dist)[o] =
                         (float)__longlong_as_double((long long)buf[r].pri);
+                }
             } else {
                 A.out_ids[o] = -1;
                 if (DT == QW_U8)
@@ -437,25 +493,32 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
     }
 }
 
+static bool one_part_per_lane(int dp, int dtype)
+{
+    return dp * (dtype == QW_U8 ? 1 : 4) / 16 <= 64;
+}
+
 int verify_per_iter(int dp, int dtype)
 {
     const int parts = dp * (dtype == QW_U8 ? 1 : 4) / 16;
     int G = 1;
     while (G < parts && G < 64) G <<= 1;
-    return (kBlock / G) * (parts <= 64 ? 4 : 2);
+    return (kBlock / G) * (one_part_per_lane(dp, dtype) ? 8 : 2);
+}
+
+static const void *verify_fn(int dp, int dtype)
+{
+    const bool small = one_part_per_lane(dp, dtype);
+    if (dtype == QW_U8)
+        return small ? (const void *)verify_kernel<QW_U8, 8, 1> : (const void *)verify_kernel<QW_U8, 2, 4>;
+    return small ? (const void *)verify_kernel<QW_F32, 8, 1> : (const void *)verify_kernel<QW_F32, 2, 4>;
 }
 
 int verify_blocks_per_cu(int dp, int dtype, size_t lds)
 {
-    const int parts = dp * (dtype == QW_U8 ? 1 : 4) / 16;
-    const bool small = parts <= 64;
-    const void *fn;
-    if (dtype == QW_U8)
-        fn = small ? (const void *)verify_kernel<QW_U8, 4, 1> : (const void *)verify_kernel<QW_U8, 2, 4>;
-    else
-        fn = small ? (const void *)verify_kernel<QW_F32, 4, 1> : (const void *)verify_kernel<QW_F32, 2, 4>;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, lds) != hipSuccess) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, verify_fn(dp, dtype), kBlock, lds) !=
+        hipSuccess) {
         (void)hipGetLastError();
         nb = 1;
     }
@@ -467,17 +530,15 @@ qw_status launch_verify(const VerifyArgs &a, int grid, hipStream_t s)
     if (grid <= 0) return QW_OK;
     const size_t lds = verify_lds_bytes((int)a.cap_log2, (int)a.buf, a.global_tab, a.L, a.dp,
                                         a.dtype);
-    const int row_bytes = a.dp * (a.dtype == QW_U8 ? 1 : 4);
-    const int parts = row_bytes / 16;
-    const bool small = parts <= 64;  // one part per lane
+    const bool small = one_part_per_lane(a.dp, a.dtype);
     if (a.dtype == QW_U8) {
         if (small)
-            verify_kernel<QW_U8, 4, 1><<<grid, kBlock, lds, s>>>(a);
+            verify_kernel<QW_U8, 8, 1><<<grid, kBlock, lds, s>>>(a);
         else
             verify_kernel<QW_U8, 2, 4><<<grid, kBlock, lds, s>>>(a);
     } else {
         if (small)
-            verify_kernel<QW_F32, 4, 1><<<grid, kBlock, lds, s>>>(a);
+            verify_kernel<QW_F32, 8, 1><<<grid, kBlock, lds, s>>>(a);
         else
             verify_kernel<QW_F32, 2, 4><<<grid, kBlock, lds, s>>>(a);
     }

@@ -1,0 +1,108 @@
+"""Parity at the configurations' full sizes, in the launch configuration that
+bench.py times: fast form, learned schedule (a count model trained on the
+engine's own features), bucket grouping, HIP graph replay.
+
+The GPU answers the whole workload; the oracle checks every output where it
+finishes in seconds (1M-point uint8 workload) and a seeded sample of outputs
+otherwise (it answers the sampled queries one by one against its own index of
+all points).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1907_11803_amd import lib, synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+I32MAX = np.iinfo(np.int32).max
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def bench_opts():
+    return lib.make_opts(form=lib.QW_FORM_FAST, sched=lib.QW_SCHED_LEARNED, group=1, graph=1)
+
+
+def compare(ids_g, dist_g, ids_o, dist_o, rows, is_u8):
+    ids_g = ids_g.cpu().numpy()[rows]
+    dist_g = dist_g.cpu().numpy()[rows]
+    bad = np.argwhere(ids_g != ids_o)
+    assert bad.size == 0, f"{len(bad)} mismatching ids, first {bad[:3].tolist()}"
+    if is_u8:
+        want = np.where(dist_o == np.iinfo(np.int64).max, I32MAX, dist_o)
+        assert np.array_equal(dist_g.astype(np.int64), want)
+    else:
+        fin = np.isfinite(dist_o)
+        assert np.array_equal(np.isfinite(dist_g), fin)
+        assert np.array_equal(dist_g[fin], dist_o[fin].astype(np.float32))
+        np.testing.assert_allclose(dist_g[fin], dist_o[fin], rtol=1e-5)
+
+
+def run_gpu(wl, w, train, queries=None):
+    p = wl.params
+    ix = lib.Index(dev(wl.data), dev(p.a), dev(p.b(w)), w)
+    if train is not None:
+        ix.train_count_model(dev(train), epochs=6, batch=1024, lr=2e-3, seed=1)
+    q = dev(wl.queries if queries is None else queries)
+    ids, dist = ix.query(q, wl.K, bench_opts())
+    ids2, dist2 = ix.query(q, wl.K, bench_opts())  # graph replay
+    torch.cuda.synchronize()
+    assert torch.equal(ids, ids2) and torch.equal(dist, dist2)
+    ids_p, dist_p = ix.query(q, wl.K, lib.make_opts(form=lib.QW_FORM_PLAIN_FP32))
+    torch.cuda.synchronize()
+    assert torch.equal(ids, ids_p) and torch.equal(dist, dist_p)
+    ix.close()
+    return ids, dist
+
+
+@pytest.mark.timeout(240)
+@pytest.mark.parametrize("w", [400.0, 1200.0])
+def test_cfg2_full_every_query(w):
+    wl = synth.make_config(2)
+    train = synth.training_queries(2, 20_000)
+    ids, dist = run_gpu(wl, w, train)
+    bi = oracle.BuiltIndex(wl.data, wl.params.a, wl.params.b(w), w)
+    ids_o, dist_o, _ = bi.query(wl.queries, wl.K)
+    bi.close()
+    compare(ids, dist, ids_o, dist_o, np.arange(wl.Q), True)
+
+
+@pytest.mark.timeout(400)
+def test_cfg3_and_cfg5_full_sampled():
+    """1M x 960 float data: the 1,000 noisy-point queries at the stated and a
+    high-recall w, then 100,000 Zipf queries with the model trained on 200,000."""
+    wl = synth.make_config(3)
+    rng = np.random.default_rng(11)
+    for w in (1.5, 12.0):
+        ids, dist = run_gpu(wl, w, None)
+        rows = np.sort(rng.choice(wl.Q, size=200, replace=False))
+        bi = oracle.BuiltIndex(wl.data, wl.params.a, wl.params.b(w), w)
+        ids_o, dist_o, _ = bi.query(wl.queries[rows], wl.K)
+        if w == 12.0:
+            q5 = synth.make_config(5, n=1).queries  # the evaluation draws only
+            train5 = synth.training_queries(5, 200_000)
+            ids5, dist5 = run_gpu(wl, w, train5, queries=q5)
+            rows5 = np.sort(rng.choice(q5.shape[0], size=300, replace=False))
+            ids5_o, dist5_o, _ = bi.query(q5[rows5], wl.K)
+            compare(ids5, dist5, ids5_o, dist5_o, rows5, False)
+        bi.close()
+        compare(ids, dist, ids_o, dist_o, rows, False)
+
+
+@pytest.mark.timeout(400)
+def test_cfg4_full_sampled():
+    """10M x 96 uint8 data, 100,000 Zipf queries, at the stated w and 2x."""
+    wl = synth.make_config(4)
+    train = synth.training_queries(4, 50_000)
+    rng = np.random.default_rng(12)
+    for w in (350.0, 700.0):
+        ids, dist = run_gpu(wl, w, train)
+        rows = np.sort(rng.choice(wl.Q, size=1000, replace=False))
+        bi = oracle.BuiltIndex(wl.data, wl.params.a, wl.params.b(w), w)
+        ids_o, dist_o, _ = bi.query(wl.queries[rows], wl.K)
+        bi.close()
+        compare(ids, dist, ids_o, dist_o, rows, True)
