@@ -92,9 +92,12 @@ typedef struct {
     int64_t probes_hit;    /* (query, layer) probes that found a bucket */
     int64_t cand_total;    /* sum over queries and layers of the bucket sizes */
     int64_t cand_unique;   /* sum over queries of |C(q)| */
-    int64_t overflow;      /* queries re-run because their hash set was sized too small */
+    int64_t overflow;      /* queries moved to a larger hash set because theirs was sized too small */
+    int64_t fallback;      /* fast form: queries answered by the fused per-query path */
     int64_t bins[8];       /* queries per hash-set size class (fast form) */
-    float ms_stage[8];     /* timing=1: hash, probe, schedule, verify, overflow, total, -, - */
+    float ms_stage[8];     /* timing=1: hash, probe, schedule, candidates+verify+top-K,
+                              fallback, total, dedup+chunking (fast form), streaming verify
+                              (fast form) */
 } qw_stats;
 
 typedef struct {

@@ -15,12 +15,16 @@ namespace {
 
 // counters buffer: u64 [kC64] then u32 [kC32]
 enum {
-    C_RECOMP = 0, C_UNIQUE, C_PROBEHIT, C_CANDTOT, C_CLASS /* .. C_CLASS+15 */, kC64 = 24
+    C_RECOMP = 0, C_UNIQUE, C_PROBEHIT, C_CANDTOT, C_CLASS /* .. C_CLASS+15 */, C_ALLOC = 20,
+    kC64 = 24
 };
 // u32: persistent work counters per class, overflow-queue lengths per class
-// (queue i holds queries that overflowed class i-1), misc
+// (queue i holds queries that overflowed class i-1), per-XCD chunk counters,
+// fallback queue, misc
 enum { W_WORK = 0 /* .. 15 */, W_QCNT = 16 /* .. 32 */, W_SIMPLE = 33, W_MAX = 34, W_DUMMY = 35,
-       kC32 = 40 };
+       W_XCD = 36 /* .. 43 */, W_FB = 44, W_FBWORK = 45, kC32 = 48 };
+constexpr int kChunk = 1024;          // candidates per chunk of the streaming verify
+constexpr int64_t kCandPerQuery = 4096;  // list space reserved per query (beyond: fallback)
 constexpr int kCmin = 10;
 constexpr int kMaxClasses = 16;
 constexpr float kMargin = 1.25f;  // learned schedule: slack on the predicted count
@@ -68,6 +72,20 @@ Plan make_plan(qw_index *ix, int K)
     const double budget = 2.0 * 1024 * 1024 * 1024;
     p.grid_g = (int)std::max(1.0, std::min((double)ix->cus, std::floor(budget / per_wg)));
     p.grid[p.ncls - 1] = p.grid_g;
+    for (int i = 0; i + 1 < p.ncls; ++i)
+        p.dgrid[i] = dedup_blocks_per_cu(dedup_lds_bytes(kCmin + i, 0, ix->L)) * ix->cus;
+    p.dgrid[p.ncls - 1] = p.grid_g;
+    p.C = kChunk;
+    p.PS = ix->dtype == QW_U8 ? std::min(K, p.C) : std::min(p.C, std::max(2 * K, K + 16));
+    p.MB = pow2_at_least(std::max(2048, 4 * K));
+    p.fgrid = flat_blocks_per_cu(p.C, ix->dp, ix->dtype) * ix->cus;
+    {  // FP32 distance bound of the streaming verify kernel (float data)
+        const int parts = ix->dp * (ix->dtype == QW_U8 ? 1 : 4) / 16;
+        int G = 1;
+        while (G < parts && G < 64) G <<= 1;
+        const int P = (parts + G - 1) / G;
+        p.eps = (float)((4 * P + 16) * std::ldexp(1.0, -24) + (ix->d + 2) * std::ldexp(1.0, -52));
+    }
     ix->plans[K] = p;
     return p;
 }
@@ -77,10 +95,15 @@ Plan make_plan(qw_index *ix, int K)
 qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan)
 {
     Workspace &w = ix->ws;
-    std::vector<void *> before = {w.qpad.p, w.h.p, w.bstart.p, w.bsize.p, w.qsum.p, w.pred.p,
-                                  w.feats.p, w.keys.p, w.keys2.p, w.vals.p, w.vals2.p,
-                                  w.binoff.p, w.counters.p, w.ovf.p, w.gscratch.p, w.mlpout.p,
-                                  w.hist.p};
+    auto ptrs = [&w]() {
+        return std::vector<void *>{w.qpad.p, w.h.p, w.bstart.p, w.bsize.p, w.qsum.p, w.pred.p,
+                                   w.feats.p, w.keys.p, w.keys2.p, w.vals.p, w.vals2.p,
+                                   w.binoff.p, w.counters.p, w.ovf.p, w.gscratch.p, w.mlpout.p,
+                                   w.hist.p, w.scan.p, w.ucount.p, w.coff.p, w.flag.p,
+                                   w.nch_item.p, w.chunk_off.p, w.qcbeg.p, w.qnch.p, w.desc.p,
+                                   w.part.p, w.pcount.p, w.cand.p, w.fb.p};
+    };
+    const std::vector<void *> before = ptrs();
     const size_t elem = ix->dtype == QW_U8 ? 1 : 4;
     const int64_t q = std::max<int64_t>(Q, 1);
     QW_TRY(w.qpad.ensure(elem * (size_t)q * ix->dp));
@@ -99,15 +122,26 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan)
     QW_TRY(w.binoff.ensure(sizeof(unsigned long long) * 2 * kMaxClasses));
     QW_TRY(w.counters.ensure(sizeof(unsigned long long) * kC64 + sizeof(uint32_t) * kC32));
     QW_TRY(w.hist.ensure(radix_sort_scratch_bytes(q)));
+    QW_TRY(w.scan.ensure(scan_scratch_bytes(q)));
     if (plan) {
         const size_t g = (size_t)plan->grid_g * (size_t(1) << plan->cap_g) * 4;
         QW_TRY(w.gscratch.ensure(g));
+        const int64_t cand_cap = std::max<int64_t>(q * kCandPerQuery, 1 << 20);
+        const int64_t nchunk_cap = cand_cap / plan->C + q;
+        QW_TRY(w.ucount.ensure(sizeof(uint32_t) * q));
+        QW_TRY(w.coff.ensure(sizeof(unsigned long long) * q));
+        QW_TRY(w.flag.ensure(sizeof(uint32_t) * q));
+        QW_TRY(w.nch_item.ensure(sizeof(uint32_t) * q));
+        QW_TRY(w.chunk_off.ensure(sizeof(unsigned long long) * (q + 1)));
+        QW_TRY(w.qcbeg.ensure(sizeof(uint32_t) * q));
+        QW_TRY(w.qnch.ensure(sizeof(uint32_t) * q));
+        QW_TRY(w.desc.ensure(sizeof(unsigned long long) * nchunk_cap));
+        QW_TRY(w.part.ensure(sizeof(unsigned long long) * nchunk_cap * plan->PS));
+        QW_TRY(w.pcount.ensure(sizeof(uint32_t) * nchunk_cap));
+        QW_TRY(w.cand.ensure(sizeof(int32_t) * cand_cap));
+        QW_TRY(w.fb.ensure(sizeof(int32_t) * q));
     }
-    std::vector<void *> after = {w.qpad.p, w.h.p, w.bstart.p, w.bsize.p, w.qsum.p, w.pred.p,
-                                 w.feats.p, w.keys.p, w.keys2.p, w.vals.p, w.vals2.p,
-                                 w.binoff.p, w.counters.p, w.ovf.p, w.gscratch.p, w.mlpout.p,
-                                 w.hist.p};
-    if (before != after) drop_graphs(ix);
+    if (before != ptrs()) drop_graphs(ix);
     return QW_OK;
 }
 
@@ -205,6 +239,9 @@ qw_status check_index(const qw_index *ix)
     return QW_OK;
 }
 
+// Fast form: exact MFMA hashing, probe, schedule (size classes from the
+// selected count source, bucket grouping), per-class dedup into device-wide
+// candidate lists, chunked streaming verify, per-query merge, fallback.
 qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int64_t Q, int K,
                        const qw_opts &o, hipStream_t s, int32_t *out_ids, void *out_dist,
                        hipEvent_t *ev)
@@ -215,10 +252,10 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     QW_TRY(front(ix, queries, Q, QW_FORM_FAST, s, ev));
     if (ev) QW_HIP(hipEventRecord(ev[2], s));
     const bool learned = o.sched == QW_SCHED_LEARNED && !ix->mlp.empty();
-    const int32_t *exact = nullptr;
-    const float *pred_log = nullptr;
     unsigned long long *seg = w.binoff.as<unsigned long long>();
     unsigned long long *ccount = c64(ix) + C_CLASS;
+    int32_t *queues = w.ovf.as<int32_t>();
+    const int64_t cand_cap = (int64_t)(w.cand.bytes / sizeof(int32_t));
     auto schedule = [&](const int32_t *ex, const float *pl, int force_max,
                         const int32_t **order) -> qw_status {
         QW_TRY(launch_classify(Q, ix->L, ix->n, w.qsum.as<uint32_t>(), w.bstart.as<uint32_t>(),
@@ -236,10 +273,10 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     // Classes run from the smallest hash set to the global one.  Each launch
     // serves its segment of the order, then the queue of queries that
     // overflowed the previous class; its own overflows go to the next queue.
-    int32_t *queues = w.ovf.as<int32_t>();
-    auto run_classes = [&](const int32_t *order, int mode, int32_t *counts) -> qw_status {
+    auto dedup_classes = [&](const int32_t *order, int count_only) -> qw_status {
         for (int i = 0; i < plan.ncls; ++i) {
-            VerifyArgs a = base_args(ix, K, mode);
+            DedupArgs a;
+            std::memset(&a, 0, sizeof(a));
             a.order = order;
             a.seg = seg + 2 * i;
             a.counter = c32(ix) + W_WORK + i;
@@ -247,11 +284,19 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
             a.in_count = i > 0 ? c32(ix) + W_QCNT + i : nullptr;
             a.ovf_list = queues + (int64_t)(i + 1) * Q;
             a.ovf_count = c32(ix) + W_QCNT + i + 1;
-            a.buf = (uint32_t)plan.buf;
-            a.out_ids = out_ids;
-            a.out_dist = out_dist;
-            a.out_counts = counts;
-            a.unique_total = mode == VM_TOPK ? c64(ix) + C_UNIQUE : nullptr;
+            a.bstart = w.bstart.as<uint32_t>();
+            a.bsize = w.bsize.as<uint32_t>();
+            a.ids = ix->ids.as<int32_t>();
+            a.n = ix->n;
+            a.L = ix->L;
+            a.count_only = count_only;
+            a.alloc = c64(ix) + C_ALLOC;
+            a.cand_cap = (unsigned long long)cand_cap;
+            a.cand = w.cand.as<int32_t>();
+            a.ucount = w.ucount.as<uint32_t>();
+            a.coff = w.coff.as<unsigned long long>();
+            a.flag = w.flag.as<uint32_t>();
+            a.unique_total = count_only ? nullptr : c64(ix) + C_UNIQUE;
             if (i == plan.ncls - 1) {
                 a.cap_log2 = (uint32_t)plan.cap_g;
                 a.limit = (1u << plan.cap_g) / 4 * 3;
@@ -261,17 +306,19 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
                 a.cap_log2 = (uint32_t)(kCmin + i);
                 a.limit = (1u << (kCmin + i)) / 4 * 3;
             }
-            QW_TRY(launch_verify(a, plan.grid[i], s));
+            QW_TRY(launch_dedup(a, plan.dgrid[i], s));
         }
         return QW_OK;
     };
     const int32_t *order = nullptr;
-    if (o.sched == QW_SCHED_ACTUAL) {
+    const int32_t *exact = nullptr;
+    const float *pred_log = nullptr;
+    if (o.sched == QW_SCHED_ACTUAL) {  // extra counting pass: exact |C(q)|
         QW_TRY(schedule(nullptr, nullptr, 0, &order));
-        QW_TRY(run_classes(order, VM_COUNT, w.pred.as<int32_t>()));
+        QW_TRY(dedup_classes(order, 1));
         QW_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(ccount), 0u, 2 * kMaxClasses, s));
         QW_TRY(launch_fill_u32(c32(ix) + W_WORK, 0u, W_SIMPLE - W_WORK, s));
-        exact = w.pred.as<int32_t>();
+        exact = reinterpret_cast<const int32_t *>(w.ucount.p);
     } else if (learned) {
         QW_TRY(launch_mlp_features(w.bsize.as<uint32_t>(), Q, ix->L, w.feats.as<float>(), s));
         QW_TRY(launch_mlp_predict_bf16(ix->mlp_dev.as<float>(), ix->L, w.feats.as<float>(), Q,
@@ -279,9 +326,72 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
         pred_log = w.mlpout.as<float>();
     }
     QW_TRY(schedule(exact, pred_log, o.sched == QW_SCHED_NONE, &order));
+    QW_TRY(launch_fill_u32(w.flag.as<uint32_t>(), 0u, Q, s));
     if (ev) QW_HIP(hipEventRecord(ev[3], s));
-    QW_TRY(run_classes(order, VM_TOPK, nullptr));
+    QW_TRY(dedup_classes(order, 0));
+    QW_TRY(launch_chunks(order, Q, w.ucount.as<uint32_t>(), (uint32_t)plan.C,
+                         w.nch_item.as<uint32_t>(), w.chunk_off.as<unsigned long long>(), w.scan,
+                         w.desc.as<unsigned long long>(), w.qcbeg.as<uint32_t>(),
+                         w.qnch.as<uint32_t>(), s));
+    if (ev) QW_HIP(hipEventRecord(ev[6], s));
+    FlatArgs f;
+    std::memset(&f, 0, sizeof(f));
+    f.desc = w.desc.as<unsigned long long>();
+    f.nchunks = w.chunk_off.as<unsigned long long>() + Q;
+    f.xcd_ctr = c32(ix) + W_XCD;
+    f.data = ix->data.p;
+    f.queries = w.qpad.p;
+    f.cand = w.cand.as<int32_t>();
+    f.coff = w.coff.as<unsigned long long>();
+    f.ucount = w.ucount.as<uint32_t>();
+    f.dp = ix->dp;
+    f.d = ix->d;
+    f.dtype = ix->dtype;
+    f.K = K;
+    f.C = plan.C;
+    f.PS = plan.PS;
+    f.part = w.part.as<unsigned long long>();
+    f.pcount = w.pcount.as<uint32_t>();
+    f.flag = w.flag.as<uint32_t>();
+    QW_TRY(launch_verify_flat(f, plan.fgrid, s));
+    if (ev) QW_HIP(hipEventRecord(ev[7], s));
+    MergeArgs m;
+    std::memset(&m, 0, sizeof(m));
+    m.qnch = w.qnch.as<uint32_t>();
+    m.qcbeg = w.qcbeg.as<uint32_t>();
+    m.pcount = w.pcount.as<uint32_t>();
+    m.part = w.part.as<unsigned long long>();
+    m.PS = plan.PS;
+    m.MB = plan.MB;
+    m.K = K;
+    m.dtype = ix->dtype;
+    m.dp = ix->dp;
+    m.d = ix->d;
+    m.eps = plan.eps;
+    m.flag = w.flag.as<uint32_t>();
+    m.fb_count = c32(ix) + W_FB;
+    m.fb_list = w.fb.as<int32_t>();
+    m.out_ids = out_ids;
+    m.out_dist = out_dist;
+    m.data = ix->data.p;
+    m.queries = w.qpad.p;
+    QW_TRY(launch_merge(m, Q, s));
     if (ev) QW_HIP(hipEventRecord(ev[4], s));
+    // queries flagged on the way (list space, float band, merge capacity):
+    // the fused per-query kernel with a global hash set answers them
+    VerifyArgs a = base_args(ix, K, VM_TOPK);
+    a.nitems = 0;
+    a.in_list = w.fb.as<int32_t>();
+    a.in_count = c32(ix) + W_FB;
+    a.counter = c32(ix) + W_FBWORK;
+    a.buf = (uint32_t)plan.buf;
+    a.cap_log2 = (uint32_t)plan.cap_g;
+    a.limit = (1u << plan.cap_g) / 4 * 3;
+    a.global_tab = 1;
+    a.gscratch = w.gscratch.as<uint32_t>();
+    a.out_ids = out_ids;
+    a.out_dist = out_dist;
+    QW_TRY(launch_verify(a, plan.grid_g, s));
     if (ev) QW_HIP(hipEventRecord(ev[5], s));
     return QW_OK;
 }
@@ -307,6 +417,7 @@ qw_status fill_stats(qw_index *ix, int64_t Q, hipStream_t s, qw_stats *st, hipEv
     st->overflow = 0;
     if (fast)
         for (int i = 1; i <= kMaxClasses; ++i) st->overflow += (int64_t)h32[W_QCNT + i];
+    st->fallback = fast ? (int64_t)h32[W_FB] : 0;
     if (fast)
         for (int i = 0; i < 8; ++i) st->bins[i] = (int64_t)h64[C_CLASS + i];
     if (ev) {
@@ -317,6 +428,10 @@ qw_status fill_stats(qw_index *ix, int64_t Q, hipStream_t s, qw_stats *st, hipEv
         if (hipEventElapsedTime(&ms, ev[3], ev[4]) == hipSuccess) st->ms_stage[3] = ms;
         if (hipEventElapsedTime(&ms, ev[4], ev[5]) == hipSuccess) st->ms_stage[4] = ms;
         if (hipEventElapsedTime(&ms, ev[0], ev[5]) == hipSuccess) st->ms_stage[5] = ms;
+        if (fast) {  // dedup+chunks, streaming verify
+            if (hipEventElapsedTime(&ms, ev[3], ev[6]) == hipSuccess) st->ms_stage[6] = ms;
+            if (hipEventElapsedTime(&ms, ev[6], ev[7]) == hipSuccess) st->ms_stage[7] = ms;
+        }
         (void)hipGetLastError();
     }
     return QW_OK;

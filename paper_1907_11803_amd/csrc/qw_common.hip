@@ -241,6 +241,11 @@ __global__ __launch_bounds__(kBlock) void scan_small_kernel(const uint32_t *__re
     if (threadIdx.x == 0) out[count] = tot;
 }
 
+size_t scan_scratch_bytes(int64_t count)
+{
+    return sizeof(unsigned long long) * (ceil_div(std::max<int64_t>(count, 1), kScanTile) + 1);
+}
+
 qw_status launch_scan_u32_to_u64(const uint32_t *in, int64_t count, unsigned long long *out,
                                  DevBuf &scratch, hipStream_t s)
 {
@@ -248,7 +253,12 @@ qw_status launch_scan_u32_to_u64(const uint32_t *in, int64_t count, unsigned lon
         return launch_fill_u64(out, 0ull, 1, s);
     }
     int64_t ntiles = ceil_div(count, kScanTile);
-    QW_TRY(scratch.ensure(sizeof(unsigned long long) * (ntiles + 1)));
+    if (ntiles == 1) {  // one workgroup does it all
+        scan_small_kernel<<<1, kBlock, 0, s>>>(in, count, out);
+        QW_HIP(hipGetLastError());
+        return QW_OK;
+    }
+    QW_TRY(scratch.ensure(scan_scratch_bytes(count)));
     auto *sums = scratch.as<unsigned long long>();
     scan_tile_sums<<<(unsigned)ntiles, kBlock, 0, s>>>(in, count, sums);
     QW_HIP(hipGetLastError());

@@ -63,6 +63,8 @@ struct TabEntry {
 struct Workspace {
     DevBuf qpad, h, bstart, bsize, qsum, pred, feats, keys, keys2, vals, vals2, hist,
         order, binoff, counters, ovf, gscratch, mlpout, scan;
+    // flat pipeline
+    DevBuf ucount, coff, flag, nch_item, chunk_off, qcbeg, qnch, desc, part, pcount, cand, fb;
 };
 
 // Launch plan of the fast form for one top-K size: hash-set size classes and
@@ -71,8 +73,14 @@ struct Plan {
     int buf = 64;
     int cmax = 10;      // largest LDS class (log2 capacity)
     int ncls = 2;       // LDS classes + 1 global class
-    int grid[16] = {};
+    int grid[16] = {};  // fused verify kernel, per class
+    int dgrid[16] = {}; // dedup kernel, per class
     int cap_g = 20, grid_g = 1;
+    int C = 1024;       // candidates per chunk
+    int PS = 10;        // chunk result entries
+    int MB = 2048;      // merge capacity (entries)
+    int fgrid = 256;    // streaming verify grid
+    float eps = 0.f;    // FP32 distance bound (float data)
 };
 
 struct GraphKey {
@@ -177,6 +185,7 @@ struct VerifyArgs {
     uint32_t limit;              // abort when more unique ids than this (overflow); <= 3/4 capacity
     uint32_t buf;                // top-K buffer entries (power of two)
     int32_t global_tab;          // 1: hash set in global scratch
+    int32_t short_probe;         // 1: bounded probing (only where an overflow moves the query on)
     uint32_t *gscratch;          // global scratch (global_tab): 2^cap_log2 words per workgroup
     uint32_t *ovf_count;         // queue receiving queries whose set overflowed
     int32_t *ovf_list;
@@ -215,6 +224,73 @@ qw_status launch_labels(const int32_t *counts, int64_t m, float *out, hipStream_
 qw_status build_index(const void *data, int64_t n, int32_t d, int32_t dtype, const float *a,
                       const float *b, float w, int32_t L, int32_t k, int32_t form,
                       hipStream_t s, qw_index **out);
+
+// ---------------------------------------------------------------- flat pipeline
+struct DedupArgs {
+    const int32_t *order;            // scheduled query order
+    const unsigned long long *seg;   // {begin, end} of this class in the order
+    uint32_t *counter;               // persistent work counter
+    const uint32_t *in_count;        // nullable: queue of overflowed queries served after the segment
+    const int32_t *in_list;
+    uint32_t *ovf_count;             // queue receiving this class's overflows
+    int32_t *ovf_list;
+    const uint32_t *bstart, *bsize;
+    const int32_t *ids;
+    int64_t n;
+    int32_t L;
+    uint32_t cap_log2, limit;
+    int32_t global_tab;
+    uint32_t *gscratch;              // 2^cap_log2 words per workgroup (global_tab)
+    int32_t count_only;              // write |C(q)| only
+    unsigned long long *alloc;       // bump allocator over cand
+    unsigned long long cand_cap;
+    int32_t *cand;                   // unique candidate lists
+    uint32_t *ucount;                // |C(q)|
+    unsigned long long *coff;        // offset of each query's list in cand
+    uint32_t *flag;                  // 1 = answer q with the fallback
+    unsigned long long *unique_total;
+};
+
+struct FlatArgs {
+    const unsigned long long *desc;    // chunk -> (q << 32) | first candidate
+    const unsigned long long *nchunks; // device total
+    uint32_t *xcd_ctr;                 // 8 work counters, one per XCD range
+    const void *data, *queries;
+    const int32_t *cand;
+    const unsigned long long *coff;
+    const uint32_t *ucount;
+    int32_t dp, d, dtype, K, C, PS;
+    unsigned long long *part;          // [chunk][PS] (distance << 32 | id) keys
+    uint32_t *pcount;
+    uint32_t *flag;
+};
+
+struct MergeArgs {
+    const uint32_t *qnch, *qcbeg, *pcount;
+    const unsigned long long *part;
+    int32_t PS, MB, K, dtype, dp, d;
+    float eps;
+    const uint32_t *flag;
+    uint32_t *fb_count;
+    int32_t *fb_list;
+    int32_t *out_ids;
+    void *out_dist;
+    const void *data, *queries;
+};
+
+size_t dedup_lds_bytes(int cap_log2, int global_tab, int L);
+int dedup_blocks_per_cu(size_t lds);
+qw_status launch_dedup(const DedupArgs &a, int grid, hipStream_t s);
+qw_status launch_chunks(const int32_t *order, int64_t Q, const uint32_t *ucount, uint32_t C,
+                        uint32_t *nch_item, unsigned long long *chunk_off, DevBuf &scan,
+                        unsigned long long *desc, uint32_t *qcbeg, uint32_t *qnch, hipStream_t s);
+size_t flat_lds_bytes(int C, int dp, int dtype);
+int flat_blocks_per_cu(int C, int dp, int dtype);
+qw_status launch_verify_flat(const FlatArgs &a, int grid, hipStream_t s);
+size_t merge_lds_bytes(int MB, int dtype);
+qw_status launch_merge(const MergeArgs &a, int64_t Q, hipStream_t s);
+// Scratch bytes launch_scan_u32_to_u64 needs for `count` values.
+size_t scan_scratch_bytes(int64_t count);
 
 // ---------------------------------------------------------------- model
 qw_status launch_mlp_features(const uint32_t *bsize, int64_t Q, int32_t L, float *feats,

@@ -25,6 +25,7 @@
 // Work items: a launch serves a segment of the scheduled order plus a queue of
 // queries that overflowed a smaller hash set; a query whose unique candidates
 // exceed this launch's set is appended to the next launch's queue.
+#include "qw_dedup.h"
 #include "qw_internal.h"
 
 namespace qw {
@@ -90,26 +91,6 @@ __device__ __noinline__ double exact_dist_f32(const float *__restrict__ x, const
         acc = __dadd_rn(acc, __dmul_rn(t, t));
     }
     return acc;
-}
-
-__device__ inline uint32_t hash_id(uint32_t id, int cap_log2)
-{
-    return (id * 0x9E3779B1u) >> (32 - cap_log2);
-}
-
-enum { INS_NEW = 0, INS_DUP = 1, INS_FULL = 2 };
-
-__device__ inline int set_insert(uint32_t *tab, int cap_log2, uint32_t id)
-{
-    const uint32_t mask = (1u << cap_log2) - 1u;
-    uint32_t slot = hash_id(id, cap_log2);
-    for (uint32_t it = 0; it <= mask; ++it) {
-        uint32_t old = atomicCAS(&tab[slot], kEmpty, id);
-        if (old == kEmpty) return INS_NEW;
-        if (old == id) return INS_DUP;
-        slot = (slot + 1) & mask;
-    }
-    return INS_FULL;
 }
 
 // Compact the top-K buffer: rank unranked float entries in FP64, sort the live
@@ -288,45 +269,10 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
         __syncthreads();
 
         // ---- phase 1: de-duplicated union of the L bucket lists
-        for (uint32_t base = 0; base < T; base += 4 * kBlock) {
-            // every thread reads the flag before any thread of this pass can set
-            // it, so the early exit is uniform
-            const bool stop = scal[S_OVF] != 0;
-            __syncthreads();
-            if (stop) break;
-            uint32_t ids4[4];
-            bool ok4[4];
-            for (int r = 0; r < 4; ++r) {
-                const uint32_t pos = base + (uint32_t)(r * kBlock + tid);
-                ok4[r] = pos < T;
-                ids4[r] = 0;
-                if (ok4[r]) {
-                    int lo = 0, hi = A.L;  // lpref[lo] <= pos < lpref[hi]
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (lpref[mid] <= pos) lo = mid; else hi = mid;
-                    }
-                    ids4[r] = (uint32_t)A.ids[(int64_t)lo * A.n + lstart[lo] + (pos - lpref[lo])];
-                }
-            }
-            uint32_t nnew = 0;
-            bool full = false;
-            for (int r = 0; r < 4; ++r) {
-                if (!ok4[r]) continue;
-                const int res = set_insert(tab, cap_log2, ids4[r]);
-                nnew += res == INS_NEW;
-                full |= res == INS_FULL;
-            }
-            // one LDS atomic per wave for the unique count
-            for (int off = 32; off > 0; off >>= 1) nnew += (uint32_t)__shfl_xor((int)nnew, off);
-            const bool anyfull = __ballot(full) != 0ull;
-            if (lane == 0 && (nnew || anyfull)) {
-                const uint32_t tot = atomicAdd(&scal[S_UCOUNT], nnew) + nnew;
-                if (tot > limit || anyfull) scal[S_OVF] = 1;
-            }
-            if (glob) __threadfence();
-            __syncthreads();
-        }
+        if (A.mode != VM_ALL)
+            set_union(A.ids, A.n, A.L, lpref, lstart, T, tab, cap_log2, limit, glob != 0,
+                      A.short_probe ? kShortProbe : 0xFFFFFFFFu, &scal[S_UCOUNT], &scal[S_OVF],
+                      &scal[S_CPOS]);
         const uint32_t U = A.mode == VM_ALL ? (uint32_t)A.n : scal[S_UCOUNT];
         if (A.mode != VM_ALL && (scal[S_OVF] || U > limit)) {
             if (tid == 0) {
@@ -335,23 +281,6 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
             }
             __syncthreads();
             continue;
-        }
-        // compact the set in place: contents move only to lower positions that
-        // were read in this or an earlier round
-        if (A.mode != VM_ALL) {
-            for (uint32_t base = 0; base < cap; base += kBlock) {
-                const uint32_t v = tab[base + tid];
-                const bool occ = v != kEmpty;
-                if (glob) __threadfence();
-                __syncthreads();
-                const unsigned long long m = __ballot(occ);
-                uint32_t wb = 0;
-                if (lane == 0 && m) wb = atomicAdd(&scal[S_CPOS], (uint32_t)__popcll(m));
-                wb = (uint32_t)__shfl((int)wb, 0);
-                if (occ) tab[wb + (uint32_t)__popcll(m & lt_mask)] = v;
-            }
-            if (glob) __threadfence();
-            __syncthreads();
         }
         if (tid == 0 && A.unique_total && A.mode != VM_ALL)
             atomicAdd(A.unique_total, (unsigned long long)U);

@@ -42,7 +42,8 @@ class qw_stats(ctypes.Structure):
     _fields_ = [("projections", ctypes.c_int64), ("recomputed", ctypes.c_int64),
                 ("recompute_frac", ctypes.c_double), ("probes_hit", ctypes.c_int64),
                 ("cand_total", ctypes.c_int64), ("cand_unique", ctypes.c_int64),
-                ("overflow", ctypes.c_int64), ("bins", ctypes.c_int64 * 8),
+                ("overflow", ctypes.c_int64), ("fallback", ctypes.c_int64),
+                ("bins", ctypes.c_int64 * 8),
                 ("ms_stage", ctypes.c_float * 8)]
 
     def as_dict(self) -> dict:
