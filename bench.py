@@ -55,9 +55,11 @@ def recall_at_10(ids_lsh, ids_true, dist_lsh, dist_true):
     return hits / (K * ids_lsh.shape[0])
 
 
-def verify_source_hash():
+def gather_source_hash():
+    """Identifies the gather kernel's source: stored HBM traffic is used only
+    while it matches."""
     h = hashlib.sha256()
-    for f in ("qw_verify.hip", "qw_internal.h"):
+    for f in ("qw_flat.hip", "qw_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_1907_11803_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -196,17 +198,19 @@ def main():
     L = wl.params.L
     alg_bytes = (wl.Q * wl.d * elem + 8 * L * wl.Q + 4 * st["cand_total"] +
                  st["cand_unique"] * wl.d * elem + 8 * K * wl.Q)
-    # dominant kernel: the streaming verify (one launch per step); its algorithmic
-    # bytes are the candidate rows, their ids and the query rows
-    verify_bytes = st["cand_unique"] * (wl.d * elem + 4) + wl.Q * wl.d * elem
-    verify_ms = float(stage[7])
-    achieved = verify_bytes / (verify_ms * 1e-3) / 1e9 if verify_ms > 0 else None
+    # dominant kernel: the gather (one launch per step).  Algorithmic bytes per
+    # (query, candidate) pair: the candidate's row, the pair (id, query) read
+    # and the (distance, id) key written; plus each query row once.
+    pair_bytes = wl.d * elem + 8 + 8
+    gather_bytes = st["cand_unique"] * pair_bytes + wl.Q * wl.d * elem
+    gather_ms = float(stage[7])
+    achieved = gather_bytes / (gather_ms * 1e-3) / 1e9 if gather_ms > 0 else None
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"verify_cfg{args.config}_traffic.json")
+    tfile = os.path.join(ROOT, "profiles", f"gather_cfg{args.config}_traffic.json")
     if os.path.exists(tfile):
         tj = json.load(open(tfile))
-        if tj.get("verify_source") == verify_source_hash() and abs(tj.get("w", -1) - w) < 1e-9:
-            traffic = tj.get("bytes_per_step")
+        if tj.get("source") == gather_source_hash() and abs(tj.get("w", -1) - w) < 1e-9:
+            traffic = tj.get("bytes_per_launch")
 
     # ---- CPU oracle on a bounded sample
     cpu = None
@@ -258,8 +262,9 @@ def main():
         "forms_identical": identical,
         "sched_ms_per_step": sched_ms,
         "stage_ms": {"hash": round(stage[0], 4), "probe": round(stage[1], 4),
-                     "schedule": round(stage[2], 4), "dedup_chunks": round(stage[6], 4),
-                     "stream_verify": round(stage[7], 4),
+                     "schedule": round(stage[2], 4), "dedup": round(stage[6], 4),
+                     "gather": round(stage[7], 4),
+                     "select": round(stage[3] - stage[6] - stage[7], 4),
                      "candidates_verify_topk": round(stage[3], 4),
                      "fallback": round(stage[4], 4), "total": round(stage[5], 4)},
         "recompute_frac": st["recompute_frac"],
@@ -271,8 +276,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                     "traffic": traffic, "kernel": "verify_flat_kernel",
-                     "kernel_algorithmic_bytes": int(verify_bytes),
+                     "traffic": traffic, "kernel": "gather_kernel",
+                     "kernel_ms": round(gather_ms, 4),
+                     "kernel_algorithmic_bytes": int(gather_bytes),
                      "path_algorithmic_bytes_per_step": int(alg_bytes)},
         "cpu_baseline": cpu,
     }

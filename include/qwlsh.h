@@ -96,8 +96,7 @@ typedef struct {
     int64_t fallback;      /* fast form: queries answered by the fused per-query path */
     int64_t bins[8];       /* queries per hash-set size class (fast form) */
     float ms_stage[8];     /* timing=1: hash, probe, schedule, candidates+verify+top-K,
-                              fallback, total, dedup+chunking (fast form), streaming verify
-                              (fast form) */
+                              fallback, total, dedup (fast form), gather (fast form) */
 } qw_stats;
 
 typedef struct {

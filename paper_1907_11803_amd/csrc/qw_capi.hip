@@ -16,15 +16,14 @@ namespace {
 // counters buffer: u64 [kC64] then u32 [kC32]
 enum {
     C_RECOMP = 0, C_UNIQUE, C_PROBEHIT, C_CANDTOT, C_CLASS /* .. C_CLASS+15 */, C_ALLOC = 20,
-    kC64 = 24
+    C_VEND = 21, kC64 = 24
 };
 // u32: persistent work counters per class, overflow-queue lengths per class
 // (queue i holds queries that overflowed class i-1), per-XCD chunk counters,
 // fallback queue, misc
 enum { W_WORK = 0 /* .. 15 */, W_QCNT = 16 /* .. 32 */, W_SIMPLE = 33, W_MAX = 34, W_DUMMY = 35,
        W_XCD = 36 /* .. 43 */, W_FB = 44, W_FBWORK = 45, kC32 = 48 };
-constexpr int kChunk = 1024;          // candidates per chunk of the streaming verify
-constexpr int64_t kCandPerQuery = 4096;  // list space reserved per query (beyond: fallback)
+constexpr int64_t kCandPerQuery = 4096;  // pair space reserved per query (beyond: fallback)
 constexpr int kCmin = 10;
 constexpr int kMaxClasses = 16;
 constexpr float kMargin = 1.25f;  // learned schedule: slack on the predicted count
@@ -75,11 +74,12 @@ Plan make_plan(qw_index *ix, int K)
     for (int i = 0; i + 1 < p.ncls; ++i)
         p.dgrid[i] = dedup_blocks_per_cu(dedup_lds_bytes(kCmin + i, 0, ix->L)) * ix->cus;
     p.dgrid[p.ncls - 1] = p.grid_g;
-    p.C = kChunk;
-    p.PS = ix->dtype == QW_U8 ? std::min(K, p.C) : std::min(p.C, std::max(2 * K, K + 16));
-    p.MB = pow2_at_least(std::max(2048, 4 * K));
-    p.fgrid = flat_blocks_per_cu(p.C, ix->dp, ix->dtype) * ix->cus;
-    {  // FP32 distance bound of the streaming verify kernel (float data)
+    // a pass adds at most 4 * kBlock keys to a list cut back to <= LC/2, and
+    // K <= 1024 keeps LC <= 4096 (32 KiB of keys, 64 KiB with the FP64 re-rank)
+    static_assert(4 * kBlock <= 1024 && kMaxTopK <= 1024, "select list sizing");
+    p.LC = pow2_at_least(std::max(2048, 4 * K));
+    p.ggrid = gather_blocks_per_cu(ix->dp, ix->dtype) * ix->cus;
+    {  // FP32 distance bound of the gather kernel (float data)
         const int parts = ix->dp * (ix->dtype == QW_U8 ? 1 : 4) / 16;
         int G = 1;
         while (G < parts && G < 64) G <<= 1;
@@ -100,8 +100,7 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan)
                                    w.feats.p, w.keys.p, w.keys2.p, w.vals.p, w.vals2.p,
                                    w.binoff.p, w.counters.p, w.ovf.p, w.gscratch.p, w.mlpout.p,
                                    w.hist.p, w.scan.p, w.ucount.p, w.coff.p, w.flag.p,
-                                   w.nch_item.p, w.chunk_off.p, w.qcbeg.p, w.qnch.p, w.desc.p,
-                                   w.part.p, w.pcount.p, w.cand.p, w.fb.p};
+                                   w.cand.p, w.candq.p, w.pkeys.p, w.fb.p};
     };
     const std::vector<void *> before = ptrs();
     const size_t elem = ix->dtype == QW_U8 ? 1 : 4;
@@ -127,18 +126,12 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan)
         const size_t g = (size_t)plan->grid_g * (size_t(1) << plan->cap_g) * 4;
         QW_TRY(w.gscratch.ensure(g));
         const int64_t cand_cap = std::max<int64_t>(q * kCandPerQuery, 1 << 20);
-        const int64_t nchunk_cap = cand_cap / plan->C + q;
         QW_TRY(w.ucount.ensure(sizeof(uint32_t) * q));
         QW_TRY(w.coff.ensure(sizeof(unsigned long long) * q));
         QW_TRY(w.flag.ensure(sizeof(uint32_t) * q));
-        QW_TRY(w.nch_item.ensure(sizeof(uint32_t) * q));
-        QW_TRY(w.chunk_off.ensure(sizeof(unsigned long long) * (q + 1)));
-        QW_TRY(w.qcbeg.ensure(sizeof(uint32_t) * q));
-        QW_TRY(w.qnch.ensure(sizeof(uint32_t) * q));
-        QW_TRY(w.desc.ensure(sizeof(unsigned long long) * nchunk_cap));
-        QW_TRY(w.part.ensure(sizeof(unsigned long long) * nchunk_cap * plan->PS));
-        QW_TRY(w.pcount.ensure(sizeof(uint32_t) * nchunk_cap));
         QW_TRY(w.cand.ensure(sizeof(int32_t) * cand_cap));
+        QW_TRY(w.candq.ensure(sizeof(int32_t) * cand_cap));
+        QW_TRY(w.pkeys.ensure(sizeof(unsigned long long) * cand_cap));
         QW_TRY(w.fb.ensure(sizeof(int32_t) * q));
     }
     if (before != ptrs()) drop_graphs(ix);
@@ -293,6 +286,8 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
             a.alloc = c64(ix) + C_ALLOC;
             a.cand_cap = (unsigned long long)cand_cap;
             a.cand = w.cand.as<int32_t>();
+            a.candq = w.candq.as<int32_t>();
+            a.valid_end = c64(ix) + C_VEND;
             a.ucount = w.ucount.as<uint32_t>();
             a.coff = w.coff.as<unsigned long long>();
             a.flag = w.flag.as<uint32_t>();
@@ -329,55 +324,40 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     QW_TRY(launch_fill_u32(w.flag.as<uint32_t>(), 0u, Q, s));
     if (ev) QW_HIP(hipEventRecord(ev[3], s));
     QW_TRY(dedup_classes(order, 0));
-    QW_TRY(launch_chunks(order, Q, w.ucount.as<uint32_t>(), (uint32_t)plan.C,
-                         w.nch_item.as<uint32_t>(), w.chunk_off.as<unsigned long long>(), w.scan,
-                         w.desc.as<unsigned long long>(), w.qcbeg.as<uint32_t>(),
-                         w.qnch.as<uint32_t>(), s));
     if (ev) QW_HIP(hipEventRecord(ev[6], s));
-    FlatArgs f;
-    std::memset(&f, 0, sizeof(f));
-    f.desc = w.desc.as<unsigned long long>();
-    f.nchunks = w.chunk_off.as<unsigned long long>() + Q;
-    f.xcd_ctr = c32(ix) + W_XCD;
-    f.data = ix->data.p;
-    f.queries = w.qpad.p;
-    f.cand = w.cand.as<int32_t>();
-    f.coff = w.coff.as<unsigned long long>();
-    f.ucount = w.ucount.as<uint32_t>();
-    f.dp = ix->dp;
-    f.d = ix->d;
-    f.dtype = ix->dtype;
-    f.K = K;
-    f.C = plan.C;
-    f.PS = plan.PS;
-    f.part = w.part.as<unsigned long long>();
-    f.pcount = w.pcount.as<uint32_t>();
-    f.flag = w.flag.as<uint32_t>();
-    QW_TRY(launch_verify_flat(f, plan.fgrid, s));
+    GatherArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.npairs = c64(ix) + C_VEND;
+    g.cand = w.cand.as<int32_t>();
+    g.candq = w.candq.as<int32_t>();
+    g.data = ix->data.p;
+    g.queries = w.qpad.p;
+    g.dp = ix->dp;
+    g.dtype = ix->dtype;
+    g.keys = w.pkeys.as<unsigned long long>();
+    QW_TRY(launch_gather(g, plan.ggrid, s));
     if (ev) QW_HIP(hipEventRecord(ev[7], s));
-    MergeArgs m;
+    SelectArgs m;
     std::memset(&m, 0, sizeof(m));
-    m.qnch = w.qnch.as<uint32_t>();
-    m.qcbeg = w.qcbeg.as<uint32_t>();
-    m.pcount = w.pcount.as<uint32_t>();
-    m.part = w.part.as<unsigned long long>();
-    m.PS = plan.PS;
-    m.MB = plan.MB;
+    m.keys = w.pkeys.as<unsigned long long>();
+    m.coff = w.coff.as<unsigned long long>();
+    m.ucount = w.ucount.as<uint32_t>();
+    m.flag = w.flag.as<uint32_t>();
     m.K = K;
+    m.LC = plan.LC;
     m.dtype = ix->dtype;
     m.dp = ix->dp;
     m.d = ix->d;
     m.eps = plan.eps;
-    m.flag = w.flag.as<uint32_t>();
     m.fb_count = c32(ix) + W_FB;
     m.fb_list = w.fb.as<int32_t>();
     m.out_ids = out_ids;
     m.out_dist = out_dist;
     m.data = ix->data.p;
     m.queries = w.qpad.p;
-    QW_TRY(launch_merge(m, Q, s));
+    QW_TRY(launch_select(m, Q, s));
     if (ev) QW_HIP(hipEventRecord(ev[4], s));
-    // queries flagged on the way (list space, float band, merge capacity):
+    // queries flagged on the way (list space, ties or band wider than the list):
     // the fused per-query kernel with a global hash set answers them
     VerifyArgs a = base_args(ix, K, VM_TOPK);
     a.nitems = 0;
@@ -428,7 +408,7 @@ qw_status fill_stats(qw_index *ix, int64_t Q, hipStream_t s, qw_stats *st, hipEv
         if (hipEventElapsedTime(&ms, ev[3], ev[4]) == hipSuccess) st->ms_stage[3] = ms;
         if (hipEventElapsedTime(&ms, ev[4], ev[5]) == hipSuccess) st->ms_stage[4] = ms;
         if (hipEventElapsedTime(&ms, ev[0], ev[5]) == hipSuccess) st->ms_stage[5] = ms;
-        if (fast) {  // dedup+chunks, streaming verify
+        if (fast) {  // dedup, gather (select = stage 3 minus both)
             if (hipEventElapsedTime(&ms, ev[3], ev[6]) == hipSuccess) st->ms_stage[6] = ms;
             if (hipEventElapsedTime(&ms, ev[6], ev[7]) == hipSuccess) st->ms_stage[7] = ms;
         }

@@ -39,14 +39,15 @@ __device__ inline int set_insert(uint32_t *tab, int cap_log2, uint32_t id, uint3
 // layer lists (layer l holds positions [lpref[l], lpref[l+1]) and starts at
 // ids[l*n + lstart[l]]) into the cleared set `tab` of 2^cap_log2 slots.  The
 // unique count goes to *ucount; *ovf is set when it exceeds `limit` or the
-// set fills.  Without overflow the set is then compacted in place: tab[0..U)
-// holds the unique ids (unspecified order).  *ucount, *ovf and *cpos must be 0
-// and visible to all threads on entry; returns after a barrier.
+// set fills.  Without overflow and with `compact`, the set is then compacted in
+// place: tab[0..U) holds the unique ids (unspecified order).  *ucount, *ovf
+// and *cpos must be 0 and visible to all threads on entry; returns after a
+// barrier.
 __device__ inline void set_union(const int32_t *__restrict__ ids, int64_t n, int32_t L,
                                  const uint32_t *lpref, const uint32_t *lstart, uint32_t T,
                                  uint32_t *tab, int cap_log2, uint32_t limit, bool glob,
-                                 uint32_t max_probe, uint32_t *ucount, uint32_t *ovf,
-                                 uint32_t *cpos)
+                                 uint32_t max_probe, bool compact, uint32_t *ucount,
+                                 uint32_t *ovf, uint32_t *cpos)
 {
     const int tid = threadIdx.x, lane = tid & 63;
     const unsigned long long lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -89,7 +90,7 @@ __device__ inline void set_union(const int32_t *__restrict__ ids, int64_t n, int
         if (glob) __threadfence();
         __syncthreads();
     }
-    if (*ovf || *ucount > limit) return;  // uniform: read after the last barrier
+    if (!compact || *ovf || *ucount > limit) return;  // uniform: read after the last barrier
     // compact in place: contents move only to lower positions that were read
     // in this or an earlier round
     const uint32_t cap = 1u << cap_log2;

@@ -1,30 +1,29 @@
-// Flat query pipeline of the fast form: dedup -> chunks -> streaming verify ->
-// merge.
+// Flat query pipeline of the fast form: dedup -> gather -> select.
 //
 // 1. dedup_kernel: one workgroup per query builds C(q) (the union of the
 //    query's buckets, Sections 1.2 and 5.1) in an LDS hash set sized by the
-//    predicted count and appends the unique ids to a device-wide list through a
-//    bump allocator.  Queries whose set overflows move to the next size class.
-// 2. chunk kernels: each query's list is cut into chunks of at most C
-//    candidates, emitted in the scheduled (bucket-grouped) query order.
-// 3. verify_flat_kernel: persistent workgroups stream the chunks -- gather the
-//    rows, exact distances (the false-positive removal of Section 1.2), sort
-//    the chunk's keys and keep its K best (plus, for float data, every entry
-//    within the proven FP32 error band of the K-th).  Chunks are split into
-//    eight contiguous ranges, one per XCD (workgroup b runs on XCD b % 8), so
-//    consecutive chunks of a bucket group share that XCD's L2; an XCD that
-//    drains its range takes work from the next.
-// 4. merge_kernel: per query, the chunk results are combined into the top-K by
-//    (distance, id) (the c-k-ANN output, Section 3); float data is re-ranked
-//    by the FP64 index-order distance inside the band.
-// Queries that do not fit (list space, band or merge capacity) are flagged and
-// answered by the fused per-query kernel afterwards.
+//    predicted count, and scatters the unique ids -- each tagged with its query
+//    -- into a device-wide pair list through a bump allocator.  Queries whose
+//    set overflows move to the next size class.
+// 2. gather_kernel: a pure streaming pass over all (query, candidate) pairs:
+//    gather the row, compute the exact squared distance (the false-positive
+//    removal of Section 1.2), write one (distance, id) key per pair.  The pair
+//    list is cut into eight contiguous ranges, one per XCD (workgroup b runs on
+//    XCD b % 8); the pairs of a bucket group are adjacent, so their rows are
+//    shared through that XCD's L2.  No barriers: every wave keeps loads in
+//    flight all the time.
+// 3. select_kernel: one workgroup per query selects the K smallest keys of its
+//    contiguous pair range by (distance, id) (the c-k-ANN output, Section 3);
+//    for float data every key within the proven FP32 error band of the K-th is
+//    re-ranked by its FP64 index-order distance.
+// Queries that do not fit (list space, band capacity) are flagged and answered
+// by the fused per-query kernel afterwards.
 #include "qw_dedup.h"
 #include "qw_internal.h"
 
 namespace qw {
 
-enum { D_ITEM = 0, D_UCOUNT, D_OVF, D_CPOS, D_T, D_CAP, D_NSCAL = 8 };
+enum { D_ITEM = 0, D_UCOUNT, D_OVF, D_CPOS, D_T, D_CAP, D_OFF = 6 /* u64 */, D_NSCAL = 8 };
 
 __host__ __device__ inline size_t a16(size_t v) { return (v + 15) & ~size_t(15); }
 
@@ -37,7 +36,8 @@ size_t dedup_lds_bytes(int cap_log2, int global_tab, int L)
 __global__ __launch_bounds__(kBlock) void dedup_kernel(DedupArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const unsigned long long lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     const bool glob = A.global_tab != 0;
     const size_t tab_bytes = glob ? 0 : (size_t(4) << A.cap_log2);
     uint32_t *lpref = reinterpret_cast<uint32_t *>(smem + tab_bytes);
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(kBlock) void dedup_kernel(DedupArgs A)
         if (glob) __threadfence();
         __syncthreads();
         set_union(A.ids, A.n, A.L, lpref, lstart, scal[D_T], tab, cap_log2, limit, glob,
-                  glob ? 0xFFFFFFFFu : kShortProbe, &scal[D_UCOUNT], &scal[D_OVF],
+                  glob ? 0xFFFFFFFFu : kShortProbe, false, &scal[D_UCOUNT], &scal[D_OVF],
                   &scal[D_CPOS]);
         const uint32_t U = scal[D_UCOUNT];
         if (scal[D_OVF] || U > limit) {
@@ -112,6 +112,7 @@ __global__ __launch_bounds__(kBlock) void dedup_kernel(DedupArgs A)
             __syncthreads();
             continue;
         }
+        unsigned long long *soff = reinterpret_cast<unsigned long long *>(&scal[D_OFF]);
         if (tid == 0) {
             unsigned long long off = atomicAdd(A.alloc, (unsigned long long)U);
             if (off + U > A.cand_cap) {  // no list space: answered by the fallback
@@ -121,15 +122,29 @@ __global__ __launch_bounds__(kBlock) void dedup_kernel(DedupArgs A)
             } else {
                 A.ucount[q] = U;
                 A.coff[q] = off;
+                atomicMax(A.valid_end, off + U);
                 if (A.unique_total) atomicAdd(A.unique_total, (unsigned long long)U);
             }
-            scal[D_T] = (uint32_t)(off == ~0ull ? 0xFFFFFFFFu : 0u);
-            reinterpret_cast<unsigned long long *>(lstart)[0] = off;  // broadcast
+            *soff = off;
         }
         __syncthreads();
-        if (scal[D_T] == 0u) {
-            const unsigned long long off = reinterpret_cast<unsigned long long *>(lstart)[0];
-            for (uint32_t i = tid; i < U; i += kBlock) A.cand[off + i] = (int32_t)tab[i];
+        const unsigned long long off = *soff;
+        if (off != ~0ull) {
+            // scatter the set's ids straight from the hashed layout: a wave
+            // reserves its run of positions with one LDS atomic per round
+            for (uint32_t base = 0; base < cap; base += kBlock) {
+                const uint32_t v = tab[base + tid];
+                const bool occ = v != kEmpty;
+                const unsigned long long m = __ballot(occ);
+                uint32_t wb = 0;
+                if (lane == 0 && m) wb = atomicAdd(&scal[D_CPOS], (uint32_t)__popcll(m));
+                wb = (uint32_t)__shfl((int)wb, 0);
+                if (occ) {
+                    const unsigned long long e = off + wb + (uint32_t)__popcll(m & lt_mask);
+                    A.cand[e] = (int32_t)v;
+                    A.candq[e] = (int32_t)q;
+                }
+            }
         }
         __syncthreads();
     }
@@ -154,53 +169,148 @@ int dedup_blocks_per_cu(size_t lds)
     return nb > 0 ? nb : 1;
 }
 
-// ---------------------------------------------------------------- chunks
+// ---------------------------------------------------------------- gather
 
-__global__ void nchunks_kernel(const int32_t *__restrict__ order, int64_t Q,
-                               const uint32_t *__restrict__ ucount, uint32_t C,
-                               uint32_t *__restrict__ nch_item)
+// Every pair e < N: key[e] = (squared distance << 32) | id, uint8 distances
+// exact (sum over 16-byte parts of |x|^2 - 2 x.q + |q|^2 by dot4), float
+// distances as FP32 bits (non-negative, so the bits order like the values).
+template <int DT, int UN, int PM>
+__global__ __launch_bounds__(kBlock) void gather_kernel(GatherArgs A)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < Q;
-         i += (int64_t)gridDim.x * blockDim.x)
-        nch_item[i] = (ucount[order[i]] + C - 1) / C;
-}
-
-__global__ void emit_chunks_kernel(const int32_t *__restrict__ order, int64_t Q,
-                                   const uint32_t *__restrict__ nch_item,
-                                   const unsigned long long *__restrict__ chunk_off, uint32_t C,
-                                   unsigned long long *__restrict__ desc,
-                                   uint32_t *__restrict__ qcbeg, uint32_t *__restrict__ qnch)
-{
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < Q;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t q = (uint32_t)order[i];
-        const unsigned long long c0 = chunk_off[i];
-        const uint32_t nc = nch_item[i];
-        qcbeg[q] = (uint32_t)c0;
-        qnch[q] = nc;
-        for (uint32_t t = 0; t < nc; ++t)
-            desc[c0 + t] = ((unsigned long long)q << 32) | (unsigned long long)(t * C);
+    const int tid = threadIdx.x;
+    const int elem = DT == QW_U8 ? 1 : 4;
+    const int row_bytes = A.dp * elem;
+    const int parts = row_bytes / 16;
+    int G = 1;
+    while (G < parts && G < 64) G <<= 1;
+    const int P = (parts + G - 1) / G;
+    const int NG = kBlock / G;
+    const int PI = NG * UN;  // pairs per workgroup iteration
+    const int grp = tid / G, j = tid % G;
+    const unsigned long long N = *A.npairs;
+    // XCD-local contiguous range
+    const int x = blockIdx.x & 7;
+    const int64_t nwg = ((int64_t)gridDim.x - x + 7) / 8;
+    const int64_t r = blockIdx.x >> 3;
+    const int64_t rb = (int64_t)(N * x / 8), re = (int64_t)(N * (x + 1) / 8);
+    for (int64_t base = rb + r * PI; base < re; base += nwg * PI) {
+        uint32_t cid[UN], cq[UN];
+        bool cv[UN];
+        for (int u = 0; u < UN; ++u) {
+            const int64_t e = base + grp + (int64_t)NG * u;
+            cv[u] = e < re;
+            cid[u] = cv[u] ? (uint32_t)A.cand[e] : 0u;
+            cq[u] = cv[u] ? (uint32_t)A.candq[e] : 0u;
+        }
+        uint32_t accu[UN];
+        float accf[UN];
+        for (int u = 0; u < UN; ++u) {
+            accu[u] = 0;
+            accf[u] = 0.f;
+        }
+        for (int p0 = 0; p0 < P; p0 += PM) {
+            uint4 xv[UN][PM], qv[UN][PM];
+            for (int u = 0; u < UN; ++u)
+                for (int pp = 0; pp < PM; ++pp) {
+                    const int part = j + G * (p0 + pp);
+                    if (cv[u] && p0 + pp < P && part < parts) {
+                        xv[u][pp] = reinterpret_cast<const uint4 *>(
+                            (const unsigned char *)A.data + (int64_t)cid[u] * row_bytes)[part];
+                        qv[u][pp] = reinterpret_cast<const uint4 *>(
+                            (const unsigned char *)A.queries + (int64_t)cq[u] * row_bytes)[part];
+                    } else {
+                        xv[u][pp] = make_uint4(0, 0, 0, 0);
+                        qv[u][pp] = make_uint4(0, 0, 0, 0);
+                    }
+                }
+            for (int u = 0; u < UN; ++u)
+                for (int pp = 0; pp < PM; ++pp) {
+                    const uint4 xw = xv[u][pp], qw = qv[u][pp];
+                    if (DT == QW_U8) {
+                        uint32_t xx = 0, xq = 0, qq = 0;
+                        xx = __builtin_amdgcn_udot4(xw.x, xw.x, xx, false);
+                        xx = __builtin_amdgcn_udot4(xw.y, xw.y, xx, false);
+                        xx = __builtin_amdgcn_udot4(xw.z, xw.z, xx, false);
+                        xx = __builtin_amdgcn_udot4(xw.w, xw.w, xx, false);
+                        xq = __builtin_amdgcn_udot4(xw.x, qw.x, xq, false);
+                        xq = __builtin_amdgcn_udot4(xw.y, qw.y, xq, false);
+                        xq = __builtin_amdgcn_udot4(xw.z, qw.z, xq, false);
+                        xq = __builtin_amdgcn_udot4(xw.w, qw.w, xq, false);
+                        qq = __builtin_amdgcn_udot4(qw.x, qw.x, qq, false);
+                        qq = __builtin_amdgcn_udot4(qw.y, qw.y, qq, false);
+                        qq = __builtin_amdgcn_udot4(qw.z, qw.z, qq, false);
+                        qq = __builtin_amdgcn_udot4(qw.w, qw.w, qq, false);
+                        accu[u] += xx - 2u * xq + qq;
+                    } else {
+                        const float d0 = __uint_as_float(xw.x) - __uint_as_float(qw.x);
+                        const float d1 = __uint_as_float(xw.y) - __uint_as_float(qw.y);
+                        const float d2 = __uint_as_float(xw.z) - __uint_as_float(qw.z);
+                        const float d3 = __uint_as_float(xw.w) - __uint_as_float(qw.w);
+                        float sacc = accf[u];
+                        sacc = fmaf(d0, d0, sacc);
+                        sacc = fmaf(d1, d1, sacc);
+                        sacc = fmaf(d2, d2, sacc);
+                        sacc = fmaf(d3, d3, sacc);
+                        accf[u] = sacc;
+                    }
+                }
+        }
+        for (int u = 0; u < UN; ++u)
+            for (int off = G >> 1; off > 0; off >>= 1) {
+                if (DT == QW_U8)
+                    accu[u] += (uint32_t)__shfl_xor((int)accu[u], off);
+                else
+                    accf[u] += __shfl_xor(accf[u], off);
+            }
+        if (j == 0)
+            for (int u = 0; u < UN; ++u)
+                if (cv[u]) {
+                    const uint32_t hi = DT == QW_U8 ? accu[u] : __float_as_uint(accf[u]);
+                    A.keys[base + grp + (int64_t)NG * u] = ((unsigned long long)hi << 32) | cid[u];
+                }
     }
 }
 
-qw_status launch_chunks(const int32_t *order, int64_t Q, const uint32_t *ucount, uint32_t C,
-                        uint32_t *nch_item, unsigned long long *chunk_off, DevBuf &scan,
-                        unsigned long long *desc, uint32_t *qcbeg, uint32_t *qnch, hipStream_t s)
+static bool gather_small(int dp, int dtype) { return dp * (dtype == QW_U8 ? 1 : 4) / 16 <= 64; }
+
+static const void *gather_fn(int dp, int dtype)
 {
-    if (Q <= 0) return QW_OK;
-    const int g = (int)std::min<int64_t>(4096, ceil_div(Q, kBlock));
-    nchunks_kernel<<<g, kBlock, 0, s>>>(order, Q, ucount, C, nch_item);
-    QW_HIP(hipGetLastError());
-    QW_TRY(launch_scan_u32_to_u64(nch_item, Q, chunk_off, scan, s));
-    emit_chunks_kernel<<<g, kBlock, 0, s>>>(order, Q, nch_item, chunk_off, C, desc, qcbeg, qnch);
+    const bool small = gather_small(dp, dtype);
+    if (dtype == QW_U8)
+        return small ? (const void *)gather_kernel<QW_U8, 4, 1> : (const void *)gather_kernel<QW_U8, 2, 4>;
+    return small ? (const void *)gather_kernel<QW_F32, 4, 1> : (const void *)gather_kernel<QW_F32, 2, 4>;
+}
+
+int gather_blocks_per_cu(int dp, int dtype)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, gather_fn(dp, dtype), kBlock, 0) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        nb = 1;
+    }
+    return nb > 0 ? nb : 1;
+}
+
+qw_status launch_gather(const GatherArgs &a, int grid, hipStream_t s)
+{
+    if (grid <= 0) return QW_OK;
+    const bool small = gather_small(a.dp, a.dtype);
+    if (a.dtype == QW_U8) {
+        if (small) gather_kernel<QW_U8, 4, 1><<<grid, kBlock, 0, s>>>(a);
+        else gather_kernel<QW_U8, 2, 4><<<grid, kBlock, 0, s>>>(a);
+    } else {
+        if (small) gather_kernel<QW_F32, 4, 1><<<grid, kBlock, 0, s>>>(a);
+        else gather_kernel<QW_F32, 2, 4><<<grid, kBlock, 0, s>>>(a);
+    }
     QW_HIP(hipGetLastError());
     return QW_OK;
 }
 
-// ---------------------------------------------------------------- streaming verify
+// ---------------------------------------------------------------- select
 
-// Bitonic sort of keys[0..n) (n <= cap, cap a power of two) ascending; the
-// tail up to the next power of two is padded with ~0.  Whole workgroup.
+// Bitonic sort of keys[0..n) ascending (the tail up to the next power of two
+// is padded with ~0; that power of two must fit the buffer).  Whole workgroup.
 __device__ inline void sort_keys(unsigned long long *keys, int n)
 {
     int ns = 2;
@@ -224,8 +334,8 @@ __device__ inline void sort_keys(unsigned long long *keys, int n)
     }
 }
 
-// Relative bound of the FP32 distance (see the verify kernel) and the band
-// threshold F_K * (1 + eps) / (1 - eps), rounded up to float.
+// Band threshold F_K * (1 + eps) / (1 - eps), rounded up to float: every key
+// of the exact top-K has an FP32 distance at most this (see the verify kernel).
 __device__ inline float band_threshold(float FK, float eps)
 {
     const double t = (double)FK * (1.0 + (double)eps) / (1.0 - (double)eps) + 0x1p-100;
@@ -234,271 +344,12 @@ __device__ inline float band_threshold(float FK, float eps)
     return f;
 }
 
-enum { F_CHUNK = 0, F_QQ, F_NC, F_NSCAL = 8 };
-
-__device__ inline unsigned long long wave_min_u64(unsigned long long v)
-{
-    for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long o = __shfl_xor(v, off);
-        v = o < v ? o : v;
-    }
-    return v;
-}
-
-__device__ inline void cswap(unsigned long long &a, unsigned long long &b)
-{
-    const unsigned long long lo = a < b ? a : b, hi = a < b ? b : a;
-    a = lo;
-    b = hi;
-}
-
-// The R smallest of the 4*64 keys held four per lane, ascending, into out[0..R)
-// (lane 0 writes).  Keys are distinct apart from ~0 padding.  One wave.
-__device__ inline void wave_extract(unsigned long long e0, unsigned long long e1,
-                                    unsigned long long e2, unsigned long long e3, int R,
-                                    unsigned long long *out)
-{
-    cswap(e0, e1);
-    cswap(e2, e3);
-    cswap(e0, e2);
-    cswap(e1, e3);
-    cswap(e1, e2);
-    int h = 0;
-    for (int r = 0; r < R; ++r) {
-        const unsigned long long v = h == 0 ? e0 : h == 1 ? e1 : h == 2 ? e2 : h == 3 ? e3 : ~0ull;
-        const unsigned long long m = wave_min_u64(v);
-        if (v == m && m != ~0ull) ++h;
-        if ((threadIdx.x & 63) == 0) out[r] = m;
-    }
-}
-
-template <int DT, int UN, int PM>
-__global__ __launch_bounds__(kBlock) void verify_flat_kernel(FlatArgs A)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int tid = threadIdx.x;
-    unsigned long long *keys = reinterpret_cast<unsigned long long *>(smem);
-    unsigned char *qrow = smem + size_t(A.C) * 8;
-    const int elem = DT == QW_U8 ? 1 : 4;
-    const int row_bytes = A.dp * elem;
-    uint32_t *scal = reinterpret_cast<uint32_t *>(qrow + a16(row_bytes));
-    unsigned long long *wout = reinterpret_cast<unsigned long long *>(
-        reinterpret_cast<unsigned char *>(scal) + F_NSCAL * 4 + 16);  // [4][64]
-    uint32_t *cids = reinterpret_cast<uint32_t *>(wout + 4 * 64);     // [C] chunk's ids
-    const int parts = row_bytes / 16;
-    int G = 1;
-    while (G < parts && G < 64) G <<= 1;
-    const int P = (parts + G - 1) / G;
-    const int NG = kBlock / G;
-    const int per_iter = NG * UN;
-    const int grp = tid / G, j = tid % G;
-    const float eps = (float)((4 * P + 16) * 0x1p-24 + (A.d + 2) * 0x1p-52);
-    const unsigned long long N = *A.nchunks;
-    const int xcd = blockIdx.x & 7;
-
-    while (true) {
-        if (tid == 0) {
-            unsigned long long pick = ~0ull;
-            for (int r = 0; r < 8 && pick == ~0ull; ++r) {
-                const int x = (xcd + r) & 7;
-                const unsigned long long b = N * x / 8, e = N * (x + 1) / 8;
-                if (A.xcd_ctr[x] >= (uint32_t)(e - b)) continue;  // drained (read may be stale)
-                const unsigned long long t = b + atomicAdd(&A.xcd_ctr[x], 1u);
-                if (t < e) pick = t;
-            }
-            reinterpret_cast<unsigned long long *>(scal)[0] = pick;
-        }
-        __syncthreads();
-        const unsigned long long chunk = reinterpret_cast<unsigned long long *>(scal)[0];
-        if (chunk == ~0ull) break;
-        const unsigned long long dsc = A.desc[chunk];
-        const int64_t q = (int64_t)(dsc >> 32);
-        const uint32_t cb = (uint32_t)dsc;
-        const uint32_t U = A.ucount[q];
-        const int nc = (int)min((uint32_t)A.C, U - cb);
-        const int32_t *list = A.cand + A.coff[q] + cb;
-        for (int i = tid; i < nc; i += kBlock) cids[i] = (uint32_t)list[i];
-        {  // query row and candidate ids into LDS (+ |q|^2 for uint8)
-            const uint4 *src = reinterpret_cast<const uint4 *>((const unsigned char *)A.queries +
-                                                               q * (int64_t)row_bytes);
-            uint4 *dst = reinterpret_cast<uint4 *>(qrow);
-            uint32_t qq = 0;
-            for (int i = tid; i < parts; i += kBlock) {
-                const uint4 v = src[i];
-                dst[i] = v;
-                if (DT == QW_U8) {
-                    qq = __builtin_amdgcn_udot4(v.x, v.x, qq, false);
-                    qq = __builtin_amdgcn_udot4(v.y, v.y, qq, false);
-                    qq = __builtin_amdgcn_udot4(v.z, v.z, qq, false);
-                    qq = __builtin_amdgcn_udot4(v.w, v.w, qq, false);
-                }
-            }
-            if (tid == 0) scal[2 + F_QQ] = 0;
-            __syncthreads();
-            if (DT == QW_U8 && qq) atomicAdd(&scal[2 + F_QQ], qq);
-            __syncthreads();
-        }
-        const uint32_t qq = scal[2 + F_QQ];
-        for (int c0 = 0; c0 < nc; c0 += per_iter) {
-            uint32_t cid[UN];
-            bool cv[UN];
-            for (int u = 0; u < UN; ++u) {
-                const int c = c0 + grp + NG * u;
-                cv[u] = c < nc;
-                cid[u] = cv[u] ? cids[c] : 0u;
-            }
-            uint32_t accu[UN];
-            float accf[UN];
-            for (int u = 0; u < UN; ++u) {
-                accu[u] = 0;
-                accf[u] = 0.f;
-            }
-            for (int p0 = 0; p0 < P; p0 += PM) {
-                uint4 xv[UN][PM];
-                for (int u = 0; u < UN; ++u)
-                    for (int pp = 0; pp < PM; ++pp) {
-                        const int part = j + G * (p0 + pp);
-                        if (cv[u] && p0 + pp < P && part < parts)
-                            xv[u][pp] = reinterpret_cast<const uint4 *>(
-                                (const unsigned char *)A.data + (int64_t)cid[u] * row_bytes)[part];
-                        else
-                            xv[u][pp] = make_uint4(0, 0, 0, 0);
-                    }
-                for (int pp = 0; pp < PM; ++pp) {
-                    const int part = j + G * (p0 + pp);
-                    if (p0 + pp >= P || part >= parts) continue;
-                    const uint4 qv = reinterpret_cast<const uint4 *>(qrow)[part];
-                    for (int u = 0; u < UN; ++u) {
-                        const uint4 x = xv[u][pp];
-                        if (DT == QW_U8) {
-                            uint32_t xx = 0, xq = 0;
-                            xx = __builtin_amdgcn_udot4(x.x, x.x, xx, false);
-                            xx = __builtin_amdgcn_udot4(x.y, x.y, xx, false);
-                            xx = __builtin_amdgcn_udot4(x.z, x.z, xx, false);
-                            xx = __builtin_amdgcn_udot4(x.w, x.w, xx, false);
-                            xq = __builtin_amdgcn_udot4(x.x, qv.x, xq, false);
-                            xq = __builtin_amdgcn_udot4(x.y, qv.y, xq, false);
-                            xq = __builtin_amdgcn_udot4(x.z, qv.z, xq, false);
-                            xq = __builtin_amdgcn_udot4(x.w, qv.w, xq, false);
-                            accu[u] += xx - 2u * xq;
-                        } else {
-                            const float d0 = __uint_as_float(x.x) - __uint_as_float(qv.x);
-                            const float d1 = __uint_as_float(x.y) - __uint_as_float(qv.y);
-                            const float d2 = __uint_as_float(x.z) - __uint_as_float(qv.z);
-                            const float d3 = __uint_as_float(x.w) - __uint_as_float(qv.w);
-                            float sacc = accf[u];
-                            sacc = fmaf(d0, d0, sacc);
-                            sacc = fmaf(d1, d1, sacc);
-                            sacc = fmaf(d2, d2, sacc);
-                            sacc = fmaf(d3, d3, sacc);
-                            accf[u] = sacc;
-                        }
-                    }
-                }
-            }
-            for (int u = 0; u < UN; ++u)
-                for (int off = G >> 1; off > 0; off >>= 1) {
-                    if (DT == QW_U8)
-                        accu[u] += (uint32_t)__shfl_xor((int)accu[u], off);
-                    else
-                        accf[u] += __shfl_xor(accf[u], off);
-                }
-            if (j == 0)
-                for (int u = 0; u < UN; ++u) {
-                    if (!cv[u]) continue;
-                    const uint32_t hi = DT == QW_U8 ? accu[u] + qq : __float_as_uint(accf[u]);
-                    keys[c0 + grp + NG * u] = ((unsigned long long)hi << 32) | cid[u];
-                }
-        }
-        __syncthreads();
-        if (A.PS < 64 && A.C == 4 * kBlock) {
-            // wave-level selection: each wave extracts the PS+1 smallest of its
-            // quarter, then wave 0 extracts the PS+1 smallest of the four lists
-            const int wid = tid >> 6, lane = tid & 63, R = A.PS + 1;
-            unsigned long long e[4];
-            for (int i = 0; i < 4; ++i) {
-                const int idx = wid * 256 + lane + 64 * i;
-                e[i] = idx < nc ? keys[idx] : ~0ull;
-            }
-            wave_extract(e[0], e[1], e[2], e[3], R, wout + wid * 64);
-            __syncthreads();
-            if (wid == 0) {
-                for (int i = 0; i < 4; ++i) e[i] = lane < R ? wout[i * 64 + lane] : ~0ull;
-                wave_extract(e[0], e[1], e[2], e[3], R, keys);
-            }
-            __syncthreads();
-        } else {
-            sort_keys(keys, nc);
-        }
-        // chunk result: the K best, plus for float data the band around the K-th
-        int cnt = nc < A.K ? nc : A.K;
-        if (DT == QW_F32 && nc > A.K) {
-            const float thr = band_threshold(__uint_as_float((uint32_t)(keys[A.K - 1] >> 32)), eps);
-            while (cnt < nc && cnt < A.PS && __uint_as_float((uint32_t)(keys[cnt] >> 32)) <= thr)
-                ++cnt;
-            if (cnt == A.PS && cnt < nc && __uint_as_float((uint32_t)(keys[cnt] >> 32)) <= thr &&
-                tid == 0)
-                A.flag[q] = 1;  // band wider than the chunk result: fallback
-        }
-        for (int t = tid; t < cnt; t += kBlock) A.part[chunk * A.PS + t] = keys[t];
-        if (tid == 0) A.pcount[chunk] = (uint32_t)cnt;
-        __syncthreads();
-    }
-}
-
-static bool flat_small(int dp, int dtype) { return dp * (dtype == QW_U8 ? 1 : 4) / 16 <= 64; }
-
-size_t flat_lds_bytes(int C, int dp, int dtype)
-{
-    return size_t(C) * 8 + a16(size_t(dp) * (dtype == QW_U8 ? 1 : 4)) + F_NSCAL * 4 + 16 +
-           4 * 64 * 8 + size_t(C) * 4;
-}
-
-static const void *flat_fn(int dp, int dtype)
-{
-    const bool small = flat_small(dp, dtype);
-    if (dtype == QW_U8)
-        return small ? (const void *)verify_flat_kernel<QW_U8, 4, 1>
-                     : (const void *)verify_flat_kernel<QW_U8, 2, 4>;
-    return small ? (const void *)verify_flat_kernel<QW_F32, 4, 1>
-                 : (const void *)verify_flat_kernel<QW_F32, 2, 4>;
-}
-
-int flat_blocks_per_cu(int C, int dp, int dtype)
-{
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, flat_fn(dp, dtype), kBlock,
-                                                     flat_lds_bytes(C, dp, dtype)) != hipSuccess) {
-        (void)hipGetLastError();
-        nb = 1;
-    }
-    return nb > 0 ? nb : 1;
-}
-
-qw_status launch_verify_flat(const FlatArgs &a, int grid, hipStream_t s)
-{
-    if (grid <= 0) return QW_OK;
-    const size_t lds = flat_lds_bytes(a.C, a.dp, a.dtype);
-    const bool small = flat_small(a.dp, a.dtype);
-    if (a.dtype == QW_U8) {
-        if (small) verify_flat_kernel<QW_U8, 4, 1><<<grid, kBlock, lds, s>>>(a);
-        else verify_flat_kernel<QW_U8, 2, 4><<<grid, kBlock, lds, s>>>(a);
-    } else {
-        if (small) verify_flat_kernel<QW_F32, 4, 1><<<grid, kBlock, lds, s>>>(a);
-        else verify_flat_kernel<QW_F32, 2, 4><<<grid, kBlock, lds, s>>>(a);
-    }
-    QW_HIP(hipGetLastError());
-    return QW_OK;
-}
-
-// ---------------------------------------------------------------- merge
-
 struct RankF {
     double D;
     uint32_t id, pad;
 };
 
-__device__ __noinline__ double exact_dist_f32_m(const float *__restrict__ x,
+__device__ __noinline__ double exact_dist_f32_s(const float *__restrict__ x,
                                                 const float *__restrict__ q, int32_t d)
 {
     double acc = 0.0;
@@ -509,51 +360,84 @@ __device__ __noinline__ double exact_dist_f32_m(const float *__restrict__ x,
     return acc;
 }
 
-// One workgroup per query: gather the chunk results, sort, keep K.
+// One workgroup per query.  Keys stream through a threshold: a key enters the
+// LDS list only if it is at most the current K-th key (uint8: keys are unique
+// (distance, id) pairs, so exactly K survive) or within the band of the K-th
+// distance (float); when the list passes half its capacity it is sorted and cut
+// back to the K best plus the band.
 template <int DT>
-__global__ __launch_bounds__(kBlock) void merge_kernel(MergeArgs A)
+__global__ __launch_bounds__(kBlock) void select_kernel(SelectArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    unsigned long long *keys = reinterpret_cast<unsigned long long *>(smem);
-    RankF *rk = reinterpret_cast<RankF *>(smem + size_t(A.MB) * 8);
-    __shared__ uint32_t s_total, s_bad;
+    unsigned long long *lst = reinterpret_cast<unsigned long long *>(smem);
+    RankF *rk = reinterpret_cast<RankF *>(smem + size_t(A.LC) * 8);
+    __shared__ unsigned long long s_thr;
+    __shared__ uint32_t s_cnt, s_bad;
     const int64_t q = blockIdx.x;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const unsigned long long lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     if (tid == 0) {
-        s_total = 0;
+        s_cnt = 0;
+        s_thr = ~0ull;
         s_bad = A.flag[q];
     }
     __syncthreads();
-    const uint32_t nch = A.qnch[q], c0 = A.qcbeg[q];
-    if (!s_bad) {
-        // chunk results are appended at positions from an LDS counter (order is
-        // irrelevant: everything is sorted afterwards)
-        for (uint32_t t = tid; t < nch; t += kBlock) {
-            const uint32_t cnt = A.pcount[c0 + t];
-            const uint32_t pos = atomicAdd(&s_total, cnt);
-            if (pos + cnt > (uint32_t)A.MB) {
-                s_bad = 1;
-                continue;
-            }
-            for (uint32_t e = 0; e < cnt; ++e) keys[pos + e] = A.part[(size_t)(c0 + t) * A.PS + e];
-        }
-    }
-    __syncthreads();
     if (s_bad) {
-        if (tid == 0) {
-            const uint32_t o = atomicAdd(A.fb_count, 1u);
-            A.fb_list[o] = (int32_t)q;
-        }
+        if (tid == 0) A.fb_list[atomicAdd(A.fb_count, 1u)] = (int32_t)q;
         return;
     }
-    const int total = (int)s_total;
-    sort_keys(keys, total);
+    const uint32_t U = A.ucount[q];
+    const unsigned long long *keys = A.keys + (U ? A.coff[q] : 0ull);
+    // trim: sort the list, keep the K best (uint8) or every key within the band
+    // of the K-th (float); the threshold tightens accordingly
+    auto trim = [&]() {
+        const int n = (int)s_cnt;
+        sort_keys(lst, n);
+        if (tid == 0 && n >= A.K) {
+            const unsigned long long kk = lst[A.K - 1];
+            unsigned long long thr = kk;
+            int keep = A.K;
+            if (DT != QW_U8) {
+                const float bt = band_threshold(__uint_as_float((uint32_t)(kk >> 32)), A.eps);
+                thr = ((unsigned long long)__float_as_uint(bt) << 32) | 0xFFFFFFFFull;
+                while (keep < n && lst[keep] <= thr) ++keep;
+            }
+            s_cnt = (uint32_t)keep;
+            s_thr = thr;
+            if (keep > A.LC / 2) s_bad = 1;  // band too wide for the list
+        }
+        __syncthreads();
+    };
+    for (uint32_t b0 = 0; b0 < U; b0 += 4 * kBlock) {
+        const unsigned long long thr = s_thr;
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t e = b0 + (uint32_t)(i * kBlock + tid);
+            const unsigned long long k = e < U ? keys[e] : ~0ull;
+            const bool take = e < U && k <= thr;
+            const unsigned long long m = __ballot(take);
+            uint32_t wb = 0;
+            if (lane == 0 && m) wb = atomicAdd(&s_cnt, (uint32_t)__popcll(m));
+            wb = (uint32_t)__shfl((int)wb, 0);
+            if (take) lst[wb + (uint32_t)__popcll(m & lt_mask)] = k;
+        }
+        __syncthreads();
+        const bool full = (int)s_cnt > A.LC / 2;
+        __syncthreads();  // every thread has read s_cnt before the next pass adds to it
+        if (full) trim();
+        if (s_bad) break;  // set only inside trim, before its barrier
+    }
+    if (!s_bad) trim();
+    if (s_bad) {
+        if (tid == 0) A.fb_list[atomicAdd(A.fb_count, 1u)] = (int32_t)q;
+        return;
+    }
+    const int n = (int)s_cnt;
     if (DT == QW_U8) {
         for (int r = tid; r < A.K; r += kBlock) {
             const int64_t o = q * A.K + r;
-            if (r < total) {
-                A.out_ids[o] = (int32_t)(uint32_t)keys[r];
-                reinterpret_cast<int32_t *>(A.out_dist)[o] = (int32_t)(keys[r] >> 32);
+            if (r < n) {
+                A.out_ids[o] = (int32_t)(uint32_t)lst[r];
+                reinterpret_cast<int32_t *>(A.out_dist)[o] = (int32_t)(lst[r] >> 32);
             } else {
                 A.out_ids[o] = -1;
                 reinterpret_cast<int32_t *>(A.out_dist)[o] = INT32_MAX;
@@ -561,23 +445,17 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(MergeArgs A)
         }
         return;
     }
-    // float data: FP64 index-order distances for every entry within the band of
-    // the K-th FP32 distance, then the exact (D, id) order
-    int nb = total;
-    if (total > A.K) {
-        const float thr = band_threshold(__uint_as_float((uint32_t)(keys[A.K - 1] >> 32)), A.eps);
-        nb = A.K;
-        while (nb < total && __uint_as_float((uint32_t)(keys[nb] >> 32)) <= thr) ++nb;
-    }
+    // float data: FP64 index-order distances of every key in the band, then
+    // the exact (D, id) order
     const float *qrow = (const float *)A.queries + q * (int64_t)A.dp;
-    for (int e = tid; e < nb; e += kBlock) {
-        const uint32_t id = (uint32_t)keys[e];
-        rk[e].D = exact_dist_f32_m((const float *)A.data + (int64_t)id * A.dp, qrow, A.d);
+    for (int e = tid; e < n; e += kBlock) {
+        const uint32_t id = (uint32_t)lst[e];
+        rk[e].D = exact_dist_f32_s((const float *)A.data + (int64_t)id * A.dp, qrow, A.d);
         rk[e].id = id;
     }
     int ns = 2;
-    while (ns < nb) ns <<= 1;
-    for (int e = nb + tid; e < ns; e += kBlock) {
+    while (ns < n) ns <<= 1;
+    for (int e = n + tid; e < ns; e += kBlock) {
         rk[e].D = INFINITY;
         rk[e].id = 0xFFFFFFFFu;
     }
@@ -599,7 +477,7 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(MergeArgs A)
         }
     for (int r = tid; r < A.K; r += kBlock) {
         const int64_t o = q * A.K + r;
-        if (r < nb) {
+        if (r < n) {
             A.out_ids[o] = (int32_t)rk[r].id;
             reinterpret_cast<float *>(A.out_dist)[o] = (float)rk[r].D;
         } else {
@@ -609,19 +487,21 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(MergeArgs A)
     }
 }
 
-size_t merge_lds_bytes(int MB, int dtype)
+// The key list holds LC entries; the FP64 re-rank of float data needs LC/2
+// (a band wider than that goes to the fallback).
+size_t select_lds_bytes(int LC, int dtype)
 {
-    return size_t(MB) * 8 + (dtype == QW_F32 ? size_t(MB) * sizeof(RankF) : 0);
+    return size_t(LC) * 8 + (dtype == QW_F32 ? size_t(LC / 2) * sizeof(RankF) : 0);
 }
 
-qw_status launch_merge(const MergeArgs &a, int64_t Q, hipStream_t s)
+qw_status launch_select(const SelectArgs &a, int64_t Q, hipStream_t s)
 {
     if (Q <= 0) return QW_OK;
-    const size_t lds = merge_lds_bytes(a.MB, a.dtype);
+    const size_t lds = select_lds_bytes(a.LC, a.dtype);
     if (a.dtype == QW_U8)
-        merge_kernel<QW_U8><<<(unsigned)Q, kBlock, lds, s>>>(a);
+        select_kernel<QW_U8><<<(unsigned)Q, kBlock, lds, s>>>(a);
     else
-        merge_kernel<QW_F32><<<(unsigned)Q, kBlock, lds, s>>>(a);
+        select_kernel<QW_F32><<<(unsigned)Q, kBlock, lds, s>>>(a);
     QW_HIP(hipGetLastError());
     return QW_OK;
 }

@@ -64,7 +64,7 @@ struct Workspace {
     DevBuf qpad, h, bstart, bsize, qsum, pred, feats, keys, keys2, vals, vals2, hist,
         order, binoff, counters, ovf, gscratch, mlpout, scan;
     // flat pipeline
-    DevBuf ucount, coff, flag, nch_item, chunk_off, qcbeg, qnch, desc, part, pcount, cand, fb;
+    DevBuf ucount, coff, flag, cand, candq, pkeys, fb;
 };
 
 // Launch plan of the fast form for one top-K size: hash-set size classes and
@@ -76,10 +76,8 @@ struct Plan {
     int grid[16] = {};  // fused verify kernel, per class
     int dgrid[16] = {}; // dedup kernel, per class
     int cap_g = 20, grid_g = 1;
-    int C = 1024;       // candidates per chunk
-    int PS = 10;        // chunk result entries
-    int MB = 2048;      // merge capacity (entries)
-    int fgrid = 256;    // streaming verify grid
+    int LC = 2048;      // select kernel list capacity (entries)
+    int ggrid = 256;    // gather grid
     float eps = 0.f;    // FP32 distance bound (float data)
 };
 
@@ -244,33 +242,30 @@ struct DedupArgs {
     int32_t count_only;              // write |C(q)| only
     unsigned long long *alloc;       // bump allocator over cand
     unsigned long long cand_cap;
-    int32_t *cand;                   // unique candidate lists
+    int32_t *cand;                   // unique candidate lists (pair -> id)
+    int32_t *candq;                  // pair -> query
+    unsigned long long *valid_end;   // end of the last granted list
     uint32_t *ucount;                // |C(q)|
     unsigned long long *coff;        // offset of each query's list in cand
     uint32_t *flag;                  // 1 = answer q with the fallback
     unsigned long long *unique_total;
 };
 
-struct FlatArgs {
-    const unsigned long long *desc;    // chunk -> (q << 32) | first candidate
-    const unsigned long long *nchunks; // device total
-    uint32_t *xcd_ctr;                 // 8 work counters, one per XCD range
+struct GatherArgs {
+    const unsigned long long *npairs;  // device: number of valid pairs
+    const int32_t *cand, *candq;       // pair -> candidate id, query
     const void *data, *queries;
-    const int32_t *cand;
-    const unsigned long long *coff;
-    const uint32_t *ucount;
-    int32_t dp, d, dtype, K, C, PS;
-    unsigned long long *part;          // [chunk][PS] (distance << 32 | id) keys
-    uint32_t *pcount;
-    uint32_t *flag;
+    int32_t dp, dtype;
+    unsigned long long *keys;          // pair -> (distance << 32) | id
 };
 
-struct MergeArgs {
-    const uint32_t *qnch, *qcbeg, *pcount;
-    const unsigned long long *part;
-    int32_t PS, MB, K, dtype, dp, d;
-    float eps;
+struct SelectArgs {
+    const unsigned long long *keys;
+    const unsigned long long *coff;
+    const uint32_t *ucount;
     const uint32_t *flag;
+    int32_t K, LC, dtype, dp, d;
+    float eps;
     uint32_t *fb_count;
     int32_t *fb_list;
     int32_t *out_ids;
@@ -281,14 +276,10 @@ struct MergeArgs {
 size_t dedup_lds_bytes(int cap_log2, int global_tab, int L);
 int dedup_blocks_per_cu(size_t lds);
 qw_status launch_dedup(const DedupArgs &a, int grid, hipStream_t s);
-qw_status launch_chunks(const int32_t *order, int64_t Q, const uint32_t *ucount, uint32_t C,
-                        uint32_t *nch_item, unsigned long long *chunk_off, DevBuf &scan,
-                        unsigned long long *desc, uint32_t *qcbeg, uint32_t *qnch, hipStream_t s);
-size_t flat_lds_bytes(int C, int dp, int dtype);
-int flat_blocks_per_cu(int C, int dp, int dtype);
-qw_status launch_verify_flat(const FlatArgs &a, int grid, hipStream_t s);
-size_t merge_lds_bytes(int MB, int dtype);
-qw_status launch_merge(const MergeArgs &a, int64_t Q, hipStream_t s);
+int gather_blocks_per_cu(int dp, int dtype);
+qw_status launch_gather(const GatherArgs &a, int grid, hipStream_t s);
+size_t select_lds_bytes(int LC, int dtype);
+qw_status launch_select(const SelectArgs &a, int64_t Q, hipStream_t s);
 // Scratch bytes launch_scan_u32_to_u64 needs for `count` values.
 size_t scan_scratch_bytes(int64_t count);
 

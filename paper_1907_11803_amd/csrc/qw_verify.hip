@@ -271,7 +271,7 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
         // ---- phase 1: de-duplicated union of the L bucket lists
         if (A.mode != VM_ALL)
             set_union(A.ids, A.n, A.L, lpref, lstart, T, tab, cap_log2, limit, glob != 0,
-                      A.short_probe ? kShortProbe : 0xFFFFFFFFu, &scal[S_UCOUNT], &scal[S_OVF],
+                      A.short_probe ? kShortProbe : 0xFFFFFFFFu, true, &scal[S_UCOUNT], &scal[S_OVF],
                       &scal[S_CPOS]);
         const uint32_t U = A.mode == VM_ALL ? (uint32_t)A.n : scal[S_UCOUNT];
         if (A.mode != VM_ALL && (scal[S_OVF] || U > limit)) {
