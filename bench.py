@@ -111,6 +111,9 @@ def main():
         t1 = time.time()
         ix = lib.Index(data_d, a_d, b_d, w, form=lib.QW_FORM_FAST)
         build_s = time.time() - t1
+        if args.profile:  # profiling runs time the query loop only
+            chosen = (w, ix, b_d, None, None)
+            break
         if truth is None:
             t1 = time.time()
             ti, td = ix.bruteforce(q_d, K)
@@ -135,7 +138,8 @@ def main():
     train_d = torch.from_numpy(train).to(dev)
     train_loss = ix.train_count_model(train_d, epochs=8, batch=1024, lr=2e-3, seed=1)
     del train_d
-    log(f"[bench] count model trained on {args.train_queries} queries, loss {train_loss:.4f} "
+    log(f"[bench] count model trained on {args.train_queries} queries, loss {train_loss:.4f}, "
+        f"sizing margin {ix.info()['count_margin']:.3f} "
         f"in {time.time() - t1:.1f}s")
 
     out_ids = torch.empty((wl.Q, K), dtype=torch.int32, device=dev)
@@ -183,6 +187,8 @@ def main():
     for name, sc in (("sum", lib.QW_SCHED_SUM), ("actual", lib.QW_SCHED_ACTUAL),
                      ("none", lib.QW_SCHED_NONE), ("learned", lib.QW_SCHED_LEARNED)):
         sched_ms[name] = round(timed(lib.make_opts(sched=sc), max(5, args.steps // 2), 2), 4)
+    sched_ms["learned_no_grouping"] = round(
+        timed(lib.make_opts(sched=lib.QW_SCHED_LEARNED, group=0), max(5, args.steps // 2), 2), 4)
     log(f"[bench] fast {ms_fast:.3f} ms/step, plain {ms_plain:.3f} ms/step, scheds {sched_ms}")
 
     # ---- per-stage timing of the fast pipeline (events inside the library)

@@ -108,6 +108,7 @@ typedef struct {
     int64_t max_bucket;    /* largest bucket size */
     int64_t device_bytes;  /* device memory held by the index */
     int32_t has_count_model;
+    float count_margin;    /* log-space margin added to the model's prediction when sizing sets */
 } qw_index_info;
 
 typedef struct qw_index qw_index;
@@ -230,16 +231,23 @@ qw_status qw_mlp_predict_bf16(const float *params, int32_t L, const float *feats
 /*
  * Train the index's count model on m training queries (device, m x d): the
  * engine computes features (bucket sizes) and labels (exact |C(q)|) itself and
- * runs `epochs` passes of minibatch Adam.  final_loss: host, nullable.
- * Synchronises `stream`.
+ * runs `epochs` passes of minibatch Adam.  It then calibrates the sizing
+ * margin: the 99.5th percentile of log(1 + |C(q)|) minus the prediction over
+ * the training queries (at least 0.05), so that about 1 query in 200 outgrows
+ * the set chosen for it.  final_loss: host, nullable.  Synchronises `stream`.
  */
 qw_status qw_train_count_model(qw_index *ix, const void *train_queries, int64_t m,
                                int32_t epochs, int32_t batch, float lr, uint64_t seed,
                                void *stream, float *final_loss);
 
-/* Install / read the count model parameters (host float32 [P]). */
+/* Install / read the count model parameters (host float32 [P]).  Installing
+ * resets the sizing margin to log(1.25). */
 qw_status qw_set_count_model(qw_index *ix, const float *params, int32_t P);
 qw_status qw_get_count_model(const qw_index *ix, float *params, int32_t P);
+
+/* Sizing margin: a set is sized for expm1(prediction + margin) + 32 ids
+ * (finite, -4 <= margin <= 8; QW_EINVAL otherwise). */
+qw_status qw_set_count_margin(qw_index *ix, float margin);
 
 #ifdef __cplusplus
 }

@@ -15,8 +15,8 @@ namespace {
 
 // counters buffer: u64 [kC64] then u32 [kC32]
 enum {
-    C_RECOMP = 0, C_UNIQUE, C_PROBEHIT, C_CANDTOT, C_CLASS /* .. C_CLASS+15 */, C_ALLOC = 20,
-    C_VEND = 21, kC64 = 24
+    C_RECOMP = 0, C_UNIQUE, C_PROBEHIT, C_CANDTOT, C_CLASS /* .. C_CLASS+15 */,
+    C_ALLOC = 20 /* .. +kXcd-1 */, C_FAIL = 28 /* .. +kXcd-1 */, C_SPARE = 36, kC64 = 40
 };
 // u32: persistent work counters per class, overflow-queue lengths per class
 // (queue i holds queries that overflowed class i-1), per-XCD chunk counters,
@@ -26,7 +26,6 @@ enum { W_WORK = 0 /* .. 15 */, W_QCNT = 16 /* .. 32 */, W_SIMPLE = 33, W_MAX = 3
 constexpr int64_t kCandPerQuery = 4096;  // pair space reserved per query (beyond: fallback)
 constexpr int kCmin = 10;
 constexpr int kMaxClasses = 16;
-constexpr float kMargin = 1.25f;  // learned schedule: slack on the predicted count
 
 
 inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
@@ -55,13 +54,17 @@ Plan make_plan(qw_index *ix, int K)
     p.buf = pow2_at_least(std::max(64, 2 * (K + verify_per_iter(ix->dp, ix->dtype))));
     int c = kCmin;
     while (c + 1 < 30 && (int)(c + 1 - kCmin) < kMaxClasses - 1 &&
-           verify_lds_bytes(c + 1, p.buf, 0, ix->L, ix->dp, ix->dtype) <= ix->lds_max)
+           dedup_lds_bytes(c + 1, 0, ix->L) <= ix->lds_max)
         ++c;
     p.cmax = c;
     p.ncls = (p.cmax - kCmin + 1) + 1;
-    for (int i = 0; i + 1 < p.ncls; ++i) {
-        const size_t lds = verify_lds_bytes(kCmin + i, p.buf, 0, ix->L, ix->dp, ix->dtype);
-        p.grid[i] = verify_blocks_per_cu(ix->dp, ix->dtype, lds) * ix->cus;
+    // largest LDS set that does not lower the dedup kernel's occupancy (its
+    // registers bound it first): smaller sets save nothing
+    p.cfloor = kCmin;
+    {
+        const int nb0 = dedup_blocks_per_cu(dedup_lds_bytes(kCmin, 0, ix->L));
+        while (p.cfloor < p.cmax && dedup_blocks_per_cu(dedup_lds_bytes(p.cfloor + 1, 0, ix->L)) >= nb0)
+            ++p.cfloor;
     }
     const uint64_t bound = std::min<uint64_t>((uint64_t)ix->L * (uint64_t)std::max<int64_t>(1, ix->max_bucket),
                                               (uint64_t)ix->n);
@@ -70,14 +73,13 @@ Plan make_plan(qw_index *ix, int K)
     const double per_wg = std::ldexp(4.0, p.cap_g);
     const double budget = 2.0 * 1024 * 1024 * 1024;
     p.grid_g = (int)std::max(1.0, std::min((double)ix->cus, std::floor(budget / per_wg)));
-    p.grid[p.ncls - 1] = p.grid_g;
     for (int i = 0; i + 1 < p.ncls; ++i)
         p.dgrid[i] = dedup_blocks_per_cu(dedup_lds_bytes(kCmin + i, 0, ix->L)) * ix->cus;
     p.dgrid[p.ncls - 1] = p.grid_g;
-    // a pass adds at most 4 * kBlock keys to a list cut back to <= LC/2, and
-    // K <= 1024 keeps LC <= 4096 (32 KiB of keys, 64 KiB with the FP64 re-rank)
-    static_assert(4 * kBlock <= 1024 && kMaxTopK <= 1024, "select list sizing");
-    p.LC = pow2_at_least(std::max(2048, 4 * K));
+    // select list: a few K keys in the usual case; K <= 1024 keeps LC <= 4096
+    // (32 KiB of keys, 64 KiB with the FP64 re-rank of float data)
+    static_assert(kMaxTopK <= 1024 && kBlock <= 1024, "select list sizing");
+    p.LC = pow2_at_least(std::max(1024, 4 * K));
     p.ggrid = gather_blocks_per_cu(ix->dp, ix->dtype) * ix->cus;
     {  // FP32 distance bound of the gather kernel (float data)
         const int parts = ix->dp * (ix->dtype == QW_U8 ? 1 : 4) / 16;
@@ -122,11 +124,12 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan)
     QW_TRY(w.counters.ensure(sizeof(unsigned long long) * kC64 + sizeof(uint32_t) * kC32));
     QW_TRY(w.hist.ensure(radix_sort_scratch_bytes(q)));
     QW_TRY(w.scan.ensure(scan_scratch_bytes(q)));
+    QW_TRY(w.ucount.ensure(sizeof(uint32_t) * q));  // |C(q)|, written on every path
     if (plan) {
         const size_t g = (size_t)plan->grid_g * (size_t(1) << plan->cap_g) * 4;
         QW_TRY(w.gscratch.ensure(g));
+        // a multiple of kXcd: one equal region per XCD
         const int64_t cand_cap = std::max<int64_t>(q * kCandPerQuery, 1 << 20);
-        QW_TRY(w.ucount.ensure(sizeof(uint32_t) * q));
         QW_TRY(w.coff.ensure(sizeof(unsigned long long) * q));
         QW_TRY(w.flag.ensure(sizeof(uint32_t) * q));
         QW_TRY(w.cand.ensure(sizeof(int32_t) * cand_cap));
@@ -156,6 +159,7 @@ VerifyArgs base_args(qw_index *ix, int K, int mode)
     a.queries = ix->ws.qpad.p;
     a.ovf_count = c32(ix) + W_DUMMY;  // callers that can overflow set a real queue
     a.ovf_list = ix->ws.ovf.as<int32_t>();
+    a.ucount_out = ix->ws.ucount.as<uint32_t>();
     return a;
 }
 
@@ -203,7 +207,6 @@ qw_status verify_simple(qw_index *ix, int64_t Q, int K, int mode, hipStream_t s,
     a.out_dist = out_dist;
     a.out_counts = out_counts;
     a.offsets = offsets;
-    a.unique_total = c64(ix) + C_UNIQUE;
     if (verify_lds_bytes(cap, buf, 0, ix->L, ix->dp, ix->dtype) <= ix->lds_max) {
         a.cap_log2 = (uint32_t)cap;
         a.limit = (1u << cap) / 4 * 3;
@@ -252,8 +255,8 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     auto schedule = [&](const int32_t *ex, const float *pl, int force_max,
                         const int32_t **order) -> qw_status {
         QW_TRY(launch_classify(Q, ix->L, ix->n, w.qsum.as<uint32_t>(), w.bstart.as<uint32_t>(),
-                               w.bsize.as<uint32_t>(), ex, pl, kMargin, force_max, kCmin,
-                               plan.cmax, plan.ncls, o.group, w.keys.as<unsigned long long>(),
+                               w.bsize.as<uint32_t>(), ex, pl, ix->mlp_margin, force_max, kCmin,
+                               plan.cfloor, plan.cmax, plan.ncls, o.group, w.keys.as<unsigned long long>(),
                                w.vals.as<int32_t>(), ccount, s));
         bool alt = false;
         QW_TRY(radix_sort_pairs(w.keys.as<unsigned long long>(), w.vals.as<int32_t>(), Q,
@@ -272,7 +275,6 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
             std::memset(&a, 0, sizeof(a));
             a.order = order;
             a.seg = seg + 2 * i;
-            a.counter = c32(ix) + W_WORK + i;
             a.in_list = i > 0 ? queues + (int64_t)i * Q : nullptr;
             a.in_count = i > 0 ? c32(ix) + W_QCNT + i : nullptr;
             a.ovf_list = queues + (int64_t)(i + 1) * Q;
@@ -284,14 +286,13 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
             a.L = ix->L;
             a.count_only = count_only;
             a.alloc = c64(ix) + C_ALLOC;
-            a.cand_cap = (unsigned long long)cand_cap;
+            a.fail = c64(ix) + C_FAIL;
+            a.region = (unsigned long long)(cand_cap / kXcd);
             a.cand = w.cand.as<int32_t>();
             a.candq = w.candq.as<int32_t>();
-            a.valid_end = c64(ix) + C_VEND;
             a.ucount = w.ucount.as<uint32_t>();
             a.coff = w.coff.as<unsigned long long>();
             a.flag = w.flag.as<uint32_t>();
-            a.unique_total = count_only ? nullptr : c64(ix) + C_UNIQUE;
             if (i == plan.ncls - 1) {
                 a.cap_log2 = (uint32_t)plan.cap_g;
                 a.limit = (1u << plan.cap_g) / 4 * 3;
@@ -327,7 +328,9 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     if (ev) QW_HIP(hipEventRecord(ev[6], s));
     GatherArgs g;
     std::memset(&g, 0, sizeof(g));
-    g.npairs = c64(ix) + C_VEND;
+    g.alloc = c64(ix) + C_ALLOC;
+    g.fail = c64(ix) + C_FAIL;
+    g.region = (unsigned long long)(cand_cap / kXcd);
     g.cand = w.cand.as<int32_t>();
     g.candq = w.candq.as<int32_t>();
     g.data = ix->data.p;
@@ -383,6 +386,9 @@ qw_status fill_stats(qw_index *ix, int64_t Q, hipStream_t s, qw_stats *st, hipEv
     if (Q <= 0) return QW_OK;
     QW_TRY(launch_probe_stats(ix->ws.bsize.as<uint32_t>(), Q * ix->L, c64(ix) + C_PROBEHIT,
                               c64(ix) + C_CANDTOT, s));
+    // |C(q)| of every query, written by whichever kernel answered it
+    QW_TRY(launch_probe_stats(ix->ws.ucount.as<uint32_t>(), Q, c64(ix) + C_SPARE,
+                              c64(ix) + C_UNIQUE, s));
     unsigned long long h64[kC64];
     uint32_t h32[kC32];
     QW_HIP(hipMemcpyAsync(h64, c64(ix), sizeof(h64), hipMemcpyDeviceToHost, s));
@@ -512,6 +518,7 @@ qw_status qw_get_index_info(const qw_index *ix, qw_index_info *info)
                             &ix->ids, &ix->tab, &ix->tab_off, &ix->tab_mask, &ix->mlp_dev};
     for (const DevBuf *b : bufs) info->device_bytes += (int64_t)b->bytes;
     info->has_count_model = ix->mlp.empty() ? 0 : 1;
+    info->count_margin = ix->mlp_margin;
     return QW_OK;
 }
 
@@ -726,6 +733,15 @@ qw_status qw_set_count_model(qw_index *ix, const float *params, int32_t P)
     QW_TRY(ix->mlp_dev.ensure(sizeof(float) * P));
     QW_HIP(hipMemcpy(ix->mlp_dev.p, params, sizeof(float) * P, hipMemcpyHostToDevice));
     ix->mlp.assign(params, params + P);
+    ix->mlp_margin = 0.22314355f;
+    drop_graphs(ix);
+    return QW_OK;
+}
+
+qw_status qw_set_count_margin(qw_index *ix, float margin)
+{
+    if (!ix || !std::isfinite(margin) || margin < -4.f || margin > 8.f) return QW_EINVAL;
+    ix->mlp_margin = margin;
     drop_graphs(ix);
     return QW_OK;
 }
@@ -813,7 +829,27 @@ qw_status qw_train_count_model(qw_index *ix, const void *train_queries, int64_t 
         }
         std::vector<float> hp(P);
         QW_HIP(hipMemcpy(hp.data(), params.p, sizeof(float) * P, hipMemcpyDeviceToHost));
-        return qw_set_count_model(ix, hp.data(), P);
+        QW_TRY(qw_set_count_model(ix, hp.data(), P));
+        // calibrate the sizing margin on the training queries, with the same
+        // BF16 inference the schedule uses
+        DevBuf pred;
+        QW_TRY(pred.ensure(sizeof(float) * m));
+        for (int64_t off = 0; off < m; off += INT32_MAX) {
+            const int32_t cnt = (int32_t)std::min<int64_t>(m - off, INT32_MAX);
+            QW_TRY(launch_mlp_predict_bf16(ix->mlp_dev.as<float>(), L, feats.as<float>() + off * L, cnt,
+                                           pred.as<float>() + off, s));
+        }
+        std::vector<float> hpred(m);
+        QW_HIP(hipMemcpyAsync(hpred.data(), pred.p, sizeof(float) * m, hipMemcpyDeviceToHost, s));
+        QW_HIP(hipStreamSynchronize(s));
+        std::vector<float> res(m);
+        for (int64_t i = 0; i < m; ++i) res[i] = hl[i] - hpred[i];
+        const int64_t at = std::min<int64_t>(m - 1, (int64_t)std::ceil(0.995 * (double)m) - 1);
+        std::nth_element(res.begin(), res.begin() + std::max<int64_t>(0, at), res.end());
+        float margin = res[std::max<int64_t>(0, at)];
+        if (!std::isfinite(margin)) margin = 0.22314355f;
+        ix->mlp_margin = std::min(8.f, std::max(0.05f, margin));
+        return QW_OK;
     } catch (const std::bad_alloc &) {
         return QW_ENOMEM;
     }

@@ -1,6 +1,9 @@
 // De-duplicated union of one query's bucket id lists (Sections 1.2 and 5.1:
 // the candidates are the union of the buckets the query falls in, one per
 // layer).  Device code shared by the fused verify kernel and the dedup kernel.
+//
+// The set is an open-addressing hash table of 2^c slots (kEmpty = free) with
+// double hashing; every lane keeps several inserts in flight at once.
 #pragma once
 
 #include "qw_internal.h"
@@ -12,27 +15,138 @@ __device__ inline uint32_t hash_id(uint32_t id, int cap_log2)
     return (id * 0x9E3779B1u) >> (32 - cap_log2);
 }
 
-enum { INS_NEW = 0, INS_DUP = 1, INS_FULL = 2 };
+// odd step: the probe sequence visits every slot of a power-of-two table
+__device__ inline uint32_t hash_step(uint32_t id, int cap_log2)
+{
+    return ((id * 0x85EBCA77u) >> (32 - cap_log2)) | 1u;
+}
 
-// Open addressing with linear probing, at most max_probe slots per insert.
-// Sets that may pass an overflowing query on to a larger set use a short
-// bound (kShortProbe): at load factor <= 3/4 a longer run means the set is
-// (nearly) over its limit, and the insert reports INS_FULL instead of scanning
-// on.  Sets that must hold every id probe the whole capacity.
+// Sets that may pass an overflowing query on to a larger set bound the probes
+// per id (kShortProbe): at load factor <= 3/4 a longer sequence means the set
+// is (nearly) over its limit.  Sets that must hold every id probe every slot.
 constexpr uint32_t kShortProbe = 64;
 
-__device__ inline int set_insert(uint32_t *tab, int cap_log2, uint32_t id, uint32_t max_probe)
+// Inserts the ids id[r] (r < R; bit r of `valid` set, a prefix in r) into the
+// set tab (2^cap_log2 slots, cap_log2 >= 1).  Returns the mask of ids that were
+// new; sets `full` when some id found no slot within max_probe probes (that id
+// is then neither new nor known to be present).
+//
+// The R ids form S streams (stream s: ids s, s + S, ...); each stream inserts
+// its ids one after another, a probe being one compare-and-swap on the slot
+// (free: taken, the id: a duplicate, else the next slot of the id's sequence).
+// The S streams keep S independent LDS atomics in flight per lane, and the
+// work per lane follows the probes its ids need, not the longest sequence of
+// the wave times R.
+template <int R, int S>
+__device__ inline uint32_t insert_streams(uint32_t *tab, int cap_log2, const uint32_t (&id)[R],
+                                          uint32_t valid, uint32_t max_probe, bool &full)
 {
+    static_assert(R % S == 0, "streams split the ids evenly");
+    constexpr int E = R / S;
     const uint32_t mask = (1u << cap_log2) - 1u;
-    uint32_t slot = hash_id(id, cap_log2);
     const uint32_t probes = mask < max_probe ? mask + 1 : max_probe;
-    for (uint32_t it = 0; it < probes; ++it) {
-        uint32_t old = atomicCAS(&tab[slot], kEmpty, id);
-        if (old == kEmpty) return INS_NEW;
-        if (old == id) return INS_DUP;
-        slot = (slot + 1) & mask;
+    // stream s holds its remaining ids in qv[s][0..E) (front = the id being
+    // inserted); finishing one shifts the queue, so every index is static
+    uint32_t qv[S][E];
+    int cur[S], ne[S];
+    uint32_t slot[S], np[S];
+    uint32_t newm = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        ne[s] = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            qv[s][e] = id[s + e * S];
+            ne[s] += (valid >> (s + e * S)) & 1u;
+        }
+        cur[s] = 0;
+        slot[s] = hash_id(qv[s][0], cap_log2);
+        np[s] = 0;
     }
-    return INS_FULL;
+    while (true) {
+        bool any = false;
+#pragma unroll
+        for (int s = 0; s < S; ++s) any |= cur[s] < ne[s];
+        if (!any) break;
+        uint32_t o[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            o[s] = cur[s] < ne[s] ? atomicCAS(&tab[slot[s]], kEmpty, qv[s][0]) : 0u;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const bool act = cur[s] < ne[s];
+            const bool is_new = act && o[s] == kEmpty;
+            const bool moved = act && o[s] != kEmpty && o[s] != qv[s][0];
+            const bool give_up = moved && np[s] + 1 >= probes;
+            const bool done = act && (!moved || give_up);
+            newm |= is_new ? 1u << (s + cur[s] * S) : 0u;
+            full |= give_up;
+            np[s] = done ? 0u : np[s] + (moved ? 1u : 0u);
+            slot[s] = moved && !give_up ? (slot[s] + hash_step(qv[s][0], cap_log2)) & mask : slot[s];
+            if (done) {  // next id of the stream
+#pragma unroll
+                for (int e = 0; e + 1 < E; ++e) qv[s][e] = qv[s][e + 1];
+                ++cur[s];
+                slot[s] = hash_id(qv[s][0], cap_log2);
+            }
+        }
+    }
+    return newm;
+}
+
+// Wave 0 only: lpref[1..L] holds the L list sizes; turns lpref[0..L] into
+// their exclusive prefix and returns the total (L <= 64).
+__device__ inline uint32_t wave_layer_prefix(uint32_t *lpref, int L)
+{
+    const int lane = threadIdx.x & 63;
+    uint32_t v = lane < L ? lpref[lane + 1] : 0u;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_up((int)v, off);
+        if (lane >= off) v += t;
+    }
+    if (lane < L) lpref[lane + 1] = v;
+    if (lane == 0) lpref[0] = 0;
+    return (uint32_t)__shfl((int)v, 63);
+}
+
+// Loads positions base + r * kBlock + threadIdx.x (r < R) of the concatenated
+// layer lists (layer l holds positions [lpref[l], lpref[l+1]) and starts at
+// ids[l*n + lstart[l]]) into id[r]; returns the mask of positions below T.
+// The layers are found by one interleaved binary search (L <= 64: six steps),
+// so all R searches and then all R loads are in flight together.
+template <int R>
+__device__ inline uint32_t load_ids(const int32_t *__restrict__ ids, int64_t n, int32_t L,
+                                    const uint32_t *lpref, const uint32_t *lstart, uint32_t T,
+                                    uint32_t base, uint32_t (&id)[R])
+{
+    uint32_t pos[R];
+    int lo[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        pos[r] = base + (uint32_t)(r * kBlock) + threadIdx.x;
+        lo[r] = 0;
+    }
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            // largest l < L with lpref[l] <= pos; lpref[L] = T > pos stops the
+            // search at the end without a branch around the read
+            const int m = lo[r] + step;
+            const uint32_t v = lpref[m < L ? m : L];
+            lo[r] = v <= pos[r] ? m : lo[r];
+        }
+    uint32_t valid = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        id[r] = 0;
+        if (pos[r] < T) {
+            const int l = lo[r];
+            id[r] = (uint32_t)ids[(int64_t)l * n + lstart[l] + (pos[r] - lpref[l])];
+            valid |= 1u << r;
+        }
+    }
+    return valid;
 }
 
 // Whole workgroup (kBlock threads).  Inserts the T ids of the concatenated
@@ -49,37 +163,19 @@ __device__ inline void set_union(const int32_t *__restrict__ ids, int64_t n, int
                                  uint32_t max_probe, bool compact, uint32_t *ucount,
                                  uint32_t *ovf, uint32_t *cpos)
 {
+    constexpr int R = 8;
     const int tid = threadIdx.x, lane = tid & 63;
     const unsigned long long lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
-    for (uint32_t base = 0; base < T; base += 4 * kBlock) {
+    for (uint32_t base = 0; base < T; base += R * kBlock) {
         // every thread reads the flag before any thread of this pass can set
         // it, so the early exit is uniform
         const bool stop = *ovf != 0;
         __syncthreads();
         if (stop) break;
-        uint32_t ids4[4];
-        bool ok4[4];
-        for (int r = 0; r < 4; ++r) {
-            const uint32_t pos = base + (uint32_t)(r * kBlock + tid);
-            ok4[r] = pos < T;
-            ids4[r] = 0;
-            if (ok4[r]) {
-                int lo = 0, hi = L;  // lpref[lo] <= pos < lpref[hi]
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (lpref[mid] <= pos) lo = mid; else hi = mid;
-                }
-                ids4[r] = (uint32_t)ids[(int64_t)lo * n + lstart[lo] + (pos - lpref[lo])];
-            }
-        }
-        uint32_t nnew = 0;
+        uint32_t idr[R];
+        const uint32_t pend = load_ids<R>(ids, n, L, lpref, lstart, T, base, idr);
         bool full = false;
-        for (int r = 0; r < 4; ++r) {
-            if (!ok4[r]) continue;
-            const int res = set_insert(tab, cap_log2, ids4[r], max_probe);
-            nnew += res == INS_NEW;
-            full |= res == INS_FULL;
-        }
+        uint32_t nnew = (uint32_t)__popc(insert_streams<R, 4>(tab, cap_log2, idr, pend, max_probe, full));
         // one LDS atomic per wave for the unique count
         for (int off = 32; off > 0; off >>= 1) nnew += (uint32_t)__shfl_xor((int)nnew, off);
         const bool anyfull = __ballot(full) != 0ull;

@@ -7,11 +7,10 @@
 //    set overflows move to the next size class.
 // 2. gather_kernel: a pure streaming pass over all (query, candidate) pairs:
 //    gather the row, compute the exact squared distance (the false-positive
-//    removal of Section 1.2), write one (distance, id) key per pair.  The pair
-//    list is cut into eight contiguous ranges, one per XCD (workgroup b runs on
-//    XCD b % 8); the pairs of a bucket group are adjacent, so their rows are
-//    shared through that XCD's L2.  No barriers: every wave keeps loads in
-//    flight all the time.
+//    removal of Section 1.2), write one (distance, id) key per pair.  XCD x
+//    (workgroup b runs on XCD b % 8) streams the region of the pair list that
+//    the dedup workgroups of XCD x filled.  No barriers: every wave keeps loads
+//    in flight all the time.
 // 3. select_kernel: one workgroup per query selects the K smallest keys of its
 //    contiguous pair range by (distance, id) (the c-k-ANN output, Section 3);
 //    for float data every key within the proven FP32 error band of the K-th is
@@ -23,7 +22,11 @@
 
 namespace qw {
 
-enum { D_ITEM = 0, D_UCOUNT, D_OVF, D_CPOS, D_T, D_CAP, D_OFF = 6 /* u64 */, D_NSCAL = 8 };
+enum {
+    D_UCOUNT = 0, D_OVF, D_CPOS, D_T, D_CAP, D_OFF = 6 /* u64 */,
+    D_WT = 8 /* per-wave counts, kBlock / 64 */, D_NSCAL = 16
+};
+constexpr int kRegIds = 16;  // ids per thread of the register-resident path
 
 __host__ __device__ inline size_t a16(size_t v) { return (v + 15) & ~size_t(15); }
 
@@ -33,32 +36,49 @@ size_t dedup_lds_bytes(int cap_log2, int global_tab, int L)
            a16(size_t(L) * 4) + D_NSCAL * 4;
 }
 
+// Exclusive prefix of the per-wave counts in scal[D_WT..]: the wave's base and
+// the workgroup total.  Call after the barrier that publishes the counts.
+__device__ inline uint32_t wave_base(const uint32_t *scal, int wave, uint32_t *total)
+{
+    uint32_t b = 0, t = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+        const uint32_t c = scal[D_WT + w];
+        b += w < wave ? c : 0u;
+        t += c;
+    }
+    *total = t;
+    return b;
+}
+
+// One workgroup per query (persistent: workgroup b takes items b, b + grid,
+// ... -- no shared work counter, whose atomics would serialise every
+// workgroup on one address).  Queries with at most kRegIds * kBlock
+// bucket entries in an LDS set keep their ids in registers from the load to
+// the write; larger ones (and the global-memory class, GLOB) go through the
+// set and read the unique ids back from it.
+template <bool GLOB>
 __global__ __launch_bounds__(kBlock) void dedup_kernel(DedupArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int tid = threadIdx.x, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const unsigned long long lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
-    const bool glob = A.global_tab != 0;
+    constexpr bool glob = GLOB;
     const size_t tab_bytes = glob ? 0 : (size_t(4) << A.cap_log2);
     uint32_t *lpref = reinterpret_cast<uint32_t *>(smem + tab_bytes);
     uint32_t *lstart = reinterpret_cast<uint32_t *>(smem + tab_bytes + a16(size_t(A.L + 1) * 4));
     uint32_t *scal = reinterpret_cast<uint32_t *>(smem + tab_bytes + a16(size_t(A.L + 1) * 4) +
                                                   a16(size_t(A.L) * 4));
-    uint32_t *tab = glob ? A.gscratch + (size_t)blockIdx.x * (size_t(1) << A.cap_log2)
+    uint32_t *tab = GLOB ? A.gscratch + (size_t)blockIdx.x * (size_t(1) << A.cap_log2)
                          : reinterpret_cast<uint32_t *>(smem);
+    unsigned long long *soff = reinterpret_cast<unsigned long long *>(&scal[D_OFF]);
     const int64_t sbeg = (int64_t)A.seg[0];
     const int64_t nseg = (int64_t)A.seg[1] - sbeg;
     const int64_t nin = A.in_count ? (int64_t)*A.in_count : 0;
     const int64_t nall = nseg + nin;
+    const int xcd = blockIdx.x % kXcd;
+    const unsigned long long rbase = (unsigned long long)xcd * A.region;
 
-    while (true) {
-        if (tid == 0) {
-            const int64_t it = (int64_t)atomicAdd(A.counter, 1u);
-            scal[D_ITEM] = it < nall ? (uint32_t)it : 0xFFFFFFFFu;
-        }
-        __syncthreads();
-        if (scal[D_ITEM] == 0xFFFFFFFFu) break;
-        const int64_t item = scal[D_ITEM];
+    for (int64_t item = blockIdx.x; item < nall; item += gridDim.x) {
         const int64_t q = item < nseg ? (int64_t)A.order[sbeg + item]
                                       : (int64_t)A.in_list[item - nseg];
         if (tid < A.L) {
@@ -71,89 +91,124 @@ __global__ __launch_bounds__(kBlock) void dedup_kernel(DedupArgs A)
             scal[D_CPOS] = 0;
         }
         __syncthreads();
-        if (tid == 0) {
-            uint32_t run = 0;
-            lpref[0] = 0;
-            for (int l = 0; l < A.L; ++l) {
-                run += lpref[l + 1];
-                lpref[l + 1] = run;
+        if (tid < 64) {
+            const uint32_t run = wave_layer_prefix(lpref, A.L);
+            if (tid == 0) {
+                scal[D_T] = run;
+                int c = (int)A.cap_log2;
+                if (glob) {  // set sized from the exact bound min(sum_l s_{q,l}, n)
+                    const uint64_t bound = min((uint64_t)run, (uint64_t)A.n);
+                    c = 10;
+                    while (c < (int)A.cap_log2 && (3ull << c) < 4 * bound) ++c;
+                }
+                scal[D_CAP] = (uint32_t)c;
             }
-            scal[D_T] = run;
-            int c = (int)A.cap_log2;
-            if (glob) {  // set sized from the exact bound min(sum_l s_{q,l}, n)
-                const uint64_t bound = min((uint64_t)run, (uint64_t)A.n);
-                c = 10;
-                while (c < (int)A.cap_log2 && (3ull << c) < 4 * bound) ++c;
-            }
-            scal[D_CAP] = (uint32_t)c;
         }
         __syncthreads();
+        const uint32_t T = scal[D_T];
         const int cap_log2 = (int)scal[D_CAP];
         const uint32_t cap = 1u << cap_log2;
         const uint32_t set_limit = (cap >> 2) * 3;
         const uint32_t limit = glob ? set_limit : (A.limit < set_limit ? A.limit : set_limit);
+        const uint32_t max_probe = glob ? 0xFFFFFFFFu : kShortProbe;
         for (uint32_t i = tid; i < cap; i += kBlock) tab[i] = kEmpty;
         if (glob) __threadfence();
         __syncthreads();
-        set_union(A.ids, A.n, A.L, lpref, lstart, scal[D_T], tab, cap_log2, limit, glob,
-                  glob ? 0xFFFFFFFFu : kShortProbe, false, &scal[D_UCOUNT], &scal[D_OVF],
-                  &scal[D_CPOS]);
-        const uint32_t U = scal[D_UCOUNT];
-        if (scal[D_OVF] || U > limit) {
+        const bool in_regs = !glob && T <= (uint32_t)(kRegIds * kBlock);
+        uint32_t idr[kRegIds];
+        uint32_t newm = 0;
+        uint32_t U = 0, wbase = 0;
+        bool ovf = false;
+        if (in_regs) {
+            const uint32_t pend = load_ids<kRegIds>(A.ids, A.n, A.L, lpref, lstart, T, 0u, idr);
+            bool full = false;
+            newm = insert_streams<kRegIds, 4>(tab, cap_log2, idr, pend, max_probe, full);
+            // this lane's position among the wave's new ids
+            uint32_t cnt = (uint32_t)__popc(newm), incl = cnt;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t t = (uint32_t)__shfl_up((int)incl, off);
+                if (lane >= off) incl += t;
+            }
+            wbase = incl - cnt;
+            if (lane == 63) scal[D_WT + wave] = incl;
+            if (__ballot(full) != 0ull && lane == 0) scal[D_OVF] = 1;
+            __syncthreads();
+            uint32_t tot = 0;
+            wbase += wave_base(scal, wave, &tot);
+            U = tot;
+            ovf = scal[D_OVF] != 0 || U > limit;
+        } else {
+            set_union(A.ids, A.n, A.L, lpref, lstart, T, tab, cap_log2, limit, glob, max_probe,
+                      false, &scal[D_UCOUNT], &scal[D_OVF], &scal[D_CPOS]);
+            U = scal[D_UCOUNT];
+            ovf = scal[D_OVF] != 0 || U > limit;
+        }
+        if (ovf) {
             if (tid == 0) {
                 const uint32_t o = atomicAdd(A.ovf_count, 1u);
                 A.ovf_list[o] = (int32_t)q;
             }
-            __syncthreads();
-            continue;
-        }
-        if (A.count_only) {
+        } else if (A.count_only) {
             if (tid == 0) A.ucount[q] = U;
-            __syncthreads();
-            continue;
-        }
-        unsigned long long *soff = reinterpret_cast<unsigned long long *>(&scal[D_OFF]);
-        if (tid == 0) {
-            unsigned long long off = atomicAdd(A.alloc, (unsigned long long)U);
-            if (off + U > A.cand_cap) {  // no list space: answered by the fallback
-                A.flag[q] = 1;
-                A.ucount[q] = 0;
-                off = ~0ull;
-            } else {
-                A.ucount[q] = U;
-                A.coff[q] = off;
-                atomicMax(A.valid_end, off + U);
-                if (A.unique_total) atomicAdd(A.unique_total, (unsigned long long)U);
+        } else {
+            if (tid == 0) {
+                unsigned long long off = atomicAdd(A.alloc + xcd, (unsigned long long)U);
+                if (off + U > A.region) {  // no list space: answered by the fallback
+                    atomicMax(A.fail + xcd, ~off);
+                    A.flag[q] = 1;
+                    A.ucount[q] = 0;
+                    off = ~0ull;
+                } else {
+                    off += rbase;
+                    A.ucount[q] = U;
+                    A.coff[q] = off;
+                }
+                *soff = off;
             }
-            *soff = off;
-        }
-        __syncthreads();
-        const unsigned long long off = *soff;
-        if (off != ~0ull) {
-            // scatter the set's ids straight from the hashed layout: a wave
-            // reserves its run of positions with one LDS atomic per round
-            for (uint32_t base = 0; base < cap; base += kBlock) {
-                const uint32_t v = tab[base + tid];
-                const bool occ = v != kEmpty;
-                const unsigned long long m = __ballot(occ);
-                uint32_t wb = 0;
-                if (lane == 0 && m) wb = atomicAdd(&scal[D_CPOS], (uint32_t)__popcll(m));
-                wb = (uint32_t)__shfl((int)wb, 0);
-                if (occ) {
-                    const unsigned long long e = off + wb + (uint32_t)__popcll(m & lt_mask);
-                    A.cand[e] = (int32_t)v;
-                    A.candq[e] = (int32_t)q;
+            __syncthreads();
+            const unsigned long long off = *soff;
+            if (off != ~0ull && in_regs) {
+                unsigned long long e = off + wbase;
+#pragma unroll
+                for (int r = 0; r < kRegIds; ++r)
+                    if ((newm >> r) & 1u) {
+                        A.cand[e] = (int32_t)idr[r];
+                        A.candq[e] = (int32_t)q;
+                        ++e;
+                    }
+            } else if (off != ~0ull) {
+                // read the set back: wave w takes slots [w * cap / 4, (w + 1) * cap / 4)
+                const uint32_t seg = cap / (kBlock / 64);
+                const uint32_t s0 = (uint32_t)wave * seg;
+                uint32_t cnt = 0;
+                for (uint32_t i = s0 + lane; i < s0 + seg; i += 64)
+                    cnt += (uint32_t)__popcll(__ballot(tab[i] != kEmpty));
+                if (lane == 0) scal[D_WT + wave] = cnt;
+                __syncthreads();
+                uint32_t tot = 0;
+                unsigned long long e = off + wave_base(scal, wave, &tot);
+                for (uint32_t i = s0 + lane; i < s0 + seg; i += 64) {
+                    const uint32_t v = tab[i];
+                    const unsigned long long m = __ballot(v != kEmpty);
+                    if (v != kEmpty) {
+                        const unsigned long long p = e + (uint32_t)__popcll(m & lt_mask);
+                        A.cand[p] = (int32_t)v;
+                        A.candq[p] = (int32_t)q;
+                    }
+                    e += (uint32_t)__popcll(m);
                 }
             }
         }
-        __syncthreads();
+        __syncthreads();  // scal is rewritten by the next item
     }
 }
 
 qw_status launch_dedup(const DedupArgs &a, int grid, hipStream_t s)
 {
     if (grid <= 0) return QW_OK;
-    dedup_kernel<<<grid, kBlock, dedup_lds_bytes((int)a.cap_log2, a.global_tab, a.L), s>>>(a);
+    const size_t lds = dedup_lds_bytes((int)a.cap_log2, a.global_tab, a.L);
+    if (a.global_tab) dedup_kernel<true><<<grid, kBlock, lds, s>>>(a);
+    else dedup_kernel<false><<<grid, kBlock, lds, s>>>(a);
     QW_HIP(hipGetLastError());
     return QW_OK;
 }
@@ -161,7 +216,7 @@ qw_status launch_dedup(const DedupArgs &a, int grid, hipStream_t s)
 int dedup_blocks_per_cu(size_t lds)
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)dedup_kernel, kBlock, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void *)dedup_kernel<false>, kBlock, lds) !=
         hipSuccess) {
         (void)hipGetLastError();
         nb = 1;
@@ -187,12 +242,16 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(GatherArgs A)
     const int NG = kBlock / G;
     const int PI = NG * UN;  // pairs per workgroup iteration
     const int grp = tid / G, j = tid % G;
-    const unsigned long long N = *A.npairs;
-    // XCD-local contiguous range
-    const int x = blockIdx.x & 7;
-    const int64_t nwg = ((int64_t)gridDim.x - x + 7) / 8;
-    const int64_t r = blockIdx.x >> 3;
-    const int64_t rb = (int64_t)(N * x / 8), re = (int64_t)(N * (x + 1) / 8);
+    // the XCD's own region of the pair list (filled by the dedup workgroups of
+    // the same XCD)
+    const int x = blockIdx.x % kXcd;
+    const int64_t nwg = ((int64_t)gridDim.x - x + kXcd - 1) / kXcd;
+    const int64_t r = blockIdx.x / kXcd;
+    unsigned long long used = A.alloc[x];
+    const unsigned long long f = A.fail[x];
+    if (f && ~f < used) used = ~f;
+    const int64_t rb = (int64_t)((unsigned long long)x * A.region);
+    const int64_t re = rb + (int64_t)(used < A.region ? used : A.region);
     for (int64_t base = rb + r * PI; base < re; base += nwg * PI) {
         uint32_t cid[UN], cq[UN];
         bool cv[UN];
@@ -309,31 +368,6 @@ qw_status launch_gather(const GatherArgs &a, int grid, hipStream_t s)
 
 // ---------------------------------------------------------------- select
 
-// Bitonic sort of keys[0..n) ascending (the tail up to the next power of two
-// is padded with ~0; that power of two must fit the buffer).  Whole workgroup.
-__device__ inline void sort_keys(unsigned long long *keys, int n)
-{
-    int ns = 2;
-    while (ns < n) ns <<= 1;
-    for (int e = n + threadIdx.x; e < ns; e += kBlock) keys[e] = ~0ull;
-    __syncthreads();
-    for (int size = 2; size <= ns; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = threadIdx.x; i < ns / 2; i += kBlock) {
-                const int lo = 2 * i - (i & (stride - 1));
-                const int hi = lo + stride;
-                const bool asc = (lo & size) == 0;
-                const unsigned long long a = keys[lo], b = keys[hi];
-                if ((b < a) == asc) {
-                    keys[lo] = b;
-                    keys[hi] = a;
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
-
 // Band threshold F_K * (1 + eps) / (1 - eps), rounded up to float: every key
 // of the exact top-K has an FP32 distance at most this (see the verify kernel).
 __device__ inline float band_threshold(float FK, float eps)
@@ -360,25 +394,50 @@ __device__ __noinline__ double exact_dist_f32_s(const float *__restrict__ x,
     return acc;
 }
 
-// One workgroup per query.  Keys stream through a threshold: a key enters the
-// LDS list only if it is at most the current K-th key (uint8: keys are unique
-// (distance, id) pairs, so exactly K survive) or within the band of the K-th
-// distance (float); when the list passes half its capacity it is sorted and cut
-// back to the K best plus the band.
+// Ascending bitonic sort of one value per lane across a wave.
+__device__ inline unsigned long long wave_sort_u64(unsigned long long v)
+{
+    const int lane = threadIdx.x & 63;
+    for (int k = 2; k <= 64; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const unsigned long long o = __shfl_xor(v, j);
+            const bool asc = (lane & k) == 0, lower = (lane & j) == 0;
+            v = (lower == asc) ? (o < v ? o : v) : (o > v ? o : v);
+        }
+    return v;
+}
+
+// One workgroup per query, over its U keys (unique (distance, id) pairs):
+// 1. every lane takes the minimum of its stride-kBlock stream of keys (K > 64:
+//    V = ceil(K / kBlock) streams per thread);
+// 2. a key t with at least K keys at or below it bounds the K-th key: the K-th
+//    smallest minimum of any set of streams is one (K <= 64: per wave, from a
+//    shuffle sort of its 64 minima, the smallest over the waves; else the K-th
+//    of all minima by rank counting).  Float data widen the bound to the FP32
+//    error band of its distance;
+// 3. a second pass collects the keys at or below the bound into an LDS list
+//    (typically a few K entries);
+// 4. uint8: each list entry's rank is counted, ranks below K are the output.
+//    float: the K-th key of the list fixes the band, every entry in the band is
+//    re-ranked by its FP64 index-order distance (the c-k-ANN output, Section 3).
+// A list or band beyond capacity sends the query to the fallback.
 template <int DT>
 __global__ __launch_bounds__(kBlock) void select_kernel(SelectArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned long long *lst = reinterpret_cast<unsigned long long *>(smem);
     RankF *rk = reinterpret_cast<RankF *>(smem + size_t(A.LC) * 8);
-    __shared__ unsigned long long s_thr;
-    __shared__ uint32_t s_cnt, s_bad;
+    unsigned long long *s_min = lst;  // the minima (K > 64) are dead before the list fills
+    __shared__ unsigned long long s_thr, s_kth;
+    __shared__ uint32_t s_cnt, s_nb, s_bad;
     const int64_t q = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63;
     const unsigned long long lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     if (tid == 0) {
         s_cnt = 0;
+        s_nb = 0;
         s_thr = ~0ull;
+        s_kth = ~0ull;
         s_bad = A.flag[q];
     }
     __syncthreads();
@@ -387,108 +446,149 @@ __global__ __launch_bounds__(kBlock) void select_kernel(SelectArgs A)
         return;
     }
     const uint32_t U = A.ucount[q];
+    const int K = A.K;
     const unsigned long long *keys = A.keys + (U ? A.coff[q] : 0ull);
-    // trim: sort the list, keep the K best (uint8) or every key within the band
-    // of the K-th (float); the threshold tightens accordingly
-    auto trim = [&]() {
-        const int n = (int)s_cnt;
-        sort_keys(lst, n);
-        if (tid == 0 && n >= A.K) {
-            const unsigned long long kk = lst[A.K - 1];
-            unsigned long long thr = kk;
-            int keep = A.K;
-            if (DT != QW_U8) {
-                const float bt = band_threshold(__uint_as_float((uint32_t)(kk >> 32)), A.eps);
-                thr = ((unsigned long long)__float_as_uint(bt) << 32) | 0xFFFFFFFFull;
-                while (keep < n && lst[keep] <= thr) ++keep;
+    // ---- 1-2: bound on the K-th key
+    if (U > (uint32_t)K) {
+        const int V = (K + kBlock - 1) / kBlock;
+        unsigned long long thr = ~0ull;
+        if (K <= 64) {
+            unsigned long long m = ~0ull;
+            uint32_t e = tid;
+            for (; e + 3 * kBlock < U; e += 4 * kBlock) {
+                const unsigned long long k0 = keys[e], k1 = keys[e + kBlock];
+                const unsigned long long k2 = keys[e + 2 * kBlock], k3 = keys[e + 3 * kBlock];
+                const unsigned long long a = k0 < k1 ? k0 : k1, b = k2 < k3 ? k2 : k3;
+                const unsigned long long c = a < b ? a : b;
+                m = c < m ? c : m;
             }
-            s_cnt = (uint32_t)keep;
-            s_thr = thr;
-            if (keep > A.LC / 2) s_bad = 1;  // band too wide for the list
+            for (; e < U; e += kBlock) m = keys[e] < m ? keys[e] : m;
+            // the K-th smallest of this wave's minima; ~0 unless K streams are non-empty
+            const unsigned long long t = __shfl(wave_sort_u64(m), K - 1);
+            if (lane == 0 && t != ~0ull) atomicMin(&s_thr, t);
+        } else {
+            for (int v = 0; v < V; ++v) {
+                unsigned long long m = ~0ull;
+                for (uint32_t e = (uint32_t)(v * kBlock + tid); e < U; e += (uint32_t)(V * kBlock))
+                    m = keys[e] < m ? keys[e] : m;
+                s_min[v * kBlock + tid] = m;
+            }
+            __syncthreads();
+            const int M = V * kBlock;
+            for (int v = 0; v < V; ++v) {
+                const unsigned long long m = s_min[v * kBlock + tid];
+                if (m == ~0ull) continue;
+                int rank = 0;
+                for (int i = 0; i < M; ++i) rank += s_min[i] < m;
+                if (rank == K - 1) s_thr = m;  // keys are unique: one writer
+            }
         }
         __syncthreads();
-    };
-    for (uint32_t b0 = 0; b0 < U; b0 += 4 * kBlock) {
+        thr = s_thr;
+        if (DT != QW_U8 && thr != ~0ull) {
+            const float bt = band_threshold(__uint_as_float((uint32_t)(thr >> 32)), A.eps);
+            thr = ((unsigned long long)__float_as_uint(bt) << 32) | 0xFFFFFFFFull;
+        }
+        __syncthreads();  // every thread has read s_thr
+        if (tid == 0) s_thr = thr;
+        __syncthreads();
+    }
+    // ---- 3: collect the keys at or below the bound
+    {
         const unsigned long long thr = s_thr;
-        for (int i = 0; i < 4; ++i) {
-            const uint32_t e = b0 + (uint32_t)(i * kBlock + tid);
+        for (uint32_t b0 = 0; b0 < U; b0 += kBlock) {
+            const uint32_t e = b0 + tid;
             const unsigned long long k = e < U ? keys[e] : ~0ull;
             const bool take = e < U && k <= thr;
             const unsigned long long m = __ballot(take);
             uint32_t wb = 0;
             if (lane == 0 && m) wb = atomicAdd(&s_cnt, (uint32_t)__popcll(m));
             wb = (uint32_t)__shfl((int)wb, 0);
-            if (take) lst[wb + (uint32_t)__popcll(m & lt_mask)] = k;
+            const uint32_t pos = wb + (uint32_t)__popcll(m & lt_mask);
+            if (take && pos < (uint32_t)A.LC) lst[pos] = k;
         }
-        __syncthreads();
-        const bool full = (int)s_cnt > A.LC / 2;
-        __syncthreads();  // every thread has read s_cnt before the next pass adds to it
-        if (full) trim();
-        if (s_bad) break;  // set only inside trim, before its barrier
     }
-    if (!s_bad) trim();
-    if (s_bad) {
+    __syncthreads();
+    const int c = (int)s_cnt;
+    if (c > A.LC) {  // list beyond capacity
         if (tid == 0) A.fb_list[atomicAdd(A.fb_count, 1u)] = (int32_t)q;
         return;
     }
-    const int n = (int)s_cnt;
+    // ---- 4: ranks within the list (keys are unique)
     if (DT == QW_U8) {
-        for (int r = tid; r < A.K; r += kBlock) {
-            const int64_t o = q * A.K + r;
-            if (r < n) {
-                A.out_ids[o] = (int32_t)(uint32_t)lst[r];
-                reinterpret_cast<int32_t *>(A.out_dist)[o] = (int32_t)(lst[r] >> 32);
-            } else {
-                A.out_ids[o] = -1;
-                reinterpret_cast<int32_t *>(A.out_dist)[o] = INT32_MAX;
+        for (int i = tid; i < c; i += kBlock) {
+            const unsigned long long k = lst[i];
+            int r = 0;
+            for (int j = 0; j < c; ++j) r += lst[j] < k;
+            if (r < K) {
+                const int64_t o = q * K + r;
+                A.out_ids[o] = (int32_t)(uint32_t)k;
+                reinterpret_cast<int32_t *>(A.out_dist)[o] = (int32_t)(k >> 32);
             }
+        }
+        for (int r = c + tid; r < K; r += kBlock) {
+            const int64_t o = q * K + r;
+            A.out_ids[o] = -1;
+            reinterpret_cast<int32_t *>(A.out_dist)[o] = INT32_MAX;
         }
         return;
     }
-    // float data: FP64 index-order distances of every key in the band, then
-    // the exact (D, id) order
-    const float *qrow = (const float *)A.queries + q * (int64_t)A.dp;
-    for (int e = tid; e < n; e += kBlock) {
-        const uint32_t id = (uint32_t)lst[e];
-        rk[e].D = exact_dist_f32_s((const float *)A.data + (int64_t)id * A.dp, qrow, A.d);
-        rk[e].id = id;
+    // float data: the list's K-th key fixes the band of the exact top K
+    if (c >= K)
+        for (int i = tid; i < c; i += kBlock) {
+            const unsigned long long k = lst[i];
+            int r = 0;
+            for (int j = 0; j < c; ++j) r += lst[j] < k;
+            if (r == K - 1) s_kth = k;
+        }
+    __syncthreads();
+    unsigned long long bthr = ~0ull;
+    if (c >= K) {
+        const float bt = band_threshold(__uint_as_float((uint32_t)(s_kth >> 32)), A.eps);
+        bthr = ((unsigned long long)__float_as_uint(bt) << 32) | 0xFFFFFFFFull;
     }
-    int ns = 2;
-    while (ns < n) ns <<= 1;
-    for (int e = n + tid; e < ns; e += kBlock) {
-        rk[e].D = INFINITY;
-        rk[e].id = 0xFFFFFFFFu;
+    const int cap_b = A.LC / 2;
+    for (int b0 = 0; b0 < c; b0 += kBlock) {
+        const int i = b0 + tid;
+        const bool take = i < c && lst[i] <= bthr;
+        const unsigned long long m = __ballot(take);
+        uint32_t wb = 0;
+        if (lane == 0 && m) wb = atomicAdd(&s_nb, (uint32_t)__popcll(m));
+        wb = (uint32_t)__shfl((int)wb, 0);
+        const uint32_t pos = wb + (uint32_t)__popcll(m & lt_mask);
+        if (take && pos < (uint32_t)cap_b) rk[pos].id = (uint32_t)lst[i];
     }
     __syncthreads();
-    for (int size = 2; size <= ns; size <<= 1)
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = tid; i < ns / 2; i += kBlock) {
-                const int lo = 2 * i - (i & (stride - 1));
-                const int hi = lo + stride;
-                const bool asc = (lo & size) == 0;
-                const RankF a = rk[lo], b = rk[hi];
-                const bool less = b.D < a.D || (b.D == a.D && b.id < a.id);
-                if (less == asc) {
-                    rk[lo] = b;
-                    rk[hi] = a;
-                }
-            }
-            __syncthreads();
+    const int nb = (int)s_nb;
+    if (nb > cap_b) {  // band beyond capacity
+        if (tid == 0) A.fb_list[atomicAdd(A.fb_count, 1u)] = (int32_t)q;
+        return;
+    }
+    const float *qrow = (const float *)A.queries + q * (int64_t)A.dp;
+    for (int i = tid; i < nb; i += kBlock)
+        rk[i].D = exact_dist_f32_s((const float *)A.data + (int64_t)rk[i].id * A.dp, qrow, A.d);
+    __syncthreads();
+    for (int i = tid; i < nb; i += kBlock) {
+        const double D = rk[i].D;
+        const uint32_t id = rk[i].id;
+        int r = 0;
+        for (int j = 0; j < nb; ++j) r += rk[j].D < D || (rk[j].D == D && rk[j].id < id);
+        if (r < K) {
+            const int64_t o = q * K + r;
+            A.out_ids[o] = (int32_t)id;
+            reinterpret_cast<float *>(A.out_dist)[o] = (float)D;
         }
-    for (int r = tid; r < A.K; r += kBlock) {
-        const int64_t o = q * A.K + r;
-        if (r < n) {
-            A.out_ids[o] = (int32_t)rk[r].id;
-            reinterpret_cast<float *>(A.out_dist)[o] = (float)rk[r].D;
-        } else {
-            A.out_ids[o] = -1;
-            reinterpret_cast<float *>(A.out_dist)[o] = INFINITY;
-        }
+    }
+    for (int r = nb + tid; r < K; r += kBlock) {
+        const int64_t o = q * K + r;
+        A.out_ids[o] = -1;
+        reinterpret_cast<float *>(A.out_dist)[o] = INFINITY;
     }
 }
 
-// The key list holds LC entries; the FP64 re-rank of float data needs LC/2
-// (a band wider than that goes to the fallback).
+// The key list holds LC >= 4K entries (also room for the ceil(K / kBlock) *
+// kBlock minima of K > 64); the FP64 re-rank of float data needs LC/2 (a band
+// wider than that goes to the fallback).
 size_t select_lds_bytes(int LC, int dtype)
 {
     return size_t(LC) * 8 + (dtype == QW_F32 ? size_t(LC / 2) * sizeof(RankF) : 0);

@@ -13,6 +13,7 @@
 
 namespace qw {
 
+constexpr int kXcd = 8;                   // XCDs: workgroup b runs on XCD b % 8
 constexpr int kBlock = 256;              // threads per workgroup for every kernel here
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // empty hash-set slot
 constexpr int kMaxL = 64;
@@ -72,8 +73,8 @@ struct Workspace {
 struct Plan {
     int buf = 64;
     int cmax = 10;      // largest LDS class (log2 capacity)
+    int cfloor = 10;    // smallest class worth choosing (no occupancy gain below)
     int ncls = 2;       // LDS classes + 1 global class
-    int grid[16] = {};  // fused verify kernel, per class
     int dgrid[16] = {}; // dedup kernel, per class
     int cap_g = 20, grid_g = 1;
     int LC = 2048;      // select kernel list capacity (entries)
@@ -119,6 +120,7 @@ struct qw_index {
     int64_t buckets = 0, max_bucket = 0;
     // count model
     std::vector<float> mlp;  // packed host copy (empty = none)
+    float mlp_margin = 0.22314355f;  // log-space sizing margin, log(1.25) until calibrated
     qw::DevBuf mlp_dev;
     // query workspace and captured graphs
     qw::Workspace ws;
@@ -193,7 +195,7 @@ struct VerifyArgs {
     void *out_dist;              // TOPK
     int32_t *out_counts;         // COUNT
     const long long *offsets;    // LIST
-    unsigned long long *unique_total;  // nullable stats counter
+    uint32_t *ucount_out;        // nullable: |C(q)| of each answered query
 };
 
 size_t verify_lds_bytes(int cap_log2, int buf, int global_tab, int L, int dp, int dtype);
@@ -207,7 +209,8 @@ int verify_blocks_per_cu(int dp, int dtype, size_t lds);
 qw_status launch_classify(int64_t Q, int32_t L, int64_t n, const uint32_t *qsum,
                           const uint32_t *bstart, const uint32_t *bsize, const int32_t *exact,
                           const float *pred_log, float margin, int32_t force_max, int32_t cmin,
-                          int32_t cmax, int32_t ncls, int32_t group, unsigned long long *keys,
+                          int32_t cfloor, int32_t cmax, int32_t ncls, int32_t group,
+                          unsigned long long *keys,
                           int32_t *vals, unsigned long long *class_count, hipStream_t s);
 qw_status launch_segments(const unsigned long long *class_count, int32_t ncls,
                           unsigned long long *seg, hipStream_t s);
@@ -227,7 +230,6 @@ qw_status build_index(const void *data, int64_t n, int32_t d, int32_t dtype, con
 struct DedupArgs {
     const int32_t *order;            // scheduled query order
     const unsigned long long *seg;   // {begin, end} of this class in the order
-    uint32_t *counter;               // persistent work counter
     const uint32_t *in_count;        // nullable: queue of overflowed queries served after the segment
     const int32_t *in_list;
     uint32_t *ovf_count;             // queue receiving this class's overflows
@@ -240,19 +242,24 @@ struct DedupArgs {
     int32_t global_tab;
     uint32_t *gscratch;              // 2^cap_log2 words per workgroup (global_tab)
     int32_t count_only;              // write |C(q)| only
-    unsigned long long *alloc;       // bump allocator over cand
-    unsigned long long cand_cap;
+    // the pair list is cut into kXcd regions of `region` pairs; region x is
+    // filled by the workgroups of XCD x (blockIdx % kXcd) through its own
+    // bump allocator alloc[x]; fail[x] keeps the complement of the lowest
+    // offset refused there (0 = none), so region x holds the granted lists
+    // in [x * region, x * region + min(alloc[x], ~fail[x]))
+    unsigned long long *alloc;       // [kXcd]
+    unsigned long long *fail;        // [kXcd]
+    unsigned long long region;
     int32_t *cand;                   // unique candidate lists (pair -> id)
     int32_t *candq;                  // pair -> query
-    unsigned long long *valid_end;   // end of the last granted list
     uint32_t *ucount;                // |C(q)|
     unsigned long long *coff;        // offset of each query's list in cand
     uint32_t *flag;                  // 1 = answer q with the fallback
-    unsigned long long *unique_total;
 };
 
 struct GatherArgs {
-    const unsigned long long *npairs;  // device: number of valid pairs
+    const unsigned long long *alloc, *fail;  // per-XCD region fill (see DedupArgs)
+    unsigned long long region;
     const int32_t *cand, *candq;       // pair -> candidate id, query
     const void *data, *queries;
     int32_t dp, dtype;

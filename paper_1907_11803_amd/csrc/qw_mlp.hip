@@ -42,39 +42,35 @@ __device__ inline float bf16_round(float x)
     return __uint_as_float(u & 0xFFFF0000u);
 }
 
-// One thread per query; the H hidden pre-activations live in registers (static
-// indices) while the L inputs stream in.
+// One wave per query (H = 64 = the wave width): lane h computes hidden unit h
+// from W1 held transposed in LDS (consecutive lanes read consecutive words),
+// and a wave reduction sums W2 . relu(z + b1).  Waves loop over queries.
 __global__ __launch_bounds__(kBlock) void mlp_predict_bf16_kernel(const float *__restrict__ params,
                                                                   int32_t L,
                                                                   const float *__restrict__ feats,
                                                                   int64_t B, float *__restrict__ out)
 {
-    extern __shared__ float sw[];  // W1 bf16 [H][L], b1 [H], W2 bf16 [H], b2
+    static_assert(H == 64, "one hidden unit per lane");
+    extern __shared__ float sw[];  // W1^T bf16 [L][H], b1 [H], W2 bf16 [H], b2
     const int P = H * L + 2 * H + 1;
     for (int i = threadIdx.x; i < P; i += kBlock) {
-        const bool is_bias = (i >= H * L && i < H * L + H) || i == P - 1;
-        sw[i] = is_bias ? params[i] : bf16_round(params[i]);
+        const float v = params[i];
+        if (i < H * L) sw[(i % L) * H + i / L] = bf16_round(v);  // W1[h][l] -> W1^T[l][h]
+        else if (i < H * L + H || i == P - 1) sw[i] = v;         // biases stay FP32
+        else sw[i] = bf16_round(v);                               // W2
     }
     __syncthreads();
-    const float *W1 = sw, *b1 = sw + H * L, *W2 = sw + H * L + H;
+    const float *W1t = sw, *b1 = sw + H * L, *W2 = sw + H * L + H;
     const float b2 = sw[P - 1];
-    for (int64_t q = blockIdx.x * (int64_t)kBlock + threadIdx.x; q < B;
-         q += (int64_t)gridDim.x * kBlock) {
-        float z[H];
-#pragma unroll
-        for (int h = 0; h < H; ++h) z[h] = 0.f;
-        for (int l = 0; l < L; ++l) {
-            const float f = bf16_round(feats[q * L + l]);
-#pragma unroll
-            for (int h = 0; h < H; ++h) z[h] = fmaf(W1[h * L + l], f, z[h]);
-        }
-        float y = 0.f;
-#pragma unroll
-        for (int h = 0; h < H; ++h) {
-            const float zz = z[h] + b1[h];
-            y = fmaf(W2[h], bf16_round(zz > 0.f ? zz : 0.f), y);
-        }
-        out[q] = y + b2;
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t q = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); q < B; q += nwaves) {
+        float z = 0.f;
+        for (int l = 0; l < L; ++l) z = fmaf(W1t[l * H + lane], bf16_round(feats[q * L + l]), z);
+        const float zz = z + b1[lane];
+        float y = W2[lane] * bf16_round(zz > 0.f ? zz : 0.f);
+        for (int off = 32; off > 0; off >>= 1) y += __shfl_xor(y, off);
+        if (lane == 0) out[q] = y + b2;
     }
 }
 
@@ -83,7 +79,7 @@ qw_status launch_mlp_predict_bf16(const float *params, int32_t L, const float *f
 {
     if (B <= 0) return QW_OK;
     const size_t lds = sizeof(float) * (H * L + 2 * H + 1);
-    int g = (int)std::min<int64_t>(4096, ceil_div(B, kBlock));
+    const int g = (int)std::min<int64_t>(2048, ceil_div(B, kBlock / 64));
     mlp_predict_bf16_kernel<<<g, kBlock, lds, s>>>(params, L, feats, B, out);
     QW_HIP(hipGetLastError());
     return QW_OK;

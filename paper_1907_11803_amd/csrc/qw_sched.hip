@@ -28,7 +28,7 @@ __global__ __launch_bounds__(kBlock) void classify_kernel(
     int64_t Q, int32_t L, int64_t n, const uint32_t *__restrict__ qsum,
     const uint32_t *__restrict__ bstart, const uint32_t *__restrict__ bsize,
     const int32_t *__restrict__ exact, const float *__restrict__ pred_log, float margin,
-    int32_t force_max, int32_t cmin, int32_t cmax, int32_t ncls, int32_t group,
+    int32_t force_max, int32_t cmin, int32_t cfloor, int32_t cmax, int32_t ncls, int32_t group,
     unsigned long long *__restrict__ keys, int32_t *__restrict__ vals,
     unsigned long long *class_count)
 {
@@ -37,16 +37,22 @@ __global__ __launch_bounds__(kBlock) void classify_kernel(
     __syncthreads();
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < Q;
          q += (int64_t)gridDim.x * blockDim.x) {
+        // |C(q)| <= min(sum of the bucket sizes, n): the class of that bound
+        // always holds the set; a predicted or exact count may pick a smaller
+        // one, but never one below cfloor (no occupancy gained there)
         const uint64_t bound = min((uint64_t)qsum[q], (uint64_t)n);
         uint64_t need = bound;
         if (exact) {
             need = min(need, (uint64_t)exact[q]);
         } else if (pred_log) {
-            const float p = expm1f(pred_log[q]) * margin + 32.f;
+            const float p = expm1f(pred_log[q] + margin) + 32.f;
             if (p == p && p < (float)need) need = p > 0.f ? (uint64_t)ceilf(p) : 0;
         }
+        int cb = cmin;
+        while (cb < 40 && (3ull << cb) < 4 * bound) ++cb;
         int c = cmin;
         while (c < 40 && (3ull << c) < 4 * need) ++c;
+        c = max(c, min(cb, cfloor));
         if (force_max && c <= cmax) c = cmax;
         const int cls = c <= cmax ? c - cmin : ncls - 1;
         uint32_t g = 0;
@@ -70,13 +76,14 @@ __global__ __launch_bounds__(kBlock) void classify_kernel(
 qw_status launch_classify(int64_t Q, int32_t L, int64_t n, const uint32_t *qsum,
                           const uint32_t *bstart, const uint32_t *bsize, const int32_t *exact,
                           const float *pred_log, float margin, int32_t force_max, int32_t cmin,
-                          int32_t cmax, int32_t ncls, int32_t group, unsigned long long *keys,
-                          int32_t *vals, unsigned long long *class_count, hipStream_t s)
+                          int32_t cfloor, int32_t cmax, int32_t ncls, int32_t group,
+                          unsigned long long *keys, int32_t *vals,
+                          unsigned long long *class_count, hipStream_t s)
 {
     if (Q <= 0) return QW_OK;
     int g = (int)std::min<int64_t>(1024, ceil_div(Q, kBlock));
     classify_kernel<<<g, kBlock, 0, s>>>(Q, L, n, qsum, bstart, bsize, exact, pred_log, margin,
-                                         force_max, cmin, cmax, ncls, group, keys, vals,
+                                         force_max, cmin, cfloor, cmax, ncls, group, keys, vals,
                                          class_count);
     QW_HIP(hipGetLastError());
     return QW_OK;
@@ -123,32 +130,45 @@ qw_status launch_max_u32(const uint32_t *v, int64_t count, uint32_t *out, hipStr
 }
 
 // probes that hit a bucket, and the total of the bucket sizes
-__global__ void probe_stats_kernel(const uint32_t *__restrict__ bsize, int64_t count,
-                                   unsigned long long *hits, unsigned long long *total)
+// Count of non-zero entries and their sum (one atomic pair per workgroup).
+__global__ __launch_bounds__(kBlock) void probe_stats_kernel(const uint32_t *__restrict__ v,
+                                                             int64_t count,
+                                                             unsigned long long *nonzero,
+                                                             unsigned long long *total)
 {
+    __shared__ unsigned long long sh[kBlock / 64], st[kBlock / 64];
     unsigned long long h = 0, t = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t v = bsize[i];
-        h += v ? 1 : 0;
-        t += v;
+        const uint32_t x = v[i];
+        h += x ? 1 : 0;
+        t += x;
     }
     for (int off = 32; off > 0; off >>= 1) {
         h += __shfl_xor(h, off);
         t += __shfl_xor(t, off);
     }
     if ((threadIdx.x & 63) == 0) {
-        atomicAdd(hits, h);
+        sh[threadIdx.x >> 6] = h;
+        st[threadIdx.x >> 6] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) {
+            h += sh[w];
+            t += st[w];
+        }
+        atomicAdd(nonzero, h);
         atomicAdd(total, t);
     }
 }
 
-qw_status launch_probe_stats(const uint32_t *bsize, int64_t count, unsigned long long *hits,
+qw_status launch_probe_stats(const uint32_t *v, int64_t count, unsigned long long *nonzero,
                              unsigned long long *total, hipStream_t s)
 {
     if (count <= 0) return QW_OK;
-    int g = (int)std::min<int64_t>(1024, ceil_div(count, kBlock));
-    probe_stats_kernel<<<g, kBlock, 0, s>>>(bsize, count, hits, total);
+    int g = (int)std::min<int64_t>(64, ceil_div(count, kBlock));
+    probe_stats_kernel<<<g, kBlock, 0, s>>>(v, count, nonzero, total);
     QW_HIP(hipGetLastError());
     return QW_OK;
 }

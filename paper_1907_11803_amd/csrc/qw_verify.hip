@@ -150,20 +150,22 @@ __device__ void topk_compact(typename TopT<DT>::type *buf, uint32_t *scal, int n
     __syncthreads();
 }
 
-template <int DT, int UN, int PM>
+// GLOB: the hash sets live in global scratch (one per workgroup) instead of
+// LDS; a compile-time choice so that LDS sets compile to LDS instructions.
+template <int DT, int UN, int PM, bool GLOB>
 __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
 {
     using E = typename TopT<DT>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x, lane = tid & 63;
-    const int glob = A.global_tab;
+    constexpr int glob = GLOB ? 1 : 0;
     const LdsLayout lay = lds_layout((int)A.cap_log2, (int)A.buf, glob, A.L, A.dp, A.dtype);
     E *buf = reinterpret_cast<E *>(smem + lay.buf);
     uint32_t *lpref = reinterpret_cast<uint32_t *>(smem + lay.lpref);
     uint32_t *lstart = reinterpret_cast<uint32_t *>(smem + lay.lstart);
     uint32_t *scal = reinterpret_cast<uint32_t *>(smem + lay.scal);
     const size_t gcap = size_t(1) << A.cap_log2;
-    uint32_t *tab = glob ? A.gscratch + (size_t)blockIdx.x * gcap
+    uint32_t *tab = GLOB ? A.gscratch + (size_t)blockIdx.x * gcap
                          : reinterpret_cast<uint32_t *>(smem + lay.tab);
 
     const int elem = DT == QW_U8 ? 1 : 4;
@@ -242,20 +244,18 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
             __syncthreads();
             if (DT == QW_U8 && qq) atomicAdd(&scal[S_QQ], qq);
         }
-        if (tid == 0) {
-            uint32_t run = 0;
-            for (int l = 0; l < A.L; ++l) {
-                run += lpref[l + 1];
-                lpref[l + 1] = run;
+        if (tid < 64) {
+            const uint32_t run = wave_layer_prefix(lpref, A.L);
+            if (tid == 0) {
+                scal[S_T] = run;
+                int c = (int)A.cap_log2;
+                if (glob) {  // set sized from the exact bound min(sum_l s_{q,l}, n)
+                    const uint64_t bound = min((uint64_t)run, (uint64_t)A.n);
+                    c = 10;
+                    while (c < (int)A.cap_log2 && (3ull << c) < 4 * bound) ++c;
+                }
+                scal[S_CAP] = (uint32_t)c;
             }
-            scal[S_T] = run;
-            int c = (int)A.cap_log2;
-            if (glob) {  // set sized from the exact bound min(sum_l s_{q,l}, n)
-                const uint64_t bound = min((uint64_t)run, (uint64_t)A.n);
-                c = 10;
-                while (c < (int)A.cap_log2 && (3ull << c) < 4 * bound) ++c;
-            }
-            scal[S_CAP] = (uint32_t)c;
         }
         __syncthreads();
         const int cap_log2 = (int)scal[S_CAP];
@@ -282,8 +282,7 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
             __syncthreads();
             continue;
         }
-        if (tid == 0 && A.unique_total && A.mode != VM_ALL)
-            atomicAdd(A.unique_total, (unsigned long long)U);
+        if (tid == 0 && A.ucount_out && A.mode != VM_ALL) A.ucount_out[q] = U;
         if (A.mode == VM_COUNT) {
             if (tid == 0) A.out_counts[q] = (int32_t)U;
             __syncthreads();
@@ -439,8 +438,10 @@ static const void *verify_fn(int dp, int dtype)
 {
     const bool small = one_part_per_lane(dp, dtype);
     if (dtype == QW_U8)
-        return small ? (const void *)verify_kernel<QW_U8, 8, 1> : (const void *)verify_kernel<QW_U8, 2, 4>;
-    return small ? (const void *)verify_kernel<QW_F32, 8, 1> : (const void *)verify_kernel<QW_F32, 2, 4>;
+        return small ? (const void *)verify_kernel<QW_U8, 8, 1, false>
+                     : (const void *)verify_kernel<QW_U8, 2, 4, false>;
+    return small ? (const void *)verify_kernel<QW_F32, 8, 1, false>
+                 : (const void *)verify_kernel<QW_F32, 2, 4, false>;
 }
 
 int verify_blocks_per_cu(int dp, int dtype, size_t lds)
@@ -460,16 +461,17 @@ qw_status launch_verify(const VerifyArgs &a, int grid, hipStream_t s)
     const size_t lds = verify_lds_bytes((int)a.cap_log2, (int)a.buf, a.global_tab, a.L, a.dp,
                                         a.dtype);
     const bool small = one_part_per_lane(a.dp, a.dtype);
+    const bool g = a.global_tab != 0;
     if (a.dtype == QW_U8) {
-        if (small)
-            verify_kernel<QW_U8, 8, 1><<<grid, kBlock, lds, s>>>(a);
-        else
-            verify_kernel<QW_U8, 2, 4><<<grid, kBlock, lds, s>>>(a);
+        if (small && g) verify_kernel<QW_U8, 8, 1, true><<<grid, kBlock, lds, s>>>(a);
+        else if (small) verify_kernel<QW_U8, 8, 1, false><<<grid, kBlock, lds, s>>>(a);
+        else if (g) verify_kernel<QW_U8, 2, 4, true><<<grid, kBlock, lds, s>>>(a);
+        else verify_kernel<QW_U8, 2, 4, false><<<grid, kBlock, lds, s>>>(a);
     } else {
-        if (small)
-            verify_kernel<QW_F32, 8, 1><<<grid, kBlock, lds, s>>>(a);
-        else
-            verify_kernel<QW_F32, 2, 4><<<grid, kBlock, lds, s>>>(a);
+        if (small && g) verify_kernel<QW_F32, 8, 1, true><<<grid, kBlock, lds, s>>>(a);
+        else if (small) verify_kernel<QW_F32, 8, 1, false><<<grid, kBlock, lds, s>>>(a);
+        else if (g) verify_kernel<QW_F32, 2, 4, true><<<grid, kBlock, lds, s>>>(a);
+        else verify_kernel<QW_F32, 2, 4, false><<<grid, kBlock, lds, s>>>(a);
     }
     QW_HIP(hipGetLastError());
     return QW_OK;

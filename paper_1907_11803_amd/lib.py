@@ -58,7 +58,7 @@ class qw_index_info(ctypes.Structure):
                 ("L", ctypes.c_int32), ("k", ctypes.c_int32), ("w", ctypes.c_float),
                 ("key_bits", ctypes.c_int32 * 64), ("buckets", ctypes.c_int64),
                 ("max_bucket", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("has_count_model", ctypes.c_int32)]
+                ("has_count_model", ctypes.c_int32), ("count_margin", ctypes.c_float)]
 
 
 # exported symbols and their signatures (restype qw_status unless noted)
@@ -82,6 +82,7 @@ SIGNATURES = {
     "qw_train_count_model": (ctypes.c_int, [_P, _P, _I64, _I32, _I32, _F32, _U64, _P, _P]),
     "qw_set_count_model": (ctypes.c_int, [_P, _P, _I32]),
     "qw_get_count_model": (ctypes.c_int, [_P, _P, _I32]),
+    "qw_set_count_margin": (ctypes.c_int, [_P, ctypes.c_float]),
 }
 
 _lib = None
@@ -296,6 +297,10 @@ def qw_set_count_model(ix, params: np.ndarray):
     _check(load().qw_set_count_model(ix, ctypes.c_void_p(p.ctypes.data), p.size), "qw_set_count_model")
 
 
+def qw_set_count_margin(ix, margin: float):
+    _check(load().qw_set_count_margin(ix, float(margin)), "qw_set_count_margin")
+
+
 def qw_get_count_model(ix, L: int) -> np.ndarray:
     p = np.empty(qw_mlp_param_count(L), dtype=np.float32)
     _check(load().qw_get_count_model(ix, ctypes.c_void_p(p.ctypes.data), p.size), "qw_get_count_model")
@@ -341,6 +346,9 @@ class Index:
 
     def get_count_model(self) -> np.ndarray:
         return qw_get_count_model(self.handle, self.L)
+
+    def set_count_margin(self, margin: float):
+        qw_set_count_margin(self.handle, margin)
 
     def info(self) -> dict:
         return qw_get_index_info(self.handle)

@@ -275,18 +275,47 @@ def test_learned_schedule_trains_and_keeps_results(cfg1):
     loss = ix.train_count_model(dev(train), epochs=4, batch=256, lr=3e-3, seed=1)
     assert math.isfinite(loss)
     assert ix.info()["has_count_model"] == 1
+    # the sizing margin is calibrated on the training queries: at least 0.05,
+    # and about 1 training query in 200 exceeds its sized prediction
+    margin = ix.info()["count_margin"]
+    assert 0.05 <= margin <= 8.0
+    with pytest.raises(lib.QwError):
+        ix.set_count_margin(float("nan"))
+    with pytest.raises(lib.QwError):
+        ix.set_count_margin(9.0)
     ids_o, dist_o, _ = oracle.lsh_query(cfg1.data, cfg1.queries, p.a, p.b(w), w, cfg1.K)
     ids, dist, st = ix.query(dev(cfg1.queries), cfg1.K,
                              lib.make_opts(sched=lib.QW_SCHED_LEARNED), stats=True)
     check_topk(ids, dist, ids_o, dist_o, True)
-    # a sabotaged model (predicts 0 candidates) forces the overflow path
+    # a sabotaged model (predicts 0 candidates) still gives the exact results
     P = lib.qw_mlp_param_count(p.L)
     bad = np.zeros(P, np.float32)
     bad[-1] = -5.0
     ix.set_count_model(bad)
+    assert abs(ix.info()["count_margin"] - math.log(1.25)) < 1e-6
     ids, dist, st = ix.query(dev(cfg1.queries), cfg1.K,
                              lib.make_opts(sched=lib.QW_SCHED_LEARNED), stats=True)
     check_topk(ids, dist, ids_o, dist_o, True)
+    ix.set_count_margin(-4.0)  # smallest margin: still exact results
+    ids, dist, st = ix.query(dev(cfg1.queries), cfg1.K,
+                             lib.make_opts(sched=lib.QW_SCHED_LEARNED), stats=True)
+    check_topk(ids, dist, ids_o, dist_o, True)
+    ix.close()
+    # every point a candidate (|C(q)| = n = 10,000): sets chosen from the
+    # sabotaged prediction overflow and the queries move up the size classes
+    wh = 1e7
+    bh = np.full_like(p.b(wh), wh / 2)
+    ixh = build(cfg1.data, p.a, bh, wh)
+    ixh.set_count_model(bad)
+    ids_o, dist_o, cnt_o = oracle.lsh_query(cfg1.data, cfg1.queries, p.a, bh, wh, cfg1.K)
+    assert np.all(cnt_o == cfg1.data.shape[0])
+    for group in (0, 1):
+        ids, dist, st = ixh.query(dev(cfg1.queries), cfg1.K,
+                                  lib.make_opts(sched=lib.QW_SCHED_LEARNED, group=group), stats=True)
+        check_topk(ids, dist, ids_o, dist_o, True)
+        assert st["overflow"] >= cfg1.queries.shape[0]
+        assert st["cand_unique"] == int(cnt_o.sum())
+    ixh.close()
 
 
 # ---------------------------------------------------------------- errors
