@@ -55,13 +55,17 @@ def recall_at_10(ids_lsh, ids_true, dist_lsh, dist_true):
     return hits / (K * ids_lsh.shape[0])
 
 
-def gather_source_hash():
-    """Identifies the gather kernel's source: stored HBM traffic is used only
-    while it matches."""
+def kernel_source_hash(files):
+    """Identifies a kernel's source: stored HBM traffic is used only while it
+    matches."""
     h = hashlib.sha256()
-    for f in ("qw_flat.hip", "qw_internal.h"):
+    for f in files:
         h.update(open(os.path.join(ROOT, "paper_1907_11803_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
+
+
+FUSED_SOURCES = ("qw_dedup.hip", "qw_dedup.h", "qw_dist.h")
+GATHER_SOURCES = ("qw_gather.hip", "qw_dist.h")
 
 
 def main():
@@ -159,7 +163,7 @@ def main():
         torch.cuda.synchronize()
         return start.elapsed_time(stop) / steps
 
-    fast_opts = lib.make_opts(form=lib.QW_FORM_FAST, sched=lib.QW_SCHED_LEARNED, group=1, graph=1)
+    fast_opts = lib.make_opts(form=lib.QW_FORM_FAST, sched=lib.QW_SCHED_LEARNED, group=0, graph=1)
     if args.profile:
         # a plain device copy of known size (1 GiB read + 1 GiB written) to
         # calibrate the HBM byte counters of a profiling run
@@ -187,8 +191,8 @@ def main():
     for name, sc in (("sum", lib.QW_SCHED_SUM), ("actual", lib.QW_SCHED_ACTUAL),
                      ("none", lib.QW_SCHED_NONE), ("learned", lib.QW_SCHED_LEARNED)):
         sched_ms[name] = round(timed(lib.make_opts(sched=sc), max(5, args.steps // 2), 2), 4)
-    sched_ms["learned_no_grouping"] = round(
-        timed(lib.make_opts(sched=lib.QW_SCHED_LEARNED, group=0), max(5, args.steps // 2), 2), 4)
+    sched_ms["learned_grouped"] = round(
+        timed(lib.make_opts(sched=lib.QW_SCHED_LEARNED, group=1), max(5, args.steps // 2), 2), 4)
     log(f"[bench] fast {ms_fast:.3f} ms/step, plain {ms_plain:.3f} ms/step, scheds {sched_ms}")
 
     # ---- per-stage timing of the fast pipeline (events inside the library)
@@ -204,18 +208,26 @@ def main():
     L = wl.params.L
     alg_bytes = (wl.Q * wl.d * elem + 8 * L * wl.Q + 4 * st["cand_total"] +
                  st["cand_unique"] * wl.d * elem + 8 * K * wl.Q)
-    # dominant kernel: the gather (one launch per step).  Algorithmic bytes per
-    # (query, candidate) pair: the candidate's row, the pair (id, query) read
-    # and the (distance, id) key written; plus each query row once.
-    pair_bytes = wl.d * elem + 8 + 8
-    gather_bytes = st["cand_unique"] * pair_bytes + wl.Q * wl.d * elem
-    gather_ms = float(stage[7])
-    achieved = gather_bytes / (gather_ms * 1e-3) / 1e9 if gather_ms > 0 else None
+    # Dominant kernel.  Fused form (no separate gather launch): the dedup
+    # kernel, which also verifies its candidates; algorithmic bytes per query:
+    # the bucket ids (4 per entry), each unique candidate's row and its
+    # (distance, id) key, the query row.  Otherwise the streaming gather: per
+    # pair the row, the (id, query) pair and the key; plus each query row.
+    fused = float(stage[7]) < 0.02 * float(stage[6])
+    if fused:
+        kname, ksrc, kfile = "dedup_kernel (dedup + verify)", FUSED_SOURCES, "dedup_verify"
+        kbytes = 4 * st["cand_total"] + st["cand_unique"] * (wl.d * elem + 8) + wl.Q * wl.d * elem
+        kms = float(stage[6])
+    else:
+        kname, ksrc, kfile = "gather_kernel", GATHER_SOURCES, "gather"
+        kbytes = st["cand_unique"] * (wl.d * elem + 16) + wl.Q * wl.d * elem
+        kms = float(stage[7])
+    achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else None
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"gather_cfg{args.config}_traffic.json")
+    tfile = os.path.join(ROOT, "profiles", f"{kfile}_cfg{args.config}_traffic.json")
     if os.path.exists(tfile):
         tj = json.load(open(tfile))
-        if tj.get("source") == gather_source_hash() and abs(tj.get("w", -1) - w) < 1e-9:
+        if tj.get("source") == kernel_source_hash(ksrc) and abs(tj.get("w", -1) - w) < 1e-9:
             traffic = tj.get("bytes_per_launch")
 
     # ---- CPU oracle on a bounded sample
@@ -282,9 +294,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                     "traffic": traffic, "kernel": "gather_kernel",
-                     "kernel_ms": round(gather_ms, 4),
-                     "kernel_algorithmic_bytes": int(gather_bytes),
+                     "traffic": traffic, "kernel": kname,
+                     "kernel_ms": round(kms, 4),
+                     "kernel_algorithmic_bytes": int(kbytes),
                      "path_algorithmic_bytes_per_step": int(alg_bytes)},
         "cpu_baseline": cpu,
     }

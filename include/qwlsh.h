@@ -61,8 +61,9 @@ typedef enum {
      * workload. */
     QW_FORM_PLAIN_FP32 = 0,
     /* FP16 (uint8 data) or FP32 (float data) MFMA projections with an FP64 guard
-     * band; queries grouped by bucket, binned by predicted candidate count and
-     * served by a persistent verify kernel; replayed from a HIP graph. */
+     * band; queries binned by predicted candidate count (optionally grouped by
+     * bucket) into persistent dedup-and-verify kernels, then a per-query top-K
+     * select; replayed from a HIP graph. */
     QW_FORM_FAST = 1
 } qw_form;
 
@@ -77,7 +78,8 @@ typedef enum {
 typedef struct {
     int32_t form;      /* qw_form */
     int32_t sched;     /* qw_sched (fast form only) */
-    int32_t group;     /* fast form: 1 = order queries by bucket key (default), 0 = workload order */
+    int32_t group;     /* fast form: 1 = order queries by bucket key within a size class,
+                          0 = no bucket ordering (default) */
     int32_t graph;     /* fast form: 1 = capture/replay the query pipeline as a HIP graph */
     int32_t timing;    /* 1 = record per-stage HIP events and report them in qw_stats (syncs) */
     int32_t reserved[3];
@@ -114,7 +116,7 @@ typedef struct {
 typedef struct qw_index qw_index;
 
 /* Default options: fast form, learned schedule when a model is loaded (else
- * the bucket-size sum), grouping on, graph on, timing off. */
+ * the bucket-size sum), grouping off, graph on, timing off. */
 void qw_default_opts(qw_opts *o);
 
 /*

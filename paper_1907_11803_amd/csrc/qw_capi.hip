@@ -13,19 +13,20 @@ using namespace qw;
 
 namespace {
 
+constexpr int kCmin = 10;
+constexpr int kMaxClasses = 16;
+
 // counters buffer: u64 [kC64] then u32 [kC32]
 enum {
     C_RECOMP = 0, C_UNIQUE, C_PROBEHIT, C_CANDTOT, C_CLASS /* .. C_CLASS+15 */,
     C_ALLOC = 20 /* .. +kXcd-1 */, C_FAIL = 28 /* .. +kXcd-1 */, C_SPARE = 36, kC64 = 40
 };
-// u32: persistent work counters per class, overflow-queue lengths per class
-// (queue i holds queries that overflowed class i-1), per-XCD chunk counters,
-// fallback queue, misc
-enum { W_WORK = 0 /* .. 15 */, W_QCNT = 16 /* .. 32 */, W_SIMPLE = 33, W_MAX = 34, W_DUMMY = 35,
-       W_XCD = 36 /* .. 43 */, W_FB = 44, W_FBWORK = 45, kC32 = 48 };
+// u32: overflow-queue lengths per class (queue i holds queries that overflowed
+// class i-1), fallback queue, misc, then kXcd work counters per class
+enum { W_WORK = 0 /* .. 15: unused */, W_QCNT = 16 /* .. 32 */, W_SIMPLE = 33, W_MAX = 34,
+       W_DUMMY = 35, W_FB = 44, W_FBWORK = 45, W_XWORK = 48,
+       kC32 = W_XWORK + kXcd * kMaxClasses };
 constexpr int64_t kCandPerQuery = 4096;  // pair space reserved per query (beyond: fallback)
-constexpr int kCmin = 10;
-constexpr int kMaxClasses = 16;
 
 
 inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
@@ -52,9 +53,10 @@ Plan make_plan(qw_index *ix, int K)
     if (hit != ix->plans.end()) return hit->second;
     Plan p;
     p.buf = pow2_at_least(std::max(64, 2 * (K + verify_per_iter(ix->dp, ix->dtype))));
+    const int rbytes = ix->dp * (ix->dtype == QW_U8 ? 1 : 4);
     int c = kCmin;
     while (c + 1 < 30 && (int)(c + 1 - kCmin) < kMaxClasses - 1 &&
-           dedup_lds_bytes(c + 1, 0, ix->L) <= ix->lds_max)
+           dedup_lds_bytes(c + 1, 0, ix->L, rbytes) <= ix->lds_max)
         ++c;
     p.cmax = c;
     p.ncls = (p.cmax - kCmin + 1) + 1;
@@ -62,8 +64,9 @@ Plan make_plan(qw_index *ix, int K)
     // registers bound it first): smaller sets save nothing
     p.cfloor = kCmin;
     {
-        const int nb0 = dedup_blocks_per_cu(dedup_lds_bytes(kCmin, 0, ix->L));
-        while (p.cfloor < p.cmax && dedup_blocks_per_cu(dedup_lds_bytes(p.cfloor + 1, 0, ix->L)) >= nb0)
+        const int nb0 = dedup_blocks_per_cu(dedup_lds_bytes(kCmin, 0, ix->L, rbytes), ix->dtype);
+        while (p.cfloor < p.cmax &&
+               dedup_blocks_per_cu(dedup_lds_bytes(p.cfloor + 1, 0, ix->L, rbytes), ix->dtype) >= nb0)
             ++p.cfloor;
     }
     const uint64_t bound = std::min<uint64_t>((uint64_t)ix->L * (uint64_t)std::max<int64_t>(1, ix->max_bucket),
@@ -74,7 +77,7 @@ Plan make_plan(qw_index *ix, int K)
     const double budget = 2.0 * 1024 * 1024 * 1024;
     p.grid_g = (int)std::max(1.0, std::min((double)ix->cus, std::floor(budget / per_wg)));
     for (int i = 0; i + 1 < p.ncls; ++i)
-        p.dgrid[i] = dedup_blocks_per_cu(dedup_lds_bytes(kCmin + i, 0, ix->L)) * ix->cus;
+        p.dgrid[i] = dedup_blocks_per_cu(dedup_lds_bytes(kCmin + i, 0, ix->L, rbytes), ix->dtype) * ix->cus;
     p.dgrid[p.ncls - 1] = p.grid_g;
     // select list: a few K keys in the usual case; K <= 1024 keeps LC <= 4096
     // (32 KiB of keys, 64 KiB with the FP64 re-rank of float data)
@@ -98,7 +101,7 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan)
 {
     Workspace &w = ix->ws;
     auto ptrs = [&w]() {
-        return std::vector<void *>{w.qpad.p, w.h.p, w.bstart.p, w.bsize.p, w.qsum.p, w.pred.p,
+        return std::vector<void *>{w.qpad.p, w.h.p, w.bstart.p, w.bsize.p, w.pred.p,
                                    w.feats.p, w.keys.p, w.keys2.p, w.vals.p, w.vals2.p,
                                    w.binoff.p, w.counters.p, w.ovf.p, w.gscratch.p, w.mlpout.p,
                                    w.hist.p, w.scan.p, w.ucount.p, w.coff.p, w.flag.p,
@@ -111,7 +114,6 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan)
     QW_TRY(w.h.ensure(sizeof(int32_t) * (size_t)q * ix->nf));
     QW_TRY(w.bstart.ensure(sizeof(uint32_t) * (size_t)q * ix->L));
     QW_TRY(w.bsize.ensure(sizeof(uint32_t) * (size_t)q * ix->L));
-    QW_TRY(w.qsum.ensure(sizeof(uint32_t) * q));
     QW_TRY(w.pred.ensure(sizeof(int32_t) * q));
     QW_TRY(w.feats.ensure(sizeof(float) * (size_t)q * ix->L));
     QW_TRY(w.mlpout.ensure(sizeof(float) * q));
@@ -132,8 +134,10 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan)
         const int64_t cand_cap = std::max<int64_t>(q * kCandPerQuery, 1 << 20);
         QW_TRY(w.coff.ensure(sizeof(unsigned long long) * q));
         QW_TRY(w.flag.ensure(sizeof(uint32_t) * q));
-        QW_TRY(w.cand.ensure(sizeof(int32_t) * cand_cap));
-        QW_TRY(w.candq.ensure(sizeof(int32_t) * cand_cap));
+        if (!plan->fuse) {  // pair list for the streaming gather
+            QW_TRY(w.cand.ensure(sizeof(int32_t) * cand_cap));
+            QW_TRY(w.candq.ensure(sizeof(int32_t) * cand_cap));
+        }
         QW_TRY(w.pkeys.ensure(sizeof(unsigned long long) * cand_cap));
         QW_TRY(w.fb.ensure(sizeof(int32_t) * q));
     }
@@ -163,17 +167,17 @@ VerifyArgs base_args(qw_index *ix, int K, int mode)
     return a;
 }
 
-// pad -> hash -> probe for Q queries (counters must already be cleared)
+// pad -> hash -> probe for Q queries (counters must already be cleared);
+// feats (nullable) receives the count-model inputs log(1 + s_{q,l})
 qw_status front(qw_index *ix, const void *queries, int64_t Q, int form, hipStream_t s,
-                hipEvent_t *ev = nullptr)
+                hipEvent_t *ev = nullptr, float *feats = nullptr)
 {
     QW_TRY(launch_pad_rows(queries, Q, ix->d, ix->dp, ix->dtype, ix->ws.qpad.p, s));
     QW_TRY(launch_hash(ix, ix->ws.qpad.p, Q, 0, ix->nf, form, ix->ws.h.as<int32_t>(), ix->nf,
                        c64(ix) + C_RECOMP, s));
     if (ev) QW_HIP(hipEventRecord(ev[1], s));
-    QW_TRY(launch_fill_u32(ix->ws.qsum.as<uint32_t>(), 0u, Q, s));
     QW_TRY(launch_probe(ix, ix->ws.h.as<int32_t>(), Q, ix->ws.bstart.as<uint32_t>(),
-                        ix->ws.bsize.as<uint32_t>(), ix->ws.qsum.as<uint32_t>(), s));
+                        ix->ws.bsize.as<uint32_t>(), feats, s));
     return QW_OK;
 }
 
@@ -191,7 +195,7 @@ qw_status verify_simple(qw_index *ix, int64_t Q, int K, int mode, hipStream_t s,
 {
     uint32_t *mx = c32(ix) + W_MAX;
     QW_TRY(launch_fill_u32(mx, 0u, 1, s));
-    QW_TRY(launch_max_u32(ix->ws.qsum.as<uint32_t>(), Q, mx, s));
+    QW_TRY(launch_max_bucket_sum(ix->ws.bsize.as<uint32_t>(), Q, ix->L, mx, s));
     uint32_t maxsum = 0;
     QW_HIP(hipMemcpyAsync(&maxsum, mx, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     QW_HIP(hipStreamSynchronize(s));
@@ -236,8 +240,8 @@ qw_status check_index(const qw_index *ix)
 }
 
 // Fast form: exact MFMA hashing, probe, schedule (size classes from the
-// selected count source, bucket grouping), per-class dedup into device-wide
-// candidate lists, chunked streaming verify, per-query merge, fallback.
+// selected count source, bucket grouping), per-class dedup into per-XCD pair
+// regions, gather, select, fallback.
 qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int64_t Q, int K,
                        const qw_opts &o, hipStream_t s, int32_t *out_ids, void *out_dist,
                        hipEvent_t *ev)
@@ -245,16 +249,16 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     Workspace &w = ix->ws;
     if (ev) QW_HIP(hipEventRecord(ev[0], s));
     QW_TRY(clear_counters(ix, s));
-    QW_TRY(front(ix, queries, Q, QW_FORM_FAST, s, ev));
-    if (ev) QW_HIP(hipEventRecord(ev[2], s));
     const bool learned = o.sched == QW_SCHED_LEARNED && !ix->mlp.empty();
+    QW_TRY(front(ix, queries, Q, QW_FORM_FAST, s, ev, learned ? w.feats.as<float>() : nullptr));
+    if (ev) QW_HIP(hipEventRecord(ev[2], s));
     unsigned long long *seg = w.binoff.as<unsigned long long>();
     unsigned long long *ccount = c64(ix) + C_CLASS;
     int32_t *queues = w.ovf.as<int32_t>();
-    const int64_t cand_cap = (int64_t)(w.cand.bytes / sizeof(int32_t));
+    const int64_t cand_cap = (int64_t)(w.pkeys.bytes / sizeof(unsigned long long));
     auto schedule = [&](const int32_t *ex, const float *pl, int force_max,
                         const int32_t **order) -> qw_status {
-        QW_TRY(launch_classify(Q, ix->L, ix->n, w.qsum.as<uint32_t>(), w.bstart.as<uint32_t>(),
+        QW_TRY(launch_classify(Q, ix->L, ix->n, w.bstart.as<uint32_t>(),
                                w.bsize.as<uint32_t>(), ex, pl, ix->mlp_margin, force_max, kCmin,
                                plan.cfloor, plan.cmax, plan.ncls, o.group, w.keys.as<unsigned long long>(),
                                w.vals.as<int32_t>(), ccount, s));
@@ -269,16 +273,24 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     // Classes run from the smallest hash set to the global one.  Each launch
     // serves its segment of the order, then the queue of queries that
     // overflowed the previous class; its own overflows go to the next queue.
+    // One launch serves every LDS class up to cfloor (their sets cost no
+    // occupancy, so the launch is sized for the largest; queries go largest
+    // first); the larger classes follow one launch each, each serving its
+    // segment and then the queue of queries that overflowed the launch before.
     auto dedup_classes = [&](const int32_t *order, int count_only) -> qw_status {
-        for (int i = 0; i < plan.ncls; ++i) {
+        auto launch_range = [&](int lo, int hi) -> qw_status {
             DedupArgs a;
             std::memset(&a, 0, sizeof(a));
             a.order = order;
-            a.seg = seg + 2 * i;
-            a.in_list = i > 0 ? queues + (int64_t)i * Q : nullptr;
-            a.in_count = i > 0 ? c32(ix) + W_QCNT + i : nullptr;
-            a.ovf_list = queues + (int64_t)(i + 1) * Q;
-            a.ovf_count = c32(ix) + W_QCNT + i + 1;
+            a.seg = seg;
+            a.cls_lo = lo;
+            a.cls_hi = hi;
+            a.cap_base = kCmin;
+            a.xwork = c32(ix) + W_XWORK + kXcd * hi;
+            a.in_list = lo > 0 ? queues + (int64_t)lo * Q : nullptr;
+            a.in_count = lo > 0 ? c32(ix) + W_QCNT + lo : nullptr;
+            a.ovf_list = queues + (int64_t)(hi + 1) * Q;
+            a.ovf_count = c32(ix) + W_QCNT + hi + 1;
             a.bstart = w.bstart.as<uint32_t>();
             a.bsize = w.bsize.as<uint32_t>();
             a.ids = ix->ids.as<int32_t>();
@@ -290,20 +302,29 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
             a.region = (unsigned long long)(cand_cap / kXcd);
             a.cand = w.cand.as<int32_t>();
             a.candq = w.candq.as<int32_t>();
+            a.fuse = plan.fuse;
+            a.dp = ix->dp;
+            a.dtype = ix->dtype;
+            a.data = ix->data.p;
+            a.queries = w.qpad.p;
+            a.keys = w.pkeys.as<unsigned long long>();
             a.ucount = w.ucount.as<uint32_t>();
             a.coff = w.coff.as<unsigned long long>();
             a.flag = w.flag.as<uint32_t>();
-            if (i == plan.ncls - 1) {
+            if (hi == plan.ncls - 1) {
                 a.cap_log2 = (uint32_t)plan.cap_g;
                 a.limit = (1u << plan.cap_g) / 4 * 3;
                 a.global_tab = 1;
                 a.gscratch = w.gscratch.as<uint32_t>();
             } else {
-                a.cap_log2 = (uint32_t)(kCmin + i);
-                a.limit = (1u << (kCmin + i)) / 4 * 3;
+                a.cap_log2 = (uint32_t)(kCmin + hi);  // LDS size; also the queue's class
+                a.limit = 0xFFFFFFFFu;                 // each set's own 3/4 bound
             }
-            QW_TRY(launch_dedup(a, plan.dgrid[i], s));
-        }
+            return launch_dedup(a, plan.dgrid[hi], s);
+        };
+        const int merged = std::max(0, std::min(plan.cfloor - kCmin, plan.ncls - 2));
+        QW_TRY(launch_range(0, merged));
+        for (int i = merged + 1; i < plan.ncls; ++i) QW_TRY(launch_range(i, i));
         return QW_OK;
     };
     const int32_t *order = nullptr;
@@ -314,9 +335,9 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
         QW_TRY(dedup_classes(order, 1));
         QW_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(ccount), 0u, 2 * kMaxClasses, s));
         QW_TRY(launch_fill_u32(c32(ix) + W_WORK, 0u, W_SIMPLE - W_WORK, s));
+        QW_TRY(launch_fill_u32(c32(ix) + W_XWORK, 0u, kXcd * kMaxClasses, s));
         exact = reinterpret_cast<const int32_t *>(w.ucount.p);
     } else if (learned) {
-        QW_TRY(launch_mlp_features(w.bsize.as<uint32_t>(), Q, ix->L, w.feats.as<float>(), s));
         QW_TRY(launch_mlp_predict_bf16(ix->mlp_dev.as<float>(), ix->L, w.feats.as<float>(), Q,
                                        w.mlpout.as<float>(), s));
         pred_log = w.mlpout.as<float>();
@@ -338,7 +359,7 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     g.dp = ix->dp;
     g.dtype = ix->dtype;
     g.keys = w.pkeys.as<unsigned long long>();
-    QW_TRY(launch_gather(g, plan.ggrid, s));
+    if (!plan.fuse) QW_TRY(launch_gather(g, plan.ggrid, s));
     if (ev) QW_HIP(hipEventRecord(ev[7], s));
     SelectArgs m;
     std::memset(&m, 0, sizeof(m));
@@ -451,7 +472,7 @@ void qw_default_opts(qw_opts *o)
     std::memset(o, 0, sizeof(*o));
     o->form = QW_FORM_FAST;
     o->sched = QW_SCHED_LEARNED;
-    o->group = 1;
+    o->group = 0;  // bucket ordering costs two radix passes and buys little locality
     o->graph = 1;
     o->timing = 0;
 }

@@ -1,0 +1,400 @@
+// Candidate dedup of the fast form: one workgroup per query builds C(q)
+// (the union of the query's buckets, Sections 1.2 and 5.1) in an LDS hash set
+// sized by its size class.  Fused mode then verifies its unique candidates
+// itself -- gathers their rows, computes the exact squared distances (the
+// false-positive removal of Section 1.2) and writes one (distance, id) key per
+// candidate into the query's range of its XCD's key region; otherwise it
+// writes the unique ids, each tagged with its query, for the streaming gather.
+// Queries whose set overflows move to the next size class; queries the region
+// cannot hold are flagged for the fallback.
+#include "qw_dedup.h"
+#include "qw_dist.h"
+#include "qw_internal.h"
+
+namespace qw {
+
+enum {
+    D_UCOUNT = 0, D_OVF, D_CPOS, D_T, D_CAP, D_OFF = 6 /* u64 */,
+    D_WT = 8 /* per-wave counts, kBlock / 64 */, D_NEXT = 12, D_NSCAL = 16
+};
+constexpr int kRegIds = 16;  // ids per thread of the register-resident path
+
+__host__ __device__ inline size_t a16(size_t v) { return (v + 15) & ~size_t(15); }
+
+// set | layer prefix | layer starts | scalars | query row (fused mode)
+size_t dedup_lds_bytes(int cap_log2, int global_tab, int L, int row_bytes)
+{
+    return (global_tab ? 0 : (size_t(4) << cap_log2)) + a16(size_t(L + 1) * 4) +
+           a16(size_t(L) * 4) + a16(D_NSCAL * 4) + a16((size_t)row_bytes);
+}
+
+// Exclusive prefix of the per-wave counts in scal[D_WT..]: the wave's base and
+// the workgroup total.  Call after the barrier that publishes the counts.
+__device__ inline uint32_t wave_base(const uint32_t *scal, int wave, uint32_t *total)
+{
+    uint32_t b = 0, t = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+        const uint32_t c = scal[D_WT + w];
+        b += w < wave ? c : 0u;
+        t += c;
+    }
+    *total = t;
+    return b;
+}
+
+// Whole workgroup: key[off + i] = (squared distance << 32) | id for the U ids
+// list[0..U) against the query row qrow (parts 16-byte parts, in LDS).  A
+// group of G lanes (a power of two >= parts, at most 64) holds one row, P
+// parts per lane; UN rows per group per step.  Rows of one part per lane:
+// the next step's rows are loaded before the current step is reduced, so two
+// steps are in flight.  No barriers.
+template <int DT>
+__device__ inline void verify_list(const DedupArgs &A, const uint32_t *list, uint32_t U,
+                                   const uint4 *qrow, int parts, unsigned long long off)
+{
+    constexpr int UN = 4;
+    const int tid = threadIdx.x;
+    int G = 1;
+    while (G < parts && G < 64) G <<= 1;
+    const int P = (parts + G - 1) / G;
+    const int NG = kBlock / G;
+    const uint32_t PI = (uint32_t)(NG * UN);
+    const int grp = tid / G, j = tid % G;
+    const uint4 *drows = reinterpret_cast<const uint4 *>(A.data);
+    unsigned long long *keys = A.keys + off;
+    auto finish = [&](uint32_t base, const uint32_t (&id)[UN], uint32_t (&accu)[UN],
+                      float (&accf)[UN]) {
+#pragma unroll
+        for (int u = 0; u < UN; ++u)
+            for (int o = G >> 1; o > 0; o >>= 1) {
+                if (DT == QW_U8)
+                    accu[u] += (uint32_t)__shfl_xor((int)accu[u], o);
+                else
+                    accf[u] += __shfl_xor(accf[u], o);
+            }
+        if (j == 0)
+#pragma unroll
+            for (int u = 0; u < UN; ++u) {
+                const uint32_t i = base + (uint32_t)(grp + NG * u);
+                if (i < U) {
+                    const uint32_t hi = DT == QW_U8 ? accu[u] : __float_as_uint(accf[u]);
+                    keys[i] = ((unsigned long long)hi << 32) | id[u];
+                }
+            }
+    };
+    if (P == 1) {
+        const bool jin = j < parts;
+        const int pc = jin ? j : parts - 1;
+        const uint4 qv = qrow[pc];
+        uint32_t nid[UN];
+        uint4 nx[UN];
+        auto load_step = [&](uint32_t base) {
+#pragma unroll
+            for (int u = 0; u < UN; ++u) {
+                const uint32_t i = base + (uint32_t)(grp + NG * u);
+                nid[u] = list[i < U ? i : 0u];
+            }
+#pragma unroll
+            for (int u = 0; u < UN; ++u) nx[u] = drows[(int64_t)nid[u] * parts + pc];
+        };
+        if (U) load_step(0);
+        for (uint32_t base = 0; base < U; base += PI) {
+            uint32_t id[UN];
+            uint4 xv[UN];
+#pragma unroll
+            for (int u = 0; u < UN; ++u) {
+                id[u] = nid[u];
+                xv[u] = nx[u];
+            }
+            load_step(base + PI < U ? base + PI : base);  // the last step reloads itself
+            __builtin_amdgcn_sched_barrier(0);  // keep the next rows ahead of the waits below
+            uint32_t accu[UN];
+            float accf[UN];
+#pragma unroll
+            for (int u = 0; u < UN; ++u) {
+                accu[u] = 0;
+                accf[u] = 0.f;
+                part_dist<DT>(xv[u], qv, accu[u], accf[u]);
+                accu[u] = jin ? accu[u] : 0u;
+                accf[u] = jin ? accf[u] : 0.f;
+            }
+            finish(base, id, accu, accf);
+        }
+        return;
+    }
+    for (uint32_t base = 0; base < U; base += PI) {
+        uint32_t id[UN];
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            const uint32_t i = base + (uint32_t)(grp + NG * u);
+            id[u] = list[i < U ? i : 0u];
+        }
+        uint32_t accu[UN];
+        float accf[UN];
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            accu[u] = 0;
+            accf[u] = 0.f;
+        }
+        for (int p = 0; p < P; ++p) {
+            const int part = j + G * p;
+            const int pc = part < parts ? part : parts - 1;
+            uint4 xv[UN];
+#pragma unroll
+            for (int u = 0; u < UN; ++u) xv[u] = drows[(int64_t)id[u] * parts + pc];
+            const uint4 qv = qrow[pc];
+#pragma unroll
+            for (int u = 0; u < UN; ++u) {
+                uint32_t au = 0;
+                float af = 0.f;
+                part_dist<DT>(xv[u], qv, au, af);
+                accu[u] += part < parts ? au : 0u;
+                accf[u] += part < parts ? af : 0.f;
+            }
+        }
+        finish(base, id, accu, accf);
+    }
+}
+
+// One workgroup per query (persistent).  The workgroups of XCD x take items
+// x, x + 8, x + 16, ... through that XCD's own counter (a single shared
+// counter would serialise every workgroup's atomic on one address); each
+// workgroup fetches its next item while the current one runs.  Queries with
+// at most kRegIds * kBlock
+// bucket entries in an LDS set keep their ids in registers from the load to
+// the write; larger ones (and the global-memory class, GLOB) go through the
+// set and read the unique ids back from it.
+template <bool GLOB, int DT>
+__global__ __launch_bounds__(kBlock) void dedup_kernel(DedupArgs A)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const unsigned long long lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+    constexpr bool glob = GLOB;
+    const size_t tab_bytes = glob ? 0 : (size_t(4) << A.cap_log2);
+    uint32_t *lpref = reinterpret_cast<uint32_t *>(smem + tab_bytes);
+    uint32_t *lstart = reinterpret_cast<uint32_t *>(smem + tab_bytes + a16(size_t(A.L + 1) * 4));
+    uint32_t *scal = reinterpret_cast<uint32_t *>(smem + tab_bytes + a16(size_t(A.L + 1) * 4) +
+                                                  a16(size_t(A.L) * 4));
+    const int row_bytes = A.dp * (DT == QW_U8 ? 1 : 4);
+    const int parts = row_bytes / 16;
+    uint4 *qrow = reinterpret_cast<uint4 *>(reinterpret_cast<unsigned char *>(scal) + a16(D_NSCAL * 4));
+    uint32_t *tab = GLOB ? A.gscratch + (size_t)blockIdx.x * (size_t(1) << A.cap_log2)
+                         : reinterpret_cast<uint32_t *>(smem);
+    unsigned long long *soff = reinterpret_cast<unsigned long long *>(&scal[D_OFF]);
+    const int64_t sbeg = (int64_t)A.seg[2 * A.cls_lo];
+    const int64_t send = (int64_t)A.seg[2 * A.cls_hi + 1];
+    const int64_t nseg = send - sbeg;
+    const int64_t nin = A.in_count ? (int64_t)*A.in_count : 0;
+    const int64_t nall = nseg + nin;
+    const int xcd = blockIdx.x % kXcd;
+    const unsigned long long rbase = (unsigned long long)xcd * A.region;
+    // the launch's classes, largest first, then the queue of queries that
+    // overflowed a smaller class
+    auto query_of = [&](int64_t it) -> int64_t {
+        return it < nseg ? (int64_t)A.order[send - 1 - it] : (int64_t)A.in_list[it - nseg];
+    };
+    auto class_cap = [&](int64_t it) -> int {
+        if (it >= nseg) return (int)A.cap_log2;
+        const unsigned long long pos = (unsigned long long)(send - 1 - it);
+        int c = A.cls_lo;
+        while (c < A.cls_hi && pos >= A.seg[2 * c + 1]) ++c;
+        return A.cap_base + c;
+    };
+    // LDS sets only need LDS made visible at a barrier: outstanding global
+    // loads (ids, the next query's bucket ranges) stay in flight across it
+    auto bar = [&]() {
+        if (GLOB) {
+            __syncthreads();
+        } else {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+            __builtin_amdgcn_s_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+        }
+    };
+    if (tid == 0) scal[D_NEXT] = atomicAdd(A.xwork + xcd, 1u);
+    __syncthreads();
+    int64_t item = (int64_t)xcd + (int64_t)kXcd * scal[D_NEXT];
+    uint32_t pf_start = 0, pf_size = 0;  // threads < L: bucket range of the next query
+    if (item < nall && tid < A.L) {
+        const int64_t q0 = query_of(item);
+        pf_start = A.bstart[q0 * A.L + tid];
+        pf_size = A.bsize[q0 * A.L + tid];
+    }
+
+    while (item < nall) {  // uniform: every thread holds the same item
+        uint32_t next = 0;
+        if (tid == 0) next = atomicAdd(A.xwork + xcd, 1u);  // published at the end of the iteration
+        const int64_t q = query_of(item);
+        if (tid < A.L) {
+            lstart[tid] = pf_start;
+            lpref[tid + 1] = pf_size;
+        }
+        if (A.fuse)  // the query row, for the verification at the end
+            for (int i = tid; i < parts; i += kBlock)
+                qrow[i] = reinterpret_cast<const uint4 *>(A.queries)[q * parts + i];
+        if (tid == 0) {
+            scal[D_UCOUNT] = 0;
+            scal[D_OVF] = 0;
+            scal[D_CPOS] = 0;
+        }
+        bar();
+        if (tid < 64) {
+            const uint32_t run = wave_layer_prefix(lpref, A.L);
+            if (tid == 0) {
+                scal[D_T] = run;
+                int c = glob ? (int)A.cap_log2 : class_cap(item);
+                if (glob) {  // set sized from the exact bound min(sum_l s_{q,l}, n)
+                    const uint64_t bound = min((uint64_t)run, (uint64_t)A.n);
+                    c = 10;
+                    while (c < (int)A.cap_log2 && (3ull << c) < 4 * bound) ++c;
+                }
+                scal[D_CAP] = (uint32_t)c;
+            }
+        }
+        bar();
+        const uint32_t T = scal[D_T];
+        const int cap_log2 = (int)scal[D_CAP];
+        const uint32_t cap = 1u << cap_log2;
+        const uint32_t set_limit = (cap >> 2) * 3;
+        const uint32_t limit = glob ? set_limit : (A.limit < set_limit ? A.limit : set_limit);
+        const uint32_t max_probe = glob ? 0xFFFFFFFFu : kShortProbe;
+        const bool in_regs = !glob && T <= (uint32_t)(kRegIds * kBlock);
+        uint32_t idr[kRegIds];
+        uint32_t pend = 0;
+        if (in_regs)  // the id loads fly while the set is cleared
+            pend = load_ids<kRegIds>(A.ids, A.n, A.L, lpref, lstart, T, 0u, idr);
+        for (uint32_t i = tid; i < cap; i += kBlock) tab[i] = kEmpty;
+        if (glob) __threadfence();
+        bar();
+        uint32_t newm = 0;
+        uint32_t U = 0, wbase = 0;
+        bool ovf = false;
+        if (in_regs) {
+            bool full = false;
+            newm = insert_streams<kRegIds, 4>(tab, cap_log2, idr, pend, max_probe, full);
+            // this lane's position among the wave's new ids
+            uint32_t cnt = (uint32_t)__popc(newm), incl = cnt;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t t = (uint32_t)__shfl_up((int)incl, off);
+                if (lane >= off) incl += t;
+            }
+            wbase = incl - cnt;
+            if (lane == 63) scal[D_WT + wave] = incl;
+            if (__ballot(full) != 0ull && lane == 0) scal[D_OVF] = 1;
+            bar();
+            uint32_t tot = 0;
+            wbase += wave_base(scal, wave, &tot);
+            U = tot;
+            ovf = scal[D_OVF] != 0 || U > limit;
+        } else {
+            set_union(A.ids, A.n, A.L, lpref, lstart, T, tab, cap_log2, limit, glob, max_probe,
+                      A.fuse != 0, &scal[D_UCOUNT], &scal[D_OVF], &scal[D_CPOS]);
+            U = scal[D_UCOUNT];
+            ovf = scal[D_OVF] != 0 || U > limit;
+        }
+        if (tid == 0) {
+            unsigned long long off = ~0ull;
+            if (ovf) {  // on to the next size class
+                const uint32_t o = atomicAdd(A.ovf_count, 1u);
+                A.ovf_list[o] = (int32_t)q;
+            } else if (A.count_only) {
+                A.ucount[q] = U;
+            } else {
+                off = atomicAdd(A.alloc + xcd, (unsigned long long)U);
+                if (off + U > A.region) {  // no list space: answered by the fallback
+                    atomicMax(A.fail + xcd, ~off);
+                    A.flag[q] = 1;
+                    A.ucount[q] = 0;
+                    off = ~0ull;
+                } else {
+                    off += rbase;
+                    A.ucount[q] = U;
+                    A.coff[q] = off;
+                }
+            }
+            *soff = off;
+            scal[D_NEXT] = next;
+        }
+        bar();
+        const unsigned long long off = *soff;
+        item = (int64_t)xcd + (int64_t)kXcd * scal[D_NEXT];
+        if (item < nall && tid < A.L) {  // the next query's bucket ranges fly during the writes
+            const int64_t qn = query_of(item);
+            pf_start = A.bstart[qn * A.L + tid];
+            pf_size = A.bsize[qn * A.L + tid];
+        }
+        if (off != ~0ull && A.fuse) {
+            // the unique ids into tab[0..U) (the set path compacted already)
+            if (in_regs) {
+                uint32_t e = wbase;
+#pragma unroll
+                for (int r = 0; r < kRegIds; ++r)
+                    if ((newm >> r) & 1u) tab[e++] = idr[r];
+                bar();
+            }
+            verify_list<DT>(A, tab, U, qrow, parts, off);
+        } else if (off != ~0ull && in_regs) {
+            unsigned long long e = off + wbase;
+#pragma unroll
+            for (int r = 0; r < kRegIds; ++r)
+                if ((newm >> r) & 1u) {
+                    A.cand[e] = (int32_t)idr[r];
+                    A.candq[e] = (int32_t)q;
+                    ++e;
+                }
+        } else if (off != ~0ull) {
+            // read the set back: wave w takes slots [w * cap / 4, (w + 1) * cap / 4)
+            const uint32_t seg = cap / (kBlock / 64);
+            const uint32_t s0 = (uint32_t)wave * seg;
+            uint32_t cnt = 0;
+            for (uint32_t i = s0 + lane; i < s0 + seg; i += 64)
+                cnt += (uint32_t)__popcll(__ballot(tab[i] != kEmpty));
+            if (lane == 0) scal[D_WT + wave] = cnt;
+            bar();
+            uint32_t tot = 0;
+            unsigned long long e = off + wave_base(scal, wave, &tot);
+            for (uint32_t i = s0 + lane; i < s0 + seg; i += 64) {
+                const uint32_t v = tab[i];
+                const unsigned long long m = __ballot(v != kEmpty);
+                if (v != kEmpty) {
+                    const unsigned long long p = e + (uint32_t)__popcll(m & lt_mask);
+                    A.cand[p] = (int32_t)v;
+                    A.candq[p] = (int32_t)q;
+                }
+                e += (uint32_t)__popcll(m);
+            }
+        }
+        bar();  // scal and the set are rewritten by the next item
+    }
+}
+
+qw_status launch_dedup(const DedupArgs &a, int grid, hipStream_t s)
+{
+    if (grid <= 0) return QW_OK;
+    const size_t lds = dedup_lds_bytes((int)a.cap_log2, a.global_tab, a.L,
+                                       a.dp * (a.dtype == QW_U8 ? 1 : 4));
+    if (a.dtype == QW_U8) {
+        if (a.global_tab) dedup_kernel<true, QW_U8><<<grid, kBlock, lds, s>>>(a);
+        else dedup_kernel<false, QW_U8><<<grid, kBlock, lds, s>>>(a);
+    } else {
+        if (a.global_tab) dedup_kernel<true, QW_F32><<<grid, kBlock, lds, s>>>(a);
+        else dedup_kernel<false, QW_F32><<<grid, kBlock, lds, s>>>(a);
+    }
+    QW_HIP(hipGetLastError());
+    return QW_OK;
+}
+
+int dedup_blocks_per_cu(size_t lds, int dtype)
+{
+    int nb = 0;
+    const void *fn = dtype == QW_U8 ? (const void *)dedup_kernel<false, QW_U8>
+                                    : (const void *)dedup_kernel<false, QW_F32>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        nb = 1;
+    }
+    return nb > 0 ? nb : 1;
+}
+
+}  // namespace qw

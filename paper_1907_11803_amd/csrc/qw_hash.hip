@@ -88,6 +88,13 @@ __global__ __launch_bounds__(kBlock) void hash_fp32_kernel(
     const int64_t row0 = (int64_t)blockIdx.x * 64;
     const int fb0 = f0 + blockIdx.y * 64;
     if (threadIdx.x < 64) xmax_s[threadIdx.x] = 0u;
+    float bf[4];  // the epilogue's per-function constants, loaded up front
+    double gf[4];
+    for (int j = 0; j < 4; ++j) {
+        const int f = min(fb0 + tx + 16 * j, f0 + nfun - 1);
+        bf[j] = b[f];
+        gf[j] = gbc[f];
+    }
     float acc[4][4];
     for (int i = 0; i < 4; ++i)
         for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
@@ -123,12 +130,12 @@ __global__ __launch_bounds__(kBlock) void hash_fp32_kernel(
         for (int j = 0; j < 4; ++j) {
             const int f = fb0 + tx + 16 * j;
             if (row >= m || f >= f0 + nfun) continue;
-            double y = ((double)acc[i][j] + (double)b[f]) / w;
+            double y = ((double)acc[i][j] + (double)bf[j]) / w;
             int32_t h;
-            if (outside_band(y, band(gbc[f], xm, w, y))) {
+            if (outside_band(y, band(gf[j], xm, w, y))) {
                 h = floor_to_i32(y);
             } else {
-                h = hash_exact<T>(x + row * dp, a + (int64_t)f * dp, d, b[f], w);
+                h = hash_exact<T>(x + row * dp, a + (int64_t)f * dp, d, bf[j], w);
                 ++nre;
             }
             out[row * out_ld + (f - f0)] = h;
@@ -155,24 +162,54 @@ __global__ __launch_bounds__(kBlock) void hash_mfma_f16_kernel(
     int64_t xrow = row0 + r;
     if (xrow >= m) xrow = m - 1;
     const uint8_t *xp = x + xrow * dp + kq;
+    // the epilogue's per-function constants, loaded up front (clamped to the
+    // launch's function range; out-of-range functions are never stored)
+    float bf[4];
+    double gf[4];
+#pragma unroll
+    for (int fb = 0; fb < 4; ++fb) {
+        const int f = min(fbase + fb * 16 + r, f0 + nfun - 1);
+        bf[fb] = b[f];
+        gf[fb] = gbc[f];
+    }
     floatx4_t acc_hi[4], acc_lo[4];
+#pragma unroll
     for (int fb = 0; fb < 4; ++fb) {
         acc_hi[fb] = floatx4_t{0.f, 0.f, 0.f, 0.f};
         acc_lo[fb] = floatx4_t{0.f, 0.f, 0.f, 0.f};
     }
     uint32_t xmax = 0;
+    // double-buffered K loop: step kb + 16 is loaded (unconditionally, the
+    // last step reloads itself) while step kb feeds the MFMAs
+    uint32_t xn;
+    half4_t ahn[4], aln[4];
+    auto load_step = [&](int kb) {
+        xn = *reinterpret_cast<const uint32_t *>(xp + kb);
+#pragma unroll
+        for (int fb = 0; fb < 4; ++fb) {
+            const int64_t f = fbase + fb * 16 + r;
+            ahn[fb] = *reinterpret_cast<const half4_t *>(ahi + f * dp + kb + kq);
+            aln[fb] = *reinterpret_cast<const half4_t *>(alo + f * dp + kb + kq);
+        }
+    };
+    load_step(0);
     for (int kb = 0; kb < dp; kb += 16) {
-        const uint32_t xv = *reinterpret_cast<const uint32_t *>(xp + kb);
+        const uint32_t xv = xn;
+        half4_t ah[4], al[4];
+#pragma unroll
+        for (int fb = 0; fb < 4; ++fb) {
+            ah[fb] = ahn[fb];
+            al[fb] = aln[fb];
+        }
+        load_step(kb + 16 < dp ? kb + 16 : kb);
         const uint32_t b0 = xv & 255u, b1 = (xv >> 8) & 255u, b2 = (xv >> 16) & 255u, b3 = xv >> 24;
         xmax = max(xmax, max(max(b0, b1), max(b2, b3)));
         const half4_t xh = {(_Float16)(float)b0, (_Float16)(float)b1, (_Float16)(float)b2,
                             (_Float16)(float)b3};
+#pragma unroll
         for (int fb = 0; fb < 4; ++fb) {
-            const int64_t f = fbase + fb * 16 + r;
-            const half4_t ah = *reinterpret_cast<const half4_t *>(ahi + f * dp + kb + kq);
-            const half4_t al = *reinterpret_cast<const half4_t *>(alo + f * dp + kb + kq);
-            acc_hi[fb] = __builtin_amdgcn_mfma_f32_16x16x16f16(xh, ah, acc_hi[fb], 0, 0, 0);
-            acc_lo[fb] = __builtin_amdgcn_mfma_f32_16x16x16f16(xh, al, acc_lo[fb], 0, 0, 0);
+            acc_hi[fb] = __builtin_amdgcn_mfma_f32_16x16x16f16(xh, ah[fb], acc_hi[fb], 0, 0, 0);
+            acc_lo[fb] = __builtin_amdgcn_mfma_f32_16x16x16f16(xh, al[fb], acc_lo[fb], 0, 0, 0);
         }
     }
     xmax = max(xmax, (uint32_t)__shfl_xor((int)xmax, 16));
@@ -180,18 +217,20 @@ __global__ __launch_bounds__(kBlock) void hash_mfma_f16_kernel(
     double xm[4];
     for (int j = 0; j < 4; ++j) xm[j] = (double)__shfl((int)xmax, (lane >> 4) * 4 + j);
     unsigned long long nre = 0;
+#pragma unroll
     for (int fb = 0; fb < 4; ++fb) {
         const int f = fbase + fb * 16 + r;
+#pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int64_t row = row0 + (lane >> 4) * 4 + j;
             if (row >= m || f >= f0 + nfun) continue;
-            const double s = (double)acc_hi[fb][j] + (double)acc_lo[fb][j];
-            const double y = (s + (double)b[f]) / w;
+            const double sum = (double)acc_hi[fb][j] + (double)acc_lo[fb][j];
+            const double y = (sum + (double)bf[fb]) / w;
             int32_t h;
-            if (outside_band(y, band(gbc[f], xm[j], w, y))) {
+            if (outside_band(y, band(gf[fb], xm[j], w, y))) {
                 h = floor_to_i32(y);
             } else {
-                h = hash_exact<uint8_t>(x + row * dp, a32 + (int64_t)f * dp, d, b[f], w);
+                h = hash_exact<uint8_t>(x + row * dp, a32 + (int64_t)f * dp, d, bf[fb], w);
                 ++nre;
             }
             out[row * out_ld + (f - f0)] = h;
@@ -216,19 +255,40 @@ __global__ __launch_bounds__(kBlock) void hash_mfma_f32_kernel(
     int64_t xrow = row0 + r;
     if (xrow >= m) xrow = m - 1;
     const float *xp = x + xrow * dp + kq;
+    float bf[4];  // the epilogue's per-function constants, loaded up front
+    double gf[4];
+#pragma unroll
+    for (int fb = 0; fb < 4; ++fb) {
+        const int f = min(fbase + fb * 16 + r, f0 + nfun - 1);
+        bf[fb] = b[f];
+        gf[fb] = gbc[f];
+    }
     floatx4_t acc[4];
+#pragma unroll
     for (int fb = 0; fb < 4; ++fb) acc[fb] = floatx4_t{0.f, 0.f, 0.f, 0.f};
     float xmax = 0.f;
+    // double-buffered K loop (the last step reloads itself)
+    float4 xn, an[4];
+    auto load_step = [&](int kb) {
+        xn = *reinterpret_cast<const float4 *>(xp + kb);
+#pragma unroll
+        for (int fb = 0; fb < 4; ++fb)
+            an[fb] = *reinterpret_cast<const float4 *>(a32 + (int64_t)(fbase + fb * 16 + r) * dp + kb + kq);
+    };
+    load_step(0);
     for (int kb = 0; kb < dp; kb += 16) {
-        const float4 xv = *reinterpret_cast<const float4 *>(xp + kb);
+        const float4 xv = xn;
+        float4 av[4];
+#pragma unroll
+        for (int fb = 0; fb < 4; ++fb) av[fb] = an[fb];
+        load_step(kb + 16 < dp ? kb + 16 : kb);
         xmax = fmaxf(xmax, fmaxf(fmaxf(fabsf(xv.x), fabsf(xv.y)), fmaxf(fabsf(xv.z), fabsf(xv.w))));
+#pragma unroll
         for (int fb = 0; fb < 4; ++fb) {
-            const int64_t f = fbase + fb * 16 + r;
-            const float4 av = *reinterpret_cast<const float4 *>(a32 + f * dp + kb + kq);
-            acc[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.x, av.x, acc[fb], 0, 0, 0);
-            acc[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.y, av.y, acc[fb], 0, 0, 0);
-            acc[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.z, av.z, acc[fb], 0, 0, 0);
-            acc[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.w, av.w, acc[fb], 0, 0, 0);
+            acc[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.x, av[fb].x, acc[fb], 0, 0, 0);
+            acc[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.y, av[fb].y, acc[fb], 0, 0, 0);
+            acc[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.z, av[fb].z, acc[fb], 0, 0, 0);
+            acc[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.w, av[fb].w, acc[fb], 0, 0, 0);
         }
     }
     xmax = fmaxf(xmax, __shfl_xor(xmax, 16));
@@ -236,17 +296,19 @@ __global__ __launch_bounds__(kBlock) void hash_mfma_f32_kernel(
     double xm[4];
     for (int j = 0; j < 4; ++j) xm[j] = (double)__shfl(xmax, (lane >> 4) * 4 + j);
     unsigned long long nre = 0;
+#pragma unroll
     for (int fb = 0; fb < 4; ++fb) {
         const int f = fbase + fb * 16 + r;
+#pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int64_t row = row0 + (lane >> 4) * 4 + j;
             if (row >= m || f >= f0 + nfun) continue;
-            const double y = ((double)acc[fb][j] + (double)b[f]) / w;
+            const double y = ((double)acc[fb][j] + (double)bf[fb]) / w;
             int32_t h;
-            if (outside_band(y, band(gbc[f], xm[j], w, y))) {
+            if (outside_band(y, band(gf[fb], xm[j], w, y))) {
                 h = floor_to_i32(y);
             } else {
-                h = hash_exact<float>(x + row * dp, a32 + (int64_t)f * dp, d, b[f], w);
+                h = hash_exact<float>(x + row * dp, a32 + (int64_t)f * dp, d, bf[fb], w);
                 ++nre;
             }
             out[row * out_ld + (f - f0)] = h;
@@ -301,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(
     const int32_t *__restrict__ hmin, const int32_t *__restrict__ hmax,
     const int32_t *__restrict__ shift, const TabEntry *__restrict__ tab,
     const long long *__restrict__ tab_off, const uint32_t *__restrict__ tab_mask,
-    uint32_t *__restrict__ bstart, uint32_t *__restrict__ bsize, uint32_t *__restrict__ qsum)
+    uint32_t *__restrict__ bstart, uint32_t *__restrict__ bsize, float *__restrict__ feats)
 {
     const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (idx >= Q * L) return;
@@ -337,18 +399,18 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(
     }
     bstart[idx] = st;
     bsize[idx] = sz;
-    if (sz) atomicAdd(&qsum[q], sz);
+    if (feats) feats[idx] = log1pf((float)sz);  // count-model input, f = log(1 + s)
 }
 
 qw_status launch_probe(const qw_index *ix, const int32_t *h, int64_t Q, uint32_t *bstart,
-                       uint32_t *bsize, uint32_t *qsum, hipStream_t s)
+                       uint32_t *bsize, float *feats, hipStream_t s)
 {
     if (Q <= 0) return QW_OK;
     const int64_t total = Q * ix->L;
     probe_kernel<<<(unsigned)ceil_div(total, kBlock), kBlock, 0, s>>>(
         h, Q, ix->L, ix->k, ix->hmin.as<int32_t>(), ix->hmax.as<int32_t>(),
         ix->shift.as<int32_t>(), ix->tab.as<TabEntry>(), ix->tab_off.as<long long>(),
-        ix->tab_mask.as<uint32_t>(), bstart, bsize, qsum);
+        ix->tab_mask.as<uint32_t>(), bstart, bsize, feats);
     QW_HIP(hipGetLastError());
     return QW_OK;
 }

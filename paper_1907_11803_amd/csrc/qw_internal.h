@@ -62,7 +62,7 @@ struct TabEntry {
 };
 
 struct Workspace {
-    DevBuf qpad, h, bstart, bsize, qsum, pred, feats, keys, keys2, vals, vals2, hist,
+    DevBuf qpad, h, bstart, bsize, pred, feats, keys, keys2, vals, vals2, hist,
         order, binoff, counters, ovf, gscratch, mlpout, scan;
     // flat pipeline
     DevBuf ucount, coff, flag, cand, candq, pkeys, fb;
@@ -77,6 +77,7 @@ struct Plan {
     int ncls = 2;       // LDS classes + 1 global class
     int dgrid[16] = {}; // dedup kernel, per class
     int cap_g = 20, grid_g = 1;
+    int fuse = 1;       // dedup verifies its own candidates (no pair list, no gather)
     int LC = 2048;      // select kernel list capacity (entries)
     int ggrid = 256;    // gather grid
     float eps = 0.f;    // FP32 distance bound (float data)
@@ -145,7 +146,7 @@ qw_status launch_hash(const qw_index *ix, const void *xpad, int64_t m, int32_t f
 
 // Probe every (query, layer): bstart/bsize [Q][L] (bsize 0 = miss); qsum[q] = sum of sizes.
 qw_status launch_probe(const qw_index *ix, const int32_t *h, int64_t Q, uint32_t *bstart,
-                       uint32_t *bsize, uint32_t *qsum, hipStream_t s);
+                       uint32_t *bsize, float *feats, hipStream_t s);
 
 // Generic fills.
 qw_status launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s);
@@ -206,7 +207,7 @@ int verify_per_iter(int dp, int dtype);
 int verify_blocks_per_cu(int dp, int dtype, size_t lds);
 
 // ---------------------------------------------------------------- scheduling
-qw_status launch_classify(int64_t Q, int32_t L, int64_t n, const uint32_t *qsum,
+qw_status launch_classify(int64_t Q, int32_t L, int64_t n,
                           const uint32_t *bstart, const uint32_t *bsize, const int32_t *exact,
                           const float *pred_log, float margin, int32_t force_max, int32_t cmin,
                           int32_t cfloor, int32_t cmax, int32_t ncls, int32_t group,
@@ -215,6 +216,8 @@ qw_status launch_classify(int64_t Q, int32_t L, int64_t n, const uint32_t *qsum,
 qw_status launch_segments(const unsigned long long *class_count, int32_t ncls,
                           unsigned long long *seg, hipStream_t s);
 qw_status launch_max_u32(const uint32_t *v, int64_t count, uint32_t *out, hipStream_t s);
+qw_status launch_max_bucket_sum(const uint32_t *bsize, int64_t Q, int32_t L, uint32_t *out,
+                                hipStream_t s);
 qw_status launch_probe_stats(const uint32_t *bsize, int64_t count, unsigned long long *hits,
                              unsigned long long *total, hipStream_t s);
 qw_status launch_gather_batch(const float *feats, const float *labels, const int32_t *perm,
@@ -229,7 +232,10 @@ qw_status build_index(const void *data, int64_t n, int32_t d, int32_t dtype, con
 // ---------------------------------------------------------------- flat pipeline
 struct DedupArgs {
     const int32_t *order;            // scheduled query order
-    const unsigned long long *seg;   // {begin, end} of this class in the order
+    const unsigned long long *seg;   // {begin, end} of every class in the order
+    int32_t cls_lo, cls_hi;          // this launch serves classes cls_lo..cls_hi
+    int32_t cap_base;                // class c uses a set of 2^(cap_base + c) slots
+    uint32_t *xwork;                 // [kXcd] work counters, one per XCD (zero on entry)
     const uint32_t *in_count;        // nullable: queue of overflowed queries served after the segment
     const int32_t *in_list;
     uint32_t *ovf_count;             // queue receiving this class's overflows
@@ -255,6 +261,12 @@ struct DedupArgs {
     uint32_t *ucount;                // |C(q)|
     unsigned long long *coff;        // offset of each query's list in cand
     uint32_t *flag;                  // 1 = answer q with the fallback
+    // fused mode: verify the unique candidates in place and write
+    // keys[coff + i] = (squared distance << 32) | id instead of cand/candq
+    int32_t fuse;
+    int32_t dp, dtype;
+    const void *data, *queries;
+    unsigned long long *keys;
 };
 
 struct GatherArgs {
@@ -280,8 +292,8 @@ struct SelectArgs {
     const void *data, *queries;
 };
 
-size_t dedup_lds_bytes(int cap_log2, int global_tab, int L);
-int dedup_blocks_per_cu(size_t lds);
+size_t dedup_lds_bytes(int cap_log2, int global_tab, int L, int row_bytes);
+int dedup_blocks_per_cu(size_t lds, int dtype);
 qw_status launch_dedup(const DedupArgs &a, int grid, hipStream_t s);
 int gather_blocks_per_cu(int dp, int dtype);
 qw_status launch_gather(const GatherArgs &a, int grid, hipStream_t s);

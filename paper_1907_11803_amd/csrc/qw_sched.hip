@@ -25,7 +25,7 @@ __device__ inline uint32_t mix32(uint64_t x)
 // <= 3/4).  Classes 0 .. ncls-2 are LDS classes (c = cmin + class), class
 // ncls-1 keeps its set in global memory.  Key = class << 16 | 16-bit group.
 __global__ __launch_bounds__(kBlock) void classify_kernel(
-    int64_t Q, int32_t L, int64_t n, const uint32_t *__restrict__ qsum,
+    int64_t Q, int32_t L, int64_t n,
     const uint32_t *__restrict__ bstart, const uint32_t *__restrict__ bsize,
     const int32_t *__restrict__ exact, const float *__restrict__ pred_log, float margin,
     int32_t force_max, int32_t cmin, int32_t cfloor, int32_t cmax, int32_t ncls, int32_t group,
@@ -40,7 +40,9 @@ __global__ __launch_bounds__(kBlock) void classify_kernel(
         // |C(q)| <= min(sum of the bucket sizes, n): the class of that bound
         // always holds the set; a predicted or exact count may pick a smaller
         // one, but never one below cfloor (no occupancy gained there)
-        const uint64_t bound = min((uint64_t)qsum[q], (uint64_t)n);
+        uint64_t tsum = 0;
+        for (int32_t l = 0; l < L; ++l) tsum += bsize[q * L + l];
+        const uint64_t bound = min(tsum, (uint64_t)n);
         uint64_t need = bound;
         if (exact) {
             need = min(need, (uint64_t)exact[q]);
@@ -73,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void classify_kernel(
         atomicAdd(&class_count[threadIdx.x], (unsigned long long)hist[threadIdx.x]);
 }
 
-qw_status launch_classify(int64_t Q, int32_t L, int64_t n, const uint32_t *qsum,
+qw_status launch_classify(int64_t Q, int32_t L, int64_t n,
                           const uint32_t *bstart, const uint32_t *bsize, const int32_t *exact,
                           const float *pred_log, float margin, int32_t force_max, int32_t cmin,
                           int32_t cfloor, int32_t cmax, int32_t ncls, int32_t group,
@@ -82,7 +84,7 @@ qw_status launch_classify(int64_t Q, int32_t L, int64_t n, const uint32_t *qsum,
 {
     if (Q <= 0) return QW_OK;
     int g = (int)std::min<int64_t>(1024, ceil_div(Q, kBlock));
-    classify_kernel<<<g, kBlock, 0, s>>>(Q, L, n, qsum, bstart, bsize, exact, pred_log, margin,
+    classify_kernel<<<g, kBlock, 0, s>>>(Q, L, n, bstart, bsize, exact, pred_log, margin,
                                          force_max, cmin, cfloor, cmax, ncls, group, keys, vals,
                                          class_count);
     QW_HIP(hipGetLastError());
@@ -125,6 +127,31 @@ qw_status launch_max_u32(const uint32_t *v, int64_t count, uint32_t *out, hipStr
     if (count <= 0) return QW_OK;
     int g = (int)std::min<int64_t>(1024, ceil_div(count, kBlock));
     max_u32_kernel<<<g, kBlock, 0, s>>>(v, count, out);
+    QW_HIP(hipGetLastError());
+    return QW_OK;
+}
+
+// max over queries of sum_l s_{q,l} (clamped to 2^32 - 1), one atomic per wave
+__global__ __launch_bounds__(kBlock) void max_bucket_sum_kernel(const uint32_t *__restrict__ bsize,
+                                                                int64_t Q, int32_t L, uint32_t *out)
+{
+    uint32_t m = 0;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < Q;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t t = 0;
+        for (int32_t l = 0; l < L; ++l) t += bsize[q * L + l];
+        m = max(m, (uint32_t)min(t, (uint64_t)0xFFFFFFFFu));
+    }
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+    if ((threadIdx.x & 63) == 0 && m) atomicMax(out, m);
+}
+
+qw_status launch_max_bucket_sum(const uint32_t *bsize, int64_t Q, int32_t L, uint32_t *out,
+                                hipStream_t s)
+{
+    if (Q <= 0) return QW_OK;
+    const int g = (int)std::min<int64_t>(64, ceil_div(Q, kBlock));
+    max_bucket_sum_kernel<<<g, kBlock, 0, s>>>(bsize, Q, L, out);
     QW_HIP(hipGetLastError());
     return QW_OK;
 }
