@@ -234,6 +234,8 @@ qw_status build_index(const void *data, int64_t n, int32_t d, int32_t dtype, con
         ix->cus = v;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device) == hipSuccess && v > 0)
         ix->lds_max = (size_t)v;
+    QW_HIP(hipStreamCreateWithFlags(&ix->side, hipStreamNonBlocking));
+    for (auto &e : ix->fork) QW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     ix->n = n;
     ix->d = d;
     ix->dp = (int32_t)((d + 15) / 16 * 16);

@@ -24,8 +24,9 @@ enum {
 // u32: overflow-queue lengths per class (queue i holds queries that overflowed
 // class i-1), fallback queue, misc, then kXcd work counters per class
 enum { W_WORK = 0 /* .. 15: unused */, W_QCNT = 16 /* .. 32 */, W_SIMPLE = 33, W_MAX = 34,
-       W_DUMMY = 35, W_FB = 44, W_FBWORK = 45, W_XWORK = 48,
-       kC32 = W_XWORK + kXcd * kMaxClasses };
+       W_DUMMY = 35, W_QMERGED = 36, W_FB = 44, W_FBWORK = 45, W_XWORK = 48,
+       kC32 = W_XWORK + kXcd * (kMaxClasses + 1) };
+constexpr int kQueueMerged = kMaxClasses + 1;  // overflow queue of the merged launch
 constexpr int64_t kCandPerQuery = 4096;  // pair space reserved per query (beyond: fallback)
 
 
@@ -121,7 +122,7 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan)
     QW_TRY(w.keys2.ensure(sizeof(unsigned long long) * q));
     QW_TRY(w.vals.ensure(sizeof(int32_t) * q));
     QW_TRY(w.vals2.ensure(sizeof(int32_t) * q));
-    QW_TRY(w.ovf.ensure(sizeof(int32_t) * q * (kMaxClasses + 1)));  // one queue per class
+    QW_TRY(w.ovf.ensure(sizeof(int32_t) * q * (kQueueMerged + 1)));  // one queue per class + merged
     QW_TRY(w.binoff.ensure(sizeof(unsigned long long) * 2 * kMaxClasses));
     QW_TRY(w.counters.ensure(sizeof(unsigned long long) * kC64 + sizeof(uint32_t) * kC32));
     QW_TRY(w.hist.ensure(radix_sort_scratch_bytes(q)));
@@ -275,22 +276,27 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     // overflowed the previous class; its own overflows go to the next queue.
     // One launch serves every LDS class up to cfloor (their sets cost no
     // occupancy, so the launch is sized for the largest; queries go largest
-    // first); the larger classes follow one launch each, each serving its
-    // segment and then the queue of queries that overflowed the launch before.
+    // first).  The larger classes run beside it on the side stream, one launch
+    // each, each serving its segment and then the queue of queries that
+    // overflowed the class before it; queries that overflow the merged launch
+    // are served afterwards by the global class.
     auto dedup_classes = [&](const int32_t *order, int count_only) -> qw_status {
-        auto launch_range = [&](int lo, int hi) -> qw_status {
+        auto launch_range = [&](int lo, int hi, const int32_t *in_list, const uint32_t *in_count,
+                                int32_t *ovf_list, uint32_t *ovf_count, int slot, int queue_only,
+                                hipStream_t st) -> qw_status {
             DedupArgs a;
             std::memset(&a, 0, sizeof(a));
             a.order = order;
             a.seg = seg;
             a.cls_lo = lo;
             a.cls_hi = hi;
+            a.queue_only = queue_only;
             a.cap_base = kCmin;
-            a.xwork = c32(ix) + W_XWORK + kXcd * hi;
-            a.in_list = lo > 0 ? queues + (int64_t)lo * Q : nullptr;
-            a.in_count = lo > 0 ? c32(ix) + W_QCNT + lo : nullptr;
-            a.ovf_list = queues + (int64_t)(hi + 1) * Q;
-            a.ovf_count = c32(ix) + W_QCNT + hi + 1;
+            a.xwork = c32(ix) + W_XWORK + kXcd * slot;
+            a.in_list = in_list;
+            a.in_count = in_count;
+            a.ovf_list = ovf_list;
+            a.ovf_count = ovf_count;
             a.bstart = w.bstart.as<uint32_t>();
             a.bsize = w.bsize.as<uint32_t>();
             a.ids = ix->ids.as<int32_t>();
@@ -320,11 +326,26 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
                 a.cap_log2 = (uint32_t)(kCmin + hi);  // LDS size; also the queue's class
                 a.limit = 0xFFFFFFFFu;                 // each set's own 3/4 bound
             }
-            return launch_dedup(a, plan.dgrid[hi], s);
+            return launch_dedup(a, plan.dgrid[hi], st);
         };
         const int merged = std::max(0, std::min(plan.cfloor - kCmin, plan.ncls - 2));
-        QW_TRY(launch_range(0, merged));
-        for (int i = merged + 1; i < plan.ncls; ++i) QW_TRY(launch_range(i, i));
+        const int glob = plan.ncls - 1;
+        QW_HIP(hipEventRecord(ix->fork[0], s));
+        QW_HIP(hipStreamWaitEvent(ix->side, ix->fork[0], 0));
+        for (int i = merged + 1; i < plan.ncls; ++i) {
+            const bool first = i == merged + 1;
+            QW_TRY(launch_range(i, i, first ? nullptr : queues + (int64_t)i * Q,
+                                first ? nullptr : c32(ix) + W_QCNT + i,
+                                queues + (int64_t)(i + 1) * Q, c32(ix) + W_QCNT + i + 1, i, 0,
+                                ix->side));
+        }
+        QW_TRY(launch_range(0, merged, nullptr, nullptr, queues + (int64_t)kQueueMerged * Q,
+                            c32(ix) + W_QMERGED, merged, 0, s));
+        QW_HIP(hipEventRecord(ix->fork[1], ix->side));
+        QW_HIP(hipStreamWaitEvent(s, ix->fork[1], 0));
+        // overflow of the merged launch (usually none): the global class, queue only
+        QW_TRY(launch_range(glob, glob, queues + (int64_t)kQueueMerged * Q, c32(ix) + W_QMERGED,
+                            queues + (int64_t)(glob + 1) * Q, c32(ix) + W_DUMMY, kMaxClasses, 1, s));
         return QW_OK;
     };
     const int32_t *order = nullptr;
@@ -335,7 +356,8 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
         QW_TRY(dedup_classes(order, 1));
         QW_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(ccount), 0u, 2 * kMaxClasses, s));
         QW_TRY(launch_fill_u32(c32(ix) + W_WORK, 0u, W_SIMPLE - W_WORK, s));
-        QW_TRY(launch_fill_u32(c32(ix) + W_XWORK, 0u, kXcd * kMaxClasses, s));
+        QW_TRY(launch_fill_u32(c32(ix) + W_XWORK, 0u, kXcd * (kMaxClasses + 1), s));
+        QW_TRY(launch_fill_u32(c32(ix) + W_QMERGED, 0u, 1, s));
         exact = reinterpret_cast<const int32_t *>(w.ucount.p);
     } else if (learned) {
         QW_TRY(launch_mlp_predict_bf16(ix->mlp_dev.as<float>(), ix->L, w.feats.as<float>(), Q,
@@ -422,8 +444,10 @@ qw_status fill_stats(qw_index *ix, int64_t Q, hipStream_t s, qw_stats *st, hipEv
     st->cand_total = (int64_t)h64[C_CANDTOT];
     st->cand_unique = (int64_t)h64[C_UNIQUE];
     st->overflow = 0;
-    if (fast)
+    if (fast) {
         for (int i = 1; i <= kMaxClasses; ++i) st->overflow += (int64_t)h32[W_QCNT + i];
+        st->overflow += (int64_t)h32[W_QMERGED];
+    }
     st->fallback = fast ? (int64_t)h32[W_FB] : 0;
     if (fast)
         for (int i = 0; i < 8; ++i) st->bins[i] = (int64_t)h64[C_CLASS + i];
@@ -518,7 +542,7 @@ void qw_free_index(qw_index *ix)
     drop_graphs(ix);
     if (ix->ev_init)
         for (auto &e : ix->ev) (void)hipEventDestroy(e);
-    delete ix;
+    delete ix;  // the destructor releases the side stream and its events
 }
 
 qw_status qw_get_index_info(const qw_index *ix, qw_index_info *info)

@@ -184,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void dedup_kernel(DedupArgs A)
     unsigned long long *soff = reinterpret_cast<unsigned long long *>(&scal[D_OFF]);
     const int64_t sbeg = (int64_t)A.seg[2 * A.cls_lo];
     const int64_t send = (int64_t)A.seg[2 * A.cls_hi + 1];
-    const int64_t nseg = send - sbeg;
+    const int64_t nseg = A.queue_only ? 0 : send - sbeg;
     const int64_t nin = A.in_count ? (int64_t)*A.in_count : 0;
     const int64_t nall = nseg + nin;
     const int xcd = blockIdx.x % kXcd;

@@ -129,6 +129,20 @@ struct qw_index {
     std::map<int, qw::Plan> plans;  // by K
     hipEvent_t ev[8] = {};
     bool ev_init = false;
+    // side stream (default priority) and fork/join events: the larger size
+    // classes run beside the merged launch
+    hipStream_t side = nullptr;
+    hipEvent_t fork[2] = {};
+
+    qw_index() = default;
+    qw_index(const qw_index &) = delete;
+    qw_index &operator=(const qw_index &) = delete;
+    ~qw_index()
+    {
+        for (auto &e : fork)
+            if (e) (void)hipEventDestroy(e);
+        if (side) (void)hipStreamDestroy(side);
+    }
 };
 
 namespace qw {
@@ -234,6 +248,7 @@ struct DedupArgs {
     const int32_t *order;            // scheduled query order
     const unsigned long long *seg;   // {begin, end} of every class in the order
     int32_t cls_lo, cls_hi;          // this launch serves classes cls_lo..cls_hi
+    int32_t queue_only;              // serve only the in_list queue (no segment)
     int32_t cap_base;                // class c uses a set of 2^(cap_base + c) slots
     uint32_t *xwork;                 // [kXcd] work counters, one per XCD (zero on entry)
     const uint32_t *in_count;        // nullable: queue of overflowed queries served after the segment
