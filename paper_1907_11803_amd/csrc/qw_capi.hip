@@ -313,6 +313,10 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
             a.dtype = ix->dtype;
             a.data = ix->data.p;
             a.queries = w.qpad.p;
+            {
+                const uint64_t rb = (uint64_t)ix->dp * (ix->dtype == QW_U8 ? 1 : 4);
+                a.addr32 = (uint64_t)ix->n * rb < (1ull << 32) && ix->n < (1ll << 24) ? 1 : 0;
+            }
             a.keys = w.pkeys.as<unsigned long long>();
             a.ucount = w.ucount.as<uint32_t>();
             a.coff = w.coff.as<unsigned long long>();

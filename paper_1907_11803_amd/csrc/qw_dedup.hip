@@ -42,11 +42,112 @@ __device__ inline uint32_t wave_base(const uint32_t *scal, int wave, uint32_t *t
     return b;
 }
 
+// verify_list for rows of at most 64 parts.  A lane holds two consecutive
+// parts of a row (G = pow2 >= parts / 2 lanes per row), UN2 rows per group
+// per step; the loop is unrolled twice so the two steps in flight alternate
+// between register sets.  Row addresses: a 24-bit multiply into a 32-bit
+// offset from the uniform data pointer when the data allows (A.addr32).
+template <int DT>
+__device__ inline void verify_small(const DedupArgs &A, const uint32_t *list, uint32_t U,
+                                    const uint4 *qrow, int parts, unsigned long long *keys,
+                                    uint32_t qq)
+{
+    constexpr int UN2 = 2;
+    const int tid = threadIdx.x;
+    const int pl = (parts + 1) / 2;  // lanes' worth of part pairs
+    int G = 1;
+    while (G < pl) G <<= 1;
+    const int NG = kBlock / G;
+    const uint32_t PI = (uint32_t)(NG * UN2);
+    const int grp = tid / G, j = tid % G;
+    const int p0 = 2 * j, p1 = 2 * j + 1;
+    const bool in0 = p0 < parts, in1 = p1 < parts;
+    const int c0 = in0 ? p0 : parts - 1, c1 = in1 ? p1 : parts - 1;
+    const uint4 q0 = qrow[c0], q1 = qrow[c1];
+    const int row_bytes = parts * 16;
+    const unsigned char *dbase = reinterpret_cast<const unsigned char *>(A.data);
+    auto row_part = [&](uint32_t id, int c) -> uint4 {
+        if (A.addr32)
+            return *reinterpret_cast<const uint4 *>(dbase + (uint32_t)(__umul24(id, (uint32_t)row_bytes) + (uint32_t)c * 16u));
+        return reinterpret_cast<const uint4 *>(A.data)[(int64_t)id * parts + c];
+    };
+    struct Step {
+        uint32_t id[UN2];
+        uint4 x0[UN2], x1[UN2];
+    };
+    auto load = [&](Step &st, uint32_t base) {
+#pragma unroll
+        for (int u = 0; u < UN2; ++u) {
+            const uint32_t i = base + (uint32_t)(grp + NG * u);
+            st.id[u] = list[i < U ? i : 0u];
+        }
+#pragma unroll
+        for (int u = 0; u < UN2; ++u) {
+            st.x0[u] = row_part(st.id[u], c0);
+            st.x1[u] = row_part(st.id[u], c1);
+        }
+    };
+    auto compute = [&](const Step &st, uint32_t base) {
+        uint32_t accu[UN2];
+        float accf[UN2];
+#pragma unroll
+        for (int u = 0; u < UN2; ++u) {
+            accu[u] = 0;
+            accf[u] = 0.f;
+            if (DT == QW_U8) {
+                const uint32_t a0 = part_dot_u8(st.x0[u], st.x0[u], 0u) - 2u * part_dot_u8(st.x0[u], q0, 0u);
+                const uint32_t a1 = part_dot_u8(st.x1[u], st.x1[u], 0u) - 2u * part_dot_u8(st.x1[u], q1, 0u);
+                accu[u] = (in0 ? a0 : 0u) + (in1 ? a1 : 0u);
+            } else {
+                uint32_t du = 0;
+                float f0 = 0.f, f1 = 0.f;
+                part_dist<DT>(st.x0[u], q0, du, f0);
+                part_dist<DT>(st.x1[u], q1, du, f1);
+                accf[u] = (in0 ? f0 : 0.f) + (in1 ? f1 : 0.f);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UN2; ++u)
+            for (int o = G >> 1; o > 0; o >>= 1) {
+                if (DT == QW_U8)
+                    accu[u] += (uint32_t)__shfl_xor((int)accu[u], o);
+                else
+                    accf[u] += __shfl_xor(accf[u], o);
+            }
+        if (j == 0)
+#pragma unroll
+            for (int u = 0; u < UN2; ++u) {
+                const uint32_t i = base + (uint32_t)(grp + NG * u);
+                if (i < U) {
+                    const uint32_t hi = DT == QW_U8 ? accu[u] + qq : __float_as_uint(accf[u]);
+                    keys[i] = ((unsigned long long)hi << 32) | st.id[u];
+                }
+            }
+    };
+    if (U == 0) return;
+    Step sa, sb;
+    load(sa, 0);
+    for (uint32_t base = 0; base < U; base += 2 * PI) {
+        const uint32_t b1 = base + PI;
+        load(sb, b1 < U ? b1 : base);  // a step past the end reloads a valid one
+        __builtin_amdgcn_sched_barrier(0);
+        compute(sa, base);
+        if (b1 >= U) break;
+        const uint32_t b2 = b1 + PI;
+        load(sa, b2 < U ? b2 : b1);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(sb, b1);
+    }
+}
+
 // Whole workgroup: key[off + i] = (squared distance << 32) | id for the U ids
 // list[0..U) against the query row qrow (parts 16-byte parts, in LDS).  A
 // group of G lanes (a power of two >= parts, at most 64) holds one row, P
-// parts per lane; UN rows per group per step.  Rows of one part per lane:
-// the next step's rows are loaded before the current step is reduced, so two
+// parts per lane; UN rows per group per step.  uint8 distances are
+// sum over parts of (|x|^2 - 2 x.q) plus |q|^2 taken once per query (exact in
+// wrapping uint32 arithmetic, d * 255^2 < 2^31); float distances sum FP32
+// squares of differences.  Rows of one part per lane: the
+// next step's rows are loaded before the current step is reduced, so two
 // steps are in flight.  No barriers.
 template <int DT>
 __device__ inline void verify_list(const DedupArgs &A, const uint32_t *list, uint32_t U,
@@ -62,6 +163,18 @@ __device__ inline void verify_list(const DedupArgs &A, const uint32_t *list, uin
     const int grp = tid / G, j = tid % G;
     const uint4 *drows = reinterpret_cast<const uint4 *>(A.data);
     unsigned long long *keys = A.keys + off;
+    // |q|^2 (uint8), the same in every group
+    uint32_t qq = 0;
+    if (DT == QW_U8) {
+        for (int p = 0; p < P; ++p) {
+            const int part = j + G * p;
+            if (part < parts) {
+                const uint4 v = qrow[part];
+                qq = part_dot_u8(v, v, qq);
+            }
+        }
+        for (int o = G >> 1; o > 0; o >>= 1) qq += (uint32_t)__shfl_xor((int)qq, o);
+    }
     auto finish = [&](uint32_t base, const uint32_t (&id)[UN], uint32_t (&accu)[UN],
                       float (&accf)[UN]) {
 #pragma unroll
@@ -77,49 +190,13 @@ __device__ inline void verify_list(const DedupArgs &A, const uint32_t *list, uin
             for (int u = 0; u < UN; ++u) {
                 const uint32_t i = base + (uint32_t)(grp + NG * u);
                 if (i < U) {
-                    const uint32_t hi = DT == QW_U8 ? accu[u] : __float_as_uint(accf[u]);
+                    const uint32_t hi = DT == QW_U8 ? accu[u] + qq : __float_as_uint(accf[u]);
                     keys[i] = ((unsigned long long)hi << 32) | id[u];
                 }
             }
     };
     if (P == 1) {
-        const bool jin = j < parts;
-        const int pc = jin ? j : parts - 1;
-        const uint4 qv = qrow[pc];
-        uint32_t nid[UN];
-        uint4 nx[UN];
-        auto load_step = [&](uint32_t base) {
-#pragma unroll
-            for (int u = 0; u < UN; ++u) {
-                const uint32_t i = base + (uint32_t)(grp + NG * u);
-                nid[u] = list[i < U ? i : 0u];
-            }
-#pragma unroll
-            for (int u = 0; u < UN; ++u) nx[u] = drows[(int64_t)nid[u] * parts + pc];
-        };
-        if (U) load_step(0);
-        for (uint32_t base = 0; base < U; base += PI) {
-            uint32_t id[UN];
-            uint4 xv[UN];
-#pragma unroll
-            for (int u = 0; u < UN; ++u) {
-                id[u] = nid[u];
-                xv[u] = nx[u];
-            }
-            load_step(base + PI < U ? base + PI : base);  // the last step reloads itself
-            __builtin_amdgcn_sched_barrier(0);  // keep the next rows ahead of the waits below
-            uint32_t accu[UN];
-            float accf[UN];
-#pragma unroll
-            for (int u = 0; u < UN; ++u) {
-                accu[u] = 0;
-                accf[u] = 0.f;
-                part_dist<DT>(xv[u], qv, accu[u], accf[u]);
-                accu[u] = jin ? accu[u] : 0u;
-                accf[u] = jin ? accf[u] : 0.f;
-            }
-            finish(base, id, accu, accf);
-        }
+        verify_small<DT>(A, list, U, qrow, parts, keys, qq);
         return;
     }
     for (uint32_t base = 0; base < U; base += PI) {
@@ -147,7 +224,8 @@ __device__ inline void verify_list(const DedupArgs &A, const uint32_t *list, uin
             for (int u = 0; u < UN; ++u) {
                 uint32_t au = 0;
                 float af = 0.f;
-                part_dist<DT>(xv[u], qv, au, af);
+                if (DT == QW_U8) au = part_dot_u8(xv[u], xv[u], 0u) - 2u * part_dot_u8(xv[u], qv, 0u);
+                else part_dist<DT>(xv[u], qv, au, af);
                 accu[u] += part < parts ? au : 0u;
                 accf[u] += part < parts ? af : 0.f;
             }

@@ -41,4 +41,15 @@ __device__ inline void part_dist(const uint4 xw, const uint4 qw, uint32_t &accu,
     }
 }
 
+// x.q over one 16-byte part of uint8 rows (the cross term of |x|^2 + |q|^2 -
+// 2 x.q; the norms come from elsewhere)
+__device__ inline uint32_t part_dot_u8(const uint4 xw, const uint4 qw, uint32_t acc)
+{
+    acc = __builtin_amdgcn_udot4(xw.x, qw.x, acc, false);
+    acc = __builtin_amdgcn_udot4(xw.y, qw.y, acc, false);
+    acc = __builtin_amdgcn_udot4(xw.z, qw.z, acc, false);
+    acc = __builtin_amdgcn_udot4(xw.w, qw.w, acc, false);
+    return acc;
+}
+
 }  // namespace qw

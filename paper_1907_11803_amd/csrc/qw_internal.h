@@ -280,6 +280,7 @@ struct DedupArgs {
     // keys[coff + i] = (squared distance << 32) | id instead of cand/candq
     int32_t fuse;
     int32_t dp, dtype;
+    int32_t addr32;                  // n * row bytes < 2^32 and n < 2^24: 32-bit row offsets
     const void *data, *queries;
     unsigned long long *keys;
 };
