@@ -18,8 +18,9 @@ constexpr int kMaxClasses = 16;
 
 // counters buffer: u64 [kC64] then u32 [kC32]
 enum {
-    C_RECOMP = 0, C_UNIQUE, C_PROBEHIT, C_CANDTOT, C_CLASS /* .. C_CLASS+15 */,
-    C_ALLOC = 20 /* .. +kXcd-1 */, C_FAIL = 28 /* .. +kXcd-1 */, C_SPARE = 36, kC64 = 40
+    C_UNUSED = 0, C_UNIQUE, C_PROBEHIT, C_CANDTOT, C_CLASS /* .. C_CLASS+15 */,
+    C_ALLOC = 20 /* .. +kXcd-1 */, C_FAIL = 28 /* .. +kXcd-1 */, C_SPARE = 36,
+    C_RECOMP = 40 /* .. +kRecompSlots-1 */, kC64 = C_RECOMP + kRecompSlots
 };
 // u32: overflow-queue lengths per class (queue i holds queries that overflowed
 // class i-1), fallback queue, misc, then kXcd work counters per class
@@ -442,7 +443,7 @@ qw_status fill_stats(qw_index *ix, int64_t Q, hipStream_t s, qw_stats *st, hipEv
     QW_HIP(hipMemcpyAsync(h32, c32(ix), sizeof(h32), hipMemcpyDeviceToHost, s));
     QW_HIP(hipStreamSynchronize(s));
     st->projections = Q * ix->nf;
-    st->recomputed = (int64_t)h64[C_RECOMP];
+    for (int i = 0; i < kRecompSlots; ++i) st->recomputed += (int64_t)h64[C_RECOMP + i];
     st->recompute_frac = (double)st->recomputed / (double)st->projections;
     st->probes_hit = (int64_t)h64[C_PROBEHIT];
     st->cand_total = (int64_t)h64[C_CANDTOT];
@@ -671,10 +672,12 @@ qw_status qw_hash(qw_index *ix, const void *x, int64_t m, int32_t form, void *st
     QW_TRY(launch_pad_rows(x, m, ix->d, ix->dp, ix->dtype, ix->ws.qpad.p, s));
     QW_TRY(launch_hash(ix, ix->ws.qpad.p, m, 0, ix->nf, form, out_h, ix->nf, c64(ix) + C_RECOMP, s));
     if (out_recomputed) {
-        unsigned long long r = 0;
-        QW_HIP(hipMemcpyAsync(&r, c64(ix) + C_RECOMP, sizeof(r), hipMemcpyDeviceToHost, s));
+        unsigned long long r[kRecompSlots];
+        QW_HIP(hipMemcpyAsync(r, c64(ix) + C_RECOMP, sizeof(r), hipMemcpyDeviceToHost, s));
         QW_HIP(hipStreamSynchronize(s));
-        *out_recomputed = (int64_t)r;
+        int64_t tot = 0;
+        for (int i = 0; i < kRecompSlots; ++i) tot += (int64_t)r[i];
+        *out_recomputed = tot;
     }
     return QW_OK;
 }

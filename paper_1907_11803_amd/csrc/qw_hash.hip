@@ -16,7 +16,9 @@ typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
 // FP64, index order, correctly rounded steps: the reference sequence.  Rows
 // are padded to a multiple of 16 elements, so the inputs are read 16 at a time
-// with 16-byte loads; the summation still runs i = 0..d-1 in order.
+// with 16-byte loads; the summation still runs i = 0..d-1 in order.  Each
+// product of an FP32 parameter and a uint8 or FP32 input is exact in FP64, so
+// a multiply-add the compiler fuses rounds exactly like the separate steps.
 __device__ inline void load16(const uint8_t *p, float *v)
 {
     const uint4 w = *reinterpret_cast<const uint4 *>(p);
@@ -37,38 +39,109 @@ __device__ inline void load16(const float *p, float *v)
     }
 }
 
-template <typename T>
-__device__ __noinline__ int32_t hash_exact(const T *__restrict__ xrow,
-                                           const float *__restrict__ arow, int32_t d, float bf,
-                                           double w)
+// Raw 16-element pieces, converted to FP32 values when used.
+__device__ inline void piece_load(const uint8_t *p, uint4 (&r)[1]) { r[0] = *reinterpret_cast<const uint4 *>(p); }
+__device__ inline void piece_load(const float *p, float4 (&r)[4])
 {
-    double acc = 0.0;
-    for (int32_t i0 = 0; i0 < d; i0 += 16) {
-        float xv[16], av[16];
-        load16(xrow + i0, xv);
-        load16(arow + i0, av);
-        const int32_t lim = d - i0 < 16 ? d - i0 : 16;
 #pragma unroll
-        for (int t = 0; t < 16; ++t)
-            if (t < lim) acc = __dadd_rn(acc, __dmul_rn((double)av[t], (double)xv[t]));
+    for (int t = 0; t < 4; ++t) r[t] = reinterpret_cast<const float4 *>(p)[t];
+}
+__device__ inline float piece_value(const uint4 (&r)[1], int t)
+{
+    const uint32_t wd = t < 4 ? r[0].x : t < 8 ? r[0].y : t < 12 ? r[0].z : r[0].w;
+    return (float)((wd >> (8 * (t & 3))) & 255u);
+}
+__device__ inline float piece_value(const float4 (&r)[4], int t)
+{
+    const float4 v = r[t >> 2];
+    return (t & 3) == 0 ? v.x : (t & 3) == 1 ? v.y : (t & 3) == 2 ? v.z : v.w;
+}
+
+template <typename T> struct Piece;
+template <> struct Piece<uint8_t> { typedef uint4 V[1]; static constexpr int B = 4; };
+template <> struct Piece<float> { typedef float4 V[4]; static constexpr int B = 2; };
+
+template <typename T>
+__device__ inline int32_t hash_exact(const T *__restrict__ xrow, const float *__restrict__ arow,
+                                     int32_t d, float bf, double w)
+{
+    // B pieces of 16 elements are loaded together (one memory latency per
+    // 16 B terms); a piece past the row end re-reads the last piece and
+    // contributes nothing
+    constexpr int B = Piece<T>::B;
+    const int32_t last = (d - 1) & ~15;
+    double acc = 0.0;
+    for (int32_t i0 = 0; i0 < d; i0 += 16 * B) {
+        typename Piece<T>::V xr[B];
+        float4 ar[B][4];
+#pragma unroll
+        for (int p = 0; p < B; ++p) {
+            const int32_t o = min(i0 + 16 * p, last);
+            piece_load(xrow + o, xr[p]);
+            piece_load(arow + o, ar[p]);
+        }
+        __builtin_amdgcn_sched_barrier(0);  // all loads of the block in flight together
+#pragma unroll
+        for (int p = 0; p < B; ++p)
+#pragma unroll
+            for (int t = 0; t < 16; ++t)
+                if (i0 + 16 * p + t < d)
+                    acc = __dadd_rn(acc, __dmul_rn((double)piece_value(ar[p], t),
+                                                   (double)piece_value(xr[p], t)));
     }
     double t = __dadd_rn(acc, (double)bf);
     double y = __ddiv_rn(t, w);
     return floor_to_i32(y);
 }
 
-// Accept floor(y) when y is farther than beta from every integer.
-__device__ inline bool outside_band(double y, double beta)
+// Guard-band test, evaluated in FP32.  s is the approximate projection a.v
+// (before + b), bf = b, iw = 1/w rounded to FP32, and cw * xm bounds
+// |s - FP64 index-order a.v| / w, plus the reference's own FP64 rounding.
+// y = (s + bf) * iw is accepted when its distance to the nearest integer
+// exceeds that bound plus the error of evaluating y and the distance in FP32
+// (u = 2^-24): the sum s (when it adds two accumulators) and s + bf each
+// round once (<= u |s| / w and u |y|), iw and the product add <= 2u |y|, and
+// the distances round by at most 2^-24 (they are exact for |y| >= 1).  The
+// total is inflated by 2^-20 to cover the rounding of the bound itself.  For
+// |y| >= 2^22 the bound exceeds every distance, so nothing out of FP32's
+// integer range is accepted.
+__device__ inline bool accept_fp32(float s, float bf, float iw, float cwx, int32_t &h)
 {
-    double fl = floor(y);
-    double fr = y - fl;  // exact for doubles
-    double dist = fr < 1.0 - fr ? fr : 1.0 - fr;
+    const float y = (s + bf) * iw;
+    const float fl = floorf(y);
+    const float dist = fminf(y - fl, (fl + 1.0f) - y);
+    const float beta =
+        (cwx + 0x1p-22f * (fabsf(y) + fabsf(s) * iw) + 0x1p-23f + 0x1p-40f) * (1.0f + 0x1p-20f);
+    h = (int32_t)fl;
     return dist > beta;
 }
 
-__device__ inline double band(double coef, double xmax, double w, double y)
+// Per-function band coefficient scaled by 1/w for accept_fp32 (rounded, then
+// inflated past the rounding).
+__device__ inline float band_coef(double coef, double w)
 {
-    return coef * xmax / w + 0x1p-50 * (fabs(y) + 1.0) + 0x1p-40;
+    return (float)(coef / w) * (1.0f + 0x1p-20f);
+}
+
+// Recomputes the outputs a lane marked as inside the guard band.  The lanes
+// of a wave recompute their marked outputs side by side, so a wave waits for
+// the lane with the most marks rather than once per marked output of any lane.
+template <typename T>
+__device__ inline void recompute_marked(uint32_t pend, const T *__restrict__ x, int64_t row0,
+                                        int32_t rstride, int32_t dp, int32_t d, const float *__restrict__ a32,
+                                        const float *__restrict__ b, int fbase, int32_t f0,
+                                        double w, int32_t *__restrict__ out, int32_t out_ld,
+                                        unsigned long long &nre)
+{
+    // bit fb * 4 + j: row row0 + j * rstride, function fbase + 16 fb
+    while (pend) {
+        const int o = __ffs(pend) - 1;
+        pend &= pend - 1u;
+        const int64_t row = row0 + (int64_t)(o & 3) * rstride;
+        const int f = fbase + (o >> 2) * 16;
+        out[row * out_ld + (f - f0)] = hash_exact<T>(x + row * dp, a32 + (int64_t)f * dp, d, b[f], w);
+        ++nre;
+    }
 }
 
 // ---------------------------------------------------------------- FP32 VALU form
@@ -88,13 +161,13 @@ __global__ __launch_bounds__(kBlock) void hash_fp32_kernel(
     const int64_t row0 = (int64_t)blockIdx.x * 64;
     const int fb0 = f0 + blockIdx.y * 64;
     if (threadIdx.x < 64) xmax_s[threadIdx.x] = 0u;
-    float bf[4];  // the epilogue's per-function constants, loaded up front
-    double gf[4];
+    float bf[4], cw[4];  // the epilogue's per-function constants, loaded up front
     for (int j = 0; j < 4; ++j) {
         const int f = min(fb0 + tx + 16 * j, f0 + nfun - 1);
         bf[j] = b[f];
-        gf[j] = gbc[f];
+        cw[j] = band_coef(gbc[f], w);
     }
+    const float iw = (float)(1.0 / w);
     float acc[4][4];
     for (int i = 0; i < 4; ++i)
         for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
@@ -123,55 +196,117 @@ __global__ __launch_bounds__(kBlock) void hash_fp32_kernel(
         }
     }
     __syncthreads();
-    unsigned long long nre = 0;
+    uint32_t pend = 0;  // bit j * 4 + i: output (row0 + ty + 16 i, fb0 + tx + 16 j)
     for (int i = 0; i < 4; ++i) {
         const int64_t row = row0 + ty + 16 * i;
-        const double xm = (double)__uint_as_float(xmax_s[ty + 16 * i]);
+        const float xm = __uint_as_float(xmax_s[ty + 16 * i]);
         for (int j = 0; j < 4; ++j) {
             const int f = fb0 + tx + 16 * j;
             if (row >= m || f >= f0 + nfun) continue;
-            double y = ((double)acc[i][j] + (double)bf[j]) / w;
             int32_t h;
-            if (outside_band(y, band(gf[j], xm, w, y))) {
-                h = floor_to_i32(y);
-            } else {
-                h = hash_exact<T>(x + row * dp, a + (int64_t)f * dp, d, bf[j], w);
-                ++nre;
-            }
-            out[row * out_ld + (f - f0)] = h;
+            if (accept_fp32(acc[i][j], bf[j], iw, cw[j] * xm, h))
+                out[row * out_ld + (f - f0)] = h;
+            else
+                pend |= 1u << (j * 4 + i);
         }
     }
-    if (recomputed && nre) atomicAdd(recomputed, nre);
+    unsigned long long nre = 0;
+    recompute_marked<T>(pend, x, row0 + ty, 16, dp, d, a, b, fb0 + tx, f0, w, out, out_ld, nre);
+    if (recomputed && nre)
+        atomicAdd(recomputed + (blockIdx.y * gridDim.x + blockIdx.x) % kRecompSlots, nre);
 }
 
-// ---------------------------------------------------------------- FP16 MFMA form (uint8 data)
+// ---------------------------------------------------------------- MFMA forms
+// A workgroup computes 64 rows x 64 functions; wave wv owns rows 16 wv ..
+// 16 wv + 15 against all 64 functions (four 16 x 16 output blocks).  The K
+// dimension is staged through LDS in chunks: every thread issues its share of
+// the chunk's global loads at once, so a chunk costs one memory latency, and
+// the next chunk's loads are in flight while the current one is multiplied.
+// LDS rows are padded so that the fragment reads of a wave hit distinct banks.
+//
+// Epilogue: outputs inside the guard band are marked per lane and recomputed
+// after the accepted ones are stored.
+
+constexpr int kKcF16 = 128;  // K chunk, FP16 form (uint8 data)
+constexpr int kKcF32 = 64;   // K chunk, FP32 form (float data)
+
+// 16 loaded bytes, or zeros (masked per component: a select of the vector
+// type would go through memory)
+__device__ inline uint4 mask16(uint4 v, bool keep)
+{
+    const uint32_t mk = keep ? 0xffffffffu : 0u;
+    return uint4{v.x & mk, v.y & mk, v.z & mk, v.w & mk};
+}
+
 // a = a_hi + a_lo (+ residual counted in the bound), both FP16; uint8 values are
-// exact in FP16; products are exact in FP32.  Each wave computes 16 rows x 64
-// functions with v_mfma_f32_16x16x16f16, separately for a_hi and a_lo.
-__global__ __launch_bounds__(kBlock) void hash_mfma_f16_kernel(
+// exact in FP16; products are exact in FP32.  v_mfma_f32_16x16x16f16, once for
+// a_hi and once for a_lo.  Three workgroups per CU (registers and LDS), so a
+// 10^4-query batch (628 workgroups) runs in one round.
+__global__ __launch_bounds__(kBlock, 3) void hash_mfma_f16_kernel(
     const uint8_t *__restrict__ x, int64_t m, int32_t dp, int32_t d,
     const _Float16 *__restrict__ ahi, const _Float16 *__restrict__ alo,
     const float *__restrict__ a32, const float *__restrict__ b, int32_t f0, int32_t nfun,
     double w, const double *__restrict__ gbc, int32_t *__restrict__ out, int32_t out_ld,
     unsigned long long *recomputed)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t row0 = (int64_t)blockIdx.x * 64 + wv * 16;
+    constexpr int KC = kKcF16;
+    constexpr int XS = KC + 16;  // bytes per staged row of x
+    constexpr int AS = KC + 8;   // halves per staged function row
+    __shared__ __align__(16) uint8_t xs[64 * XS];
+    __shared__ __align__(16) _Float16 hs[64 * AS];
+    __shared__ __align__(16) _Float16 ls[64 * AS];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t rowb = (int64_t)blockIdx.x * 64;
+    const int64_t row0 = rowb + wv * 16;
     const int fbase = f0 + blockIdx.y * 64;
     const int r = lane & 15, kq = (lane >> 4) * 4;
-    int64_t xrow = row0 + r;
-    if (xrow >= m) xrow = m - 1;
-    const uint8_t *xp = x + xrow * dp + kq;
     // the epilogue's per-function constants, loaded up front (clamped to the
     // launch's function range; out-of-range functions are never stored)
-    float bf[4];
-    double gf[4];
+    float bf[4], cw[4];
 #pragma unroll
     for (int fb = 0; fb < 4; ++fb) {
         const int f = min(fbase + fb * 16 + r, f0 + nfun - 1);
         bf[fb] = b[f];
-        gf[fb] = gbc[f];
+        cw[fb] = band_coef(gbc[f], w);
     }
+    const float iw = (float)(1.0 / w);
+    // staging registers: x = 64 rows x KC bytes (2 x 16 B per thread), a_hi and
+    // a_lo = 64 functions x KC halves (4 x 16 B each); rows past m repeat row
+    // m - 1; a piece past dp re-reads the row's last piece (every load is in
+    // bounds and none waits on a branch) and is stored as zeros
+    uint4 xr[2], hr[4], lr[4];
+    auto load_chunk = [&](int kc) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int e = tid + i * kBlock, row = e >> 3, k = kc + (e & 7) * 16;
+            const int64_t gr = rowb + row < m ? rowb + row : m - 1;
+            xr[i] = *reinterpret_cast<const uint4 *>(x + gr * dp + min(k, dp - 16));
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = tid + i * kBlock, f = e >> 4, k = kc + (e & 15) * 8;
+            const int64_t off = (int64_t)(fbase + f) * dp + min(k, dp - 8);
+            hr[i] = *reinterpret_cast<const uint4 *>(ahi + off);
+            lr[i] = *reinterpret_cast<const uint4 *>(alo + off);
+        }
+    };
+    // masking happens here, not at the load, so the loads of the next chunk
+    // stay in flight while the current one is multiplied
+    auto store_chunk = [&](int kc) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int e = tid + i * kBlock;
+            *reinterpret_cast<uint4 *>(xs + (e >> 3) * XS + (e & 7) * 16) =
+                mask16(xr[i], kc + (e & 7) * 16 < dp);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = tid + i * kBlock, o = (e >> 4) * AS + (e & 15) * 8;
+            const bool keep = kc + (e & 15) * 8 < dp;
+            *reinterpret_cast<uint4 *>(hs + o) = mask16(hr[i], keep);
+            *reinterpret_cast<uint4 *>(ls + o) = mask16(lr[i], keep);
+        }
+    };
     floatx4_t acc_hi[4], acc_lo[4];
 #pragma unroll
     for (int fb = 0; fb < 4; ++fb) {
@@ -179,68 +314,63 @@ __global__ __launch_bounds__(kBlock) void hash_mfma_f16_kernel(
         acc_lo[fb] = floatx4_t{0.f, 0.f, 0.f, 0.f};
     }
     uint32_t xmax = 0;
-    // double-buffered K loop: step kb + 16 is loaded (unconditionally, the
-    // last step reloads itself) while step kb feeds the MFMAs
-    uint32_t xn;
-    half4_t ahn[4], aln[4];
-    auto load_step = [&](int kb) {
-        xn = *reinterpret_cast<const uint32_t *>(xp + kb);
+    load_chunk(0);
+    for (int kc = 0; kc < dp; kc += KC) {
+        __syncthreads();  // the previous chunk's reads are done
+        store_chunk(kc);
+        __syncthreads();
+        if (kc + KC < dp) load_chunk(kc + KC);
+        const int ns = (dp - kc < KC ? dp - kc : KC) / 16;
 #pragma unroll
-        for (int fb = 0; fb < 4; ++fb) {
-            const int64_t f = fbase + fb * 16 + r;
-            ahn[fb] = *reinterpret_cast<const half4_t *>(ahi + f * dp + kb + kq);
-            aln[fb] = *reinterpret_cast<const half4_t *>(alo + f * dp + kb + kq);
-        }
-    };
-    load_step(0);
-    for (int kb = 0; kb < dp; kb += 16) {
-        const uint32_t xv = xn;
-        half4_t ah[4], al[4];
+        for (int st = 0; st < KC / 16; ++st) {
+            if (st >= ns) break;
+            const uint32_t xv = *reinterpret_cast<const uint32_t *>(xs + (wv * 16 + r) * XS + st * 16 + kq);
+            half4_t ah[4], al[4];
 #pragma unroll
-        for (int fb = 0; fb < 4; ++fb) {
-            ah[fb] = ahn[fb];
-            al[fb] = aln[fb];
-        }
-        load_step(kb + 16 < dp ? kb + 16 : kb);
-        const uint32_t b0 = xv & 255u, b1 = (xv >> 8) & 255u, b2 = (xv >> 16) & 255u, b3 = xv >> 24;
-        xmax = max(xmax, max(max(b0, b1), max(b2, b3)));
-        const half4_t xh = {(_Float16)(float)b0, (_Float16)(float)b1, (_Float16)(float)b2,
-                            (_Float16)(float)b3};
+            for (int fb = 0; fb < 4; ++fb) {
+                const int o = (fb * 16 + r) * AS + st * 16 + kq;
+                ah[fb] = *reinterpret_cast<const half4_t *>(hs + o);
+                al[fb] = *reinterpret_cast<const half4_t *>(ls + o);
+            }
+            const uint32_t b0 = xv & 255u, b1 = (xv >> 8) & 255u, b2 = (xv >> 16) & 255u, b3 = xv >> 24;
+            xmax = max(xmax, max(max(b0, b1), max(b2, b3)));
+            const half4_t xh = {(_Float16)(float)b0, (_Float16)(float)b1, (_Float16)(float)b2,
+                                (_Float16)(float)b3};
 #pragma unroll
-        for (int fb = 0; fb < 4; ++fb) {
-            acc_hi[fb] = __builtin_amdgcn_mfma_f32_16x16x16f16(xh, ah[fb], acc_hi[fb], 0, 0, 0);
-            acc_lo[fb] = __builtin_amdgcn_mfma_f32_16x16x16f16(xh, al[fb], acc_lo[fb], 0, 0, 0);
+            for (int fb = 0; fb < 4; ++fb) {
+                acc_hi[fb] = __builtin_amdgcn_mfma_f32_16x16x16f16(xh, ah[fb], acc_hi[fb], 0, 0, 0);
+                acc_lo[fb] = __builtin_amdgcn_mfma_f32_16x16x16f16(xh, al[fb], acc_lo[fb], 0, 0, 0);
+            }
         }
     }
     xmax = max(xmax, (uint32_t)__shfl_xor((int)xmax, 16));
     xmax = max(xmax, (uint32_t)__shfl_xor((int)xmax, 32));
-    double xm[4];
-    for (int j = 0; j < 4; ++j) xm[j] = (double)__shfl((int)xmax, (lane >> 4) * 4 + j);
-    unsigned long long nre = 0;
+    float xm[4];
+    for (int j = 0; j < 4; ++j) xm[j] = (float)__shfl((int)xmax, (lane >> 4) * 4 + j);
+    // this lane's outputs: rows rl + j (j < 4), functions fbase + r + 16 fb
+    const int64_t rl = row0 + (lane >> 4) * 4;
+    uint32_t pend = 0;
 #pragma unroll
     for (int fb = 0; fb < 4; ++fb) {
         const int f = fbase + fb * 16 + r;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int64_t row = row0 + (lane >> 4) * 4 + j;
+            const int64_t row = rl + j;
             if (row >= m || f >= f0 + nfun) continue;
-            const double sum = (double)acc_hi[fb][j] + (double)acc_lo[fb][j];
-            const double y = (sum + (double)bf[fb]) / w;
             int32_t h;
-            if (outside_band(y, band(gf[fb], xm[j], w, y))) {
-                h = floor_to_i32(y);
-            } else {
-                h = hash_exact<uint8_t>(x + row * dp, a32 + (int64_t)f * dp, d, bf[fb], w);
-                ++nre;
-            }
-            out[row * out_ld + (f - f0)] = h;
+            if (accept_fp32(acc_hi[fb][j] + acc_lo[fb][j], bf[fb], iw, cw[fb] * xm[j], h))
+                out[row * out_ld + (f - f0)] = h;
+            else
+                pend |= 1u << (fb * 4 + j);
         }
     }
-    if (recomputed && nre) atomicAdd(recomputed, nre);
+    unsigned long long nre = 0;
+    recompute_marked<uint8_t>(pend, x, rl, 1, dp, d, a32, b, fbase + r, f0, w, out, out_ld, nre);
+    if (recomputed && nre)
+        atomicAdd(recomputed + (blockIdx.y * gridDim.x + blockIdx.x) % kRecompSlots, nre);
 }
 
-// ---------------------------------------------------------------- FP32 MFMA form (float data)
-// v_mfma_f32_16x16x4f32; each lane loads 4 consecutive k of its row and of its
+// v_mfma_f32_16x16x4f32; each lane reads 4 consecutive k of its row and of its
 // function and feeds them to 4 MFMAs, so A and B share one k permutation.
 __global__ __launch_bounds__(kBlock) void hash_mfma_f32_kernel(
     const float *__restrict__ x, int64_t m, int32_t dp, int32_t d, const float *__restrict__ a32,
@@ -248,73 +378,99 @@ __global__ __launch_bounds__(kBlock) void hash_mfma_f32_kernel(
     const double *__restrict__ gbc, int32_t *__restrict__ out, int32_t out_ld,
     unsigned long long *recomputed)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t row0 = (int64_t)blockIdx.x * 64 + wv * 16;
+    constexpr int KC = kKcF32;
+    constexpr int RS = KC + 4;  // floats per staged row
+    __shared__ __align__(16) float xs[64 * RS];
+    __shared__ __align__(16) float as[64 * RS];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t rowb = (int64_t)blockIdx.x * 64;
+    const int64_t row0 = rowb + wv * 16;
     const int fbase = f0 + blockIdx.y * 64;
     const int r = lane & 15, kq = (lane >> 4) * 4;
-    int64_t xrow = row0 + r;
-    if (xrow >= m) xrow = m - 1;
-    const float *xp = x + xrow * dp + kq;
-    float bf[4];  // the epilogue's per-function constants, loaded up front
-    double gf[4];
+    float bf[4], cw[4];  // the epilogue's per-function constants, loaded up front
 #pragma unroll
     for (int fb = 0; fb < 4; ++fb) {
         const int f = min(fbase + fb * 16 + r, f0 + nfun - 1);
         bf[fb] = b[f];
-        gf[fb] = gbc[f];
+        cw[fb] = band_coef(gbc[f], w);
     }
+    const float iw = (float)(1.0 / w);
+    // staging registers: 64 rows (functions) x KC floats = 4 x 16 B per thread;
+    // rows past m repeat row m - 1; a piece past dp re-reads the row's last
+    // piece and is stored as zeros
+    uint4 xr[4], ar[4];
+    auto load_chunk = [&](int kc) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = tid + i * kBlock, row = e >> 4, k = kc + (e & 15) * 4;
+            const int64_t gr = rowb + row < m ? rowb + row : m - 1;
+            const int kk = min(k, dp - 4);
+            xr[i] = *reinterpret_cast<const uint4 *>(x + gr * dp + kk);
+            ar[i] = *reinterpret_cast<const uint4 *>(a32 + (int64_t)(fbase + row) * dp + kk);
+        }
+    };
+    auto store_chunk = [&](int kc) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = tid + i * kBlock, o = (e >> 4) * RS + (e & 15) * 4;
+            const bool keep = kc + (e & 15) * 4 < dp;
+            *reinterpret_cast<uint4 *>(xs + o) = mask16(xr[i], keep);
+            *reinterpret_cast<uint4 *>(as + o) = mask16(ar[i], keep);
+        }
+    };
     floatx4_t acc[4];
 #pragma unroll
     for (int fb = 0; fb < 4; ++fb) acc[fb] = floatx4_t{0.f, 0.f, 0.f, 0.f};
     float xmax = 0.f;
-    // double-buffered K loop (the last step reloads itself)
-    float4 xn, an[4];
-    auto load_step = [&](int kb) {
-        xn = *reinterpret_cast<const float4 *>(xp + kb);
+    load_chunk(0);
+    for (int kc = 0; kc < dp; kc += KC) {
+        __syncthreads();  // the previous chunk's reads are done
+        store_chunk(kc);
+        __syncthreads();
+        if (kc + KC < dp) load_chunk(kc + KC);
+        const int ns = (dp - kc < KC ? dp - kc : KC) / 16;
 #pragma unroll
-        for (int fb = 0; fb < 4; ++fb)
-            an[fb] = *reinterpret_cast<const float4 *>(a32 + (int64_t)(fbase + fb * 16 + r) * dp + kb + kq);
-    };
-    load_step(0);
-    for (int kb = 0; kb < dp; kb += 16) {
-        const float4 xv = xn;
-        float4 av[4];
+        for (int st = 0; st < KC / 16; ++st) {
+            if (st >= ns) break;
+            const float4 xv = *reinterpret_cast<const float4 *>(xs + (wv * 16 + r) * RS + st * 16 + kq);
+            float4 av[4];
 #pragma unroll
-        for (int fb = 0; fb < 4; ++fb) av[fb] = an[fb];
-        load_step(kb + 16 < dp ? kb + 16 : kb);
-        xmax = fmaxf(xmax, fmaxf(fmaxf(fabsf(xv.x), fabsf(xv.y)), fmaxf(fabsf(xv.z), fabsf(xv.w))));
+            for (int fb = 0; fb < 4; ++fb)
+                av[fb] = *reinterpret_cast<const float4 *>(as + (fb * 16 + r) * RS + st * 16 + kq);
+            xmax = fmaxf(xmax, fmaxf(fmaxf(fabsf(xv.x), fabsf(xv.y)), fmaxf(fabsf(xv.z), fabsf(xv.w))));
 #pragma unroll
-        for (int fb = 0; fb < 4; ++fb) {
-            acc[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.x, av[fb].x, acc[fb], 0, 0, 0);
-            acc[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.y, av[fb].y, acc[fb], 0, 0, 0);
-            acc[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.z, av[fb].z, acc[fb], 0, 0, 0);
-            acc[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.w, av[fb].w, acc[fb], 0, 0, 0);
+            for (int fb = 0; fb < 4; ++fb) {
+                acc[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.x, av[fb].x, acc[fb], 0, 0, 0);
+                acc[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.y, av[fb].y, acc[fb], 0, 0, 0);
+                acc[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.z, av[fb].z, acc[fb], 0, 0, 0);
+                acc[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.w, av[fb].w, acc[fb], 0, 0, 0);
+            }
         }
     }
     xmax = fmaxf(xmax, __shfl_xor(xmax, 16));
     xmax = fmaxf(xmax, __shfl_xor(xmax, 32));
-    double xm[4];
-    for (int j = 0; j < 4; ++j) xm[j] = (double)__shfl(xmax, (lane >> 4) * 4 + j);
-    unsigned long long nre = 0;
+    float xm[4];
+    for (int j = 0; j < 4; ++j) xm[j] = __shfl(xmax, (lane >> 4) * 4 + j);
+    const int64_t rl = row0 + (lane >> 4) * 4;
+    uint32_t pend = 0;
 #pragma unroll
     for (int fb = 0; fb < 4; ++fb) {
         const int f = fbase + fb * 16 + r;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int64_t row = row0 + (lane >> 4) * 4 + j;
+            const int64_t row = rl + j;
             if (row >= m || f >= f0 + nfun) continue;
-            const double y = ((double)acc[fb][j] + (double)bf[fb]) / w;
             int32_t h;
-            if (outside_band(y, band(gf[fb], xm[j], w, y))) {
-                h = floor_to_i32(y);
-            } else {
-                h = hash_exact<float>(x + row * dp, a32 + (int64_t)f * dp, d, bf[fb], w);
-                ++nre;
-            }
-            out[row * out_ld + (f - f0)] = h;
+            if (accept_fp32(acc[fb][j], bf[fb], iw, cw[fb] * xm[j], h))
+                out[row * out_ld + (f - f0)] = h;
+            else
+                pend |= 1u << (fb * 4 + j);
         }
     }
-    if (recomputed && nre) atomicAdd(recomputed, nre);
+    unsigned long long nre = 0;
+    recompute_marked<float>(pend, x, rl, 1, dp, d, a32, b, fbase + r, f0, w, out, out_ld, nre);
+    if (recomputed && nre)
+        atomicAdd(recomputed + (blockIdx.y * gridDim.x + blockIdx.x) % kRecompSlots, nre);
 }
 
 qw_status launch_hash(const qw_index *ix, const void *xpad, int64_t m, int32_t f0, int32_t nfun,

@@ -15,6 +15,10 @@ namespace qw {
 
 constexpr int kXcd = 8;                   // XCDs: workgroup b runs on XCD b % 8
 constexpr int kBlock = 256;              // threads per workgroup for every kernel here
+// The guard-band recompute count is spread over this many device counters
+// (workgroup b adds to slot b % kRecompSlots): one counter shared by every
+// workgroup serialises their atomic adds at the end of the hash kernel.
+constexpr int kRecompSlots = 32;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // empty hash-set slot
 constexpr int kMaxL = 64;
 constexpr int kMaxK = 32;
@@ -153,7 +157,8 @@ qw_status launch_pad_rows(const void *src, int64_t m, int32_t d, int32_t dp, int
                           void *dst, hipStream_t s);
 
 // Hash m padded rows for functions [f0, f0+nfun): out[row][f - f0] (row stride out_ld).
-// form 0: FP32 VALU, form 1: MFMA.  recomputed: device counter (nullable).
+// form 0: FP32 VALU, form 1: MFMA.  recomputed: kRecompSlots device counters
+// whose sum is the recompute count (nullable).
 qw_status launch_hash(const qw_index *ix, const void *xpad, int64_t m, int32_t f0, int32_t nfun,
                       int32_t form, int32_t *out, int32_t out_ld,
                       unsigned long long *recomputed, hipStream_t s);

@@ -62,12 +62,16 @@ def test_hash_bit_exact_cfg1(cfg1, form):
 
 
 @pytest.mark.parametrize("form", FORMS)
-def test_hash_boundary_cases(form):
-    """Projections exactly on bucket boundaries or one ulp of b beside them."""
-    L, k, d = 3, 5, 48
+@pytest.mark.parametrize("dtype,d", [("u8", 48), ("u8", 150), ("f32", 150)])
+def test_hash_boundary_cases(form, dtype, d):
+    """Projections exactly on bucket boundaries or one ulp of b beside them
+    (float data holds small integers, so its projections hit them too)."""
+    L, k = 3, 5
     a, b, w = synth.boundary_params(17, L, k, d, w=4.0)
     rng = np.random.default_rng(18)
     x = rng.integers(0, 256, size=(777, d), dtype=np.uint8)
+    if dtype == "f32":
+        x = x.astype(np.float32)
     ix = build(x, a, b, w, form)
     h, rec = ix.hash(dev(x), form)
     assert np.array_equal(h.cpu().numpy(), oracle.hash_points(x, a, b, w))
@@ -81,6 +85,19 @@ def test_hash_float_data_ragged_d(form):
     ix = build(wl.data, p.a, p.b(), p.w, form)
     h, _ = ix.hash(dev(wl.queries), form)
     assert np.array_equal(h.cpu().numpy(), oracle.hash_points(wl.queries, p.a, p.b(), p.w))
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("dtype,d", [("f32", 200), ("u8", 300)])
+def test_hash_several_k_chunks(form, dtype, d):
+    """Rows longer than one staged K chunk, with a ragged last chunk."""
+    wl = synth.random_small(29, n=700, d=d, Q=131, L=4, k=9,
+                            w=3.0 if dtype == "f32" else 900.0, dtype=dtype)
+    p = wl.params
+    ix = build(wl.data, p.a, p.b(), p.w, form)
+    for x in (wl.data, wl.queries):
+        h, _ = ix.hash(dev(x), form)
+        assert np.array_equal(h.cpu().numpy(), oracle.hash_points(x, p.a, p.b(), p.w))
 
 
 # ---------------------------------------------------------------- candidates
