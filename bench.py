@@ -64,7 +64,7 @@ def kernel_source_hash(files):
     return h.hexdigest()[:16]
 
 
-FUSED_SOURCES = ("qw_dedup.hip", "qw_dedup.h", "qw_dist.h")
+FUSED_SOURCES = ("qw_dedup.hip", "qw_dedup.h", "qw_dist.h", "qw_wave.h")
 GATHER_SOURCES = ("qw_gather.hip", "qw_dist.h")
 
 
@@ -210,13 +210,20 @@ def main():
                  st["cand_unique"] * wl.d * elem + 8 * K * wl.Q)
     # Dominant kernel.  Fused form (no separate gather launch): the dedup
     # kernel, which also verifies its candidates; algorithmic bytes per query:
-    # the bucket ids (4 per entry), each unique candidate's row and its
-    # (distance, id) key, the query row.  Otherwise the streaming gather: per
-    # pair the row, the (id, query) pair and the key; plus each query row.
+    # the bucket ids (4 per entry), each unique candidate's row, the query row,
+    # and either each candidate's (distance, id) key for the select kernel or,
+    # when the kernel selects the top K itself (uint8 rows of at most 1024
+    # bytes, K <= 16, the library's rule), the K output pairs.  Otherwise the
+    # streaming gather: per pair the row, the (id, query) pair and the key;
+    # plus each query row.
     fused = float(stage[7]) < 0.02 * float(stage[6])
+    topk_fused = is_u8 and K <= 16 and (wl.d + 15) // 16 <= 64
     if fused:
-        kname, ksrc, kfile = "dedup_kernel (dedup + verify)", FUSED_SOURCES, "dedup_verify"
-        kbytes = 4 * st["cand_total"] + st["cand_unique"] * (wl.d * elem + 8) + wl.Q * wl.d * elem
+        kname, ksrc, kfile = "dedup_kernel (dedup + verify + top-K)" if topk_fused else \
+            "dedup_kernel (dedup + verify)", FUSED_SOURCES, "dedup_verify"
+        per_cand = wl.d * elem + (0 if topk_fused else 8)
+        kbytes = (4 * st["cand_total"] + st["cand_unique"] * per_cand + wl.Q * wl.d * elem +
+                  (8 * K * wl.Q if topk_fused else 0))
         kms = float(stage[6])
     else:
         kname, ksrc, kfile = "gather_kernel", GATHER_SOURCES, "gather"

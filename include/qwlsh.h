@@ -82,7 +82,12 @@ typedef struct {
                           0 = no bucket ordering (default) */
     int32_t graph;     /* fast form: 1 = capture/replay the query pipeline as a HIP graph */
     int32_t timing;    /* 1 = record per-stage HIP events and report them in qw_stats (syncs) */
-    int32_t reserved[3];
+    int32_t topk_keep; /* fast form, uint8 rows of at most 1024 bytes, K <= 16: the dedup kernel
+                          selects the top K itself, each lane keeping this many of its
+                          candidates' keys (1..3; 0 = 3); a query whose top K that cannot
+                          settle goes to the fallback, so smaller values only send more
+                          queries there (diagnostic).  -1 = a separate select kernel. */
+    int32_t reserved[2];
 } qw_opts;
 
 /* Filled (host memory) by qw_query_workload when non-NULL; the call then
@@ -116,7 +121,8 @@ typedef struct {
 typedef struct qw_index qw_index;
 
 /* Default options: fast form, learned schedule when a model is loaded (else
- * the bucket-size sum), grouping off, graph on, timing off. */
+ * the bucket-size sum), grouping off, graph on, timing off, in-kernel top K
+ * where it applies (topk_keep 0). */
 void qw_default_opts(qw_opts *o);
 
 /*

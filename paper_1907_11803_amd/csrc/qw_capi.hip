@@ -86,6 +86,9 @@ Plan make_plan(qw_index *ix, int K)
     static_assert(kMaxTopK <= 1024 && kBlock <= 1024, "select list sizing");
     p.LC = pow2_at_least(std::max(1024, 4 * K));
     p.ggrid = gather_blocks_per_cu(ix->dp, ix->dtype) * ix->cus;
+    // uint8 rows of at most 64 parts and small K: the dedup kernel selects
+    // the top K itself
+    p.topk = (ix->dtype == QW_U8 && p.fuse && K <= kFusedTopK && rbytes / 16 <= 64) ? K : 0;
     {  // FP32 distance bound of the gather kernel (float data)
         const int parts = ix->dp * (ix->dtype == QW_U8 ? 1 : 4) / 16;
         int G = 1;
@@ -251,6 +254,7 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     Workspace &w = ix->ws;
     if (ev) QW_HIP(hipEventRecord(ev[0], s));
     QW_TRY(clear_counters(ix, s));
+    const int topk = o.topk_keep >= 0 ? plan.topk : 0;  // in-kernel top K
     const bool learned = o.sched == QW_SCHED_LEARNED && !ix->mlp.empty();
     QW_TRY(front(ix, queries, Q, QW_FORM_FAST, s, ev, learned ? w.feats.as<float>() : nullptr));
     if (ev) QW_HIP(hipEventRecord(ev[2], s));
@@ -319,6 +323,12 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
                 a.addr32 = (uint64_t)ix->n * rb < (1ull << 32) && ix->n < (1ll << 24) ? 1 : 0;
             }
             a.keys = w.pkeys.as<unsigned long long>();
+            a.topk = topk;
+            a.topk_keep = o.topk_keep == 0 ? 3 : o.topk_keep;
+            a.out_ids = out_ids;
+            a.out_dist = out_dist;
+            a.fb_count = c32(ix) + W_FB;
+            a.fb_list = w.fb.as<int32_t>();
             a.ucount = w.ucount.as<uint32_t>();
             a.coff = w.coff.as<unsigned long long>();
             a.flag = w.flag.as<uint32_t>();
@@ -406,7 +416,7 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     m.out_dist = out_dist;
     m.data = ix->data.p;
     m.queries = w.qpad.p;
-    QW_TRY(launch_select(m, Q, s));
+    if (!topk) QW_TRY(launch_select(m, Q, s));
     if (ev) QW_HIP(hipEventRecord(ev[4], s));
     // queries flagged on the way (list space, ties or band wider than the list):
     // the fused per-query kernel with a global hash set answers them
@@ -583,6 +593,7 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
     if (o) opt = *o; else qw_default_opts(&opt);
     if (opt.form != QW_FORM_PLAIN_FP32 && opt.form != QW_FORM_FAST) return QW_EINVAL;
     if (opt.sched < QW_SCHED_SUM || opt.sched > QW_SCHED_NONE) return QW_EINVAL;
+    if (opt.topk_keep < -1 || opt.topk_keep > 3) return QW_EINVAL;
     if (Q == 0) {
         if (st) std::memset(st, 0, sizeof(*st));
         return QW_OK;
@@ -620,6 +631,7 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
             std::memset(&key, 0, sizeof(key));
             key.q = queries; key.Q = Q; key.K = K; key.ids = out_ids; key.dist = out_dist;
             key.form = eff.form; key.sched = eff.sched; key.group = eff.group;
+            key.topk_keep = eff.topk_keep;
             auto it = ix->graphs.find(key);
             if (it == ix->graphs.end()) {
                 hipStream_t cs;

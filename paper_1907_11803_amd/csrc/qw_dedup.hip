@@ -2,20 +2,24 @@
 // (the union of the query's buckets, Sections 1.2 and 5.1) in an LDS hash set
 // sized by its size class.  Fused mode then verifies its unique candidates
 // itself -- gathers their rows, computes the exact squared distances (the
-// false-positive removal of Section 1.2) and writes one (distance, id) key per
-// candidate into the query's range of its XCD's key region; otherwise it
-// writes the unique ids, each tagged with its query, for the streaming gather.
-// Queries whose set overflows move to the next size class; queries the region
-// cannot hold are flagged for the fallback.
+// false-positive removal of Section 1.2) and either selects the K nearest
+// itself (uint8, small K) or writes one (distance, id) key per candidate into
+// the query's range of its XCD's key region for the select kernel; otherwise
+// it writes the unique ids, each tagged with its query, for the streaming
+// gather.  Queries whose set overflows move to the next size class; queries
+// the region cannot hold, or whose top K the fused selection cannot settle,
+// go to the fallback.
 #include "qw_dedup.h"
 #include "qw_dist.h"
 #include "qw_internal.h"
+#include "qw_wave.h"
 
 namespace qw {
 
 enum {
     D_UCOUNT = 0, D_OVF, D_CPOS, D_T, D_CAP, D_OFF = 6 /* u64 */,
-    D_WT = 8 /* per-wave counts, kBlock / 64 */, D_NEXT = 12, D_NSCAL = 16
+    D_WT = 8 /* per-wave counts, kBlock / 64 */, D_NEXT = 12, D_LCNT = 13, D_BAD = 14,
+    D_BOUND = 16 /* u64 */, D_KTH = 18 /* u64 */, D_NSCAL = 20
 };
 constexpr int kRegIds = 16;  // ids per thread of the register-resident path
 
@@ -42,15 +46,39 @@ __device__ inline uint32_t wave_base(const uint32_t *scal, int wave, uint32_t *t
     return b;
 }
 
+// Fused top K: every lane keeps the kTopR smallest keys of its own stream of
+// candidates (a stream is every G-th row its group verifies), in ascending
+// order, and the smallest key it had to drop (~0: none).
+constexpr int kTopR = 3;
+constexpr uint32_t kTopList = 512;  // list capacity, 8-byte entries in the set's memory
+
+struct LaneTop {
+    unsigned long long k[kTopR];
+    unsigned long long dmin;
+};
+
+__device__ inline void lane_top_insert(LaneTop &t, unsigned long long key, bool mine)
+{
+    unsigned long long v = mine ? key : ~0ull;
+#pragma unroll
+    for (int r = 0; r < kTopR; ++r) {
+        const bool lt = v < t.k[r];
+        const unsigned long long lo = lt ? v : t.k[r];
+        v = lt ? t.k[r] : v;
+        t.k[r] = lo;
+    }
+    t.dmin = v < t.dmin ? v : t.dmin;  // the key pushed out of the list, if any
+}
+
 // verify_list for rows of at most 64 parts.  A lane holds two consecutive
 // parts of a row (G = pow2 >= parts / 2 lanes per row), UN2 rows per group
 // per step; the loop is unrolled twice so the two steps in flight alternate
 // between register sets.  Row addresses: a 24-bit multiply into a 32-bit
 // offset from the uniform data pointer when the data allows (A.addr32).
-template <int DT>
+template <int DT, bool TOPK>
 __device__ inline void verify_small(const DedupArgs &A, const uint32_t *list, uint32_t U,
                                     const uint4 *qrow, int parts, unsigned long long *keys,
-                                    uint32_t qq)
+                                    uint32_t qq, LaneTop &top)
 {
     constexpr int UN2 = 2;
     const int tid = threadIdx.x;
@@ -60,6 +88,7 @@ __device__ inline void verify_small(const DedupArgs &A, const uint32_t *list, ui
     const int NG = kBlock / G;
     const uint32_t PI = (uint32_t)(NG * UN2);
     const int grp = tid / G, j = tid % G;
+    const int lg_ng = __builtin_ctz((unsigned)NG);
     const int p0 = 2 * j, p1 = 2 * j + 1;
     const bool in0 = p0 < parts, in1 = p1 < parts;
     const int c0 = in0 ? p0 : parts - 1, c1 = in1 ? p1 : parts - 1;
@@ -114,7 +143,25 @@ __device__ inline void verify_small(const DedupArgs &A, const uint32_t *list, ui
                 else
                     accf[u] += __shfl_xor(accf[u], o);
             }
-        if (j == 0)
+        if (TOPK) {
+            // row u of this step belongs to the stream of lane (base / NG + u) mod G
+            // of the group (every lane of the group holds the reduced distance);
+            // with G >= UN2 a lane owns at most one row of the step
+            if (G >= UN2) {
+                const uint32_t u = (uint32_t)(j - (int)(base >> lg_ng)) & (uint32_t)(G - 1);
+                const uint32_t i = base + (uint32_t)grp + (uint32_t)NG * u;
+                const bool mine = u < (uint32_t)UN2 && i < U;
+                const uint32_t dist = (u == 0 ? accu[0] : accu[UN2 - 1]) + qq;
+                const uint32_t id = u == 0 ? st.id[0] : st.id[UN2 - 1];
+                lane_top_insert(top, ((unsigned long long)dist << 32) | id, mine);
+            } else {
+#pragma unroll
+                for (int u = 0; u < UN2; ++u) {
+                    const uint32_t i = base + (uint32_t)(grp + NG * u);
+                    lane_top_insert(top, ((unsigned long long)(accu[u] + qq) << 32) | st.id[u], i < U);
+                }
+            }
+        } else if (j == 0) {
 #pragma unroll
             for (int u = 0; u < UN2; ++u) {
                 const uint32_t i = base + (uint32_t)(grp + NG * u);
@@ -123,6 +170,7 @@ __device__ inline void verify_small(const DedupArgs &A, const uint32_t *list, ui
                     keys[i] = ((unsigned long long)hi << 32) | st.id[u];
                 }
             }
+        }
     };
     if (U == 0) return;
     Step sa, sb;
@@ -149,9 +197,10 @@ __device__ inline void verify_small(const DedupArgs &A, const uint32_t *list, ui
 // squares of differences.  Rows of one part per lane: the
 // next step's rows are loaded before the current step is reduced, so two
 // steps are in flight.  No barriers.
-template <int DT>
+template <int DT, bool TOPK>
 __device__ inline void verify_list(const DedupArgs &A, const uint32_t *list, uint32_t U,
-                                   const uint4 *qrow, int parts, unsigned long long off)
+                                   const uint4 *qrow, int parts, unsigned long long off,
+                                   LaneTop &top)
 {
     constexpr int UN = 4;
     const int tid = threadIdx.x;
@@ -195,8 +244,8 @@ __device__ inline void verify_list(const DedupArgs &A, const uint32_t *list, uin
                 }
             }
     };
-    if (P == 1) {
-        verify_small<DT>(A, list, U, qrow, parts, keys, qq);
+    if (P == 1 || TOPK) {  // the fused top K runs only on rows of at most 64 parts
+        verify_small<DT, TOPK>(A, list, U, qrow, parts, keys, qq, top);
         return;
     }
     for (uint32_t base = 0; base < U; base += PI) {
@@ -234,6 +283,100 @@ __device__ inline void verify_list(const DedupArgs &A, const uint32_t *list, uin
     }
 }
 
+// Whole workgroup, fused top K of query q from the lanes' kept keys (uint8:
+// a key's high word is the exact squared distance).  lst (kTopList entries)
+// may be the set's memory: every read of the set is behind a barrier.
+//  1. the K-th smallest lane minimum of a wave bounds the K-th key of the
+//     union of kept keys (K lanes hold a key at or below it); B = the smallest
+//     such bound over the waves;
+//  2. the kept keys at or below B are collected in lst and ranked; ranks
+//     below K are the output, padded with (-1, INT32_MAX) below K entries;
+//  3. the union's top K is the query's top K unless some lane dropped a key
+//     below the union's K-th key (or fewer than K were found while a lane
+//     dropped any): then the query goes to the fallback, as it does when the
+//     list exceeds its capacity.
+// A.topk_keep < kTopR keeps fewer keys per lane (a diagnostic: more queries
+// reach the fallback; the result does not change).
+template <bool GLOB>
+__device__ inline void fused_topk(const DedupArgs &A, int64_t q, LaneTop t,
+                                  unsigned long long *lst, uint32_t *scal)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int K = A.topk;
+#pragma unroll
+    for (int r = 1; r < kTopR; ++r)
+        if (r >= A.topk_keep) {
+            t.dmin = t.k[r] < t.dmin ? t.k[r] : t.dmin;
+            t.k[r] = ~0ull;
+        }
+    const unsigned long long lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+    unsigned long long *s_bound = reinterpret_cast<unsigned long long *>(&scal[D_BOUND]);
+    unsigned long long *s_kth = reinterpret_cast<unsigned long long *>(&scal[D_KTH]);
+    auto sync = [&]() {
+        if (GLOB) __threadfence();
+        __syncthreads();
+    };
+    if (tid == 0) {
+        scal[D_LCNT] = 0;
+        scal[D_BAD] = 0;
+        *s_bound = ~0ull;
+        *s_kth = ~0ull;
+    }
+    sync();
+    const unsigned long long tw = __shfl(wave_sort_u64(t.k[0]), K - 1);
+    if (lane == 0 && tw != ~0ull) atomicMin(s_bound, tw);
+    sync();
+    const unsigned long long B = *s_bound;
+#pragma unroll
+    for (int r = 0; r < kTopR; ++r) {
+        const bool take = t.k[r] != ~0ull && t.k[r] <= B;
+        const unsigned long long m = __ballot(take);
+        uint32_t wb = 0;
+        if (lane == 0 && m) wb = atomicAdd(&scal[D_LCNT], (uint32_t)__popcll(m));
+        wb = (uint32_t)__shfl((int)wb, 0);
+        const uint32_t pos = wb + (uint32_t)__popcll(m & lt_mask);
+        if (take && pos < kTopList) lst[pos] = t.k[r];
+    }
+    sync();
+    const uint32_t c = scal[D_LCNT];
+    const bool over = c > kTopList;
+    if (!over && c <= 64) {  // the usual case: one wave sorts the list
+        if (tid < 64) {
+            const unsigned long long v = wave_sort_u64(lane < (int)c ? lst[lane] : ~0ull);
+            if (lane < K) {
+                const int64_t o = q * K + lane;
+                const bool has = lane < (int)c;
+                A.out_ids[o] = has ? (int32_t)(uint32_t)v : -1;
+                reinterpret_cast<int32_t *>(A.out_dist)[o] = has ? (int32_t)(v >> 32) : INT32_MAX;
+            }
+            if (lane == K - 1 && lane < (int)c) *s_kth = v;
+        }
+    } else if (!over) {
+        for (uint32_t i = tid; i < c; i += kBlock) {
+            const unsigned long long k = lst[i];
+            int r = 0;
+            for (uint32_t e = 0; e < c; ++e) r += lst[e] < k;
+            if (r < K) {
+                const int64_t o = q * K + r;
+                A.out_ids[o] = (int32_t)(uint32_t)k;
+                reinterpret_cast<int32_t *>(A.out_dist)[o] = (int32_t)(k >> 32);
+            }
+            if (r == K - 1) *s_kth = k;  // keys are unique: one writer
+        }
+        for (int r = (int)c + tid; r < K; r += kBlock) {
+            const int64_t o = q * K + r;
+            A.out_ids[o] = -1;
+            reinterpret_cast<int32_t *>(A.out_dist)[o] = INT32_MAX;
+        }
+    }
+    sync();
+    const unsigned long long kth = *s_kth;  // ~0 when fewer than K were found
+    const bool unsure = t.dmin != ~0ull && t.dmin <= kth;
+    if (__ballot(unsure) != 0ull && lane == 0) scal[D_BAD] = 1;
+    sync();
+    if (tid == 0 && (over || scal[D_BAD])) A.fb_list[atomicAdd(A.fb_count, 1u)] = (int32_t)q;
+}
+
 // One workgroup per query (persistent).  The workgroups of XCD x take items
 // x, x + 8, x + 16, ... through that XCD's own counter (a single shared
 // counter would serialise every workgroup's atomic on one address); each
@@ -242,8 +385,10 @@ __device__ inline void verify_list(const DedupArgs &A, const uint32_t *list, uin
 // bucket entries in an LDS set keep their ids in registers from the load to
 // the write; larger ones (and the global-memory class, GLOB) go through the
 // set and read the unique ids back from it.
+// At most 128 registers: four workgroups per CU (the fused top K would
+// otherwise cost one).
 template <bool GLOB, int DT>
-__global__ __launch_bounds__(kBlock) void dedup_kernel(DedupArgs A)
+__global__ __launch_bounds__(kBlock, 4) void dedup_kernel(DedupArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -378,6 +523,9 @@ __global__ __launch_bounds__(kBlock) void dedup_kernel(DedupArgs A)
                 A.ovf_list[o] = (int32_t)q;
             } else if (A.count_only) {
                 A.ucount[q] = U;
+            } else if (A.topk) {  // no key list: the top K is selected here
+                A.ucount[q] = U;
+                off = 0;
             } else {
                 off = atomicAdd(A.alloc + xcd, (unsigned long long)U);
                 if (off + U > A.region) {  // no list space: answered by the fallback
@@ -411,7 +559,17 @@ __global__ __launch_bounds__(kBlock) void dedup_kernel(DedupArgs A)
                     if ((newm >> r) & 1u) tab[e++] = idr[r];
                 bar();
             }
-            verify_list<DT>(A, tab, U, qrow, parts, off);
+            LaneTop top;
+#pragma unroll
+            for (int r = 0; r < kTopR; ++r) top.k[r] = ~0ull;
+            top.dmin = ~0ull;
+            if (DT == QW_U8 && A.topk) {
+                verify_list<DT, true>(A, tab, U, qrow, parts, off, top);
+                bar();  // the set's memory becomes the selection list
+                fused_topk<GLOB>(A, q, top, reinterpret_cast<unsigned long long *>(tab), scal);
+            } else {
+                verify_list<DT, false>(A, tab, U, qrow, parts, off, top);
+            }
         } else if (off != ~0ull && in_regs) {
             unsigned long long e = off + wbase;
 #pragma unroll
@@ -450,6 +608,10 @@ __global__ __launch_bounds__(kBlock) void dedup_kernel(DedupArgs A)
 qw_status launch_dedup(const DedupArgs &a, int grid, hipStream_t s)
 {
     if (grid <= 0) return QW_OK;
+    // the fused top K: uint8 rows of at most 64 parts, 1 <= K <= kFusedTopK
+    if (a.topk && (a.dtype != QW_U8 || a.dp > 64 * 16 || a.topk > kFusedTopK || a.topk < 0 ||
+                   !a.fuse || a.topk_keep < 1 || a.topk_keep > kTopR))
+        return QW_EINVAL;
     const size_t lds = dedup_lds_bytes((int)a.cap_log2, a.global_tab, a.L,
                                        a.dp * (a.dtype == QW_U8 ? 1 : 4));
     if (a.dtype == QW_U8) {

@@ -19,6 +19,8 @@ constexpr int kBlock = 256;              // threads per workgroup for every kern
 // (workgroup b adds to slot b % kRecompSlots): one counter shared by every
 // workgroup serialises their atomic adds at the end of the hash kernel.
 constexpr int kRecompSlots = 32;
+// Largest K the fused dedup kernel selects itself (uint8 data).
+constexpr int kFusedTopK = 16;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // empty hash-set slot
 constexpr int kMaxL = 64;
 constexpr int kMaxK = 32;
@@ -82,6 +84,7 @@ struct Plan {
     int dgrid[16] = {}; // dedup kernel, per class
     int cap_g = 20, grid_g = 1;
     int fuse = 1;       // dedup verifies its own candidates (no pair list, no gather)
+    int topk = 0;       // dedup also selects the top K (0: the select kernel does)
     int LC = 2048;      // select kernel list capacity (entries)
     int ggrid = 256;    // gather grid
     float eps = 0.f;    // FP32 distance bound (float data)
@@ -89,7 +92,7 @@ struct Plan {
 
 struct GraphKey {
     const void *q; int64_t Q; int32_t K; int32_t *ids; void *dist;
-    int32_t form, sched, group;
+    int32_t form, sched, group, topk_keep;
     bool operator<(const GraphKey &o) const {
         return std::memcmp(this, &o, sizeof(GraphKey)) < 0;
     }
@@ -288,6 +291,15 @@ struct DedupArgs {
     int32_t addr32;                  // n * row bytes < 2^32 and n < 2^24: 32-bit row offsets
     const void *data, *queries;
     unsigned long long *keys;
+    // fused top-K (uint8, topk = K in 1..kFusedTopK, rows of at most 64
+    // parts): the kernel selects the K nearest itself and writes the output;
+    // no keys, no list space.  Queries it cannot settle go to fb_list.
+    int32_t topk;
+    int32_t topk_keep;               // keys kept per lane, 1..3 (fewer only reach the fallback more)
+    int32_t *out_ids;
+    void *out_dist;
+    uint32_t *fb_count;
+    int32_t *fb_list;
 };
 
 struct GatherArgs {

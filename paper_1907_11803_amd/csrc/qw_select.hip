@@ -4,6 +4,7 @@
 // the K-th is re-ranked by its FP64 index-order distance.  Queries that do not
 // fit (list or band capacity) go to the fallback.
 #include "qw_internal.h"
+#include "qw_wave.h"
 
 namespace qw {
 
@@ -31,19 +32,6 @@ __device__ __noinline__ double exact_dist_f32_s(const float *__restrict__ x,
         acc = __dadd_rn(acc, __dmul_rn(t, t));
     }
     return acc;
-}
-
-// Ascending bitonic sort of one value per lane across a wave.
-__device__ inline unsigned long long wave_sort_u64(unsigned long long v)
-{
-    const int lane = threadIdx.x & 63;
-    for (int k = 2; k <= 64; k <<= 1)
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const unsigned long long o = __shfl_xor(v, j);
-            const bool asc = (lane & k) == 0, lower = (lane & j) == 0;
-            v = (lower == asc) ? (o < v ? o : v) : (o > v ? o : v);
-        }
-    return v;
 }
 
 // One workgroup per query, over its U keys (unique (distance, id) pairs):

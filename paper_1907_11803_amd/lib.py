@@ -35,7 +35,7 @@ class QwError(RuntimeError):
 class qw_opts(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int32), ("sched", ctypes.c_int32), ("group", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("topk_keep", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class qw_stats(ctypes.Structure):
@@ -138,10 +138,11 @@ def _dtype_code(t: torch.Tensor) -> int:
 
 
 def make_opts(form: int = QW_FORM_FAST, sched: int = QW_SCHED_LEARNED, group: int = 0,
-              graph: int = 1, timing: int = 0) -> qw_opts:
+              graph: int = 1, timing: int = 0, topk_keep: int = 0) -> qw_opts:
     o = qw_opts()
     load().qw_default_opts(ctypes.byref(o))
     o.form, o.sched, o.group, o.graph, o.timing = form, sched, group, graph, timing
+    o.topk_keep = topk_keep
     return o
 
 

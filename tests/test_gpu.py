@@ -148,6 +148,27 @@ def test_fast_form_schedules_identical(cfg1, sched, group):
         _ = (torch.arange(1000, device="cuda") * 2).sum().item()
 
 
+@pytest.mark.parametrize("keep", [-1, 1, 2, 3])
+def test_fused_topk_keep_and_fallback(cfg1, keep):
+    """In-kernel top K (uint8, K <= 16) and the separate select kernel (keep
+    -1) give the oracle's answer; keeping fewer keys per lane sends queries
+    to the fallback without changing the result.  w = 3000 gives 1.2K-6.7K
+    unique candidates per query, several per lane."""
+    p = cfg1.params
+    w = 3000.0
+    ix = build(cfg1.data, p.a, p.b(w), w)
+    for K in (1, 10, 16):
+        ids_o, dist_o, _ = oracle.lsh_query(cfg1.data, cfg1.queries, p.a, p.b(w), w, K)
+        for sched in (lib.QW_SCHED_SUM, lib.QW_SCHED_NONE):
+            opts = lib.make_opts(sched=sched, topk_keep=keep)
+            ids, dist, st = ix.query(dev(cfg1.queries), K, opts, stats=True)
+            check_topk(ids, dist, ids_o, dist_o, True)
+            if keep == 1 and K == 16:
+                assert st["fallback"] > 0
+            if keep == -1:
+                assert st["fallback"] == 0
+
+
 def test_ragged_u8_and_topk_sizes():
     """d not a multiple of 16, n and Q not multiples of the tile sizes, several K."""
     wl = synth.random_small(31, n=2345, d=53, Q=77, L=4, k=3, w=700.0, dtype="u8")
@@ -346,6 +367,10 @@ def test_error_paths(cfg1):
     assert e.value.status == lib.QW_EINVAL
     with pytest.raises(lib.QwError):
         ix.query(q, 5000)
+    for keep in (-2, 4):
+        with pytest.raises(lib.QwError) as e:
+            ix.query(q, 10, lib.make_opts(topk_keep=keep))
+        assert e.value.status == lib.QW_EINVAL
     with pytest.raises(lib.QwError):  # w <= 0
         lib.Index(dev(cfg1.data[:100]), dev(p.a), dev(p.b()), 0.0)
     with pytest.raises(lib.QwError):  # keys wider than 128 bits: tiny w, k = 8, huge ranges
