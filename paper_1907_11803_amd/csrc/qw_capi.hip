@@ -24,7 +24,7 @@ enum {
 };
 // u32: overflow-queue lengths per class (queue i holds queries that overflowed
 // class i-1), fallback queue, misc, then kXcd work counters per class
-enum { W_WORK = 0 /* .. 15: unused */, W_QCNT = 16 /* .. 32 */, W_SIMPLE = 33, W_MAX = 34,
+enum { W_CLSDONE = 0, W_WORK = 1 /* .. 15: unused */, W_QCNT = 16 /* .. 32 */, W_SIMPLE = 33, W_MAX = 34,
        W_DUMMY = 35, W_QMERGED = 36, W_FB = 44, W_FBWORK = 45, W_XWORK = 48,
        kC32 = W_XWORK + kXcd * (kMaxClasses + 1) };
 constexpr int kQueueMerged = kMaxClasses + 1;  // overflow queue of the merged launch
@@ -109,6 +109,7 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan)
         return std::vector<void *>{w.qpad.p, w.h.p, w.bstart.p, w.bsize.p, w.pred.p,
                                    w.feats.p, w.keys.p, w.keys2.p, w.vals.p, w.vals2.p,
                                    w.binoff.p, w.counters.p, w.ovf.p, w.gscratch.p, w.mlpout.p,
+                                   w.order.p,
                                    w.hist.p, w.scan.p, w.ucount.p, w.coff.p, w.flag.p,
                                    w.cand.p, w.candq.p, w.pkeys.p, w.fb.p};
     };
@@ -128,6 +129,7 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan)
     QW_TRY(w.vals2.ensure(sizeof(int32_t) * q));
     QW_TRY(w.ovf.ensure(sizeof(int32_t) * q * (kQueueMerged + 1)));  // one queue per class + merged
     QW_TRY(w.binoff.ensure(sizeof(unsigned long long) * 2 * kMaxClasses));
+    QW_TRY(w.order.ensure(sizeof(int32_t) * (size_t)kMaxClasses * q));  // per-class lists
     QW_TRY(w.counters.ensure(sizeof(unsigned long long) * kC64 + sizeof(uint32_t) * kC32));
     QW_TRY(w.hist.ensure(radix_sort_scratch_bytes(q)));
     QW_TRY(w.scan.ensure(scan_scratch_bytes(q)));
@@ -165,20 +167,34 @@ VerifyArgs base_args(qw_index *ix, int K, int mode)
     a.K = K;
     a.mode = mode;
     a.data = ix->data.p;
-    a.queries = ix->ws.qpad.p;
+    a.queries = ix->ws.qrows;
     a.ovf_count = c32(ix) + W_DUMMY;  // callers that can overflow set a real queue
     a.ovf_list = ix->ws.ovf.as<int32_t>();
     a.ucount_out = ix->ws.ucount.as<uint32_t>();
     return a;
 }
 
-// pad -> hash -> probe for Q queries (counters must already be cleared);
+// The query rows the kernels read: the caller's own rows when they need no
+// padding (d a multiple of 16 elements, 16-byte aligned address), else a
+// zero-padded copy in the workspace.  Sets ix->ws.qrows.
+qw_status stage_query_rows(qw_index *ix, const void *x, int64_t m, hipStream_t s)
+{
+    if (ix->d == ix->dp && (reinterpret_cast<uintptr_t>(x) & 15) == 0) {
+        ix->ws.qrows = x;
+        return QW_OK;
+    }
+    QW_TRY(launch_pad_rows(x, m, ix->d, ix->dp, ix->dtype, ix->ws.qpad.p, s));
+    ix->ws.qrows = ix->ws.qpad.p;
+    return QW_OK;
+}
+
+// stage rows -> hash -> probe for Q queries (counters must already be cleared);
 // feats (nullable) receives the count-model inputs log(1 + s_{q,l})
 qw_status front(qw_index *ix, const void *queries, int64_t Q, int form, hipStream_t s,
                 hipEvent_t *ev = nullptr, float *feats = nullptr)
 {
-    QW_TRY(launch_pad_rows(queries, Q, ix->d, ix->dp, ix->dtype, ix->ws.qpad.p, s));
-    QW_TRY(launch_hash(ix, ix->ws.qpad.p, Q, 0, ix->nf, form, ix->ws.h.as<int32_t>(), ix->nf,
+    QW_TRY(stage_query_rows(ix, queries, Q, s));
+    QW_TRY(launch_hash(ix, ix->ws.qrows, Q, 0, ix->nf, form, ix->ws.h.as<int32_t>(), ix->nf,
                        c64(ix) + C_RECOMP, s));
     if (ev) QW_HIP(hipEventRecord(ev[1], s));
     QW_TRY(launch_probe(ix, ix->ws.h.as<int32_t>(), Q, ix->ws.bstart.as<uint32_t>(),
@@ -264,6 +280,14 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     const int64_t cand_cap = (int64_t)(w.pkeys.bytes / sizeof(unsigned long long));
     auto schedule = [&](const int32_t *ex, const float *pl, int force_max,
                         const int32_t **order) -> qw_status {
+        if (!o.group) {  // classes only: one binning kernel
+            QW_TRY(launch_classify_bin(Q, ix->L, ix->n, w.bsize.as<uint32_t>(), ex, pl,
+                                       ix->mlp_margin, force_max, kCmin, plan.cfloor, plan.cmax,
+                                       plan.ncls, w.order.as<int32_t>(), ccount,
+                                       c32(ix) + W_CLSDONE, seg, s));
+            *order = w.order.as<int32_t>();
+            return QW_OK;
+        }
         QW_TRY(launch_classify(Q, ix->L, ix->n, w.bstart.as<uint32_t>(),
                                w.bsize.as<uint32_t>(), ex, pl, ix->mlp_margin, force_max, kCmin,
                                plan.cfloor, plan.cmax, plan.ncls, o.group, w.keys.as<unsigned long long>(),
@@ -317,7 +341,7 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
             a.dp = ix->dp;
             a.dtype = ix->dtype;
             a.data = ix->data.p;
-            a.queries = w.qpad.p;
+            a.queries = w.qrows;
             {
                 const uint64_t rb = (uint64_t)ix->dp * (ix->dtype == QW_U8 ? 1 : 4);
                 a.addr32 = (uint64_t)ix->n * rb < (1ull << 32) && ix->n < (1ll << 24) ? 1 : 0;
@@ -370,7 +394,7 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
         QW_TRY(schedule(nullptr, nullptr, 0, &order));
         QW_TRY(dedup_classes(order, 1));
         QW_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(ccount), 0u, 2 * kMaxClasses, s));
-        QW_TRY(launch_fill_u32(c32(ix) + W_WORK, 0u, W_SIMPLE - W_WORK, s));
+        QW_TRY(launch_fill_u32(c32(ix) + W_CLSDONE, 0u, W_SIMPLE - W_CLSDONE, s));
         QW_TRY(launch_fill_u32(c32(ix) + W_XWORK, 0u, kXcd * (kMaxClasses + 1), s));
         QW_TRY(launch_fill_u32(c32(ix) + W_QMERGED, 0u, 1, s));
         exact = reinterpret_cast<const int32_t *>(w.ucount.p);
@@ -380,7 +404,7 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
         pred_log = w.mlpout.as<float>();
     }
     QW_TRY(schedule(exact, pred_log, o.sched == QW_SCHED_NONE, &order));
-    QW_TRY(launch_fill_u32(w.flag.as<uint32_t>(), 0u, Q, s));
+    if (!topk) QW_TRY(launch_fill_u32(w.flag.as<uint32_t>(), 0u, Q, s));  // read by the select kernel
     if (ev) QW_HIP(hipEventRecord(ev[3], s));
     QW_TRY(dedup_classes(order, 0));
     if (ev) QW_HIP(hipEventRecord(ev[6], s));
@@ -392,7 +416,7 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     g.cand = w.cand.as<int32_t>();
     g.candq = w.candq.as<int32_t>();
     g.data = ix->data.p;
-    g.queries = w.qpad.p;
+    g.queries = w.qrows;
     g.dp = ix->dp;
     g.dtype = ix->dtype;
     g.keys = w.pkeys.as<unsigned long long>();
@@ -415,7 +439,7 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     m.out_ids = out_ids;
     m.out_dist = out_dist;
     m.data = ix->data.p;
-    m.queries = w.qpad.p;
+    m.queries = w.qrows;
     if (!topk) QW_TRY(launch_select(m, Q, s));
     if (ev) QW_HIP(hipEventRecord(ev[4], s));
     // queries flagged on the way (list space, ties or band wider than the list):
@@ -681,8 +705,8 @@ qw_status qw_hash(qw_index *ix, const void *x, int64_t m, int32_t form, void *st
     hipStream_t s = S(stream);
     QW_TRY(ensure_ws(ix, m, nullptr));
     QW_TRY(clear_counters(ix, s));
-    QW_TRY(launch_pad_rows(x, m, ix->d, ix->dp, ix->dtype, ix->ws.qpad.p, s));
-    QW_TRY(launch_hash(ix, ix->ws.qpad.p, m, 0, ix->nf, form, out_h, ix->nf, c64(ix) + C_RECOMP, s));
+    QW_TRY(stage_query_rows(ix, x, m, s));
+    QW_TRY(launch_hash(ix, ix->ws.qrows, m, 0, ix->nf, form, out_h, ix->nf, c64(ix) + C_RECOMP, s));
     if (out_recomputed) {
         unsigned long long r[kRecompSlots];
         QW_HIP(hipMemcpyAsync(r, c64(ix) + C_RECOMP, sizeof(r), hipMemcpyDeviceToHost, s));
@@ -748,7 +772,7 @@ qw_status qw_bruteforce_knn(qw_index *ix, const void *queries, int64_t Q, int32_
     if (Q == 0) return QW_OK;
     hipStream_t s = S(stream);
     QW_TRY(ensure_ws(ix, Q, nullptr));
-    QW_TRY(launch_pad_rows(queries, Q, ix->d, ix->dp, ix->dtype, ix->ws.qpad.p, s));
+    QW_TRY(stage_query_rows(ix, queries, Q, s));
     VerifyArgs a = base_args(ix, K, VM_ALL);
     a.L = 0;
     a.nitems = Q;

@@ -405,23 +405,35 @@ __global__ __launch_bounds__(kBlock, 4) void dedup_kernel(DedupArgs A)
     uint32_t *tab = GLOB ? A.gscratch + (size_t)blockIdx.x * (size_t(1) << A.cap_log2)
                          : reinterpret_cast<uint32_t *>(smem);
     unsigned long long *soff = reinterpret_cast<unsigned long long *>(&scal[D_OFF]);
-    const int64_t sbeg = (int64_t)A.seg[2 * A.cls_lo];
-    const int64_t send = (int64_t)A.seg[2 * A.cls_hi + 1];
-    const int64_t nseg = A.queue_only ? 0 : send - sbeg;
+    int64_t nseg = 0;
+    if (!A.queue_only)
+        for (int c = A.cls_lo; c <= A.cls_hi; ++c) nseg += (int64_t)(A.seg[2 * c + 1] - A.seg[2 * c]);
     const int64_t nin = A.in_count ? (int64_t)*A.in_count : 0;
     const int64_t nall = nseg + nin;
     const int xcd = blockIdx.x % kXcd;
     const unsigned long long rbase = (unsigned long long)xcd * A.region;
-    // the launch's classes, largest first, then the queue of queries that
-    // overflowed a smaller class
+    // the launch's classes, largest first (each class's segment of the order
+    // from its end), then the queue of queries that overflowed a smaller class
+    auto locate = [&](int64_t it, int &cls) -> int64_t {
+        for (int c = A.cls_hi; c > A.cls_lo; --c) {
+            const int64_t len = (int64_t)(A.seg[2 * c + 1] - A.seg[2 * c]);
+            if (it < len) {
+                cls = c;
+                return (int64_t)A.seg[2 * c + 1] - 1 - it;
+            }
+            it -= len;
+        }
+        cls = A.cls_lo;
+        return (int64_t)A.seg[2 * A.cls_lo + 1] - 1 - it;
+    };
     auto query_of = [&](int64_t it) -> int64_t {
-        return it < nseg ? (int64_t)A.order[send - 1 - it] : (int64_t)A.in_list[it - nseg];
+        int c;
+        return it < nseg ? (int64_t)A.order[locate(it, c)] : (int64_t)A.in_list[it - nseg];
     };
     auto class_cap = [&](int64_t it) -> int {
         if (it >= nseg) return (int)A.cap_log2;
-        const unsigned long long pos = (unsigned long long)(send - 1 - it);
-        int c = A.cls_lo;
-        while (c < A.cls_hi && pos >= A.seg[2 * c + 1]) ++c;
+        int c;
+        (void)locate(it, c);
         return A.cap_base + c;
     };
     // LDS sets only need LDS made visible at a barrier: outstanding global

@@ -512,8 +512,9 @@ qw_status launch_hash(const qw_index *ix, const void *xpad, int64_t m, int32_t f
 
 // ---------------------------------------------------------------- probe
 // One thread per (query, layer): pack the layer's k hash values into the exact
-// key (values outside the data's range cannot match any bucket: a miss), then
-// look the key up in the layer's open-addressing table.
+// key (values outside the data's range cannot match any bucket: a miss; the
+// key of such a layer is never looked up), then look the key up in the
+// layer's open-addressing table.
 __global__ __launch_bounds__(kBlock) void probe_kernel(
     const int32_t *__restrict__ h, int64_t Q, int32_t L, int32_t k,
     const int32_t *__restrict__ hmin, const int32_t *__restrict__ hmax,
@@ -521,36 +522,61 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(
     const long long *__restrict__ tab_off, const uint32_t *__restrict__ tab_mask,
     uint32_t *__restrict__ bstart, uint32_t *__restrict__ bsize, float *__restrict__ feats)
 {
-    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (idx >= Q * L) return;
-    const int64_t q = idx / L;
-    const int32_t l = (int32_t)(idx - q * L);
+    // per-function constants (value range, bit offset in the key) staged in
+    // LDS while the hash values load: one memory latency for both
+    extern __shared__ int32_t fconst[];  // [3][nf]: hmin, hmax, shift
     const int32_t nf = L * k;
+    for (int32_t f = threadIdx.x; f < nf; f += kBlock) {
+        fconst[f] = hmin[f];
+        fconst[nf + f] = hmax[f];
+        fconst[2 * nf + f] = shift[f];
+    }
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool live = idx < Q * L;
+    const int64_t q = live ? idx / L : 0;
+    const int32_t l = live ? (int32_t)(idx - q * L) : 0;
+    // the layer's k hash values, all loads issued before any is used
+    int32_t hv[kMaxK];
+#pragma unroll
+    for (int32_t j = 0; j < kMaxK; ++j)
+        if (j < k) hv[j] = h[q * nf + l * k + j];
+    __syncthreads();
+    if (!live) return;
     uint64_t klo = 0, khi = 0;
     bool valid = true;
-    for (int32_t j = 0; j < k; ++j) {
-        const int32_t f = l * k + j;
-        const int32_t v = h[q * nf + f];
-        if (v < hmin[f] || v > hmax[f]) {
-            valid = false;
-            break;
+#pragma unroll
+    for (int32_t j = 0; j < kMaxK; ++j)
+        if (j < k) {
+            const int32_t f = l * k + j, lo = fconst[f];
+            valid = valid && hv[j] >= lo && hv[j] <= fconst[nf + f];
+            key_put(klo, khi, (uint64_t)((int64_t)hv[j] - (int64_t)lo), fconst[2 * nf + f]);
         }
-        key_put(klo, khi, (uint64_t)((int64_t)v - (int64_t)hmin[f]), shift[f]);
-    }
     uint32_t st = 0, sz = 0;
     if (valid) {
+        // linear probing, four slots per round trip: the slots of a probe
+        // sequence are loaded together, so a lane's wait is a quarter of its
+        // sequence length in memory latencies
+        constexpr uint32_t kProbeRound = 4;
         const TabEntry *t = tab + tab_off[l];
         const uint32_t mask = tab_mask[l];
         uint32_t slot = (uint32_t)key_mix(klo, khi) & mask;
-        for (uint32_t it = 0; it <= mask; ++it) {
-            const TabEntry e = t[slot];
-            if (e.size == 0) break;
-            if (e.klo == klo && e.khi == khi) {
-                st = e.start;
-                sz = e.size;
-                break;
+        bool done = false;
+        for (uint32_t it = 0; it <= mask && !done; it += kProbeRound) {
+            TabEntry e[kProbeRound];
+#pragma unroll
+            for (uint32_t i = 0; i < kProbeRound; ++i) e[i] = t[(slot + i) & mask];
+#pragma unroll
+            for (uint32_t i = 0; i < kProbeRound; ++i) {
+                if (done) continue;
+                if (e[i].size == 0) {
+                    done = true;
+                } else if (e[i].klo == klo && e[i].khi == khi) {
+                    st = e[i].start;
+                    sz = e[i].size;
+                    done = true;
+                }
             }
-            slot = (slot + 1) & mask;
+            slot = (slot + kProbeRound) & mask;
         }
     }
     bstart[idx] = st;
@@ -563,7 +589,8 @@ qw_status launch_probe(const qw_index *ix, const int32_t *h, int64_t Q, uint32_t
 {
     if (Q <= 0) return QW_OK;
     const int64_t total = Q * ix->L;
-    probe_kernel<<<(unsigned)ceil_div(total, kBlock), kBlock, 0, s>>>(
+    const size_t lds = sizeof(int32_t) * 3 * (size_t)ix->nf;  // nf <= 64 * kMaxK: 24 KiB at most
+    probe_kernel<<<(unsigned)ceil_div(total, kBlock), kBlock, lds, s>>>(
         h, Q, ix->L, ix->k, ix->hmin.as<int32_t>(), ix->hmax.as<int32_t>(),
         ix->shift.as<int32_t>(), ix->tab.as<TabEntry>(), ix->tab_off.as<long long>(),
         ix->tab_mask.as<uint32_t>(), bstart, bsize, feats);

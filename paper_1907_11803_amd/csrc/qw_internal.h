@@ -72,6 +72,9 @@ struct Workspace {
         order, binoff, counters, ovf, gscratch, mlpout, scan;
     // flat pipeline
     DevBuf ucount, coff, flag, cand, candq, pkeys, fb;
+    // the query rows the kernels of the current call read: the caller's own
+    // (no padding needed) or qpad
+    const void *qrows = nullptr;
 };
 
 // Launch plan of the fast form for one top-K size: hash-set size classes and
@@ -237,6 +240,14 @@ qw_status launch_classify(int64_t Q, int32_t L, int64_t n,
                           int32_t *vals, unsigned long long *class_count, hipStream_t s);
 qw_status launch_segments(const unsigned long long *class_count, int32_t ncls,
                           unsigned long long *seg, hipStream_t s);
+// Classes without bucket grouping in one kernel: class c's queries to
+// order[c * Q ..) (any order), counts added to class_count, seg[2c], seg[2c+1]
+// = [c * Q, c * Q + count_c).  done: a zeroed counter.
+qw_status launch_classify_bin(int64_t Q, int32_t L, int64_t n, const uint32_t *bsize,
+                              const int32_t *exact, const float *pred_log, float margin,
+                              int32_t force_max, int32_t cmin, int32_t cfloor, int32_t cmax,
+                              int32_t ncls, int32_t *order, unsigned long long *class_count,
+                              uint32_t *done, unsigned long long *seg, hipStream_t s);
 qw_status launch_max_u32(const uint32_t *v, int64_t count, uint32_t *out, hipStream_t s);
 qw_status launch_max_bucket_sum(const uint32_t *bsize, int64_t Q, int32_t L, uint32_t *out,
                                 hipStream_t s);
@@ -254,7 +265,7 @@ qw_status build_index(const void *data, int64_t n, int32_t d, int32_t dtype, con
 // ---------------------------------------------------------------- flat pipeline
 struct DedupArgs {
     const int32_t *order;            // scheduled query order
-    const unsigned long long *seg;   // {begin, end} of every class in the order
+    const unsigned long long *seg;   // {begin, end} of every class in the order (gaps allowed)
     int32_t cls_lo, cls_hi;          // this launch serves classes cls_lo..cls_hi
     int32_t queue_only;              // serve only the in_list queue (no segment)
     int32_t cap_base;                // class c uses a set of 2^(cap_base + c) slots

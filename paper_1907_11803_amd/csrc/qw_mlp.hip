@@ -8,6 +8,7 @@
 // (inputs, weights and hidden activations rounded to bfloat16, FP32 sums).
 // Packed parameters: W1 [H][L], b1 [H], W2 [H], b2.
 #include "qw_internal.h"
+#include "qw_mlp.h"
 
 namespace qw {
 
@@ -33,15 +34,6 @@ qw_status launch_mlp_features(const uint32_t *bsize, int64_t Q, int32_t L, float
     return QW_OK;
 }
 
-// Round-to-nearest-even to bfloat16, returned as the float it represents.
-__device__ inline float bf16_round(float x)
-{
-    uint32_t u = __float_as_uint(x);
-    if ((u & 0x7F800000u) == 0x7F800000u) return x;  // inf / nan unchanged
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return __uint_as_float(u & 0xFFFF0000u);
-}
-
 // One wave per query (H = 64 = the wave width): lane h computes hidden unit h
 // from W1 held transposed in LDS (consecutive lanes read consecutive words),
 // and a wave reduction sums W2 . relu(z + b1).  Waves loop over queries.
@@ -52,21 +44,23 @@ __global__ __launch_bounds__(kBlock) void mlp_predict_bf16_kernel(const float *_
 {
     static_assert(H == 64, "one hidden unit per lane");
     extern __shared__ float sw[];  // W1^T bf16 [L][H], b1 [H], W2 bf16 [H], b2
-    const int P = H * L + 2 * H + 1;
-    for (int i = threadIdx.x; i < P; i += kBlock) {
-        const float v = params[i];
-        if (i < H * L) sw[(i % L) * H + i / L] = bf16_round(v);  // W1[h][l] -> W1^T[l][h]
-        else if (i < H * L + H || i == P - 1) sw[i] = v;         // biases stay FP32
-        else sw[i] = bf16_round(v);                               // W2
-    }
+    const int P = mlp_lds_floats(L);
+    mlp_stage(params, L, sw);
     __syncthreads();
     const float *W1t = sw, *b1 = sw + H * L, *W2 = sw + H * L + H;
     const float b2 = sw[P - 1];
     const int lane = threadIdx.x & 63;
     const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
-    for (int64_t q = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); q < B; q += nwaves) {
+    // lane l < L holds feature l of the query (one load per query, the next
+    // query's in flight during this one); the sum takes them by broadcast
+    int64_t q = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    float fn = q < B && lane < L ? feats[q * L + lane] : 0.f;
+    for (; q < B; q += nwaves) {
+        const float fv = bf16_round(fn);
+        const int64_t qn = q + nwaves;
+        fn = qn < B && lane < L ? feats[qn * L + lane] : 0.f;
         float z = 0.f;
-        for (int l = 0; l < L; ++l) z = fmaf(W1t[l * H + lane], bf16_round(feats[q * L + l]), z);
+        for (int l = 0; l < L; ++l) z = fmaf(W1t[l * H + lane], __shfl(fv, l), z);
         const float zz = z + b1[lane];
         float y = W2[lane] * bf16_round(zz > 0.f ? zz : 0.f);
         for (int off = 32; off > 0; off >>= 1) y += __shfl_xor(y, off);
@@ -78,6 +72,7 @@ qw_status launch_mlp_predict_bf16(const float *params, int32_t L, const float *f
                                   float *out, hipStream_t s)
 {
     if (B <= 0) return QW_OK;
+    if (L > 64) return QW_EINVAL;  // one feature per lane
     const size_t lds = sizeof(float) * (H * L + 2 * H + 1);
     const int g = (int)std::min<int64_t>(2048, ceil_div(B, kBlock / 64));
     mlp_predict_bf16_kernel<<<g, kBlock, lds, s>>>(params, L, feats, B, out);

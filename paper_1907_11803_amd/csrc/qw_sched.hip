@@ -20,10 +20,36 @@ __device__ inline uint32_t mix32(uint64_t x)
     return (uint32_t)x;
 }
 
-// Size class of every query from its predicted number of unique candidates
+// Size class of a query from its predicted number of unique candidates
 // `need`: the smallest c >= cmin with 3/4 * 2^c >= need (hash-set load factor
 // <= 3/4).  Classes 0 .. ncls-2 are LDS classes (c = cmin + class), class
-// ncls-1 keeps its set in global memory.  Key = class << 16 | 16-bit group.
+// ncls-1 keeps its set in global memory.
+// has_pred: pred = the model's log(1 + |C(q)|) prediction.
+__device__ inline int class_of(uint64_t tsum, int64_t n, const int32_t *__restrict__ exact, int64_t q,
+                               bool has_pred, float pred, float margin, int32_t force_max,
+                               int32_t cmin, int32_t cfloor, int32_t cmax, int32_t ncls)
+{
+    // |C(q)| <= min(sum of the bucket sizes, n): the class of that bound
+    // always holds the set; a predicted or exact count may pick a smaller
+    // one, but never one below cfloor (no occupancy gained there)
+    const uint64_t bound = min(tsum, (uint64_t)n);
+    uint64_t need = bound;
+    if (exact) {
+        need = min(need, (uint64_t)exact[q]);
+    } else if (has_pred) {
+        const float p = expm1f(pred + margin) + 32.f;
+        if (p == p && p < (float)need) need = p > 0.f ? (uint64_t)ceilf(p) : 0;
+    }
+    int cb = cmin;
+    while (cb < 40 && (3ull << cb) < 4 * bound) ++cb;
+    int c = cmin;
+    while (c < 40 && (3ull << c) < 4 * need) ++c;
+    c = max(c, min(cb, cfloor));
+    if (force_max && c <= cmax) c = cmax;
+    return c <= cmax ? c - cmin : ncls - 1;
+}
+
+// Key = class << 16 | 16-bit group of every query, for the radix sort.
 __global__ __launch_bounds__(kBlock) void classify_kernel(
     int64_t Q, int32_t L, int64_t n,
     const uint32_t *__restrict__ bstart, const uint32_t *__restrict__ bsize,
@@ -37,26 +63,11 @@ __global__ __launch_bounds__(kBlock) void classify_kernel(
     __syncthreads();
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < Q;
          q += (int64_t)gridDim.x * blockDim.x) {
-        // |C(q)| <= min(sum of the bucket sizes, n): the class of that bound
-        // always holds the set; a predicted or exact count may pick a smaller
-        // one, but never one below cfloor (no occupancy gained there)
         uint64_t tsum = 0;
         for (int32_t l = 0; l < L; ++l) tsum += bsize[q * L + l];
-        const uint64_t bound = min(tsum, (uint64_t)n);
-        uint64_t need = bound;
-        if (exact) {
-            need = min(need, (uint64_t)exact[q]);
-        } else if (pred_log) {
-            const float p = expm1f(pred_log[q] + margin) + 32.f;
-            if (p == p && p < (float)need) need = p > 0.f ? (uint64_t)ceilf(p) : 0;
-        }
-        int cb = cmin;
-        while (cb < 40 && (3ull << cb) < 4 * bound) ++cb;
-        int c = cmin;
-        while (c < 40 && (3ull << c) < 4 * need) ++c;
-        c = max(c, min(cb, cfloor));
-        if (force_max && c <= cmax) c = cmax;
-        const int cls = c <= cmax ? c - cmin : ncls - 1;
+        const int cls = class_of(tsum, n, exact, q, pred_log != nullptr,
+                                 pred_log ? pred_log[q] : 0.f, margin, force_max, cmin, cfloor,
+                                 cmax, ncls);
         uint32_t g = 0;
         if (group) {
             for (int32_t l = 0; l < L; ++l) {
@@ -73,6 +84,77 @@ __global__ __launch_bounds__(kBlock) void classify_kernel(
     __syncthreads();
     if (threadIdx.x < ncls && hist[threadIdx.x])
         atomicAdd(&class_count[threadIdx.x], (unsigned long long)hist[threadIdx.x]);
+}
+
+// Without bucket grouping the order within a class is free, so one kernel
+// bins the queries: class c's queries go to order[c * Q ..) (any order), a
+// workgroup taking one range per class per round of kBlock queries with one
+// atomic on the class count.  The last workgroup to finish (its done-counter
+// increment sees every other one) writes seg[2c], seg[2c+1] = [c * Q,
+// c * Q + count_c).
+__global__ __launch_bounds__(kBlock) void classify_bin_kernel(
+    int64_t Q, int32_t L, int64_t n, const uint32_t *__restrict__ bsize,
+    const int32_t *__restrict__ exact, const float *__restrict__ pred_log, float margin,
+    int32_t force_max, int32_t cmin, int32_t cfloor, int32_t cmax, int32_t ncls,
+    int32_t *__restrict__ order, unsigned long long *class_count, uint32_t *done,
+    unsigned long long *__restrict__ seg)
+{
+    __shared__ uint32_t hist[32];
+    __shared__ unsigned long long base[32];
+    __shared__ uint32_t last;
+    const int tid = threadIdx.x;
+    for (int64_t q0 = (int64_t)blockIdx.x * kBlock; q0 < Q; q0 += (int64_t)gridDim.x * kBlock) {
+        const int64_t q = q0 + tid;
+        if (tid < 32) hist[tid] = 0;
+        __syncthreads();
+        int cls = 0;
+        uint32_t p = 0;
+        if (q < Q) {
+            uint64_t tsum = 0;
+            for (int32_t l0 = 0; l0 < L; l0 += 16) {  // 16 loads in flight at a time
+                uint32_t v[16];
+#pragma unroll
+                for (int32_t i = 0; i < 16; ++i) v[i] = l0 + i < L ? bsize[q * L + l0 + i] : 0u;
+#pragma unroll
+                for (int32_t i = 0; i < 16; ++i) tsum += v[i];
+            }
+            cls = class_of(tsum, n, exact, q, pred_log != nullptr, pred_log ? pred_log[q] : 0.f,
+                           margin, force_max, cmin, cfloor, cmax, ncls);
+            p = atomicAdd(&hist[cls], 1u);
+        }
+        __syncthreads();
+        if (tid < ncls && hist[tid])
+            base[tid] = atomicAdd(&class_count[tid], (unsigned long long)hist[tid]);
+        __syncthreads();
+        if (q < Q) order[(int64_t)cls * Q + (int64_t)(base[cls] + p)] = (int32_t)q;
+        __syncthreads();  // hist is cleared for the next round
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) last = atomicAdd(done, 1u) == gridDim.x - 1 ? 1u : 0u;
+    __syncthreads();
+    if (last && tid < ncls) {
+        __threadfence();
+        const unsigned long long cnt = atomicAdd(&class_count[tid], 0ull);  // device-coherent read
+        seg[2 * tid] = (unsigned long long)tid * (unsigned long long)Q;
+        seg[2 * tid + 1] = (unsigned long long)tid * (unsigned long long)Q + cnt;
+    }
+}
+
+qw_status launch_classify_bin(int64_t Q, int32_t L, int64_t n, const uint32_t *bsize,
+                              const int32_t *exact, const float *pred_log, float margin,
+                              int32_t force_max, int32_t cmin, int32_t cfloor, int32_t cmax,
+                              int32_t ncls, int32_t *order, unsigned long long *class_count,
+                              uint32_t *done, unsigned long long *seg, hipStream_t s)
+{
+    if (Q <= 0) return QW_OK;
+    if (ncls > 32 || L > kMaxL) return QW_EINVAL;
+    const int g = (int)std::min<int64_t>(1024, ceil_div(Q, kBlock));
+    classify_bin_kernel<<<g, kBlock, 0, s>>>(Q, L, n, bsize, exact, pred_log, margin, force_max,
+                                               cmin, cfloor, cmax, ncls, order, class_count, done,
+                                               seg);
+    QW_HIP(hipGetLastError());
+    return QW_OK;
 }
 
 qw_status launch_classify(int64_t Q, int32_t L, int64_t n,
