@@ -297,6 +297,7 @@ def main():
                            "unique": st["cand_unique"] / wl.Q},
         "overflow_queries": st["overflow"],
         "fallback_queries": st["fallback"],
+        "topk_second_pass_queries": st["topk_second_pass"],
         "bins": st["bins"],
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",

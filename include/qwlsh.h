@@ -101,6 +101,8 @@ typedef struct {
     int64_t cand_unique;   /* sum over queries of |C(q)| */
     int64_t overflow;      /* queries moved to a larger hash set because theirs was sized too small */
     int64_t fallback;      /* fast form: queries answered by the fused per-query path */
+    int64_t topk_second_pass; /* fast form, in-kernel top K: queries whose lanes' kept keys did
+                                 not settle the top K, selected by a second verify pass */
     int64_t bins[8];       /* queries per hash-set size class (fast form) */
     float ms_stage[8];     /* timing=1: hash, probe, schedule, candidates+verify+top-K,
                               fallback, total, dedup (fast form), gather (fast form) */

@@ -24,7 +24,7 @@ enum {
 };
 // u32: overflow-queue lengths per class (queue i holds queries that overflowed
 // class i-1), fallback queue, misc, then kXcd work counters per class
-enum { W_CLSDONE = 0, W_WORK = 1 /* .. 15: unused */, W_QCNT = 16 /* .. 32 */, W_SIMPLE = 33, W_MAX = 34,
+enum { W_CLSDONE = 0, W_TOPK2 = 1, W_WORK = 2 /* .. 15: unused */, W_QCNT = 16 /* .. 32 */, W_SIMPLE = 33, W_MAX = 34,
        W_DUMMY = 35, W_QMERGED = 36, W_FB = 44, W_FBWORK = 45, W_XWORK = 48,
        kC32 = W_XWORK + kXcd * (kMaxClasses + 1) };
 constexpr int kQueueMerged = kMaxClasses + 1;  // overflow queue of the merged launch
@@ -353,6 +353,7 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
             a.out_dist = out_dist;
             a.fb_count = c32(ix) + W_FB;
             a.fb_list = w.fb.as<int32_t>();
+            a.topk2_count = c32(ix) + W_TOPK2;
             a.ucount = w.ucount.as<uint32_t>();
             a.coff = w.coff.as<unsigned long long>();
             a.flag = w.flag.as<uint32_t>();
@@ -488,6 +489,7 @@ qw_status fill_stats(qw_index *ix, int64_t Q, hipStream_t s, qw_stats *st, hipEv
         st->overflow += (int64_t)h32[W_QMERGED];
     }
     st->fallback = fast ? (int64_t)h32[W_FB] : 0;
+    st->topk_second_pass = fast ? (int64_t)h32[W_TOPK2] : 0;
     if (fast)
         for (int i = 0; i < 8; ++i) st->bins[i] = (int64_t)h64[C_CLASS + i];
     if (ev) {

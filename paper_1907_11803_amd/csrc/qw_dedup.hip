@@ -75,10 +75,17 @@ __device__ inline void lane_top_insert(LaneTop &t, unsigned long long key, bool 
 // per step; the loop is unrolled twice so the two steps in flight alternate
 // between register sets.  Row addresses: a 24-bit multiply into a 32-bit
 // offset from the uniform data pointer when the data allows (A.addr32).
-template <int DT, bool TOPK>
+// MODE: kVerifyKeys writes every key to keys[i]; kVerifyTop feeds the lanes'
+// streams into `top`; kVerifyCollect appends every key at or below `bound` to
+// keys[] through the LDS counter *lcnt (entries past `cap` are counted, not
+// written).
+enum { kVerifyKeys = 0, kVerifyTop = 1, kVerifyCollect = 2 };
+
+template <int DT, int MODE>
 __device__ inline void verify_small(const DedupArgs &A, const uint32_t *list, uint32_t U,
                                     const uint4 *qrow, int parts, unsigned long long *keys,
-                                    uint32_t qq, LaneTop &top)
+                                    uint32_t qq, LaneTop &top, unsigned long long bound = 0,
+                                    uint32_t *lcnt = nullptr, uint32_t cap = 0)
 {
     constexpr int UN2 = 2;
     const int tid = threadIdx.x;
@@ -143,7 +150,18 @@ __device__ inline void verify_small(const DedupArgs &A, const uint32_t *list, ui
                 else
                     accf[u] += __shfl_xor(accf[u], o);
             }
-        if (TOPK) {
+        if (MODE == kVerifyCollect) {
+            if (j == 0)
+#pragma unroll
+                for (int u = 0; u < UN2; ++u) {
+                    const uint32_t i = base + (uint32_t)(grp + NG * u);
+                    const unsigned long long key = ((unsigned long long)(accu[u] + qq) << 32) | st.id[u];
+                    if (i < U && key <= bound) {
+                        const uint32_t pos = atomicAdd(lcnt, 1u);
+                        if (pos < cap) keys[pos] = key;
+                    }
+                }
+        } else if (MODE == kVerifyTop) {
             // row u of this step belongs to the stream of lane (base / NG + u) mod G
             // of the group (every lane of the group holds the reduced distance);
             // with G >= UN2 a lane owns at most one row of the step
@@ -188,8 +206,9 @@ __device__ inline void verify_small(const DedupArgs &A, const uint32_t *list, ui
     }
 }
 
-// Whole workgroup: key[off + i] = (squared distance << 32) | id for the U ids
-// list[0..U) against the query row qrow (parts 16-byte parts, in LDS).  A
+// Whole workgroup: keys[i] = (squared distance << 32) | id for the U ids
+// list[0..U) against the query row qrow (parts 16-byte parts, in LDS), or
+// the fused top K's modes of verify_small.  A
 // group of G lanes (a power of two >= parts, at most 64) holds one row, P
 // parts per lane; UN rows per group per step.  uint8 distances are
 // sum over parts of (|x|^2 - 2 x.q) plus |q|^2 taken once per query (exact in
@@ -197,10 +216,11 @@ __device__ inline void verify_small(const DedupArgs &A, const uint32_t *list, ui
 // squares of differences.  Rows of one part per lane: the
 // next step's rows are loaded before the current step is reduced, so two
 // steps are in flight.  No barriers.
-template <int DT, bool TOPK>
+template <int DT, int MODE>
 __device__ inline void verify_list(const DedupArgs &A, const uint32_t *list, uint32_t U,
-                                   const uint4 *qrow, int parts, unsigned long long off,
-                                   LaneTop &top)
+                                   const uint4 *qrow, int parts, unsigned long long *keys,
+                                   LaneTop &top, unsigned long long bound = 0,
+                                   uint32_t *lcnt = nullptr, uint32_t cap = 0)
 {
     constexpr int UN = 4;
     const int tid = threadIdx.x;
@@ -211,7 +231,6 @@ __device__ inline void verify_list(const DedupArgs &A, const uint32_t *list, uin
     const uint32_t PI = (uint32_t)(NG * UN);
     const int grp = tid / G, j = tid % G;
     const uint4 *drows = reinterpret_cast<const uint4 *>(A.data);
-    unsigned long long *keys = A.keys + off;
     // |q|^2 (uint8), the same in every group
     uint32_t qq = 0;
     if (DT == QW_U8) {
@@ -244,8 +263,8 @@ __device__ inline void verify_list(const DedupArgs &A, const uint32_t *list, uin
                 }
             }
     };
-    if (P == 1 || TOPK) {  // the fused top K runs only on rows of at most 64 parts
-        verify_small<DT, TOPK>(A, list, U, qrow, parts, keys, qq, top);
+    if (P == 1 || MODE != kVerifyKeys) {  // the fused top K runs only on rows of at most 64 parts
+        verify_small<DT, MODE>(A, list, U, qrow, parts, keys, qq, top, bound, lcnt, cap);
         return;
     }
     for (uint32_t base = 0; base < U; base += PI) {
@@ -283,23 +302,27 @@ __device__ inline void verify_list(const DedupArgs &A, const uint32_t *list, uin
     }
 }
 
-// Whole workgroup, fused top K of query q from the lanes' kept keys (uint8:
-// a key's high word is the exact squared distance).  lst (kTopList entries)
-// may be the set's memory: every read of the set is behind a barrier.
+// Whole workgroup, fused top K of query q (uint8: a key's high word is the
+// exact squared distance) from the lanes' kept keys.  tab holds the U unique
+// ids; the selection list follows them in the same memory (cap_words words
+// in all), so the ids stay readable for a second pass.
 //  1. the K-th smallest lane minimum of a wave bounds the K-th key of the
 //     union of kept keys (K lanes hold a key at or below it); B = the smallest
 //     such bound over the waves;
-//  2. the kept keys at or below B are collected in lst and ranked; ranks
-//     below K are the output, padded with (-1, INT32_MAX) below K entries;
+//  2. the kept keys at or below B are collected and ranked; ranks below K are
+//     the output, padded with (-1, INT32_MAX) below K entries;
 //  3. the union's top K is the query's top K unless some lane dropped a key
-//     below the union's K-th key (or fewer than K were found while a lane
-//     dropped any): then the query goes to the fallback, as it does when the
-//     list exceeds its capacity.
+//     below the union's K-th key T (or fewer than K were kept while a lane
+//     dropped any).  Then a second pass verifies the candidates again and
+//     collects every key at or below T (T is at least the true K-th key, so
+//     that set holds the top K) and ranks those.  A list beyond its capacity
+//     sends the query to the fallback.
 // A.topk_keep < kTopR keeps fewer keys per lane (a diagnostic: more queries
-// reach the fallback; the result does not change).
-template <bool GLOB>
-__device__ inline void fused_topk(const DedupArgs &A, int64_t q, LaneTop t,
-                                  unsigned long long *lst, uint32_t *scal)
+// take the second pass; the result does not change).
+template <bool GLOB, int DT>
+__device__ inline void fused_topk(const DedupArgs &A, int64_t q, LaneTop t, const uint32_t *tab,
+                                  uint32_t U, uint32_t cap_words, const uint4 *qrow, int parts,
+                                  uint32_t *scal)
 {
     const int tid = threadIdx.x, lane = tid & 63;
     const int K = A.topk;
@@ -309,12 +332,48 @@ __device__ inline void fused_topk(const DedupArgs &A, int64_t q, LaneTop t,
             t.dmin = t.k[r] < t.dmin ? t.k[r] : t.dmin;
             t.k[r] = ~0ull;
         }
+    const uint32_t loff = (U + 1u) & ~1u;  // 8-byte aligned
+    unsigned long long *lst = reinterpret_cast<unsigned long long *>(const_cast<uint32_t *>(tab) + loff);
+    const uint32_t lcap = min(kTopList, (cap_words - loff) / 2u);
     const unsigned long long lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     unsigned long long *s_bound = reinterpret_cast<unsigned long long *>(&scal[D_BOUND]);
     unsigned long long *s_kth = reinterpret_cast<unsigned long long *>(&scal[D_KTH]);
     auto sync = [&]() {
         if (GLOB) __threadfence();
         __syncthreads();
+    };
+    // ranks of the c keys lst[0..c) (unique) below K to the output; the K-th
+    // key to *s_kth (left unchanged when c < K)
+    auto rank_write = [&](uint32_t c) {
+        if (c <= 64) {  // the usual case: one wave sorts the list
+            if (tid < 64) {
+                const unsigned long long v = wave_sort_u64(lane < (int)c ? lst[lane] : ~0ull);
+                if (lane < K) {
+                    const int64_t o = q * K + lane;
+                    const bool has = lane < (int)c;
+                    A.out_ids[o] = has ? (int32_t)(uint32_t)v : -1;
+                    reinterpret_cast<int32_t *>(A.out_dist)[o] = has ? (int32_t)(v >> 32) : INT32_MAX;
+                }
+                if (lane == K - 1 && lane < (int)c) *s_kth = v;
+            }
+            return;
+        }
+        for (uint32_t i = tid; i < c; i += kBlock) {
+            const unsigned long long k = lst[i];
+            int r = 0;
+            for (uint32_t e = 0; e < c; ++e) r += lst[e] < k;
+            if (r < K) {
+                const int64_t o = q * K + r;
+                A.out_ids[o] = (int32_t)(uint32_t)k;
+                reinterpret_cast<int32_t *>(A.out_dist)[o] = (int32_t)(k >> 32);
+            }
+            if (r == K - 1) *s_kth = k;  // keys are unique: one writer
+        }
+        for (int r = (int)c + tid; r < K; r += kBlock) {
+            const int64_t o = q * K + r;
+            A.out_ids[o] = -1;
+            reinterpret_cast<int32_t *>(A.out_dist)[o] = INT32_MAX;
+        }
     };
     if (tid == 0) {
         scal[D_LCNT] = 0;
@@ -335,46 +394,37 @@ __device__ inline void fused_topk(const DedupArgs &A, int64_t q, LaneTop t,
         if (lane == 0 && m) wb = atomicAdd(&scal[D_LCNT], (uint32_t)__popcll(m));
         wb = (uint32_t)__shfl((int)wb, 0);
         const uint32_t pos = wb + (uint32_t)__popcll(m & lt_mask);
-        if (take && pos < kTopList) lst[pos] = t.k[r];
+        if (take && pos < lcap) lst[pos] = t.k[r];
     }
     sync();
     const uint32_t c = scal[D_LCNT];
-    const bool over = c > kTopList;
-    if (!over && c <= 64) {  // the usual case: one wave sorts the list
-        if (tid < 64) {
-            const unsigned long long v = wave_sort_u64(lane < (int)c ? lst[lane] : ~0ull);
-            if (lane < K) {
-                const int64_t o = q * K + lane;
-                const bool has = lane < (int)c;
-                A.out_ids[o] = has ? (int32_t)(uint32_t)v : -1;
-                reinterpret_cast<int32_t *>(A.out_dist)[o] = has ? (int32_t)(v >> 32) : INT32_MAX;
-            }
-            if (lane == K - 1 && lane < (int)c) *s_kth = v;
-        }
-    } else if (!over) {
-        for (uint32_t i = tid; i < c; i += kBlock) {
-            const unsigned long long k = lst[i];
-            int r = 0;
-            for (uint32_t e = 0; e < c; ++e) r += lst[e] < k;
-            if (r < K) {
-                const int64_t o = q * K + r;
-                A.out_ids[o] = (int32_t)(uint32_t)k;
-                reinterpret_cast<int32_t *>(A.out_dist)[o] = (int32_t)(k >> 32);
-            }
-            if (r == K - 1) *s_kth = k;  // keys are unique: one writer
-        }
-        for (int r = (int)c + tid; r < K; r += kBlock) {
-            const int64_t o = q * K + r;
-            A.out_ids[o] = -1;
-            reinterpret_cast<int32_t *>(A.out_dist)[o] = INT32_MAX;
-        }
+    if (c > lcap) {  // uniform
+        if (tid == 0) A.fb_list[atomicAdd(A.fb_count, 1u)] = (int32_t)q;
+        return;
     }
+    rank_write(c);
     sync();
-    const unsigned long long kth = *s_kth;  // ~0 when fewer than K were found
-    const bool unsure = t.dmin != ~0ull && t.dmin <= kth;
+    const unsigned long long T = *s_kth;  // ~0 when fewer than K were kept
+    const bool unsure = t.dmin != ~0ull && t.dmin <= T;
     if (__ballot(unsure) != 0ull && lane == 0) scal[D_BAD] = 1;
     sync();
-    if (tid == 0 && (over || scal[D_BAD])) A.fb_list[atomicAdd(A.fb_count, 1u)] = (int32_t)q;
+    if (!scal[D_BAD]) return;  // uniform
+    // second pass: every key at or below T
+    sync();  // every thread has read D_BAD and the list
+    if (tid == 0) {
+        scal[D_LCNT] = 0;
+        atomicAdd(A.topk2_count, 1u);
+    }
+    sync();
+    LaneTop unused;
+    verify_list<DT, kVerifyCollect>(A, tab, U, qrow, parts, lst, unused, T, &scal[D_LCNT], lcap);
+    sync();
+    const uint32_t c2 = scal[D_LCNT];
+    if (c2 > lcap) {
+        if (tid == 0) A.fb_list[atomicAdd(A.fb_count, 1u)] = (int32_t)q;
+        return;
+    }
+    rank_write(c2);
 }
 
 // One workgroup per query (persistent).  The workgroups of XCD x take items
@@ -576,11 +626,11 @@ __global__ __launch_bounds__(kBlock, 4) void dedup_kernel(DedupArgs A)
             for (int r = 0; r < kTopR; ++r) top.k[r] = ~0ull;
             top.dmin = ~0ull;
             if (DT == QW_U8 && A.topk) {
-                verify_list<DT, true>(A, tab, U, qrow, parts, off, top);
-                bar();  // the set's memory becomes the selection list
-                fused_topk<GLOB>(A, q, top, reinterpret_cast<unsigned long long *>(tab), scal);
+                verify_list<DT, kVerifyTop>(A, tab, U, qrow, parts, nullptr, top);
+                // the selection list goes into the set's memory after the ids
+                fused_topk<GLOB, DT>(A, q, top, tab, U, 1u << A.cap_log2, qrow, parts, scal);
             } else {
-                verify_list<DT, false>(A, tab, U, qrow, parts, off, top);
+                verify_list<DT, kVerifyKeys>(A, tab, U, qrow, parts, A.keys + off, top);
             }
         } else if (off != ~0ull && in_regs) {
             unsigned long long e = off + wbase;

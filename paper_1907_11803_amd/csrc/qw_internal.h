@@ -311,6 +311,7 @@ struct DedupArgs {
     void *out_dist;
     uint32_t *fb_count;
     int32_t *fb_list;
+    uint32_t *topk2_count;           // queries that took the second selection pass
 };
 
 struct GatherArgs {

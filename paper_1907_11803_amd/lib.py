@@ -43,6 +43,7 @@ class qw_stats(ctypes.Structure):
                 ("recompute_frac", ctypes.c_double), ("probes_hit", ctypes.c_int64),
                 ("cand_total", ctypes.c_int64), ("cand_unique", ctypes.c_int64),
                 ("overflow", ctypes.c_int64), ("fallback", ctypes.c_int64),
+                ("topk_second_pass", ctypes.c_int64),
                 ("bins", ctypes.c_int64 * 8),
                 ("ms_stage", ctypes.c_float * 8)]
 

@@ -152,8 +152,8 @@ def test_fast_form_schedules_identical(cfg1, sched, group):
 def test_fused_topk_keep_and_fallback(cfg1, keep):
     """In-kernel top K (uint8, K <= 16) and the separate select kernel (keep
     -1) give the oracle's answer; keeping fewer keys per lane sends queries
-    to the fallback without changing the result.  w = 3000 gives 1.2K-6.7K
-    unique candidates per query, several per lane."""
+    to the second selection pass without changing the result.  w = 3000
+    gives 1.2K-6.7K unique candidates per query, several per lane."""
     p = cfg1.params
     w = 3000.0
     ix = build(cfg1.data, p.a, p.b(w), w)
@@ -164,9 +164,9 @@ def test_fused_topk_keep_and_fallback(cfg1, keep):
             ids, dist, st = ix.query(dev(cfg1.queries), K, opts, stats=True)
             check_topk(ids, dist, ids_o, dist_o, True)
             if keep == 1 and K == 16:
-                assert st["fallback"] > 0
+                assert st["topk_second_pass"] > 0
             if keep == -1:
-                assert st["fallback"] == 0
+                assert st["fallback"] == 0 and st["topk_second_pass"] == 0
 
 
 def test_ragged_u8_and_topk_sizes():
