@@ -65,7 +65,6 @@ def kernel_source_hash(files):
 
 
 FUSED_SOURCES = ("qw_dedup.hip", "qw_dedup.h", "qw_dist.h", "qw_wave.h")
-GATHER_SOURCES = ("qw_gather.hip", "qw_dist.h")
 
 
 def main():
@@ -83,7 +82,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this engine has no multi-GPU path (queries or data "
-              "would be sharded across GPUs with one gather of Q x K results; see DESIGN.md).",
+              "would be sharded across GPUs with one gather of Q x K results).",
               file=sys.stderr)
         sys.exit(2)
 
@@ -208,27 +207,20 @@ def main():
     L = wl.params.L
     alg_bytes = (wl.Q * wl.d * elem + 8 * L * wl.Q + 4 * st["cand_total"] +
                  st["cand_unique"] * wl.d * elem + 8 * K * wl.Q)
-    # Dominant kernel.  Fused form (no separate gather launch): the dedup
-    # kernel, which also verifies its candidates; algorithmic bytes per query:
-    # the bucket ids (4 per entry), each unique candidate's row, the query row,
-    # and either each candidate's (distance, id) key for the select kernel or,
-    # when the kernel selects the top K itself (uint8 rows of at most 1024
-    # bytes, K <= 16, the library's rule), the K output pairs.  Otherwise the
-    # streaming gather: per pair the row, the (id, query) pair and the key;
-    # plus each query row.
-    fused = float(stage[7]) < 0.02 * float(stage[6])
+    # Dominant kernel: the dedup kernel, which also verifies its candidates;
+    # algorithmic bytes per query: the bucket ids (4 per entry), each unique
+    # candidate's row, the query row, and either each candidate's
+    # (distance, id) key for the select kernel or, when the kernel selects the
+    # top K itself (uint8 rows of at most 1024 bytes, K <= 16, the library's
+    # rule), the K output pairs.  Its time: the dedup stage (all of its
+    # launches of one step, on two streams).
     topk_fused = is_u8 and K <= 16 and (wl.d + 15) // 16 <= 64
-    if fused:
-        kname, ksrc, kfile = "dedup_kernel (dedup + verify + top-K)" if topk_fused else \
-            "dedup_kernel (dedup + verify)", FUSED_SOURCES, "dedup_verify"
-        per_cand = wl.d * elem + (0 if topk_fused else 8)
-        kbytes = (4 * st["cand_total"] + st["cand_unique"] * per_cand + wl.Q * wl.d * elem +
-                  (8 * K * wl.Q if topk_fused else 0))
-        kms = float(stage[6])
-    else:
-        kname, ksrc, kfile = "gather_kernel", GATHER_SOURCES, "gather"
-        kbytes = st["cand_unique"] * (wl.d * elem + 16) + wl.Q * wl.d * elem
-        kms = float(stage[7])
+    kname = "dedup_kernel (dedup + verify + top-K)" if topk_fused else "dedup_kernel (dedup + verify)"
+    ksrc, kfile = FUSED_SOURCES, "dedup_verify"
+    per_cand = wl.d * elem + (0 if topk_fused else 8)
+    kbytes = (4 * st["cand_total"] + st["cand_unique"] * per_cand + wl.Q * wl.d * elem +
+              (8 * K * wl.Q if topk_fused else 0))
+    kms = float(stage[6])
     achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else None
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"{kfile}_cfg{args.config}_traffic.json")
@@ -288,8 +280,7 @@ def main():
         "sched_ms_per_step": sched_ms,
         "stage_ms": {"hash": round(stage[0], 4), "probe": round(stage[1], 4),
                      "schedule": round(stage[2], 4), "dedup": round(stage[6], 4),
-                     "gather": round(stage[7], 4),
-                     "select": round(stage[3] - stage[6] - stage[7], 4),
+                     "select": round(stage[7], 4),
                      "candidates_verify_topk": round(stage[3], 4),
                      "fallback": round(stage[4], 4), "total": round(stage[5], 4)},
         "recompute_frac": st["recompute_frac"],

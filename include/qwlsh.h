@@ -62,8 +62,9 @@ typedef enum {
     QW_FORM_PLAIN_FP32 = 0,
     /* FP16 (uint8 data) or FP32 (float data) MFMA projections with an FP64 guard
      * band; queries binned by predicted candidate count (optionally grouped by
-     * bucket) into persistent dedup-and-verify kernels, then a per-query top-K
-     * select; replayed from a HIP graph. */
+     * bucket) into persistent dedup-and-verify kernels that also select the
+     * top K (uint8 rows of at most 1024 bytes, K <= 16; otherwise a per-query
+     * select kernel does); replayed from a HIP graph. */
     QW_FORM_FAST = 1
 } qw_form;
 
@@ -105,7 +106,8 @@ typedef struct {
                                  not settle the top K, selected by a second verify pass */
     int64_t bins[8];       /* queries per hash-set size class (fast form) */
     float ms_stage[8];     /* timing=1: hash, probe, schedule, candidates+verify+top-K,
-                              fallback, total, dedup (fast form), gather (fast form) */
+                              fallback, total, dedup + verify (fast form; with the top K where
+                              the kernel selects it), select kernel (fast form) */
 } qw_stats;
 
 typedef struct {

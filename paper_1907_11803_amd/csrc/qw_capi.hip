@@ -85,11 +85,10 @@ Plan make_plan(qw_index *ix, int K)
     // (32 KiB of keys, 64 KiB with the FP64 re-rank of float data)
     static_assert(kMaxTopK <= 1024 && kBlock <= 1024, "select list sizing");
     p.LC = pow2_at_least(std::max(1024, 4 * K));
-    p.ggrid = gather_blocks_per_cu(ix->dp, ix->dtype) * ix->cus;
     // uint8 rows of at most 64 parts and small K: the dedup kernel selects
     // the top K itself
-    p.topk = (ix->dtype == QW_U8 && p.fuse && K <= kFusedTopK && rbytes / 16 <= 64) ? K : 0;
-    {  // FP32 distance bound of the gather kernel (float data)
+    p.topk = (ix->dtype == QW_U8 && K <= kFusedTopK && rbytes / 16 <= 64) ? K : 0;
+    {  // FP32 distance bound of the dedup kernel's verification (float data)
         const int parts = ix->dp * (ix->dtype == QW_U8 ? 1 : 4) / 16;
         int G = 1;
         while (G < parts && G < 64) G <<= 1;
@@ -100,9 +99,9 @@ Plan make_plan(qw_index *ix, int K)
     return p;
 }
 
-// Grow the query workspace for Q queries; drops captured graphs when any
-// buffer moves.
-qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan)
+// Grow the query workspace for Q queries (keys: the key list of the select
+// kernel); drops captured graphs when any buffer moves.
+qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan, bool keys = false)
 {
     Workspace &w = ix->ws;
     auto ptrs = [&w]() {
@@ -111,7 +110,7 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan)
                                    w.binoff.p, w.counters.p, w.ovf.p, w.gscratch.p, w.mlpout.p,
                                    w.order.p,
                                    w.hist.p, w.scan.p, w.ucount.p, w.coff.p, w.flag.p,
-                                   w.cand.p, w.candq.p, w.pkeys.p, w.fb.p};
+                                   w.pkeys.p, w.fb.p};
     };
     const std::vector<void *> before = ptrs();
     const size_t elem = ix->dtype == QW_U8 ? 1 : 4;
@@ -141,11 +140,7 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan)
         const int64_t cand_cap = std::max<int64_t>(q * kCandPerQuery, 1 << 20);
         QW_TRY(w.coff.ensure(sizeof(unsigned long long) * q));
         QW_TRY(w.flag.ensure(sizeof(uint32_t) * q));
-        if (!plan->fuse) {  // pair list for the streaming gather
-            QW_TRY(w.cand.ensure(sizeof(int32_t) * cand_cap));
-            QW_TRY(w.candq.ensure(sizeof(int32_t) * cand_cap));
-        }
-        QW_TRY(w.pkeys.ensure(sizeof(unsigned long long) * cand_cap));
+        if (keys) QW_TRY(w.pkeys.ensure(sizeof(unsigned long long) * cand_cap));
         QW_TRY(w.fb.ensure(sizeof(int32_t) * q));
     }
     if (before != ptrs()) drop_graphs(ix);
@@ -261,8 +256,9 @@ qw_status check_index(const qw_index *ix)
 }
 
 // Fast form: exact MFMA hashing, probe, schedule (size classes from the
-// selected count source, bucket grouping), per-class dedup into per-XCD pair
-// regions, gather, select, fallback.
+// selected count source, optional bucket grouping), per-class dedup kernels
+// that verify their candidates and either select the top K themselves or
+// write keys into per-XCD regions for the select kernel, then the fallback.
 qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int64_t Q, int K,
                        const qw_opts &o, hipStream_t s, int32_t *out_ids, void *out_dist,
                        hipEvent_t *ev)
@@ -335,9 +331,6 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
             a.alloc = c64(ix) + C_ALLOC;
             a.fail = c64(ix) + C_FAIL;
             a.region = (unsigned long long)(cand_cap / kXcd);
-            a.cand = w.cand.as<int32_t>();
-            a.candq = w.candq.as<int32_t>();
-            a.fuse = plan.fuse;
             a.dp = ix->dp;
             a.dtype = ix->dtype;
             a.data = ix->data.p;
@@ -409,20 +402,6 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     if (ev) QW_HIP(hipEventRecord(ev[3], s));
     QW_TRY(dedup_classes(order, 0));
     if (ev) QW_HIP(hipEventRecord(ev[6], s));
-    GatherArgs g;
-    std::memset(&g, 0, sizeof(g));
-    g.alloc = c64(ix) + C_ALLOC;
-    g.fail = c64(ix) + C_FAIL;
-    g.region = (unsigned long long)(cand_cap / kXcd);
-    g.cand = w.cand.as<int32_t>();
-    g.candq = w.candq.as<int32_t>();
-    g.data = ix->data.p;
-    g.queries = w.qrows;
-    g.dp = ix->dp;
-    g.dtype = ix->dtype;
-    g.keys = w.pkeys.as<unsigned long long>();
-    if (!plan.fuse) QW_TRY(launch_gather(g, plan.ggrid, s));
-    if (ev) QW_HIP(hipEventRecord(ev[7], s));
     SelectArgs m;
     std::memset(&m, 0, sizeof(m));
     m.keys = w.pkeys.as<unsigned long long>();
@@ -500,9 +479,9 @@ qw_status fill_stats(qw_index *ix, int64_t Q, hipStream_t s, qw_stats *st, hipEv
         if (hipEventElapsedTime(&ms, ev[3], ev[4]) == hipSuccess) st->ms_stage[3] = ms;
         if (hipEventElapsedTime(&ms, ev[4], ev[5]) == hipSuccess) st->ms_stage[4] = ms;
         if (hipEventElapsedTime(&ms, ev[0], ev[5]) == hipSuccess) st->ms_stage[5] = ms;
-        if (fast) {  // dedup, gather (select = stage 3 minus both)
+        if (fast) {  // dedup (with the verification, and the top K where fused), select
             if (hipEventElapsedTime(&ms, ev[3], ev[6]) == hipSuccess) st->ms_stage[6] = ms;
-            if (hipEventElapsedTime(&ms, ev[6], ev[7]) == hipSuccess) st->ms_stage[7] = ms;
+            if (hipEventElapsedTime(&ms, ev[6], ev[4]) == hipSuccess) st->ms_stage[7] = ms;
         }
         (void)hipGetLastError();
     }
@@ -644,7 +623,7 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
             return QW_OK;
         }
         const Plan plan = make_plan(ix, K);
-        QW_TRY(ensure_ws(ix, Q, &plan));
+        QW_TRY(ensure_ws(ix, Q, &plan, !(opt.topk_keep >= 0 && plan.topk)));
         const bool learned = opt.sched == QW_SCHED_LEARNED && !ix->mlp.empty();
         const int sched = opt.sched == QW_SCHED_LEARNED && !learned ? QW_SCHED_SUM : opt.sched;
         qw_opts eff = opt;

@@ -1,14 +1,12 @@
 // Candidate dedup of the fast form: one workgroup per query builds C(q)
 // (the union of the query's buckets, Sections 1.2 and 5.1) in an LDS hash set
-// sized by its size class.  Fused mode then verifies its unique candidates
-// itself -- gathers their rows, computes the exact squared distances (the
-// false-positive removal of Section 1.2) and either selects the K nearest
-// itself (uint8, small K) or writes one (distance, id) key per candidate into
-// the query's range of its XCD's key region for the select kernel; otherwise
-// it writes the unique ids, each tagged with its query, for the streaming
-// gather.  Queries whose set overflows move to the next size class; queries
-// the region cannot hold, or whose top K the fused selection cannot settle,
-// go to the fallback.
+// sized by its size class, then verifies its unique candidates itself --
+// gathers their rows, computes the exact squared distances (the false-
+// positive removal of Section 1.2) and either selects the K nearest itself
+// (uint8, small K) or writes one (distance, id) key per candidate into the
+// query's range of its XCD's key region for the select kernel.  Queries whose
+// set overflows move to the next size class; queries the region cannot hold,
+// or whose top K the fused selection cannot settle, go to the fallback.
 #include "qw_dedup.h"
 #include "qw_dist.h"
 #include "qw_internal.h"
@@ -25,7 +23,7 @@ constexpr int kRegIds = 16;  // ids per thread of the register-resident path
 
 __host__ __device__ inline size_t a16(size_t v) { return (v + 15) & ~size_t(15); }
 
-// set | layer prefix | layer starts | scalars | query row (fused mode)
+// set | layer prefix | layer starts | scalars | query row
 size_t dedup_lds_bytes(int cap_log2, int global_tab, int L, int row_bytes)
 {
     return (global_tab ? 0 : (size_t(4) << cap_log2)) + a16(size_t(L + 1) * 4) +
@@ -515,9 +513,8 @@ __global__ __launch_bounds__(kBlock, 4) void dedup_kernel(DedupArgs A)
             lstart[tid] = pf_start;
             lpref[tid + 1] = pf_size;
         }
-        if (A.fuse)  // the query row, for the verification at the end
-            for (int i = tid; i < parts; i += kBlock)
-                qrow[i] = reinterpret_cast<const uint4 *>(A.queries)[q * parts + i];
+        for (int i = tid; i < parts; i += kBlock)  // the query row, for the verification
+            qrow[i] = reinterpret_cast<const uint4 *>(A.queries)[q * parts + i];
         if (tid == 0) {
             scal[D_UCOUNT] = 0;
             scal[D_OVF] = 0;
@@ -574,7 +571,7 @@ __global__ __launch_bounds__(kBlock, 4) void dedup_kernel(DedupArgs A)
             ovf = scal[D_OVF] != 0 || U > limit;
         } else {
             set_union(A.ids, A.n, A.L, lpref, lstart, T, tab, cap_log2, limit, glob, max_probe,
-                      A.fuse != 0, &scal[D_UCOUNT], &scal[D_OVF], &scal[D_CPOS]);
+                      true, &scal[D_UCOUNT], &scal[D_OVF], &scal[D_CPOS]);
             U = scal[D_UCOUNT];
             ovf = scal[D_OVF] != 0 || U > limit;
         }
@@ -612,7 +609,7 @@ __global__ __launch_bounds__(kBlock, 4) void dedup_kernel(DedupArgs A)
             pf_start = A.bstart[qn * A.L + tid];
             pf_size = A.bsize[qn * A.L + tid];
         }
-        if (off != ~0ull && A.fuse) {
+        if (off != ~0ull) {
             // the unique ids into tab[0..U) (the set path compacted already)
             if (in_regs) {
                 uint32_t e = wbase;
@@ -632,36 +629,6 @@ __global__ __launch_bounds__(kBlock, 4) void dedup_kernel(DedupArgs A)
             } else {
                 verify_list<DT, kVerifyKeys>(A, tab, U, qrow, parts, A.keys + off, top);
             }
-        } else if (off != ~0ull && in_regs) {
-            unsigned long long e = off + wbase;
-#pragma unroll
-            for (int r = 0; r < kRegIds; ++r)
-                if ((newm >> r) & 1u) {
-                    A.cand[e] = (int32_t)idr[r];
-                    A.candq[e] = (int32_t)q;
-                    ++e;
-                }
-        } else if (off != ~0ull) {
-            // read the set back: wave w takes slots [w * cap / 4, (w + 1) * cap / 4)
-            const uint32_t seg = cap / (kBlock / 64);
-            const uint32_t s0 = (uint32_t)wave * seg;
-            uint32_t cnt = 0;
-            for (uint32_t i = s0 + lane; i < s0 + seg; i += 64)
-                cnt += (uint32_t)__popcll(__ballot(tab[i] != kEmpty));
-            if (lane == 0) scal[D_WT + wave] = cnt;
-            bar();
-            uint32_t tot = 0;
-            unsigned long long e = off + wave_base(scal, wave, &tot);
-            for (uint32_t i = s0 + lane; i < s0 + seg; i += 64) {
-                const uint32_t v = tab[i];
-                const unsigned long long m = __ballot(v != kEmpty);
-                if (v != kEmpty) {
-                    const unsigned long long p = e + (uint32_t)__popcll(m & lt_mask);
-                    A.cand[p] = (int32_t)v;
-                    A.candq[p] = (int32_t)q;
-                }
-                e += (uint32_t)__popcll(m);
-            }
         }
         bar();  // scal and the set are rewritten by the next item
     }
@@ -672,7 +639,7 @@ qw_status launch_dedup(const DedupArgs &a, int grid, hipStream_t s)
     if (grid <= 0) return QW_OK;
     // the fused top K: uint8 rows of at most 64 parts, 1 <= K <= kFusedTopK
     if (a.topk && (a.dtype != QW_U8 || a.dp > 64 * 16 || a.topk > kFusedTopK || a.topk < 0 ||
-                   !a.fuse || a.topk_keep < 1 || a.topk_keep > kTopR))
+                   a.topk_keep < 1 || a.topk_keep > kTopR))
         return QW_EINVAL;
     const size_t lds = dedup_lds_bytes((int)a.cap_log2, a.global_tab, a.L,
                                        a.dp * (a.dtype == QW_U8 ? 1 : 4));

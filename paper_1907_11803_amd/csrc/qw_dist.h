@@ -1,5 +1,5 @@
-// Squared L2 distance pieces shared by the gather and the fused dedup-gather
-// (the false-positive removal of Section 1.2).
+// Squared L2 distance pieces of the dedup kernel's verification (the
+// false-positive removal of Section 1.2).
 #pragma once
 
 #include "qw_internal.h"

@@ -71,7 +71,7 @@ struct Workspace {
     DevBuf qpad, h, bstart, bsize, pred, feats, keys, keys2, vals, vals2, hist,
         order, binoff, counters, ovf, gscratch, mlpout, scan;
     // flat pipeline
-    DevBuf ucount, coff, flag, cand, candq, pkeys, fb;
+    DevBuf ucount, coff, flag, pkeys, fb;
     // the query rows the kernels of the current call read: the caller's own
     // (no padding needed) or qpad
     const void *qrows = nullptr;
@@ -86,10 +86,8 @@ struct Plan {
     int ncls = 2;       // LDS classes + 1 global class
     int dgrid[16] = {}; // dedup kernel, per class
     int cap_g = 20, grid_g = 1;
-    int fuse = 1;       // dedup verifies its own candidates (no pair list, no gather)
     int topk = 0;       // dedup also selects the top K (0: the select kernel does)
     int LC = 2048;      // select kernel list capacity (entries)
-    int ggrid = 256;    // gather grid
     float eps = 0.f;    // FP32 distance bound (float data)
 };
 
@@ -282,22 +280,19 @@ struct DedupArgs {
     int32_t global_tab;
     uint32_t *gscratch;              // 2^cap_log2 words per workgroup (global_tab)
     int32_t count_only;              // write |C(q)| only
-    // the pair list is cut into kXcd regions of `region` pairs; region x is
-    // filled by the workgroups of XCD x (blockIdx % kXcd) through its own
-    // bump allocator alloc[x]; fail[x] keeps the complement of the lowest
-    // offset refused there (0 = none), so region x holds the granted lists
-    // in [x * region, x * region + min(alloc[x], ~fail[x]))
+    // the key list (select kernel) is cut into kXcd regions of `region` keys;
+    // region x is filled by the workgroups of XCD x (blockIdx % kXcd) through
+    // its own bump allocator alloc[x]; fail[x] keeps the complement of the
+    // lowest offset refused there (0 = none), so region x holds the granted
+    // lists in [x * region, x * region + min(alloc[x], ~fail[x]))
     unsigned long long *alloc;       // [kXcd]
     unsigned long long *fail;        // [kXcd]
     unsigned long long region;
-    int32_t *cand;                   // unique candidate lists (pair -> id)
-    int32_t *candq;                  // pair -> query
     uint32_t *ucount;                // |C(q)|
-    unsigned long long *coff;        // offset of each query's list in cand
+    unsigned long long *coff;        // offset of each query's keys
     uint32_t *flag;                  // 1 = answer q with the fallback
-    // fused mode: verify the unique candidates in place and write
-    // keys[coff + i] = (squared distance << 32) | id instead of cand/candq
-    int32_t fuse;
+    // every unique candidate is verified in place: keys[coff + i] =
+    // (squared distance << 32) | id, or the fused top K below
     int32_t dp, dtype;
     int32_t addr32;                  // n * row bytes < 2^32 and n < 2^24: 32-bit row offsets
     const void *data, *queries;
@@ -314,14 +309,6 @@ struct DedupArgs {
     uint32_t *topk2_count;           // queries that took the second selection pass
 };
 
-struct GatherArgs {
-    const unsigned long long *alloc, *fail;  // per-XCD region fill (see DedupArgs)
-    unsigned long long region;
-    const int32_t *cand, *candq;       // pair -> candidate id, query
-    const void *data, *queries;
-    int32_t dp, dtype;
-    unsigned long long *keys;          // pair -> (distance << 32) | id
-};
 
 struct SelectArgs {
     const unsigned long long *keys;
@@ -340,8 +327,6 @@ struct SelectArgs {
 size_t dedup_lds_bytes(int cap_log2, int global_tab, int L, int row_bytes);
 int dedup_blocks_per_cu(size_t lds, int dtype);
 qw_status launch_dedup(const DedupArgs &a, int grid, hipStream_t s);
-int gather_blocks_per_cu(int dp, int dtype);
-qw_status launch_gather(const GatherArgs &a, int grid, hipStream_t s);
 size_t select_lds_bytes(int LC, int dtype);
 qw_status launch_select(const SelectArgs &a, int64_t Q, hipStream_t s);
 // Scratch bytes launch_scan_u32_to_u64 needs for `count` values.
