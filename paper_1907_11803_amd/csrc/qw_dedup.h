@@ -157,7 +157,7 @@ __device__ inline uint32_t load_ids(const int32_t *__restrict__ ids, int64_t n, 
 // place: tab[0..U) holds the unique ids (unspecified order).  *ucount, *ovf
 // and *cpos must be 0 and visible to all threads on entry; returns after a
 // barrier.
-__device__ inline void set_union(const int32_t *__restrict__ ids, int64_t n, int32_t L,
+__device__ __attribute__((always_inline)) inline void set_union(const int32_t *__restrict__ ids, int64_t n, int32_t L,
                                  const uint32_t *lpref, const uint32_t *lstart, uint32_t T,
                                  uint32_t *tab, int cap_log2, uint32_t limit, bool glob,
                                  uint32_t max_probe, bool compact, uint32_t *ucount,
@@ -166,6 +166,9 @@ __device__ inline void set_union(const int32_t *__restrict__ ids, int64_t n, int
     constexpr int R = 8;
     const int tid = threadIdx.x, lane = tid & 63;
     const unsigned long long lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+    // the next round's ids load while this round's are inserted
+    uint32_t idn[R];
+    uint32_t pn = load_ids<R>(ids, n, L, lpref, lstart, T, 0u, idn);
     for (uint32_t base = 0; base < T; base += R * kBlock) {
         // every thread reads the flag before any thread of this pass can set
         // it, so the early exit is uniform
@@ -173,7 +176,10 @@ __device__ inline void set_union(const int32_t *__restrict__ ids, int64_t n, int
         __syncthreads();
         if (stop) break;
         uint32_t idr[R];
-        const uint32_t pend = load_ids<R>(ids, n, L, lpref, lstart, T, base, idr);
+#pragma unroll
+        for (int r = 0; r < R; ++r) idr[r] = idn[r];
+        const uint32_t pend = pn;
+        if (base + R * kBlock < T) pn = load_ids<R>(ids, n, L, lpref, lstart, T, base + R * kBlock, idn);
         bool full = false;
         uint32_t nnew = (uint32_t)__popc(insert_streams<R, 4>(tab, cap_log2, idr, pend, max_probe, full));
         // one LDS atomic per wave for the unique count

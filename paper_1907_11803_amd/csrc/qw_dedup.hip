@@ -300,13 +300,41 @@ __device__ inline void verify_list(const DedupArgs &A, const uint32_t *list, uin
     }
 }
 
+// Lane l's value (l uniform) in every lane.
+__device__ inline unsigned long long readlane_u64(unsigned long long v, int l)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// The K-th smallest of the wave's 64 values v (duplicates counted), by a
+// radix search from the top bit: 32 ballots, no shuffles.
+__device__ inline uint32_t wave_kth_u32(uint32_t v, int K)
+{
+    uint32_t prefix = 0;
+    int k = K;
+#pragma unroll
+    for (int bit = 31; bit >= 0; --bit) {
+        const uint32_t above = bit == 31 ? 0u : ~0u << (bit + 1);
+        const bool zero = ((v ^ prefix) & above) == 0u && ((v >> bit) & 1u) == 0u;
+        const int cnt = __popcll(__ballot(zero));
+        if (cnt < k) {
+            prefix |= 1u << bit;
+            k -= cnt;
+        }
+    }
+    return prefix;
+}
+
 // Whole workgroup, fused top K of query q (uint8: a key's high word is the
 // exact squared distance) from the lanes' kept keys.  tab holds the U unique
 // ids; the selection list follows them in the same memory (cap_words words
-// in all), so the ids stay readable for a second pass.
-//  1. the K-th smallest lane minimum of a wave bounds the K-th key of the
-//     union of kept keys (K lanes hold a key at or below it); B = the smallest
-//     such bound over the waves;
+// in all), so the ids stay readable for a second pass.  scal[D_LCNT],
+// scal[D_BAD], the bound and the K-th key are reset before the verification.
+//  1. the K-th smallest lane-minimum distance D_w of a wave bounds the K-th
+//     key of the union of kept keys (K lanes hold a key of distance at most
+//     D_w); B = every key of distance at most the smallest D_w of the waves;
 //  2. the kept keys at or below B are collected and ranked; ranks below K are
 //     the output, padded with (-1, INT32_MAX) below K entries;
 //  3. the union's top K is the query's top K unless some lane dropped a key
@@ -343,16 +371,19 @@ __device__ inline void fused_topk(const DedupArgs &A, int64_t q, LaneTop t, cons
     // ranks of the c keys lst[0..c) (unique) below K to the output; the K-th
     // key to *s_kth (left unchanged when c < K)
     auto rank_write = [&](uint32_t c) {
-        if (c <= 64) {  // the usual case: one wave sorts the list
+        if (c <= 64) {  // the usual case: one wave, ranks by broadcast compares
             if (tid < 64) {
-                const unsigned long long v = wave_sort_u64(lane < (int)c ? lst[lane] : ~0ull);
-                if (lane < K) {
-                    const int64_t o = q * K + lane;
+                const unsigned long long v = lane < (int)c ? lst[lane] : ~0ull;
+                int r = 0;
+                for (uint32_t e = 0; e < c; ++e) r += readlane_u64(v, (int)e) < v ? 1 : 0;
+                if (lane >= (int)c) r = lane;  // padding positions c .. K-1
+                if (r < K) {
+                    const int64_t o = q * K + r;
                     const bool has = lane < (int)c;
                     A.out_ids[o] = has ? (int32_t)(uint32_t)v : -1;
                     reinterpret_cast<int32_t *>(A.out_dist)[o] = has ? (int32_t)(v >> 32) : INT32_MAX;
                 }
-                if (lane == K - 1 && lane < (int)c) *s_kth = v;
+                if (lane < (int)c && r == K - 1) *s_kth = v;
             }
             return;
         }
@@ -373,15 +404,8 @@ __device__ inline void fused_topk(const DedupArgs &A, int64_t q, LaneTop t, cons
             reinterpret_cast<int32_t *>(A.out_dist)[o] = INT32_MAX;
         }
     };
-    if (tid == 0) {
-        scal[D_LCNT] = 0;
-        scal[D_BAD] = 0;
-        *s_bound = ~0ull;
-        *s_kth = ~0ull;
-    }
-    sync();
-    const unsigned long long tw = __shfl(wave_sort_u64(t.k[0]), K - 1);
-    if (lane == 0 && tw != ~0ull) atomicMin(s_bound, tw);
+    const uint32_t dw = wave_kth_u32((uint32_t)(t.k[0] >> 32), K);  // 0xFFFFFFFF: < K kept
+    if (lane == 0 && dw != 0xFFFFFFFFu) atomicMin(s_bound, ((unsigned long long)dw << 32) | 0xFFFFFFFFull);
     sync();
     const unsigned long long B = *s_bound;
 #pragma unroll
@@ -546,7 +570,8 @@ __global__ __launch_bounds__(kBlock, 4) void dedup_kernel(DedupArgs A)
         uint32_t pend = 0;
         if (in_regs)  // the id loads fly while the set is cleared
             pend = load_ids<kRegIds>(A.ids, A.n, A.L, lpref, lstart, T, 0u, idr);
-        for (uint32_t i = tid; i < cap; i += kBlock) tab[i] = kEmpty;
+        for (uint32_t i = 4 * tid; i < cap; i += 4 * kBlock)  // cap >= 1024: whole 16-byte stores
+            *reinterpret_cast<uint4 *>(tab + i) = uint4{kEmpty, kEmpty, kEmpty, kEmpty};
         if (glob) __threadfence();
         bar();
         uint32_t newm = 0;
@@ -600,6 +625,11 @@ __global__ __launch_bounds__(kBlock, 4) void dedup_kernel(DedupArgs A)
             }
             *soff = off;
             scal[D_NEXT] = next;
+            // the fused top K's state (read after the verification)
+            scal[D_LCNT] = 0;
+            scal[D_BAD] = 0;
+            *reinterpret_cast<unsigned long long *>(&scal[D_BOUND]) = ~0ull;
+            *reinterpret_cast<unsigned long long *>(&scal[D_KTH]) = ~0ull;
         }
         bar();
         const unsigned long long off = *soff;
