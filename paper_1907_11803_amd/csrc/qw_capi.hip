@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "qw_internal.h"
+#include "qw_mlp.h"
 
 using namespace qw;
 
@@ -268,7 +269,10 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     QW_TRY(clear_counters(ix, s));
     const int topk = o.topk_keep >= 0 ? plan.topk : 0;  // in-kernel top K
     const bool learned = o.sched == QW_SCHED_LEARNED && !ix->mlp.empty();
-    QW_TRY(front(ix, queries, Q, QW_FORM_FAST, s, ev, learned ? w.feats.as<float>() : nullptr));
+    // the binning kernel runs the count model itself; the grouped schedule
+    // takes the predictions from the inference kernel
+    QW_TRY(front(ix, queries, Q, QW_FORM_FAST, s, ev,
+                 learned && o.group ? w.feats.as<float>() : nullptr));
     if (ev) QW_HIP(hipEventRecord(ev[2], s));
     unsigned long long *seg = w.binoff.as<unsigned long long>();
     unsigned long long *ccount = c64(ix) + C_CLASS;
@@ -276,8 +280,9 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     const int64_t cand_cap = (int64_t)(w.pkeys.bytes / sizeof(unsigned long long));
     auto schedule = [&](const int32_t *ex, const float *pl, int force_max,
                         const int32_t **order) -> qw_status {
-        if (!o.group) {  // classes only: one binning kernel
-            QW_TRY(launch_classify_bin(Q, ix->L, ix->n, w.bsize.as<uint32_t>(), ex, pl,
+        if (!o.group) {  // classes only: one binning kernel (with the count model)
+            QW_TRY(launch_classify_bin(Q, ix->L, ix->n, w.bsize.as<uint32_t>(), ex,
+                                       learned && !ex ? ix->mlp_lane.as<uint32_t>() : nullptr,
                                        ix->mlp_margin, force_max, kCmin, plan.cfloor, plan.cmax,
                                        plan.ncls, w.order.as<int32_t>(), ccount,
                                        c32(ix) + W_CLSDONE, seg, s));
@@ -392,7 +397,7 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
         QW_TRY(launch_fill_u32(c32(ix) + W_XWORK, 0u, kXcd * (kMaxClasses + 1), s));
         QW_TRY(launch_fill_u32(c32(ix) + W_QMERGED, 0u, 1, s));
         exact = reinterpret_cast<const int32_t *>(w.ucount.p);
-    } else if (learned) {
+    } else if (learned && o.group) {
         QW_TRY(launch_mlp_predict_bf16(ix->mlp_dev.as<float>(), ix->L, w.feats.as<float>(), Q,
                                        w.mlpout.as<float>(), s));
         pred_log = w.mlpout.as<float>();
@@ -580,7 +585,8 @@ qw_status qw_get_index_info(const qw_index *ix, qw_index_info *info)
     info->max_bucket = ix->max_bucket;
     const DevBuf *bufs[] = {&ix->a32, &ix->b32, &ix->a_hi, &ix->a_lo, &ix->gb_plain,
                             &ix->gb_fast, &ix->data, &ix->hmin, &ix->hmax, &ix->shift,
-                            &ix->ids, &ix->tab, &ix->tab_off, &ix->tab_mask, &ix->mlp_dev};
+                            &ix->ids, &ix->tab, &ix->tab_off, &ix->tab_mask, &ix->mlp_dev,
+                            &ix->mlp_lane};
     for (const DevBuf *b : bufs) info->device_bytes += (int64_t)b->bytes;
     info->has_count_model = ix->mlp.empty() ? 0 : 1;
     info->count_margin = ix->mlp_margin;
@@ -801,6 +807,11 @@ qw_status qw_set_count_model(qw_index *ix, const float *params, int32_t P)
         if (!std::isfinite(params[i])) return QW_EINVAL;
     QW_TRY(ix->mlp_dev.ensure(sizeof(float) * P));
     QW_HIP(hipMemcpy(ix->mlp_dev.p, params, sizeof(float) * P, hipMemcpyHostToDevice));
+    std::vector<uint32_t> lanes(64 * kMlpLaneWords);
+    mlp_pack_lanes(params, ix->L, lanes.data());
+    QW_TRY(ix->mlp_lane.ensure(sizeof(uint32_t) * lanes.size()));
+    QW_HIP(hipMemcpy(ix->mlp_lane.p, lanes.data(), sizeof(uint32_t) * lanes.size(),
+                     hipMemcpyHostToDevice));
     ix->mlp.assign(params, params + P);
     ix->mlp_margin = 0.22314355f;
     drop_graphs(ix);

@@ -131,6 +131,7 @@ struct qw_index {
     std::vector<float> mlp;  // packed host copy (empty = none)
     float mlp_margin = 0.22314355f;  // log-space sizing margin, log(1.25) until calibrated
     qw::DevBuf mlp_dev;
+    qw::DevBuf mlp_lane;   // the model's inference registers, one record per lane
     // query workspace and captured graphs
     qw::Workspace ws;
     std::map<qw::GraphKey, hipGraphExec_t> graphs;
@@ -240,9 +241,11 @@ qw_status launch_segments(const unsigned long long *class_count, int32_t ncls,
                           unsigned long long *seg, hipStream_t s);
 // Classes without bucket grouping in one kernel: class c's queries to
 // order[c * Q ..) (any order), counts added to class_count, seg[2c], seg[2c+1]
-// = [c * Q, c * Q + count_c).  done: a zeroed counter.
+// = [c * Q, c * Q + count_c).  done: a zeroed counter.  mlp_lane (nullable):
+// the count model's lane records, run in the kernel on log(1 + s_l) for the
+// queries whose bound class lies above cfloor (the only ones it can move).
 qw_status launch_classify_bin(int64_t Q, int32_t L, int64_t n, const uint32_t *bsize,
-                              const int32_t *exact, const float *pred_log, float margin,
+                              const int32_t *exact, const uint32_t *mlp_lane, float margin,
                               int32_t force_max, int32_t cmin, int32_t cfloor, int32_t cmax,
                               int32_t ncls, int32_t *order, unsigned long long *class_count,
                               uint32_t *done, unsigned long long *seg, hipStream_t s);

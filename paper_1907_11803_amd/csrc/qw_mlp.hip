@@ -34,37 +34,36 @@ qw_status launch_mlp_features(const uint32_t *bsize, int64_t Q, int32_t L, float
     return QW_OK;
 }
 
-// One wave per query (H = 64 = the wave width): lane h computes hidden unit h
-// from W1 held transposed in LDS (consecutive lanes read consecutive words),
-// and a wave reduction sums W2 . relu(z + b1).  Waves loop over queries.
+// 64 queries per workgroup round: their features go to LDS as bf16 (zero
+// past L), then each wave runs the MFMA inference for 16 of them.
 __global__ __launch_bounds__(kBlock) void mlp_predict_bf16_kernel(const float *__restrict__ params,
                                                                   int32_t L,
                                                                   const float *__restrict__ feats,
                                                                   int64_t B, float *__restrict__ out)
 {
-    static_assert(H == 64, "one hidden unit per lane");
-    extern __shared__ float sw[];  // W1^T bf16 [L][H], b1 [H], W2 bf16 [H], b2
-    const int P = mlp_lds_floats(L);
-    mlp_stage(params, L, sw);
-    __syncthreads();
-    const float *W1t = sw, *b1 = sw + H * L, *W2 = sw + H * L + H;
-    const float b2 = sw[P - 1];
-    const int lane = threadIdx.x & 63;
-    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
-    // lane l < L holds feature l of the query (one load per query, the next
-    // query's in flight during this one); the sum takes them by broadcast
-    int64_t q = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    float fn = q < B && lane < L ? feats[q * L + lane] : 0.f;
-    for (; q < B; q += nwaves) {
-        const float fv = bf16_round(fn);
-        const int64_t qn = q + nwaves;
-        fn = qn < B && lane < L ? feats[qn * L + lane] : 0.f;
-        float z = 0.f;
-        for (int l = 0; l < L; ++l) z = fmaf(W1t[l * H + lane], __shfl(fv, l), z);
-        const float zz = z + b1[lane];
-        float y = W2[lane] * bf16_round(zz > 0.f ? zz : 0.f);
-        for (int off = 32; off > 0; off >>= 1) y += __shfl_xor(y, off);
-        if (lane == 0) out[q] = y + b2;
+    static_assert(H == 64, "four 16-unit MFMA tiles");
+    __shared__ __align__(16) uint16_t fsh[64 * (16 * kMlpMaxKs + 4)];
+    __shared__ float sw[kMlpH * 16 * kMlpMaxKs + 2 * kMlpH + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ksteps = (L + 15) / 16;
+    const int kp = 16 * ksteps, ld = kp + 4;  // padded rows (8-byte aligned)
+    MlpLane m;
+    mlp_lane_load(params, L, sw, m);
+    for (int64_t q0 = (int64_t)blockIdx.x * 64; q0 < B; q0 += (int64_t)gridDim.x * 64) {
+        for (int i = tid; i < 64 * kp; i += kBlock) {
+            const int r = i / kp, k = i - r * kp;
+            const int64_t q = q0 + r;
+            fsh[r * ld + k] = k < L && q < B ? bf16_bits(feats[q * L + k]) : (uint16_t)0;
+        }
+        __syncthreads();
+        const mlp_f4 y = mlp_predict16(fsh + wave * 16 * ld, ld, ksteps, m);
+        if ((lane & 15) == 0)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t q = q0 + wave * 16 + (lane >> 4) * 4 + j;
+                if (q < B) out[q] = y[j];
+            }
+        __syncthreads();  // fsh is rewritten by the next round
     }
 }
 
@@ -72,10 +71,9 @@ qw_status launch_mlp_predict_bf16(const float *params, int32_t L, const float *f
                                   float *out, hipStream_t s)
 {
     if (B <= 0) return QW_OK;
-    if (L > 64) return QW_EINVAL;  // one feature per lane
-    const size_t lds = sizeof(float) * (H * L + 2 * H + 1);
-    const int g = (int)std::min<int64_t>(2048, ceil_div(B, kBlock / 64));
-    mlp_predict_bf16_kernel<<<g, kBlock, lds, s>>>(params, L, feats, B, out);
+    if (L > 16 * kMlpMaxKs) return QW_EINVAL;
+    const int g = (int)std::min<int64_t>(1024, ceil_div(B, 64));
+    mlp_predict_bf16_kernel<<<g, kBlock, 0, s>>>(params, L, feats, B, out);
     QW_HIP(hipGetLastError());
     return QW_OK;
 }

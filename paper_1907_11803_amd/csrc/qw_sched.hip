@@ -7,6 +7,7 @@
 // served from L2 / the Infinity Cache -- the GPU counterpart of keeping reused
 // index files and data objects in the cache (Sections 4 and 5.1).
 #include "qw_internal.h"
+#include "qw_mlp.h"
 
 namespace qw {
 
@@ -92,34 +93,67 @@ __global__ __launch_bounds__(kBlock) void classify_kernel(
 // atomic on the class count.  The last workgroup to finish (its done-counter
 // increment sees every other one) writes seg[2c], seg[2c+1] = [c * Q,
 // c * Q + count_c).
+// mlp_lane (nullable): the count model.  A prediction can only move a query
+// whose bound class lies above cfloor (below it the class is the bound's), so
+// only those queries are gathered into LDS and run through the MFMA
+// inference, 16 at a time.
 __global__ __launch_bounds__(kBlock) void classify_bin_kernel(
     int64_t Q, int32_t L, int64_t n, const uint32_t *__restrict__ bsize,
-    const int32_t *__restrict__ exact, const float *__restrict__ pred_log, float margin,
+    const int32_t *__restrict__ exact, const uint32_t *__restrict__ mlp_lane, float margin,
     int32_t force_max, int32_t cmin, int32_t cfloor, int32_t cmax, int32_t ncls,
     int32_t *__restrict__ order, unsigned long long *class_count, uint32_t *done,
     unsigned long long *__restrict__ seg)
 {
+    extern __shared__ __align__(16) uint16_t fsh[];  // mlp: features [kBlock][ld] (bf16)
+    __shared__ float pred_sh[kBlock];
     __shared__ uint32_t hist[32];
     __shared__ unsigned long long base[32];
-    __shared__ uint32_t last;
-    const int tid = threadIdx.x;
+    __shared__ uint32_t last, nmodel;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ksteps = (L + 15) / 16, kp = 16 * ksteps, ld = kp + 4;
+    MlpLane m;
+    if (mlp_lane) mlp_lane_load_packed(mlp_lane, m);  // in flight with the first sizes
     for (int64_t q0 = (int64_t)blockIdx.x * kBlock; q0 < Q; q0 += (int64_t)gridDim.x * kBlock) {
         const int64_t q = q0 + tid;
         if (tid < 32) hist[tid] = 0;
+        if (tid == 0) nmodel = 0;
+        // the query's bucket sizes, all loads in flight together (L <= 64)
+        uint32_t sz[kMaxL];
+#pragma unroll
+        for (int32_t l = 0; l < kMaxL; ++l) sz[l] = q < Q && l < L ? bsize[q * L + l] : 0u;
+        uint64_t tsum = 0;
+#pragma unroll
+        for (int32_t l = 0; l < kMaxL; ++l) tsum += sz[l];
+        __syncthreads();  // hist and nmodel cleared
+        // a slot in the model's list when the bound class exceeds cfloor
+        const uint64_t bound = min(tsum, (uint64_t)n);
+        const bool use = mlp_lane && q < Q && !exact && (3ull << cfloor) < 4 * bound;
+        int slot = -1;
+        if (use) {
+            slot = (int)atomicAdd(&nmodel, 1u);
+            // f_l = log(1 + s_l) by the hardware logarithm (1 + s_l is exact
+            // for s_l < 2^24; the feature is rounded to bfloat16 anyway)
+#pragma unroll
+            for (int32_t l = 0; l < kMaxL; ++l) {
+                if (l < L) fsh[slot * ld + l] = bf16_bits(__logf(1.0f + (float)sz[l]));
+                else if (l < kp) fsh[slot * ld + l] = 0;
+            }
+        }
         __syncthreads();
+        const int nm = (int)nmodel;
+        for (int r0 = wave * 16; r0 < nm; r0 += kBlock / 4) {  // 16 rows per wave step
+            // rows past nm hold stale features; their predictions are unused
+            const mlp_f4 y = mlp_predict16(fsh + r0 * ld, ld, ksteps, m);
+            if ((lane & 15) == 0)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) pred_sh[r0 + (lane >> 4) * 4 + j] = y[j];
+        }
+        __syncthreads();  // predictions written
         int cls = 0;
         uint32_t p = 0;
         if (q < Q) {
-            uint64_t tsum = 0;
-            for (int32_t l0 = 0; l0 < L; l0 += 16) {  // 16 loads in flight at a time
-                uint32_t v[16];
-#pragma unroll
-                for (int32_t i = 0; i < 16; ++i) v[i] = l0 + i < L ? bsize[q * L + l0 + i] : 0u;
-#pragma unroll
-                for (int32_t i = 0; i < 16; ++i) tsum += v[i];
-            }
-            cls = class_of(tsum, n, exact, q, pred_log != nullptr, pred_log ? pred_log[q] : 0.f,
-                           margin, force_max, cmin, cfloor, cmax, ncls);
+            cls = class_of(tsum, n, exact, q, use, use ? pred_sh[slot] : 0.f, margin, force_max,
+                           cmin, cfloor, cmax, ncls);
             p = atomicAdd(&hist[cls], 1u);
         }
         __syncthreads();
@@ -142,7 +176,7 @@ __global__ __launch_bounds__(kBlock) void classify_bin_kernel(
 }
 
 qw_status launch_classify_bin(int64_t Q, int32_t L, int64_t n, const uint32_t *bsize,
-                              const int32_t *exact, const float *pred_log, float margin,
+                              const int32_t *exact, const uint32_t *mlp_lane, float margin,
                               int32_t force_max, int32_t cmin, int32_t cfloor, int32_t cmax,
                               int32_t ncls, int32_t *order, unsigned long long *class_count,
                               uint32_t *done, unsigned long long *seg, hipStream_t s)
@@ -150,7 +184,9 @@ qw_status launch_classify_bin(int64_t Q, int32_t L, int64_t n, const uint32_t *b
     if (Q <= 0) return QW_OK;
     if (ncls > 32 || L > kMaxL) return QW_EINVAL;
     const int g = (int)std::min<int64_t>(1024, ceil_div(Q, kBlock));
-    classify_bin_kernel<<<g, kBlock, 0, s>>>(Q, L, n, bsize, exact, pred_log, margin, force_max,
+    // features of up to kBlock rows (a wave's steps start at multiples of 16)
+    const size_t lds = mlp_lane ? sizeof(uint16_t) * (size_t)kBlock * (16 * ((L + 15) / 16) + 4) : 0;
+    classify_bin_kernel<<<g, kBlock, lds, s>>>(Q, L, n, bsize, exact, mlp_lane, margin, force_max,
                                                cmin, cfloor, cmax, ncls, order, class_count, done,
                                                seg);
     QW_HIP(hipGetLastError());

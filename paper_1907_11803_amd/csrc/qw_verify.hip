@@ -195,6 +195,7 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
     const int64_t nall = nseg + nin;
     int64_t first = A.counter ? -1 : (int64_t)blockIdx.x;
 
+    if (nall == 0) return;  // uniform: an empty queue costs no atomic on the shared counter
     while (true) {
         if (tid == 0) {
             int64_t it = A.counter ? (int64_t)atomicAdd(A.counter, 1u) : first;
