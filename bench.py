@@ -72,10 +72,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4])
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--w", type=float, default=None, help="bucket width (default: search w_0.9)")
-    ap.add_argument("--train-queries", type=int, default=50_000)
-    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle query sample (0 = all)")
+    ap.add_argument("--train-queries", type=int, default=None,
+                    help="count-model training queries (default: the configuration's, else 50,000)")
+    ap.add_argument("--recall-sample", type=int, default=2000,
+                    help="queries whose recall@10 is measured against brute force (0 = all)")
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="oracle query sample (0 = up to 10,000 uint8 / 1,000 float queries)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="only the fast-form timed loop (for rocprofv3 runs)")
@@ -119,12 +123,15 @@ def main():
             break
         if truth is None:
             t1 = time.time()
-            ti, td = ix.bruteforce(q_d, K)
+            rs = wl.Q if args.recall_sample <= 0 else min(args.recall_sample, wl.Q)
+            rsel = np.sort(np.random.default_rng(11).choice(wl.Q, size=rs, replace=False))
+            rsel_d = torch.from_numpy(rsel).to(dev)
+            ti, td = ix.bruteforce(q_d[rsel_d].contiguous(), K)
             torch.cuda.synchronize()
             truth = (ti.cpu().numpy(), td.cpu().numpy())
-            log(f"[bench] brute-force ground truth in {time.time() - t1:.1f}s")
+            log(f"[bench] brute-force ground truth for {rs} queries in {time.time() - t1:.1f}s")
         ids, dist, st = ix.query(q_d, K, lib.make_opts(sched=lib.QW_SCHED_SUM, graph=0), stats=True)
-        rec = recall_at_10(ids.cpu().numpy(), truth[0], dist.cpu().numpy(), truth[1])
+        rec = recall_at_10(ids.cpu().numpy()[rsel], truth[0], dist.cpu().numpy()[rsel], truth[1])
         tried.append({"w": w, "recall_at_10": round(rec, 4),
                       "mean_unique_candidates": st["cand_unique"] / wl.Q})
         log(f"[bench] w={w}: recall@10={rec:.4f} unique/q={st['cand_unique'] / wl.Q:.0f} "
@@ -137,13 +144,25 @@ def main():
 
     # ---- learned count model, trained on the engine's own features
     t1 = time.time()
-    train = synth.training_queries(args.config, args.train_queries)
+    ntrain = args.train_queries or spec.get("train_Q", 50_000)
+    train = synth.training_queries(args.config, ntrain)
     train_d = torch.from_numpy(train).to(dev)
     train_loss = ix.train_count_model(train_d, epochs=8, batch=1024, lr=2e-3, seed=1)
     del train_d
-    log(f"[bench] count model trained on {args.train_queries} queries, loss {train_loss:.4f}, "
+    log(f"[bench] count model trained on {ntrain} queries, loss {train_loss:.4f}, "
         f"sizing margin {ix.info()['count_margin']:.3f} "
         f"in {time.time() - t1:.1f}s")
+    count_model = None
+    if not args.profile:
+        # prediction quality on the workload's own queries: log(1 + |C(q)|)
+        feats = torch.log1p(ix.bucket_sizes(q_d).to(torch.float32)).contiguous()
+        params = torch.from_numpy(ix.get_count_model()).to(dev)
+        pred = lib.qw_mlp_predict_bf16(params, wl.params.L, feats).cpu().numpy()
+        actual = np.log1p(ix.candidate_counts(q_d).cpu().numpy().astype(np.float64))
+        count_model = {"train_queries": int(ntrain), "train_loss": round(float(train_loss), 4),
+                       "mae_log": round(float(np.mean(np.abs(pred - actual))), 4),
+                       "sizing_margin": round(float(ix.info()["count_margin"]), 4)}
+        log(f"[bench] count model on the workload: MAE {count_model['mae_log']} (log space)")
 
     out_ids = torch.empty((wl.Q, K), dtype=torch.int32, device=dev)
     out_dist = torch.empty((wl.Q, K), dtype=torch.int32 if is_u8 else torch.float32, device=dev)
@@ -162,7 +181,7 @@ def main():
         torch.cuda.synchronize()
         return start.elapsed_time(stop) / steps
 
-    fast_opts = lib.make_opts(form=lib.QW_FORM_FAST, sched=lib.QW_SCHED_LEARNED, group=0, graph=1)
+    fast_opts = lib.make_opts(form=lib.QW_FORM_FAST, sched=lib.QW_SCHED_LEARNED, group=-1, graph=1)
     if args.profile:
         # a plain device copy of known size (1 GiB read + 1 GiB written) to
         # calibrate the HBM byte counters of a profiling run
@@ -186,13 +205,24 @@ def main():
     # ---- timed regions
     ms_fast = timed(fast_opts, args.steps, args.warmup)
     ms_plain = timed(lib.make_opts(form=lib.QW_FORM_PLAIN_FP32), args.steps, args.warmup)
+    # the schedules (count sources) under the automatic grouping, then the
+    # learned schedule with each fixed grouping; every one must return the
+    # fast form's results exactly
     sched_ms = {}
-    for name, sc in (("sum", lib.QW_SCHED_SUM), ("actual", lib.QW_SCHED_ACTUAL),
-                     ("none", lib.QW_SCHED_NONE), ("learned", lib.QW_SCHED_LEARNED)):
-        sched_ms[name] = round(timed(lib.make_opts(sched=sc), max(5, args.steps // 2), 2), 4)
-    sched_ms["learned_grouped"] = round(
-        timed(lib.make_opts(sched=lib.QW_SCHED_LEARNED, group=1), max(5, args.steps // 2), 2), 4)
-    log(f"[bench] fast {ms_fast:.3f} ms/step, plain {ms_plain:.3f} ms/step, scheds {sched_ms}")
+    sched_identical = True
+    variants = [(name, lib.make_opts(sched=sc)) for name, sc in (
+        ("sum", lib.QW_SCHED_SUM), ("actual", lib.QW_SCHED_ACTUAL),
+        ("none", lib.QW_SCHED_NONE), ("learned", lib.QW_SCHED_LEARNED))]
+    variants += [(f"learned_group{g}", lib.make_opts(sched=lib.QW_SCHED_LEARNED, group=g))
+                 for g in (0, 1)]
+    f_ids_np, f_dist_np = f_ids.cpu().numpy(), f_dist.cpu().numpy()
+    for name, o in variants:
+        sched_ms[name] = round(timed(o, max(5, args.steps // 2), 2), 4)
+        s_ids, s_dist = ix.query(q_d, K, o)
+        sched_identical &= bool(np.array_equal(s_ids.cpu().numpy(), f_ids_np) and
+                                np.array_equal(s_dist.cpu().numpy(), f_dist_np))
+    log(f"[bench] fast {ms_fast:.3f} ms/step, plain {ms_plain:.3f} ms/step, scheds {sched_ms}, "
+        f"identical {sched_identical}")
 
     # ---- per-stage timing of the fast pipeline (events inside the library)
     stage = np.zeros(8)
@@ -238,7 +268,7 @@ def main():
         bi = oracle.BuiltIndex(wl.data, wl.params.a, wl.params.b(w), w, nthreads=nthreads)
         build_cpu = time.time() - t1
         rng = np.random.default_rng(7)
-        ns = wl.Q if args.cpu_sample <= 0 else min(args.cpu_sample, wl.Q)
+        ns = min(args.cpu_sample if args.cpu_sample > 0 else (10_000 if is_u8 else 1_000), wl.Q)
         sample = np.sort(rng.choice(wl.Q, size=ns, replace=False))
         t1 = time.time()
         o_ids, o_dist, _ = bi.query(wl.queries[sample], K)
@@ -271,6 +301,7 @@ def main():
                          f"Q={wl.Q} queries, L={L} k={wl.params.k} w={w} (w_0.9), K={K}"),
             "n": wl.n, "d": wl.d, "Q": wl.Q, "L": L, "k": wl.params.k, "w": w, "K": K,
             "projection": "fp16-mfma+fp64-guard" if is_u8 else "fp32-mfma+fp64-guard",
+            "bucket_grouping": "automatic (rows of 1024 bytes or more)",
             "w_search": tried,
         },
         "recall_at_10": round(rec, 4),
@@ -278,6 +309,7 @@ def main():
         "speedup_vs_plain_fp32": round(ms_plain / ms_fast, 3),
         "forms_identical": identical,
         "sched_ms_per_step": sched_ms,
+        "sched_identical": sched_identical,
         "stage_ms": {"hash": round(stage[0], 4), "probe": round(stage[1], 4),
                      "schedule": round(stage[2], 4), "dedup": round(stage[6], 4),
                      "select": round(stage[7], 4),
@@ -289,6 +321,7 @@ def main():
         "overflow_queries": st["overflow"],
         "fallback_queries": st["fallback"],
         "topk_second_pass_queries": st["topk_second_pass"],
+        "count_model": count_model,
         "bins": st["bins"],
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -80,7 +80,9 @@ typedef struct {
     int32_t form;      /* qw_form */
     int32_t sched;     /* qw_sched (fast form only) */
     int32_t group;     /* fast form: 1 = order queries by bucket key within a size class,
-                          0 = no bucket ordering (default) */
+                          0 = no bucket ordering, -1 = automatic (default): ordering for
+                          rows of 1024 bytes or more, where neighbouring queries of one
+                          bucket share the rows they verify in cache */
     int32_t graph;     /* fast form: 1 = capture/replay the query pipeline as a HIP graph */
     int32_t timing;    /* 1 = record per-stage HIP events and report them in qw_stats (syncs) */
     int32_t topk_keep; /* fast form, uint8 rows of at most 1024 bytes, K <= 16: the dedup kernel
@@ -125,7 +127,7 @@ typedef struct {
 typedef struct qw_index qw_index;
 
 /* Default options: fast form, learned schedule when a model is loaded (else
- * the bucket-size sum), grouping off, graph on, timing off, in-kernel top K
+ * the bucket-size sum), automatic grouping, graph on, timing off, in-kernel top K
  * where it applies (topk_keep 0). */
 void qw_default_opts(qw_opts *o);
 

@@ -521,7 +521,7 @@ void qw_default_opts(qw_opts *o)
     std::memset(o, 0, sizeof(*o));
     o->form = QW_FORM_FAST;
     o->sched = QW_SCHED_LEARNED;
-    o->group = 0;  // bucket ordering costs two radix passes and buys little locality
+    o->group = -1;  // automatic: order by bucket key for rows of kGroupRowBytes or more
     o->graph = 1;
     o->timing = 0;
 }
@@ -605,6 +605,7 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
     if (opt.form != QW_FORM_PLAIN_FP32 && opt.form != QW_FORM_FAST) return QW_EINVAL;
     if (opt.sched < QW_SCHED_SUM || opt.sched > QW_SCHED_NONE) return QW_EINVAL;
     if (opt.topk_keep < -1 || opt.topk_keep > 3) return QW_EINVAL;
+    if (opt.group < -1 || opt.group > 1) return QW_EINVAL;
     if (Q == 0) {
         if (st) std::memset(st, 0, sizeof(*st));
         return QW_OK;
@@ -634,6 +635,7 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
         const int sched = opt.sched == QW_SCHED_LEARNED && !learned ? QW_SCHED_SUM : opt.sched;
         qw_opts eff = opt;
         eff.sched = sched;
+        if (eff.group < 0) eff.group = ix->dp * (ix->dtype == QW_U8 ? 1 : 4) >= kGroupRowBytes;
         if (opt.timing || !opt.graph) {
             QW_TRY(enqueue_fast(ix, plan, queries, Q, K, eff, s, out_ids, out_dist,
                                 opt.timing ? ix->ev : nullptr));

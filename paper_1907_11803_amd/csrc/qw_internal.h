@@ -21,6 +21,12 @@ constexpr int kBlock = 256;              // threads per workgroup for every kern
 constexpr int kRecompSlots = 32;
 // Largest K the fused dedup kernel selects itself (uint8 data).
 constexpr int kFusedTopK = 16;
+// Automatic bucket grouping orders queries by bucket key when a candidate's row
+// is at least this many bytes: the verification then reads whole rows that
+// neighbouring queries of one bucket share in L2 and the last-level cache,
+// which outweighs the two radix passes the ordering costs.  Below it the rows
+// are short and the passes cost more than the reuse gains.
+constexpr int kGroupRowBytes = 1024;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // empty hash-set slot
 constexpr int kMaxL = 64;
 constexpr int kMaxK = 32;

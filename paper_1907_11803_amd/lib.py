@@ -138,7 +138,7 @@ def _dtype_code(t: torch.Tensor) -> int:
     return QW_U8 if t.dtype == torch.uint8 else QW_F32
 
 
-def make_opts(form: int = QW_FORM_FAST, sched: int = QW_SCHED_LEARNED, group: int = 0,
+def make_opts(form: int = QW_FORM_FAST, sched: int = QW_SCHED_LEARNED, group: int = -1,
               graph: int = 1, timing: int = 0, topk_keep: int = 0) -> qw_opts:
     o = qw_opts()
     load().qw_default_opts(ctypes.byref(o))

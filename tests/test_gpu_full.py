@@ -24,7 +24,7 @@ def dev(x):
 
 
 def bench_opts():
-    return lib.make_opts(form=lib.QW_FORM_FAST, sched=lib.QW_SCHED_LEARNED, group=0, graph=1)
+    return lib.make_opts(form=lib.QW_FORM_FAST, sched=lib.QW_SCHED_LEARNED, group=-1, graph=1)
 
 
 def compare(ids_g, dist_g, ids_o, dist_o, rows, is_u8):

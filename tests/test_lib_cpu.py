@@ -58,7 +58,7 @@ def test_host_only_entry_points(so):
     assert so.qw_mlp_param_count(16) == 64 * 16 + 2 * 64 + 1 == 1153
     o = lib.qw_opts()
     so.qw_default_opts(ctypes.byref(o))
-    assert (o.form, o.sched, o.group, o.graph, o.timing) == (lib.QW_FORM_FAST, lib.QW_SCHED_LEARNED, 0, 1, 0)
+    assert (o.form, o.sched, o.group, o.graph, o.timing) == (lib.QW_FORM_FAST, lib.QW_SCHED_LEARNED, -1, 1, 0)
 
 
 def test_validation_rejects_before_device_work(so):
