@@ -336,7 +336,7 @@ struct SelectArgs {
 size_t dedup_lds_bytes(int cap_log2, int global_tab, int L, int row_bytes);
 int dedup_blocks_per_cu(size_t lds, int dtype);
 qw_status launch_dedup(const DedupArgs &a, int grid, hipStream_t s);
-size_t select_lds_bytes(int LC, int dtype);
+size_t select_lds_bytes(int LC, int dtype, int dp);
 qw_status launch_select(const SelectArgs &a, int64_t Q, hipStream_t s);
 // Scratch bytes launch_scan_u32_to_u64 needs for `count` values.
 size_t scan_scratch_bytes(int64_t count);

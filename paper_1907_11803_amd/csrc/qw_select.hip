@@ -3,6 +3,7 @@
 // Section 3); for float data every key within the proven FP32 error band of
 // the K-th is re-ranked by its FP64 index-order distance.  Queries that do not
 // fit (list or band capacity) go to the fallback.
+#include "qw_exact.h"
 #include "qw_internal.h"
 #include "qw_wave.h"
 
@@ -18,21 +19,12 @@ __device__ inline float band_threshold(float FK, float eps)
     return f;
 }
 
+constexpr int kSelRegs = 8;  // keys per thread held in registers
+
 struct RankF {
     double D;
     uint32_t id, pad;
 };
-
-__device__ __noinline__ double exact_dist_f32_s(const float *__restrict__ x,
-                                                const float *__restrict__ q, int32_t d)
-{
-    double acc = 0.0;
-    for (int32_t i = 0; i < d; ++i) {
-        const double t = __dsub_rn((double)x[i], (double)q[i]);
-        acc = __dadd_rn(acc, __dmul_rn(t, t));
-    }
-    return acc;
-}
 
 // One workgroup per query, over its U keys (unique (distance, id) pairs):
 // 1. every lane takes the minimum of its stride-kBlock stream of keys (K > 64:
@@ -56,40 +48,44 @@ __global__ __launch_bounds__(kBlock) void select_kernel(SelectArgs A)
     RankF *rk = reinterpret_cast<RankF *>(smem + size_t(A.LC) * 8);
     unsigned long long *s_min = lst;  // the minima (K > 64) are dead before the list fills
     __shared__ unsigned long long s_thr, s_kth;
-    __shared__ uint32_t s_cnt, s_nb, s_bad;
+    __shared__ uint32_t s_cnt, s_nb;
     const int64_t q = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63;
     const unsigned long long lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
+    // the flag, the count and the range offset load together (uniform)
+    const uint32_t bad = A.flag[q];
+    const uint32_t U = A.ucount[q];
+    const unsigned long long coff = A.coff[q];
+    if (bad) {  // uniform
+        if (tid == 0) A.fb_list[atomicAdd(A.fb_count, 1u)] = (int32_t)q;
+        return;
+    }
+    const int K = A.K;
+    const unsigned long long *keys = A.keys + (U ? coff : 0ull);
+    // the first kSelRegs * kBlock keys stay in registers for steps 1 and 3
+    unsigned long long kr[kSelRegs];
+#pragma unroll
+    for (int r = 0; r < kSelRegs; ++r) {
+        const uint32_t e = (uint32_t)(tid + r * kBlock);
+        kr[r] = e < U ? keys[e] : ~0ull;
+    }
     if (tid == 0) {
         s_cnt = 0;
         s_nb = 0;
         s_thr = ~0ull;
         s_kth = ~0ull;
-        s_bad = A.flag[q];
     }
     __syncthreads();
-    if (s_bad) {
-        if (tid == 0) A.fb_list[atomicAdd(A.fb_count, 1u)] = (int32_t)q;
-        return;
-    }
-    const uint32_t U = A.ucount[q];
-    const int K = A.K;
-    const unsigned long long *keys = A.keys + (U ? A.coff[q] : 0ull);
     // ---- 1-2: bound on the K-th key
     if (U > (uint32_t)K) {
         const int V = (K + kBlock - 1) / kBlock;
         unsigned long long thr = ~0ull;
         if (K <= 64) {
             unsigned long long m = ~0ull;
-            uint32_t e = tid;
-            for (; e + 3 * kBlock < U; e += 4 * kBlock) {
-                const unsigned long long k0 = keys[e], k1 = keys[e + kBlock];
-                const unsigned long long k2 = keys[e + 2 * kBlock], k3 = keys[e + 3 * kBlock];
-                const unsigned long long a = k0 < k1 ? k0 : k1, b = k2 < k3 ? k2 : k3;
-                const unsigned long long c = a < b ? a : b;
-                m = c < m ? c : m;
-            }
-            for (; e < U; e += kBlock) m = keys[e] < m ? keys[e] : m;
+#pragma unroll
+            for (int r = 0; r < kSelRegs; ++r) m = kr[r] < m ? kr[r] : m;
+            for (uint32_t e = (uint32_t)(tid + kSelRegs * kBlock); e < U; e += kBlock)
+                m = keys[e] < m ? keys[e] : m;
             // the K-th smallest of this wave's minima; ~0 unless K streams are non-empty
             const unsigned long long t = __shfl(wave_sort_u64(m), K - 1);
             if (lane == 0 && t != ~0ull) atomicMin(&s_thr, t);
@@ -125,7 +121,14 @@ __global__ __launch_bounds__(kBlock) void select_kernel(SelectArgs A)
         const unsigned long long thr = s_thr;
         for (uint32_t b0 = 0; b0 < U; b0 += kBlock) {
             const uint32_t e = b0 + tid;
-            const unsigned long long k = e < U ? keys[e] : ~0ull;
+            const int r = (int)(b0 / kBlock);
+            unsigned long long k = ~0ull;
+            if (r < kSelRegs) {
+#pragma unroll
+                for (int i = 0; i < kSelRegs; ++i) k = i == r ? kr[i] : k;
+            } else if (e < U) {
+                k = keys[e];
+            }
             const bool take = e < U && k <= thr;
             const unsigned long long m = __ballot(take);
             uint32_t wb = 0;
@@ -191,10 +194,15 @@ __global__ __launch_bounds__(kBlock) void select_kernel(SelectArgs A)
         if (tid == 0) A.fb_list[atomicAdd(A.fb_count, 1u)] = (int32_t)q;
         return;
     }
-    const float *qrow = (const float *)A.queries + q * (int64_t)A.dp;
-    for (int i = tid; i < nb; i += kBlock)
-        rk[i].D = exact_dist_f32_s((const float *)A.data + (int64_t)rk[i].id * A.dp, qrow, A.d);
-    __syncthreads();
+    if (nb > 0) {  // uniform
+        const float *qrow = (const float *)A.queries + q * (int64_t)A.dp;
+        float *qs = reinterpret_cast<float *>(smem + size_t(A.LC) * 8 + size_t(A.LC / 2) * sizeof(RankF));
+        double *stage = reinterpret_cast<double *>(qs + A.dp);  // dp is a multiple of 4
+        for (int i = tid; i < A.dp; i += kBlock) qs[i] = qrow[i];
+        __syncthreads();
+        exact_dists_staged((const float *)A.data, A.dp, nb, qs, stage,
+                           [&](int i) { return rk[i].id; }, [&](int i, double D) { rk[i].D = D; });
+    }
     for (int i = tid; i < nb; i += kBlock) {
         const double D = rk[i].D;
         const uint32_t id = rk[i].id;
@@ -214,17 +222,19 @@ __global__ __launch_bounds__(kBlock) void select_kernel(SelectArgs A)
 }
 
 // The key list holds LC >= 4K entries (also room for the ceil(K / kBlock) *
-// kBlock minima of K > 64); the FP64 re-rank of float data needs LC/2 (a band
-// wider than that goes to the fallback).
-size_t select_lds_bytes(int LC, int dtype)
+// kBlock minima of K > 64); the FP64 re-rank of float data needs LC/2 entries
+// (a band wider than that goes to the fallback), the query row and the row
+// staging area.
+size_t select_lds_bytes(int LC, int dtype, int dp)
 {
-    return size_t(LC) * 8 + (dtype == QW_F32 ? size_t(LC / 2) * sizeof(RankF) : 0);
+    return size_t(LC) * 8 +
+           (dtype == QW_F32 ? size_t(LC / 2) * sizeof(RankF) + size_t(dp) * 4 + kStageBytes : 0);
 }
 
 qw_status launch_select(const SelectArgs &a, int64_t Q, hipStream_t s)
 {
     if (Q <= 0) return QW_OK;
-    const size_t lds = select_lds_bytes(a.LC, a.dtype);
+    const size_t lds = select_lds_bytes(a.LC, a.dtype, a.dp);
     if (a.dtype == QW_U8)
         select_kernel<QW_U8><<<(unsigned)Q, kBlock, lds, s>>>(a);
     else

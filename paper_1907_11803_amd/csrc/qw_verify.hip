@@ -26,6 +26,7 @@
 // queries that overflowed a smaller hash set; a query whose unique candidates
 // exceed this launch's set is appended to the next launch's queue.
 #include "qw_dedup.h"
+#include "qw_exact.h"
 #include "qw_internal.h"
 
 namespace qw {
@@ -82,17 +83,6 @@ __device__ inline void entry_sentinel(TopF &e)
     e.flag = 0;
 }
 
-// FP64 index-order squared distance (the reference sequence; no contraction).
-__device__ __noinline__ double exact_dist_f32(const float *__restrict__ x, const float *q, int32_t d)
-{
-    double acc = 0.0;
-    for (int32_t i = 0; i < d; ++i) {
-        double t = __dsub_rn((double)x[i], (double)q[i]);
-        acc = __dadd_rn(acc, __dmul_rn(t, t));
-    }
-    return acc;
-}
-
 // Compact the top-K buffer: rank unranked float entries in FP64, sort the live
 // entries, keep K, update the admission threshold.  Whole workgroup.
 template <int DT>
@@ -106,7 +96,7 @@ __device__ void topk_compact(typename TopT<DT>::type *buf, uint32_t *scal, int n
         for (int e = threadIdx.x; e < n_e; e += kBlock) {
             if (buf[e].flag) {
                 const float *x = (const float *)data + (int64_t)buf[e].id * dp;
-                double D = exact_dist_f32(x, qrow, d);
+                const double D = exact_dist_row(x, qrow, dp);
                 buf[e].pri = (unsigned long long)__double_as_longlong(D);
                 buf[e].flag = 0;
             }

@@ -227,6 +227,26 @@ def test_topk_float_cfg3_small(cfg3_small, form):
     check_topk(ids, dist, ids_o, dist_o, False)
 
 
+def test_float_fp64_ties_follow_rounded_sequence():
+    """Swapped pairs whose FP64 distances tie only without fused multiply-adds:
+    both forms and the brute force must order every pair by id, as the oracle."""
+    from fp64_ties import tie_workload
+    data, queries = tie_workload()
+    n = data.shape[0]
+    L, k, w = 1, 1, 1.0e4
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal((L, k, 2)).astype(np.float32)
+    b = np.full((L, k), w / 2, np.float32)
+    ix = build(data, a, b, w)
+    ids_o, dist_o, cnt = oracle.lsh_query(data, queries, a, b, w, n)
+    assert (cnt == n).all()
+    for form in FORMS:
+        ids, dist = ix.query(dev(queries), n, lib.make_opts(form=form, sched=lib.QW_SCHED_SUM))
+        check_topk(ids, dist, ids_o, dist_o, False)
+    ids, dist = ix.bruteforce(dev(queries), n)
+    check_topk(ids, dist, ids_o, dist_o, False)
+
+
 # ---------------------------------------------------------------- brute force
 
 @pytest.mark.parametrize("dtype", ["u8", "f32"])

@@ -249,6 +249,29 @@ def test_float_distance_close_to_exact_rational():
         assert abs(dist[0, r] - float(ex)) <= 1e-14 * float(ex)
 
 
+def test_float_distance_rounds_each_product_and_sum():
+    """Pairs whose distances tie with separately rounded products and sums but
+    not with a fused multiply-add: the oracle's distances equal the rounded
+    sequence written out in Python floats, each pair ties, and the tie goes to
+    the smaller id."""
+    from fp64_ties import tie_workload
+    data, queries = tie_workload()
+    n = data.shape[0]
+    ids, dist = oracle.bruteforce(data, queries, n)
+    for j in range(queries.shape[0]):
+        c = float(queries[j, 0])
+        want = {}
+        for p in range(n):
+            tx, ty = float(data[p, 0]) - c, float(data[p, 1]) - c
+            want[p] = tx * tx + ty * ty  # each product and the sum rounded once
+        for r in range(n):
+            assert dist[j, r] == want[int(ids[j, r])]
+        pos = {int(p): r for r, p in enumerate(ids[j])}
+        for p in range(0, n, 2):  # rows p and p + 1 are a swapped pair
+            assert want[p] == want[p + 1]
+            assert pos[p] < pos[p + 1]
+
+
 # ---------------------------------------------------------------- Eq. (1)
 
 def test_eq1_closed_form_matches_quadrature():
