@@ -147,17 +147,22 @@ __global__ void final_table_kernel(const uint32_t *__restrict__ bsize,
                                    const uint32_t *__restrict__ brep,
                                    const unsigned long long *__restrict__ bstart, int64_t nb,
                                    const uint64_t *__restrict__ klo,
-                                   const uint64_t *__restrict__ khi, TabEntry *tab, uint32_t mask)
+                                   const uint64_t *__restrict__ khi,
+                                   const int32_t *__restrict__ ids, TabEntry *tab, uint32_t mask)
 {
     for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
          b += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t lo = klo[brep[b]], hi = khi[brep[b]];
+        const uint32_t st = (uint32_t)bstart[b], sz = bsize[b];
+        uint32_t mh = 0xFFFFFFFFu;  // the bucket's min-hash (ids is the layer's CSR)
+        for (uint32_t i = 0; i < sz; ++i) mh = min(mh, id_mix((uint32_t)ids[st + i]));
         uint32_t slot = (uint32_t)key_mix(lo, hi) & mask;
         for (uint32_t it = 0; it <= mask; ++it) {
-            if (atomicCAS(&tab[slot].size, 0u, bsize[b]) == 0u) {
+            if (atomicCAS(&tab[slot].size, 0u, sz) == 0u) {
                 tab[slot].klo = lo;
                 tab[slot].khi = hi;
-                tab[slot].start = (uint32_t)bstart[b];
+                tab[slot].mh = mh;
+                tab[slot].start = st;
                 break;
             }
             slot = (slot + 1) & mask;
@@ -416,7 +421,8 @@ qw_status build_index(const void *data, int64_t n, int32_t d, int32_t dtype, con
             QW_TRY(launch_fill_u32(tabs[l].as<uint32_t>(), 0u, (int64_t)(sizeof(TabEntry) / 4) * fc, s));
             final_table_kernel<<<grid_of((int64_t)nb), kBlock, 0, s>>>(
                 bsize.as<uint32_t>(), brep.as<uint32_t>(), bstart.as<unsigned long long>(),
-                (int64_t)nb, klo.as<uint64_t>(), khi.as<uint64_t>(), tabs[l].as<TabEntry>(),
+                (int64_t)nb, klo.as<uint64_t>(), khi.as<uint64_t>(),
+                ix->ids.as<int32_t>() + (int64_t)l * n, tabs[l].as<TabEntry>(),
                 (uint32_t)(fc - 1));
             QW_HIP(hipGetLastError());
             masks[l] = (uint32_t)(fc - 1);

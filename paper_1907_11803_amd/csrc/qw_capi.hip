@@ -106,7 +106,7 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan, bool keys = false
 {
     Workspace &w = ix->ws;
     auto ptrs = [&w]() {
-        return std::vector<void *>{w.qpad.p, w.h.p, w.bstart.p, w.bsize.p, w.pred.p,
+        return std::vector<void *>{w.qpad.p, w.h.p, w.bstart.p, w.bsize.p, w.bmh.p, w.pred.p,
                                    w.feats.p, w.keys.p, w.keys2.p, w.vals.p, w.vals2.p,
                                    w.binoff.p, w.counters.p, w.ovf.p, w.gscratch.p, w.mlpout.p,
                                    w.order.p,
@@ -120,6 +120,7 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan, bool keys = false
     QW_TRY(w.h.ensure(sizeof(int32_t) * (size_t)q * ix->nf));
     QW_TRY(w.bstart.ensure(sizeof(uint32_t) * (size_t)q * ix->L));
     QW_TRY(w.bsize.ensure(sizeof(uint32_t) * (size_t)q * ix->L));
+    QW_TRY(w.bmh.ensure(sizeof(uint32_t) * (size_t)q * ix->L));
     QW_TRY(w.pred.ensure(sizeof(int32_t) * q));
     QW_TRY(w.feats.ensure(sizeof(float) * (size_t)q * ix->L));
     QW_TRY(w.mlpout.ensure(sizeof(float) * q));
@@ -137,8 +138,10 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan, bool keys = false
     if (plan) {
         const size_t g = (size_t)plan->grid_g * (size_t(1) << plan->cap_g) * 4;
         QW_TRY(w.gscratch.ensure(g));
-        // a multiple of kXcd: one equal region per XCD
-        const int64_t cand_cap = std::max<int64_t>(q * kCandPerQuery, 1 << 20);
+        // one equal region per XCD, each with room for its share of the
+        // queries plus one chunk of items per launch
+        const int64_t slack = (int64_t)kXcd * kXcdChunk * (kMaxClasses + 1);
+        const int64_t cand_cap = std::max<int64_t>((q + slack) * kCandPerQuery, 1 << 20);
         QW_TRY(w.coff.ensure(sizeof(unsigned long long) * q));
         QW_TRY(w.flag.ensure(sizeof(uint32_t) * q));
         if (keys) QW_TRY(w.pkeys.ensure(sizeof(unsigned long long) * cand_cap));
@@ -185,16 +188,17 @@ qw_status stage_query_rows(qw_index *ix, const void *x, int64_t m, hipStream_t s
 }
 
 // stage rows -> hash -> probe for Q queries (counters must already be cleared);
-// feats (nullable) receives the count-model inputs log(1 + s_{q,l})
+// feats (nullable) receives the count-model inputs log(1 + s_{q,l}), bmh
+// (nullable) the buckets' min-hashes
 qw_status front(qw_index *ix, const void *queries, int64_t Q, int form, hipStream_t s,
-                hipEvent_t *ev = nullptr, float *feats = nullptr)
+                hipEvent_t *ev = nullptr, float *feats = nullptr, uint32_t *bmh = nullptr)
 {
     QW_TRY(stage_query_rows(ix, queries, Q, s));
     QW_TRY(launch_hash(ix, ix->ws.qrows, Q, 0, ix->nf, form, ix->ws.h.as<int32_t>(), ix->nf,
                        c64(ix) + C_RECOMP, s));
     if (ev) QW_HIP(hipEventRecord(ev[1], s));
     QW_TRY(launch_probe(ix, ix->ws.h.as<int32_t>(), Q, ix->ws.bstart.as<uint32_t>(),
-                        ix->ws.bsize.as<uint32_t>(), feats, s));
+                        ix->ws.bsize.as<uint32_t>(), feats, bmh, s));
     return QW_OK;
 }
 
@@ -272,7 +276,8 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     // the binning kernel runs the count model itself; the grouped schedule
     // takes the predictions from the inference kernel
     QW_TRY(front(ix, queries, Q, QW_FORM_FAST, s, ev,
-                 learned && o.group ? w.feats.as<float>() : nullptr));
+                 learned && o.group ? w.feats.as<float>() : nullptr,
+                 o.group ? w.bmh.as<uint32_t>() : nullptr));
     if (ev) QW_HIP(hipEventRecord(ev[2], s));
     unsigned long long *seg = w.binoff.as<unsigned long long>();
     unsigned long long *ccount = c64(ix) + C_CLASS;
@@ -289,7 +294,7 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
             *order = w.order.as<int32_t>();
             return QW_OK;
         }
-        QW_TRY(launch_classify(Q, ix->L, ix->n, w.bstart.as<uint32_t>(),
+        QW_TRY(launch_classify(Q, ix->L, ix->n, w.bmh.as<uint32_t>(),
                                w.bsize.as<uint32_t>(), ex, pl, ix->mlp_margin, force_max, kCmin,
                                plan.cfloor, plan.cmax, plan.ncls, o.group, w.keys.as<unsigned long long>(),
                                w.vals.as<int32_t>(), ccount, s));
@@ -322,6 +327,7 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
             a.cls_hi = hi;
             a.queue_only = queue_only;
             a.cap_base = kCmin;
+            a.xchunk = o.group ? kXcdChunk : 1u;
             a.xwork = c32(ix) + W_XWORK + kXcd * slot;
             a.in_list = in_list;
             a.in_count = in_count;

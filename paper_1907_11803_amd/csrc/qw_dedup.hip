@@ -449,10 +449,13 @@ __device__ inline void fused_topk(const DedupArgs &A, int64_t q, LaneTop t, cons
     rank_write(c2);
 }
 
-// One workgroup per query (persistent).  The workgroups of XCD x take items
-// x, x + 8, x + 16, ... through that XCD's own counter (a single shared
-// counter would serialise every workgroup's atomic on one address); each
-// workgroup fetches its next item while the current one runs.  Queries with
+// One workgroup per query (persistent).  The items form chunks of A.xchunk
+// consecutive positions of the order, dealt to the XCDs in turn; the
+// workgroups of XCD x take the items of its chunks one by one through that
+// XCD's own counter (a single shared counter would serialise every
+// workgroup's atomic on one address), so neighbouring queries of the order --
+// grouped by candidate overlap -- share one XCD's L2.  Each workgroup fetches
+// its next item while the current one runs.  Queries with
 // at most kRegIds * kBlock
 // bucket entries in an LDS set keep their ids in registers from the load to
 // the write; larger ones (and the global-memory class, GLOB) go through the
@@ -519,9 +522,14 @@ __global__ __launch_bounds__(kBlock, 4) void dedup_kernel(DedupArgs A)
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
         }
     };
+    // the k-th item of this XCD
+    auto item_of = [&](uint32_t k) -> int64_t {
+        const uint32_t c = A.xchunk;
+        return ((int64_t)(k / c) * kXcd + xcd) * c + (int64_t)(k % c);
+    };
     if (tid == 0) scal[D_NEXT] = atomicAdd(A.xwork + xcd, 1u);
     __syncthreads();
-    int64_t item = (int64_t)xcd + (int64_t)kXcd * scal[D_NEXT];
+    int64_t item = item_of(scal[D_NEXT]);
     uint32_t pf_start = 0, pf_size = 0;  // threads < L: bucket range of the next query
     if (item < nall && tid < A.L) {
         const int64_t q0 = query_of(item);
@@ -633,7 +641,7 @@ __global__ __launch_bounds__(kBlock, 4) void dedup_kernel(DedupArgs A)
         }
         bar();
         const unsigned long long off = *soff;
-        item = (int64_t)xcd + (int64_t)kXcd * scal[D_NEXT];
+        item = item_of(scal[D_NEXT]);
         if (item < nall && tid < A.L) {  // the next query's bucket ranges fly during the writes
             const int64_t qn = query_of(item);
             pf_start = A.bstart[qn * A.L + tid];
@@ -668,6 +676,7 @@ qw_status launch_dedup(const DedupArgs &a, int grid, hipStream_t s)
 {
     if (grid <= 0) return QW_OK;
     // the fused top K: uint8 rows of at most 64 parts, 1 <= K <= kFusedTopK
+    if (a.xchunk < 1 || a.xchunk > kXcdChunk) return QW_EINVAL;
     if (a.topk && (a.dtype != QW_U8 || a.dp > 64 * 16 || a.topk > kFusedTopK || a.topk < 0 ||
                    a.topk_keep < 1 || a.topk_keep > kTopR))
         return QW_EINVAL;

@@ -514,13 +514,15 @@ qw_status launch_hash(const qw_index *ix, const void *xpad, int64_t m, int32_t f
 // One thread per (query, layer): pack the layer's k hash values into the exact
 // key (values outside the data's range cannot match any bucket: a miss; the
 // key of such a layer is never looked up), then look the key up in the
-// layer's open-addressing table.
+// layer's open-addressing table.  bmh (nullable) receives the bucket's
+// min-hash (0xFFFFFFFF on a miss).
 __global__ __launch_bounds__(kBlock) void probe_kernel(
     const int32_t *__restrict__ h, int64_t Q, int32_t L, int32_t k,
     const int32_t *__restrict__ hmin, const int32_t *__restrict__ hmax,
     const int32_t *__restrict__ shift, const TabEntry *__restrict__ tab,
     const long long *__restrict__ tab_off, const uint32_t *__restrict__ tab_mask,
-    uint32_t *__restrict__ bstart, uint32_t *__restrict__ bsize, float *__restrict__ feats)
+    uint32_t *__restrict__ bstart, uint32_t *__restrict__ bsize, float *__restrict__ feats,
+    uint32_t *__restrict__ bmh)
 {
     // per-function constants (value range, bit offset in the key) staged in
     // LDS while the hash values load: one memory latency for both
@@ -551,7 +553,7 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(
             valid = valid && hv[j] >= lo && hv[j] <= fconst[nf + f];
             key_put(klo, khi, (uint64_t)((int64_t)hv[j] - (int64_t)lo), fconst[2 * nf + f]);
         }
-    uint32_t st = 0, sz = 0;
+    uint32_t st = 0, sz = 0, mh = 0xFFFFFFFFu;
     if (valid) {
         // linear probing, four slots per round trip: the slots of a probe
         // sequence are loaded together, so a lane's wait is a quarter of its
@@ -573,6 +575,7 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(
                 } else if (e[i].klo == klo && e[i].khi == khi) {
                     st = e[i].start;
                     sz = e[i].size;
+                    mh = e[i].mh;
                     done = true;
                 }
             }
@@ -582,10 +585,11 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(
     bstart[idx] = st;
     bsize[idx] = sz;
     if (feats) feats[idx] = log1pf((float)sz);  // count-model input, f = log(1 + s)
+    if (bmh) bmh[idx] = mh;
 }
 
 qw_status launch_probe(const qw_index *ix, const int32_t *h, int64_t Q, uint32_t *bstart,
-                       uint32_t *bsize, float *feats, hipStream_t s)
+                       uint32_t *bsize, float *feats, uint32_t *bmh, hipStream_t s)
 {
     if (Q <= 0) return QW_OK;
     const int64_t total = Q * ix->L;
@@ -593,7 +597,7 @@ qw_status launch_probe(const qw_index *ix, const int32_t *h, int64_t Q, uint32_t
     probe_kernel<<<(unsigned)ceil_div(total, kBlock), kBlock, lds, s>>>(
         h, Q, ix->L, ix->k, ix->hmin.as<int32_t>(), ix->hmax.as<int32_t>(),
         ix->shift.as<int32_t>(), ix->tab.as<TabEntry>(), ix->tab_off.as<long long>(),
-        ix->tab_mask.as<uint32_t>(), bstart, bsize, feats);
+        ix->tab_mask.as<uint32_t>(), bstart, bsize, feats, bmh);
     QW_HIP(hipGetLastError());
     return QW_OK;
 }

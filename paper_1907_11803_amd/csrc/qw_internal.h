@@ -21,6 +21,10 @@ constexpr int kBlock = 256;              // threads per workgroup for every kern
 constexpr int kRecompSlots = 32;
 // Largest K the fused dedup kernel selects itself (uint8 data).
 constexpr int kFusedTopK = 16;
+// With bucket grouping the dedup kernel deals its items to the XCDs in chunks
+// of this many consecutive positions of the order (each XCD then takes at most
+// one chunk more than its share per launch); without, one at a time.
+constexpr uint32_t kXcdChunk = 16;
 // Automatic bucket grouping orders queries by bucket key when a candidate's row
 // is at least this many bytes: the verification then reads whole rows that
 // neighbouring queries of one bucket share in L2 and the last-level cache,
@@ -71,10 +75,25 @@ struct DevBuf {
 struct TabEntry {
     uint64_t klo, khi;
     uint32_t start, size;  // CSR range of the bucket; size == 0 marks an empty slot
+    uint32_t mh;           // min over the bucket's ids of id_mix(id) (grouping key)
+    uint32_t unused;
 };
 
+// A fixed 32-bit mixer of point ids: the minimum of id_mix over a candidate
+// set is a min-hash of the set, so two queries share their key with
+// probability equal to the Jaccard similarity of their candidate sets.
+__host__ __device__ inline uint32_t id_mix(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7FEB352Du;
+    x ^= x >> 15;
+    x *= 0x846CA68Bu;
+    x ^= x >> 16;
+    return x;
+}
+
 struct Workspace {
-    DevBuf qpad, h, bstart, bsize, pred, feats, keys, keys2, vals, vals2, hist,
+    DevBuf qpad, h, bstart, bsize, bmh, pred, feats, keys, keys2, vals, vals2, hist,
         order, binoff, counters, ovf, gscratch, mlpout, scan;
     // flat pipeline
     DevBuf ucount, coff, flag, pkeys, fb;
@@ -174,9 +193,10 @@ qw_status launch_hash(const qw_index *ix, const void *xpad, int64_t m, int32_t f
                       int32_t form, int32_t *out, int32_t out_ld,
                       unsigned long long *recomputed, hipStream_t s);
 
-// Probe every (query, layer): bstart/bsize [Q][L] (bsize 0 = miss); qsum[q] = sum of sizes.
+// Probe every (query, layer): bstart/bsize [Q][L] (bsize 0 = miss); feats
+// (nullable) log(1 + size); bmh (nullable) the bucket's min-hash.
 qw_status launch_probe(const qw_index *ix, const int32_t *h, int64_t Q, uint32_t *bstart,
-                       uint32_t *bsize, float *feats, hipStream_t s);
+                       uint32_t *bsize, float *feats, uint32_t *bmh, hipStream_t s);
 
 // Generic fills.
 qw_status launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s);
@@ -238,7 +258,7 @@ int verify_blocks_per_cu(int dp, int dtype, size_t lds);
 
 // ---------------------------------------------------------------- scheduling
 qw_status launch_classify(int64_t Q, int32_t L, int64_t n,
-                          const uint32_t *bstart, const uint32_t *bsize, const int32_t *exact,
+                          const uint32_t *bmh, const uint32_t *bsize, const int32_t *exact,
                           const float *pred_log, float margin, int32_t force_max, int32_t cmin,
                           int32_t cfloor, int32_t cmax, int32_t ncls, int32_t group,
                           unsigned long long *keys,
@@ -276,6 +296,7 @@ struct DedupArgs {
     int32_t cls_lo, cls_hi;          // this launch serves classes cls_lo..cls_hi
     int32_t queue_only;              // serve only the in_list queue (no segment)
     int32_t cap_base;                // class c uses a set of 2^(cap_base + c) slots
+    uint32_t xchunk;                 // items dealt to each XCD in turn (1 .. kXcdChunk)
     uint32_t *xwork;                 // [kXcd] work counters, one per XCD (zero on entry)
     const uint32_t *in_count;        // nullable: queue of overflowed queries served after the segment
     const int32_t *in_list;

@@ -1,11 +1,14 @@
 // Workload scheduling kernels: hash-set size classes, bucket grouping keys,
 // class segments and statistics.
 //
-// Queries of a workload that fall in the same bucket are processed back to
-// back (the sort key groups them by the bucket of their first non-empty
-// layer), so the bucket's ids and points are fetched from HBM once and then
-// served from L2 / the Infinity Cache -- the GPU counterpart of keeping reused
-// index files and data objects in the cache (Sections 4 and 5.1).
+// Queries of a workload whose candidate sets overlap are processed back to
+// back: the sort key is a min-hash of the candidate set (the minimum over the
+// query's buckets of each bucket's minimum id_mix(id), kept in the probe
+// table), equal for two queries with probability equal to the Jaccard
+// similarity of their sets.  The shared ids and points are then fetched from
+// HBM once and served from L2 / the Infinity Cache -- the GPU counterpart of
+// keeping reused index files and data objects in the cache (Sections 4 and
+// 5.1).
 #include "qw_internal.h"
 #include "qw_mlp.h"
 
@@ -53,7 +56,7 @@ __device__ inline int class_of(uint64_t tsum, int64_t n, const int32_t *__restri
 // Key = class << 16 | 16-bit group of every query, for the radix sort.
 __global__ __launch_bounds__(kBlock) void classify_kernel(
     int64_t Q, int32_t L, int64_t n,
-    const uint32_t *__restrict__ bstart, const uint32_t *__restrict__ bsize,
+    const uint32_t *__restrict__ bmh, const uint32_t *__restrict__ bsize,
     const int32_t *__restrict__ exact, const float *__restrict__ pred_log, float margin,
     int32_t force_max, int32_t cmin, int32_t cfloor, int32_t cmax, int32_t ncls, int32_t group,
     unsigned long long *__restrict__ keys, int32_t *__restrict__ vals,
@@ -70,13 +73,10 @@ __global__ __launch_bounds__(kBlock) void classify_kernel(
                                  pred_log ? pred_log[q] : 0.f, margin, force_max, cmin, cfloor,
                                  cmax, ncls);
         uint32_t g = 0;
-        if (group) {
-            for (int32_t l = 0; l < L; ++l) {
-                if (bsize[q * L + l]) {
-                    g = mix32(((uint64_t)l << 32) | bstart[q * L + l]) & 0xFFFFu;
-                    break;
-                }
-            }
+        if (group) {  // min-hash of C(q): misses carry 0xFFFFFFFF
+            uint32_t m = 0xFFFFFFFFu;
+            for (int32_t l = 0; l < L; ++l) m = min(m, bmh[q * L + l]);
+            g = mix32(m) & 0xFFFFu;
         }
         keys[q] = ((unsigned long long)cls << 16) | g;
         vals[q] = (int32_t)q;
@@ -194,7 +194,7 @@ qw_status launch_classify_bin(int64_t Q, int32_t L, int64_t n, const uint32_t *b
 }
 
 qw_status launch_classify(int64_t Q, int32_t L, int64_t n,
-                          const uint32_t *bstart, const uint32_t *bsize, const int32_t *exact,
+                          const uint32_t *bmh, const uint32_t *bsize, const int32_t *exact,
                           const float *pred_log, float margin, int32_t force_max, int32_t cmin,
                           int32_t cfloor, int32_t cmax, int32_t ncls, int32_t group,
                           unsigned long long *keys, int32_t *vals,
@@ -202,7 +202,7 @@ qw_status launch_classify(int64_t Q, int32_t L, int64_t n,
 {
     if (Q <= 0) return QW_OK;
     int g = (int)std::min<int64_t>(1024, ceil_div(Q, kBlock));
-    classify_kernel<<<g, kBlock, 0, s>>>(Q, L, n, bstart, bsize, exact, pred_log, margin,
+    classify_kernel<<<g, kBlock, 0, s>>>(Q, L, n, bmh, bsize, exact, pred_log, margin,
                                          force_max, cmin, cfloor, cmax, ncls, group, keys, vals,
                                          class_count);
     QW_HIP(hipGetLastError());
