@@ -327,6 +327,9 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
                      "traffic": traffic, "kernel": kname,
+                     # HBM bytes the counters saw over the same kernel time
+                     "traffic_achieved": round(traffic / (kms * 1e-3) / 1e9, 1) if traffic and kms > 0 else None,
+                     "traffic_frac": round(traffic / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if traffic and kms > 0 else None,
                      "kernel_ms": round(kms, 4),
                      "kernel_algorithmic_bytes": int(kbytes),
                      "path_algorithmic_bytes_per_step": int(alg_bytes)},

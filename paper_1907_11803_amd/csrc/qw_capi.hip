@@ -139,8 +139,8 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan, bool keys = false
         const size_t g = (size_t)plan->grid_g * (size_t(1) << plan->cap_g) * 4;
         QW_TRY(w.gscratch.ensure(g));
         // one equal region per XCD, each with room for its share of the
-        // queries plus one chunk of items per launch
-        const int64_t slack = (int64_t)kXcd * kXcdChunk * (kMaxClasses + 1);
+        // queries plus one chunk of items per dedup launch (at most ncls + 1)
+        const int64_t slack = (int64_t)kXcd * kXcdChunk * (plan->ncls + 1);
         const int64_t cand_cap = std::max<int64_t>((q + slack) * kCandPerQuery, 1 << 20);
         QW_TRY(w.coff.ensure(sizeof(unsigned long long) * q));
         QW_TRY(w.flag.ensure(sizeof(uint32_t) * q));

@@ -24,7 +24,7 @@ constexpr int kFusedTopK = 16;
 // With bucket grouping the dedup kernel deals its items to the XCDs in chunks
 // of this many consecutive positions of the order (each XCD then takes at most
 // one chunk more than its share per launch); without, one at a time.
-constexpr uint32_t kXcdChunk = 16;
+constexpr uint32_t kXcdChunk = 256;
 // Automatic bucket grouping orders queries by bucket key when a candidate's row
 // is at least this many bytes: the verification then reads whole rows that
 // neighbouring queries of one bucket share in L2 and the last-level cache,
