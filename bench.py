@@ -301,7 +301,7 @@ def main():
                          f"Q={wl.Q} queries, L={L} k={wl.params.k} w={w} (w_0.9), K={K}"),
             "n": wl.n, "d": wl.d, "Q": wl.Q, "L": L, "k": wl.params.k, "w": w, "K": K,
             "projection": "fp16-mfma+fp64-guard" if is_u8 else "fp32-mfma+fp64-guard",
-            "bucket_grouping": "automatic (rows of 1024 bytes or more)",
+            "bucket_grouping": "automatic (rows of 1024 bytes or more, or 32768 queries or more)",
             "w_search": tried,
         },
         "recall_at_10": round(rec, 4),

@@ -81,8 +81,9 @@ typedef struct {
     int32_t sched;     /* qw_sched (fast form only) */
     int32_t group;     /* fast form: 1 = order queries by bucket key within a size class,
                           0 = no bucket ordering, -1 = automatic (default): ordering for
-                          rows of 1024 bytes or more, where neighbouring queries of one
-                          bucket share the rows they verify in cache */
+                          rows of 1024 bytes or more or workloads of 32768 queries or
+                          more, where neighbouring queries share the rows they verify
+                          in cache */
     int32_t graph;     /* fast form: 1 = capture/replay the query pipeline as a HIP graph */
     int32_t timing;    /* 1 = record per-stage HIP events and report them in qw_stats (syncs) */
     int32_t topk_keep; /* fast form, uint8 rows of at most 1024 bytes, K <= 16: the dedup kernel

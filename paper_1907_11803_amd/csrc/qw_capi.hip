@@ -527,7 +527,7 @@ void qw_default_opts(qw_opts *o)
     std::memset(o, 0, sizeof(*o));
     o->form = QW_FORM_FAST;
     o->sched = QW_SCHED_LEARNED;
-    o->group = -1;  // automatic: order by bucket key for rows of kGroupRowBytes or more
+    o->group = -1;  // automatic: kGroupRowBytes or kGroupQueries
     o->graph = 1;
     o->timing = 0;
 }
@@ -641,7 +641,8 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
         const int sched = opt.sched == QW_SCHED_LEARNED && !learned ? QW_SCHED_SUM : opt.sched;
         qw_opts eff = opt;
         eff.sched = sched;
-        if (eff.group < 0) eff.group = ix->dp * (ix->dtype == QW_U8 ? 1 : 4) >= kGroupRowBytes;
+        if (eff.group < 0)
+            eff.group = ix->dp * (ix->dtype == QW_U8 ? 1 : 4) >= kGroupRowBytes || Q >= kGroupQueries;
         if (opt.timing || !opt.graph) {
             QW_TRY(enqueue_fast(ix, plan, queries, Q, K, eff, s, out_ids, out_dist,
                                 opt.timing ? ix->ev : nullptr));
