@@ -48,13 +48,13 @@ def _load():
         i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         lib.orc_hash.argtypes = [P, i64, i32, i32, P, P, i32, f64, i32, P]
         lib.orc_lsh_query.argtypes = [P, i64, i32, i32, P, i64, P, P, i32, i32, f64, i32, i32,
-                                      P, P, P, P]
+                                      P, P, P, P, i32]
         lib.orc_lsh_candidates.argtypes = [P, i64, i32, i32, P, i64, P, P, i32, i32, f64, i32,
-                                           P, P, P]
+                                           P, P, P, i32]
         lib.orc_bruteforce.argtypes = [P, i64, i32, i32, P, i64, i32, i32, P, P, P]
         lib.orc_lsh_build.argtypes = [P, i64, i32, i32, P, P, i32, i32, f64, i32]
         lib.orc_lsh_build.restype = ctypes.c_void_p
-        lib.orc_lsh_query_built.argtypes = [P, P, i64, i32, i32, P, P, P, P]
+        lib.orc_lsh_query_built.argtypes = [P, P, i64, i32, i32, P, P, P, P, i32]
         lib.orc_lsh_free.argtypes = [P]
         lib.orc_lsh_free.restype = None
         for f in (lib.orc_hash, lib.orc_lsh_query, lib.orc_lsh_candidates, lib.orc_bruteforce,
@@ -100,8 +100,9 @@ def hash_points(x: np.ndarray, a: np.ndarray, b: np.ndarray, w: float,
 
 
 def lsh_query(data: np.ndarray, queries: np.ndarray, a: np.ndarray, b: np.ndarray,
-              w: float, K: int, nthreads: Optional[int] = None):
-    """Top-K of every query over its LSH candidates.
+              w: float, K: int, nthreads: Optional[int] = None, probes: int = 0):
+    """Top-K of every query over its LSH candidates (probes=1: also the 2k
+    one-step neighbour buckets of every layer).
     Returns (ids int32 [Q,K], dist [Q,K] int64 (u8) or float64 (f32), counts int64 [Q])."""
     data = np.ascontiguousarray(data)
     queries = np.ascontiguousarray(queries)
@@ -120,15 +121,16 @@ def lsh_query(data: np.ndarray, queries: np.ndarray, a: np.ndarray, b: np.ndarra
         pi, pf = None, _ptr(dist)
     rc = _load().orc_lsh_query(_ptr(data), data.shape[0], d, dt, _ptr(queries), Q, _ptr(a),
                                _ptr(b), L, k, float(np.float32(w)), int(K), _threads(nthreads),
-                               _ptr(ids), pi, pf, _ptr(cnt))
+                               _ptr(ids), pi, pf, _ptr(cnt), int(probes))
     if rc:
         raise ValueError("orc_lsh_query failed (%d)" % rc)
     return ids, dist, cnt
 
 
 def lsh_candidates(data: np.ndarray, queries: np.ndarray, a: np.ndarray, b: np.ndarray,
-                   w: float, nthreads: Optional[int] = None) -> List[np.ndarray]:
-    """Candidate set C(q) of every query, each as ascending int32 ids."""
+                   w: float, nthreads: Optional[int] = None, probes: int = 0) -> List[np.ndarray]:
+    """Candidate set C(q) of every query, each as ascending int32 ids (probes=1:
+    with the one-step neighbour buckets)."""
     data = np.ascontiguousarray(data)
     queries = np.ascontiguousarray(queries)
     L, k, d = a.shape
@@ -140,13 +142,13 @@ def lsh_candidates(data: np.ndarray, queries: np.ndarray, a: np.ndarray, b: np.n
     cnt = np.empty((Q,), dtype=np.int64)
     args = (_ptr(data), data.shape[0], d, dt, _ptr(queries), Q, _ptr(a), _ptr(b), L, k,
             float(np.float32(w)), _threads(nthreads))
-    rc = lib.orc_lsh_candidates(*args, _ptr(cnt), None, None)
+    rc = lib.orc_lsh_candidates(*args, _ptr(cnt), None, None, int(probes))
     if rc:
         raise ValueError("orc_lsh_candidates failed (%d)" % rc)
     off = np.zeros(Q + 1, dtype=np.int64)
     np.cumsum(cnt, out=off[1:])
     ids = np.empty(max(1, int(off[-1])), dtype=np.int32)
-    rc = lib.orc_lsh_candidates(*args, _ptr(cnt), _ptr(off), _ptr(ids))
+    rc = lib.orc_lsh_candidates(*args, _ptr(cnt), _ptr(off), _ptr(ids), int(probes))
     if rc:
         raise ValueError("orc_lsh_candidates failed (%d)" % rc)
     return [ids[off[i]:off[i + 1]].copy() for i in range(Q)]
@@ -190,7 +192,7 @@ class BuiltIndex:
         if not self.h:
             raise ValueError("orc_lsh_build failed")
 
-    def query(self, queries, K):
+    def query(self, queries, K, probes=0):
         queries = np.ascontiguousarray(queries)
         Q = queries.shape[0]
         ids = np.empty((Q, K), dtype=np.int32)
@@ -202,7 +204,8 @@ class BuiltIndex:
             dist = np.empty((Q, K), dtype=np.float64)
             pi, pf = None, _ptr(dist)
         rc = _load().orc_lsh_query_built(ctypes.c_void_p(self.h), _ptr(queries), Q, int(K),
-                                         self.nthreads, _ptr(ids), pi, pf, _ptr(cnt))
+                                         self.nthreads, _ptr(ids), pi, pf, _ptr(cnt),
+                                         int(probes))
         if rc:
             raise ValueError("orc_lsh_query_built failed (%d)" % rc)
         return ids, dist, cnt

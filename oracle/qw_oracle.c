@@ -25,6 +25,11 @@
  *     of equal tuples.
  *  4. Candidates of query q (Section 1.2 / 5.1: the index yields candidate ids):
  *     C(q) = { p : exists l with key_l(p) == key_l(q) }, as a set.
+ *     With neighbour probing (the multi-probe variant of Lv et al. that
+ *     Section 2 summarises: look into the buckets next to the query's bucket
+ *     instead of adding layers) every layer also contributes the buckets whose
+ *     tuple differs from the query's in exactly one coordinate by -1 or +1:
+ *     C(q) = { p : exists l with key_l(p) - key_l(q) in {0, -e_j, +e_j} }.
  *  5. Verification (removing false positives, Section 1.2): exact squared
  *     Euclidean distance; int64 for uint8 data, double accumulated in index
  *     order for float32 data: acc = acc + (x-q)*(x-q) with x-q formed in double.
@@ -242,6 +247,7 @@ static void distance(const void *data, const void *q, int dtype, int32_t d,
 
 typedef struct {
     const orc_index *ix; const int32_t *hq; /* [Q][L*k] query hashes (NULL = brute force) */
+    int32_t probes; /* 1: also the 2k one-step neighbour buckets of every layer */
     const void *data; const void *q; int dtype; int32_t d; int64_t Q; int32_t K;
     int32_t *out_ids; int64_t *out_di; double *out_df; int64_t *out_cnt;
     int64_t *cand_off; int32_t *cand_ids; /* optional candidate-list output */
@@ -257,15 +263,24 @@ static void *query_worker(void *p)
     scored *sc = (scored *)malloc(sizeof(scored) * (size_t)(n > 0 ? n : 1));
     if (!mark || !list || !sc) { j->err = 1; free(mark); free(list); free(sc); return NULL; }
     int32_t L = j->ix->L, k = j->ix->k;
+    int32_t t[64];
+    const int32_t nprobe = j->probes ? 1 + 2 * k : 1;
     for (int64_t qi = j->tid; qi < j->Q; qi += j->nthreads) {
         int64_t nc = 0;
-        if (j->hq) {  /* step 4: union of the query's bucket in every layer */
+        if (j->hq) {  /* step 4: union of the query's bucket(s) in every layer */
             for (int32_t l = 0; l < L; ++l) {
-                int64_t cnt;
-                int64_t pos = bucket_find(j->ix, l, j->hq + qi * (int64_t)L * k + (int64_t)l * k, &cnt);
-                const int32_t *o = j->ix->order + (int64_t)l * n;
-                for (int64_t e = pos; e < pos + cnt; ++e)
-                    if (!mark[o[e]]) { mark[o[e]] = 1; list[nc++] = o[e]; }
+                const int32_t *home = j->hq + qi * (int64_t)L * k + (int64_t)l * k;
+                for (int32_t pr = 0; pr < nprobe; ++pr) {
+                    /* probe 0: the home tuple; probe 1 + 2c + s: coordinate c moved
+                       by -1 (s = 0) or +1 (s = 1) */
+                    for (int32_t c = 0; c < k; ++c) t[c] = home[c];
+                    if (pr > 0) t[(pr - 1) / 2] += ((pr - 1) % 2) ? 1 : -1;
+                    int64_t cnt;
+                    int64_t pos = bucket_find(j->ix, l, t, &cnt);
+                    const int32_t *o = j->ix->order + (int64_t)l * n;
+                    for (int64_t e = pos; e < pos + cnt; ++e)
+                        if (!mark[o[e]]) { mark[o[e]] = 1; list[nc++] = o[e]; }
+                }
             }
             for (int64_t c = 0; c < nc; ++c) mark[list[c]] = 0;
         } else {      /* step 7: every point */
@@ -333,9 +348,11 @@ static int check_common(const void *data, int64_t n, int32_t d, const void *q, i
 int orc_lsh_query(const void *data, int64_t n, int32_t d, int32_t dtype,
                   const void *q, int64_t Q, const float *a, const float *b,
                   int32_t L, int32_t k, double w, int32_t K, int32_t nthreads,
-                  int32_t *out_ids, int64_t *out_di, double *out_df, int64_t *out_cnt)
+                  int32_t *out_ids, int64_t *out_di, double *out_df, int64_t *out_cnt,
+                  int32_t probes)
 {
     if (check_common(data, n, d, q, Q, a, b, L, k, w) || K <= 0 || !out_ids) return -1;
+    if (probes < 0 || probes > 1 || k > 64) return -1;
     int32_t nf = L * k;
     int32_t *hd = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1) * nf);
     int32_t *hq = (int32_t *)malloc(sizeof(int32_t) * (size_t)(Q > 0 ? Q : 1) * nf);
@@ -345,8 +362,8 @@ int orc_lsh_query(const void *data, int64_t n, int32_t d, int32_t dtype,
     orc_index ix = {0};
     if (!rc) rc = index_build(&ix, hd, n, L, k, nthreads);
     if (!rc) {
-        query_job t = {&ix, hq, data, q, dtype, d, Q, K, out_ids, out_di, out_df, out_cnt,
-                       NULL, NULL, 0, 1, 0};
+        query_job t = {&ix, hq, probes, data, q, dtype, d, Q, K, out_ids, out_di, out_df,
+                       out_cnt, NULL, NULL, 0, 1, 0};
         rc = run_queries(&t, nthreads);
     }
     free(ix.order); free(hd); free(hq);
@@ -361,9 +378,11 @@ int orc_lsh_query(const void *data, int64_t n, int32_t d, int32_t dtype,
 int orc_lsh_candidates(const void *data, int64_t n, int32_t d, int32_t dtype,
                        const void *q, int64_t Q, const float *a, const float *b,
                        int32_t L, int32_t k, double w, int32_t nthreads,
-                       int64_t *out_cnt, const int64_t *cand_off, int32_t *cand_ids)
+                       int64_t *out_cnt, const int64_t *cand_off, int32_t *cand_ids,
+                       int32_t probes)
 {
     if (check_common(data, n, d, q, Q, a, b, L, k, w) || !out_cnt) return -1;
+    if (probes < 0 || probes > 1 || k > 64) return -1;
     if (cand_ids && !cand_off) return -1;
     int32_t nf = L * k;
     int32_t *hd = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1) * nf);
@@ -374,7 +393,7 @@ int orc_lsh_candidates(const void *data, int64_t n, int32_t d, int32_t dtype,
     orc_index ix = {0};
     if (!rc) rc = index_build(&ix, hd, n, L, k, nthreads);
     if (!rc) {
-        query_job t = {&ix, hq, data, q, dtype, d, Q, 0, NULL, NULL, NULL, out_cnt,
+        query_job t = {&ix, hq, probes, data, q, dtype, d, Q, 0, NULL, NULL, NULL, out_cnt,
                        (int64_t *)cand_off, cand_ids, 0, 1, 0};
         rc = run_queries(&t, nthreads);
     }
@@ -410,16 +429,18 @@ void *orc_lsh_build(const void *data, int64_t n, int32_t d, int32_t dtype, const
 }
 
 int orc_lsh_query_built(void *h, const void *q, int64_t Q, int32_t K, int32_t nthreads,
-                        int32_t *out_ids, int64_t *out_di, double *out_df, int64_t *out_cnt)
+                        int32_t *out_ids, int64_t *out_di, double *out_df, int64_t *out_cnt,
+                        int32_t probes)
 {
     orc_built *o = (orc_built *)h;
     if (!o || !q || Q < 0 || K <= 0 || !out_ids) return -1;
+    if (probes < 0 || probes > 1 || o->k > 64) return -1;
     int32_t *hq = (int32_t *)malloc(sizeof(int32_t) * (size_t)(Q > 0 ? Q : 1) * o->L * o->k);
     if (!hq) return -5;
     int rc = orc_hash(q, Q, o->d, o->dtype, o->a, o->b, o->L * o->k, o->w, nthreads, hq);
     if (!rc) {
-        query_job t = {&o->ix, hq, o->data, q, o->dtype, o->d, Q, K, out_ids, out_di, out_df,
-                       out_cnt, NULL, NULL, 0, 1, 0};
+        query_job t = {&o->ix, hq, probes, o->data, q, o->dtype, o->d, Q, K, out_ids, out_di,
+                       out_df, out_cnt, NULL, NULL, 0, 1, 0};
         rc = run_queries(&t, nthreads);
     }
     free(hq);
@@ -441,7 +462,7 @@ int orc_bruteforce(const void *data, int64_t n, int32_t d, int32_t dtype,
     if (!data || !q || n < 0 || Q < 0 || d <= 0 || K <= 0 || !out_ids || n > INT32_MAX)
         return -1;
     orc_index ix = {NULL, NULL, n, 1, 1};
-    query_job t = {&ix, NULL, data, q, dtype, d, Q, K, out_ids, out_di, out_df, NULL,
+    query_job t = {&ix, NULL, 0, data, q, dtype, d, Q, K, out_ids, out_di, out_df, NULL,
                    NULL, NULL, 0, 1, 0};
     return run_queries(&t, nthreads);
 }

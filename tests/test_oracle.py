@@ -144,6 +144,60 @@ def test_candidates_equal_union_of_bucket_members(dtype):
         assert np.array_equal(c, nv)
 
 
+def _naive_probe_candidates(hd, hq, L, k):
+    """Neighbour probing written from its definition with numpy broadcasting: p
+    is a candidate when, in some layer, its tuple minus the query's is zero or
+    has a single non-zero coordinate equal to -1 or +1."""
+    hd3 = hd.reshape(hd.shape[0], L, k).astype(np.int64)
+    out = []
+    for q in range(hq.shape[0]):
+        diff = hd3 - hq[q].reshape(1, L, k).astype(np.int64)  # [n, L, k]
+        nz = np.count_nonzero(diff, axis=2)
+        l1 = np.abs(diff).sum(axis=2)
+        ok = (nz == 0) | ((nz == 1) & (l1 == 1))
+        out.append(np.nonzero(ok.any(axis=1))[0].astype(np.int32))
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_neighbour_probing_candidates_match_definition(dtype):
+    """Candidates with neighbour probing equal the definition, contain the
+    plain candidates, and add some (w chosen so buckets are small)."""
+    wl = synth.make_config(1, n=3000, Q=40, w=500.0) if dtype == "u8" else \
+        synth.make_config(3, n=2000, Q=30, ncomp=20, w=4.0)
+    a, b, w = wl.params.a, wl.params.b(), wl.params.w
+    L, k = wl.params.L, wl.params.k
+    plain = oracle.lsh_candidates(wl.data, wl.queries, a, b, w)
+    probed = oracle.lsh_candidates(wl.data, wl.queries, a, b, w, probes=1)
+    hd = oracle.hash_points(wl.data, a, b, w)
+    hq = oracle.hash_points(wl.queries, a, b, w)
+    naive = _naive_probe_candidates(hd, hq, L, k)
+    added = 0
+    for c0, c1, nv in zip(plain, probed, naive):
+        assert np.array_equal(c1, nv)
+        assert np.isin(c0, c1).all()
+        added += len(c1) - len(c0)
+    assert added > 0
+
+
+def test_neighbour_probing_topk_is_topk_of_candidates():
+    """The probed top K is the (distance, id) top K of the probed candidate set,
+    selected here with numpy's lexsort over int64 distances."""
+    wl = synth.make_config(1, n=3000, Q=25, w=500.0)
+    a, b, w, K = wl.params.a, wl.params.b(), wl.params.w, 10
+    ids, dist, cnt = oracle.lsh_query(wl.data, wl.queries, a, b, w, K, probes=1)
+    cands = oracle.lsh_candidates(wl.data, wl.queries, a, b, w, probes=1)
+    for q in range(wl.queries.shape[0]):
+        c = cands[q]
+        assert cnt[q] == len(c)
+        dq = ((wl.data[c].astype(np.int64) - wl.queries[q].astype(np.int64)) ** 2).sum(axis=1)
+        order = np.lexsort((c, dq))[:K]
+        want = np.full(K, -1, np.int32)
+        want[:len(order)] = c[order]
+        assert np.array_equal(ids[q], want)
+        assert np.array_equal(dist[q, :len(order)], dq[order])
+
+
 def test_huge_w_equals_exact_knn_u8():
     """w huge and b = w/2: every projection lands in bucket 0, so every point is a
     candidate and the result is exact kNN (checked against numpy brute force)."""
@@ -403,8 +457,9 @@ def test_adam_first_step_is_lr_times_sign():
 def test_built_index_matches_one_shot_query():
     wl = synth.make_config(1, n=2000, Q=30, w=1000.0)
     a, b, w = wl.params.a, wl.params.b(), wl.params.w
-    ids1, d1, c1 = oracle.lsh_query(wl.data, wl.queries, a, b, w, 10)
     bi = oracle.BuiltIndex(wl.data, a, b, w)
-    ids2, d2, c2 = bi.query(wl.queries, 10)
+    for probes in (0, 1):
+        ids1, d1, c1 = oracle.lsh_query(wl.data, wl.queries, a, b, w, 10, probes=probes)
+        ids2, d2, c2 = bi.query(wl.queries, 10, probes=probes)
+        assert np.array_equal(ids1, ids2) and np.array_equal(d1, d2) and np.array_equal(c1, c2)
     bi.close()
-    assert np.array_equal(ids1, ids2) and np.array_equal(d1, d2) and np.array_equal(c1, c2)
