@@ -123,6 +123,7 @@ typedef struct {
     int64_t device_bytes;  /* device memory held by the index */
     int32_t has_count_model;
     float count_margin;    /* log-space margin added to the model's prediction when sizing sets */
+    int32_t probing;       /* qw_set_probing mode (0: the query's own bucket per layer) */
 } qw_index_info;
 
 typedef struct qw_index qw_index;
@@ -263,6 +264,23 @@ qw_status qw_get_count_model(const qw_index *ix, float *params, int32_t P);
 /* Sizing margin: a set is sized for expm1(prediction + margin) + 32 ids
  * (finite, -4 <= margin <= 8; QW_EINVAL otherwise). */
 qw_status qw_set_count_margin(qw_index *ix, float margin);
+
+/*
+ * Neighbour probing: the multi-probe variant that Section 2 summarises
+ * (look into the buckets next to the query's bucket instead of adding
+ * layers).
+ *  mode 0 (default): each layer contributes the query's own bucket;
+ *  mode 1: each layer also contributes the 2k buckets whose k-tuple differs
+ *          from the query's in exactly one coordinate by -1 or +1, so
+ *          C(q) = { p : exists l, key_l(p) - key_l(q) in {0, -e_j, +e_j} }.
+ * Every later call on the index (queries, candidate counts and lists, bucket
+ * sizes -- then the sum over each layer's probed buckets -- and count-model
+ * training) uses the mode.  Changing it drops captured graphs and the count
+ * model, which was fitted to the other candidate sets.  Needs
+ * L * (2k + 1) <= 1024 lists per query (QW_EUNSUPPORTED otherwise); QW_EINVAL
+ * for another mode.  Not to be called while work on the index is in flight.
+ */
+qw_status qw_set_probing(qw_index *ix, int32_t mode);
 
 #ifdef __cplusplus
 }

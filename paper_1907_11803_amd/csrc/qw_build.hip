@@ -246,6 +246,9 @@ qw_status build_index(const void *data, int64_t n, int32_t d, int32_t dtype, con
     ix->dp = (int32_t)((d + 15) / 16 * 16);
     ix->dtype = dtype;
     ix->L = L;
+    ix->nprobe = 1;
+    ix->nl = L;
+    ix->pmagic = 0;
     ix->k = k;
     ix->nf = L * k;
     // one extra 64-row tile: function tiles may start at any f0 during the build

@@ -59,7 +59,7 @@ Plan make_plan(qw_index *ix, int K)
     const int rbytes = ix->dp * (ix->dtype == QW_U8 ? 1 : 4);
     int c = kCmin;
     while (c + 1 < 30 && (int)(c + 1 - kCmin) < kMaxClasses - 1 &&
-           dedup_lds_bytes(c + 1, 0, ix->L, rbytes) <= ix->lds_max)
+           dedup_lds_bytes(c + 1, 0, ix->nl, rbytes) <= ix->lds_max)
         ++c;
     p.cmax = c;
     p.ncls = (p.cmax - kCmin + 1) + 1;
@@ -67,12 +67,12 @@ Plan make_plan(qw_index *ix, int K)
     // registers bound it first): smaller sets save nothing
     p.cfloor = kCmin;
     {
-        const int nb0 = dedup_blocks_per_cu(dedup_lds_bytes(kCmin, 0, ix->L, rbytes), ix->dtype);
+        const int nb0 = dedup_blocks_per_cu(dedup_lds_bytes(kCmin, 0, ix->nl, rbytes), ix->dtype);
         while (p.cfloor < p.cmax &&
-               dedup_blocks_per_cu(dedup_lds_bytes(p.cfloor + 1, 0, ix->L, rbytes), ix->dtype) >= nb0)
+               dedup_blocks_per_cu(dedup_lds_bytes(p.cfloor + 1, 0, ix->nl, rbytes), ix->dtype) >= nb0)
             ++p.cfloor;
     }
-    const uint64_t bound = std::min<uint64_t>((uint64_t)ix->L * (uint64_t)std::max<int64_t>(1, ix->max_bucket),
+    const uint64_t bound = std::min<uint64_t>((uint64_t)ix->nl * (uint64_t)std::max<int64_t>(1, ix->max_bucket),
                                               (uint64_t)ix->n);
     p.cap_g = p.cmax + 1;
     while ((3ull << p.cap_g) < 4 * bound) ++p.cap_g;  // load factor <= 3/4
@@ -80,7 +80,7 @@ Plan make_plan(qw_index *ix, int K)
     const double budget = 2.0 * 1024 * 1024 * 1024;
     p.grid_g = (int)std::max(1.0, std::min((double)ix->cus, std::floor(budget / per_wg)));
     for (int i = 0; i + 1 < p.ncls; ++i)
-        p.dgrid[i] = dedup_blocks_per_cu(dedup_lds_bytes(kCmin + i, 0, ix->L, rbytes), ix->dtype) * ix->cus;
+        p.dgrid[i] = dedup_blocks_per_cu(dedup_lds_bytes(kCmin + i, 0, ix->nl, rbytes), ix->dtype) * ix->cus;
     p.dgrid[p.ncls - 1] = p.grid_g;
     // select list: a few K keys in the usual case; K <= 1024 keeps LC <= 4096
     // (32 KiB of keys, 64 KiB with the FP64 re-rank of float data)
@@ -106,7 +106,8 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan, bool keys = false
 {
     Workspace &w = ix->ws;
     auto ptrs = [&w]() {
-        return std::vector<void *>{w.qpad.p, w.h.p, w.bstart.p, w.bsize.p, w.bmh.p, w.pred.p,
+        return std::vector<void *>{w.qpad.p, w.h.p, w.bstart.p, w.bsize.p, w.bmh.p, w.lsum.p,
+                                   w.lmh.p, w.pred.p,
                                    w.feats.p, w.keys.p, w.keys2.p, w.vals.p, w.vals2.p,
                                    w.binoff.p, w.counters.p, w.ovf.p, w.gscratch.p, w.mlpout.p,
                                    w.order.p,
@@ -118,9 +119,13 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan, bool keys = false
     const int64_t q = std::max<int64_t>(Q, 1);
     QW_TRY(w.qpad.ensure(elem * (size_t)q * ix->dp));
     QW_TRY(w.h.ensure(sizeof(int32_t) * (size_t)q * ix->nf));
-    QW_TRY(w.bstart.ensure(sizeof(uint32_t) * (size_t)q * ix->L));
-    QW_TRY(w.bsize.ensure(sizeof(uint32_t) * (size_t)q * ix->L));
-    QW_TRY(w.bmh.ensure(sizeof(uint32_t) * (size_t)q * ix->L));
+    QW_TRY(w.bstart.ensure(sizeof(uint32_t) * (size_t)q * ix->nl));
+    QW_TRY(w.bsize.ensure(sizeof(uint32_t) * (size_t)q * ix->nl));
+    QW_TRY(w.bmh.ensure(sizeof(uint32_t) * (size_t)q * ix->nl));
+    if (ix->nprobe > 1) {
+        QW_TRY(w.lsum.ensure(sizeof(uint32_t) * (size_t)q * ix->L));
+        QW_TRY(w.lmh.ensure(sizeof(uint32_t) * (size_t)q * ix->L));
+    }
     QW_TRY(w.pred.ensure(sizeof(int32_t) * q));
     QW_TRY(w.feats.ensure(sizeof(float) * (size_t)q * ix->L));
     QW_TRY(w.mlpout.ensure(sizeof(float) * q));
@@ -159,7 +164,8 @@ VerifyArgs base_args(qw_index *ix, int K, int mode)
     a.bsize = ix->ws.bsize.as<uint32_t>();
     a.ids = ix->ids.as<int32_t>();
     a.n = ix->n;
-    a.L = ix->L;
+    a.nl = ix->nl;
+    a.pmagic = ix->pmagic;
     a.d = ix->d;
     a.dp = ix->dp;
     a.dtype = ix->dtype;
@@ -187,9 +193,21 @@ qw_status stage_query_rows(qw_index *ix, const void *x, int64_t m, hipStream_t s
     return QW_OK;
 }
 
+// Per (query, layer) bucket sizes and min-hashes, as the schedule and the
+// count model read them: the lists themselves without neighbour probing, the
+// sums (smallest min-hash) over each layer's lists with it.
+const uint32_t *layer_sizes(qw_index *ix)
+{
+    return ix->nprobe > 1 ? ix->ws.lsum.as<uint32_t>() : ix->ws.bsize.as<uint32_t>();
+}
+const uint32_t *layer_mh(qw_index *ix)
+{
+    return ix->nprobe > 1 ? ix->ws.lmh.as<uint32_t>() : ix->ws.bmh.as<uint32_t>();
+}
+
 // stage rows -> hash -> probe for Q queries (counters must already be cleared);
-// feats (nullable) receives the count-model inputs log(1 + s_{q,l}), bmh
-// (nullable) the buckets' min-hashes
+// feats (nullable) receives the count-model inputs log(1 + s_{q,l}) (s: the
+// layer's size), bmh (nullable) the buckets' min-hashes
 qw_status front(qw_index *ix, const void *queries, int64_t Q, int form, hipStream_t s,
                 hipEvent_t *ev = nullptr, float *feats = nullptr, uint32_t *bmh = nullptr)
 {
@@ -198,7 +216,11 @@ qw_status front(qw_index *ix, const void *queries, int64_t Q, int form, hipStrea
                        c64(ix) + C_RECOMP, s));
     if (ev) QW_HIP(hipEventRecord(ev[1], s));
     QW_TRY(launch_probe(ix, ix->ws.h.as<int32_t>(), Q, ix->ws.bstart.as<uint32_t>(),
-                        ix->ws.bsize.as<uint32_t>(), feats, bmh, s));
+                        ix->ws.bsize.as<uint32_t>(), ix->nprobe == 1 ? feats : nullptr, bmh, s));
+    if (ix->nprobe > 1)
+        QW_TRY(launch_layer_sums(ix->ws.bsize.as<uint32_t>(), bmh, Q, ix->L, ix->nprobe,
+                                 ix->ws.lsum.as<uint32_t>(), bmh ? ix->ws.lmh.as<uint32_t>() : nullptr,
+                                 feats, s));
     return QW_OK;
 }
 
@@ -216,7 +238,7 @@ qw_status verify_simple(qw_index *ix, int64_t Q, int K, int mode, hipStream_t s,
 {
     uint32_t *mx = c32(ix) + W_MAX;
     QW_TRY(launch_fill_u32(mx, 0u, 1, s));
-    QW_TRY(launch_max_bucket_sum(ix->ws.bsize.as<uint32_t>(), Q, ix->L, mx, s));
+    QW_TRY(launch_max_bucket_sum(layer_sizes(ix), Q, ix->L, mx, s));
     uint32_t maxsum = 0;
     QW_HIP(hipMemcpyAsync(&maxsum, mx, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     QW_HIP(hipStreamSynchronize(s));
@@ -232,7 +254,7 @@ qw_status verify_simple(qw_index *ix, int64_t Q, int K, int mode, hipStream_t s,
     a.out_dist = out_dist;
     a.out_counts = out_counts;
     a.offsets = offsets;
-    if (verify_lds_bytes(cap, buf, 0, ix->L, ix->dp, ix->dtype) <= ix->lds_max) {
+    if (verify_lds_bytes(cap, buf, 0, ix->nl, ix->dp, ix->dtype) <= ix->lds_max) {
         a.cap_log2 = (uint32_t)cap;
         a.limit = (1u << cap) / 4 * 3;
         return launch_verify(a, (int)Q, s);
@@ -286,7 +308,7 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     auto schedule = [&](const int32_t *ex, const float *pl, int force_max,
                         const int32_t **order) -> qw_status {
         if (!o.group) {  // classes only: one binning kernel (with the count model)
-            QW_TRY(launch_classify_bin(Q, ix->L, ix->n, w.bsize.as<uint32_t>(), ex,
+            QW_TRY(launch_classify_bin(Q, ix->L, ix->n, layer_sizes(ix), ex,
                                        learned && !ex ? ix->mlp_lane.as<uint32_t>() : nullptr,
                                        ix->mlp_margin, force_max, kCmin, plan.cfloor, plan.cmax,
                                        plan.ncls, w.order.as<int32_t>(), ccount,
@@ -294,8 +316,8 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
             *order = w.order.as<int32_t>();
             return QW_OK;
         }
-        QW_TRY(launch_classify(Q, ix->L, ix->n, w.bmh.as<uint32_t>(),
-                               w.bsize.as<uint32_t>(), ex, pl, ix->mlp_margin, force_max, kCmin,
+        QW_TRY(launch_classify(Q, ix->L, ix->n, layer_mh(ix),
+                               layer_sizes(ix), ex, pl, ix->mlp_margin, force_max, kCmin,
                                plan.cfloor, plan.cmax, plan.ncls, o.group, w.keys.as<unsigned long long>(),
                                w.vals.as<int32_t>(), ccount, s));
         bool alt = false;
@@ -337,7 +359,8 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
             a.bsize = w.bsize.as<uint32_t>();
             a.ids = ix->ids.as<int32_t>();
             a.n = ix->n;
-            a.L = ix->L;
+            a.nl = ix->nl;
+            a.pmagic = ix->pmagic;
             a.count_only = count_only;
             a.alloc = c64(ix) + C_ALLOC;
             a.fail = c64(ix) + C_FAIL;
@@ -457,7 +480,7 @@ qw_status fill_stats(qw_index *ix, int64_t Q, hipStream_t s, qw_stats *st, hipEv
 {
     std::memset(st, 0, sizeof(*st));
     if (Q <= 0) return QW_OK;
-    QW_TRY(launch_probe_stats(ix->ws.bsize.as<uint32_t>(), Q * ix->L, c64(ix) + C_PROBEHIT,
+    QW_TRY(launch_probe_stats(ix->ws.bsize.as<uint32_t>(), Q * ix->nl, c64(ix) + C_PROBEHIT,
                               c64(ix) + C_CANDTOT, s));
     // |C(q)| of every query, written by whichever kernel answered it
     QW_TRY(launch_probe_stats(ix->ws.ucount.as<uint32_t>(), Q, c64(ix) + C_SPARE,
@@ -596,6 +619,7 @@ qw_status qw_get_index_info(const qw_index *ix, qw_index_info *info)
     for (const DevBuf *b : bufs) info->device_bytes += (int64_t)b->bytes;
     info->has_count_model = ix->mlp.empty() ? 0 : 1;
     info->count_margin = ix->mlp_margin;
+    info->probing = ix->nprobe > 1 ? 1 : 0;
     return QW_OK;
 }
 
@@ -725,7 +749,7 @@ qw_status qw_bucket_sizes(qw_index *ix, const void *queries, int64_t Q, void *st
     QW_TRY(ensure_ws(ix, Q, nullptr));
     QW_TRY(clear_counters(ix, s));
     QW_TRY(front(ix, queries, Q, QW_FORM_FAST, s));
-    QW_HIP(hipMemcpyAsync(out_sizes, ix->ws.bsize.p, sizeof(int32_t) * Q * ix->L,
+    QW_HIP(hipMemcpyAsync(out_sizes, layer_sizes(ix), sizeof(int32_t) * Q * ix->L,
                           hipMemcpyDeviceToDevice, s));
     return QW_OK;
 }
@@ -770,7 +794,8 @@ qw_status qw_bruteforce_knn(qw_index *ix, const void *queries, int64_t Q, int32_
     QW_TRY(ensure_ws(ix, Q, nullptr));
     QW_TRY(stage_query_rows(ix, queries, Q, s));
     VerifyArgs a = base_args(ix, K, VM_ALL);
-    a.L = 0;
+    a.nl = 0;  // no bucket lists: every point
+    a.pmagic = 0;
     a.nitems = Q;
     a.cap_log2 = 1;
     a.limit = 1;
@@ -835,6 +860,28 @@ qw_status qw_set_count_margin(qw_index *ix, float margin)
     return QW_OK;
 }
 
+qw_status qw_set_probing(qw_index *ix, int32_t mode)
+{
+    QW_TRY(check_index(ix));
+    if (mode != 0 && mode != 1) return QW_EINVAL;
+    const int32_t P = mode ? 2 * ix->k + 1 : 1;
+    if ((int64_t)ix->L * P > kMaxLists) return QW_EUNSUPPORTED;
+    uint32_t magic = 0;
+    if (P > 1) {  // layer of list i: (i * magic) >> 20, checked over every list index
+        magic = ((1u << 20) + (uint32_t)P - 1) / (uint32_t)P;
+        for (int i = 0; i < kMaxLists; ++i)
+            if ((int)(((uint32_t)i * magic) >> 20) != i / P) return QW_EINTERNAL;
+    }
+    if (P == ix->nprobe) return QW_OK;
+    drop_graphs(ix);
+    ix->plans.clear();
+    ix->nprobe = P;
+    ix->nl = ix->L * P;
+    ix->pmagic = magic;
+    ix->mlp.clear();
+    return QW_OK;
+}
+
 qw_status qw_get_count_model(const qw_index *ix, float *params, int32_t P)
 {
     if (!ix || !params || ix->mlp.empty() || P != (int32_t)ix->mlp.size()) return QW_EINVAL;
@@ -871,7 +918,7 @@ qw_status qw_train_count_model(qw_index *ix, const void *train_queries, int64_t 
         QW_TRY(vel.ensure(sizeof(float) * P));
         const int64_t steps_per_epoch = (m + B - 1) / B;
         QW_TRY(loss.ensure(sizeof(float) * steps_per_epoch));
-        QW_TRY(launch_mlp_features(ix->ws.bsize.as<uint32_t>(), m, L, feats.as<float>(), s));
+        QW_TRY(launch_mlp_features(layer_sizes(ix), m, L, feats.as<float>(), s));
         QW_TRY(launch_labels(ix->ws.pred.as<int32_t>(), m, labels.as<float>(), s));
         std::vector<float> hl(m);
         QW_HIP(hipMemcpyAsync(hl.data(), labels.p, sizeof(float) * m, hipMemcpyDeviceToHost, s));

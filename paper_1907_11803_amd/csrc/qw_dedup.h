@@ -94,6 +94,15 @@ __device__ inline uint32_t insert_streams(uint32_t *tab, int cap_log2, const uin
     return newm;
 }
 
+// A query's bucket lists: list i of layer layer_of(i).  Without neighbour
+// probing every layer has one list (layer = i); with it, each layer has P
+// consecutive lists and layer = (i * pmagic) >> 20 with pmagic = ceil(2^20 / P),
+// exact for i < kMaxLists.
+__device__ inline int layer_of(int i, uint32_t pmagic)
+{
+    return pmagic ? (int)(((uint32_t)i * pmagic) >> 20) : i;
+}
+
 // Wave 0 only: lpref[1..L] holds the L list sizes; turns lpref[0..L] into
 // their exclusive prefix and returns the total (L <= 64).
 __device__ inline uint32_t wave_layer_prefix(uint32_t *lpref, int L)
@@ -109,15 +118,54 @@ __device__ inline uint32_t wave_layer_prefix(uint32_t *lpref, int L)
     return (uint32_t)__shfl((int)v, 63);
 }
 
+// Whole workgroup: lpref[1..nl] holds the nl list sizes (nl <= 4 * kBlock);
+// turns lpref[0..nl] into their exclusive prefix and returns the total in
+// every thread.  tmp: kBlock / 64 words of LDS.  Barriers inside.
+__device__ inline uint32_t block_list_prefix(uint32_t *lpref, int nl, uint32_t *tmp)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t v[4], s = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int e = 4 * tid + i;
+        v[i] = e < nl ? lpref[e + 1] : 0u;
+        s += v[i];
+    }
+    uint32_t incl = s;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_up((int)incl, off);
+        if (lane >= off) incl += t;
+    }
+    __syncthreads();  // every thread has read its sizes
+    if (lane == 63) tmp[wave] = incl;
+    __syncthreads();
+    uint32_t run = incl - s, total = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+        run += w < wave ? tmp[w] : 0u;
+        total += tmp[w];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int e = 4 * tid + i;
+        run += v[i];
+        if (e < nl) lpref[e + 1] = run;
+    }
+    if (tid == 0) lpref[0] = 0;
+    __syncthreads();
+    return total;
+}
+
 // Loads positions base + r * kBlock + threadIdx.x (r < R) of the concatenated
-// layer lists (layer l holds positions [lpref[l], lpref[l+1]) and starts at
-// ids[l*n + lstart[l]]) into id[r]; returns the mask of positions below T.
-// The layers are found by one interleaved binary search (L <= 64: six steps),
-// so all R searches and then all R loads are in flight together.
-template <int R>
-__device__ inline uint32_t load_ids(const int32_t *__restrict__ ids, int64_t n, int32_t L,
-                                    const uint32_t *lpref, const uint32_t *lstart, uint32_t T,
-                                    uint32_t base, uint32_t (&id)[R])
+// bucket lists (list i holds positions [lpref[i], lpref[i+1]) and starts at
+// ids[layer_of(i) * n + lstart[i]]) into id[r]; returns the mask of positions
+// below T.  The lists are found by one interleaved binary search (TOP = the
+// largest power of two below the list count: 32 for at most 64 lists), so all
+// R searches and then all R loads are in flight together.
+template <int R, int TOP = 32>
+__device__ inline uint32_t load_ids(const int32_t *__restrict__ ids, int64_t n, int32_t nl,
+                                    uint32_t pmagic, const uint32_t *lpref,
+                                    const uint32_t *lstart, uint32_t T, uint32_t base,
+                                    uint32_t (&id)[R])
 {
     uint32_t pos[R];
     int lo[R];
@@ -127,13 +175,13 @@ __device__ inline uint32_t load_ids(const int32_t *__restrict__ ids, int64_t n, 
         lo[r] = 0;
     }
 #pragma unroll
-    for (int step = 32; step > 0; step >>= 1)
+    for (int step = TOP; step > 0; step >>= 1)
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            // largest l < L with lpref[l] <= pos; lpref[L] = T > pos stops the
+            // largest i < nl with lpref[i] <= pos; lpref[nl] = T > pos stops the
             // search at the end without a branch around the read
             const int m = lo[r] + step;
-            const uint32_t v = lpref[m < L ? m : L];
+            const uint32_t v = lpref[m < nl ? m : nl];
             lo[r] = v <= pos[r] ? m : lo[r];
         }
     uint32_t valid = 0;
@@ -141,8 +189,8 @@ __device__ inline uint32_t load_ids(const int32_t *__restrict__ ids, int64_t n, 
     for (int r = 0; r < R; ++r) {
         id[r] = 0;
         if (pos[r] < T) {
-            const int l = lo[r];
-            id[r] = (uint32_t)ids[(int64_t)l * n + lstart[l] + (pos[r] - lpref[l])];
+            const int i = lo[r];
+            id[r] = (uint32_t)ids[(int64_t)layer_of(i, pmagic) * n + lstart[i] + (pos[r] - lpref[i])];
             valid |= 1u << r;
         }
     }
@@ -150,15 +198,16 @@ __device__ inline uint32_t load_ids(const int32_t *__restrict__ ids, int64_t n, 
 }
 
 // Whole workgroup (kBlock threads).  Inserts the T ids of the concatenated
-// layer lists (layer l holds positions [lpref[l], lpref[l+1]) and starts at
-// ids[l*n + lstart[l]]) into the cleared set `tab` of 2^cap_log2 slots.  The
+// bucket lists (as load_ids reads them) into the cleared set `tab` of
+// 2^cap_log2 slots.  The
 // unique count goes to *ucount; *ovf is set when it exceeds `limit` or the
 // set fills.  Without overflow and with `compact`, the set is then compacted in
 // place: tab[0..U) holds the unique ids (unspecified order).  *ucount, *ovf
 // and *cpos must be 0 and visible to all threads on entry; returns after a
 // barrier.
-__device__ __attribute__((always_inline)) inline void set_union(const int32_t *__restrict__ ids, int64_t n, int32_t L,
-                                 const uint32_t *lpref, const uint32_t *lstart, uint32_t T,
+template <int TOP = 32>
+__device__ __attribute__((always_inline)) inline void set_union(const int32_t *__restrict__ ids, int64_t n, int32_t nl,
+                                 uint32_t pmagic, const uint32_t *lpref, const uint32_t *lstart, uint32_t T,
                                  uint32_t *tab, int cap_log2, uint32_t limit, bool glob,
                                  uint32_t max_probe, bool compact, uint32_t *ucount,
                                  uint32_t *ovf, uint32_t *cpos)
@@ -168,7 +217,7 @@ __device__ __attribute__((always_inline)) inline void set_union(const int32_t *_
     const unsigned long long lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     // the next round's ids load while this round's are inserted
     uint32_t idn[R];
-    uint32_t pn = load_ids<R>(ids, n, L, lpref, lstart, T, 0u, idn);
+    uint32_t pn = load_ids<R, TOP>(ids, n, nl, pmagic, lpref, lstart, T, 0u, idn);
     for (uint32_t base = 0; base < T; base += R * kBlock) {
         // every thread reads the flag before any thread of this pass can set
         // it, so the early exit is uniform
@@ -179,7 +228,7 @@ __device__ __attribute__((always_inline)) inline void set_union(const int32_t *_
 #pragma unroll
         for (int r = 0; r < R; ++r) idr[r] = idn[r];
         const uint32_t pend = pn;
-        if (base + R * kBlock < T) pn = load_ids<R>(ids, n, L, lpref, lstart, T, base + R * kBlock, idn);
+        if (base + R * kBlock < T) pn = load_ids<R, TOP>(ids, n, nl, pmagic, lpref, lstart, T, base + R * kBlock, idn);
         bool full = false;
         uint32_t nnew = (uint32_t)__popc(insert_streams<R, 4>(tab, cap_log2, idr, pend, max_probe, full));
         // one LDS atomic per wave for the unique count

@@ -23,11 +23,11 @@ constexpr int kRegIds = 16;  // ids per thread of the register-resident path
 
 __host__ __device__ inline size_t a16(size_t v) { return (v + 15) & ~size_t(15); }
 
-// set | layer prefix | layer starts | scalars | query row
-size_t dedup_lds_bytes(int cap_log2, int global_tab, int L, int row_bytes)
+// set | list prefix | list starts | scalars | query row
+size_t dedup_lds_bytes(int cap_log2, int global_tab, int nl, int row_bytes)
 {
-    return (global_tab ? 0 : (size_t(4) << cap_log2)) + a16(size_t(L + 1) * 4) +
-           a16(size_t(L) * 4) + a16(D_NSCAL * 4) + a16((size_t)row_bytes);
+    return (global_tab ? 0 : (size_t(4) << cap_log2)) + a16(size_t(nl + 1) * 4) +
+           a16(size_t(nl) * 4) + a16(D_NSCAL * 4) + a16((size_t)row_bytes);
 }
 
 // Exclusive prefix of the per-wave counts in scal[D_WT..]: the wave's base and
@@ -462,7 +462,10 @@ __device__ inline void fused_topk(const DedupArgs &A, int64_t q, LaneTop t, cons
 // set and read the unique ids back from it.
 // At most 128 registers: four workgroups per CU (the fused top K would
 // otherwise cost one).
-template <bool GLOB, int DT>
+// MP: neighbour probing (more than 64 lists per query): the list ranges load
+// at the start of each query instead of during the previous one, the list
+// prefix takes the whole workgroup and the list search ten steps.
+template <bool GLOB, int DT, bool MP>
 __global__ __launch_bounds__(kBlock, 4) void dedup_kernel(DedupArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -471,9 +474,10 @@ __global__ __launch_bounds__(kBlock, 4) void dedup_kernel(DedupArgs A)
     constexpr bool glob = GLOB;
     const size_t tab_bytes = glob ? 0 : (size_t(4) << A.cap_log2);
     uint32_t *lpref = reinterpret_cast<uint32_t *>(smem + tab_bytes);
-    uint32_t *lstart = reinterpret_cast<uint32_t *>(smem + tab_bytes + a16(size_t(A.L + 1) * 4));
-    uint32_t *scal = reinterpret_cast<uint32_t *>(smem + tab_bytes + a16(size_t(A.L + 1) * 4) +
-                                                  a16(size_t(A.L) * 4));
+    uint32_t *lstart = reinterpret_cast<uint32_t *>(smem + tab_bytes + a16(size_t(A.nl + 1) * 4));
+    uint32_t *scal = reinterpret_cast<uint32_t *>(smem + tab_bytes + a16(size_t(A.nl + 1) * 4) +
+                                                  a16(size_t(A.nl) * 4));
+    constexpr int kTop = MP ? kMaxLists / 2 : 32;  // list search steps: log2(kTop) + 1
     const int row_bytes = A.dp * (DT == QW_U8 ? 1 : 4);
     const int parts = row_bytes / 16;
     uint4 *qrow = reinterpret_cast<uint4 *>(reinterpret_cast<unsigned char *>(scal) + a16(D_NSCAL * 4));
@@ -530,18 +534,23 @@ __global__ __launch_bounds__(kBlock, 4) void dedup_kernel(DedupArgs A)
     if (tid == 0) scal[D_NEXT] = atomicAdd(A.xwork + xcd, 1u);
     __syncthreads();
     int64_t item = item_of(scal[D_NEXT]);
-    uint32_t pf_start = 0, pf_size = 0;  // threads < L: bucket range of the next query
-    if (item < nall && tid < A.L) {
+    uint32_t pf_start = 0, pf_size = 0;  // threads < nl: bucket range of the next query
+    if (!MP && item < nall && tid < A.nl) {
         const int64_t q0 = query_of(item);
-        pf_start = A.bstart[q0 * A.L + tid];
-        pf_size = A.bsize[q0 * A.L + tid];
+        pf_start = A.bstart[q0 * A.nl + tid];
+        pf_size = A.bsize[q0 * A.nl + tid];
     }
 
     while (item < nall) {  // uniform: every thread holds the same item
         uint32_t next = 0;
         if (tid == 0) next = atomicAdd(A.xwork + xcd, 1u);  // published at the end of the iteration
         const int64_t q = query_of(item);
-        if (tid < A.L) {
+        if (MP) {
+            for (int i = tid; i < A.nl; i += kBlock) {
+                lstart[i] = A.bstart[q * A.nl + i];
+                lpref[i + 1] = A.bsize[q * A.nl + i];
+            }
+        } else if (tid < A.nl) {
             lstart[tid] = pf_start;
             lpref[tid + 1] = pf_size;
         }
@@ -553,8 +562,10 @@ __global__ __launch_bounds__(kBlock, 4) void dedup_kernel(DedupArgs A)
             scal[D_CPOS] = 0;
         }
         bar();
+        uint32_t run = 0;
+        if (MP) run = block_list_prefix(lpref, A.nl, &scal[D_WT]);  // every thread
+        else if (tid < 64) run = wave_layer_prefix(lpref, A.nl);
         if (tid < 64) {
-            const uint32_t run = wave_layer_prefix(lpref, A.L);
             if (tid == 0) {
                 scal[D_T] = run;
                 int c = glob ? (int)A.cap_log2 : class_cap(item);
@@ -577,7 +588,7 @@ __global__ __launch_bounds__(kBlock, 4) void dedup_kernel(DedupArgs A)
         uint32_t idr[kRegIds];
         uint32_t pend = 0;
         if (in_regs)  // the id loads fly while the set is cleared
-            pend = load_ids<kRegIds>(A.ids, A.n, A.L, lpref, lstart, T, 0u, idr);
+            pend = load_ids<kRegIds, kTop>(A.ids, A.n, A.nl, A.pmagic, lpref, lstart, T, 0u, idr);
         for (uint32_t i = 4 * tid; i < cap; i += 4 * kBlock)  // cap >= 1024: whole 16-byte stores
             *reinterpret_cast<uint4 *>(tab + i) = uint4{kEmpty, kEmpty, kEmpty, kEmpty};
         if (glob) __threadfence();
@@ -603,7 +614,7 @@ __global__ __launch_bounds__(kBlock, 4) void dedup_kernel(DedupArgs A)
             U = tot;
             ovf = scal[D_OVF] != 0 || U > limit;
         } else {
-            set_union(A.ids, A.n, A.L, lpref, lstart, T, tab, cap_log2, limit, glob, max_probe,
+            set_union<kTop>(A.ids, A.n, A.nl, A.pmagic, lpref, lstart, T, tab, cap_log2, limit, glob, max_probe,
                       true, &scal[D_UCOUNT], &scal[D_OVF], &scal[D_CPOS]);
             U = scal[D_UCOUNT];
             ovf = scal[D_OVF] != 0 || U > limit;
@@ -642,10 +653,10 @@ __global__ __launch_bounds__(kBlock, 4) void dedup_kernel(DedupArgs A)
         bar();
         const unsigned long long off = *soff;
         item = item_of(scal[D_NEXT]);
-        if (item < nall && tid < A.L) {  // the next query's bucket ranges fly during the writes
+        if (!MP && item < nall && tid < A.nl) {  // the next query's bucket ranges fly during the writes
             const int64_t qn = query_of(item);
-            pf_start = A.bstart[qn * A.L + tid];
-            pf_size = A.bsize[qn * A.L + tid];
+            pf_start = A.bstart[qn * A.nl + tid];
+            pf_size = A.bsize[qn * A.nl + tid];
         }
         if (off != ~0ull) {
             // the unique ids into tab[0..U) (the set path compacted already)
@@ -680,14 +691,26 @@ qw_status launch_dedup(const DedupArgs &a, int grid, hipStream_t s)
     if (a.topk && (a.dtype != QW_U8 || a.dp > 64 * 16 || a.topk > kFusedTopK || a.topk < 0 ||
                    a.topk_keep < 1 || a.topk_keep > kTopR))
         return QW_EINVAL;
-    const size_t lds = dedup_lds_bytes((int)a.cap_log2, a.global_tab, a.L,
+    if (a.nl < 1 || a.nl > kMaxLists || (a.nl > 64 && !a.pmagic)) return QW_EINVAL;
+    const size_t lds = dedup_lds_bytes((int)a.cap_log2, a.global_tab, a.nl,
                                        a.dp * (a.dtype == QW_U8 ? 1 : 4));
+    const bool mp = a.pmagic != 0;
     if (a.dtype == QW_U8) {
-        if (a.global_tab) dedup_kernel<true, QW_U8><<<grid, kBlock, lds, s>>>(a);
-        else dedup_kernel<false, QW_U8><<<grid, kBlock, lds, s>>>(a);
+        if (mp) {
+            if (a.global_tab) dedup_kernel<true, QW_U8, true><<<grid, kBlock, lds, s>>>(a);
+            else dedup_kernel<false, QW_U8, true><<<grid, kBlock, lds, s>>>(a);
+        } else {
+            if (a.global_tab) dedup_kernel<true, QW_U8, false><<<grid, kBlock, lds, s>>>(a);
+            else dedup_kernel<false, QW_U8, false><<<grid, kBlock, lds, s>>>(a);
+        }
     } else {
-        if (a.global_tab) dedup_kernel<true, QW_F32><<<grid, kBlock, lds, s>>>(a);
-        else dedup_kernel<false, QW_F32><<<grid, kBlock, lds, s>>>(a);
+        if (mp) {
+            if (a.global_tab) dedup_kernel<true, QW_F32, true><<<grid, kBlock, lds, s>>>(a);
+            else dedup_kernel<false, QW_F32, true><<<grid, kBlock, lds, s>>>(a);
+        } else {
+            if (a.global_tab) dedup_kernel<true, QW_F32, false><<<grid, kBlock, lds, s>>>(a);
+            else dedup_kernel<false, QW_F32, false><<<grid, kBlock, lds, s>>>(a);
+        }
     }
     QW_HIP(hipGetLastError());
     return QW_OK;
@@ -696,8 +719,8 @@ qw_status launch_dedup(const DedupArgs &a, int grid, hipStream_t s)
 int dedup_blocks_per_cu(size_t lds, int dtype)
 {
     int nb = 0;
-    const void *fn = dtype == QW_U8 ? (const void *)dedup_kernel<false, QW_U8>
-                                    : (const void *)dedup_kernel<false, QW_F32>;
+    const void *fn = dtype == QW_U8 ? (const void *)dedup_kernel<false, QW_U8, false>
+                                    : (const void *)dedup_kernel<false, QW_F32, false>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, lds) != hipSuccess) {
         (void)hipGetLastError();
         nb = 1;

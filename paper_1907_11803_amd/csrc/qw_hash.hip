@@ -511,13 +511,17 @@ qw_status launch_hash(const qw_index *ix, const void *xpad, int64_t m, int32_t f
 }
 
 // ---------------------------------------------------------------- probe
-// One thread per (query, layer): pack the layer's k hash values into the exact
-// key (values outside the data's range cannot match any bucket: a miss; the
-// key of such a layer is never looked up), then look the key up in the
-// layer's open-addressing table.  bmh (nullable) receives the bucket's
-// min-hash (0xFFFFFFFF on a miss).
+// One thread per (query, layer, probe): probe 0 is the query's own bucket;
+// with neighbour probing (P = 2k + 1) probe 1 + 2j + s moves hash value j by
+// -1 (s = 0) or +1 (s = 1), the buckets next to the query's in one coordinate
+// (the multi-probe variant summarised in Section 2).  The k values are packed
+// into the exact key (values outside the data's range cannot match any
+// bucket: a miss; such a key is never looked up), then the key is looked up
+// in the layer's open-addressing table.  Outputs are [Q][L][P]; bmh
+// (nullable) receives the bucket's min-hash (0xFFFFFFFF on a miss); feats
+// (nullable, P = 1 only) the count-model input log(1 + size).
 __global__ __launch_bounds__(kBlock) void probe_kernel(
-    const int32_t *__restrict__ h, int64_t Q, int32_t L, int32_t k,
+    const int32_t *__restrict__ h, int64_t Q, int32_t L, int32_t k, int32_t P,
     const int32_t *__restrict__ hmin, const int32_t *__restrict__ hmax,
     const int32_t *__restrict__ shift, const TabEntry *__restrict__ tab,
     const long long *__restrict__ tab_off, const uint32_t *__restrict__ tab_mask,
@@ -534,9 +538,11 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(
         fconst[2 * nf + f] = shift[f];
     }
     const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool live = idx < Q * L;
-    const int64_t q = live ? idx / L : 0;
-    const int32_t l = live ? (int32_t)(idx - q * L) : 0;
+    const bool live = idx < Q * L * P;
+    const int64_t ql = live ? idx / P : 0;
+    const int32_t p = live ? (int32_t)(idx - ql * P) : 0;
+    const int64_t q = ql / L;
+    const int32_t l = (int32_t)(ql - q * L);
     // the layer's k hash values, all loads issued before any is used
     int32_t hv[kMaxK];
 #pragma unroll
@@ -544,8 +550,17 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(
         if (j < k) hv[j] = h[q * nf + l * k + j];
     __syncthreads();
     if (!live) return;
-    uint64_t klo = 0, khi = 0;
     bool valid = true;
+    if (p > 0) {  // neighbour probe: one value moved by one (a move past the int32 range: a miss)
+        const int32_t jp = (p - 1) >> 1, dlt = (p - 1) & 1 ? 1 : -1;
+#pragma unroll
+        for (int32_t j = 0; j < kMaxK; ++j)
+            if (j == jp) {
+                valid = dlt > 0 ? hv[j] != INT32_MAX : hv[j] != INT32_MIN;
+                hv[j] += valid ? dlt : 0;
+            }
+    }
+    uint64_t klo = 0, khi = 0;
 #pragma unroll
     for (int32_t j = 0; j < kMaxK; ++j)
         if (j < k) {
@@ -592,10 +607,11 @@ qw_status launch_probe(const qw_index *ix, const int32_t *h, int64_t Q, uint32_t
                        uint32_t *bsize, float *feats, uint32_t *bmh, hipStream_t s)
 {
     if (Q <= 0) return QW_OK;
-    const int64_t total = Q * ix->L;
+    if (feats && ix->nprobe != 1) return QW_EINTERNAL;  // features of probed layers: layer sums
+    const int64_t total = Q * ix->nl;
     const size_t lds = sizeof(int32_t) * 3 * (size_t)ix->nf;  // nf <= 64 * kMaxK: 24 KiB at most
     probe_kernel<<<(unsigned)ceil_div(total, kBlock), kBlock, lds, s>>>(
-        h, Q, ix->L, ix->k, ix->hmin.as<int32_t>(), ix->hmax.as<int32_t>(),
+        h, Q, ix->L, ix->k, ix->nprobe, ix->hmin.as<int32_t>(), ix->hmax.as<int32_t>(),
         ix->shift.as<int32_t>(), ix->tab.as<TabEntry>(), ix->tab_off.as<long long>(),
         ix->tab_mask.as<uint32_t>(), bstart, bsize, feats, bmh);
     QW_HIP(hipGetLastError());

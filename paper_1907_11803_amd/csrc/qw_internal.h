@@ -21,6 +21,8 @@ constexpr int kBlock = 256;              // threads per workgroup for every kern
 constexpr int kRecompSlots = 32;
 // Largest K the fused dedup kernel selects itself (uint8 data).
 constexpr int kFusedTopK = 16;
+// Bucket lists per query at most (neighbour probing: L * (2k + 1)).
+constexpr int kMaxLists = 1024;
 // With bucket grouping the dedup kernel deals its items to the XCDs in chunks
 // of this many consecutive positions of the order (each XCD then takes at most
 // one chunk more than its share per launch); without, one at a time.
@@ -96,7 +98,7 @@ __host__ __device__ inline uint32_t id_mix(uint32_t x)
 }
 
 struct Workspace {
-    DevBuf qpad, h, bstart, bsize, bmh, pred, feats, keys, keys2, vals, vals2, hist,
+    DevBuf qpad, h, bstart, bsize, bmh, lsum, lmh, pred, feats, keys, keys2, vals, vals2, hist,
         order, binoff, counters, ovf, gscratch, mlpout, scan;
     // flat pipeline
     DevBuf ucount, coff, flag, pkeys, fb;
@@ -135,6 +137,10 @@ struct qw_index {
     size_t lds_max = 65536;
     int64_t n = 0;
     int32_t d = 0, dp = 0, dtype = 0, L = 0, k = 0, nf = 0, nf_pad = 0;
+    // bucket lists per layer (1, or 2k + 1 with neighbour probing), lists per
+    // query (L * nprobe) and the layer-of-list multiplier (0 without probing)
+    int32_t nprobe = 1, nl = 0;
+    uint32_t pmagic = 0;
     float w = 0.f;
     // hash parameters (device)
     qw::DevBuf a32;      // float [nf_pad][dp], zero padded
@@ -230,10 +236,12 @@ struct VerifyArgs {
     int64_t nitems;              // used when seg == nullptr and nitems_dev == nullptr
     const uint32_t *nitems_dev;  // nullable: item count read from device memory
     uint32_t *counter;           // persistent work counter (nullable = one item per workgroup)
-    const uint32_t *bstart, *bsize;
+    const uint32_t *bstart, *bsize;  // [Q][nl] bucket lists (layer-relative starts)
     const int32_t *ids;
     int64_t n;
-    int32_t L, d, dp, dtype, K, mode;
+    int32_t nl;                  // lists per query (L, or L * P with neighbour probing)
+    uint32_t pmagic;             // 0, or ceil(2^20 / P): list i belongs to layer (i * pmagic) >> 20
+    int32_t d, dp, dtype, K, mode;
     const void *data, *queries;
     uint32_t cap_log2;           // hash-set capacity 2^cap_log2
     uint32_t limit;              // abort when more unique ids than this (overflow); <= 3/4 capacity
@@ -279,6 +287,10 @@ qw_status launch_classify_bin(int64_t Q, int32_t L, int64_t n, const uint32_t *b
                               int32_t ncls, int32_t *order, unsigned long long *class_count,
                               uint32_t *done, unsigned long long *seg, hipStream_t s);
 qw_status launch_max_u32(const uint32_t *v, int64_t count, uint32_t *out, hipStream_t s);
+// Neighbour probing: per (query, layer) the sum of its P list sizes, the
+// smallest min-hash (lmh nullable) and log(1 + sum) (feats nullable).
+qw_status launch_layer_sums(const uint32_t *bsize, const uint32_t *bmh, int64_t Q, int32_t L,
+                            int32_t P, uint32_t *lsum, uint32_t *lmh, float *feats, hipStream_t s);
 qw_status launch_max_bucket_sum(const uint32_t *bsize, int64_t Q, int32_t L, uint32_t *out,
                                 hipStream_t s);
 qw_status launch_probe_stats(const uint32_t *bsize, int64_t count, unsigned long long *hits,
@@ -305,10 +317,11 @@ struct DedupArgs {
     const int32_t *in_list;
     uint32_t *ovf_count;             // queue receiving this class's overflows
     int32_t *ovf_list;
-    const uint32_t *bstart, *bsize;
+    const uint32_t *bstart, *bsize;  // [Q][nl] bucket lists (layer-relative starts)
     const int32_t *ids;
     int64_t n;
-    int32_t L;
+    int32_t nl;                      // lists per query (L, or L * P with neighbour probing)
+    uint32_t pmagic;                 // 0, or ceil(2^20 / P): list i belongs to layer (i * pmagic) >> 20
     uint32_t cap_log2, limit;
     int32_t global_tab;
     uint32_t *gscratch;              // 2^cap_log2 words per workgroup (global_tab)

@@ -41,7 +41,8 @@ template <int DT> struct TopT;
 template <> struct TopT<QW_U8> { using type = unsigned long long; };  // (dist << 32) | id
 template <> struct TopT<QW_F32> { using type = TopF; };
 
-enum { S_ITEM = 0, S_UCOUNT, S_OVF, S_BUFCOUNT, S_THR, S_QQ, S_T, S_CAP, S_CPOS, S_NSCAL = 16 };
+enum { S_ITEM = 0, S_UCOUNT, S_OVF, S_BUFCOUNT, S_THR, S_QQ, S_T, S_CAP, S_CPOS, S_TMP = 12,
+       S_NSCAL = 16 };
 
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
 
@@ -49,7 +50,7 @@ struct LdsLayout {
     size_t buf, q, tab, lpref, lstart, scal, total;
 };
 
-__host__ __device__ inline LdsLayout lds_layout(int cap_log2, int buf, int global_tab, int L,
+__host__ __device__ inline LdsLayout lds_layout(int cap_log2, int buf, int global_tab, int nl,
                                                 int dp, int dtype)
 {
     LdsLayout o;
@@ -59,15 +60,15 @@ __host__ __device__ inline LdsLayout lds_layout(int cap_log2, int buf, int globa
     o.q = o.buf + align16(size_t(buf) * esz);
     o.tab = o.q + align16(size_t(dp) * (dtype == QW_U8 ? 1 : 4));
     o.lpref = o.tab + (global_tab ? 0 : cap * 4);
-    o.lstart = o.lpref + align16(size_t(L + 1) * 4);
-    o.scal = o.lstart + align16(size_t(L) * 4);
+    o.lstart = o.lpref + align16(size_t(nl + 1) * 4);
+    o.scal = o.lstart + align16(size_t(nl) * 4);
     o.total = o.scal + S_NSCAL * 4;
     return o;
 }
 
-size_t verify_lds_bytes(int cap_log2, int buf, int global_tab, int L, int dp, int dtype)
+size_t verify_lds_bytes(int cap_log2, int buf, int global_tab, int nl, int dp, int dtype)
 {
-    return lds_layout(cap_log2, buf, global_tab, L, dp, dtype).total;
+    return lds_layout(cap_log2, buf, global_tab, nl, dp, dtype).total;
 }
 
 __device__ inline bool entry_less(unsigned long long a, unsigned long long b) { return a < b; }
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x, lane = tid & 63;
     constexpr int glob = GLOB ? 1 : 0;
-    const LdsLayout lay = lds_layout((int)A.cap_log2, (int)A.buf, glob, A.L, A.dp, A.dtype);
+    const LdsLayout lay = lds_layout((int)A.cap_log2, (int)A.buf, glob, A.nl, A.dp, A.dtype);
     E *buf = reinterpret_cast<E *>(smem + lay.buf);
     uint32_t *lpref = reinterpret_cast<uint32_t *>(smem + lay.lpref);
     uint32_t *lstart = reinterpret_cast<uint32_t *>(smem + lay.lstart);
@@ -204,9 +205,9 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
         }
 
         // ---- per-query setup
-        if (tid < A.L) {
-            lstart[tid] = A.bstart[q * A.L + tid];
-            lpref[tid + 1] = A.bsize[q * A.L + tid];
+        for (int i = tid; i < A.nl; i += kBlock) {
+            lstart[i] = A.bstart[q * A.nl + i];
+            lpref[i + 1] = A.bsize[q * A.nl + i];
         }
         if (tid == 0) {
             lpref[0] = 0;
@@ -235,8 +236,10 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
             __syncthreads();
             if (DT == QW_U8 && qq) atomicAdd(&scal[S_QQ], qq);
         }
+        uint32_t run = 0;
+        if (A.nl > 64) run = block_list_prefix(lpref, A.nl, &scal[S_TMP]);  // uniform
+        else if (tid < 64) run = wave_layer_prefix(lpref, A.nl);
         if (tid < 64) {
-            const uint32_t run = wave_layer_prefix(lpref, A.L);
             if (tid == 0) {
                 scal[S_T] = run;
                 int c = (int)A.cap_log2;
@@ -259,11 +262,18 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
         if (glob) __threadfence();
         __syncthreads();
 
-        // ---- phase 1: de-duplicated union of the L bucket lists
-        if (A.mode != VM_ALL)
-            set_union(A.ids, A.n, A.L, lpref, lstart, T, tab, cap_log2, limit, glob != 0,
-                      A.short_probe ? kShortProbe : 0xFFFFFFFFu, true, &scal[S_UCOUNT], &scal[S_OVF],
-                      &scal[S_CPOS]);
+        // ---- phase 1: de-duplicated union of the bucket lists
+        if (A.mode != VM_ALL) {
+            const uint32_t mprobe = A.short_probe ? kShortProbe : 0xFFFFFFFFu;
+            if (A.nl > 64)  // uniform: neighbour probing, up to kMaxLists lists
+                set_union<kMaxLists / 2>(A.ids, A.n, A.nl, A.pmagic, lpref, lstart, T, tab, cap_log2,
+                                         limit, glob != 0, mprobe, true, &scal[S_UCOUNT],
+                                         &scal[S_OVF], &scal[S_CPOS]);
+            else
+                set_union<32>(A.ids, A.n, A.nl, A.pmagic, lpref, lstart, T, tab, cap_log2, limit,
+                              glob != 0, mprobe, true, &scal[S_UCOUNT], &scal[S_OVF],
+                              &scal[S_CPOS]);
+        }
         const uint32_t U = A.mode == VM_ALL ? (uint32_t)A.n : scal[S_UCOUNT];
         if (A.mode != VM_ALL && (scal[S_OVF] || U > limit)) {
             if (tid == 0) {
@@ -449,7 +459,9 @@ int verify_blocks_per_cu(int dp, int dtype, size_t lds)
 qw_status launch_verify(const VerifyArgs &a, int grid, hipStream_t s)
 {
     if (grid <= 0) return QW_OK;
-    const size_t lds = verify_lds_bytes((int)a.cap_log2, (int)a.buf, a.global_tab, a.L, a.dp,
+    // nl = 0: brute force (no lists)
+    if (a.nl < 0 || a.nl > kMaxLists || (a.nl > 64 && !a.pmagic)) return QW_EINVAL;
+    const size_t lds = verify_lds_bytes((int)a.cap_log2, (int)a.buf, a.global_tab, a.nl, a.dp,
                                         a.dtype);
     const bool small = one_part_per_lane(a.dp, a.dtype);
     const bool g = a.global_tab != 0;

@@ -59,7 +59,8 @@ class qw_index_info(ctypes.Structure):
                 ("L", ctypes.c_int32), ("k", ctypes.c_int32), ("w", ctypes.c_float),
                 ("key_bits", ctypes.c_int32 * 64), ("buckets", ctypes.c_int64),
                 ("max_bucket", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("has_count_model", ctypes.c_int32), ("count_margin", ctypes.c_float)]
+                ("has_count_model", ctypes.c_int32), ("count_margin", ctypes.c_float),
+                ("probing", ctypes.c_int32)]
 
 
 # exported symbols and their signatures (restype qw_status unless noted)
@@ -84,6 +85,7 @@ SIGNATURES = {
     "qw_set_count_model": (ctypes.c_int, [_P, _P, _I32]),
     "qw_get_count_model": (ctypes.c_int, [_P, _P, _I32]),
     "qw_set_count_margin": (ctypes.c_int, [_P, ctypes.c_float]),
+    "qw_set_probing": (ctypes.c_int, [_P, ctypes.c_int32]),
 }
 
 _lib = None
@@ -303,6 +305,10 @@ def qw_set_count_margin(ix, margin: float):
     _check(load().qw_set_count_margin(ix, float(margin)), "qw_set_count_margin")
 
 
+def qw_set_probing(ix, mode: int):
+    _check(load().qw_set_probing(ix, int(mode)), "qw_set_probing")
+
+
 def qw_get_count_model(ix, L: int) -> np.ndarray:
     p = np.empty(qw_mlp_param_count(L), dtype=np.float32)
     _check(load().qw_get_count_model(ix, ctypes.c_void_p(p.ctypes.data), p.size), "qw_get_count_model")
@@ -351,6 +357,9 @@ class Index:
 
     def set_count_margin(self, margin: float):
         qw_set_count_margin(self.handle, margin)
+
+    def set_probing(self, mode: int):
+        qw_set_probing(self.handle, mode)
 
     def info(self) -> dict:
         return qw_get_index_info(self.handle)

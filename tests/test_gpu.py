@@ -118,6 +118,82 @@ def test_candidate_sets_cfg1(cfg1, w):
     assert np.all(sizes.sum(axis=1) >= cnt)
 
 
+# ---------------------------------------------------------------- neighbour probing
+
+@pytest.mark.parametrize("w", [400.0, 900.0])
+def test_neighbour_probing_cfg1(cfg1, w):
+    """Probing the one-step neighbour buckets: candidate sets, counts, layer
+    sums and the top K of both forms and every schedule match the oracle with
+    probes=1; switching back restores the plain results.  L = 10, k = 8: 170
+    lists per query."""
+    p = cfg1.params
+    ix = build(cfg1.data, p.a, p.b(w), w)
+    q = cfg1.queries
+    ix.set_probing(1)
+    assert ix.info()["probing"] == 1
+    got = ix.candidate_lists(dev(q))
+    want = oracle.lsh_candidates(cfg1.data, q, p.a, p.b(w), w, probes=1)
+    plain = oracle.lsh_candidates(cfg1.data, q, p.a, p.b(w), w)
+    assert sum(len(o) for o in want) > sum(len(o) for o in plain)
+    for g, o in zip(got, want):
+        assert np.array_equal(g, o)
+    cnt = ix.candidate_counts(dev(q)).cpu().numpy()
+    assert cnt.tolist() == [len(o) for o in want]
+    sizes = ix.bucket_sizes(dev(q)).cpu().numpy()
+    assert sizes.shape == (q.shape[0], p.L) and np.all(sizes.sum(axis=1) >= cnt)
+    ids_o, dist_o, cnt_o = oracle.lsh_query(cfg1.data, q, p.a, p.b(w), w, cfg1.K, probes=1)
+    for form in FORMS:
+        ids, dist, st = ix.query(dev(q), cfg1.K, lib.make_opts(form=form, sched=lib.QW_SCHED_SUM),
+                                 stats=True)
+        check_topk(ids, dist, ids_o, dist_o, True)
+        assert st["cand_unique"] == int(cnt_o.sum())
+    for sched in SCHEDS:
+        for group in (0, 1):
+            ids, dist = ix.query(dev(q), cfg1.K, lib.make_opts(sched=sched, group=group))
+            check_topk(ids, dist, ids_o, dist_o, True)
+    ix.set_probing(0)
+    ids_o, dist_o, _ = oracle.lsh_query(cfg1.data, q, p.a, p.b(w), w, cfg1.K)
+    ids, dist = ix.query(dev(q), cfg1.K)
+    check_topk(ids, dist, ids_o, dist_o, True)
+
+
+def test_neighbour_probing_float_and_learned():
+    """Float data with probing (L = 16, k = 12: 400 lists per query), both
+    forms, and a count model trained under probing keeps the results."""
+    wl = synth.make_config(3, n=6000, Q=60, ncomp=30, w=4.0)
+    p = wl.params
+    ix = build(wl.data, p.a, p.b(), p.w)
+    ix.set_probing(1)
+    ids_o, dist_o, cnt = oracle.lsh_query(wl.data, wl.queries, p.a, p.b(), p.w, wl.K, probes=1)
+    assert cnt.mean() > 20
+    for form in FORMS:
+        ids, dist = ix.query(dev(wl.queries), wl.K, lib.make_opts(form=form, sched=lib.QW_SCHED_SUM))
+        check_topk(ids, dist, ids_o, dist_o, False)
+    train = synth.training_queries(3, 2000, n=6000, ncomp=30)
+    ix.train_count_model(dev(train), epochs=2, batch=256, lr=2e-3, seed=1)
+    assert ix.info()["has_count_model"] == 1
+    for group in (0, 1):
+        ids, dist = ix.query(dev(wl.queries), wl.K, lib.make_opts(sched=lib.QW_SCHED_LEARNED,
+                                                                   group=group))
+        check_topk(ids, dist, ids_o, dist_o, False)
+    ix.set_probing(0)
+    assert ix.info()["has_count_model"] == 0
+
+
+def test_neighbour_probing_limits():
+    rng = np.random.default_rng(9)
+    data = rng.integers(0, 256, size=(500, 16), dtype=np.uint8)
+    L, k, w = 64, 8, 600.0  # 64 * 17 = 1088 lists: beyond 1024
+    a = rng.standard_normal((L, k, 16)).astype(np.float32)
+    b = (rng.random((L, k)) * w).astype(np.float32)
+    ix = build(data, a, b, w)
+    with pytest.raises(lib.QwError):
+        ix.set_probing(1)
+    with pytest.raises(lib.QwError):
+        ix.set_probing(2)
+    assert ix.info()["probing"] == 0
+
+
 # ---------------------------------------------------------------- top-K, uint8
 
 @pytest.mark.parametrize("w", [400.0, 1200.0])

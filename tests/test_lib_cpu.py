@@ -40,15 +40,15 @@ def test_struct_layout_matches_c(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "qwlsh.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu\\n\", sizeof(qw_opts), sizeof(qw_stats),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(qw_opts), sizeof(qw_stats),"
         " sizeof(qw_index_info), offsetof(qw_stats, ms_stage), offsetof(qw_index_info, buckets),"
-        " offsetof(qw_index_info, has_count_model));return 0;}\n")
+        " offsetof(qw_index_info, has_count_model), offsetof(qw_index_info, probing));return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(lib.qw_opts), ctypes.sizeof(lib.qw_stats), ctypes.sizeof(lib.qw_index_info),
             lib.qw_stats.ms_stage.offset, lib.qw_index_info.buckets.offset,
-            lib.qw_index_info.has_count_model.offset]
+            lib.qw_index_info.has_count_model.offset, lib.qw_index_info.probing.offset]
     assert got == want
 
 
@@ -71,6 +71,7 @@ def test_validation_rejects_before_device_work(so):
     assert so.qw_get_index_info(None, None) == lib.QW_EINVAL
     assert so.qw_set_count_model(None, None, 0) == lib.QW_EINVAL
     assert so.qw_set_count_margin(None, 0.5) == lib.QW_EINVAL
+    assert so.qw_set_probing(None, 1) == lib.QW_EINVAL
     assert so.qw_mlp_loss_grad(None, 4, None, None, 1, None, None, None) == lib.QW_EINVAL
     so.qw_free_index(None)  # no-op
 
