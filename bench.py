@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--w", type=float, default=None, help="bucket width (default: search w_0.9)")
+    ap.add_argument("--probes", type=int, default=0, choices=[0, 1],
+                    help="1: also probe each layer's 2k one-step neighbour buckets")
     ap.add_argument("--train-queries", type=int, default=None,
                     help="count-model training queries (default: the configuration's, else 50,000)")
     ap.add_argument("--recall-sample", type=int, default=2000,
@@ -117,6 +119,8 @@ def main():
         b_d = torch.from_numpy(wl.params.b(w)).to(dev)
         t1 = time.time()
         ix = lib.Index(data_d, a_d, b_d, w, form=lib.QW_FORM_FAST)
+        if args.probes:
+            ix.set_probing(1)
         build_s = time.time() - t1
         if args.profile:  # profiling runs time the query loop only
             chosen = (w, ix, b_d, None, None)
@@ -256,7 +260,8 @@ def main():
     tfile = os.path.join(ROOT, "profiles", f"{kfile}_cfg{args.config}_traffic.json")
     if os.path.exists(tfile):
         tj = json.load(open(tfile))
-        if tj.get("source") == kernel_source_hash(ksrc) and abs(tj.get("w", -1) - w) < 1e-9:
+        if (tj.get("source") == kernel_source_hash(ksrc) and abs(tj.get("w", -1) - w) < 1e-9
+                and tj.get("probes", 0) == args.probes):
             traffic = tj.get("bytes_per_launch")
 
     # ---- CPU oracle on a bounded sample
@@ -271,7 +276,7 @@ def main():
         ns = min(args.cpu_sample if args.cpu_sample > 0 else (10_000 if is_u8 else 1_000), wl.Q)
         sample = np.sort(rng.choice(wl.Q, size=ns, replace=False))
         t1 = time.time()
-        o_ids, o_dist, _ = bi.query(wl.queries[sample], K)
+        o_ids, o_dist, _ = bi.query(wl.queries[sample], K, probes=args.probes)
         q_cpu = time.time() - t1
         bi.close()
         cpu_match = bool(np.array_equal(o_ids, ref_ids[sample]))
@@ -298,10 +303,12 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": (f"cfg{args.config}: n={wl.n} d={wl.d} {'u8' if is_u8 else 'f32'}, "
-                         f"Q={wl.Q} queries, L={L} k={wl.params.k} w={w} (w_0.9), K={K}"),
+                         f"Q={wl.Q} queries, L={L} k={wl.params.k} w={w} (w_0.9), K={K}"
+                         + (", one-step neighbour buckets probed" if args.probes else "")),
             "n": wl.n, "d": wl.d, "Q": wl.Q, "L": L, "k": wl.params.k, "w": w, "K": K,
             "projection": "fp16-mfma+fp64-guard" if is_u8 else "fp32-mfma+fp64-guard",
             "bucket_grouping": "automatic (rows of 1024 bytes or more, or 32768 queries or more)",
+            "neighbour_probing": bool(args.probes),
             "w_search": tried,
         },
         "recall_at_10": round(rec, 4),
