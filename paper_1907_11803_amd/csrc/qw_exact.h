@@ -125,12 +125,19 @@ __device__ inline void exact_dists_staged(const float *__restrict__ data, int dp
                 load(ring[kStageAhead - 1], nx < nch ? nx : nch - 1);
             }
             if (my < nr) {
-                const int ne = dp - ch * kStageCols < kStageCols ? dp - ch * kStageCols : kStageCols;
+                // the whole chunk, 32 squares per batch of LDS reads: columns
+                // past dp hold +0.0, which leaves the (non-negative) sum unchanged
                 const double *srow = stage + my * kStageLd;
-                for (int e = 0; e < ne; e += 2) {
-                    const double2 p = *reinterpret_cast<const double2 *>(srow + e);
-                    acc = acc + p.x;
-                    acc = acc + p.y;
+#pragma unroll
+                for (int e0 = 0; e0 < kStageCols; e0 += 32) {
+                    double2 p[16];
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) p[i] = *reinterpret_cast<const double2 *>(srow + e0 + 2 * i);
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        acc = acc + p[i].x;
+                        acc = acc + p[i].y;
+                    }
                 }
             }
         }
