@@ -29,6 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_FP16_TFLOPS = 2500.0  # dense FP16 matrix peak (no sparsity)
+MFMA_PEAK_FP32_TFLOPS = 157.3   # dense FP32 matrix peak
 W_GRID = [1, 1.5, 2, 2.5, 3, 4, 6, 8]
 METRIC = "queries/sec at recall@10>=0.9, BF16+learned vs plain FP32 on 1 MI355X"
 
@@ -280,12 +282,30 @@ def main():
         q_cpu = time.time() - t1
         bi.close()
         cpu_match = bool(np.array_equal(o_ids, ref_ids[sample]))
+        cpu_model = None
+        try:
+            with open("/proc/cpuinfo") as f:
+                cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+        except OSError:
+            pass
         cpu = {"value": round(len(sample) / q_cpu, 2), "unit": "queries/s", "cores": nthreads,
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": cpu_model, "host_threads": os.cpu_count(),
                "sample": f"{len(sample)} of {wl.Q} queries against the full {wl.n}-point index; "
                          f"oracle index build {build_cpu:.1f}s excluded, query phase {q_cpu:.2f}s",
                "matches_gpu": cpu_match}
         log(f"[bench] oracle: {cpu['value']} q/s on {nthreads} threads (build {build_cpu:.1f}s)")
+
+    # hashing (A1-A2): algorithmic projection flops against the dense MFMA peak
+    # of the type the kernel multiplies in (FP16 for uint8 data, FP32 for float)
+    hash_flops = 2.0 * wl.d * L * wl.params.k * wl.Q
+    hash_peak = MFMA_PEAK_FP16_TFLOPS if is_u8 else MFMA_PEAK_FP32_TFLOPS
+    hash_tflops = hash_flops / (stage[0] * 1e-3) / 1e12 if stage[0] > 0 else None
+    hash_info = {"kernel": "hash_mfma_f16_kernel" if is_u8 else "hash_mfma_f32_kernel",
+                 "ms": round(float(stage[0]), 4),
+                 "algorithmic_tflops": round(hash_tflops, 2) if hash_tflops else None,
+                 "peak_tflops": hash_peak,
+                 "frac": round(hash_tflops / hash_peak, 5) if hash_tflops else None,
+                 "index_build_s": round(build_s, 3)}
 
     qps = wl.Q / (ms_fast * 1e-3)
     line = {
@@ -340,6 +360,7 @@ def main():
                      "kernel_ms": round(kms, 4),
                      "kernel_algorithmic_bytes": int(kbytes),
                      "path_algorithmic_bytes_per_step": int(alg_bytes)},
+        "hash_mfma": hash_info,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
