@@ -12,8 +12,10 @@
  * forms the de-duplicated union of the bucket members (the candidates found by
  * accessing the index, Section 1.2), removes false positives by exact distance
  * and returns the top-K (the c-k-ANN output of Section 3).  The workload is
- * processed as a whole (Sections 4 and 5.1): queries that share buckets are
- * scheduled together so a bucket's ids and points are fetched once and reused.
+ * processed as a whole (Sections 4 and 5.1): queries whose candidate sets
+ * overlap are scheduled together so shared ids and points are fetched once and
+ * reused from cache.  Optionally every layer also probes the neighbouring
+ * buckets (qw_set_probing).
  *
  * Conventions for every entry point:
  *  - Pointers documented "device" must point to memory of the current HIP
@@ -61,8 +63,9 @@ typedef enum {
      * workload. */
     QW_FORM_PLAIN_FP32 = 0,
     /* FP16 (uint8 data) or FP32 (float data) MFMA projections with an FP64 guard
-     * band; queries binned by predicted candidate count (optionally grouped by
-     * bucket) into persistent dedup-and-verify kernels that also select the
+     * band; queries binned by predicted candidate count (and, with grouping,
+     * ordered by a min-hash of their candidate sets) into persistent
+     * dedup-and-verify kernels that also select the
      * top K (uint8 rows of at most 1024 bytes, K <= 16; otherwise a per-query
      * select kernel does); replayed from a HIP graph. */
     QW_FORM_FAST = 1
@@ -79,7 +82,10 @@ typedef enum {
 typedef struct {
     int32_t form;      /* qw_form */
     int32_t sched;     /* qw_sched (fast form only) */
-    int32_t group;     /* fast form: 1 = order queries by bucket key within a size class,
+    int32_t group;     /* fast form: 1 = order queries within a size class by a min-hash of
+                          their candidate sets (the minimum over their buckets of each
+                          bucket's smallest mixed id) and deal the order to the XCDs in
+                          chunks, so queries with overlapping candidates share an L2,
                           0 = no bucket ordering, -1 = automatic (default): ordering for
                           rows of 1024 bytes or more or workloads of 32768 queries or
                           more, where neighbouring queries share the rows they verify
@@ -189,7 +195,9 @@ qw_status qw_get_index_info(const qw_index *ix, qw_index_info *info);
 qw_status qw_hash(qw_index *ix, const void *x, int64_t m, int32_t form, void *stream,
                   int32_t *out_h, int64_t *out_recomputed);
 
-/* Bucket size of each (query, layer): out_sizes device int32 [Q][L] (0 = miss). */
+/* Bucket size of each (query, layer): out_sizes device int32 [Q][L] (0 = miss);
+ * with neighbour probing (qw_set_probing) the sum over the layer's probed
+ * buckets. */
 qw_status qw_bucket_sizes(qw_index *ix, const void *queries, int64_t Q, void *stream,
                           int32_t *out_sizes);
 
