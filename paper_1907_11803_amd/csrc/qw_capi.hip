@@ -82,10 +82,11 @@ Plan make_plan(qw_index *ix, int K)
     for (int i = 0; i + 1 < p.ncls; ++i)
         p.dgrid[i] = dedup_blocks_per_cu(dedup_lds_bytes(kCmin + i, 0, ix->nl, rbytes), ix->dtype) * ix->cus;
     p.dgrid[p.ncls - 1] = p.grid_g;
-    // select list: a few K keys in the usual case; K <= 1024 keeps LC <= 4096
-    // (32 KiB of keys, 64 KiB with the FP64 re-rank of float data)
+    // select list: a few K keys in the usual case (512 entries at K <= 128;
+    // a list beyond it sends the query to the fallback); K <= 1024 keeps
+    // LC <= 4096 (32 KiB of keys, 64 KiB with the FP64 re-rank of float data)
     static_assert(kMaxTopK <= 1024 && kBlock <= 1024, "select list sizing");
-    p.LC = pow2_at_least(std::max(1024, 4 * K));
+    p.LC = pow2_at_least(std::max(512, 4 * K));
     // uint8 rows of at most 64 parts and small K: the dedup kernel selects
     // the top K itself
     p.topk = (ix->dtype == QW_U8 && K <= kFusedTopK && rbytes / 16 <= 64) ? K : 0;

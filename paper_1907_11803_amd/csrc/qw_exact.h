@@ -60,8 +60,8 @@ __device__ inline double exact_dist_row(const float *__restrict__ x, const float
 // sums then run on lanes 0-3 of the four waves (row r on wave r % 4), one add
 // per element, so four SIMDs share the chains.
 constexpr int kStageRows = 16;
-constexpr int kStageCols = 128;
-constexpr int kStageAhead = 4;
+constexpr int kStageCols = 64;
+constexpr int kStageAhead = 6;
 constexpr int kStageLd = kStageCols + 2;  // row stride (doubles): rows start four banks apart
 constexpr size_t kStageBytes = size_t(kStageRows) * kStageLd * 8;
 
@@ -125,16 +125,16 @@ __device__ inline void exact_dists_staged(const float *__restrict__ data, int dp
                 load(ring[kStageAhead - 1], nx < nch ? nx : nch - 1);
             }
             if (my < nr) {
-                // the whole chunk, 32 squares per batch of LDS reads: columns
+                // the whole chunk, 16 squares per batch of LDS reads: columns
                 // past dp hold +0.0, which leaves the (non-negative) sum unchanged
                 const double *srow = stage + my * kStageLd;
 #pragma unroll
-                for (int e0 = 0; e0 < kStageCols; e0 += 32) {
-                    double2 p[16];
+                for (int e0 = 0; e0 < kStageCols; e0 += 16) {
+                    double2 p[8];
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) p[i] = *reinterpret_cast<const double2 *>(srow + e0 + 2 * i);
+                    for (int i = 0; i < 8; ++i) p[i] = *reinterpret_cast<const double2 *>(srow + e0 + 2 * i);
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) {
+                    for (int i = 0; i < 8; ++i) {
                         acc = acc + p[i].x;
                         acc = acc + p[i].y;
                     }
