@@ -42,9 +42,11 @@ def compare(ids_g, dist_g, ids_o, dist_o, rows, is_u8):
         np.testing.assert_allclose(dist_g[fin], dist_o[fin], rtol=1e-5)
 
 
-def run_gpu(wl, w, train, queries=None):
+def run_gpu(wl, w, train, queries=None, probes=0):
     p = wl.params
     ix = lib.Index(dev(wl.data), dev(p.a), dev(p.b(w)), w)
+    if probes:
+        ix.set_probing(1)
     if train is not None:
         ix.train_count_model(dev(train), epochs=6, batch=1024, lr=2e-3, seed=1)
     q = dev(wl.queries if queries is None else queries)
@@ -69,6 +71,22 @@ def test_cfg2_full_every_query(w):
     ids_o, dist_o, _ = bi.query(wl.queries, wl.K)
     bi.close()
     compare(ids, dist, ids_o, dist_o, np.arange(wl.Q), True)
+
+
+@pytest.mark.timeout(300)
+def test_cfg2_full_neighbour_probing_sampled():
+    """1M x 128 uint8 with the one-step neighbour buckets probed (420 lists per
+    query) at the probing w_0.9 (800): fast form, graph replay and plain form
+    agree; 1,000 sampled queries match the oracle with probes=1."""
+    wl = synth.make_config(2)
+    w = 800.0
+    train = synth.training_queries(2, 20_000)
+    ids, dist = run_gpu(wl, w, train, probes=1)
+    rows = np.sort(np.random.default_rng(13).choice(wl.Q, size=1000, replace=False))
+    bi = oracle.BuiltIndex(wl.data, wl.params.a, wl.params.b(w), w)
+    ids_o, dist_o, _ = bi.query(wl.queries[rows], wl.K, probes=1)
+    bi.close()
+    compare(ids, dist, ids_o, dist_o, rows, True)
 
 
 @pytest.mark.timeout(400)
