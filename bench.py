@@ -201,6 +201,23 @@ def main():
         log(f"[bench] profile loop: {ms:.3f} ms/step")
         return
 
+    # the copy rate this GPU reaches: 1 GiB device to device (1 GiB read and
+    # 1 GiB written per copy), the best of five, as a measured HBM ceiling
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    copy_gbs = 0.0
+    for _ in range(6):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbs = max(copy_gbs, 2 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del src, dst
+    torch.cuda.empty_cache()
+    log(f"[bench] device copy: {copy_gbs:.0f} GB/s")
+
     # exactness of the timed forms against each other and the brute-force recall
     ref_ids, ref_dist = ix.query(q_d, K, lib.make_opts(form=lib.QW_FORM_PLAIN_FP32))
     ref_ids, ref_dist = ref_ids.cpu().numpy(), ref_dist.cpu().numpy()
@@ -354,6 +371,8 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
                      "traffic": traffic, "kernel": kname,
+                     "measured_copy_gbs": round(copy_gbs, 1),
+                     "frac_of_measured_copy": round(achieved / copy_gbs, 4) if achieved else None,
                      # HBM bytes the counters saw over the same kernel time
                      "traffic_achieved": round(traffic / (kms * 1e-3) / 1e9, 1) if traffic and kms > 0 else None,
                      "traffic_frac": round(traffic / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if traffic and kms > 0 else None,
