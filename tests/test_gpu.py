@@ -180,6 +180,35 @@ def test_neighbour_probing_float_and_learned():
     assert ix.info()["has_count_model"] == 0
 
 
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_neighbour_probing_960_lists(dtype):
+    """L = 64, k = 7: 64 * 15 = 960 lists per query, near the 1024-list limit
+    (the workgroup prefix uses all four entries per thread, the list search
+    all ten steps); both forms and the candidate lists match the oracle."""
+    rng = np.random.default_rng(21)
+    n, d, Q, L, k = 2500, 16, 40, 64, 7
+    if dtype == "u8":
+        data = rng.integers(0, 256, size=(n, d), dtype=np.uint8)
+        q = np.clip(data[:Q].astype(np.int32) + rng.integers(-3, 4, size=(Q, d)), 0, 255).astype(np.uint8)
+        w = 250.0
+    else:
+        data = rng.random((n, d), dtype=np.float32)
+        q = (data[:Q] + rng.normal(0, 0.01, size=(Q, d))).astype(np.float32)
+        w = 1.2
+    a = rng.standard_normal((L, k, d)).astype(np.float32)
+    b = (rng.random((L, k)) * w).astype(np.float32)
+    ix = build(data, a, b, w)
+    ix.set_probing(1)
+    want = oracle.lsh_candidates(data, q, a, b, w, probes=1)
+    for g, o in zip(ix.candidate_lists(dev(q)), want):
+        assert np.array_equal(g, o)
+    ids_o, dist_o, cnt = oracle.lsh_query(data, q, a, b, w, 10, probes=1)
+    assert cnt.mean() > 100  # 135 (uint8) and 436 (float) candidates per query
+    for form in FORMS:
+        ids, dist = ix.query(dev(q), 10, lib.make_opts(form=form, sched=lib.QW_SCHED_SUM))
+        check_topk(ids, dist, ids_o, dist_o, dtype == "u8")
+
+
 def test_neighbour_probing_limits():
     rng = np.random.default_rng(9)
     data = rng.integers(0, 256, size=(500, 16), dtype=np.uint8)
