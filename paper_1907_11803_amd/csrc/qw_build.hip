@@ -189,7 +189,10 @@ static void hash_constants(const std::vector<float> &a, int32_t nf, int32_t d, i
 {
     const double u32 = std::ldexp(1.0, -24), u64 = std::ldexp(1.0, -53);
     const double g32 = gamma_n(d + 2, u32), g64 = gamma_n(d + 2, u64);
-    const double g32m = gamma_n(d + 3, u32);
+    // FP32 matrix cores, float data: FP32 within each chunk of kHashChunkF32
+    // elements (factor 2: unknown internal order), FP64 over the chunk sums
+    const double g32c = gamma_n(kHashChunkF32 + 3, u32);
+    const double g64c = gamma_n((dp + kHashChunkF32 - 1) / kHashChunkF32 + 1, u64);
     gb_plain.assign(nf, 0.0);
     gb_fast.assign(nf, 0.0);
     anorm.assign(nf, 0.0);
@@ -224,7 +227,7 @@ static void hash_constants(const std::vector<float> &a, int32_t nf, int32_t d, i
         if (use_f16)
             gb_fast[f] = (rep * safety + 2.0 * g32 * (ahn + aln) * safety + g64 * an) * safety;
         else
-            gb_fast[f] = (2.0 * g32m + g64) * an * safety;
+            gb_fast[f] = (2.0 * g32c + g64c + g64) * an * safety;
     }
 }
 

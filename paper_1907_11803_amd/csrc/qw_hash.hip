@@ -228,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void hash_fp32_kernel(
 // after the accepted ones are stored.
 
 constexpr int kKcF16 = 128;  // K chunk, FP16 form (uint8 data)
-constexpr int kKcF32 = 64;   // K chunk, FP32 form (float data)
+constexpr int kKcF32 = kHashChunkF32;  // K chunk, FP32 form (float data)
 
 // 16 loaded bytes, or zeros (masked per component: a select of the vector
 // type would go through memory)
@@ -418,9 +418,14 @@ __global__ __launch_bounds__(kBlock) void hash_mfma_f32_kernel(
             *reinterpret_cast<uint4 *>(as + o) = mask16(ar[i], keep);
         }
     };
+    // each KC-element chunk accumulates in FP32 on the matrix cores and is
+    // then added to an FP64 sum, so the FP32 error grows with KC, not d
     floatx4_t acc[4];
+    double dacc[4][4];
 #pragma unroll
-    for (int fb = 0; fb < 4; ++fb) acc[fb] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    for (int fb = 0; fb < 4; ++fb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) dacc[fb][j] = 0.0;
     float xmax = 0.f;
     load_chunk(0);
     for (int kc = 0; kc < dp; kc += KC) {
@@ -428,6 +433,8 @@ __global__ __launch_bounds__(kBlock) void hash_mfma_f32_kernel(
         store_chunk(kc);
         __syncthreads();
         if (kc + KC < dp) load_chunk(kc + KC);
+#pragma unroll
+        for (int fb = 0; fb < 4; ++fb) acc[fb] = floatx4_t{0.f, 0.f, 0.f, 0.f};
         const int ns = (dp - kc < KC ? dp - kc : KC) / 16;
 #pragma unroll
         for (int st = 0; st < KC / 16; ++st) {
@@ -446,6 +453,10 @@ __global__ __launch_bounds__(kBlock) void hash_mfma_f32_kernel(
                 acc[fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(xv.w, av[fb].w, acc[fb], 0, 0, 0);
             }
         }
+#pragma unroll
+        for (int fb = 0; fb < 4; ++fb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) dacc[fb][j] += (double)acc[fb][j];
     }
     xmax = fmaxf(xmax, __shfl_xor(xmax, 16));
     xmax = fmaxf(xmax, __shfl_xor(xmax, 32));
@@ -461,7 +472,7 @@ __global__ __launch_bounds__(kBlock) void hash_mfma_f32_kernel(
             const int64_t row = rl + j;
             if (row >= m || f >= f0 + nfun) continue;
             int32_t h;
-            if (accept_fp32(acc[fb][j], bf[fb], iw, cw[fb] * xm[j], h))
+            if (accept_fp32((float)dacc[fb][j], bf[fb], iw, cw[fb] * xm[j], h))
                 out[row * out_ld + (f - f0)] = h;
             else
                 pend |= 1u << (fb * 4 + j);

@@ -21,6 +21,9 @@ constexpr int kBlock = 256;              // threads per workgroup for every kern
 constexpr int kRecompSlots = 32;
 // Largest K the fused dedup kernel selects itself (uint8 data).
 constexpr int kFusedTopK = 16;
+// K chunk of the FP32 matrix-core hashing of float data: each chunk sums in
+// FP32, the chunk sums add up in FP64 (the guard band depends on it).
+constexpr int kHashChunkF32 = 64;
 // Bucket lists per query at most (neighbour probing: L * (2k + 1)).
 constexpr int kMaxLists = 1024;
 // With bucket grouping the dedup kernel deals its items to the XCDs in chunks
