@@ -48,13 +48,14 @@ def _load():
         i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         lib.orc_hash.argtypes = [P, i64, i32, i32, P, P, i32, f64, i32, P]
         lib.orc_lsh_query.argtypes = [P, i64, i32, i32, P, i64, P, P, i32, i32, f64, i32, i32,
-                                      P, P, P, P, i32]
+                                      P, P, P, P, i32, i32]
         lib.orc_lsh_candidates.argtypes = [P, i64, i32, i32, P, i64, P, P, i32, i32, f64, i32,
-                                           P, P, P, i32]
+                                           P, P, P, i32, i32]
+        lib.orc_project.argtypes = [P, i64, i32, i32, P, P, i32, f64, P]
         lib.orc_bruteforce.argtypes = [P, i64, i32, i32, P, i64, i32, i32, P, P, P]
         lib.orc_lsh_build.argtypes = [P, i64, i32, i32, P, P, i32, i32, f64, i32]
         lib.orc_lsh_build.restype = ctypes.c_void_p
-        lib.orc_lsh_query_built.argtypes = [P, P, i64, i32, i32, P, P, P, P, i32]
+        lib.orc_lsh_query_built.argtypes = [P, P, i64, i32, i32, P, P, P, P, i32, i32]
         lib.orc_lsh_free.argtypes = [P]
         lib.orc_lsh_free.restype = None
         for f in (lib.orc_hash, lib.orc_lsh_query, lib.orc_lsh_candidates, lib.orc_bruteforce,
@@ -99,10 +100,25 @@ def hash_points(x: np.ndarray, a: np.ndarray, b: np.ndarray, w: float,
     return out
 
 
+def project(x: np.ndarray, a: np.ndarray, b: np.ndarray, w: float) -> np.ndarray:
+    """y [m, L*k] float64: (a.x + b) / w in the hashing's FP64 sequence (h = floor(y))."""
+    x = np.ascontiguousarray(x)
+    a2 = np.ascontiguousarray(a.reshape(-1, a.shape[-1]), dtype=np.float32)
+    b2 = np.ascontiguousarray(b.reshape(-1), dtype=np.float32)
+    out = np.empty((x.shape[0], a2.shape[0]), dtype=np.float64)
+    rc = _load().orc_project(_ptr(x), x.shape[0], x.shape[1], _dtype_code(x), _ptr(a2), _ptr(b2),
+                             a2.shape[0], float(np.float32(w)), _ptr(out))
+    if rc:
+        raise ValueError("orc_project failed (%d)" % rc)
+    return out
+
+
 def lsh_query(data: np.ndarray, queries: np.ndarray, a: np.ndarray, b: np.ndarray,
-              w: float, K: int, nthreads: Optional[int] = None, probes: int = 0):
+              w: float, K: int, nthreads: Optional[int] = None, probes: int = 0,
+              probe_t: int = 0):
     """Top-K of every query over its LSH candidates (probes=1: also the 2k
-    one-step neighbour buckets of every layer).
+    one-step neighbour buckets of every layer; probes=2: the probe_t of them
+    with the smallest boundary-distance scores).
     Returns (ids int32 [Q,K], dist [Q,K] int64 (u8) or float64 (f32), counts int64 [Q])."""
     data = np.ascontiguousarray(data)
     queries = np.ascontiguousarray(queries)
@@ -121,14 +137,15 @@ def lsh_query(data: np.ndarray, queries: np.ndarray, a: np.ndarray, b: np.ndarra
         pi, pf = None, _ptr(dist)
     rc = _load().orc_lsh_query(_ptr(data), data.shape[0], d, dt, _ptr(queries), Q, _ptr(a),
                                _ptr(b), L, k, float(np.float32(w)), int(K), _threads(nthreads),
-                               _ptr(ids), pi, pf, _ptr(cnt), int(probes))
+                               _ptr(ids), pi, pf, _ptr(cnt), int(probes), int(probe_t))
     if rc:
         raise ValueError("orc_lsh_query failed (%d)" % rc)
     return ids, dist, cnt
 
 
 def lsh_candidates(data: np.ndarray, queries: np.ndarray, a: np.ndarray, b: np.ndarray,
-                   w: float, nthreads: Optional[int] = None, probes: int = 0) -> List[np.ndarray]:
+                   w: float, nthreads: Optional[int] = None, probes: int = 0,
+                   probe_t: int = 0) -> List[np.ndarray]:
     """Candidate set C(q) of every query, each as ascending int32 ids (probes=1:
     with the one-step neighbour buckets)."""
     data = np.ascontiguousarray(data)
@@ -142,13 +159,13 @@ def lsh_candidates(data: np.ndarray, queries: np.ndarray, a: np.ndarray, b: np.n
     cnt = np.empty((Q,), dtype=np.int64)
     args = (_ptr(data), data.shape[0], d, dt, _ptr(queries), Q, _ptr(a), _ptr(b), L, k,
             float(np.float32(w)), _threads(nthreads))
-    rc = lib.orc_lsh_candidates(*args, _ptr(cnt), None, None, int(probes))
+    rc = lib.orc_lsh_candidates(*args, _ptr(cnt), None, None, int(probes), int(probe_t))
     if rc:
         raise ValueError("orc_lsh_candidates failed (%d)" % rc)
     off = np.zeros(Q + 1, dtype=np.int64)
     np.cumsum(cnt, out=off[1:])
     ids = np.empty(max(1, int(off[-1])), dtype=np.int32)
-    rc = lib.orc_lsh_candidates(*args, _ptr(cnt), _ptr(off), _ptr(ids), int(probes))
+    rc = lib.orc_lsh_candidates(*args, _ptr(cnt), _ptr(off), _ptr(ids), int(probes), int(probe_t))
     if rc:
         raise ValueError("orc_lsh_candidates failed (%d)" % rc)
     return [ids[off[i]:off[i + 1]].copy() for i in range(Q)]
@@ -192,7 +209,7 @@ class BuiltIndex:
         if not self.h:
             raise ValueError("orc_lsh_build failed")
 
-    def query(self, queries, K, probes=0):
+    def query(self, queries, K, probes=0, probe_t=0):
         queries = np.ascontiguousarray(queries)
         Q = queries.shape[0]
         ids = np.empty((Q, K), dtype=np.int32)
@@ -205,7 +222,7 @@ class BuiltIndex:
             pi, pf = None, _ptr(dist)
         rc = _load().orc_lsh_query_built(ctypes.c_void_p(self.h), _ptr(queries), Q, int(K),
                                          self.nthreads, _ptr(ids), pi, pf, _ptr(cnt),
-                                         int(probes))
+                                         int(probes), int(probe_t))
         if rc:
             raise ValueError("orc_lsh_query_built failed (%d)" % rc)
         return ids, dist, cnt

@@ -30,6 +30,12 @@
  *     instead of adding layers) every layer also contributes the buckets whose
  *     tuple differs from the query's in exactly one coordinate by -1 or +1:
  *     C(q) = { p : exists l with key_l(p) - key_l(q) in {0, -e_j, +e_j} }.
+ *     Query-directed (Lv et al.'s ordering of probes by how close the query
+ *     lies to each slot boundary): only the T of those 2k neighbours with the
+ *     smallest score, where for y_j = (a_j.q + b_j) / w (step 1's FP64
+ *     sequence) and f_j = y_j - floor(y_j), moving coordinate j by -1 scores
+ *     f_j * f_j and by +1 scores (1 - f_j) * (1 - f_j), each rounded in FP64;
+ *     ties go to the smaller j, then to -1.
  *  5. Verification (removing false positives, Section 1.2): exact squared
  *     Euclidean distance; int64 for uint8 data, double accumulated in index
  *     order for float32 data: acc = acc + (x-q)*(x-q) with x-q formed in double.
@@ -58,14 +64,20 @@ static double elem(const void *x, int dtype, int64_t idx)
 
 /* ---- step 1: h = floor((a.v + b) / w), FP64 in index order ---------------- */
 
-static int hash_one(const void *x, int dtype, int64_t row, int32_t d,
-                    const float *a_j, float b_j, double w, int32_t *out)
+static double project_one(const void *x, int dtype, int64_t row, int32_t d,
+                          const float *a_j, float b_j, double w)
 {
     double acc = 0.0;
     for (int32_t i = 0; i < d; ++i)
         acc = acc + (double)a_j[i] * elem(x, dtype, row * (int64_t)d + i);
     double t = acc + (double)b_j;
-    double y = t / w;
+    return t / w;
+}
+
+static int hash_one(const void *x, int dtype, int64_t row, int32_t d,
+                    const float *a_j, float b_j, double w, int32_t *out)
+{
+    double y = project_one(x, dtype, row, d, a_j, b_j, w);
     double f = floor(y);
     if (!(f >= -2147483648.0 && f <= 2147483647.0))
         return -1;
@@ -100,6 +112,18 @@ static int run_threads(void *(*fn)(void *), void *jobs, size_t job_size, int nth
             return -1;
     for (int t = 0; t < nthreads; ++t)
         pthread_join(th[t], NULL);
+    return 0;
+}
+
+/* y[m][nf] = (a.x + b) / w in step 1's FP64 sequence (the value h floors). */
+int orc_project(const void *x, int64_t m, int32_t d, int32_t dtype, const float *a,
+                const float *b, int32_t nf, double w, double *out_y)
+{
+    if (!x || !a || !b || !out_y || m < 0 || d <= 0 || nf <= 0 || !(w > 0) || !isfinite(w))
+        return -1;
+    for (int64_t r = 0; r < m; ++r)
+        for (int32_t f = 0; f < nf; ++f)
+            out_y[r * nf + f] = project_one(x, dtype, r, d, a + (int64_t)f * d, b[f], w);
     return 0;
 }
 
@@ -247,7 +271,10 @@ static void distance(const void *data, const void *q, int dtype, int32_t d,
 
 typedef struct {
     const orc_index *ix; const int32_t *hq; /* [Q][L*k] query hashes (NULL = brute force) */
-    int32_t probes; /* 1: also the 2k one-step neighbour buckets of every layer */
+    int32_t probes; /* 1: also the 2k one-step neighbour buckets of every layer;
+                       2: the probe_t of them with the smallest scores */
+    int32_t probe_t;
+    const float *a, *b; double w; /* for the scores of probes == 2 */
     const void *data; const void *q; int dtype; int32_t d; int64_t Q; int32_t K;
     int32_t *out_ids; int64_t *out_di; double *out_df; int64_t *out_cnt;
     int64_t *cand_off; int32_t *cand_ids; /* optional candidate-list output */
@@ -264,17 +291,45 @@ static void *query_worker(void *p)
     if (!mark || !list || !sc) { j->err = 1; free(mark); free(list); free(sc); return NULL; }
     int32_t L = j->ix->L, k = j->ix->k;
     int32_t t[64];
-    const int32_t nprobe = j->probes ? 1 + 2 * k : 1;
+    double score[128];
+    int32_t pick[128];
+    const int32_t nprobe = j->probes == 2 ? 1 + j->probe_t : (j->probes ? 1 + 2 * k : 1);
     for (int64_t qi = j->tid; qi < j->Q; qi += j->nthreads) {
         int64_t nc = 0;
         if (j->hq) {  /* step 4: union of the query's bucket(s) in every layer */
             for (int32_t l = 0; l < L; ++l) {
                 const int32_t *home = j->hq + qi * (int64_t)L * k + (int64_t)l * k;
+                if (j->probes == 2) {
+                    /* scores of the 2k moves (index 2c + s), then the probe_t
+                       smallest by (score, index) */
+                    for (int32_t c = 0; c < k; ++c) {
+                        const int32_t fn = l * k + c;
+                        double y = project_one(j->q, j->dtype, qi, j->d,
+                                               j->a + (int64_t)fn * j->d, j->b[fn], j->w);
+                        double fr = y - floor(y);
+                        double up = 1.0 - fr;
+                        score[2 * c] = fr * fr;
+                        score[2 * c + 1] = up * up;
+                    }
+                    for (int32_t u = 0; u < 2 * k; ++u) pick[u] = u;
+                    for (int32_t u = 1; u < 2 * k; ++u) {  /* insertion sort by (score, index) */
+                        int32_t v = pick[u], z = u;
+                        while (z > 0 && (score[pick[z - 1]] > score[v] ||
+                                         (score[pick[z - 1]] == score[v] && pick[z - 1] > v))) {
+                            pick[z] = pick[z - 1];
+                            --z;
+                        }
+                        pick[z] = v;
+                    }
+                }
                 for (int32_t pr = 0; pr < nprobe; ++pr) {
                     /* probe 0: the home tuple; probe 1 + 2c + s: coordinate c moved
-                       by -1 (s = 0) or +1 (s = 1) */
+                       by -1 (s = 0) or +1 (s = 1); query-directed: the pr-th pick */
                     for (int32_t c = 0; c < k; ++c) t[c] = home[c];
-                    if (pr > 0) t[(pr - 1) / 2] += ((pr - 1) % 2) ? 1 : -1;
+                    if (pr > 0) {
+                        const int32_t mv = j->probes == 2 ? pick[pr - 1] : pr - 1;
+                        t[mv / 2] += (mv % 2) ? 1 : -1;
+                    }
                     int64_t cnt;
                     int64_t pos = bucket_find(j->ix, l, t, &cnt);
                     const int32_t *o = j->ix->order + (int64_t)l * n;
@@ -349,10 +404,11 @@ int orc_lsh_query(const void *data, int64_t n, int32_t d, int32_t dtype,
                   const void *q, int64_t Q, const float *a, const float *b,
                   int32_t L, int32_t k, double w, int32_t K, int32_t nthreads,
                   int32_t *out_ids, int64_t *out_di, double *out_df, int64_t *out_cnt,
-                  int32_t probes)
+                  int32_t probes, int32_t probe_t)
 {
     if (check_common(data, n, d, q, Q, a, b, L, k, w) || K <= 0 || !out_ids) return -1;
-    if (probes < 0 || probes > 1 || k > 64) return -1;
+    if (probes < 0 || probes > 2 || k > 64) return -1;
+    if (probes == 2 && (probe_t < 1 || probe_t > 2 * k)) return -1;
     int32_t nf = L * k;
     int32_t *hd = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1) * nf);
     int32_t *hq = (int32_t *)malloc(sizeof(int32_t) * (size_t)(Q > 0 ? Q : 1) * nf);
@@ -362,7 +418,7 @@ int orc_lsh_query(const void *data, int64_t n, int32_t d, int32_t dtype,
     orc_index ix = {0};
     if (!rc) rc = index_build(&ix, hd, n, L, k, nthreads);
     if (!rc) {
-        query_job t = {&ix, hq, probes, data, q, dtype, d, Q, K, out_ids, out_di, out_df,
+        query_job t = {&ix, hq, probes, probe_t, a, b, w, data, q, dtype, d, Q, K, out_ids, out_di, out_df,
                        out_cnt, NULL, NULL, 0, 1, 0};
         rc = run_queries(&t, nthreads);
     }
@@ -379,10 +435,11 @@ int orc_lsh_candidates(const void *data, int64_t n, int32_t d, int32_t dtype,
                        const void *q, int64_t Q, const float *a, const float *b,
                        int32_t L, int32_t k, double w, int32_t nthreads,
                        int64_t *out_cnt, const int64_t *cand_off, int32_t *cand_ids,
-                       int32_t probes)
+                       int32_t probes, int32_t probe_t)
 {
     if (check_common(data, n, d, q, Q, a, b, L, k, w) || !out_cnt) return -1;
-    if (probes < 0 || probes > 1 || k > 64) return -1;
+    if (probes < 0 || probes > 2 || k > 64) return -1;
+    if (probes == 2 && (probe_t < 1 || probe_t > 2 * k)) return -1;
     if (cand_ids && !cand_off) return -1;
     int32_t nf = L * k;
     int32_t *hd = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1) * nf);
@@ -393,7 +450,7 @@ int orc_lsh_candidates(const void *data, int64_t n, int32_t d, int32_t dtype,
     orc_index ix = {0};
     if (!rc) rc = index_build(&ix, hd, n, L, k, nthreads);
     if (!rc) {
-        query_job t = {&ix, hq, probes, data, q, dtype, d, Q, 0, NULL, NULL, NULL, out_cnt,
+        query_job t = {&ix, hq, probes, probe_t, a, b, w, data, q, dtype, d, Q, 0, NULL, NULL, NULL, out_cnt,
                        (int64_t *)cand_off, cand_ids, 0, 1, 0};
         rc = run_queries(&t, nthreads);
     }
@@ -430,16 +487,17 @@ void *orc_lsh_build(const void *data, int64_t n, int32_t d, int32_t dtype, const
 
 int orc_lsh_query_built(void *h, const void *q, int64_t Q, int32_t K, int32_t nthreads,
                         int32_t *out_ids, int64_t *out_di, double *out_df, int64_t *out_cnt,
-                        int32_t probes)
+                        int32_t probes, int32_t probe_t)
 {
     orc_built *o = (orc_built *)h;
     if (!o || !q || Q < 0 || K <= 0 || !out_ids) return -1;
-    if (probes < 0 || probes > 1 || o->k > 64) return -1;
+    if (probes < 0 || probes > 2 || o->k > 64) return -1;
+    if (probes == 2 && (probe_t < 1 || probe_t > 2 * o->k)) return -1;
     int32_t *hq = (int32_t *)malloc(sizeof(int32_t) * (size_t)(Q > 0 ? Q : 1) * o->L * o->k);
     if (!hq) return -5;
     int rc = orc_hash(q, Q, o->d, o->dtype, o->a, o->b, o->L * o->k, o->w, nthreads, hq);
     if (!rc) {
-        query_job t = {&o->ix, hq, probes, o->data, q, o->dtype, o->d, Q, K, out_ids, out_di,
+        query_job t = {&o->ix, hq, probes, probe_t, o->a, o->b, o->w, o->data, q, o->dtype, o->d, Q, K, out_ids, out_di,
                        out_df, out_cnt, NULL, NULL, 0, 1, 0};
         rc = run_queries(&t, nthreads);
     }
@@ -462,7 +520,7 @@ int orc_bruteforce(const void *data, int64_t n, int32_t d, int32_t dtype,
     if (!data || !q || n < 0 || Q < 0 || d <= 0 || K <= 0 || !out_ids || n > INT32_MAX)
         return -1;
     orc_index ix = {NULL, NULL, n, 1, 1};
-    query_job t = {&ix, NULL, 0, data, q, dtype, d, Q, K, out_ids, out_di, out_df, NULL,
+    query_job t = {&ix, NULL, 0, 0, NULL, NULL, 0.0, data, q, dtype, d, Q, K, out_ids, out_di, out_df, NULL,
                    NULL, NULL, 0, 1, 0};
     return run_queries(&t, nthreads);
 }

@@ -180,6 +180,55 @@ def test_neighbour_probing_candidates_match_definition(dtype):
     assert added > 0
 
 
+def test_project_floors_to_hash_and_is_close_to_exact():
+    """y = (a.x + b) / w from the oracle floors to its hash values and lies within
+    a few FP64 ulps of the exact rational value."""
+    wl = synth.make_config(1, n=200, Q=5, w=500.0)
+    a, b, w = wl.params.a, wl.params.b(), wl.params.w
+    y = oracle.project(wl.queries, a, b, w)
+    assert np.array_equal(np.floor(y).astype(np.int32), oracle.hash_points(wl.queries, a, b, w))
+    af = a.reshape(-1, a.shape[-1])
+    for r in range(wl.queries.shape[0]):
+        for f in range(0, af.shape[0], 7):
+            ex = (sum(Fraction(float(u)) * int(v) for u, v in zip(af[f], wl.queries[r])) +
+                  Fraction(float(b.reshape(-1)[f]))) / Fraction(float(np.float32(w)))
+            assert abs(y[r, f] - float(ex)) <= 1e-12 * max(1.0, abs(float(ex)))
+
+
+@pytest.mark.parametrize("T", [1, 3, 6])
+def test_query_directed_probing_matches_definition(T):
+    """The T best moves by (score, index) with score f^2 for -1 and (1 - f)^2 for
+    +1 (f the fractional part of y), selected here with numpy's lexsort from the
+    oracle's y, then the candidate set by broadcasting; T = 2k equals probing
+    every neighbour."""
+    wl = synth.make_config(1, n=3000, Q=25, w=500.0)
+    a, b, w = wl.params.a, wl.params.b(), wl.params.w
+    L, k = wl.params.L, wl.params.k
+    got = oracle.lsh_candidates(wl.data, wl.queries, a, b, w, probes=2, probe_t=T)
+    hd = oracle.hash_points(wl.data, a, b, w).reshape(-1, L, k).astype(np.int64)
+    hq = oracle.hash_points(wl.queries, a, b, w).reshape(-1, L, k).astype(np.int64)
+    y = oracle.project(wl.queries, a, b, w).reshape(-1, L, k)
+    for q in range(wl.queries.shape[0]):
+        ok = np.zeros(hd.shape[0], dtype=bool)
+        for l in range(L):
+            fr = y[q, l] - np.floor(y[q, l])
+            score = np.empty(2 * k)
+            score[0::2] = fr * fr
+            score[1::2] = (1.0 - fr) * (1.0 - fr)
+            moves = np.lexsort((np.arange(2 * k), score))[:T]
+            targets = [hq[q, l].copy()]
+            for mv in moves:
+                t = hq[q, l].copy()
+                t[mv // 2] += 1 if mv % 2 else -1
+                targets.append(t)
+            for t in targets:
+                ok |= np.all(hd[:, l, :] == t, axis=1)
+        assert np.array_equal(got[q], np.nonzero(ok)[0].astype(np.int32))
+    full = oracle.lsh_candidates(wl.data, wl.queries, a, b, w, probes=2, probe_t=2 * k)
+    every = oracle.lsh_candidates(wl.data, wl.queries, a, b, w, probes=1)
+    assert all(np.array_equal(x, z) for x, z in zip(full, every))
+
+
 def test_neighbour_probing_topk_is_topk_of_candidates():
     """The probed top K is the (distance, id) top K of the probed candidate set,
     selected here with numpy's lexsort over int64 distances."""
