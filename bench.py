@@ -76,8 +76,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--w", type=float, default=None, help="bucket width (default: search w_0.9)")
-    ap.add_argument("--probes", type=int, default=0, choices=[0, 1],
-                    help="1: also probe each layer's 2k one-step neighbour buckets")
+    ap.add_argument("--probes", type=int, default=0, choices=[0, 1, 2],
+                    help="1: also probe each layer's 2k one-step neighbour buckets; "
+                         "2: only the --probe-t best of them per query (query-directed)")
+    ap.add_argument("--probe-t", type=int, default=4, help="moves per layer for --probes 2")
     ap.add_argument("--train-queries", type=int, default=None,
                     help="count-model training queries (default: the configuration's, else 50,000)")
     ap.add_argument("--recall-sample", type=int, default=2000,
@@ -122,7 +124,7 @@ def main():
         t1 = time.time()
         ix = lib.Index(data_d, a_d, b_d, w, form=lib.QW_FORM_FAST)
         if args.probes:
-            ix.set_probing(1)
+            ix.set_probing(args.probes, args.probe_t)
         build_s = time.time() - t1
         if args.profile:  # profiling runs time the query loop only
             chosen = (w, ix, b_d, None, None)
@@ -280,7 +282,7 @@ def main():
     if os.path.exists(tfile):
         tj = json.load(open(tfile))
         if (tj.get("source") == kernel_source_hash(ksrc) and abs(tj.get("w", -1) - w) < 1e-9
-                and tj.get("probes", 0) == args.probes):
+                and tj.get("probes", 0) == args.probes and args.probes != 2):
             traffic = tj.get("bytes_per_launch")
 
     # ---- CPU oracle on a bounded sample
@@ -295,7 +297,8 @@ def main():
         ns = min(args.cpu_sample if args.cpu_sample > 0 else (10_000 if is_u8 else 1_000), wl.Q)
         sample = np.sort(rng.choice(wl.Q, size=ns, replace=False))
         t1 = time.time()
-        o_ids, o_dist, _ = bi.query(wl.queries[sample], K, probes=args.probes)
+        o_ids, o_dist, _ = bi.query(wl.queries[sample], K, probes=args.probes,
+                                    probe_t=args.probe_t if args.probes == 2 else 0)
         q_cpu = time.time() - t1
         bi.close()
         cpu_match = bool(np.array_equal(o_ids, ref_ids[sample]))
@@ -341,11 +344,12 @@ def main():
         "config": {
             "workload": (f"cfg{args.config}: n={wl.n} d={wl.d} {'u8' if is_u8 else 'f32'}, "
                          f"Q={wl.Q} queries, L={L} k={wl.params.k} w={w} (w_0.9), K={K}"
-                         + (", one-step neighbour buckets probed" if args.probes else "")),
+                         + ({0: "", 1: ", one-step neighbour buckets probed",
+                             2: f", {args.probe_t} query-directed neighbour probes per layer"}[args.probes])),
             "n": wl.n, "d": wl.d, "Q": wl.Q, "L": L, "k": wl.params.k, "w": w, "K": K,
             "projection": "fp16-mfma+fp64-guard" if is_u8 else "fp32-mfma+fp64-guard",
             "bucket_grouping": "automatic (rows of 1024 bytes or more, or 32768 queries or more)",
-            "neighbour_probing": bool(args.probes),
+            "neighbour_probing": {0: None, 1: "all one-step", 2: f"query-directed, {args.probe_t} per layer"}[args.probes],
             "w_search": tried,
         },
         "recall_at_10": round(rec, 4),

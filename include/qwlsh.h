@@ -130,6 +130,7 @@ typedef struct {
     int32_t has_count_model;
     float count_margin;    /* log-space margin added to the model's prediction when sizing sets */
     int32_t probing;       /* qw_set_probing mode (0: the query's own bucket per layer) */
+    int32_t probes_per_layer; /* neighbour buckets probed per layer (0 without probing) */
 } qw_index_info;
 
 typedef struct qw_index qw_index;
@@ -280,15 +281,24 @@ qw_status qw_set_count_margin(qw_index *ix, float margin);
  *  mode 0 (default): each layer contributes the query's own bucket;
  *  mode 1: each layer also contributes the 2k buckets whose k-tuple differs
  *          from the query's in exactly one coordinate by -1 or +1, so
- *          C(q) = { p : exists l, key_l(p) - key_l(q) in {0, -e_j, +e_j} }.
+ *          C(q) = { p : exists l, key_l(p) - key_l(q) in {0, -e_j, +e_j} };
+ *  mode 2: query-directed (Lv et al.'s ordering): only the per_layer
+ *          (1 <= per_layer <= 2k) of those moves with the smallest scores,
+ *          where with y_j = (a_j.q + b_j) / w (the hashing's FP64 sequence)
+ *          and f_j = y_j - floor(y_j) moving coordinate j by -1 scores
+ *          f_j * f_j and by +1 scores (1 - f_j) * (1 - f_j), each operation
+ *          rounded in FP64, ties to the smaller j, then to -1.  The GPU
+ *          computes these projections in FP64 for the queries.
+ * per_layer is ignored for modes 0 and 1.
  * Every later call on the index (queries, candidate counts and lists, bucket
  * sizes -- then the sum over each layer's probed buckets -- and count-model
  * training) uses the mode.  Changing it drops captured graphs and the count
  * model, which was fitted to the other candidate sets.  Needs
- * L * (2k + 1) <= 1024 lists per query (QW_EUNSUPPORTED otherwise); QW_EINVAL
- * for another mode.  Not to be called while work on the index is in flight.
+ * L * (1 + probes per layer) <= 1024 lists per query (QW_EUNSUPPORTED
+ * otherwise); QW_EINVAL for another mode or per_layer out of range.  Not to be
+ * called while work on the index is in flight.
  */
-qw_status qw_set_probing(qw_index *ix, int32_t mode);
+qw_status qw_set_probing(qw_index *ix, int32_t mode, int32_t per_layer);
 
 #ifdef __cplusplus
 }

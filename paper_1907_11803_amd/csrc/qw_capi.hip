@@ -108,7 +108,7 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan, bool keys = false
     Workspace &w = ix->ws;
     auto ptrs = [&w]() {
         return std::vector<void *>{w.qpad.p, w.h.p, w.bstart.p, w.bsize.p, w.bmh.p, w.lsum.p,
-                                   w.lmh.p, w.pred.p,
+                                   w.lmh.p, w.yq.p, w.moves.p, w.pred.p,
                                    w.feats.p, w.keys.p, w.keys2.p, w.vals.p, w.vals2.p,
                                    w.binoff.p, w.counters.p, w.ovf.p, w.gscratch.p, w.mlpout.p,
                                    w.order.p,
@@ -126,6 +126,10 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan, bool keys = false
     if (ix->nprobe > 1) {
         QW_TRY(w.lsum.ensure(sizeof(uint32_t) * (size_t)q * ix->L));
         QW_TRY(w.lmh.ensure(sizeof(uint32_t) * (size_t)q * ix->L));
+    }
+    if (ix->probe_mode == 2) {
+        QW_TRY(w.yq.ensure(sizeof(double) * (size_t)q * ix->nf));
+        QW_TRY(w.moves.ensure((size_t)q * ix->L * (ix->nprobe - 1)));
     }
     QW_TRY(w.pred.ensure(sizeof(int32_t) * q));
     QW_TRY(w.feats.ensure(sizeof(float) * (size_t)q * ix->L));
@@ -216,8 +220,15 @@ qw_status front(qw_index *ix, const void *queries, int64_t Q, int form, hipStrea
     QW_TRY(launch_hash(ix, ix->ws.qrows, Q, 0, ix->nf, form, ix->ws.h.as<int32_t>(), ix->nf,
                        c64(ix) + C_RECOMP, s));
     if (ev) QW_HIP(hipEventRecord(ev[1], s));
+    const uint8_t *moves = nullptr;
+    if (ix->probe_mode == 2) {
+        QW_TRY(launch_probe_moves(ix, ix->ws.qrows, Q, ix->ws.yq.as<double>(),
+                                  ix->ws.moves.as<uint8_t>(), s));
+        moves = ix->ws.moves.as<uint8_t>();
+    }
     QW_TRY(launch_probe(ix, ix->ws.h.as<int32_t>(), Q, ix->ws.bstart.as<uint32_t>(),
-                        ix->ws.bsize.as<uint32_t>(), ix->nprobe == 1 ? feats : nullptr, bmh, s));
+                        ix->ws.bsize.as<uint32_t>(), ix->nprobe == 1 ? feats : nullptr, bmh,
+                        moves, s));
     if (ix->nprobe > 1)
         QW_TRY(launch_layer_sums(ix->ws.bsize.as<uint32_t>(), bmh, Q, ix->L, ix->nprobe,
                                  ix->ws.lsum.as<uint32_t>(), bmh ? ix->ws.lmh.as<uint32_t>() : nullptr,
@@ -620,7 +631,8 @@ qw_status qw_get_index_info(const qw_index *ix, qw_index_info *info)
     for (const DevBuf *b : bufs) info->device_bytes += (int64_t)b->bytes;
     info->has_count_model = ix->mlp.empty() ? 0 : 1;
     info->count_margin = ix->mlp_margin;
-    info->probing = ix->nprobe > 1 ? 1 : 0;
+    info->probing = ix->probe_mode;
+    info->probes_per_layer = ix->nprobe - 1;
     return QW_OK;
 }
 
@@ -861,11 +873,12 @@ qw_status qw_set_count_margin(qw_index *ix, float margin)
     return QW_OK;
 }
 
-qw_status qw_set_probing(qw_index *ix, int32_t mode)
+qw_status qw_set_probing(qw_index *ix, int32_t mode, int32_t per_layer)
 {
     QW_TRY(check_index(ix));
-    if (mode != 0 && mode != 1) return QW_EINVAL;
-    const int32_t P = mode ? 2 * ix->k + 1 : 1;
+    if (mode < 0 || mode > 2) return QW_EINVAL;
+    if (mode == 2 && (per_layer < 1 || per_layer > 2 * ix->k)) return QW_EINVAL;
+    const int32_t P = mode == 2 ? 1 + per_layer : (mode ? 2 * ix->k + 1 : 1);
     if ((int64_t)ix->L * P > kMaxLists) return QW_EUNSUPPORTED;
     uint32_t magic = 0;
     if (P > 1) {  // layer of list i: (i * magic) >> 20, checked over every list index
@@ -873,9 +886,10 @@ qw_status qw_set_probing(qw_index *ix, int32_t mode)
         for (int i = 0; i < kMaxLists; ++i)
             if ((int)(((uint32_t)i * magic) >> 20) != i / P) return QW_EINTERNAL;
     }
-    if (P == ix->nprobe) return QW_OK;
+    if (P == ix->nprobe && mode == ix->probe_mode) return QW_OK;
     drop_graphs(ix);
     ix->plans.clear();
+    ix->probe_mode = mode;
     ix->nprobe = P;
     ix->nl = ix->L * P;
     ix->pmagic = magic;

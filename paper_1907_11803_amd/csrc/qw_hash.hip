@@ -521,11 +521,92 @@ qw_status launch_hash(const qw_index *ix, const void *xpad, int64_t m, int32_t f
     return QW_OK;
 }
 
+// ---------------------------------------------------------------- probe scores
+// Query-directed probing.  y[q][f] = (a_f.x_q + b_f) / w in FP64, index order
+// (each product of a float parameter and a uint8 or float input is exact in
+// FP64, so the fused multiply-add rounds like the separate steps); one thread
+// per (query, function), the lanes of a wave on consecutive functions of one
+// query.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void project_fp64_kernel(
+    const T *__restrict__ x, int64_t Q, int32_t dp, int32_t d, const float *__restrict__ a32,
+    const float *__restrict__ b, int32_t nf, double w, double *__restrict__ y)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= Q * nf) return;
+    const int64_t q = i / nf;
+    const int32_t f = (int32_t)(i - q * nf);
+    const T *xr = x + q * dp;
+    const float *ar = a32 + (int64_t)f * dp;
+    double acc = 0.0;
+    for (int32_t e = 0; e < d; ++e) acc = __dadd_rn(acc, __dmul_rn((double)ar[e], (double)xr[e]));
+    y[i] = __dadd_rn(acc, (double)b[f]) / w;
+}
+
+// One thread per (query, layer): the T one-step moves with the smallest
+// scores, in (score, move) order -- move 2j + s shifts hash value j by -1
+// (s = 0, score f_j * f_j) or +1 (s = 1, score (1 - f_j) * (1 - f_j)), with
+// f_j = y_j - floor(y_j), every operation rounded in FP64 as the scores are
+// defined.  Pass t takes the smallest (score, move) above the previous pick.
+__global__ __launch_bounds__(kBlock) void select_moves_kernel(
+    const double *__restrict__ y, int64_t Q, int32_t L, int32_t k, int32_t T,
+    uint8_t *__restrict__ moves)
+{
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= Q * L) return;
+    const double *yl = y + i * k;  // the layer's k values (nf = L * k per query)
+    double ps = -1.0;
+    int32_t pm = -1;
+    for (int32_t t = 0; t < T; ++t) {
+        double bs = INFINITY;
+        int32_t bm = 2 * k;
+        for (int32_t j = 0; j < k; ++j) {
+            const double v = yl[j];
+            const double fr = v - floor(v);
+            const double up = 1.0 - fr;
+            const double s0 = fr * fr, s1 = up * up;
+            const int32_t m0 = 2 * j, m1 = 2 * j + 1;
+            // candidates strictly after the previous pick in (score, move) order
+            const bool e0 = s0 > ps || (s0 == ps && m0 > pm);
+            const bool e1 = s1 > ps || (s1 == ps && m1 > pm);
+            if (e0 && (s0 < bs || (s0 == bs && m0 < bm))) { bs = s0; bm = m0; }
+            if (e1 && (s1 < bs || (s1 == bs && m1 < bm))) { bs = s1; bm = m1; }
+        }
+        moves[i * T + t] = (uint8_t)bm;
+        ps = bs;
+        pm = bm;
+    }
+}
+
+qw_status launch_probe_moves(const qw_index *ix, const void *xpad, int64_t Q, double *y,
+                             uint8_t *moves, hipStream_t s)
+{
+    if (Q <= 0) return QW_OK;
+    const int64_t nt = Q * ix->nf;
+    const unsigned g = (unsigned)ceil_div(nt, kBlock);
+    if (ix->dtype == QW_U8)
+        project_fp64_kernel<uint8_t><<<g, kBlock, 0, s>>>((const uint8_t *)xpad, Q, ix->dp, ix->d,
+                                                          ix->a32.as<float>(), ix->b32.as<float>(),
+                                                          ix->nf, (double)ix->w, y);
+    else
+        project_fp64_kernel<float><<<g, kBlock, 0, s>>>((const float *)xpad, Q, ix->dp, ix->d,
+                                                        ix->a32.as<float>(), ix->b32.as<float>(),
+                                                        ix->nf, (double)ix->w, y);
+    QW_HIP(hipGetLastError());
+    const int32_t T = ix->nprobe - 1;
+    select_moves_kernel<<<(unsigned)ceil_div(Q * ix->L, kBlock), kBlock, 0, s>>>(
+        y, Q, ix->L, ix->k, T, moves);
+    QW_HIP(hipGetLastError());
+    return QW_OK;
+}
+
 // ---------------------------------------------------------------- probe
 // One thread per (query, layer, probe): probe 0 is the query's own bucket;
 // with neighbour probing (P = 2k + 1) probe 1 + 2j + s moves hash value j by
 // -1 (s = 0) or +1 (s = 1), the buckets next to the query's in one coordinate
-// (the multi-probe variant summarised in Section 2).  The k values are packed
+// (the multi-probe variant summarised in Section 2); query-directed (moves
+// non-null, P = T + 1) probe 1 + t takes the layer's t-th chosen move.  The k values are packed
 // into the exact key (values outside the data's range cannot match any
 // bucket: a miss; such a key is never looked up), then the key is looked up
 // in the layer's open-addressing table.  Outputs are [Q][L][P]; bmh
@@ -537,7 +618,7 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(
     const int32_t *__restrict__ shift, const TabEntry *__restrict__ tab,
     const long long *__restrict__ tab_off, const uint32_t *__restrict__ tab_mask,
     uint32_t *__restrict__ bstart, uint32_t *__restrict__ bsize, float *__restrict__ feats,
-    uint32_t *__restrict__ bmh)
+    uint32_t *__restrict__ bmh, const uint8_t *__restrict__ moves)
 {
     // per-function constants (value range, bit offset in the key) staged in
     // LDS while the hash values load: one memory latency for both
@@ -563,7 +644,9 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(
     if (!live) return;
     bool valid = true;
     if (p > 0) {  // neighbour probe: one value moved by one (a move past the int32 range: a miss)
-        const int32_t jp = (p - 1) >> 1, dlt = (p - 1) & 1 ? 1 : -1;
+        // every neighbour (probe p is move p - 1), or the query's chosen moves
+        const int32_t mv = moves ? (int32_t)moves[ql * (P - 1) + (p - 1)] : p - 1;
+        const int32_t jp = mv >> 1, dlt = mv & 1 ? 1 : -1;
 #pragma unroll
         for (int32_t j = 0; j < kMaxK; ++j)
             if (j == jp) {
@@ -616,7 +699,8 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(
 }
 
 qw_status launch_probe(const qw_index *ix, const int32_t *h, int64_t Q, uint32_t *bstart,
-                       uint32_t *bsize, float *feats, uint32_t *bmh, hipStream_t s)
+                       uint32_t *bsize, float *feats, uint32_t *bmh, const uint8_t *moves,
+                       hipStream_t s)
 {
     if (Q <= 0) return QW_OK;
     if (feats && ix->nprobe != 1) return QW_EINTERNAL;  // features of probed layers: layer sums
@@ -625,7 +709,7 @@ qw_status launch_probe(const qw_index *ix, const int32_t *h, int64_t Q, uint32_t
     probe_kernel<<<(unsigned)ceil_div(total, kBlock), kBlock, lds, s>>>(
         h, Q, ix->L, ix->k, ix->nprobe, ix->hmin.as<int32_t>(), ix->hmax.as<int32_t>(),
         ix->shift.as<int32_t>(), ix->tab.as<TabEntry>(), ix->tab_off.as<long long>(),
-        ix->tab_mask.as<uint32_t>(), bstart, bsize, feats, bmh);
+        ix->tab_mask.as<uint32_t>(), bstart, bsize, feats, bmh, moves);
     QW_HIP(hipGetLastError());
     return QW_OK;
 }

@@ -101,8 +101,8 @@ __host__ __device__ inline uint32_t id_mix(uint32_t x)
 }
 
 struct Workspace {
-    DevBuf qpad, h, bstart, bsize, bmh, lsum, lmh, pred, feats, keys, keys2, vals, vals2, hist,
-        order, binoff, counters, ovf, gscratch, mlpout, scan;
+    DevBuf qpad, h, bstart, bsize, bmh, lsum, lmh, yq, moves, pred, feats, keys, keys2, vals,
+        vals2, hist, order, binoff, counters, ovf, gscratch, mlpout, scan;
     // flat pipeline
     DevBuf ucount, coff, flag, pkeys, fb;
     // the query rows the kernels of the current call read: the caller's own
@@ -144,6 +144,7 @@ struct qw_index {
     // query (L * nprobe) and the layer-of-list multiplier (0 without probing)
     int32_t nprobe = 1, nl = 0;
     uint32_t pmagic = 0;
+    int32_t probe_mode = 0;  // qw_set_probing mode: 2 = query-directed (nprobe - 1 moves)
     float w = 0.f;
     // hash parameters (device)
     qw::DevBuf a32;      // float [nf_pad][dp], zero padded
@@ -208,7 +209,12 @@ qw_status launch_hash(const qw_index *ix, const void *xpad, int64_t m, int32_t f
 // Probe every (query, layer): bstart/bsize [Q][L] (bsize 0 = miss); feats
 // (nullable) log(1 + size); bmh (nullable) the bucket's min-hash.
 qw_status launch_probe(const qw_index *ix, const int32_t *h, int64_t Q, uint32_t *bstart,
-                       uint32_t *bsize, float *feats, uint32_t *bmh, hipStream_t s);
+                       uint32_t *bsize, float *feats, uint32_t *bmh, const uint8_t *moves,
+                       hipStream_t s);
+// Query-directed probing: FP64 projections y [Q][nf] of the query rows and
+// each layer's T chosen moves [Q][L][T] (T = nprobe - 1).
+qw_status launch_probe_moves(const qw_index *ix, const void *xpad, int64_t Q, double *y,
+                             uint8_t *moves, hipStream_t s);
 
 // Generic fills.
 qw_status launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s);

@@ -60,7 +60,7 @@ class qw_index_info(ctypes.Structure):
                 ("key_bits", ctypes.c_int32 * 64), ("buckets", ctypes.c_int64),
                 ("max_bucket", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("has_count_model", ctypes.c_int32), ("count_margin", ctypes.c_float),
-                ("probing", ctypes.c_int32)]
+                ("probing", ctypes.c_int32), ("probes_per_layer", ctypes.c_int32)]
 
 
 # exported symbols and their signatures (restype qw_status unless noted)
@@ -85,7 +85,7 @@ SIGNATURES = {
     "qw_set_count_model": (ctypes.c_int, [_P, _P, _I32]),
     "qw_get_count_model": (ctypes.c_int, [_P, _P, _I32]),
     "qw_set_count_margin": (ctypes.c_int, [_P, ctypes.c_float]),
-    "qw_set_probing": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "qw_set_probing": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
 }
 
 _lib = None
@@ -305,8 +305,8 @@ def qw_set_count_margin(ix, margin: float):
     _check(load().qw_set_count_margin(ix, float(margin)), "qw_set_count_margin")
 
 
-def qw_set_probing(ix, mode: int):
-    _check(load().qw_set_probing(ix, int(mode)), "qw_set_probing")
+def qw_set_probing(ix, mode: int, per_layer: int = 0):
+    _check(load().qw_set_probing(ix, int(mode), int(per_layer)), "qw_set_probing")
 
 
 def qw_get_count_model(ix, L: int) -> np.ndarray:
@@ -358,8 +358,8 @@ class Index:
     def set_count_margin(self, margin: float):
         qw_set_count_margin(self.handle, margin)
 
-    def set_probing(self, mode: int):
-        qw_set_probing(self.handle, mode)
+    def set_probing(self, mode: int, per_layer: int = 0):
+        qw_set_probing(self.handle, mode, per_layer)
 
     def info(self) -> dict:
         return qw_get_index_info(self.handle)

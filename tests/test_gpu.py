@@ -180,6 +180,46 @@ def test_neighbour_probing_float_and_learned():
     assert ix.info()["has_count_model"] == 0
 
 
+@pytest.mark.parametrize("T", [1, 4, 16])
+def test_query_directed_probing_cfg1(cfg1, T):
+    """Query-directed probing (the T best one-step moves by boundary-distance
+    score, from FP64 projections on the GPU): candidate lists and the top K of
+    both forms, every schedule and both groupings match the oracle."""
+    p = cfg1.params
+    w = 600.0
+    ix = build(cfg1.data, p.a, p.b(w), w)
+    q = cfg1.queries
+    ix.set_probing(2, T)
+    info = ix.info()
+    assert info["probing"] == 2 and info["probes_per_layer"] == T
+    want = oracle.lsh_candidates(cfg1.data, q, p.a, p.b(w), w, probes=2, probe_t=T)
+    for g, o in zip(ix.candidate_lists(dev(q)), want):
+        assert np.array_equal(g, o)
+    ids_o, dist_o, _ = oracle.lsh_query(cfg1.data, q, p.a, p.b(w), w, cfg1.K, probes=2, probe_t=T)
+    for form in FORMS:
+        ids, dist = ix.query(dev(q), cfg1.K, lib.make_opts(form=form, sched=lib.QW_SCHED_SUM))
+        check_topk(ids, dist, ids_o, dist_o, True)
+    for sched in SCHEDS:
+        for group in (0, 1):
+            ids, dist = ix.query(dev(q), cfg1.K, lib.make_opts(sched=sched, group=group))
+            check_topk(ids, dist, ids_o, dist_o, True)
+
+
+def test_query_directed_probing_float():
+    wl = synth.make_config(3, n=6000, Q=60, ncomp=30, w=4.0)
+    p = wl.params
+    ix = build(wl.data, p.a, p.b(), p.w)
+    ix.set_probing(2, 5)
+    ids_o, dist_o, cnt = oracle.lsh_query(wl.data, wl.queries, p.a, p.b(), p.w, wl.K, probes=2,
+                                          probe_t=5)
+    assert cnt.mean() > 10
+    for form in FORMS:
+        ids, dist = ix.query(dev(wl.queries), wl.K, lib.make_opts(form=form, sched=lib.QW_SCHED_SUM))
+        check_topk(ids, dist, ids_o, dist_o, False)
+    with pytest.raises(lib.QwError):
+        ix.set_probing(2, 2 * p.k + 1)
+
+
 @pytest.mark.parametrize("dtype", ["u8", "f32"])
 def test_neighbour_probing_960_lists(dtype):
     """L = 64, k = 7: 64 * 15 = 960 lists per query, near the 1024-list limit
