@@ -17,6 +17,17 @@ namespace qw {
 
 // ---------------------------------------------------------------- kernels
 
+// out[c][r] = in[r][c] for an r x c float matrix
+__global__ void transpose_f32_kernel(const float *__restrict__ in, int32_t rows, int32_t cols,
+                                     float *__restrict__ out)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)rows * cols;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / cols, c = i - r * cols;
+        out[c * rows + r] = in[i];
+    }
+}
+
 __global__ void maxabs_f32_kernel(const float *__restrict__ x, int64_t count, uint32_t *out)
 {
     float m = 0.f;
@@ -277,6 +288,10 @@ qw_status build_index(const void *data, int64_t n, int32_t d, int32_t dtype, con
     QW_TRY(ix->a32.ensure(sizeof(float) * (size_t)ix->nf_pad * dp));
     QW_HIP(hipMemsetAsync(ix->a32.p, 0, ix->a32.bytes, s));
     QW_TRY(launch_pad_rows(a, nf, d, dp, QW_F32, ix->a32.p, s));
+    QW_TRY(ix->a32t.ensure(sizeof(float) * (size_t)ix->nf_pad * dp));
+    transpose_f32_kernel<<<grid_of((int64_t)ix->nf_pad * dp), kBlock, 0, s>>>(
+        ix->a32.as<float>(), ix->nf_pad, dp, ix->a32t.as<float>());
+    QW_HIP(hipGetLastError());
     QW_TRY(ix->b32.ensure(sizeof(float) * nf));
     QW_HIP(hipMemcpyAsync(ix->b32.p, b, sizeof(float) * nf, hipMemcpyDeviceToDevice, s));
     QW_TRY(ix->gb_plain.ensure(sizeof(double) * nf));

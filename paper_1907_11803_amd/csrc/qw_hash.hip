@@ -524,23 +524,63 @@ qw_status launch_hash(const qw_index *ix, const void *xpad, int64_t m, int32_t f
 // ---------------------------------------------------------------- probe scores
 // Query-directed probing.  y[q][f] = (a_f.x_q + b_f) / w in FP64, index order
 // (each product of a float parameter and a uint8 or float input is exact in
-// FP64, so the fused multiply-add rounds like the separate steps); one thread
-// per (query, function), the lanes of a wave on consecutive functions of one
-// query.
+// FP64, so the fused multiply-add rounds like the separate steps).  One
+// thread per (query, group of kProjF functions): the lanes of a wave take
+// consecutive queries of one function group, so the parameters are uniform
+// (scalar loads from a32 [nf_pad][dp]), each query element is converted once
+// and feeds kProjF independent sums.
+constexpr int kProjF = 8;
+
+__device__ inline void load16(const uint8_t *p, double (&v)[16])
+{
+    const uint4 w = *reinterpret_cast<const uint4 *>(p);
+    const uint32_t u[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = (double)((u[i >> 2] >> (8 * (i & 3))) & 0xFFu);
+}
+__device__ inline void load16(const float *p, double (&v)[16])
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float4 w = reinterpret_cast<const float4 *>(p)[i];
+        v[4 * i] = (double)w.x;
+        v[4 * i + 1] = (double)w.y;
+        v[4 * i + 2] = (double)w.z;
+        v[4 * i + 3] = (double)w.w;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void project_fp64_kernel(
     const T *__restrict__ x, int64_t Q, int32_t dp, int32_t d, const float *__restrict__ a32,
     const float *__restrict__ b, int32_t nf, double w, double *__restrict__ y)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= Q * nf) return;
-    const int64_t q = i / nf;
-    const int32_t f = (int32_t)(i - q * nf);
-    const T *xr = x + q * dp;
-    const float *ar = a32 + (int64_t)f * dp;
-    double acc = 0.0;
-    for (int32_t e = 0; e < d; ++e) acc = __dadd_rn(acc, __dmul_rn((double)ar[e], (double)xr[e]));
-    y[i] = __dadd_rn(acc, (double)b[f]) / w;
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int32_t f0 = blockIdx.y * kProjF;  // a32 has nf_pad >= f0 + kProjF zero-padded rows
+    if (q >= Q) return;
+    const T *xr = x + q * dp;  // dp: a multiple of 16 elements, zero padded past d
+    double acc[kProjF];
+#pragma unroll
+    for (int j = 0; j < kProjF; ++j) acc[j] = 0.0;
+    for (int32_t e0 = 0; e0 < d; e0 += 16) {
+        double xv[16];
+        load16(xr + e0, xv);
+        // the 16 x kProjF parameters of this step (uniform: scalar loads)
+        float av[kProjF][16];
+#pragma unroll
+        for (int j = 0; j < kProjF; ++j)
+#pragma unroll
+            for (int u = 0; u < 16; ++u) av[j][u] = a32[(int64_t)(f0 + j) * dp + e0 + u];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (e0 + u < d)  // uniform
+#pragma unroll
+                for (int j = 0; j < kProjF; ++j)
+                    acc[j] = __dadd_rn(acc[j], __dmul_rn((double)av[j][u], xv[u]));
+    }
+#pragma unroll
+    for (int j = 0; j < kProjF; ++j)
+        if (f0 + j < nf) y[q * nf + f0 + j] = __dadd_rn(acc[j], (double)b[f0 + j]) / w;
 }
 
 // One thread per (query, layer): the T one-step moves with the smallest
@@ -583,8 +623,7 @@ qw_status launch_probe_moves(const qw_index *ix, const void *xpad, int64_t Q, do
                              uint8_t *moves, hipStream_t s)
 {
     if (Q <= 0) return QW_OK;
-    const int64_t nt = Q * ix->nf;
-    const unsigned g = (unsigned)ceil_div(nt, kBlock);
+    const dim3 g((unsigned)ceil_div(Q, kBlock), (unsigned)ceil_div(ix->nf, kProjF));
     if (ix->dtype == QW_U8)
         project_fp64_kernel<uint8_t><<<g, kBlock, 0, s>>>((const uint8_t *)xpad, Q, ix->dp, ix->d,
                                                           ix->a32.as<float>(), ix->b32.as<float>(),

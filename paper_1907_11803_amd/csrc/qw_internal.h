@@ -148,6 +148,7 @@ struct qw_index {
     float w = 0.f;
     // hash parameters (device)
     qw::DevBuf a32;      // float [nf_pad][dp], zero padded
+    qw::DevBuf a32t;     // float [dp][nf_pad]: a32 transposed (FP64 query projections)
     qw::DevBuf b32;      // float [nf]
     qw::DevBuf a_hi;     // _Float16 [nf_pad][dp]  (uint8 data, MFMA path)
     qw::DevBuf a_lo;     // _Float16 [nf_pad][dp]
