@@ -5,9 +5,10 @@ CPU-baseline leg are the only callers.  Nothing in the GPU library imports this
 package, and this package imports nothing from the library.
 
 Modules:
-  qw_oracle.c  -- hashing, per-layer buckets, candidate union, exact verification,
-                  top-K and brute-force kNN in FP64 / int64 (plain C, threads over
-                  queries only); loaded here through ctypes.
+  qw_oracle.c  -- hashing, per-layer buckets, candidate union (or collision
+                  counting with a cap), exact verification, top-K and brute-force
+                  kNN in FP64 / int64 (plain C, threads over queries only);
+                  loaded here through ctypes.
   mlp.py       -- FP64 forward/backward of the candidate-count regressor.
   collision.py -- the p-stable collision probability of Eq. (1).
 """
@@ -56,6 +57,9 @@ def _load():
         lib.orc_lsh_build.argtypes = [P, i64, i32, i32, P, P, i32, i32, f64, i32]
         lib.orc_lsh_build.restype = ctypes.c_void_p
         lib.orc_lsh_query_built.argtypes = [P, P, i64, i32, i32, P, P, P, P, i32, i32]
+        lib.orc_lsh_query_counting.argtypes = [P, i64, i32, i32, P, i64, P, P, i32, i32, f64,
+                                               i32, i32, i32, i32, P, P, P, P]
+        lib.orc_lsh_query_counting.restype = ctypes.c_int
         lib.orc_lsh_free.argtypes = [P]
         lib.orc_lsh_free.restype = None
         for f in (lib.orc_hash, lib.orc_lsh_query, lib.orc_lsh_candidates, lib.orc_bruteforce,
@@ -140,6 +144,37 @@ def lsh_query(data: np.ndarray, queries: np.ndarray, a: np.ndarray, b: np.ndarra
                                _ptr(ids), pi, pf, _ptr(cnt), int(probes), int(probe_t))
     if rc:
         raise ValueError("orc_lsh_query failed (%d)" % rc)
+    return ids, dist, cnt
+
+
+def lsh_query_counting(data: np.ndarray, queries: np.ndarray, a: np.ndarray, b: np.ndarray,
+                       w: float, K: int, theta: int, v: int, nthreads: Optional[int] = None):
+    """Collision counting with a candidate cap (Section 2.4): the points sharing
+    a bucket with the query in at least theta layers, ranked by (layer count
+    descending, id ascending), the first K + v of them verified, the top K kept.
+    Returns (ids int32 [Q,K], dist [Q,K] int64 (u8) or float64 (f32),
+    verified int64 [Q])."""
+    data = np.ascontiguousarray(data)
+    queries = np.ascontiguousarray(queries)
+    L, k, d = a.shape
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    b = np.ascontiguousarray(b, dtype=np.float32)
+    Q = queries.shape[0]
+    ids = np.empty((Q, K), dtype=np.int32)
+    cnt = np.empty((Q,), dtype=np.int64)
+    dt = _dtype_code(data)
+    if dt == U8:
+        dist = np.empty((Q, K), dtype=np.int64)
+        pi, pf = _ptr(dist), None
+    else:
+        dist = np.empty((Q, K), dtype=np.float64)
+        pi, pf = None, _ptr(dist)
+    rc = _load().orc_lsh_query_counting(_ptr(data), data.shape[0], d, dt, _ptr(queries), Q,
+                                        _ptr(a), _ptr(b), L, k, float(np.float32(w)), int(K),
+                                        int(theta), int(v), _threads(nthreads), _ptr(ids), pi,
+                                        pf, _ptr(cnt))
+    if rc:
+        raise ValueError("orc_lsh_query_counting failed (%d)" % rc)
     return ids, dist, cnt
 
 

@@ -43,6 +43,14 @@
  *     when |C(q)| < K the tail is padded with id -1 and distance INT64_MAX
  *     (u8) or +inf (f32).
  *  7. Brute force: step 6 over all n points (exact kNN).
+ *  8. Collision counting with a candidate cap (Section 2.4, after C2LSH: each
+ *     layer acts as one collision test, a threshold on the number of tests a
+ *     point passes replaces the plain union, and at most k + v points -- K
+ *     results plus v allowed false positives -- are verified): #Col(p) is the
+ *     number of layers l with key_l(p) == key_l(q); the points with
+ *     #Col(p) >= theta are ranked by (#Col descending, id ascending), the
+ *     first K + v of them are verified (step 5) and the top K taken (step 6).
+ *     theta = 1 with a cap above |C(q)| is the plain union of step 4.
  *
  * All entry points return 0 on success and a negative value on bad input.
  */
@@ -279,7 +287,17 @@ typedef struct {
     int32_t *out_ids; int64_t *out_di; double *out_df; int64_t *out_cnt;
     int64_t *cand_off; int32_t *cand_ids; /* optional candidate-list output */
     int tid, nthreads; int err;
+    int32_t theta, vextra; /* step 8 when theta >= 1: threshold and extra verified points */
 } query_job;
+
+typedef struct { int32_t count, id; } counted;
+
+static int cmp_counted(const void *pa, const void *pb)
+{
+    const counted *a = (const counted *)pa, *b = (const counted *)pb;
+    if (a->count != b->count) return a->count > b->count ? -1 : 1;
+    return (a->id > b->id) - (a->id < b->id);
+}
 
 static void *query_worker(void *p)
 {
@@ -288,7 +306,11 @@ static void *query_worker(void *p)
     uint8_t *mark = (uint8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
     int32_t *list = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     scored *sc = (scored *)malloc(sizeof(scored) * (size_t)(n > 0 ? n : 1));
-    if (!mark || !list || !sc) { j->err = 1; free(mark); free(list); free(sc); return NULL; }
+    int32_t *col = j->theta > 0 ? (int32_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t)) : NULL;
+    counted *ct = j->theta > 0 ? (counted *)malloc(sizeof(counted) * (size_t)(n > 0 ? n : 1)) : NULL;
+    if (!mark || !list || !sc || (j->theta > 0 && (!col || !ct))) {
+        j->err = 1; free(mark); free(list); free(sc); free(col); free(ct); return NULL;
+    }
     int32_t L = j->ix->L, k = j->ix->k;
     int32_t t[64];
     double score[128];
@@ -333,11 +355,24 @@ static void *query_worker(void *p)
                     int64_t cnt;
                     int64_t pos = bucket_find(j->ix, l, t, &cnt);
                     const int32_t *o = j->ix->order + (int64_t)l * n;
-                    for (int64_t e = pos; e < pos + cnt; ++e)
+                    for (int64_t e = pos; e < pos + cnt; ++e) {
+                        if (col) ++col[o[e]];
                         if (!mark[o[e]]) { mark[o[e]] = 1; list[nc++] = o[e]; }
+                    }
                 }
             }
             for (int64_t c = 0; c < nc; ++c) mark[list[c]] = 0;
+            if (col) {  /* step 8: threshold, rank by (count desc, id asc), cap at K + v */
+                int64_t m = 0;
+                for (int64_t c = 0; c < nc; ++c) {
+                    if (col[list[c]] >= j->theta) { ct[m].count = col[list[c]]; ct[m].id = list[c]; ++m; }
+                    col[list[c]] = 0;
+                }
+                qsort(ct, (size_t)m, sizeof(counted), cmp_counted);
+                const int64_t cap = (int64_t)j->K + j->vextra;
+                nc = m < cap ? m : cap;
+                for (int64_t c = 0; c < nc; ++c) list[c] = ct[c].id;
+            }
         } else {      /* step 7: every point */
             for (int64_t c = 0; c < n; ++c) list[c] = (int32_t)c;
             nc = n;
@@ -367,7 +402,7 @@ static void *query_worker(void *p)
             }
         }
     }
-    free(mark); free(list); free(sc);
+    free(mark); free(list); free(sc); free(col); free(ct);
     return NULL;
 }
 
@@ -419,7 +454,36 @@ int orc_lsh_query(const void *data, int64_t n, int32_t d, int32_t dtype,
     if (!rc) rc = index_build(&ix, hd, n, L, k, nthreads);
     if (!rc) {
         query_job t = {&ix, hq, probes, probe_t, a, b, w, data, q, dtype, d, Q, K, out_ids, out_di, out_df,
-                       out_cnt, NULL, NULL, 0, 1, 0};
+                       out_cnt, NULL, NULL, 0, 1, 0, 0, 0};
+        rc = run_queries(&t, nthreads);
+    }
+    free(ix.order); free(hd); free(hq);
+    return rc;
+}
+
+/*
+ * Collision counting (step 8) on the plain layers: out_cnt [Q] (nullable)
+ * receives the number of points verified, min(K + v, #{p : #Col(p) >= theta}).
+ */
+int orc_lsh_query_counting(const void *data, int64_t n, int32_t d, int32_t dtype,
+                           const void *q, int64_t Q, const float *a, const float *b,
+                           int32_t L, int32_t k, double w, int32_t K, int32_t theta,
+                           int32_t v, int32_t nthreads, int32_t *out_ids, int64_t *out_di,
+                           double *out_df, int64_t *out_cnt)
+{
+    if (check_common(data, n, d, q, Q, a, b, L, k, w) || K <= 0 || !out_ids) return -1;
+    if (theta < 1 || v < 0 || k > 64) return -1;
+    int32_t nf = L * k;
+    int32_t *hd = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1) * nf);
+    int32_t *hq = (int32_t *)malloc(sizeof(int32_t) * (size_t)(Q > 0 ? Q : 1) * nf);
+    if (!hd || !hq) { free(hd); free(hq); return -5; }
+    int rc = orc_hash(data, n, d, dtype, a, b, nf, w, nthreads, hd);
+    if (!rc) rc = orc_hash(q, Q, d, dtype, a, b, nf, w, nthreads, hq);
+    orc_index ix = {0};
+    if (!rc) rc = index_build(&ix, hd, n, L, k, nthreads);
+    if (!rc) {
+        query_job t = {&ix, hq, 0, 0, a, b, w, data, q, dtype, d, Q, K, out_ids, out_di, out_df,
+                       out_cnt, NULL, NULL, 0, 1, 0, theta, v};
         rc = run_queries(&t, nthreads);
     }
     free(ix.order); free(hd); free(hq);
@@ -451,7 +515,7 @@ int orc_lsh_candidates(const void *data, int64_t n, int32_t d, int32_t dtype,
     if (!rc) rc = index_build(&ix, hd, n, L, k, nthreads);
     if (!rc) {
         query_job t = {&ix, hq, probes, probe_t, a, b, w, data, q, dtype, d, Q, 0, NULL, NULL, NULL, out_cnt,
-                       (int64_t *)cand_off, cand_ids, 0, 1, 0};
+                       (int64_t *)cand_off, cand_ids, 0, 1, 0, 0, 0};
         rc = run_queries(&t, nthreads);
     }
     free(ix.order); free(hd); free(hq);
@@ -498,7 +562,7 @@ int orc_lsh_query_built(void *h, const void *q, int64_t Q, int32_t K, int32_t nt
     int rc = orc_hash(q, Q, o->d, o->dtype, o->a, o->b, o->L * o->k, o->w, nthreads, hq);
     if (!rc) {
         query_job t = {&o->ix, hq, probes, probe_t, o->a, o->b, o->w, o->data, q, o->dtype, o->d, Q, K, out_ids, out_di,
-                       out_df, out_cnt, NULL, NULL, 0, 1, 0};
+                       out_df, out_cnt, NULL, NULL, 0, 1, 0, 0, 0};
         rc = run_queries(&t, nthreads);
     }
     free(hq);
@@ -521,6 +585,6 @@ int orc_bruteforce(const void *data, int64_t n, int32_t d, int32_t dtype,
         return -1;
     orc_index ix = {NULL, NULL, n, 1, 1};
     query_job t = {&ix, NULL, 0, 0, NULL, NULL, 0.0, data, q, dtype, d, Q, K, out_ids, out_di, out_df, NULL,
-                   NULL, NULL, 0, 1, 0};
+                   NULL, NULL, 0, 1, 0, 0, 0};
     return run_queries(&t, nthreads);
 }

@@ -512,3 +512,86 @@ def test_built_index_matches_one_shot_query():
         ids2, d2, c2 = bi.query(wl.queries, 10, probes=probes)
         assert np.array_equal(ids1, ids2) and np.array_equal(d1, d2) and np.array_equal(c1, c2)
     bi.close()
+
+
+# ---------------------------------------------------------------- collision counting
+
+def test_counting_hand_example():
+    """Three single-function layers reading one coordinate each (a = e_j, b = 0,
+    w = 1, so h_j(v) = v_j): the layer counts of the query (0, 0, 0) are 3, 2,
+    1, 2, 0 for the five points; the cap keeps the best-counted points and
+    breaks equal counts by id, whatever their distances."""
+    data = np.array([[0, 0, 0], [0, 0, 5], [0, 5, 5], [5, 0, 0], [5, 5, 5]], np.uint8)
+    qs = np.zeros((1, 3), np.uint8)
+    a = np.eye(3, dtype=np.float32).reshape(3, 1, 3)
+    b = np.zeros((3, 1), np.float32)
+    run = lambda K, theta, v: oracle.lsh_query_counting(data, qs, a, b, 1.0, K, theta, v)
+    ids, dist, cnt = run(1, 2, 1)
+    assert ids.tolist() == [[0]] and dist.tolist() == [[0]] and cnt.tolist() == [2]
+    ids, dist, cnt = run(2, 2, 0)  # points 1 and 3 tie on count 2: id 1 is kept
+    assert ids.tolist() == [[0, 1]] and dist.tolist() == [[0, 25]] and cnt.tolist() == [2]
+    ids, dist, cnt = run(3, 2, 0)
+    assert ids.tolist() == [[0, 1, 3]] and dist.tolist() == [[0, 25, 25]]
+    ids, dist, cnt = run(3, 1, 10)  # point 2 (count 1) joins; point 4 never does
+    assert ids.tolist() == [[0, 1, 3]] and cnt.tolist() == [4]
+    ids, dist, cnt = run(2, 3, 5)
+    assert ids.tolist() == [[0, -1]] and dist.tolist() == [[0, I64MAX]] and cnt.tolist() == [1]
+    ids, dist, cnt = run(2, 4, 5)  # a threshold above L: nothing qualifies
+    assert ids.tolist() == [[-1, -1]] and cnt.tolist() == [0]
+
+
+def _naive_counting(data, qs, hd, hq, L, k, K, theta, v):
+    """Collision counting from its definition with numpy: the number of layers
+    whose whole k-tuple matches, by broadcasting over all points; a lexsort by
+    (count descending, id ascending) for the cap; then (distance, id)."""
+    n = hd.shape[0]
+    hd3 = hd.reshape(n, L, k)
+    out = []
+    for q in range(qs.shape[0]):
+        col = np.all(hd3 == hq[q].reshape(1, L, k), axis=2).sum(axis=1)
+        c = np.nonzero(col >= theta)[0]
+        c = c[np.lexsort((c, -col[c]))][:K + v]
+        dd = ((data[c].astype(np.int64) - qs[q].astype(np.int64)) ** 2).sum(axis=1)
+        order = np.lexsort((c, dd))[:K]
+        out.append((c[order].tolist() + [-1] * (K - len(order)), len(c), dd[order].tolist()))
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_counting_matches_dense_definition(dtype):
+    """Small random cases, several thresholds and caps, against the dense count
+    over all points (float rows hold small integers, so every distance is exact
+    and the float and integer orders agree)."""
+    rng = np.random.default_rng(31)
+    for trial in range(25):
+        n, d = int(rng.integers(1, 200)), int(rng.integers(1, 9))
+        Q, L, k = 5, int(rng.integers(1, 7)), int(rng.integers(1, 3))
+        K, theta, v = int(rng.integers(1, 9)), int(rng.integers(1, L + 2)), int(rng.integers(0, 12))
+        data = rng.integers(0, 8, size=(n, d)).astype(np.uint8)
+        qs = rng.integers(0, 8, size=(Q, d)).astype(np.uint8)
+        if dtype == "f32":
+            data, qs = data.astype(np.float32), qs.astype(np.float32)
+        a = rng.standard_normal((L, k, d)).astype(np.float32)
+        w = 4.0
+        b = (rng.random((L, k)) * w).astype(np.float32)
+        ids, dist, cnt = oracle.lsh_query_counting(data, qs, a, b, w, K, theta, v)
+        hd = oracle.hash_points(data, a, b, w)
+        hq = oracle.hash_points(qs, a, b, w)
+        for q, (want_ids, nver, want_d) in enumerate(_naive_counting(data, qs, hd, hq, L, k, K,
+                                                                     theta, v)):
+            assert ids[q].tolist() == want_ids
+            assert cnt[q] == nver
+            assert dist[q][:len(want_d)].tolist() == want_d
+
+
+def test_counting_threshold_one_without_cap_is_the_union():
+    wl = synth.make_config(1, n=3000, Q=40, w=900.0)
+    a, b, w = wl.params.a, wl.params.b(), wl.params.w
+    ids0, dist0, cnt0 = oracle.lsh_query(wl.data, wl.queries, a, b, w, 10)
+    ids1, dist1, cnt1 = oracle.lsh_query_counting(wl.data, wl.queries, a, b, w, 10, 1, 3000)
+    assert np.array_equal(ids0, ids1) and np.array_equal(dist0, dist1)
+    assert np.array_equal(cnt0, cnt1)
+    # a tighter threshold or cap verifies fewer points and never a better answer
+    ids2, dist2, cnt2 = oracle.lsh_query_counting(wl.data, wl.queries, a, b, w, 10, 2, 100)
+    assert np.all(cnt2 <= np.minimum(cnt0, 110))
+    assert np.all(dist2 >= dist0)
