@@ -15,7 +15,8 @@
  * processed as a whole (Sections 4 and 5.1): queries whose candidate sets
  * overlap are scheduled together so shared ids and points are fetched once and
  * reused from cache.  Optionally every layer also probes the neighbouring
- * buckets (qw_set_probing).
+ * buckets (qw_set_probing), or the union gives way to collision counting with
+ * a cap on the verified points (qw_set_counting).
  *
  * Conventions for every entry point:
  *  - Pointers documented "device" must point to memory of the current HIP
@@ -131,6 +132,8 @@ typedef struct {
     float count_margin;    /* log-space margin added to the model's prediction when sizing sets */
     int32_t probing;       /* qw_set_probing mode (0: the query's own bucket per layer) */
     int32_t probes_per_layer; /* neighbour buckets probed per layer (0 without probing) */
+    int32_t count_threshold;  /* qw_set_counting threshold (0: plain union) */
+    int32_t count_extra;      /* qw_set_counting extra (v) */
 } qw_index_info;
 
 typedef struct qw_index qw_index;
@@ -299,6 +302,28 @@ qw_status qw_set_count_margin(qw_index *ix, float margin);
  * called while work on the index is in flight.
  */
 qw_status qw_set_probing(qw_index *ix, int32_t mode, int32_t per_layer);
+
+/*
+ * Collision counting with a candidate cap (Section 2.4, after C2LSH: the
+ * number of layers in which a point shares the query's bucket is counted, a
+ * threshold on that count replaces the plain union, and at most k + v points
+ * -- the K results plus v allowed false positives -- are verified).
+ *  threshold 0 (default): the plain union of Section 1.2;
+ *  threshold t in 1..L: #Col(p) = #{ l : key_l(p) == key_l(q) }; the points
+ *      with #Col(p) >= t, ranked by (#Col descending, id ascending), are
+ *      verified up to the first K + extra of them, and the top K of those by
+ *      (distance, id) is returned (padded as on the plain path).  A layer of
+ *      one function (k = 1) is C2LSH's single collision test.
+ * extra >= 0 is v.  qw_query_workload then answers with both forms (the form
+ * only chooses the hashing) through one kernel that holds a query's counts in
+ * LDS; it needs neighbour probing off, K + extra <= 1024 and at most 12288
+ * listed ids (the sum of a query's L bucket sizes) per query, else it returns
+ * QW_EUNSUPPORTED with the outputs untouched (the check synchronises the
+ * stream).  qw_stats then reports the verified points as cand_unique.
+ * QW_EINVAL for a threshold outside 0..L or a negative extra.  Not to be
+ * called while work on the index is in flight.
+ */
+qw_status qw_set_counting(qw_index *ix, int32_t threshold, int32_t extra);
 
 #ifdef __cplusplus
 }

@@ -285,6 +285,46 @@ qw_status verify_simple(qw_index *ix, int64_t Q, int K, int mode, hipStream_t s,
     return launch_verify(a, grid, s);
 }
 
+// Collision counting: one set size for all queries (from the largest list
+// total), one workgroup per query.  Checks the limits before anything is
+// written to the outputs; syncs.
+qw_status count_query(qw_index *ix, int64_t Q, int K, hipStream_t s, int32_t *out_ids,
+                      void *out_dist, hipEvent_t ev_sched)
+{
+    if (ix->nprobe != 1 || K + ix->count_extra > kMaxTopK) return QW_EUNSUPPORTED;
+    uint32_t *mx = c32(ix) + W_MAX;
+    QW_TRY(launch_fill_u32(mx, 0u, 1, s));
+    QW_TRY(launch_max_bucket_sum(ix->ws.bsize.as<uint32_t>(), Q, ix->L, mx, s));
+    uint32_t maxsum = 0;
+    QW_HIP(hipMemcpyAsync(&maxsum, mx, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    QW_HIP(hipStreamSynchronize(s));
+    if (ev_sched) QW_HIP(hipEventRecord(ev_sched, s));
+    if (maxsum > kCountMaxListed) return QW_EUNSUPPORTED;
+    int cap = 8;
+    while ((3ull << cap) < 4ull * maxsum) ++cap;  // load factor <= 3/4
+    CountArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.bstart = ix->ws.bstart.as<uint32_t>();
+    a.bsize = ix->ws.bsize.as<uint32_t>();
+    a.ids = ix->ids.as<int32_t>();
+    a.n = ix->n;
+    a.L = ix->L;
+    a.theta = ix->count_theta;
+    a.K = K;
+    a.extra = ix->count_extra;
+    a.ncap = (K + ix->count_extra + 1) & ~1;
+    a.dtype = ix->dtype;
+    a.dp = ix->dp;
+    a.cap_log2 = (uint32_t)cap;
+    a.data = ix->data.p;
+    a.queries = ix->ws.qrows;
+    a.out_ids = out_ids;
+    a.out_dist = out_dist;
+    a.out_counts = ix->ws.ucount.as<uint32_t>();
+    if (cap > kCountMaxSetLog2 || count_lds_bytes(cap, a.ncap) > ix->lds_max) return QW_EUNSUPPORTED;
+    return launch_count(a, Q, s);
+}
+
 qw_status check_index(const qw_index *ix)
 {
     if (!ix) return QW_EINVAL;
@@ -633,6 +673,8 @@ qw_status qw_get_index_info(const qw_index *ix, qw_index_info *info)
     info->count_margin = ix->mlp_margin;
     info->probing = ix->probe_mode;
     info->probes_per_layer = ix->nprobe - 1;
+    info->count_threshold = ix->count_theta;
+    info->count_extra = ix->count_extra;
     return QW_OK;
 }
 
@@ -656,6 +698,21 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
     hipStream_t s = S(stream);
     try {
         if (opt.timing) QW_TRY(ensure_events(ix));
+        if (ix->count_theta > 0) {  // collision counting, either form's hashing
+            QW_TRY(ensure_ws(ix, Q, nullptr));
+            hipEvent_t *ev = opt.timing ? ix->ev : nullptr;
+            if (ev) QW_HIP(hipEventRecord(ev[0], s));
+            QW_TRY(clear_counters(ix, s));
+            QW_TRY(front(ix, queries, Q, opt.form, s, ev));
+            if (ev) QW_HIP(hipEventRecord(ev[2], s));
+            QW_TRY(count_query(ix, Q, K, s, out_ids, out_dist, ev ? ev[3] : nullptr));
+            if (ev) {
+                QW_HIP(hipEventRecord(ev[4], s));
+                QW_HIP(hipEventRecord(ev[5], s));
+            }
+            if (st) QW_TRY(fill_stats(ix, Q, s, st, ev, false));
+            return QW_OK;
+        }
         if (opt.form == QW_FORM_PLAIN_FP32) {
             QW_TRY(ensure_ws(ix, Q, nullptr));
             hipEvent_t *ev = opt.timing ? ix->ev : nullptr;
@@ -894,6 +951,15 @@ qw_status qw_set_probing(qw_index *ix, int32_t mode, int32_t per_layer)
     ix->nl = ix->L * P;
     ix->pmagic = magic;
     ix->mlp.clear();
+    return QW_OK;
+}
+
+qw_status qw_set_counting(qw_index *ix, int32_t threshold, int32_t extra)
+{
+    QW_TRY(check_index(ix));
+    if (threshold < 0 || threshold > ix->L || extra < 0) return QW_EINVAL;
+    ix->count_theta = threshold;
+    ix->count_extra = threshold ? extra : 0;
     return QW_OK;
 }
 

@@ -1,0 +1,240 @@
+// Collision counting with a candidate cap (Section 2.4, after C2LSH): every
+// layer of the index is one collision test, a point is a candidate when it
+// shares the query's bucket in at least theta layers, and at most K + v of the
+// candidates are verified -- the K results plus v allowed false positives --
+// namely the first K + v by (layer count descending, id ascending).  The
+// verified points then give the top K by (distance, id) as on the plain path.
+//
+// One workgroup per query, all state in LDS:
+//   1. the query's L bucket lists go into an open-addressing set of 2^c slots
+//      (ids) with a byte counter beside every slot (counts <= L <= 64);
+//   2. a histogram of the counts >= theta gives the count c* at which the
+//      ranking crosses K + v: every id counted above c* is kept, and of the
+//      ids counted exactly c* the `need` smallest, found by a 4-pass radix
+//      select on the id bytes (ids are distinct in the set);
+//   3. the kept ids are verified (uint8: exact integer; float: the FP64
+//      rounded sequence of the plain path) and ranked by (distance, id) by
+//      counting, for each one, the kept ids before it.
+#include "qw_dedup.h"
+#include "qw_dist.h"
+#include "qw_exact.h"
+
+namespace qw {
+
+namespace {
+
+constexpr int kHistBins = kMaxL + 2;
+
+struct CountLayout {
+    size_t tab, cw, cid, ckey, hist, radix, scal, total;
+};
+
+__host__ __device__ inline CountLayout count_layout(int cap_log2, int ncap)
+{
+    CountLayout o;
+    const size_t cap = size_t(1) << cap_log2;
+    o.tab = 0;
+    o.cw = o.tab + cap * 4;
+    o.cid = o.cw + cap;                       // one count byte per slot
+    o.ckey = o.cid + size_t(ncap) * 4;        // ncap even: 8-byte aligned
+    o.hist = o.ckey + size_t(ncap) * 8;
+    o.radix = o.hist + kHistBins * 4;
+    o.scal = o.radix + 256 * 4;
+    o.total = o.scal + 8 * 4;
+    return o;
+}
+
+enum { SC_CSTAR = 0, SC_NEED, SC_PREFIX, SC_REM, SC_NCAND };
+
+__device__ inline uint32_t slot_count(const uint32_t *cw, uint32_t s)
+{
+    return (cw[s >> 2] >> ((s & 3u) * 8u)) & 0xFFu;
+}
+
+template <int DT>
+__global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    const CountLayout lay = count_layout((int)A.cap_log2, A.ncap);
+    uint32_t *tab = reinterpret_cast<uint32_t *>(smem + lay.tab);
+    uint32_t *cw = reinterpret_cast<uint32_t *>(smem + lay.cw);
+    uint32_t *cid = reinterpret_cast<uint32_t *>(smem + lay.cid);
+    uint64_t *ckey = reinterpret_cast<uint64_t *>(smem + lay.ckey);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(smem + lay.hist);
+    uint32_t *radix = reinterpret_cast<uint32_t *>(smem + lay.radix);
+    uint32_t *scal = reinterpret_cast<uint32_t *>(smem + lay.scal);
+
+    const int tid = threadIdx.x;
+    const int64_t q = blockIdx.x;
+    const int c = (int)A.cap_log2;
+    const uint32_t cap = 1u << c, mask = cap - 1u;
+
+    for (uint32_t s = tid; s < cap; s += kBlock) tab[s] = kEmpty;
+    for (uint32_t s = tid; s < cap / 4; s += kBlock) cw[s] = 0u;
+    for (int s = tid; s < kHistBins; s += kBlock) hist[s] = 0u;
+    if (tid == 0) scal[SC_NCAND] = 0u;
+    __syncthreads();
+
+    // 1. count: one insert per listed id (a point lies in one bucket per layer)
+    for (int l = 0; l < A.L; ++l) {
+        const uint32_t start = A.bstart[q * A.L + l], size = A.bsize[q * A.L + l];
+        const int32_t *lst = A.ids + (int64_t)l * A.n + start;
+        for (uint32_t i = tid; i < size; i += kBlock) {
+            const uint32_t id = (uint32_t)lst[i];
+            uint32_t h = hash_id(id, c);
+            const uint32_t step = hash_step(id, c);
+            // the set holds at most 3/4 of its slots (checked by the host), so
+            // some slot of the odd-step sequence is free or holds the id
+            for (uint32_t t = 0; t < cap; ++t) {
+                const uint32_t prev = atomicCAS(&tab[h], kEmpty, id);
+                if (prev == kEmpty || prev == id) {
+                    atomicAdd(&cw[h >> 2], 1u << ((h & 3u) * 8u));
+                    break;
+                }
+                h = (h + step) & mask;
+            }
+        }
+    }
+    __syncthreads();
+
+    // 2. counts >= theta, the crossing count c* and how many ids it contributes
+    for (uint32_t s = tid; s < cap; s += kBlock)
+        if (tab[s] != kEmpty) {
+            const uint32_t k = slot_count(cw, s);
+            if (k >= (uint32_t)A.theta) atomicAdd(&hist[k], 1u);
+        }
+    __syncthreads();
+    if (tid == 0) {
+        const uint32_t capn = (uint32_t)(A.K + A.extra);
+        uint32_t cum = 0, cstar = (uint32_t)A.theta, need = hist[A.theta];
+        for (int k = A.L; k >= A.theta; --k) {
+            if (cum + hist[k] >= capn) {
+                cstar = (uint32_t)k;
+                need = capn - cum;
+                break;
+            }
+            cum += hist[k];
+        }
+        scal[SC_CSTAR] = cstar;
+        scal[SC_NEED] = need;
+        scal[SC_PREFIX] = 0u;
+        scal[SC_REM] = need;
+    }
+    __syncthreads();
+    const uint32_t cstar = scal[SC_CSTAR];
+    uint32_t last = 0xFFFFFFFFu;  // largest id kept among those counted c*
+    if (scal[SC_NEED] < hist[cstar]) {
+        // the need-th smallest id counted exactly c*, one byte per pass (MSB first)
+        for (int shift = 24; shift >= 0; shift -= 8) {
+            for (int b = tid; b < 256; b += kBlock) radix[b] = 0u;
+            __syncthreads();
+            const uint32_t prefix = scal[SC_PREFIX];
+            const uint32_t hmask = shift == 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
+            for (uint32_t s = tid; s < cap; s += kBlock) {
+                const uint32_t id = tab[s];
+                if (id != kEmpty && slot_count(cw, s) == cstar && (id & hmask) == prefix)
+                    atomicAdd(&radix[(id >> shift) & 255u], 1u);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                uint32_t rem = scal[SC_REM], cum = 0;
+                for (int b = 0; b < 256; ++b) {
+                    if (cum + radix[b] >= rem) {
+                        scal[SC_PREFIX] = prefix | ((uint32_t)b << shift);
+                        scal[SC_REM] = rem - cum;
+                        break;
+                    }
+                    cum += radix[b];
+                }
+            }
+            __syncthreads();
+        }
+        last = scal[SC_PREFIX];
+    }
+
+    // kept: counted above c*, or counted c* with an id up to `last`
+    for (uint32_t s = tid; s < cap; s += kBlock) {
+        const uint32_t id = tab[s];
+        if (id == kEmpty) continue;
+        const uint32_t k = slot_count(cw, s);
+        if (k > cstar || (k == cstar && id <= last)) {
+            const uint32_t at = atomicAdd(&scal[SC_NCAND], 1u);
+            cid[at] = id;
+        }
+    }
+    __syncthreads();
+    const int nc = (int)scal[SC_NCAND];
+
+    // 3. verify the kept ids
+    for (int i = tid; i < nc; i += kBlock) {
+        const uint32_t id = cid[i];
+        if constexpr (DT == QW_U8) {
+            const uint4 *x = reinterpret_cast<const uint4 *>(static_cast<const uint8_t *>(A.data) +
+                                                             (int64_t)id * A.dp);
+            const uint4 *qv = reinterpret_cast<const uint4 *>(static_cast<const uint8_t *>(A.queries) +
+                                                              q * A.dp);
+            uint32_t acc = 0;
+            float unused = 0.f;
+            for (int p = 0; p < A.dp / 16; ++p) part_dist<QW_U8>(x[p], qv[p], acc, unused);
+            ckey[i] = ((uint64_t)acc << 32) | id;
+        } else {
+            const float *x = static_cast<const float *>(A.data) + (int64_t)id * A.dp;
+            const float *qv = static_cast<const float *>(A.queries) + q * A.dp;
+            ckey[i] = (uint64_t)__double_as_longlong(exact_dist_row(x, qv, A.dp));
+        }
+    }
+    __syncthreads();
+    // rank of each kept id under (distance, id); the keys are distinct
+    for (int i = tid; i < nc; i += kBlock) {
+        const uint64_t ki = ckey[i];
+        const uint32_t ii = cid[i];
+        int r = 0;
+        for (int j = 0; j < nc; ++j) {
+            const uint64_t kj = ckey[j];
+            if constexpr (DT == QW_U8) {
+                r += kj < ki;
+            } else {  // non-negative FP64 bit patterns order as the values do
+                r += kj < ki || (kj == ki && cid[j] < ii);
+            }
+        }
+        if (r < A.K) {
+            const int64_t o = q * A.K + r;
+            A.out_ids[o] = (int32_t)ii;
+            if constexpr (DT == QW_U8)
+                reinterpret_cast<int32_t *>(A.out_dist)[o] = (int32_t)(ki >> 32);
+            else
+                reinterpret_cast<float *>(A.out_dist)[o] = (float)__longlong_as_double((long long)ki);
+        }
+    }
+    for (int r = nc + tid; r < A.K; r += kBlock) {
+        const int64_t o = q * A.K + r;
+        A.out_ids[o] = -1;
+        if constexpr (DT == QW_U8)
+            reinterpret_cast<int32_t *>(A.out_dist)[o] = INT32_MAX;
+        else
+            reinterpret_cast<float *>(A.out_dist)[o] = INFINITY;
+    }
+    if (tid == 0 && A.out_counts) A.out_counts[q] = (uint32_t)nc;
+}
+
+}  // namespace
+
+size_t count_lds_bytes(int cap_log2, int ncap) { return count_layout(cap_log2, ncap).total; }
+
+qw_status launch_count(const CountArgs &a, int64_t Q, hipStream_t s)
+{
+    if (Q <= 0) return QW_OK;
+    if (a.L < 1 || a.L > kMaxL || a.theta < 1 || a.theta > a.L || a.K < 1 || a.extra < 0 ||
+        a.K + a.extra > a.ncap || (a.ncap & 1) || a.cap_log2 < 4 || a.cap_log2 > 16 ||
+        Q > 0x7FFFFFFF)
+        return QW_EINTERNAL;
+    const size_t lds = count_lds_bytes((int)a.cap_log2, a.ncap);
+    if (a.dtype == QW_U8)
+        count_kernel<QW_U8><<<(unsigned)Q, kBlock, lds, s>>>(a);
+    else
+        count_kernel<QW_F32><<<(unsigned)Q, kBlock, lds, s>>>(a);
+    QW_HIP(hipGetLastError());
+    return QW_OK;
+}
+
+}  // namespace qw

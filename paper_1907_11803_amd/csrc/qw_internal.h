@@ -144,6 +144,7 @@ struct qw_index {
     // query (L * nprobe) and the layer-of-list multiplier (0 without probing)
     int32_t nprobe = 1, nl = 0;
     uint32_t pmagic = 0;
+    int32_t count_theta = 0, count_extra = 0;  // qw_set_counting: 0 = plain union
     int32_t probe_mode = 0;  // qw_set_probing mode: 2 = query-directed (nprobe - 1 moves)
     float w = 0.f;
     // hash parameters (device)
@@ -269,6 +270,27 @@ struct VerifyArgs {
     const long long *offsets;    // LIST
     uint32_t *ucount_out;        // nullable: |C(q)| of each answered query
 };
+
+// Collision counting (one workgroup per query; plain layer lists, no probing).
+struct CountArgs {
+    const uint32_t *bstart, *bsize;  // [Q][L] bucket lists (layer-relative starts)
+    const int32_t *ids;
+    int64_t n;
+    int32_t L, theta, K, extra;      // count threshold; K + extra ids verified at most
+    int32_t ncap;                    // kept-id buffer entries (even, >= K + extra)
+    int32_t dtype, dp;
+    uint32_t cap_log2;               // set slots 2^cap_log2, at least 4/3 of the listed ids
+    const void *data, *queries;
+    int32_t *out_ids;                // [Q][K]
+    void *out_dist;                  // [Q][K] int32 (uint8 data) or float
+    uint32_t *out_counts;            // nullable: [Q] ids verified
+};
+size_t count_lds_bytes(int cap_log2, int ncap);
+qw_status launch_count(const CountArgs &a, int64_t Q, hipStream_t s);
+// Largest sum of one query's L list lengths the counting set takes (3/4 of
+// the largest set, 2^14 slots).
+constexpr uint32_t kCountMaxListed = 12288;
+constexpr int kCountMaxSetLog2 = 14;
 
 size_t verify_lds_bytes(int cap_log2, int buf, int global_tab, int L, int dp, int dtype);
 qw_status launch_verify(const VerifyArgs &a, int grid, hipStream_t s);

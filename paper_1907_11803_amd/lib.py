@@ -60,7 +60,8 @@ class qw_index_info(ctypes.Structure):
                 ("key_bits", ctypes.c_int32 * 64), ("buckets", ctypes.c_int64),
                 ("max_bucket", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("has_count_model", ctypes.c_int32), ("count_margin", ctypes.c_float),
-                ("probing", ctypes.c_int32), ("probes_per_layer", ctypes.c_int32)]
+                ("probing", ctypes.c_int32), ("probes_per_layer", ctypes.c_int32),
+                ("count_threshold", ctypes.c_int32), ("count_extra", ctypes.c_int32)]
 
 
 # exported symbols and their signatures (restype qw_status unless noted)
@@ -86,6 +87,7 @@ SIGNATURES = {
     "qw_get_count_model": (ctypes.c_int, [_P, _P, _I32]),
     "qw_set_count_margin": (ctypes.c_int, [_P, ctypes.c_float]),
     "qw_set_probing": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
+    "qw_set_counting": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
 }
 
 _lib = None
@@ -309,6 +311,10 @@ def qw_set_probing(ix, mode: int, per_layer: int = 0):
     _check(load().qw_set_probing(ix, int(mode), int(per_layer)), "qw_set_probing")
 
 
+def qw_set_counting(ix, threshold: int, extra: int = 0):
+    _check(load().qw_set_counting(ix, int(threshold), int(extra)), "qw_set_counting")
+
+
 def qw_get_count_model(ix, L: int) -> np.ndarray:
     p = np.empty(qw_mlp_param_count(L), dtype=np.float32)
     _check(load().qw_get_count_model(ix, ctypes.c_void_p(p.ctypes.data), p.size), "qw_get_count_model")
@@ -360,6 +366,11 @@ class Index:
 
     def set_probing(self, mode: int, per_layer: int = 0):
         qw_set_probing(self.handle, mode, per_layer)
+
+    def set_counting(self, threshold: int, extra: int = 0):
+        """Collision counting: threshold on the layers shared with the query
+        (0: the plain union), at most K + extra points verified."""
+        qw_set_counting(self.handle, threshold, extra)
 
     def info(self) -> dict:
         return qw_get_index_info(self.handle)

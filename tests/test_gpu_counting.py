@@ -1,0 +1,128 @@
+"""GPU parity of collision counting with a candidate cap (Section 2.4): the
+points found in at least theta of the query's layer buckets, ranked by (count
+descending, id ascending), the first K + v verified, the top K returned.  Ids
+and uint8 distances bit-exact against the CPU oracle, float distances within
+1e-5 relative of its FP64 values."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1907_11803_amd import lib, synth
+
+pytestmark = pytest.mark.gpu
+
+I32MAX = np.iinfo(np.int32).max
+FORMS = [lib.QW_FORM_PLAIN_FP32, lib.QW_FORM_FAST]
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def check(ids_g, dist_g, ids_o, dist_o, is_u8):
+    ids_g = ids_g.cpu().numpy()
+    dist_g = dist_g.cpu().numpy()
+    assert np.array_equal(ids_g, ids_o), np.argwhere(ids_g != ids_o)[:5]
+    if is_u8:
+        want = np.where(dist_o == np.iinfo(np.int64).max, I32MAX, dist_o)
+        assert np.array_equal(dist_g.astype(np.int64), want.astype(np.int64))
+    else:
+        fin = np.isfinite(dist_o)
+        assert np.array_equal(np.isfinite(dist_g), fin)
+        np.testing.assert_allclose(dist_g[fin], dist_o[fin], rtol=1e-5, atol=0)
+
+
+def run_case(wl, w, K, cases, is_u8):
+    p = wl.params
+    ix = lib.Index(dev(wl.data), dev(p.a), dev(p.b(w)), w)
+    q = dev(wl.queries)
+    for theta, v in cases:
+        ix.set_counting(theta, v)
+        info = ix.info()
+        assert info["count_threshold"] == theta and info["count_extra"] == v
+        ids_o, dist_o, cnt = oracle.lsh_query_counting(wl.data, wl.queries, p.a, p.b(w), w, K,
+                                                       theta, v)
+        print("counting", wl.name, "theta", theta, "v", v,
+              "verified", float(cnt.mean()), flush=True)
+        for form in FORMS:
+            ids, dist, st = ix.query(q, K, lib.make_opts(form=form), stats=True)
+            check(ids, dist, ids_o, dist_o, is_u8)
+            assert st["cand_unique"] == int(cnt.sum())
+    ix.set_counting(0)
+    ids_o, dist_o, _ = oracle.lsh_query(wl.data, wl.queries, p.a, p.b(w), w, K)
+    ids, dist = ix.query(q, K)
+    check(ids, dist, ids_o, dist_o, is_u8)  # the plain union again
+    ix.close()
+
+
+def test_counting_cfg1_layers():
+    """cfg1's layers (L = 10, k = 8, w = 1200): caps that bind on every query
+    (ties at the crossing count go to the smaller ids) and a threshold-1
+    uncapped case equal to the plain union."""
+    wl = synth.make_config(1)
+    run_case(wl, 1200.0, wl.K, [(1, 0), (2, 5), (3, 1000), (1, 1000)], True)
+    ids_o, dist_o, _ = oracle.lsh_query(wl.data, wl.queries, wl.params.a, wl.params.b(1200.0),
+                                        1200.0, wl.K)
+    ids_c, dist_c, _ = oracle.lsh_query_counting(wl.data, wl.queries, wl.params.a,
+                                                 wl.params.b(1200.0), 1200.0, wl.K, 1, 1000)
+    assert np.array_equal(ids_o, ids_c)
+
+
+def test_counting_single_function_layers():
+    """C2LSH's setting: 32 layers of one function each (k = 1, w = 80), about
+    9,000 listed ids per query, thresholds 2-6 and caps 10-110."""
+    wl = synth.make_config(1, L=32, k=1, w=80.0)
+    run_case(wl, 80.0, wl.K, [(2, 0), (2, 20), (4, 100), (6, 100)], True)
+
+
+def test_counting_large_K_and_K1():
+    wl = synth.make_config(1, L=32, k=1, w=80.0)
+    run_case(wl, 80.0, 64, [(2, 300), (3, 0)], True)
+    run_case(wl, 80.0, 1, [(2, 0), (5, 7)], True)
+
+
+def test_counting_float():
+    wl = synth.make_config(3, n=6000, Q=60, ncomp=30, w=10.0)
+    run_case(wl, 10.0, wl.K, [(2, 50), (1, 5), (4, 0)], False)
+
+
+def test_counting_limits_leave_outputs_untouched():
+    """More than 12288 listed ids for some query (48 single-function layers at
+    w = 60 list up to 12328), neighbour probing, K + v above 1024: the call
+    fails with QW_EUNSUPPORTED before writing anything."""
+    wl = synth.make_config(1, L=48, k=1, w=60.0)
+    p = wl.params
+    ix = lib.Index(dev(wl.data), dev(p.a), dev(p.b(60.0)), 60.0)
+    q = dev(wl.queries)
+    ids = torch.full((wl.queries.shape[0], 10), -7, dtype=torch.int32, device="cuda")
+    dist = torch.full_like(ids, -7)
+    ix.set_counting(2, 10)
+    with pytest.raises(lib.QwError) as e:
+        ix.query(q, 10, out_ids=ids, out_dist=dist)
+    assert e.value.status == lib.QW_EUNSUPPORTED
+    torch.cuda.synchronize()
+    assert bool((ids == -7).all()) and bool((dist == -7).all())
+    with pytest.raises(lib.QwError) as e:
+        ix.set_counting(49, 0)
+    assert e.value.status == lib.QW_EINVAL
+    ix.close()
+    wl = synth.make_config(1)
+    p = wl.params
+    ix = lib.Index(dev(wl.data), dev(p.a), dev(p.b(1200.0)), 1200.0)
+    q = dev(wl.queries)
+    ix.set_counting(2, 1020)
+    with pytest.raises(lib.QwError) as e:
+        ix.query(q, 10)
+    assert e.value.status == lib.QW_EUNSUPPORTED
+    ix.set_counting(2, 10)
+    ix.set_probing(1)
+    with pytest.raises(lib.QwError) as e:
+        ix.query(q, 10)
+    assert e.value.status == lib.QW_EUNSUPPORTED
+    ix.set_probing(0)
+    ids, dist = ix.query(q, 10)
+    ids_o, dist_o, _ = oracle.lsh_query_counting(wl.data, wl.queries, p.a, p.b(1200.0), 1200.0,
+                                                 10, 2, 10)
+    check(ids, dist, ids_o, dist_o, True)
+    ix.close()

@@ -72,6 +72,7 @@ def test_validation_rejects_before_device_work(so):
     assert so.qw_set_count_model(None, None, 0) == lib.QW_EINVAL
     assert so.qw_set_count_margin(None, 0.5) == lib.QW_EINVAL
     assert so.qw_set_probing(None, 1, 0) == lib.QW_EINVAL
+    assert so.qw_set_counting(None, 1, 0) == lib.QW_EINVAL
     assert so.qw_mlp_loss_grad(None, 4, None, None, 1, None, None, None) == lib.QW_EINVAL
     so.qw_free_index(None)  # no-op
 
