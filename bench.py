@@ -88,6 +88,11 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="oracle query sample (0 = up to 10,000 uint8 / 1,000 float queries)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--count-theta", type=int, default=None,
+                    help="collision-counting leg: threshold on shared layers (0: skip; "
+                         "default 3 for config 2, else 0)")
+    ap.add_argument("--count-v", type=int, default=800,
+                    help="collision-counting leg: extra verified points v (K + v in all)")
     ap.add_argument("--profile", action="store_true",
                     help="only the fast-form timed loop (for rocprofv3 runs)")
     args = ap.parse_args()
@@ -187,15 +192,16 @@ def main():
     out_dist = torch.empty((wl.Q, K), dtype=torch.int32 if is_u8 else torch.float32, device=dev)
     stream = torch.cuda.current_stream()
 
-    def timed(opts, steps, warmup):
+    def timed(opts, steps, warmup, index=None):
+        index = index or ix
         for _ in range(warmup):
-            ix.query(q_d, K, opts, out_ids=out_ids, out_dist=out_dist)
+            index.query(q_d, K, opts, out_ids=out_ids, out_dist=out_dist)
         torch.cuda.synchronize()
         start = torch.cuda.Event(enable_timing=True)
         stop = torch.cuda.Event(enable_timing=True)
         start.record(stream)
         for _ in range(steps):
-            ix.query(q_d, K, opts, out_ids=out_ids, out_dist=out_dist)
+            index.query(q_d, K, opts, out_ids=out_ids, out_dist=out_dist)
         stop.record(stream)
         torch.cuda.synchronize()
         return start.elapsed_time(stop) / steps
@@ -327,6 +333,65 @@ def main():
                "matches_gpu": cpu_match}
         log(f"[bench] oracle: {cpu['value']} q/s on {nthreads} threads (build {build_cpu:.1f}s)")
 
+    # ---- collision counting with a candidate cap (Section 2.4) on an index of
+    # 64 layers over the same data and queries: the points sharing the query's
+    # bucket in at least theta layers, ranked by (count desc, id asc), K + v of
+    # them verified; beside it the plain union on that index.  Its kernel's
+    # algorithmic bytes: the listed ids (4 each), the verified rows, the query
+    # rows and the K output pairs.
+    counting = None
+    count_theta = args.count_theta if args.count_theta is not None else (3 if args.config == 2 else 0)
+    if count_theta > 0:
+        cL, cw = 64, 2.5 * spec["w"]
+        cp = synth.hash_params(2100 + args.config, cL, wl.params.k, wl.d, cw)
+        cix = lib.Index(data_d, torch.from_numpy(cp.a).to(dev), torch.from_numpy(cp.b()).to(dev),
+                        cw, form=lib.QW_FORM_FAST)
+        try:
+            cix.set_counting(count_theta, args.count_v)
+            max_listed = int(cix.bucket_sizes(q_d).to(torch.int64).sum(1).max())
+            copts = lib.make_opts(form=lib.QW_FORM_FAST, graph=0)
+            c_ids, c_dist, cst = cix.query(q_d, K, copts, stats=True)
+            c_ids, c_dist = c_ids.cpu().numpy(), c_dist.cpu().numpy()
+            crec = recall_at_10(c_ids[rsel], truth[0], c_dist[rsel], truth[1])
+            p_ids, p_dist = cix.query(q_d, K, lib.make_opts(form=lib.QW_FORM_PLAIN_FP32))
+            c_same = bool(np.array_equal(p_ids.cpu().numpy(), c_ids) and
+                          np.array_equal(p_dist.cpu().numpy(), c_dist))
+            cms = timed(copts, args.steps, args.warmup, cix)
+            kms_c = 0.0
+            for _ in range(nrep):
+                _, _, cs = cix.query(q_d, K, lib.make_opts(timing=1, graph=0), out_ids=out_ids,
+                                     out_dist=out_dist, stats=True)
+                kms_c += cs["ms_stage"][3] / nrep
+            cbytes = (4 * cst["cand_total"] + cst["cand_unique"] * wl.d * elem + wl.Q * wl.d * elem
+                      + 8 * K * wl.Q)
+            cix.set_counting(0)
+            u_ids, u_dist, ust = cix.query(q_d, K, fast_opts, stats=True)
+            urec = recall_at_10(u_ids.cpu().numpy()[rsel], truth[0], u_dist.cpu().numpy()[rsel],
+                                truth[1])
+            ums = timed(fast_opts, args.steps, args.warmup, cix)
+            cach = cbytes / (kms_c * 1e-3) / 1e9 if kms_c > 0 else None
+            counting = {
+                "index": {"L": cL, "k": wl.params.k, "w": cw}, "theta": count_theta,
+                "v": args.count_v, "qps": round(wl.Q / (cms * 1e-3), 1),
+                "ms_per_step": round(cms, 4), "recall_at_10": round(crec, 4),
+                "verified_per_query": cst["cand_unique"] / wl.Q,
+                "listed_per_query": cst["cand_total"] / wl.Q, "max_listed": max_listed,
+                "forms_identical": c_same,
+                "kernel": {"name": "count_kernel", "ms": round(kms_c, 4),
+                           "algorithmic_bytes": int(cbytes),
+                           "achieved_gbs": round(cach, 1) if cach else None,
+                           "frac": round(cach / HBM_PEAK_GBS, 4) if cach else None},
+                "union_same_index": {"qps": round(wl.Q / (ums * 1e-3), 1),
+                                     "recall_at_10": round(urec, 4),
+                                     "unique_per_query": ust["cand_unique"] / wl.Q},
+            }
+            log(f"[bench] counting theta={count_theta} v={args.count_v}: {cms:.3f} ms/step, "
+                f"recall {crec:.4f}, kernel {kms_c:.3f} ms; union on that index {ums:.3f} ms, "
+                f"recall {urec:.4f}")
+        except lib.QwError as e:
+            counting = {"error": str(e)}
+        cix.close()
+
     # hashing (A1-A2): algorithmic projection flops against the dense MFMA peak
     # of the type the kernel multiplies in (FP16 for uint8 data, FP32 for float)
     hash_flops = 2.0 * wl.d * L * wl.params.k * wl.Q
@@ -370,6 +435,7 @@ def main():
         "forms_identical": identical,
         "sched_ms_per_step": sched_ms,
         "sched_identical": sched_identical,
+        "collision_counting": counting,
         "stage_ms": {"hash": round(stage[0], 4), "probe": round(stage[1], 4),
                      "schedule": round(stage[2], 4), "dedup": round(stage[6], 4),
                      "select": round(stage[7], 4),

@@ -46,6 +46,17 @@ __host__ __device__ inline CountLayout count_layout(int cap_log2, int ncap)
 
 enum { SC_CSTAR = 0, SC_NEED, SC_PREFIX, SC_REM, SC_NCAND };
 
+// inclusive prefix sum over the 64 lanes of a wave
+__device__ inline uint32_t wave_inclusive_sum(uint32_t v)
+{
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_up((int)v, off);
+        if ((threadIdx.x & 63) >= (unsigned)off) v += t;
+    }
+    return v;
+}
+
 __device__ inline uint32_t slot_count(const uint32_t *cw, uint32_t s)
 {
     return (cw[s >> 2] >> ((s & 3u) * 8u)) & 0xFFu;
@@ -64,9 +75,27 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
     uint32_t *radix = reinterpret_cast<uint32_t *>(smem + lay.radix);
     uint32_t *scal = reinterpret_cast<uint32_t *>(smem + lay.scal);
 
+    __shared__ uint32_t lpref[kMaxL + 1], lstart[kMaxL];
     const int tid = threadIdx.x;
     const int64_t q = blockIdx.x;
-    const int c = (int)A.cap_log2;
+
+    // list offsets: an exclusive prefix of the L list sizes over the first wave
+    if (tid < 64) {
+        uint32_t sz = 0, st = 0;
+        if (tid < A.L) {
+            sz = A.bsize[q * A.L + tid];
+            st = A.bstart[q * A.L + tid];
+        }
+        const uint32_t inc = wave_inclusive_sum(sz);
+        lpref[tid] = inc - sz;
+        lstart[tid] = st;
+        if (tid == 63) lpref[kMaxL] = inc;
+    }
+    __syncthreads();
+    const uint32_t total = lpref[kMaxL];
+    // this query's set: at least 4/3 of its listed ids (<= the launch's size)
+    int c = 4;
+    while ((3u << c) < 4u * total && c < (int)A.cap_log2) ++c;
     const uint32_t cap = 1u << c, mask = cap - 1u;
 
     for (uint32_t s = tid; s < cap; s += kBlock) tab[s] = kEmpty;
@@ -75,19 +104,36 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
     if (tid == 0) scal[SC_NCAND] = 0u;
     __syncthreads();
 
-    // 1. count: one insert per listed id (a point lies in one bucket per layer)
-    for (int l = 0; l < A.L; ++l) {
-        const uint32_t start = A.bstart[q * A.L + l], size = A.bsize[q * A.L + l];
-        const int32_t *lst = A.ids + (int64_t)l * A.n + start;
-        for (uint32_t i = tid; i < size; i += kBlock) {
-            const uint32_t id = (uint32_t)lst[i];
-            uint32_t h = hash_id(id, c);
-            const uint32_t step = hash_step(id, c);
-            // the set holds at most 3/4 of its slots (checked by the host), so
-            // some slot of the odd-step sequence is free or holds the id
+    // 1. count: one insert per listed id (a point lies in one bucket per
+    // layer); kCountLoads positions of the concatenated lists per thread are
+    // located (binary search over the prefix) and loaded together
+    constexpr int kCountLoads = 4;
+    for (uint32_t base = 0; base < total; base += kCountLoads * kBlock) {
+        uint32_t id[kCountLoads];
+#pragma unroll
+        for (int r = 0; r < kCountLoads; ++r) {
+            const uint32_t pos = base + (uint32_t)(r * kBlock + tid);
+            id[r] = kEmpty;
+            if (pos < total) {
+                int lo = 0;  // largest layer with lpref <= pos (its list holds pos)
+#pragma unroll
+                for (int step = kMaxL / 2; step > 0; step >>= 1) {
+                    const int m = lo + step;
+                    if (m < A.L && lpref[m] <= pos) lo = m;
+                }
+                id[r] = (uint32_t)A.ids[(int64_t)lo * A.n + lstart[lo] + (pos - lpref[lo])];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kCountLoads; ++r) {
+            if (id[r] == kEmpty) continue;
+            uint32_t h = hash_id(id[r], c);
+            const uint32_t step = hash_step(id[r], c);
+            // the set holds at most 3/4 of its slots, so some slot of the
+            // odd-step sequence is free or holds the id
             for (uint32_t t = 0; t < cap; ++t) {
-                const uint32_t prev = atomicCAS(&tab[h], kEmpty, id);
-                if (prev == kEmpty || prev == id) {
+                const uint32_t prev = atomicCAS(&tab[h], kEmpty, id[r]);
+                if (prev == kEmpty || prev == id[r]) {
                     atomicAdd(&cw[h >> 2], 1u << ((h & 3u) * 8u));
                     break;
                 }
@@ -104,23 +150,26 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
             if (k >= (uint32_t)A.theta) atomicAdd(&hist[k], 1u);
         }
     __syncthreads();
-    if (tid == 0) {
+    if (tid < 64) {
+        // lane i holds the ids counted L - i (descending counts); the lane
+        // whose inclusive sum first reaches K + v holds c*
         const uint32_t capn = (uint32_t)(A.K + A.extra);
-        uint32_t cum = 0, cstar = (uint32_t)A.theta, need = hist[A.theta];
-        for (int k = A.L; k >= A.theta; --k) {
-            if (cum + hist[k] >= capn) {
-                cstar = (uint32_t)k;
-                need = capn - cum;
-                break;
-            }
-            cum += hist[k];
+        const int k = A.L - tid;
+        const uint32_t v = k >= A.theta ? hist[k] : 0u;
+        const uint32_t inc = wave_inclusive_sum(v);
+        const uint32_t excl = inc - v;
+        if (excl < capn && inc >= capn) {  // at most one lane
+            scal[SC_CSTAR] = (uint32_t)k;
+            scal[SC_NEED] = capn - excl;
         }
-        scal[SC_CSTAR] = cstar;
-        scal[SC_NEED] = need;
-        scal[SC_PREFIX] = 0u;
-        scal[SC_REM] = need;
+        if (tid == 63 && inc < capn) {  // fewer than K + v qualify: all of them
+            scal[SC_CSTAR] = (uint32_t)A.theta;
+            scal[SC_NEED] = hist[A.theta];
+        }
+        if (tid == 0) scal[SC_PREFIX] = 0u;
     }
     __syncthreads();
+    if (tid == 0) scal[SC_REM] = scal[SC_NEED];
     const uint32_t cstar = scal[SC_CSTAR];
     uint32_t last = 0xFFFFFFFFu;  // largest id kept among those counted c*
     if (scal[SC_NEED] < hist[cstar]) {
@@ -136,15 +185,19 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
                     atomicAdd(&radix[(id >> shift) & 255u], 1u);
             }
             __syncthreads();
-            if (tid == 0) {
-                uint32_t rem = scal[SC_REM], cum = 0;
-                for (int b = 0; b < 256; ++b) {
-                    if (cum + radix[b] >= rem) {
-                        scal[SC_PREFIX] = prefix | ((uint32_t)b << shift);
-                        scal[SC_REM] = rem - cum;
-                        break;
-                    }
-                    cum += radix[b];
+            if (tid < 64) {  // lane i: bins 4i..4i+3; the lane whose range reaches rem
+                const uint32_t rem = scal[SC_REM];
+                const uint32_t r0 = radix[4 * tid], r1 = radix[4 * tid + 1];
+                const uint32_t r2 = radix[4 * tid + 2], r3 = radix[4 * tid + 3];
+                const uint32_t sum = r0 + r1 + r2 + r3;
+                const uint32_t inc = wave_inclusive_sum(sum);
+                uint32_t cum = inc - sum;
+                if (cum < rem && inc >= rem) {  // exactly one lane
+                    const uint32_t rb[4] = {r0, r1, r2, r3};
+                    int b = 0;
+                    while (cum + rb[b] < rem) cum += rb[b++];
+                    scal[SC_PREFIX] = prefix | ((uint32_t)(4 * tid + b) << shift);
+                    scal[SC_REM] = rem - cum;
                 }
             }
             __syncthreads();
@@ -175,7 +228,15 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
                                                               q * A.dp);
             uint32_t acc = 0;
             float unused = 0.f;
-            for (int p = 0; p < A.dp / 16; ++p) part_dist<QW_U8>(x[p], qv[p], acc, unused);
+            const int n16 = A.dp / 16;
+            for (int p0 = 0; p0 < n16; p0 += 8) {  // eight 16-byte parts in flight
+                uint4 xv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) xv[u] = x[p0 + u < n16 ? p0 + u : n16 - 1];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (p0 + u < n16) part_dist<QW_U8>(xv[u], qv[p0 + u], acc, unused);
+            }
             ckey[i] = ((uint64_t)acc << 32) | id;
         } else {
             const float *x = static_cast<const float *>(A.data) + (int64_t)id * A.dp;
@@ -189,6 +250,7 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
         const uint64_t ki = ckey[i];
         const uint32_t ii = cid[i];
         int r = 0;
+#pragma unroll 8
         for (int j = 0; j < nc; ++j) {
             const uint64_t kj = ckey[j];
             if constexpr (DT == QW_U8) {
