@@ -26,7 +26,7 @@ namespace {
 constexpr int kHistBins = kMaxL + 2;
 
 struct CountLayout {
-    size_t tab, cw, cid, ckey, hist, radix, scal, total;
+    size_t tab, cw, cid, ckey, surv, hist, radix, scal, total;
 };
 
 __host__ __device__ inline CountLayout count_layout(int cap_log2, int ncap)
@@ -37,14 +37,15 @@ __host__ __device__ inline CountLayout count_layout(int cap_log2, int ncap)
     o.cw = o.tab + cap * 4;
     o.cid = o.cw + cap;                       // one count byte per slot
     o.ckey = o.cid + size_t(ncap) * 4;        // ncap even: 8-byte aligned
-    o.hist = o.ckey + size_t(ncap) * 8;
+    o.surv = o.ckey + size_t(ncap) * 8;
+    o.hist = o.surv + size_t(ncap) * 4;
     o.radix = o.hist + kHistBins * 4;
     o.scal = o.radix + 256 * 4;
     o.total = o.scal + 8 * 4;
     return o;
 }
 
-enum { SC_CSTAR = 0, SC_NEED, SC_PREFIX, SC_REM, SC_NCAND };
+enum { SC_CSTAR = 0, SC_NEED, SC_PREFIX, SC_REM, SC_NCAND, SC_NSURV };
 
 // inclusive prefix sum over the 64 lanes of a wave
 __device__ inline uint32_t wave_inclusive_sum(uint32_t v)
@@ -62,6 +63,62 @@ __device__ inline uint32_t slot_count(const uint32_t *cw, uint32_t s)
     return (cw[s >> 2] >> ((s & 3u) * 8u)) & 0xFFu;
 }
 
+// Whole workgroup.  Among the items i < nitems with pred(i), the need-th
+// smallest of the 32-bit values val(i) (1 <= need <= that many items), one
+// byte per pass, most significant first: each pass counts the values that
+// share the bytes chosen so far in 256 bins, and the first wave finds the bin
+// in which the count reaches the rank still wanted.
+template <typename Val, typename Pred>
+__device__ inline uint32_t block_select(uint32_t nitems, uint32_t need, Val val, Pred pred,
+                                        uint32_t *radix, uint32_t *scal)
+{
+    const int tid = threadIdx.x;
+    __syncthreads();  // earlier readers of scal are done
+    if (tid == 0) {
+        scal[SC_PREFIX] = 0u;
+        scal[SC_REM] = need;
+    }
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        for (int b = tid; b < 256; b += kBlock) radix[b] = 0u;
+        __syncthreads();
+        const uint32_t prefix = scal[SC_PREFIX];
+        const uint32_t hmask = shift == 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
+        for (uint32_t i = tid; i < nitems; i += kBlock)
+            if (pred(i)) {
+                const uint32_t v = val(i);
+                if ((v & hmask) == prefix) atomicAdd(&radix[(v >> shift) & 255u], 1u);
+            }
+        __syncthreads();
+        if (tid < 64) {  // lane i: bins 4i..4i+3; the lane whose range reaches rem
+            const uint32_t rem = scal[SC_REM];
+            const uint32_t r0 = radix[4 * tid], r1 = radix[4 * tid + 1];
+            const uint32_t r2 = radix[4 * tid + 2], r3 = radix[4 * tid + 3];
+            const uint32_t sum = r0 + r1 + r2 + r3;
+            const uint32_t inc = wave_inclusive_sum(sum);
+            uint32_t cum = inc - sum;
+            if (cum < rem && inc >= rem) {  // exactly one lane
+                uint32_t b = 0;
+                if (cum + r0 < rem) {
+                    cum += r0;
+                    b = 1;
+                    if (cum + r1 < rem) {
+                        cum += r1;
+                        b = 2;
+                        if (cum + r2 < rem) {
+                            cum += r2;
+                            b = 3;
+                        }
+                    }
+                }
+                scal[SC_PREFIX] = prefix | ((4u * (uint32_t)tid + b) << shift);
+                scal[SC_REM] = rem - cum;
+            }
+        }
+        __syncthreads();
+    }
+    return scal[SC_PREFIX];
+}
+
 template <int DT>
 __global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
 {
@@ -71,6 +128,7 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
     uint32_t *cw = reinterpret_cast<uint32_t *>(smem + lay.cw);
     uint32_t *cid = reinterpret_cast<uint32_t *>(smem + lay.cid);
     uint64_t *ckey = reinterpret_cast<uint64_t *>(smem + lay.ckey);
+    uint32_t *surv = reinterpret_cast<uint32_t *>(smem + lay.surv);
     uint32_t *hist = reinterpret_cast<uint32_t *>(smem + lay.hist);
     uint32_t *radix = reinterpret_cast<uint32_t *>(smem + lay.radix);
     uint32_t *scal = reinterpret_cast<uint32_t *>(smem + lay.scal);
@@ -166,44 +224,14 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
             scal[SC_CSTAR] = (uint32_t)A.theta;
             scal[SC_NEED] = hist[A.theta];
         }
-        if (tid == 0) scal[SC_PREFIX] = 0u;
     }
     __syncthreads();
-    if (tid == 0) scal[SC_REM] = scal[SC_NEED];
     const uint32_t cstar = scal[SC_CSTAR];
     uint32_t last = 0xFFFFFFFFu;  // largest id kept among those counted c*
-    if (scal[SC_NEED] < hist[cstar]) {
-        // the need-th smallest id counted exactly c*, one byte per pass (MSB first)
-        for (int shift = 24; shift >= 0; shift -= 8) {
-            for (int b = tid; b < 256; b += kBlock) radix[b] = 0u;
-            __syncthreads();
-            const uint32_t prefix = scal[SC_PREFIX];
-            const uint32_t hmask = shift == 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
-            for (uint32_t s = tid; s < cap; s += kBlock) {
-                const uint32_t id = tab[s];
-                if (id != kEmpty && slot_count(cw, s) == cstar && (id & hmask) == prefix)
-                    atomicAdd(&radix[(id >> shift) & 255u], 1u);
-            }
-            __syncthreads();
-            if (tid < 64) {  // lane i: bins 4i..4i+3; the lane whose range reaches rem
-                const uint32_t rem = scal[SC_REM];
-                const uint32_t r0 = radix[4 * tid], r1 = radix[4 * tid + 1];
-                const uint32_t r2 = radix[4 * tid + 2], r3 = radix[4 * tid + 3];
-                const uint32_t sum = r0 + r1 + r2 + r3;
-                const uint32_t inc = wave_inclusive_sum(sum);
-                uint32_t cum = inc - sum;
-                if (cum < rem && inc >= rem) {  // exactly one lane
-                    const uint32_t rb[4] = {r0, r1, r2, r3};
-                    int b = 0;
-                    while (cum + rb[b] < rem) cum += rb[b++];
-                    scal[SC_PREFIX] = prefix | ((uint32_t)(4 * tid + b) << shift);
-                    scal[SC_REM] = rem - cum;
-                }
-            }
-            __syncthreads();
-        }
-        last = scal[SC_PREFIX];
-    }
+    if (scal[SC_NEED] < hist[cstar])  // the need-th smallest id counted exactly c*
+        last = block_select(
+            cap, scal[SC_NEED], [&](uint32_t s) { return tab[s]; },
+            [&](uint32_t s) { return tab[s] != kEmpty && slot_count(cw, s) == cstar; }, radix, scal);
 
     // kept: counted above c*, or counted c* with an id up to `last`
     for (uint32_t s = tid; s < cap; s += kBlock) {
@@ -245,13 +273,29 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
         }
     }
     __syncthreads();
-    // rank of each kept id under (distance, id); the keys are distinct
-    for (int i = tid; i < nc; i += kBlock) {
+    // the K-th smallest high word of the keys (uint8: the distance; float: the
+    // high word of the non-negative FP64 distance, which orders as the value
+    // does): a key with a larger high word is not in the top K
+    uint32_t hbound = 0xFFFFFFFFu;
+    if (nc > A.K)
+        hbound = block_select(
+            (uint32_t)nc, (uint32_t)A.K, [&](uint32_t i) { return (uint32_t)(ckey[i] >> 32); },
+            [&](uint32_t) { return true; }, radix, scal);
+    if (tid == 0) scal[SC_NSURV] = 0u;
+    __syncthreads();
+    for (int i = tid; i < nc; i += kBlock)
+        if ((uint32_t)(ckey[i] >> 32) <= hbound) surv[atomicAdd(&scal[SC_NSURV], 1u)] = (uint32_t)i;
+    __syncthreads();
+    const int ns = (int)scal[SC_NSURV];
+    // rank of each survivor under (distance, id) among the survivors (at least
+    // K of them; every key of the top K is one); the keys are distinct
+    for (int a = tid; a < ns; a += kBlock) {
+        const uint32_t i = surv[a];
         const uint64_t ki = ckey[i];
         const uint32_t ii = cid[i];
         int r = 0;
-#pragma unroll 8
-        for (int j = 0; j < nc; ++j) {
+        for (int b = 0; b < ns; ++b) {
+            const uint32_t j = surv[b];
             const uint64_t kj = ckey[j];
             if constexpr (DT == QW_U8) {
                 r += kj < ki;
