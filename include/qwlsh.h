@@ -316,7 +316,7 @@ qw_status qw_set_probing(qw_index *ix, int32_t mode, int32_t per_layer);
  *      one function (k = 1) is C2LSH's single collision test.
  * extra >= 0 is v.  qw_query_workload then answers with both forms (the form
  * only chooses the hashing) through one kernel that holds a query's counts in
- * LDS; it needs neighbour probing off, K + extra <= 1024 and at most 12288
+ * LDS; it needs neighbour probing off, n < 2^25 - 1, K + extra <= 1024 and at most 12288
  * listed ids (the sum of a query's L bucket sizes) per query, else it returns
  * QW_EUNSUPPORTED with the outputs untouched (the check synchronises the
  * stream).  qw_stats then reports the verified points as cand_unique.

@@ -291,7 +291,8 @@ qw_status verify_simple(qw_index *ix, int64_t Q, int K, int mode, hipStream_t s,
 qw_status count_query(qw_index *ix, int64_t Q, int K, hipStream_t s, int32_t *out_ids,
                       void *out_dist, hipEvent_t ev_sched)
 {
-    if (ix->nprobe != 1 || K + ix->count_extra > kMaxTopK) return QW_EUNSUPPORTED;
+    if (ix->nprobe != 1 || K + ix->count_extra > kMaxTopK || ix->n >= kCountMaxN)
+        return QW_EUNSUPPORTED;
     uint32_t *mx = c32(ix) + W_MAX;
     QW_TRY(launch_fill_u32(mx, 0u, 1, s));
     QW_TRY(launch_max_bucket_sum(ix->ws.bsize.as<uint32_t>(), Q, ix->L, mx, s));

@@ -6,8 +6,9 @@
 // verified points then give the top K by (distance, id) as on the plain path.
 //
 // One workgroup per query, all state in LDS:
-//   1. the query's L bucket lists go into an open-addressing set of 2^c slots
-//      (ids) with a byte counter beside every slot (counts <= L <= 64);
+//   1. the query's L bucket lists go into an open-addressing set of 2^c slots,
+//      each holding an id (below 2^25 - 1) and its count (<= L <= 64) in one
+//      word, so two workgroups fit in a CU's LDS;
 //   2. a histogram of the counts >= theta gives the count c* at which the
 //      ranking crosses K + v: every id counted above c* is kept, and of the
 //      ids counted exactly c* the `need` smallest, found by a 4-pass radix
@@ -26,7 +27,7 @@ namespace {
 constexpr int kHistBins = kMaxL + 2;
 
 struct CountLayout {
-    size_t tab, cw, cid, ckey, surv, hist, radix, scal, total;
+    size_t tab, cid, ckey, surv, hist, radix, scal, total;
 };
 
 __host__ __device__ inline CountLayout count_layout(int cap_log2, int ncap)
@@ -34,8 +35,7 @@ __host__ __device__ inline CountLayout count_layout(int cap_log2, int ncap)
     CountLayout o;
     const size_t cap = size_t(1) << cap_log2;
     o.tab = 0;
-    o.cw = o.tab + cap * 4;
-    o.cid = o.cw + cap;                       // one count byte per slot
+    o.cid = o.tab + cap * 4;
     o.ckey = o.cid + size_t(ncap) * 4;        // ncap even: 8-byte aligned
     o.surv = o.ckey + size_t(ncap) * 8;
     o.hist = o.surv + size_t(ncap) * 4;
@@ -58,10 +58,11 @@ __device__ inline uint32_t wave_inclusive_sum(uint32_t v)
     return v;
 }
 
-__device__ inline uint32_t slot_count(const uint32_t *cw, uint32_t s)
-{
-    return (cw[s >> 2] >> ((s & 3u) * 8u)) & 0xFFu;
-}
+// A set slot holds (count << kCountShift) | (id + 1); 0 is a free slot.
+constexpr int kCountShift = 25;
+constexpr uint32_t kSlotId = (1u << kCountShift) - 1u;
+__device__ inline uint32_t slot_id(uint32_t w) { return (w & kSlotId) - 1u; }
+__device__ inline uint32_t slot_count(uint32_t w) { return w >> kCountShift; }
 
 // Whole workgroup.  Among the items i < nitems with pred(i), the need-th
 // smallest of the 32-bit values val(i) (1 <= need <= that many items), one
@@ -125,7 +126,6 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
     extern __shared__ __align__(16) uint8_t smem[];
     const CountLayout lay = count_layout((int)A.cap_log2, A.ncap);
     uint32_t *tab = reinterpret_cast<uint32_t *>(smem + lay.tab);
-    uint32_t *cw = reinterpret_cast<uint32_t *>(smem + lay.cw);
     uint32_t *cid = reinterpret_cast<uint32_t *>(smem + lay.cid);
     uint64_t *ckey = reinterpret_cast<uint64_t *>(smem + lay.ckey);
     uint32_t *surv = reinterpret_cast<uint32_t *>(smem + lay.surv);
@@ -156,8 +156,7 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
     while ((3u << c) < 4u * total && c < (int)A.cap_log2) ++c;
     const uint32_t cap = 1u << c, mask = cap - 1u;
 
-    for (uint32_t s = tid; s < cap; s += kBlock) tab[s] = kEmpty;
-    for (uint32_t s = tid; s < cap / 4; s += kBlock) cw[s] = 0u;
+    for (uint32_t s = tid; s < cap; s += kBlock) tab[s] = 0u;
     for (int s = tid; s < kHistBins; s += kBlock) hist[s] = 0u;
     if (tid == 0) scal[SC_NCAND] = 0u;
     __syncthreads();
@@ -190,9 +189,11 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
             // the set holds at most 3/4 of its slots, so some slot of the
             // odd-step sequence is free or holds the id
             for (uint32_t t = 0; t < cap; ++t) {
-                const uint32_t prev = atomicCAS(&tab[h], kEmpty, id[r]);
-                if (prev == kEmpty || prev == id[r]) {
-                    atomicAdd(&cw[h >> 2], 1u << ((h & 3u) * 8u));
+                const uint32_t key = id[r] + 1u;
+                const uint32_t prev = atomicCAS(&tab[h], 0u, key | (1u << kCountShift));
+                if (prev == 0u) break;  // new, counted once
+                if ((prev & kSlotId) == key) {
+                    atomicAdd(&tab[h], 1u << kCountShift);
                     break;
                 }
                 h = (h + step) & mask;
@@ -203,8 +204,8 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
 
     // 2. counts >= theta, the crossing count c* and how many ids it contributes
     for (uint32_t s = tid; s < cap; s += kBlock)
-        if (tab[s] != kEmpty) {
-            const uint32_t k = slot_count(cw, s);
+        if (tab[s] != 0u) {
+            const uint32_t k = slot_count(tab[s]);
             if (k >= (uint32_t)A.theta) atomicAdd(&hist[k], 1u);
         }
     __syncthreads();
@@ -230,14 +231,14 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
     uint32_t last = 0xFFFFFFFFu;  // largest id kept among those counted c*
     if (scal[SC_NEED] < hist[cstar])  // the need-th smallest id counted exactly c*
         last = block_select(
-            cap, scal[SC_NEED], [&](uint32_t s) { return tab[s]; },
-            [&](uint32_t s) { return tab[s] != kEmpty && slot_count(cw, s) == cstar; }, radix, scal);
+            cap, scal[SC_NEED], [&](uint32_t s) { return slot_id(tab[s]); },
+            [&](uint32_t s) { return tab[s] != 0u && slot_count(tab[s]) == cstar; }, radix, scal);
 
     // kept: counted above c*, or counted c* with an id up to `last`
     for (uint32_t s = tid; s < cap; s += kBlock) {
-        const uint32_t id = tab[s];
-        if (id == kEmpty) continue;
-        const uint32_t k = slot_count(cw, s);
+        const uint32_t w = tab[s];
+        if (w == 0u) continue;
+        const uint32_t id = slot_id(w), k = slot_count(w);
         if (k > cstar || (k == cstar && id <= last)) {
             const uint32_t at = atomicAdd(&scal[SC_NCAND], 1u);
             cid[at] = id;

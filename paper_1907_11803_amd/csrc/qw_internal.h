@@ -291,6 +291,8 @@ qw_status launch_count(const CountArgs &a, int64_t Q, hipStream_t s);
 // the largest set, 2^14 slots).
 constexpr uint32_t kCountMaxListed = 12288;
 constexpr int kCountMaxSetLog2 = 14;
+// Ids share a set word with their count (7 bits), so counting needs n below this.
+constexpr int64_t kCountMaxN = (int64_t(1) << 25) - 1;
 
 size_t verify_lds_bytes(int cap_log2, int buf, int global_tab, int L, int dp, int dtype);
 qw_status launch_verify(const VerifyArgs &a, int grid, hipStream_t s);
