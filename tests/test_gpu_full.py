@@ -89,6 +89,29 @@ def test_cfg2_full_neighbour_probing_sampled():
     compare(ids, dist, ids_o, dist_o, rows, True)
 
 
+@pytest.mark.timeout(300)
+def test_cfg2_full_collision_counting_sampled():
+    """The collision-counting configuration the benchmark times: 1M x 128 uint8,
+    all 10K queries, an index of 64 layers of k = 10 at w = 1000 (parameter
+    seed 2102), threshold 3, v = 800 (up to 8,690 listed ids per query); both
+    forms agree and 200 sampled queries match the oracle."""
+    wl = synth.make_config(2)
+    cp = synth.hash_params(2102, 64, wl.params.k, wl.d, 1000.0)
+    ix = lib.Index(dev(wl.data), dev(cp.a), dev(cp.b()), 1000.0)
+    ix.set_counting(3, 800)
+    q = dev(wl.queries)
+    ids, dist = ix.query(q, wl.K, lib.make_opts(form=lib.QW_FORM_FAST, graph=0))
+    ids_p, dist_p = ix.query(q, wl.K, lib.make_opts(form=lib.QW_FORM_PLAIN_FP32))
+    torch.cuda.synchronize()
+    assert torch.equal(ids, ids_p) and torch.equal(dist, dist_p)
+    ix.close()
+    rows = np.sort(np.random.default_rng(5).choice(wl.Q, size=200, replace=False))
+    ids_o, dist_o, cnt = oracle.lsh_query_counting(wl.data, wl.queries[rows], cp.a, cp.b(),
+                                                   1000.0, wl.K, 3, 800)
+    assert cnt.mean() > 500
+    compare(ids, dist, ids_o, dist_o, rows, True)
+
+
 @pytest.mark.timeout(400)
 def test_cfg3_and_cfg5_full_sampled():
     """1M x 960 float data: the 1,000 noisy-point queries at the stated and a
