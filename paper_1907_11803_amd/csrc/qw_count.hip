@@ -25,6 +25,9 @@ namespace qw {
 namespace {
 
 constexpr int kHistBins = kMaxL + 2;
+// Threads per workgroup: two workgroups share a CU's LDS, so each brings
+// eight waves to hide the latency of its LDS atomics and dependent loads.
+constexpr int kCountBlock = 512;
 
 struct CountLayout {
     size_t tab, cid, ckey, surv, hist, radix, scal, total;
@@ -80,11 +83,11 @@ __device__ inline uint32_t block_select(uint32_t nitems, uint32_t need, Val val,
         scal[SC_REM] = need;
     }
     for (int shift = 24; shift >= 0; shift -= 8) {
-        for (int b = tid; b < 256; b += kBlock) radix[b] = 0u;
+        for (int b = tid; b < 256; b += kCountBlock) radix[b] = 0u;
         __syncthreads();
         const uint32_t prefix = scal[SC_PREFIX];
         const uint32_t hmask = shift == 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
-        for (uint32_t i = tid; i < nitems; i += kBlock)
+        for (uint32_t i = tid; i < nitems; i += kCountBlock)
             if (pred(i)) {
                 const uint32_t v = val(i);
                 if ((v & hmask) == prefix) atomicAdd(&radix[(v >> shift) & 255u], 1u);
@@ -121,7 +124,7 @@ __device__ inline uint32_t block_select(uint32_t nitems, uint32_t need, Val val,
 }
 
 template <int DT>
-__global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
+__global__ __launch_bounds__(kCountBlock) void count_kernel(const CountArgs A)
 {
     extern __shared__ __align__(16) uint8_t smem[];
     const CountLayout lay = count_layout((int)A.cap_log2, A.ncap);
@@ -156,8 +159,8 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
     while ((3u << c) < 4u * total && c < (int)A.cap_log2) ++c;
     const uint32_t cap = 1u << c, mask = cap - 1u;
 
-    for (uint32_t s = tid; s < cap; s += kBlock) tab[s] = 0u;
-    for (int s = tid; s < kHistBins; s += kBlock) hist[s] = 0u;
+    for (uint32_t s = tid; s < cap; s += kCountBlock) tab[s] = 0u;
+    for (int s = tid; s < kHistBins; s += kCountBlock) hist[s] = 0u;
     if (tid == 0) scal[SC_NCAND] = 0u;
     __syncthreads();
 
@@ -165,11 +168,11 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
     // layer); kCountLoads positions of the concatenated lists per thread are
     // located (binary search over the prefix) and loaded together
     constexpr int kCountLoads = 4;
-    for (uint32_t base = 0; base < total; base += kCountLoads * kBlock) {
+    for (uint32_t base = 0; base < total; base += kCountLoads * kCountBlock) {
         uint32_t id[kCountLoads];
 #pragma unroll
         for (int r = 0; r < kCountLoads; ++r) {
-            const uint32_t pos = base + (uint32_t)(r * kBlock + tid);
+            const uint32_t pos = base + (uint32_t)(r * kCountBlock + tid);
             id[r] = kEmpty;
             if (pos < total) {
                 int lo = 0;  // largest layer with lpref <= pos (its list holds pos)
@@ -203,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
     __syncthreads();
 
     // 2. counts >= theta, the crossing count c* and how many ids it contributes
-    for (uint32_t s = tid; s < cap; s += kBlock)
+    for (uint32_t s = tid; s < cap; s += kCountBlock)
         if (tab[s] != 0u) {
             const uint32_t k = slot_count(tab[s]);
             if (k >= (uint32_t)A.theta) atomicAdd(&hist[k], 1u);
@@ -235,7 +238,7 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
             [&](uint32_t s) { return tab[s] != 0u && slot_count(tab[s]) == cstar; }, radix, scal);
 
     // kept: counted above c*, or counted c* with an id up to `last`
-    for (uint32_t s = tid; s < cap; s += kBlock) {
+    for (uint32_t s = tid; s < cap; s += kCountBlock) {
         const uint32_t w = tab[s];
         if (w == 0u) continue;
         const uint32_t id = slot_id(w), k = slot_count(w);
@@ -248,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
     const int nc = (int)scal[SC_NCAND];
 
     // 3. verify the kept ids
-    for (int i = tid; i < nc; i += kBlock) {
+    for (int i = tid; i < nc; i += kCountBlock) {
         const uint32_t id = cid[i];
         if constexpr (DT == QW_U8) {
             const uint4 *x = reinterpret_cast<const uint4 *>(static_cast<const uint8_t *>(A.data) +
@@ -284,13 +287,13 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
             [&](uint32_t) { return true; }, radix, scal);
     if (tid == 0) scal[SC_NSURV] = 0u;
     __syncthreads();
-    for (int i = tid; i < nc; i += kBlock)
+    for (int i = tid; i < nc; i += kCountBlock)
         if ((uint32_t)(ckey[i] >> 32) <= hbound) surv[atomicAdd(&scal[SC_NSURV], 1u)] = (uint32_t)i;
     __syncthreads();
     const int ns = (int)scal[SC_NSURV];
     // rank of each survivor under (distance, id) among the survivors (at least
     // K of them; every key of the top K is one); the keys are distinct
-    for (int a = tid; a < ns; a += kBlock) {
+    for (int a = tid; a < ns; a += kCountBlock) {
         const uint32_t i = surv[a];
         const uint64_t ki = ckey[i];
         const uint32_t ii = cid[i];
@@ -313,7 +316,7 @@ __global__ __launch_bounds__(kBlock) void count_kernel(const CountArgs A)
                 reinterpret_cast<float *>(A.out_dist)[o] = (float)__longlong_as_double((long long)ki);
         }
     }
-    for (int r = nc + tid; r < A.K; r += kBlock) {
+    for (int r = nc + tid; r < A.K; r += kCountBlock) {
         const int64_t o = q * A.K + r;
         A.out_ids[o] = -1;
         if constexpr (DT == QW_U8)
@@ -337,9 +340,9 @@ qw_status launch_count(const CountArgs &a, int64_t Q, hipStream_t s)
         return QW_EINTERNAL;
     const size_t lds = count_lds_bytes((int)a.cap_log2, a.ncap);
     if (a.dtype == QW_U8)
-        count_kernel<QW_U8><<<(unsigned)Q, kBlock, lds, s>>>(a);
+        count_kernel<QW_U8><<<(unsigned)Q, kCountBlock, lds, s>>>(a);
     else
-        count_kernel<QW_F32><<<(unsigned)Q, kBlock, lds, s>>>(a);
+        count_kernel<QW_F32><<<(unsigned)Q, kCountBlock, lds, s>>>(a);
     QW_HIP(hipGetLastError());
     return QW_OK;
 }
