@@ -333,7 +333,7 @@ def main():
                "matches_gpu": cpu_match}
         log(f"[bench] oracle: {cpu['value']} q/s on {nthreads} threads (build {build_cpu:.1f}s)")
 
-    # ---- collision counting with a candidate cap (Section 2.4) on an index of
+    # ---- collision counting with a candidate cap (Section 3, "Collision Counting") on an index of
     # 64 layers over the same data and queries: the points sharing the query's
     # bucket in at least theta layers, ranked by (count desc, id asc), K + v of
     # them verified; beside it the plain union on that index.  Its kernel's

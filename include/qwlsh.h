@@ -304,7 +304,7 @@ qw_status qw_set_count_margin(qw_index *ix, float margin);
 qw_status qw_set_probing(qw_index *ix, int32_t mode, int32_t per_layer);
 
 /*
- * Collision counting with a candidate cap (Section 2.4, after C2LSH: the
+ * Collision counting with a candidate cap (Section 3, "Collision Counting", after C2LSH: the
  * number of layers in which a point shares the query's bucket is counted, a
  * threshold on that count replaces the plain union, and at most k + v points
  * -- the K results plus v allowed false positives -- are verified).
@@ -320,7 +320,7 @@ qw_status qw_set_probing(qw_index *ix, int32_t mode, int32_t per_layer);
  * listed ids (the sum of a query's L bucket sizes) per query, else it returns
  * QW_EUNSUPPORTED with the outputs untouched (the check synchronises the
  * stream).  qw_stats then reports the verified points as cand_unique.
- * QW_EINVAL for a threshold outside 0..L or a negative extra.  Not to be
+ * QW_EINVAL for a threshold outside 0..L or an extra outside 0..1024.  Not to be
  * called while work on the index is in flight.
  */
 qw_status qw_set_counting(qw_index *ix, int32_t threshold, int32_t extra);

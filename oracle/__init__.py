@@ -149,7 +149,7 @@ def lsh_query(data: np.ndarray, queries: np.ndarray, a: np.ndarray, b: np.ndarra
 
 def lsh_query_counting(data: np.ndarray, queries: np.ndarray, a: np.ndarray, b: np.ndarray,
                        w: float, K: int, theta: int, v: int, nthreads: Optional[int] = None):
-    """Collision counting with a candidate cap (Section 2.4): the points sharing
+    """Collision counting with a candidate cap (Section 3, "Collision Counting"): the points sharing
     a bucket with the query in at least theta layers, ranked by (layer count
     descending, id ascending), the first K + v of them verified, the top K kept.
     Returns (ids int32 [Q,K], dist [Q,K] int64 (u8) or float64 (f32),

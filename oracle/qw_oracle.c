@@ -43,7 +43,7 @@
  *     when |C(q)| < K the tail is padded with id -1 and distance INT64_MAX
  *     (u8) or +inf (f32).
  *  7. Brute force: step 6 over all n points (exact kNN).
- *  8. Collision counting with a candidate cap (Section 2.4, after C2LSH: each
+ *  8. Collision counting with a candidate cap (Section 3, "Collision Counting", after C2LSH: each
  *     layer acts as one collision test, a threshold on the number of tests a
  *     point passes replaces the plain union, and at most k + v points -- K
  *     results plus v allowed false positives -- are verified): #Col(p) is the

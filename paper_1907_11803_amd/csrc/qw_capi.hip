@@ -291,7 +291,7 @@ qw_status verify_simple(qw_index *ix, int64_t Q, int K, int mode, hipStream_t s,
 qw_status count_query(qw_index *ix, int64_t Q, int K, hipStream_t s, int32_t *out_ids,
                       void *out_dist, hipEvent_t ev_sched)
 {
-    if (ix->nprobe != 1 || K + ix->count_extra > kMaxTopK || ix->n >= kCountMaxN)
+    if (ix->nprobe != 1 || (int64_t)K + ix->count_extra > kMaxTopK || ix->n >= kCountMaxN)
         return QW_EUNSUPPORTED;
     uint32_t *mx = c32(ix) + W_MAX;
     QW_TRY(launch_fill_u32(mx, 0u, 1, s));
@@ -958,7 +958,7 @@ qw_status qw_set_probing(qw_index *ix, int32_t mode, int32_t per_layer)
 qw_status qw_set_counting(qw_index *ix, int32_t threshold, int32_t extra)
 {
     QW_TRY(check_index(ix));
-    if (threshold < 0 || threshold > ix->L || extra < 0) return QW_EINVAL;
+    if (threshold < 0 || threshold > ix->L || extra < 0 || extra > kMaxTopK) return QW_EINVAL;
     ix->count_theta = threshold;
     ix->count_extra = threshold ? extra : 0;
     return QW_OK;

@@ -1,4 +1,4 @@
-// Collision counting with a candidate cap (Section 2.4, after C2LSH): every
+// Collision counting with a candidate cap (Section 3, "Collision Counting", after C2LSH): every
 // layer of the index is one collision test, a point is a candidate when it
 // shares the query's bucket in at least theta layers, and at most K + v of the
 // candidates are verified -- the K results plus v allowed false positives --

@@ -1,4 +1,4 @@
-"""GPU parity of collision counting with a candidate cap (Section 2.4): the
+"""GPU parity of collision counting with a candidate cap (Section 3, "Collision Counting"): the
 points found in at least theta of the query's layer buckets, ranked by (count
 descending, id ascending), the first K + v verified, the top K returned.  Ids
 and uint8 distances bit-exact against the CPU oracle, float distances within
@@ -106,6 +106,10 @@ def test_counting_limits_leave_outputs_untouched():
     with pytest.raises(lib.QwError) as e:
         ix.set_counting(49, 0)
     assert e.value.status == lib.QW_EINVAL
+    for extra in (1025, 2**31 - 1):  # v beyond the largest verified count
+        with pytest.raises(lib.QwError) as e:
+            ix.set_counting(2, extra)
+        assert e.value.status == lib.QW_EINVAL
     ix.close()
     wl = synth.make_config(1)
     p = wl.params

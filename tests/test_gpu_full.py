@@ -147,3 +147,64 @@ def test_cfg4_full_sampled():
         ids_o, dist_o, _ = bi.query(wl.queries[rows], wl.K)
         bi.close()
         compare(ids, dist, ids_o, dist_o, rows, True)
+
+
+@pytest.mark.timeout(300)
+def test_headline_configuration_every_query():
+    """The benchmark's timed configuration exactly: 1M x 128 uint8, all 10K
+    queries, w = 800, query-directed probing with two moves per layer, a count
+    model trained as the benchmark trains it (50,000 queries, 8 epochs), the
+    learned schedule with automatic grouping, replayed from a HIP graph.  Ids
+    and int32 distances of every query equal the oracle's (probes=2, T=2), and
+    the plain form returns the same."""
+    wl = synth.make_config(2)
+    w = 800.0
+    p = wl.params
+    ix = lib.Index(dev(wl.data), dev(p.a), dev(p.b(w)), w)
+    ix.set_probing(2, 2)
+    ix.train_count_model(dev(synth.training_queries(2, 50_000)), epochs=8, batch=1024,
+                         lr=2e-3, seed=1)
+    q = dev(wl.queries)
+    out_ids = torch.empty((wl.Q, wl.K), dtype=torch.int32, device="cuda")
+    out_dist = torch.empty((wl.Q, wl.K), dtype=torch.int32, device="cuda")
+    results = []
+    for _ in range(3):  # capture, then two replays into the same (poisoned) outputs
+        out_ids.fill_(-7)
+        out_dist.fill_(-7)
+        ix.query(q, wl.K, bench_opts(), out_ids=out_ids, out_dist=out_dist)
+        torch.cuda.synchronize()
+        results.append((out_ids.clone(), out_dist.clone()))
+    for r in results[1:]:
+        assert torch.equal(r[0], results[0][0]) and torch.equal(r[1], results[0][1])
+    ids_p, dist_p = ix.query(q, wl.K, lib.make_opts(form=lib.QW_FORM_PLAIN_FP32))
+    torch.cuda.synchronize()
+    assert torch.equal(ids_p, results[0][0]) and torch.equal(dist_p, results[0][1])
+    ix.close()
+    bi = oracle.BuiltIndex(wl.data, p.a, p.b(w), w)
+    ids_o, dist_o, _ = bi.query(wl.queries, wl.K, probes=2, probe_t=2)
+    bi.close()
+    compare(results[0][0], results[0][1], ids_o, dist_o, np.arange(wl.Q), True)
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("w", [800.0, 1200.0])
+def test_cfg2_bucket_ids_full_size(w):
+    """Bucket ids of all 1M data rows and all 10K queries (L * k = 200
+    functions each) equal the oracle's FP64 floors element by element, for both
+    projection forms; the guard band recomputed some of them in FP64."""
+    wl = synth.make_config(2)
+    p = wl.params
+    ix = lib.Index(dev(wl.data), dev(p.a), dev(p.b(w)), w)
+    for x in (wl.queries, wl.data):
+        want = oracle.hash_points(x, p.a, p.b(w), w)
+        xd = dev(x)
+        for form in (lib.QW_FORM_PLAIN_FP32, lib.QW_FORM_FAST):
+            h, rec = ix.hash(xd, form)
+            got = h.cpu().numpy()
+            bad = np.argwhere(got != want)
+            assert bad.size == 0, f"form {form}: {len(bad)} bucket ids differ, first {bad[:3].tolist()}"
+            if x.shape[0] == wl.n:
+                assert rec > 0
+            del h
+        del xd
+    ix.close()

@@ -229,6 +229,46 @@ def test_query_directed_probing_matches_definition(T):
     assert all(np.array_equal(x, z) for x, z in zip(full, every))
 
 
+def test_query_directed_probing_picks_nearest_neighbour_cells():
+    """Geometric statement of the query-directed order (Lv et al.): in the
+    projected space of a layer (coordinates y_j = (a_j.q + b_j) / w) the query
+    lies in the cell prod_j [h_j, h_j + 1); the neighbour bucket that moves
+    coordinate j by -1 is the adjacent cell whose nearest point lies y_j - h_j
+    away, by +1 the one lying h_j + 1 - y_j away.  The T chosen moves are the T
+    adjacent cells nearest to the query's point, computed here in exact rational
+    arithmetic from the float32 parameters (no FP64 rounding, no squares).  The
+    paper fixes no probe order; this pins the reading, not a printed value."""
+    wl = synth.make_config(1, n=1500, Q=8, w=500.0)
+    a, b, w = wl.params.a, wl.params.b(), wl.params.w
+    L, k, d = a.shape
+    hd = oracle.hash_points(wl.data, a, b, w).reshape(-1, L, k).astype(np.int64)
+    wf = Fraction(float(np.float32(w)))
+    af = [[[Fraction(float(v)) for v in a[l, j]] for j in range(k)] for l in range(L)]
+    for T in (1, 4):
+        got = oracle.lsh_candidates(wl.data, wl.queries, a, b, w, probes=2, probe_t=T)
+        for q in range(wl.queries.shape[0]):
+            x = [int(v) for v in wl.queries[q]]
+            ok = np.zeros(hd.shape[0], dtype=bool)
+            for l in range(L):
+                y = [(sum(u * v for u, v in zip(af[l][j], x)) + Fraction(float(b[l, j]))) / wf
+                     for j in range(k)]
+                h = [math.floor(v) for v in y]
+                cells = []
+                for j in range(k):
+                    cells.append((y[j] - h[j], j, -1))
+                    cells.append((h[j] + 1 - y[j], j, +1))
+                cells.sort()
+                assert all(c0[0] != c1[0] for c0, c1 in zip(cells, cells[1:]))  # no exact ties
+                targets = [np.array(h)]
+                for _, j, s in cells[:T]:
+                    t = np.array(h)
+                    t[j] += s
+                    targets.append(t)
+                for t in targets:
+                    ok |= np.all(hd[:, l, :] == t, axis=1)
+            assert np.array_equal(got[q], np.nonzero(ok)[0].astype(np.int32))
+
+
 def test_neighbour_probing_topk_is_topk_of_candidates():
     """The probed top K is the (distance, id) top K of the probed candidate set,
     selected here with numpy's lexsort over int64 distances."""
@@ -501,6 +541,44 @@ def test_adam_first_step_is_lr_times_sign():
     g = np.array([0.3, -2.0, 1e-3])
     p, m, v = mlp.adam_step(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, 0.01)
     np.testing.assert_allclose(p, -0.01 * np.sign(g), rtol=1e-4)
+
+
+def test_adam_second_step_hand_worked():
+    """Two Adam steps from zero moments, worked by hand with exact fractions.
+    beta1 = 9/10, beta2 = 999/1000; gradients g1 = 1 then g2 in {1, -1, 3}:
+      m2 = (9/100) g1 + (1/10) g2,   mhat2 = m2 / (1 - 81/100)
+      v2 = (999/10^6) g1^2 + (1/1000) g2^2,   vhat2 = v2 / (1 - 998001/10^6)
+    g2 = 1: mhat2 = 1, vhat2 = 1; g2 = -1: mhat2 = -1/19, vhat2 = 1;
+    g2 = 3: mhat2 = 39/19, vhat2 = 9999/1999.  A dropped bias correction,
+    beta1 and beta2 swapped, or the corrections taken at step - 1 fail here."""
+    lr, eps = 0.01, 1e-8
+    cases = {1.0: (Fraction(1), Fraction(1)), -1.0: (Fraction(-1, 19), Fraction(1)),
+             3.0: (Fraction(39, 19), Fraction(9999, 1999))}
+    for g2, (mhat, vhat) in cases.items():
+        p, m, v = mlp.adam_step(np.zeros(1), np.ones(1), np.zeros(1), np.zeros(1), 1, lr)
+        p1 = -lr * 1.0 / (1.0 + eps)
+        np.testing.assert_allclose(p, [p1], rtol=1e-15)
+        np.testing.assert_allclose(m, [0.1], rtol=1e-15)
+        np.testing.assert_allclose(v, [0.001], rtol=1e-15)
+        p, m, v = mlp.adam_step(p, np.array([g2]), m, v, 2, lr)
+        np.testing.assert_allclose(m, [float(Fraction(9, 100) + Fraction(1, 10) * Fraction(g2))],
+                                   rtol=1e-14)
+        np.testing.assert_allclose(v, [float(Fraction(999, 10**6) + Fraction(1, 1000) * Fraction(g2) ** 2)],
+                                   rtol=1e-14)
+        want = p1 - lr * float(mhat) / (math.sqrt(float(vhat)) + eps)
+        np.testing.assert_allclose(p, [want], rtol=1e-13)
+
+
+def test_adam_constant_gradient_moves_lr_per_step():
+    """With a constant gradient g the bias-corrected moments equal g and g^2 at
+    every step, so each of the first steps moves the parameter by
+    lr * g / (|g| + eps)."""
+    lr, eps = 0.003, 1e-8
+    g = np.array([0.25, -4.0, 2.0e-3])
+    p, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
+    for step in range(1, 7):
+        p, m, v = mlp.adam_step(p, g, m, v, step, lr, eps=eps)
+        np.testing.assert_allclose(p, -step * lr * g / (np.abs(g) + eps), rtol=1e-9)
 
 
 def test_built_index_matches_one_shot_query():
