@@ -694,7 +694,7 @@ qw_status launch_dedup(const DedupArgs &a, int grid, hipStream_t s)
     if (a.nl < 1 || a.nl > kMaxLists || (a.nl > 64 && !a.pmagic)) return QW_EINVAL;
     const size_t lds = dedup_lds_bytes((int)a.cap_log2, a.global_tab, a.nl,
                                        a.dp * (a.dtype == QW_U8 ? 1 : 4));
-    const bool mp = a.pmagic != 0;
+    const bool mp = a.nl > 64;  // the wide-list instantiation only where 64 lists do not suffice
     if (a.dtype == QW_U8) {
         if (mp) {
             if (a.global_tab) dedup_kernel<true, QW_U8, true><<<grid, kBlock, lds, s>>>(a);
