@@ -179,6 +179,31 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
                             const qw_opts *o, void *stream, int32_t *out_ids, void *out_dist,
                             qw_stats *st);
 
+/*
+ * The plain form's query workload without any allocation, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, results and
+ * output conventions as qw_query_workload with o->form = QW_FORM_PLAIN_FP32
+ * (or collision counting when qw_set_counting is active); no options, no
+ * statistics.
+ * Every workspace buffer (query hashes, bucket ranges, counters, the padded
+ * query copy when d is not a multiple of 16 or `queries` is not 16-byte
+ * aligned, the query-directed probing projections) comes from one static
+ * device array of 32 MiB per GPU, held until the process ends.  The call
+ * allocates nothing -- no hipMalloc, no hipFree -- and grows no buffer of the
+ * index.  Limits: the workspace of Q queries, about
+ * Q * (4*L*k + 8*lists + 8 [+ 4*L with probing] [+ 8*L*k + T*L with
+ * query-directed probing] [+ d*elem when padded]) bytes plus alignment, must
+ * fit 32 MiB, and each query's hash set must fit on-chip memory; otherwise
+ * QW_EUNSUPPORTED, with the outputs untouched.
+ * Every call on one GPU shares that GPU's array and overwrites it: calls that
+ * overlap on one GPU (other streams, other threads, other indexes) race and
+ * must be serialised by the caller.  Synchronises `stream` once (the hash-set
+ * size is read back from the device).
+ */
+qw_status qw_query_workload_noalloc(qw_index *ix, const void *queries, int64_t Q, int32_t K,
+                                    void *stream, int32_t *out_ids, void *out_dist);
+
 /* Release the index and all device memory it holds (NULL is a no-op). */
 void qw_free_index(qw_index *ix);
 

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <random>
 #include <vector>
@@ -11,6 +12,13 @@
 #include "qw_mlp.h"
 
 using namespace qw;
+
+// Device scratch of qw_query_workload_noalloc (see carve_plain_ws below): one
+// copy per GPU, held until the process ends.  Host code never passes this
+// name to a kernel or a copy: it takes the device address from
+// hipGetSymbolAddress once per device and uses that.
+constexpr size_t kNoAllocBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 namespace {
 
@@ -244,9 +252,12 @@ qw_status clear_counters(qw_index *ix, hipStream_t s)
 
 // One hash-set size for all queries (from the largest bound), one workgroup per
 // query.  Used by the plain form and by the introspection calls.  Syncs.
+// may_alloc = false (the allocation-free entry point): a set beyond LDS, which
+// would need global scratch, returns QW_EUNSUPPORTED before any verification.
 qw_status verify_simple(qw_index *ix, int64_t Q, int K, int mode, hipStream_t s,
                         int32_t *out_ids, void *out_dist, int32_t *out_counts,
-                        const long long *offsets, hipEvent_t ev_sched = nullptr)
+                        const long long *offsets, hipEvent_t ev_sched = nullptr,
+                        bool may_alloc = true)
 {
     uint32_t *mx = c32(ix) + W_MAX;
     QW_TRY(launch_fill_u32(mx, 0u, 1, s));
@@ -272,6 +283,7 @@ qw_status verify_simple(qw_index *ix, int64_t Q, int K, int mode, hipStream_t s,
         return launch_verify(a, (int)Q, s);
     }
     // very large candidate sets: hash sets in global scratch, persistent workgroups
+    if (!may_alloc) return QW_EUNSUPPORTED;
     const int grid = (int)std::min<int64_t>(Q, ix->cus);
     void *old = ix->ws.gscratch.p;
     QW_TRY(ix->ws.gscratch.ensure((size_t)grid * (size_t(1) << cap) * 4));
@@ -591,6 +603,63 @@ qw_status check_vectors(const qw_index *ix, const void *x, int64_t m)
     return QW_OK;
 }
 
+// ---------------------------------------------------------------- allocation-free queries
+// Device scratch of qw_query_workload_noalloc: every workspace buffer of the
+// plain form's pipeline is carved from it, so that entry point allocates
+// nothing.  Each GPU the library runs on holds its own copy until the process
+// ends; its device address is taken once per device (hipGetSymbolAddress, with
+// the device current) and only that address is handed to kernels and fills.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+
+qw_status scratch_address(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return QW_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        QW_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return QW_EDEVICE;
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return QW_OK;
+}
+
+// Workspace views into `base` (kNoAllocBytes bytes) for the plain form over Q
+// queries: the buffers front(), verify_simple() and count_query() read.
+// Returns false when they do not fit.
+bool carve_plain_ws(const qw_index *ix, int64_t Q, bool pad, unsigned char *base, Workspace &w)
+{
+    size_t off = 0;
+    bool ok = true;
+    auto take = [&](DevBuf &b, size_t bytes) {
+        const size_t at = (off + 255) & ~size_t(255);
+        if (!ok || bytes > kNoAllocBytes || at > kNoAllocBytes - bytes) {
+            ok = false;
+            return;
+        }
+        b.view(base + at, bytes ? bytes : 16);
+        off = at + (bytes ? bytes : 16);
+    };
+    const size_t q = (size_t)Q;
+    const size_t elem = ix->dtype == QW_U8 ? 1 : 4;
+    take(w.counters, sizeof(unsigned long long) * kC64 + sizeof(uint32_t) * kC32);
+    if (pad) take(w.qpad, elem * q * (size_t)ix->dp);
+    take(w.h, sizeof(int32_t) * q * (size_t)ix->nf);
+    take(w.bstart, sizeof(uint32_t) * q * (size_t)ix->nl);
+    take(w.bsize, sizeof(uint32_t) * q * (size_t)ix->nl);
+    if (ix->nprobe > 1) take(w.lsum, sizeof(uint32_t) * q * (size_t)ix->L);
+    if (ix->probe_mode == 2) {
+        take(w.yq, sizeof(double) * q * (size_t)ix->nf);
+        take(w.moves, q * (size_t)ix->L * (size_t)(ix->nprobe - 1));
+    }
+    take(w.ucount, sizeof(uint32_t) * q);
+    take(w.ovf, sizeof(int32_t) * q);
+    return ok;
+}
+
 }  // namespace
 
 // ============================================================================ ABI
@@ -777,6 +846,39 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
         return QW_OK;
     } catch (const std::bad_alloc &) {
         return QW_ENOMEM;
+    } catch (...) {
+        return QW_EINTERNAL;
+    }
+}
+
+qw_status qw_query_workload_noalloc(qw_index *ix, const void *queries, int64_t Q, int32_t K,
+                                    void *stream, int32_t *out_ids, void *out_dist)
+{
+    QW_TRY(check_index(ix));
+    QW_TRY(check_vectors(ix, queries, Q));
+    if (K < 1 || K > kMaxTopK || (Q > 0 && (!out_ids || !out_dist))) return QW_EINVAL;
+    if (Q == 0) return QW_OK;
+    void *base = nullptr;
+    QW_TRY(scratch_address(ix->device, &base));
+    const bool pad = !(ix->d == ix->dp && (reinterpret_cast<uintptr_t>(queries) & 15) == 0);
+    Workspace view;
+    if (!carve_plain_ws(ix, Q, pad, static_cast<unsigned char *>(base), view))
+        return QW_EUNSUPPORTED;  // the workspace of Q queries exceeds the scratch
+    hipStream_t s = S(stream);
+    // the index's own workspace steps aside for the call and comes back on
+    // every path; nothing below grows a buffer (a view refuses to)
+    std::swap(ix->ws, view);
+    struct Restore {
+        qw_index *ix;
+        Workspace *saved;
+        ~Restore() { std::swap(ix->ws, *saved); }
+    } restore{ix, &view};
+    try {
+        QW_TRY(clear_counters(ix, s));
+        QW_TRY(front(ix, queries, Q, QW_FORM_PLAIN_FP32, s));
+        if (ix->count_theta > 0) return count_query(ix, Q, K, s, out_ids, out_dist, nullptr);
+        return verify_simple(ix, Q, K, VM_TOPK, s, out_ids, out_dist, nullptr, nullptr, nullptr,
+                             false);
     } catch (...) {
         return QW_EINTERNAL;
     }

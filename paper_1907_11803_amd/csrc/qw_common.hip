@@ -20,6 +20,7 @@ void note_hip_error(hipError_t e, const char *what, const char *file, int line)
 qw_status DevBuf::ensure(size_t want)
 {
     if (want <= bytes && p) return QW_OK;
+    if (!owned) return QW_EINTERNAL;  // a view never allocates
     release();
     if (want == 0) want = 16;
     want = (want + 255) & ~size_t(255);
@@ -35,9 +36,10 @@ qw_status DevBuf::ensure(size_t want)
 
 void DevBuf::release()
 {
-    if (p) (void)hipFree(p);
+    if (p && owned) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    owned = true;
 }
 
 // ---------------------------------------------------------------- fills

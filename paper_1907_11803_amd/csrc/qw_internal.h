@@ -64,17 +64,45 @@ constexpr int kMaxD = 8192;
 void note_hip_error(hipError_t e, const char *what, const char *file, int line);
 
 // ---------------------------------------------------------------- device buffers
-// A device allocation owned by the library.
+// A device allocation owned by the library, or a view of `bytes` bytes of
+// memory owned elsewhere (never freed, never grown: ensure() beyond its size
+// fails with QW_EINTERNAL instead of allocating).
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool owned = true;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes), owned(o.owned)
+    {
+        o.p = nullptr;
+        o.bytes = 0;
+        o.owned = true;
+    }
+    DevBuf &operator=(DevBuf &&o) noexcept
+    {
+        if (this != &o) {
+            release();
+            p = o.p;
+            bytes = o.bytes;
+            owned = o.owned;
+            o.p = nullptr;
+            o.bytes = 0;
+            o.owned = true;
+        }
+        return *this;
+    }
     ~DevBuf() { release(); }
     qw_status ensure(size_t want);  // grows (contents discarded); never shrinks
     void release();
+    void view(void *mem, size_t n)
+    {
+        release();
+        p = mem;
+        bytes = n;
+        owned = false;
+    }
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
 

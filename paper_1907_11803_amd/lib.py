@@ -71,6 +71,7 @@ SIGNATURES = {
     "qw_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "qw_build_index": (ctypes.c_int, [_P, _I64, _I32, _I32, _P, _P, _F32, _I32, _I32, _P, _P, _P]),
     "qw_query_workload": (ctypes.c_int, [_P, _P, _I64, _I32, _P, _P, _P, _P, _P]),
+    "qw_query_workload_noalloc": (ctypes.c_int, [_P, _P, _I64, _I32, _P, _P, _P]),
     "qw_free_index": (None, [_P]),
     "qw_get_index_info": (ctypes.c_int, [_P, _P]),
     "qw_hash": (ctypes.c_int, [_P, _P, _I64, _I32, _P, _P, _P]),
@@ -187,6 +188,16 @@ def qw_query_workload(ix, queries: torch.Tensor, K: int, opts: Optional[qw_opts]
                                   ctypes.byref(st) if st is not None else None)
     _check(rc, "qw_query_workload")
     return (out_ids, out_dist, st.as_dict()) if stats else (out_ids, out_dist)
+
+
+def qw_query_workload_noalloc(ix, queries: torch.Tensor, K: int, out_ids: torch.Tensor,
+                              out_dist: torch.Tensor, stream=None):
+    """The allocation-free plain-form query: the caller passes the outputs."""
+    queries = _dev(queries, (torch.uint8, torch.float32), "queries")
+    rc = load().qw_query_workload_noalloc(ix, _ptr(queries), queries.shape[0], int(K),
+                                          _stream(stream), _ptr(out_ids), _ptr(out_dist))
+    _check(rc, "qw_query_workload_noalloc")
+    return out_ids, out_dist
 
 
 def qw_free_index(ix):
