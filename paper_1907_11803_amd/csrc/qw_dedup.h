@@ -103,32 +103,50 @@ __device__ inline int layer_of(int i, uint32_t pmagic)
     return pmagic ? (int)(((uint32_t)i * pmagic) >> 20) : i;
 }
 
-// Wave 0 only: lpref[1..L] holds the L list sizes; turns lpref[0..L] into
-// their exclusive prefix and returns the total (L <= 64).
-__device__ inline uint32_t wave_layer_prefix(uint32_t *lpref, int L)
+// The lists' id offsets: after a prefix below, lstart[i] maps a position p of
+// the concatenated lists that falls in list i to ids[lstart[i] + p]: the
+// list's start in its layer plus layer_of(i) * n, minus its prefix (wrapping
+// uint32 arithmetic; the index itself is below 2^31 since n * L < 2^31).
+__device__ inline uint32_t list_offset(int i, uint32_t start, uint32_t excl, int64_t n, uint32_t pmagic)
+{
+    return (uint32_t)layer_of(i, pmagic) * (uint32_t)n + start - excl;
+}
+
+// Wave 0 only: lpref[1..L] holds the L list sizes and lstart[0..L) their
+// starts within their layers; turns lpref[0..L] into the exclusive prefix of
+// the sizes and lstart into the list offsets, and returns the total (L <= 64).
+__device__ inline uint32_t wave_layer_prefix(uint32_t *lpref, uint32_t *lstart, int L, int64_t n,
+                                             uint32_t pmagic)
 {
     const int lane = threadIdx.x & 63;
-    uint32_t v = lane < L ? lpref[lane + 1] : 0u;
+    const uint32_t sz = lane < L ? lpref[lane + 1] : 0u;
+    uint32_t v = sz;
     for (int off = 1; off < 64; off <<= 1) {
         const uint32_t t = (uint32_t)__shfl_up((int)v, off);
         if (lane >= off) v += t;
     }
-    if (lane < L) lpref[lane + 1] = v;
+    if (lane < L) {
+        lpref[lane + 1] = v;
+        lstart[lane] = list_offset(lane, lstart[lane], v - sz, n, pmagic);
+    }
     if (lane == 0) lpref[0] = 0;
     return (uint32_t)__shfl((int)v, 63);
 }
 
-// Whole workgroup: lpref[1..nl] holds the nl list sizes (nl <= 4 * kBlock);
-// turns lpref[0..nl] into their exclusive prefix and returns the total in
-// every thread.  tmp: kBlock / 64 words of LDS.  Barriers inside.
-__device__ inline uint32_t block_list_prefix(uint32_t *lpref, int nl, uint32_t *tmp)
+// Whole workgroup: lpref[1..nl] holds the nl list sizes and lstart[0..nl)
+// their starts (nl <= 4 * kBlock); turns lpref[0..nl] into their exclusive
+// prefix and lstart into the list offsets, and returns the total in every
+// thread.  tmp: kBlock / 64 words of LDS.  Barriers inside.
+__device__ inline uint32_t block_list_prefix(uint32_t *lpref, uint32_t *lstart, int nl, int64_t n,
+                                             uint32_t pmagic, uint32_t *tmp)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    uint32_t v[4], s = 0;
+    uint32_t v[4], st[4], s = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int e = 4 * tid + i;
         v[i] = e < nl ? lpref[e + 1] : 0u;
+        st[i] = e < nl ? lstart[e] : 0u;
         s += v[i];
     }
     uint32_t incl = s;
@@ -147,8 +165,11 @@ __device__ inline uint32_t block_list_prefix(uint32_t *lpref, int nl, uint32_t *
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int e = 4 * tid + i;
+        if (e < nl) {
+            lstart[e] = list_offset(e, st[i], run, n, pmagic);
+            lpref[e + 1] = run + v[i];
+        }
         run += v[i];
-        if (e < nl) lpref[e + 1] = run;
     }
     if (tid == 0) lpref[0] = 0;
     __syncthreads();
@@ -156,42 +177,52 @@ __device__ inline uint32_t block_list_prefix(uint32_t *lpref, int nl, uint32_t *
 }
 
 // Loads positions base + r * kBlock + threadIdx.x (r < R) of the concatenated
-// bucket lists (list i holds positions [lpref[i], lpref[i+1]) and starts at
-// ids[layer_of(i) * n + lstart[i]]) into id[r]; returns the mask of positions
-// below T.  The lists are found by one interleaved binary search (TOP = the
-// largest power of two below the list count: 32 for at most 64 lists), so all
-// R searches and then all R loads are in flight together.
+// bucket lists (list i holds positions [lpref[i], lpref[i+1]); lstart holds
+// the list offsets of a prefix above) into id[r]; returns the mask of
+// positions below T.  The list of a position is found by a binary search
+// (TOP = the largest power of two below the list count: 32 for at most 64
+// lists), four positions interleaved so their reads and loads are in flight
+// together; each group of four positions starts only if some position of the
+// workgroup's group lies below T (uniform), so the work follows the query's
+// list total rather than R.
 template <int R, int TOP = 32>
-__device__ inline uint32_t load_ids(const int32_t *__restrict__ ids, int64_t n, int32_t nl,
-                                    uint32_t pmagic, const uint32_t *lpref,
-                                    const uint32_t *lstart, uint32_t T, uint32_t base,
-                                    uint32_t (&id)[R])
+__device__ inline uint32_t load_ids(const int32_t *__restrict__ ids, int32_t nl,
+                                    const uint32_t *lpref, const uint32_t *lstart, uint32_t T,
+                                    uint32_t base, uint32_t (&id)[R])
 {
-    uint32_t pos[R];
-    int lo[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        pos[r] = base + (uint32_t)(r * kBlock) + threadIdx.x;
-        lo[r] = 0;
-    }
-#pragma unroll
-    for (int step = TOP; step > 0; step >>= 1)
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            // largest i < nl with lpref[i] <= pos; lpref[nl] = T > pos stops the
-            // search at the end without a branch around the read
-            const int m = lo[r] + step;
-            const uint32_t v = lpref[m < nl ? m : nl];
-            lo[r] = v <= pos[r] ? m : lo[r];
-        }
+    static_assert(R % 4 == 0, "groups of four positions");
     uint32_t valid = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        id[r] = 0;
-        if (pos[r] < T) {
-            const int i = lo[r];
-            id[r] = (uint32_t)ids[(int64_t)layer_of(i, pmagic) * n + lstart[i] + (pos[r] - lpref[i])];
-            valid |= 1u << r;
+    for (int g = 0; g < R / 4; ++g) {
+        if (base + (uint32_t)(4 * g * kBlock) < T) {  // uniform
+            uint32_t pos[4];
+            int lo[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                pos[r] = base + (uint32_t)((4 * g + r) * kBlock) + threadIdx.x;
+                lo[r] = 0;
+            }
+#pragma unroll
+            for (int step = TOP; step > 0; step >>= 1)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    // largest i < nl with lpref[i] <= pos; lpref[nl] = T > pos stops
+                    // the search at the end without a branch around the read
+                    const int m = lo[r] + step;
+                    const uint32_t v = lpref[m < nl ? m : nl];
+                    lo[r] = v <= pos[r] ? m : lo[r];
+                }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                id[4 * g + r] = 0;
+                if (pos[r] < T) {
+                    id[4 * g + r] = (uint32_t)ids[lstart[lo[r]] + pos[r]];
+                    valid |= 1u << (4 * g + r);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) id[4 * g + r] = 0;
         }
     }
     return valid;
@@ -206,8 +237,8 @@ __device__ inline uint32_t load_ids(const int32_t *__restrict__ ids, int64_t n, 
 // and *cpos must be 0 and visible to all threads on entry; returns after a
 // barrier.
 template <int TOP = 32>
-__device__ __attribute__((always_inline)) inline void set_union(const int32_t *__restrict__ ids, int64_t n, int32_t nl,
-                                 uint32_t pmagic, const uint32_t *lpref, const uint32_t *lstart, uint32_t T,
+__device__ __attribute__((always_inline)) inline void set_union(const int32_t *__restrict__ ids, int32_t nl,
+                                 const uint32_t *lpref, const uint32_t *lstart, uint32_t T,
                                  uint32_t *tab, int cap_log2, uint32_t limit, bool glob,
                                  uint32_t max_probe, bool compact, uint32_t *ucount,
                                  uint32_t *ovf, uint32_t *cpos)
@@ -217,7 +248,7 @@ __device__ __attribute__((always_inline)) inline void set_union(const int32_t *_
     const unsigned long long lt_mask = lane ? (~0ull >> (64 - lane)) : 0ull;
     // the next round's ids load while this round's are inserted
     uint32_t idn[R];
-    uint32_t pn = load_ids<R, TOP>(ids, n, nl, pmagic, lpref, lstart, T, 0u, idn);
+    uint32_t pn = load_ids<R, TOP>(ids, nl, lpref, lstart, T, 0u, idn);
     for (uint32_t base = 0; base < T; base += R * kBlock) {
         // every thread reads the flag before any thread of this pass can set
         // it, so the early exit is uniform
@@ -228,7 +259,7 @@ __device__ __attribute__((always_inline)) inline void set_union(const int32_t *_
 #pragma unroll
         for (int r = 0; r < R; ++r) idr[r] = idn[r];
         const uint32_t pend = pn;
-        if (base + R * kBlock < T) pn = load_ids<R, TOP>(ids, n, nl, pmagic, lpref, lstart, T, base + R * kBlock, idn);
+        if (base + R * kBlock < T) pn = load_ids<R, TOP>(ids, nl, lpref, lstart, T, base + R * kBlock, idn);
         bool full = false;
         uint32_t nnew = (uint32_t)__popc(insert_streams<R, 4>(tab, cap_log2, idr, pend, max_probe, full));
         // one LDS atomic per wave for the unique count

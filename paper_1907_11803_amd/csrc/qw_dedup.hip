@@ -563,8 +563,8 @@ __global__ __launch_bounds__(kBlock, 4) void dedup_kernel(DedupArgs A)
         }
         bar();
         uint32_t run = 0;
-        if (MP) run = block_list_prefix(lpref, A.nl, &scal[D_WT]);  // every thread
-        else if (tid < 64) run = wave_layer_prefix(lpref, A.nl);
+        if (MP) run = block_list_prefix(lpref, lstart, A.nl, A.n, A.pmagic, &scal[D_WT]);  // every thread
+        else if (tid < 64) run = wave_layer_prefix(lpref, lstart, A.nl, A.n, A.pmagic);
         if (tid < 64) {
             if (tid == 0) {
                 scal[D_T] = run;
@@ -588,7 +588,7 @@ __global__ __launch_bounds__(kBlock, 4) void dedup_kernel(DedupArgs A)
         uint32_t idr[kRegIds];
         uint32_t pend = 0;
         if (in_regs)  // the id loads fly while the set is cleared
-            pend = load_ids<kRegIds, kTop>(A.ids, A.n, A.nl, A.pmagic, lpref, lstart, T, 0u, idr);
+            pend = load_ids<kRegIds, kTop>(A.ids, A.nl, lpref, lstart, T, 0u, idr);
         for (uint32_t i = 4 * tid; i < cap; i += 4 * kBlock)  // cap >= 1024: whole 16-byte stores
             *reinterpret_cast<uint4 *>(tab + i) = uint4{kEmpty, kEmpty, kEmpty, kEmpty};
         if (glob) __threadfence();
@@ -614,7 +614,7 @@ __global__ __launch_bounds__(kBlock, 4) void dedup_kernel(DedupArgs A)
             U = tot;
             ovf = scal[D_OVF] != 0 || U > limit;
         } else {
-            set_union<kTop>(A.ids, A.n, A.nl, A.pmagic, lpref, lstart, T, tab, cap_log2, limit, glob, max_probe,
+            set_union<kTop>(A.ids, A.nl, lpref, lstart, T, tab, cap_log2, limit, glob, max_probe,
                       true, &scal[D_UCOUNT], &scal[D_OVF], &scal[D_CPOS]);
             U = scal[D_UCOUNT];
             ovf = scal[D_OVF] != 0 || U > limit;
@@ -663,8 +663,11 @@ __global__ __launch_bounds__(kBlock, 4) void dedup_kernel(DedupArgs A)
             if (in_regs) {
                 uint32_t e = wbase;
 #pragma unroll
-                for (int r = 0; r < kRegIds; ++r)
-                    if ((newm >> r) & 1u) tab[e++] = idr[r];
+                for (int g = 0; g < kRegIds / 4; ++g)
+                    if ((uint32_t)(4 * g * kBlock) < T)  // uniform: groups that held ids
+#pragma unroll
+                        for (int r = 4 * g; r < 4 * g + 4; ++r)
+                            if ((newm >> r) & 1u) tab[e++] = idr[r];
                 bar();
             }
             LaneTop top;

@@ -237,8 +237,8 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
             if (DT == QW_U8 && qq) atomicAdd(&scal[S_QQ], qq);
         }
         uint32_t run = 0;
-        if (A.nl > 64) run = block_list_prefix(lpref, A.nl, &scal[S_TMP]);  // uniform
-        else if (tid < 64) run = wave_layer_prefix(lpref, A.nl);
+        if (A.nl > 64) run = block_list_prefix(lpref, lstart, A.nl, A.n, A.pmagic, &scal[S_TMP]);  // uniform
+        else if (tid < 64) run = wave_layer_prefix(lpref, lstart, A.nl, A.n, A.pmagic);
         if (tid < 64) {
             if (tid == 0) {
                 scal[S_T] = run;
@@ -266,11 +266,11 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
         if (A.mode != VM_ALL) {
             const uint32_t mprobe = A.short_probe ? kShortProbe : 0xFFFFFFFFu;
             if (A.nl > 64)  // uniform: neighbour probing, up to kMaxLists lists
-                set_union<kMaxLists / 2>(A.ids, A.n, A.nl, A.pmagic, lpref, lstart, T, tab, cap_log2,
+                set_union<kMaxLists / 2>(A.ids, A.nl, lpref, lstart, T, tab, cap_log2,
                                          limit, glob != 0, mprobe, true, &scal[S_UCOUNT],
                                          &scal[S_OVF], &scal[S_CPOS]);
             else
-                set_union<32>(A.ids, A.n, A.nl, A.pmagic, lpref, lstart, T, tab, cap_log2, limit,
+                set_union<32>(A.ids, A.nl, lpref, lstart, T, tab, cap_log2, limit,
                               glob != 0, mprobe, true, &scal[S_UCOUNT], &scal[S_OVF],
                               &scal[S_CPOS]);
         }
