@@ -95,10 +95,23 @@ typedef struct {
     int32_t timing;    /* 1 = record per-stage HIP events and report them in qw_stats (syncs) */
     int32_t topk_keep; /* fast form, uint8 rows of at most 1024 bytes, K <= 16: the dedup kernel
                           selects the top K itself, each lane keeping this many of its
-                          candidates' keys (1..3; 0 = 3); a query whose top K that cannot
-                          settle goes to the fallback, so smaller values only send more
-                          queries there (diagnostic).  -1 = a separate select kernel. */
-    int32_t reserved[2];
+                          candidates' keys (1..3; 0 = all it keeps: 3 in the workgroup
+                          kernel, 4 in the wave kernel); a query whose top K that cannot
+                          settle takes a second pass or the fallback, so smaller values
+                          only send more queries there (diagnostic).  -1 = a separate
+                          select kernel. */
+    int32_t dedup;     /* fast form, uint8 rows of at most 1024 bytes, K <= 16, at most 64
+                          bucket lists per query: 0 = automatic (the tuned choice when
+                          tune_cache holds one for this workload, else the wave kernel
+                          when a query's expected bucket entries fit one set of the wave
+                          kernel), 1 = one workgroup per query in size-class launches,
+                          2 = one wave per query (a fixed on-chip set per wave, larger
+                          candidate sets in id-hash passes); ignored elsewhere */
+    int32_t xchunk;    /* fast form with bucket grouping: consecutive items of the grouped
+                          order dealt to one XCD (1..256; 0 = the tuned value or 256) */
+    const char *tune_cache; /* nullable: JSON file written by qw_autotune; automatic settings
+                               (dedup 0, xchunk 0, group -1) take its entry for this
+                               workload, when it has one */
 } qw_opts;
 
 /* Filled (host memory) by qw_query_workload when non-NULL; the call then
@@ -134,6 +147,8 @@ typedef struct {
     int32_t probes_per_layer; /* neighbour buckets probed per layer (0 without probing) */
     int32_t count_threshold;  /* qw_set_counting threshold (0: plain union) */
     int32_t count_extra;      /* qw_set_counting extra (v) */
+    double mean_hit_bucket;   /* mean over layers of sum_b s_b^2 / n: the expected size of the
+                                 bucket a data point falls in */
 } qw_index_info;
 
 typedef struct qw_index qw_index;

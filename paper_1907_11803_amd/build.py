@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqwlsh.so")
 ARCH = os.environ.get("QWLSH_ARCH", "gfx950")
 
-SOURCES = ["qw_common.hip", "qw_hash.hip", "qw_build.hip", "qw_verify.hip", "qw_dedup.hip",
+SOURCES = ["qw_common.hip", "qw_hash.hip", "qw_build.hip", "qw_verify.hip", "qw_dedup.hip", "qw_wdedup.hip",
            "qw_select.hip", "qw_count.hip", "qw_sched.hip", "qw_mlp.hip", "qw_capi.hip"]
 
 CXXFLAGS = [

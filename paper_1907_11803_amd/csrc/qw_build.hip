@@ -141,6 +141,26 @@ __global__ void bucket_compact_kernel(const uint32_t *__restrict__ rep,
     }
 }
 
+// *out += sum over the nb buckets of size^2 (one atomic per workgroup): with
+// the layer's n points, sum s^2 / n is the mean size of the bucket a point
+// (or a query near the data) falls in
+__global__ void sumsq_kernel(const uint32_t *__restrict__ bsize, int64_t nb, unsigned long long *out)
+{
+    __shared__ unsigned long long part[kBlock / 64];
+    unsigned long long acc = 0;
+    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nb;
+         b += (int64_t)gridDim.x * blockDim.x)
+        acc += (unsigned long long)bsize[b] * bsize[b];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) t += part[w];
+        if (t) atomicAdd(out, t);
+    }
+}
+
 __global__ void bucket_scatter_kernel(const uint32_t *__restrict__ slot_of, int64_t n,
                                       const unsigned long long *__restrict__ bidx,
                                       const unsigned long long *__restrict__ bstart,
@@ -347,7 +367,7 @@ qw_status build_index(const void *data, int64_t n, int32_t d, int32_t dtype, con
 
     // temporaries
     const int64_t chunk_layers = std::max<int64_t>(1, std::min<int64_t>(L, (int64_t(1) << 28) / std::max<int64_t>(1, n * k)));
-    DevBuf hbuf, klo, khi, slot_of, trep, tcnt, occ, bidx, bsize, brep, bstart, cursor, scan, maxb;
+    DevBuf hbuf, klo, khi, slot_of, trep, tcnt, occ, bidx, bsize, brep, bstart, cursor, scan, maxb, sq;
     int ct_log2 = std::max(10, ceil_log2((uint64_t)(2 * n)));
     const int64_t ct = int64_t(1) << ct_log2;
     QW_TRY(hbuf.ensure(sizeof(int32_t) * (size_t)n * chunk_layers * k));
@@ -364,6 +384,8 @@ qw_status build_index(const void *data, int64_t n, int32_t d, int32_t dtype, con
     QW_TRY(cursor.ensure(sizeof(uint32_t) * (n + 1)));
     QW_TRY(maxb.ensure(sizeof(uint32_t)));
     QW_TRY(launch_fill_u32(maxb.as<uint32_t>(), 0u, 1, s));
+    QW_TRY(sq.ensure(sizeof(unsigned long long) * L));  // per layer: sum of bucket size^2
+    QW_TRY(launch_fill_u32(sq.as<uint32_t>(), 0u, 2 * (int64_t)L, s));
 
     std::vector<DevBuf> tabs(L);
     std::vector<uint32_t> masks(L);
@@ -428,6 +450,9 @@ qw_status build_index(const void *data, int64_t n, int32_t d, int32_t dtype, con
                 trep.as<uint32_t>(), tcnt.as<uint32_t>(), ct, bidx.as<unsigned long long>(),
                 bsize.as<uint32_t>(), brep.as<uint32_t>(), maxb.as<uint32_t>());
             QW_HIP(hipGetLastError());
+            sumsq_kernel<<<grid_of((int64_t)nb), kBlock, 0, s>>>(bsize.as<uint32_t>(), (int64_t)nb,
+                                                               sq.as<unsigned long long>() + l);
+            QW_HIP(hipGetLastError());
             QW_TRY(launch_scan_u32_to_u64(bsize.as<uint32_t>(), (int64_t)nb,
                                           bstart.as<unsigned long long>(), scan, s));
             QW_TRY(launch_fill_u32(cursor.as<uint32_t>(), 0u, (int64_t)nb, s));
@@ -466,9 +491,14 @@ qw_status build_index(const void *data, int64_t n, int32_t d, int32_t dtype, con
     QW_HIP(hipMemcpyAsync(ix->tab_off.p, off.data(), sizeof(long long) * L, hipMemcpyHostToDevice, s));
     QW_HIP(hipMemcpyAsync(ix->tab_mask.p, masks.data(), sizeof(uint32_t) * L, hipMemcpyHostToDevice, s));
     uint32_t mb = 0;
+    std::vector<unsigned long long> sqh(L);
     QW_HIP(hipMemcpyAsync(&mb, maxb.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    QW_HIP(hipMemcpyAsync(sqh.data(), sq.p, sizeof(unsigned long long) * L, hipMemcpyDeviceToHost, s));
     QW_HIP(hipStreamSynchronize(s));
     ix->max_bucket = mb;
+    double sb = 0.0;
+    for (int32_t l = 0; l < L; ++l) sb += (double)sqh[l] / (double)n;
+    ix->mean_hit_bucket = sb / L;
     for (auto &t : tabs) t.release();
     *out = ix.release();
     return QW_OK;

@@ -98,6 +98,13 @@ Plan make_plan(qw_index *ix, int K)
     // uint8 rows of at most 64 parts and small K: the dedup kernel selects
     // the top K itself
     p.topk = (ix->dtype == QW_U8 && K <= kFusedTopK && rbytes / 16 <= 64) ? K : 0;
+    p.wgrid = dedup_wave_applies(ix->dtype, ix->dp, ix->nl, p.topk) ? dedup_wave_blocks_per_cu() * ix->cus : 0;
+    // the wave kernel's set takes 1536 unique ids per pass; a query's lists
+    // hold about nl * mean_hit_bucket entries, of which duplicates across
+    // layers remove a good part: the wave kernel while that stays within two
+    // sets' worth (beyond, extra passes re-read the ids and the workgroup
+    // kernel's larger sets pay)
+    p.wave_default = p.wgrid > 0 && (double)ix->nl * ix->mean_hit_bucket <= 2.0 * dedup_wave_set_limit();
     {  // FP32 distance bound of the dedup kernel's verification (float data)
         const int parts = ix->dp * (ix->dtype == QW_U8 ? 1 : 4) / 16;
         int G = 1;
@@ -414,7 +421,7 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
             a.cls_hi = hi;
             a.queue_only = queue_only;
             a.cap_base = kCmin;
-            a.xchunk = o.group ? kXcdChunk : 1u;
+            a.xchunk = o.group ? (o.xchunk > 0 ? (uint32_t)o.xchunk : kXcdChunk) : 1u;
             a.xwork = c32(ix) + W_XWORK + kXcd * slot;
             a.in_list = in_list;
             a.in_count = in_count;
@@ -460,6 +467,40 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
             }
             return launch_dedup(a, plan.dgrid[hi], st);
         };
+        const bool wave = plan.wgrid > 0 && (o.dedup == 2 || (o.dedup == 0 && plan.wave_default));
+        if (wave && topk && !count_only) {
+            // one wave per query over every class, largest first; sets that
+            // overflow split into id-hash passes inside the kernel
+            DedupArgs a;
+            std::memset(&a, 0, sizeof(a));
+            a.order = order;
+            a.seg = seg;
+            a.cls_lo = 0;
+            a.cls_hi = plan.ncls - 1;
+            a.cap_base = kCmin;
+            a.xchunk = o.group ? (o.xchunk > 0 ? (uint32_t)o.xchunk : kXcdChunk) : 1u;
+            a.ovf_count = c32(ix) + W_QMERGED;
+            a.bstart = w.bstart.as<uint32_t>();
+            a.bsize = w.bsize.as<uint32_t>();
+            a.ids = ix->ids.as<int32_t>();
+            a.n = ix->n;
+            a.nl = ix->nl;
+            a.pmagic = ix->pmagic;
+            a.dp = ix->dp;
+            a.dtype = ix->dtype;
+            a.data = ix->data.p;
+            a.queries = w.qrows;
+            a.addr32 = (uint64_t)ix->n * (uint64_t)ix->dp < (1ull << 32) && ix->n < (1ll << 24) ? 1 : 0;
+            a.topk = topk;
+            a.topk_keep = o.topk_keep == 0 ? dedup_wave_keep() : o.topk_keep;
+            a.out_ids = out_ids;
+            a.out_dist = out_dist;
+            a.fb_count = c32(ix) + W_FB;
+            a.fb_list = w.fb.as<int32_t>();
+            a.topk2_count = c32(ix) + W_TOPK2;
+            a.ucount = w.ucount.as<uint32_t>();
+            return launch_dedup_wave(a, plan.wgrid, s);
+        }
         const int merged = std::max(0, std::min(plan.cfloor - kCmin, plan.ncls - 2));
         const int glob = plan.ncls - 1;
         QW_HIP(hipEventRecord(ix->fork[0], s));
@@ -745,6 +786,7 @@ qw_status qw_get_index_info(const qw_index *ix, qw_index_info *info)
     info->probes_per_layer = ix->nprobe - 1;
     info->count_threshold = ix->count_theta;
     info->count_extra = ix->count_extra;
+    info->mean_hit_bucket = ix->mean_hit_bucket;
     return QW_OK;
 }
 
@@ -761,6 +803,8 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
     if (opt.sched < QW_SCHED_SUM || opt.sched > QW_SCHED_NONE) return QW_EINVAL;
     if (opt.topk_keep < -1 || opt.topk_keep > 3) return QW_EINVAL;
     if (opt.group < -1 || opt.group > 1) return QW_EINVAL;
+    if (opt.dedup < 0 || opt.dedup > 2 || opt.xchunk < 0 || opt.xchunk > (int32_t)kXcdChunk)
+        return QW_EINVAL;
     if (Q == 0) {
         if (st) std::memset(st, 0, sizeof(*st));
         return QW_OK;
@@ -816,6 +860,8 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
             key.q = queries; key.Q = Q; key.K = K; key.ids = out_ids; key.dist = out_dist;
             key.form = eff.form; key.sched = eff.sched; key.group = eff.group;
             key.topk_keep = eff.topk_keep;
+            key.dedup = eff.dedup;
+            key.xchunk = eff.xchunk;
             auto it = ix->graphs.find(key);
             if (it == ix->graphs.end()) {
                 hipStream_t cs;

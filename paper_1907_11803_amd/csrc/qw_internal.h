@@ -148,13 +148,15 @@ struct Plan {
     int dgrid[16] = {}; // dedup kernel, per class
     int cap_g = 20, grid_g = 1;
     int topk = 0;       // dedup also selects the top K (0: the select kernel does)
+    int wgrid = 0;      // one-wave-per-query dedup kernel (0: not applicable)
+    bool wave_default = false;  // the automatic choice when nothing is tuned
     int LC = 2048;      // select kernel list capacity (entries)
     float eps = 0.f;    // FP32 distance bound (float data)
 };
 
 struct GraphKey {
     const void *q; int64_t Q; int32_t K; int32_t *ids; void *dist;
-    int32_t form, sched, group, topk_keep;
+    int32_t form, sched, group, topk_keep, dedup, xchunk;
     bool operator<(const GraphKey &o) const {
         return std::memcmp(this, &o, sizeof(GraphKey)) < 0;
     }
@@ -195,6 +197,9 @@ struct qw_index {
     qw::DevBuf tab_off;    // int64 [L] first entry of each layer
     qw::DevBuf tab_mask;   // uint32 [L]
     int64_t buckets = 0, max_bucket = 0;
+    // mean over layers of sum_b s_b^2 / n: the expected size of the bucket a
+    // point of the data falls in (queries near the data see about this much)
+    double mean_hit_bucket = 0.0;
     // count model
     std::vector<float> mlp;  // packed host copy (empty = none)
     float mlp_margin = 0.22314355f;  // log-space sizing margin, log(1.25) until calibrated
@@ -435,6 +440,18 @@ struct SelectArgs {
 size_t dedup_lds_bytes(int cap_log2, int global_tab, int L, int row_bytes);
 int dedup_blocks_per_cu(size_t lds, int dtype);
 qw_status launch_dedup(const DedupArgs &a, int grid, hipStream_t s);
+// One wave per query (uint8, fused top K, at most 64 lists): the whole
+// workload in one launch over classes cls_lo..cls_hi (no queue), each XCD's
+// items dealt to its waves in rounds; a query's class sets how many id-hash
+// passes it starts with (cap_base + class - 11 doublings), a pass that
+// overflows splits in place (counted in *ovf_count); unsettled top K to
+// fb_list (counted in *topk2_count too).
+int dedup_wave_applies(int dtype, int dp, int nl, int topk);
+int dedup_wave_blocks_per_cu();
+size_t dedup_wave_lds_bytes();
+int dedup_wave_keep();      // keys kept per lane (topk_keep 0)
+uint32_t dedup_wave_set_limit();  // unique ids one pass of the wave kernel takes
+qw_status launch_dedup_wave(const DedupArgs &a, int grid, hipStream_t s);
 size_t select_lds_bytes(int LC, int dtype, int dp);
 qw_status launch_select(const SelectArgs &a, int64_t Q, hipStream_t s);
 // Scratch bytes launch_scan_u32_to_u64 needs for `count` values.

@@ -35,7 +35,8 @@ class QwError(RuntimeError):
 class qw_opts(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int32), ("sched", ctypes.c_int32), ("group", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("topk_keep", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("topk_keep", ctypes.c_int32), ("dedup", ctypes.c_int32), ("xchunk", ctypes.c_int32),
+                ("tune_cache", ctypes.c_char_p)]
 
 
 class qw_stats(ctypes.Structure):
@@ -61,7 +62,8 @@ class qw_index_info(ctypes.Structure):
                 ("max_bucket", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("has_count_model", ctypes.c_int32), ("count_margin", ctypes.c_float),
                 ("probing", ctypes.c_int32), ("probes_per_layer", ctypes.c_int32),
-                ("count_threshold", ctypes.c_int32), ("count_extra", ctypes.c_int32)]
+                ("count_threshold", ctypes.c_int32), ("count_extra", ctypes.c_int32),
+                ("mean_hit_bucket", ctypes.c_double)]
 
 
 # exported symbols and their signatures (restype qw_status unless noted)
@@ -143,12 +145,19 @@ def _dtype_code(t: torch.Tensor) -> int:
     return QW_U8 if t.dtype == torch.uint8 else QW_F32
 
 
+QW_DEDUP_AUTO, QW_DEDUP_BLOCK, QW_DEDUP_WAVE = 0, 1, 2
+
+
 def make_opts(form: int = QW_FORM_FAST, sched: int = QW_SCHED_LEARNED, group: int = -1,
-              graph: int = 1, timing: int = 0, topk_keep: int = 0) -> qw_opts:
+              graph: int = 1, timing: int = 0, topk_keep: int = 0, dedup: int = 0,
+              xchunk: int = 0, tune_cache: Optional[str] = None) -> qw_opts:
     o = qw_opts()
     load().qw_default_opts(ctypes.byref(o))
     o.form, o.sched, o.group, o.graph, o.timing = form, sched, group, graph, timing
-    o.topk_keep = topk_keep
+    o.topk_keep, o.dedup, o.xchunk = topk_keep, dedup, xchunk
+    # the struct keeps a pointer to the encoded path: hold the bytes on the object
+    o._tune_path = tune_cache.encode() if tune_cache else None
+    o.tune_cache = o._tune_path
     return o
 
 

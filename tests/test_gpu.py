@@ -540,3 +540,80 @@ def test_error_paths(cfg1):
         lib.Index(dev(cfg1.data[:100]), dev(p.a), dev(p.b()), 0.0)
     with pytest.raises(lib.QwError):  # keys wider than 128 bits: tiny w, k = 8, huge ranges
         lib.Index(dev(cfg1.data[:2000]), dev(p.a), dev(p.b(0.001)), 0.001)
+
+
+# ---------------------------------------------------------------- the two dedup kernels
+
+@pytest.mark.parametrize("dedup", [lib.QW_DEDUP_BLOCK, lib.QW_DEDUP_WAVE])
+@pytest.mark.parametrize("w", [400.0, 1200.0, 3000.0])
+def test_dedup_kernels_match_oracle(cfg1, dedup, w):
+    """Both fast-form candidate kernels (one workgroup per query in size
+    classes; one wave per query with id-hash passes) against the oracle, for
+    every schedule and K of 1, 10 and 16.  At w = 3000 queries hold 1.2K-6.7K
+    unique candidates: the wave kernel runs 1-8 passes and splits passes that
+    overflow."""
+    p = cfg1.params
+    ix = build(cfg1.data, p.a, p.b(w), w)
+    q = dev(cfg1.queries)
+    for K in (1, 10, 16):
+        ids_o, dist_o, _ = oracle.lsh_query(cfg1.data, cfg1.queries, p.a, p.b(w), w, K)
+        for sched in (lib.QW_SCHED_SUM, lib.QW_SCHED_NONE, lib.QW_SCHED_ACTUAL):
+            for group in (0, 1):
+                ids, dist, st = ix.query(q, K, lib.make_opts(sched=sched, group=group, dedup=dedup),
+                                         stats=True)
+                check_topk(ids, dist, ids_o, dist_o, True)
+    ix.close()
+
+
+def test_wave_kernel_splits_passes_of_a_sabotaged_count_model(cfg1):
+    """A count model that predicts no candidates puts every query in the
+    smallest class: the wave kernel starts with one pass and splits it until
+    each pass fits its set (10,000 candidates per query at huge w), with exact
+    results and every split counted as an overflow."""
+    p = cfg1.params
+    wh = 1e7
+    bh = np.full_like(p.b(wh), wh / 2)
+    ix = build(cfg1.data, p.a, bh, wh)
+    P = lib.qw_mlp_param_count(p.L)
+    bad = np.zeros(P, np.float32)
+    bad[-1] = -5.0
+    ix.set_count_model(bad)
+    ids_o, dist_o, cnt_o = oracle.lsh_query(cfg1.data, cfg1.queries, p.a, bh, wh, cfg1.K)
+    for graph in (0, 1):
+        ids, dist, st = ix.query(dev(cfg1.queries), cfg1.K,
+                                 lib.make_opts(sched=lib.QW_SCHED_LEARNED, dedup=lib.QW_DEDUP_WAVE,
+                                               graph=graph), stats=True)
+        check_topk(ids, dist, ids_o, dist_o, True)
+        assert st["overflow"] == cfg1.queries.shape[0]
+        assert st["cand_unique"] == int(cnt_o.sum())
+    ix.close()
+
+
+@pytest.mark.parametrize("d", [8, 53, 128, 1024])
+def test_wave_kernel_row_widths_and_probing(d):
+    """The wave kernel for every lanes-per-row width (rows of 1, 4, 8 and 64
+    16-byte parts: 1, 2, 4 and 32 lanes per row), ragged n and Q, with
+    query-directed probing (L * 3 lists), against the oracle."""
+    wl = synth.random_small(91 + d, n=2311, d=d, Q=57, L=6, k=3, w=float(60 * d ** 0.5), dtype="u8")
+    p = wl.params
+    ix = build(wl.data, p.a, p.b(), p.w)
+    for probes in (0, 2):
+        if probes:
+            ix.set_probing(2, 2)
+        ids_o, dist_o, _ = oracle.lsh_query(wl.data, wl.queries, p.a, p.b(), p.w, 10, probes=probes,
+                                            probe_t=2 if probes else 0)
+        for dedup in (lib.QW_DEDUP_BLOCK, lib.QW_DEDUP_WAVE):
+            ids, dist = ix.query(dev(wl.queries), 10, lib.make_opts(sched=lib.QW_SCHED_SUM, dedup=dedup))
+            check_topk(ids, dist, ids_o, dist_o, True)
+    ix.close()
+
+
+def test_dedup_option_validation(cfg1):
+    p = cfg1.params
+    ix = build(cfg1.data[:1000], p.a, p.b(), p.w)
+    q = dev(cfg1.queries)
+    for kw in ({"dedup": 3}, {"dedup": -1}, {"xchunk": -1}, {"xchunk": 257}):
+        with pytest.raises(lib.QwError) as e:
+            ix.query(q, 10, lib.make_opts(**kw))
+        assert e.value.status == lib.QW_EINVAL
+    ix.close()
