@@ -9,20 +9,23 @@ d=128 Gaussian mixture (1,000 components, sigma 20), Q=10,000 noisy data
 points, L=20 layers of k=10 functions, K=10.  Its stated bucket width w=400
 reaches recall@10 of only ~0.13, so the benchmark runs at w_0.9: the smallest w
 on the grid {1, 1.5, 2, 2.5, 3, 4, 6, 8} x 400 whose measured recall@10 (against
-GPU brute force over all points) is >= 0.9; L and k are unchanged.
+GPU brute force) is >= 0.9; L and k are unchanged.
 
-Reported: the fast form (FP16 MFMA + FP64 guard band, bucket grouping,
-learned-count binning, persistent verify, HIP graph) as `value`; the plain FP32
-form beside it; the verify kernel's achieved HBM bandwidth against the 8 TB/s
-peak; and the CPU oracle timed on a bounded query sample.
+Reported: the fast form (FP16 MFMA + FP64 guard band, learned-count binning,
+one-wave or one-workgroup-per-query candidate kernel, HIP graph) with the
+scheduling settings the autotuner picked for this workload as `value`; the
+plain FP32 form beside it; the candidate kernel's achieved HBM bandwidth
+against the 8 TB/s peak; the plain union (no neighbour probing) at its own
+w_0.9; the schedules on the 1M x 960 float Zipf workload; the index build's
+hashing rate; and the CPU oracle timed on a bounded query sample.
 """
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -33,6 +36,9 @@ MFMA_PEAK_FP16_TFLOPS = 2500.0  # dense FP16 matrix peak (no sparsity)
 MFMA_PEAK_FP32_TFLOPS = 157.3   # dense FP32 matrix peak
 W_GRID = [1, 1.5, 2, 2.5, 3, 4, 6, 8]
 METRIC = "queries/sec at recall@10>=0.9, BF16+learned vs plain FP32 on 1 MI355X"
+# w_0.9 of the 1M x 960 float Zipf workload without neighbour probing (8 x 1.5),
+# measured with the w search above; its leg re-measures the recall
+CFG5_W = 12.0
 
 
 def log(msg):
@@ -42,7 +48,6 @@ def log(msg):
 def recall_at_10(ids_lsh, ids_true, dist_lsh, dist_true):
     """Tie-tolerant recall@10: a returned id counts when it is one of the exact
     top-10 ids or its distance is <= the exact 10th distance."""
-    import numpy as np
     K = 10
     hits = 0
     for q in range(ids_lsh.shape[0]):
@@ -57,16 +62,60 @@ def recall_at_10(ids_lsh, ids_true, dist_lsh, dist_true):
     return hits / (K * ids_lsh.shape[0])
 
 
-def kernel_source_hash(files):
-    """Identifies a kernel's source: stored HBM traffic is used only while it
-    matches."""
-    h = hashlib.sha256()
-    for f in files:
-        h.update(open(os.path.join(ROOT, "paper_1907_11803_amd", "csrc", f), "rb").read())
-    return h.hexdigest()[:16]
+# the candidate kernels' sources (the stored traffic of each is tied to them)
+BLOCK_SOURCES = ("qw_dedup.hip", "qw_dedup.h", "qw_dist.h", "qw_wave.h")
+WAVE_SOURCES = ("qw_wdedup.hip", "qw_dedup.h", "qw_dist.h", "qw_wave.h")
 
 
-FUSED_SOURCES = ("qw_dedup.hip", "qw_dedup.h", "qw_dist.h", "qw_wave.h")
+def probe_tag(probes, probe_t):
+    return {0: "noprobe", 1: "allprobe", 2: f"qd{probe_t}"}[probes]
+
+
+def traffic_path(kfile, config, w, probes, probe_t):
+    """Stored FETCH/WRITE summary of one candidate kernel on one workload."""
+    return os.path.join(ROOT, "profiles",
+                        f"{kfile}_cfg{config}_w{w:g}_{probe_tag(probes, probe_t)}_traffic.json")
+
+
+def candidate_roofline(st, kms, Q, d, elem, K, is_u8, config, w, probes, probe_t):
+    """The dominant kernel: the candidate kernel, which also verifies its
+    candidates.  Algorithmic bytes per query: the bucket ids (4 per entry),
+    each unique candidate's row, the query row, and either each candidate's
+    (distance, id) key for the select kernel or, when the kernel selects the
+    top K itself (uint8 rows of at most 1024 bytes, K <= 16), the K output
+    pairs.  Its time: the dedup stage of one step (HIP events in the library,
+    on the stream the kernel runs on)."""
+    from paper_1907_11803_amd.profsum import source_hash
+    topk_fused = is_u8 and K <= 16 and (d + 15) // 16 <= 64
+    wave = topk_fused and st.get("dedup_used") == 2
+    if wave:
+        kname, kfile, ksrc = ("dedup_wave_kernel (dedup + verify + top-K, one wave per query)",
+                              "dedup_wave", WAVE_SOURCES)
+    else:
+        kname = "dedup_kernel (dedup + verify + top-K)" if topk_fused else "dedup_kernel (dedup + verify)"
+        kfile, ksrc = "dedup_verify", BLOCK_SOURCES
+    per_cand = d * elem + (0 if topk_fused else 8)
+    kbytes = (4 * st["cand_total"] + st["cand_unique"] * per_cand + Q * d * elem +
+              (8 * K * Q if topk_fused else 0))
+    achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else None
+    traffic = None
+    tfile = traffic_path(kfile, config, w, probes, probe_t)
+    if os.path.exists(tfile):
+        tj = json.load(open(tfile))
+        if (tj.get("source") == source_hash(ksrc) and abs(tj.get("w", -1) - w) < 1e-9
+                and tj.get("probes", 0) == probes
+                and tj.get("probe_t", 0) == (probe_t if probes == 2 else 0)):
+            traffic = tj.get("bytes_per_launch")
+    return {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+            "traffic": traffic, "kernel": kname,
+            # HBM bytes the counters saw over the same kernel time
+            "traffic_achieved": round(traffic / (kms * 1e-3) / 1e9, 1) if traffic and kms > 0 else None,
+            "traffic_frac": round(traffic / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if traffic and kms > 0 else None,
+            "traffic_file": os.path.relpath(tfile, ROOT),
+            "kernel_ms": round(kms, 4),
+            "kernel_algorithmic_bytes": int(kbytes)}
 
 
 def main():
@@ -93,8 +142,22 @@ def main():
                          "default 3 for config 2, else 0)")
     ap.add_argument("--count-v", type=int, default=800,
                     help="collision-counting leg: extra verified points v (K + v in all)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="tuning cache (JSON) to create or update; default: a fresh file in "
+                         "the temporary directory, removed at exit")
+    ap.add_argument("--no-tune", action="store_true", help="time the built-in automatic settings")
+    ap.add_argument("--dedup", type=int, default=0, choices=[0, 1, 2],
+                    help="candidate kernel (0: automatic/tuned, 1: workgroup, 2: wave per query)")
+    ap.add_argument("--group", type=int, default=-1, choices=[-1, 0, 1],
+                    help="bucket grouping (-1: automatic/tuned)")
+    ap.add_argument("--xchunk", type=int, default=0, help="XCD chunk with grouping (0: automatic/tuned)")
+    ap.add_argument("--no-union-leg", action="store_true",
+                    help="skip the plain-union leg (no neighbour probing, its own w_0.9)")
+    ap.add_argument("--no-float-leg", action="store_true",
+                    help="skip the schedules on the 1M x 960 float Zipf workload")
     ap.add_argument("--profile", action="store_true",
-                    help="only the fast-form timed loop (for rocprofv3 runs)")
+                    help="only the fast-form timed loop (for rocprofv3 runs): no tuning unless "
+                         "--tune-cache names an existing file")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this engine has no multi-GPU path (queries or data "
@@ -129,42 +192,94 @@ def main():
     a_d = torch.from_numpy(wl.params.a).to(dev)
     K = wl.K
     is_u8 = wl.data.dtype == np.uint8
+    elem = 1 if is_u8 else 4
+    L = wl.params.L
+    stream = torch.cuda.current_stream()
+    out_ids = torch.empty((wl.Q, K), dtype=torch.int32, device=dev)
+    out_dist = torch.empty((wl.Q, K), dtype=torch.int32 if is_u8 else torch.float32, device=dev)
 
-    # ---- choose w_0.9 (recall measured on every query against GPU brute force)
-    grid = [args.w] if args.w else [m * spec["w"] for m in W_GRID]
-    truth = None
-    chosen = None
-    tried = []
-    for w in grid:
-        b_d = torch.from_numpy(wl.params.b(w)).to(dev)
+    own_cache = args.tune_cache is None
+    tune_path = args.tune_cache or os.path.join(tempfile.gettempdir(), f"qwlsh_tune_{os.getpid()}.json")
+
+    def timed(index, opts, steps, warmup, queries=None, oi=None, od=None):
+        queries = q_d if queries is None else queries
+        oi = out_ids if oi is None else oi
+        od = out_dist if od is None else od
+        for _ in range(warmup):
+            index.query(queries, K, opts, out_ids=oi, out_dist=od)
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for _ in range(steps):
+            index.query(queries, K, opts, out_ids=oi, out_dist=od)
+        stop.record(stream)
+        torch.cuda.synchronize()
+        return start.elapsed_time(stop) / steps
+
+    def stage_times(index, kw, nrep=5, queries=None):
+        """Per-stage times of the fast pipeline (events inside the library)."""
+        queries = q_d if queries is None else queries
+        stage = np.zeros(8)
+        s = None
+        for _ in range(nrep):
+            _, _, s = index.query(queries, K, lib.make_opts(**kw, timing=1, graph=0), stats=True)
+            stage += np.array(s["ms_stage"])
+        return stage / nrep, s
+
+    def tune(index, queries, kw):
+        """Autotune the scheduling settings unless they are fixed; returns the
+        record for the bench line."""
+        if args.no_tune or args.profile:  # a profiling run takes an existing cache as it is
+            return None
+        if args.dedup or args.group >= 0 or args.xchunk:
+            return None
         t1 = time.time()
-        ix = lib.Index(data_d, a_d, b_d, w, form=lib.QW_FORM_FAST)
-        if args.probes:
-            ix.set_probing(args.probes, args.probe_t)
-        build_s = time.time() - t1
-        if args.profile:  # profiling runs time the query loop only
-            chosen = (w, ix, b_d, None, None)
-            break
-        if truth is None:
+        r = index.autotune(queries, K, tune_path, lib.make_opts(**kw))
+        r = {"choice": {"dedup": {1: "workgroup per query", 2: "wave per query"}[r["dedup"]],
+                        "group": r["group"], "xchunk": r["xchunk"]},
+             "ms": round(r["ms"], 4), "ms_default": round(r["ms_default"], 4),
+             "candidates": r["candidates"], "tune_s": round(time.time() - t1, 2)}
+        log(f"[bench] autotune: {r}")
+        return r
+
+    def search_w(probes, probe_t, grid, truth_box):
+        """The first w on the grid whose recall@10 reaches 0.9 (or the last)."""
+        tried = []
+        for w in grid:
+            b_d = torch.from_numpy(wl.params.b(w)).to(dev)
             t1 = time.time()
-            rs = wl.Q if args.recall_sample <= 0 else min(args.recall_sample, wl.Q)
-            rsel = np.sort(np.random.default_rng(11).choice(wl.Q, size=rs, replace=False))
-            rsel_d = torch.from_numpy(rsel).to(dev)
-            ti, td = ix.bruteforce(q_d[rsel_d].contiguous(), K)
-            torch.cuda.synchronize()
-            truth = (ti.cpu().numpy(), td.cpu().numpy())
-            log(f"[bench] brute-force ground truth for {rs} queries in {time.time() - t1:.1f}s")
-        ids, dist, st = ix.query(q_d, K, lib.make_opts(sched=lib.QW_SCHED_SUM, graph=0), stats=True)
-        rec = recall_at_10(ids.cpu().numpy()[rsel], truth[0], dist.cpu().numpy()[rsel], truth[1])
-        tried.append({"w": w, "recall_at_10": round(rec, 4),
-                      "mean_unique_candidates": st["cand_unique"] / wl.Q})
-        log(f"[bench] w={w}: recall@10={rec:.4f} unique/q={st['cand_unique'] / wl.Q:.0f} "
-            f"sum/q={st['cand_total'] / wl.Q:.0f} build {build_s:.1f}s")
-        if rec >= 0.9 or w == grid[-1]:
-            chosen = (w, ix, b_d, rec, st)
-            break
-        ix.close()
-    w, ix, b_d, rec, st0 = chosen
+            ix = lib.Index(data_d, a_d, b_d, w, form=lib.QW_FORM_FAST)
+            if probes:
+                ix.set_probing(probes, probe_t)
+            build_s = time.time() - t1
+            if args.profile:  # profiling runs time the query loop only
+                return w, ix, None, None, tried, build_s
+            if truth_box.get("truth") is None:
+                t1 = time.time()
+                rs = wl.Q if args.recall_sample <= 0 else min(args.recall_sample, wl.Q)
+                rsel = np.sort(np.random.default_rng(11).choice(wl.Q, size=rs, replace=False))
+                ti, td = ix.bruteforce(q_d[torch.from_numpy(rsel).to(dev)].contiguous(), K)
+                torch.cuda.synchronize()
+                truth_box["truth"] = (ti.cpu().numpy(), td.cpu().numpy())
+                truth_box["rsel"] = rsel
+                log(f"[bench] brute-force ground truth for {rs} queries in {time.time() - t1:.1f}s")
+            truth, rsel = truth_box["truth"], truth_box["rsel"]
+            ids, dist, st = ix.query(q_d, K, lib.make_opts(sched=lib.QW_SCHED_SUM, graph=0), stats=True)
+            rec = recall_at_10(ids.cpu().numpy()[rsel], truth[0], dist.cpu().numpy()[rsel], truth[1])
+            tried.append({"w": w, "recall_at_10": round(rec, 4),
+                          "mean_unique_candidates": st["cand_unique"] / wl.Q})
+            log(f"[bench] w={w} {probe_tag(probes, probe_t)}: recall@10={rec:.4f} "
+                f"unique/q={st['cand_unique'] / wl.Q:.0f} sum/q={st['cand_total'] / wl.Q:.0f} "
+                f"build {build_s:.1f}s")
+            if rec >= 0.9 or w == grid[-1]:
+                return w, ix, rec, st, tried, build_s
+            ix.close()
+
+    # ---- choose w_0.9 (recall measured against GPU brute force)
+    grid = [args.w] if args.w else [m * spec["w"] for m in W_GRID]
+    tb = {}
+    w, ix, rec, st0, tried, build_s = search_w(args.probes, args.probe_t, grid, tb)
 
     # ---- learned count model, trained on the engine's own features
     t1 = time.time()
@@ -172,7 +287,6 @@ def main():
     train = synth.training_queries(args.config, ntrain)
     train_d = torch.from_numpy(train).to(dev)
     train_loss = ix.train_count_model(train_d, epochs=8, batch=1024, lr=2e-3, seed=1)
-    del train_d
     log(f"[bench] count model trained on {ntrain} queries, loss {train_loss:.4f}, "
         f"sizing margin {ix.info()['count_margin']:.3f} "
         f"in {time.time() - t1:.1f}s")
@@ -181,32 +295,18 @@ def main():
         # prediction quality on the workload's own queries: log(1 + |C(q)|)
         feats = torch.log1p(ix.bucket_sizes(q_d).to(torch.float32)).contiguous()
         params = torch.from_numpy(ix.get_count_model()).to(dev)
-        pred = lib.qw_mlp_predict_bf16(params, wl.params.L, feats).cpu().numpy()
+        pred = lib.qw_mlp_predict_bf16(params, L, feats).cpu().numpy()
         actual = np.log1p(ix.candidate_counts(q_d).cpu().numpy().astype(np.float64))
         count_model = {"train_queries": int(ntrain), "train_loss": round(float(train_loss), 4),
                        "mae_log": round(float(np.mean(np.abs(pred - actual))), 4),
                        "sizing_margin": round(float(ix.info()["count_margin"]), 4)}
         log(f"[bench] count model on the workload: MAE {count_model['mae_log']} (log space)")
 
-    out_ids = torch.empty((wl.Q, K), dtype=torch.int32, device=dev)
-    out_dist = torch.empty((wl.Q, K), dtype=torch.int32 if is_u8 else torch.float32, device=dev)
-    stream = torch.cuda.current_stream()
-
-    def timed(opts, steps, warmup, index=None):
-        index = index or ix
-        for _ in range(warmup):
-            index.query(q_d, K, opts, out_ids=out_ids, out_dist=out_dist)
-        torch.cuda.synchronize()
-        start = torch.cuda.Event(enable_timing=True)
-        stop = torch.cuda.Event(enable_timing=True)
-        start.record(stream)
-        for _ in range(steps):
-            index.query(q_d, K, opts, out_ids=out_ids, out_dist=out_dist)
-        stop.record(stream)
-        torch.cuda.synchronize()
-        return start.elapsed_time(stop) / steps
-
-    fast_opts = lib.make_opts(form=lib.QW_FORM_FAST, sched=lib.QW_SCHED_LEARNED, group=-1, graph=1)
+    base_kw = dict(form=lib.QW_FORM_FAST, sched=lib.QW_SCHED_LEARNED)
+    autotune = tune(ix, q_d, base_kw)
+    fast_kw = dict(base_kw, group=args.group, dedup=args.dedup, xchunk=args.xchunk, graph=1,
+                   tune_cache=tune_path if os.path.exists(tune_path) else None)
+    fast_opts = lib.make_opts(**fast_kw)
     if args.profile:
         # a plain device copy of known size (1 GiB read + 1 GiB written) to
         # calibrate the HBM byte counters of a profiling run
@@ -216,7 +316,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-        ms = timed(fast_opts, args.steps, args.warmup)
+        _, _, sp = ix.query(q_d, K, fast_opts, stats=True)
+        log(f"[bench] profile settings: dedup {sp['dedup_used']} group {sp['group_used']} "
+            f"xchunk {sp['xchunk_used']} tuned {sp['tuned']}")
+        ms = timed(ix, fast_opts, args.steps, args.warmup)
         log(f"[bench] profile loop: {ms:.3f} ms/step")
         return
 
@@ -237,108 +340,89 @@ def main():
     torch.cuda.empty_cache()
     log(f"[bench] device copy: {copy_gbs:.0f} GB/s")
 
-    # exactness of the timed forms against each other and the brute-force recall
+    # exactness of the timed forms against each other
     ref_ids, ref_dist = ix.query(q_d, K, lib.make_opts(form=lib.QW_FORM_PLAIN_FP32))
     ref_ids, ref_dist = ref_ids.cpu().numpy(), ref_dist.cpu().numpy()
     f_ids, f_dist = ix.query(q_d, K, fast_opts)
-    identical = bool(np.array_equal(f_ids.cpu().numpy(), ref_ids) and
-                     np.array_equal(f_dist.cpu().numpy(), ref_dist))
+    f_ids_np, f_dist_np = f_ids.cpu().numpy(), f_dist.cpu().numpy()
+    identical = bool(np.array_equal(f_ids_np, ref_ids) and np.array_equal(f_dist_np, ref_dist))
 
     # ---- timed regions
-    ms_fast = timed(fast_opts, args.steps, args.warmup)
-    ms_plain = timed(lib.make_opts(form=lib.QW_FORM_PLAIN_FP32), args.steps, args.warmup)
-    # the schedules (count sources) under the automatic grouping, then the
-    # learned schedule with each fixed grouping; every one must return the
-    # fast form's results exactly
+    ms_fast = timed(ix, fast_opts, args.steps, args.warmup)
+    ms_plain = timed(ix, lib.make_opts(form=lib.QW_FORM_PLAIN_FP32), args.steps, args.warmup)
+    # the schedules (count sources) under the tuned settings, then the learned
+    # schedule with each fixed grouping and each candidate kernel; every one
+    # must return the fast form's results exactly
     sched_ms = {}
     sched_identical = True
-    variants = [(name, lib.make_opts(sched=sc)) for name, sc in (
+    tc = fast_kw["tune_cache"]
+    variants = [(name, lib.make_opts(sched=sc, tune_cache=tc)) for name, sc in (
         ("sum", lib.QW_SCHED_SUM), ("actual", lib.QW_SCHED_ACTUAL),
         ("none", lib.QW_SCHED_NONE), ("learned", lib.QW_SCHED_LEARNED))]
-    variants += [(f"learned_group{g}", lib.make_opts(sched=lib.QW_SCHED_LEARNED, group=g))
+    variants += [(f"learned_group{g}", lib.make_opts(sched=lib.QW_SCHED_LEARNED, group=g, tune_cache=tc))
                  for g in (0, 1)]
-    f_ids_np, f_dist_np = f_ids.cpu().numpy(), f_dist.cpu().numpy()
+    variants += [(f"learned_{nm}", lib.make_opts(sched=lib.QW_SCHED_LEARNED, dedup=dd, tune_cache=tc))
+                 for nm, dd in (("workgroup_kernel", 1), ("wave_kernel", 2))]
     for name, o in variants:
-        sched_ms[name] = round(timed(o, max(5, args.steps // 2), 2), 4)
+        sched_ms[name] = round(timed(ix, o, max(5, args.steps // 2), 2), 4)
         s_ids, s_dist = ix.query(q_d, K, o)
         sched_identical &= bool(np.array_equal(s_ids.cpu().numpy(), f_ids_np) and
                                 np.array_equal(s_dist.cpu().numpy(), f_dist_np))
     log(f"[bench] fast {ms_fast:.3f} ms/step, plain {ms_plain:.3f} ms/step, scheds {sched_ms}, "
         f"identical {sched_identical}")
 
-    # ---- per-stage timing of the fast pipeline (events inside the library)
-    stage = np.zeros(8)
-    nrep = 5
-    for _ in range(nrep):
-        _, _, s = ix.query(q_d, K, lib.make_opts(sched=lib.QW_SCHED_LEARNED, timing=1, graph=0),
-                           out_ids=out_ids, out_dist=out_dist, stats=True)
-        stage += np.array(s["ms_stage"])
-    stage /= nrep
-    st = s
-    elem = 1 if is_u8 else 4
-    L = wl.params.L
+    stage, st = stage_times(ix, {k: v for k, v in fast_kw.items() if k != "graph"})
     alg_bytes = (wl.Q * wl.d * elem + 8 * L * wl.Q + 4 * st["cand_total"] +
                  st["cand_unique"] * wl.d * elem + 8 * K * wl.Q)
-    # Dominant kernel: the dedup kernel, which also verifies its candidates;
-    # algorithmic bytes per query: the bucket ids (4 per entry), each unique
-    # candidate's row, the query row, and either each candidate's
-    # (distance, id) key for the select kernel or, when the kernel selects the
-    # top K itself (uint8 rows of at most 1024 bytes, K <= 16, the library's
-    # rule), the K output pairs.  Its time: the dedup stage (all of its
-    # launches of one step, on two streams).
-    topk_fused = is_u8 and K <= 16 and (wl.d + 15) // 16 <= 64
-    kname = "dedup_kernel (dedup + verify + top-K)" if topk_fused else "dedup_kernel (dedup + verify)"
-    ksrc, kfile = FUSED_SOURCES, "dedup_verify"
-    per_cand = wl.d * elem + (0 if topk_fused else 8)
-    kbytes = (4 * st["cand_total"] + st["cand_unique"] * per_cand + wl.Q * wl.d * elem +
-              (8 * K * wl.Q if topk_fused else 0))
-    kms = float(stage[6])
-    achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else None
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"{kfile}_cfg{args.config}_traffic.json")
-    if os.path.exists(tfile):
-        tj = json.load(open(tfile))
-        if (tj.get("source") == kernel_source_hash(ksrc) and abs(tj.get("w", -1) - w) < 1e-9
-                and tj.get("probes", 0) == args.probes
-                and tj.get("probe_t", 0) == (args.probe_t if args.probes == 2 else 0)):
-            traffic = tj.get("bytes_per_launch")
+    roof = candidate_roofline(st, float(stage[6]), wl.Q, wl.d, elem, K, is_u8, args.config, w,
+                              args.probes, args.probe_t)
+    roof["measured_copy_gbs"] = round(copy_gbs, 1)
+    roof["frac_of_measured_copy"] = round(roof["achieved"] / copy_gbs, 4) if roof["achieved"] else None
+    roof["path_algorithmic_bytes_per_step"] = int(alg_bytes)
+    settings = {"dedup": {1: "workgroup per query", 2: "wave per query"}.get(st["dedup_used"]),
+                "group": st["group_used"], "xchunk": st["xchunk_used"], "from_tune_cache": bool(st["tuned"])}
 
-    # ---- CPU oracle on a bounded sample
-    cpu = None
-    if not args.no_cpu:
-        import oracle
-        nthreads = max(1, min(16, os.cpu_count() or 1))
-        t1 = time.time()
-        bi = oracle.BuiltIndex(wl.data, wl.params.a, wl.params.b(w), w, nthreads=nthreads)
-        build_cpu = time.time() - t1
-        rng = np.random.default_rng(7)
-        ns = min(args.cpu_sample if args.cpu_sample > 0 else (10_000 if is_u8 else 1_000), wl.Q)
-        sample = np.sort(rng.choice(wl.Q, size=ns, replace=False))
-        t1 = time.time()
-        o_ids, o_dist, _ = bi.query(wl.queries[sample], K, probes=args.probes,
-                                    probe_t=args.probe_t if args.probes == 2 else 0)
-        q_cpu = time.time() - t1
-        bi.close()
-        cpu_match = bool(np.array_equal(o_ids, ref_ids[sample]))
-        cpu_model = None
-        try:
-            with open("/proc/cpuinfo") as f:
-                cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
-        except OSError:
-            pass
-        cpu = {"value": round(len(sample) / q_cpu, 2), "unit": "queries/s", "cores": nthreads,
-               "kind": "oracle", "cpu_model": cpu_model, "host_threads": os.cpu_count(),
-               "sample": f"{len(sample)} of {wl.Q} queries against the full {wl.n}-point index; "
-                         f"oracle index build {build_cpu:.1f}s excluded, query phase {q_cpu:.2f}s",
-               "matches_gpu": cpu_match}
-        log(f"[bench] oracle: {cpu['value']} q/s on {nthreads} threads (build {build_cpu:.1f}s)")
+    # ---- hashing: algorithmic projection flops against the dense MFMA peak of
+    # the type the kernel multiplies in (FP16 for uint8 data, FP32 for float),
+    # at query time (one step's hash stage) and over the n data rows the build
+    # hashes (the same kernel, timed on its own with events)
+    hash_peak = MFMA_PEAK_FP16_TFLOPS if is_u8 else MFMA_PEAK_FP32_TFLOPS
+    hash_flops = 2.0 * wl.d * L * wl.params.k * wl.Q
+    hash_tflops = hash_flops / (stage[0] * 1e-3) / 1e12 if stage[0] > 0 else None
+    ix.hash(data_d)  # warm: grows the workspace to n rows
+    hb = []
+    for _ in range(3):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        _, brec = ix.hash(data_d)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        hb.append(e0.elapsed_time(e1))
+    bms = min(hb)
+    build_tflops = 2.0 * wl.d * L * wl.params.k * wl.n / (bms * 1e-3) / 1e12
+    hash_info = {"kernel": "hash_mfma_f16_kernel" if is_u8 else "hash_mfma_f32_kernel",
+                 "query_ms": round(float(stage[0]), 4),
+                 "query_algorithmic_tflops": round(hash_tflops, 2) if hash_tflops else None,
+                 "peak_tflops": hash_peak,
+                 "query_frac": round(hash_tflops / hash_peak, 5) if hash_tflops else None,
+                 "build_rows": wl.n, "build_hash_ms": round(bms, 4),
+                 "build_algorithmic_tflops": round(build_tflops, 2),
+                 "build_frac": round(build_tflops / hash_peak, 5),
+                 "build_recompute_frac": round(brec / (wl.n * L * wl.params.k), 6),
+                 "index_build_s": round(build_s, 3)}
+    log(f"[bench] hashing: query {stage[0]:.4f} ms, build rows {bms:.3f} ms "
+        f"({build_tflops:.1f} TFLOP/s)")
+    del ix  # the workspace of n rows goes with it below
+    torch.cuda.synchronize()
 
-    # ---- collision counting with a candidate cap (Section 3, "Collision Counting") on an index of
-    # 64 layers over the same data and queries: the points sharing the query's
-    # bucket in at least theta layers, ranked by (count desc, id asc), K + v of
-    # them verified; beside it the plain union on that index.  Its kernel's
-    # algorithmic bytes: the listed ids (4 each), the verified rows, the query
-    # rows and the K output pairs.
+    # ---- collision counting with a candidate cap (Section 3, "Collision
+    # Counting") on an index of 64 layers over the same data and queries: the
+    # points sharing the query's bucket in at least theta layers, ranked by
+    # (count desc, id asc), K + v of them verified; beside it the plain union
+    # on that index.  Its kernel's algorithmic bytes: the listed ids (4 each),
+    # the verified rows, the query rows and the K output pairs.
+    truth, rsel = tb["truth"], tb["rsel"]
     counting = None
     count_theta = args.count_theta if args.count_theta is not None else (3 if args.config == 2 else 0)
     if count_theta > 0:
@@ -356,19 +440,20 @@ def main():
             p_ids, p_dist = cix.query(q_d, K, lib.make_opts(form=lib.QW_FORM_PLAIN_FP32))
             c_same = bool(np.array_equal(p_ids.cpu().numpy(), c_ids) and
                           np.array_equal(p_dist.cpu().numpy(), c_dist))
-            cms = timed(copts, args.steps, args.warmup, cix)
+            cms = timed(cix, copts, args.steps, args.warmup)
             kms_c = 0.0
-            for _ in range(nrep):
+            for _ in range(5):
                 _, _, cs = cix.query(q_d, K, lib.make_opts(timing=1, graph=0), out_ids=out_ids,
                                      out_dist=out_dist, stats=True)
-                kms_c += cs["ms_stage"][3] / nrep
+                kms_c += cs["ms_stage"][3] / 5
             cbytes = (4 * cst["cand_total"] + cst["cand_unique"] * wl.d * elem + wl.Q * wl.d * elem
                       + 8 * K * wl.Q)
             cix.set_counting(0)
-            u_ids, u_dist, ust = cix.query(q_d, K, fast_opts, stats=True)
+            uopts = lib.make_opts(sched=lib.QW_SCHED_SUM)
+            u_ids, u_dist, ust = cix.query(q_d, K, uopts, stats=True)
             urec = recall_at_10(u_ids.cpu().numpy()[rsel], truth[0], u_dist.cpu().numpy()[rsel],
                                 truth[1])
-            ums = timed(fast_opts, args.steps, args.warmup, cix)
+            ums = timed(cix, uopts, args.steps, args.warmup)
             cach = cbytes / (kms_c * 1e-3) / 1e9 if kms_c > 0 else None
             counting = {
                 "index": {"L": cL, "k": wl.params.k, "w": cw}, "theta": count_theta,
@@ -383,7 +468,8 @@ def main():
                            "frac": round(cach / HBM_PEAK_GBS, 4) if cach else None},
                 "union_same_index": {"qps": round(wl.Q / (ums * 1e-3), 1),
                                      "recall_at_10": round(urec, 4),
-                                     "unique_per_query": ust["cand_unique"] / wl.Q},
+                                     "unique_per_query": ust["cand_unique"] / wl.Q,
+                                     "sched": "sum (no count model on this index)"},
             }
             log(f"[bench] counting theta={count_theta} v={args.count_v}: {cms:.3f} ms/step, "
                 f"recall {crec:.4f}, kernel {kms_c:.3f} ms; union on that index {ums:.3f} ms, "
@@ -392,17 +478,135 @@ def main():
             counting = {"error": str(e)}
         cix.close()
 
-    # hashing (A1-A2): algorithmic projection flops against the dense MFMA peak
-    # of the type the kernel multiplies in (FP16 for uint8 data, FP32 for float)
-    hash_flops = 2.0 * wl.d * L * wl.params.k * wl.Q
-    hash_peak = MFMA_PEAK_FP16_TFLOPS if is_u8 else MFMA_PEAK_FP32_TFLOPS
-    hash_tflops = hash_flops / (stage[0] * 1e-3) / 1e12 if stage[0] > 0 else None
-    hash_info = {"kernel": "hash_mfma_f16_kernel" if is_u8 else "hash_mfma_f32_kernel",
-                 "ms": round(float(stage[0]), 4),
-                 "algorithmic_tflops": round(hash_tflops, 2) if hash_tflops else None,
-                 "peak_tflops": hash_peak,
-                 "frac": round(hash_tflops / hash_peak, 5) if hash_tflops else None,
-                 "index_build_s": round(build_s, 3)}
+    # ---- the plain union: each layer's own bucket only (no neighbour
+    # probing), at its own w_0.9 (searched from the headline's w upward), with
+    # a count model trained the same way and its own tuning
+    plain_union = None
+    if args.probes and not args.no_union_leg:
+        ugrid = [m * spec["w"] for m in W_GRID if m * spec["w"] >= w] if not args.w else [args.w]
+        uw, uix, urec, _, utried, _ = search_w(0, 0, ugrid, tb)
+        uix.train_count_model(train_d, epochs=8, batch=1024, lr=2e-3, seed=1)
+        uat = tune(uix, q_d, base_kw)
+        ukw = dict(base_kw, graph=1, tune_cache=tune_path if os.path.exists(tune_path) else None)
+        ums = timed(uix, lib.make_opts(**ukw), args.steps, args.warmup)
+        u_ids, u_dist = uix.query(q_d, K, lib.make_opts(**ukw))
+        p_ids, p_dist = uix.query(q_d, K, lib.make_opts(form=lib.QW_FORM_PLAIN_FP32))
+        u_same = bool(torch.equal(u_ids, p_ids) and torch.equal(u_dist, p_dist))
+        ustage, ust = stage_times(uix, {k: v for k, v in ukw.items() if k != "graph"})
+        uroof = candidate_roofline(ust, float(ustage[6]), wl.Q, wl.d, elem, K, is_u8, args.config,
+                                   uw, 0, 0)
+        plain_union = {"w": uw, "w_search": utried, "recall_at_10": round(urec, 4),
+                       "qps": round(wl.Q / (ums * 1e-3), 1), "ms_per_step": round(ums, 4),
+                       "unique_per_query": ust["cand_unique"] / wl.Q,
+                       "sum_of_buckets_per_query": ust["cand_total"] / wl.Q,
+                       "forms_identical": u_same, "autotune": uat,
+                       "settings": {"dedup": ust["dedup_used"], "group": ust["group_used"],
+                                    "xchunk": ust["xchunk_used"]},
+                       "roofline": uroof}
+        log(f"[bench] plain union w={uw}: {ums:.3f} ms/step, recall {urec:.4f}, "
+            f"kernel frac {uroof['frac']}")
+        uix.close()
+    del train_d
+    torch.cuda.empty_cache()
+
+    # ---- CPU oracle on a bounded sample
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        nthreads = max(1, min(16, os.cpu_count() or 1))
+        t1 = time.time()
+        bi = oracle.BuiltIndex(wl.data, wl.params.a, wl.params.b(w), w, nthreads=nthreads)
+        build_cpu = time.time() - t1
+        rng = np.random.default_rng(7)
+        ns = min(args.cpu_sample if args.cpu_sample > 0 else (10_000 if is_u8 else 1_000), wl.Q)
+        sample = np.sort(rng.choice(wl.Q, size=ns, replace=False))
+        t1 = time.time()
+        o_ids, o_dist, _ = bi.query(wl.queries[sample], K, probes=args.probes,
+                                    probe_t=args.probe_t if args.probes == 2 else 0)
+        q_cpu = time.time() - t1
+        bi.close()
+        g_dist = ref_dist[sample]
+        if is_u8:  # int32 distances; a missing neighbour is INT32_MAX here, INT64_MAX there
+            want = np.where(o_dist == np.iinfo(np.int64).max, np.iinfo(np.int32).max, o_dist)
+            dist_ok = np.array_equal(g_dist.astype(np.int64), want.astype(np.int64))
+        else:  # the library rounds the FP64 distance once; missing = +inf on both sides
+            fin = np.isfinite(o_dist)
+            dist_ok = (np.array_equal(np.isfinite(g_dist), fin) and
+                       np.array_equal(g_dist[fin], o_dist[fin].astype(np.float32)))
+        cpu_match = bool(np.array_equal(o_ids, ref_ids[sample]) and dist_ok)
+        cpu_model = None
+        try:
+            with open("/proc/cpuinfo") as f:
+                cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+        except OSError:
+            pass
+        cpu = {"value": round(len(sample) / q_cpu, 2), "unit": "queries/s", "cores": nthreads,
+               "kind": "oracle", "cpu_model": cpu_model, "host_threads": os.cpu_count(),
+               "sample": f"{len(sample)} of {wl.Q} queries against the full {wl.n}-point index; "
+                         f"oracle index build {build_cpu:.1f}s excluded, query phase {q_cpu:.2f}s",
+               "matches_gpu": cpu_match}
+        log(f"[bench] oracle: {cpu['value']} q/s on {nthreads} threads (build {build_cpu:.1f}s)")
+    del data_d, q_d
+    torch.cuda.empty_cache()
+
+    # ---- the schedules on the 1M x 960 float Zipf workload (100,000 queries
+    # drawn with a Zipf law over 500 hot components, the count model trained on
+    # 200,000 queries drawn the same way), where a query's candidate count
+    # varies most: learned sizing against the sum-of-buckets bound, the exact
+    # count (an extra counting pass) and one size for all
+    float_leg = None
+    if args.config == 2 and not args.no_float_leg:
+        t1 = time.time()
+        wl5 = synth.make_config(5)
+        tr5 = synth.training_queries(5, synth.CONFIGS[5]["train_Q"])
+        log(f"[bench] float Zipf workload generated in {time.time() - t1:.1f}s")
+        d5 = torch.from_numpy(wl5.data).to(dev)
+        q5 = torch.from_numpy(wl5.queries).to(dev)
+        ix5 = lib.Index(d5, torch.from_numpy(wl5.params.a).to(dev),
+                        torch.from_numpy(wl5.params.b(CFG5_W)).to(dev), CFG5_W)
+        tr5_d = torch.from_numpy(tr5).to(dev)
+        t1 = time.time()
+        loss5 = ix5.train_count_model(tr5_d, epochs=8, batch=1024, lr=2e-3, seed=1)
+        train5_s = time.time() - t1
+        del tr5_d
+        oi5 = torch.empty((wl5.Q, wl5.K), dtype=torch.int32, device=dev)
+        od5 = torch.empty((wl5.Q, wl5.K), dtype=torch.float32, device=dev)
+        sel5 = np.sort(np.random.default_rng(12).choice(wl5.Q, size=500, replace=False))
+        ti5, td5 = ix5.bruteforce(q5[torch.from_numpy(sel5).to(dev)].contiguous(), wl5.K)
+        ms5 = {}
+        same5 = True
+        ref5 = None
+        for name, sc in (("learned", lib.QW_SCHED_LEARNED), ("sum", lib.QW_SCHED_SUM),
+                         ("actual", lib.QW_SCHED_ACTUAL), ("none", lib.QW_SCHED_NONE)):
+            o = lib.make_opts(sched=sc)
+            ms5[name] = round(timed(ix5, o, 5, 2, q5, oi5, od5), 3)
+            r_ids, r_dist = ix5.query(q5, wl5.K, o, out_ids=oi5, out_dist=od5)
+            got = (r_ids.cpu().numpy(), r_dist.cpu().numpy())
+            if ref5 is None:
+                ref5 = got
+            else:
+                same5 &= bool(np.array_equal(got[0], ref5[0]) and np.array_equal(got[1], ref5[1]))
+        rec5 = recall_at_10(ref5[0][sel5], ti5.cpu().numpy(), ref5[1][sel5], td5.cpu().numpy())
+        _, _, s5 = ix5.query(q5, wl5.K, lib.make_opts(sched=lib.QW_SCHED_LEARNED, graph=0),
+                             out_ids=oi5, out_dist=od5, stats=True)
+        float_leg = {
+            "workload": (f"n={wl5.n} d={wl5.d} f32, Q={wl5.Q} Zipf queries, L={wl5.params.L} "
+                         f"k={wl5.params.k} w={CFG5_W}, K={wl5.K}, no neighbour probing"),
+            "ms_per_step": ms5, "sched_identical": same5,
+            "learned_vs_sum": round(ms5["sum"] / ms5["learned"], 3),
+            "recall_at_10_sample500": round(rec5, 4),
+            "train_queries": int(tr5.shape[0]), "train_loss": round(float(loss5), 4),
+            "train_s": round(train5_s, 1),
+            "unique_per_query": s5["cand_unique"] / wl5.Q,
+            "sum_of_buckets_per_query": s5["cand_total"] / wl5.Q,
+        }
+        log(f"[bench] float Zipf schedules: {ms5}, identical {same5}, recall {rec5:.4f}")
+        ix5.close()
+        del d5, q5
+        torch.cuda.empty_cache()
+
+    if own_cache and os.path.exists(tune_path):
+        os.remove(tune_path)
 
     qps = wl.Q / (ms_fast * 1e-3)
     line = {
@@ -425,16 +629,19 @@ def main():
                              2: f", {args.probe_t} query-directed neighbour probes per layer"}[args.probes])),
             "n": wl.n, "d": wl.d, "Q": wl.Q, "L": L, "k": wl.params.k, "w": w, "K": K,
             "projection": "fp16-mfma+fp64-guard" if is_u8 else "fp32-mfma+fp64-guard",
-            "bucket_grouping": "automatic (rows of 1024 bytes or more, or 32768 queries or more)",
             "neighbour_probing": {0: None, 1: "all one-step", 2: f"query-directed, {args.probe_t} per layer"}[args.probes],
+            "settings": settings,
             "w_search": tried,
         },
         "recall_at_10": round(rec, 4),
+        "autotune": autotune,
         "plain_fp32_qps": round(wl.Q / (ms_plain * 1e-3), 1),
         "speedup_vs_plain_fp32": round(ms_plain / ms_fast, 3),
         "forms_identical": identical,
         "sched_ms_per_step": sched_ms,
         "sched_identical": sched_identical,
+        "plain_union": plain_union,
+        "float_zipf_schedules": float_leg,
         "collision_counting": counting,
         "stage_ms": {"hash": round(stage[0], 4), "probe": round(stage[1], 4),
                      "schedule": round(stage[2], 4), "dedup": round(stage[6], 4),
@@ -449,23 +656,11 @@ def main():
         "topk_second_pass_queries": st["topk_second_pass"],
         "count_model": count_model,
         "bins": st["bins"],
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1) if achieved else None,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                     "traffic": traffic, "kernel": kname,
-                     "measured_copy_gbs": round(copy_gbs, 1),
-                     "frac_of_measured_copy": round(achieved / copy_gbs, 4) if achieved else None,
-                     # HBM bytes the counters saw over the same kernel time
-                     "traffic_achieved": round(traffic / (kms * 1e-3) / 1e9, 1) if traffic and kms > 0 else None,
-                     "traffic_frac": round(traffic / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if traffic and kms > 0 else None,
-                     "kernel_ms": round(kms, 4),
-                     "kernel_algorithmic_bytes": int(kbytes),
-                     "path_algorithmic_bytes_per_step": int(alg_bytes)},
+        "roofline": roof,
         "hash_mfma": hash_info,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
-    ix.close()
 
 
 if __name__ == "__main__":

@@ -131,6 +131,12 @@ typedef struct {
     float ms_stage[8];     /* timing=1: hash, probe, schedule, candidates+verify+top-K,
                               fallback, total, dedup + verify (fast form; with the top K where
                               the kernel selects it), select kernel (fast form) */
+    int32_t dedup_used;    /* fast form: the settings the call ran with (automatic ones
+                              resolved): dedup kernel (1 or 2), */
+    int32_t group_used;    /* bucket grouping (0 or 1), */
+    int32_t xchunk_used;   /* XCD chunk (0 without grouping), */
+    int32_t tuned;         /* 1 when the tuning cache supplied an automatic setting; all four
+                              are 0 in the plain form and under collision counting */
 } qw_stats;
 
 typedef struct {
@@ -218,6 +224,43 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
  */
 qw_status qw_query_workload_noalloc(qw_index *ix, const void *queries, int64_t Q, int32_t K,
                                     void *stream, int32_t *out_ids, void *out_dist);
+
+/* Outcome of qw_autotune (host). */
+typedef struct {
+    int32_t dedup, group, xchunk; /* the fastest setting, explicit values (qw_opts meaning) */
+    float ms;                     /* its time per call (graph replay, mean of 5) */
+    float ms_default;             /* the built-in automatic setting's time per call */
+    int32_t candidates;           /* settings timed */
+} qw_tune_result;
+
+/*
+ * Tune the fast form's scheduling settings for one workload and record the
+ * fastest in a JSON cache.  The cost-model role of Section 5 (Cost Models and
+ * Workflow of qwLSH: a split chosen offline from the data's shape and then
+ * applied to every workload of that shape), with measured times in place of
+ * a trained model.  Each candidate setting -- the dedup kernel (qw_opts.dedup
+ * 1, or 2 where the wave kernel applies), bucket grouping off, or on with an
+ * XCD chunk of 16, 64 or 256 -- answers `queries` (device, Q x d) for K
+ * neighbours: two warm-up calls, then five timed graph replays on `stream`.
+ * All settings return the same ids and distances; a candidate whose outputs
+ * differ from the built-in automatic setting's is a library bug and gives
+ * QW_EINTERNAL.  `base` (nullable) supplies the remaining options (form must
+ * be QW_FORM_FAST; its schedule is part of the cache key).
+ *  cache_path  host string: the JSON file, created or updated in place (one
+ *              entry per line, keyed by the GPU architecture, e.g. gfx950, and
+ *              a hash of n, d, dtype, L, k, w, the probing, Q, K, the schedule
+ *              and whether a count model is set).  A call whose
+ *              qw_opts.tune_cache names this file takes the entry for its
+ *              workload wherever its own settings are automatic.
+ *  out         host; the chosen setting and times.
+ * Allocates two output buffers of Q*K*4 bytes each and the workspace of the
+ * candidates' graphs; synchronises `stream`.  Errors: QW_EINVAL (bad
+ * arguments, collision counting active, another device current, or the file
+ * cannot be written), QW_ENOMEM, QW_EDEVICE, QW_EINTERNAL as above.
+ */
+qw_status qw_autotune(qw_index *ix, const void *queries, int64_t Q, int32_t K,
+                      const qw_opts *base, const char *cache_path, void *stream,
+                      qw_tune_result *out);
 
 /* Release the index and all device memory it holds (NULL is a no-op). */
 void qw_free_index(qw_index *ix);

@@ -467,7 +467,7 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
             }
             return launch_dedup(a, plan.dgrid[hi], st);
         };
-        const bool wave = plan.wgrid > 0 && (o.dedup == 2 || (o.dedup == 0 && plan.wave_default));
+        const bool wave = plan.wgrid > 0 && o.dedup == 2;  // o: settings resolved by the caller
         if (wave && topk && !count_only) {
             // one wave per query over every class, largest first; sets that
             // overflow split into id-hash passes inside the kernel
@@ -703,6 +703,29 @@ bool carve_plain_ws(const qw_index *ix, int64_t Q, bool pad, unsigned char *base
 
 }  // namespace
 
+bool qw::resolve_fast_auto(qw_index *ix, int64_t Q, int32_t K, qw_opts *o, bool *wave_ok)
+{
+    const Plan plan = make_plan(ix, K);
+    if (wave_ok) *wave_ok = plan.wgrid > 0;
+    TuneEntry e;
+    bool tuned = false;
+    if (o->tune_cache && (o->dedup == 0 || o->group < 0 || o->xchunk == 0) &&
+        tune_lookup(ix, o->tune_cache, Q, K, o->sched, &e)) {
+        tuned = true;
+        const bool grp = o->group < 0 ? e.group != 0 : o->group != 0;
+        if (o->dedup == 0) o->dedup = e.dedup;
+        if (o->group < 0) o->group = e.group;
+        // the tuned chunk belongs to the tuned grouping
+        if (o->xchunk == 0 && grp && e.group) o->xchunk = e.xchunk;
+    }
+    if (o->dedup == 0) o->dedup = plan.wgrid > 0 && plan.wave_default ? 2 : 1;
+    if (o->group < 0)
+        o->group = ix->dp * (ix->dtype == QW_U8 ? 1 : 4) >= kGroupRowBytes || Q >= kGroupQueries;
+    if (o->xchunk == 0 && o->group) o->xchunk = (int32_t)kXcdChunk;
+    if (!o->group) o->xchunk = 0;  // unused without grouping
+    return tuned;
+}
+
 // ============================================================================ ABI
 
 extern "C" {
@@ -849,8 +872,7 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
         const int sched = opt.sched == QW_SCHED_LEARNED && !learned ? QW_SCHED_SUM : opt.sched;
         qw_opts eff = opt;
         eff.sched = sched;
-        if (eff.group < 0)
-            eff.group = ix->dp * (ix->dtype == QW_U8 ? 1 : 4) >= kGroupRowBytes || Q >= kGroupQueries;
+        const bool tuned = resolve_fast_auto(ix, Q, K, &eff, nullptr);
         if (opt.timing || !opt.graph) {
             QW_TRY(enqueue_fast(ix, plan, queries, Q, K, eff, s, out_ids, out_dist,
                                 opt.timing ? ix->ev : nullptr));
@@ -888,7 +910,13 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
             }
             QW_HIP(hipGraphLaunch(it->second, s));
         }
-        if (st) QW_TRY(fill_stats(ix, Q, s, st, opt.timing ? ix->ev : nullptr, true));
+        if (st) {
+            QW_TRY(fill_stats(ix, Q, s, st, opt.timing ? ix->ev : nullptr, true));
+            st->dedup_used = eff.dedup;
+            st->group_used = eff.group;
+            st->xchunk_used = eff.xchunk;
+            st->tuned = tuned;
+        }
         return QW_OK;
     } catch (const std::bad_alloc &) {
         return QW_ENOMEM;

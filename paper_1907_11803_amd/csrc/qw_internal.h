@@ -154,6 +154,14 @@ struct Plan {
     float eps = 0.f;    // FP32 distance bound (float data)
 };
 
+// One entry of the tuning cache: the fastest explicit fast-form settings for
+// one GPU architecture and workload shape, with the times that chose them.
+struct TuneEntry {
+    std::string arch, key, desc;
+    int32_t dedup = 0, group = -1, xchunk = 0;
+    double ms = 0.0, ms_default = 0.0;
+};
+
 struct GraphKey {
     const void *q; int64_t Q; int32_t K; int32_t *ids; void *dist;
     int32_t form, sched, group, topk_keep, dedup, xchunk;
@@ -215,6 +223,10 @@ struct qw_index {
     // classes run beside the merged launch
     hipStream_t side = nullptr;
     hipEvent_t fork[2] = {};
+    // tuning cache: the file last named by a call, read once, and the
+    // device's architecture name
+    std::string tune_path, tune_arch;
+    std::vector<qw::TuneEntry> tune_entries;
 
     qw_index() = default;
     qw_index(const qw_index &) = delete;
@@ -228,6 +240,19 @@ struct qw_index {
 };
 
 namespace qw {
+
+// ---------------------------------------------------------------- tuning
+// Key of a workload in the tuning cache (a hash of the index's shape and
+// settings, Q, K and the schedule); desc (nullable) receives a readable form.
+std::string tune_key(const qw_index *ix, int64_t Q, int32_t K, int32_t sched, std::string *desc);
+// The cache entry at `path` for this workload on this GPU's architecture.
+bool tune_lookup(qw_index *ix, const char *path, int64_t Q, int32_t K, int32_t sched, TuneEntry *out);
+// The fast form's automatic settings (dedup 0, group -1, xchunk 0) resolved
+// to the explicit values a call uses: the tuning cache's entry when
+// o->tune_cache names one for this workload, else the built-in rules.
+// wave_ok (nullable): whether the one-wave-per-query kernel applies.
+// Returns whether the cache supplied a setting.
+bool resolve_fast_auto(qw_index *ix, int64_t Q, int32_t K, qw_opts *o, bool *wave_ok);
 
 // ---------------------------------------------------------------- kernels (launch wrappers)
 // Copy m rows of d elements into rows of dp elements (zero padding).

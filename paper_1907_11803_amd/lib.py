@@ -46,7 +46,9 @@ class qw_stats(ctypes.Structure):
                 ("overflow", ctypes.c_int64), ("fallback", ctypes.c_int64),
                 ("topk_second_pass", ctypes.c_int64),
                 ("bins", ctypes.c_int64 * 8),
-                ("ms_stage", ctypes.c_float * 8)]
+                ("ms_stage", ctypes.c_float * 8),
+                ("dedup_used", ctypes.c_int32), ("group_used", ctypes.c_int32),
+                ("xchunk_used", ctypes.c_int32), ("tuned", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -66,6 +68,11 @@ class qw_index_info(ctypes.Structure):
                 ("mean_hit_bucket", ctypes.c_double)]
 
 
+class qw_tune_result(ctypes.Structure):
+    _fields_ = [("dedup", ctypes.c_int32), ("group", ctypes.c_int32), ("xchunk", ctypes.c_int32),
+                ("ms", ctypes.c_float), ("ms_default", ctypes.c_float), ("candidates", ctypes.c_int32)]
+
+
 # exported symbols and their signatures (restype qw_status unless noted)
 _P, _I32, _I64, _F32, _U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_uint64
 SIGNATURES = {
@@ -74,6 +81,7 @@ SIGNATURES = {
     "qw_build_index": (ctypes.c_int, [_P, _I64, _I32, _I32, _P, _P, _F32, _I32, _I32, _P, _P, _P]),
     "qw_query_workload": (ctypes.c_int, [_P, _P, _I64, _I32, _P, _P, _P, _P, _P]),
     "qw_query_workload_noalloc": (ctypes.c_int, [_P, _P, _I64, _I32, _P, _P, _P]),
+    "qw_autotune": (ctypes.c_int, [_P, _P, _I64, _I32, _P, ctypes.c_char_p, _P, _P]),
     "qw_free_index": (None, [_P]),
     "qw_get_index_info": (ctypes.c_int, [_P, _P]),
     "qw_hash": (ctypes.c_int, [_P, _P, _I64, _I32, _P, _P, _P]),
@@ -207,6 +215,19 @@ def qw_query_workload_noalloc(ix, queries: torch.Tensor, K: int, out_ids: torch.
                                           _stream(stream), _ptr(out_ids), _ptr(out_dist))
     _check(rc, "qw_query_workload_noalloc")
     return out_ids, out_dist
+
+
+def qw_autotune(ix, queries: torch.Tensor, K: int, cache_path: str, opts: Optional[qw_opts] = None,
+                stream=None) -> dict:
+    """Time the fast form's scheduling settings on this workload and record the
+    fastest in the JSON cache at `cache_path`; returns the choice and times."""
+    queries = _dev(queries, (torch.uint8, torch.float32), "queries")
+    r = qw_tune_result()
+    rc = load().qw_autotune(ix, _ptr(queries), queries.shape[0], int(K),
+                            ctypes.byref(opts) if opts is not None else None,
+                            str(cache_path).encode(), _stream(stream), ctypes.byref(r))
+    _check(rc, "qw_autotune")
+    return {f: getattr(r, f) for f, _ in r._fields_}
 
 
 def qw_free_index(ix):
@@ -356,6 +377,9 @@ class Index:
     def query(self, queries, K, opts: Optional[qw_opts] = None, stream=None, out_ids=None,
               out_dist=None, stats: bool = False):
         return qw_query_workload(self.handle, queries, K, opts, stream, out_ids, out_dist, stats)
+
+    def autotune(self, queries, K, cache_path, opts: Optional[qw_opts] = None, stream=None) -> dict:
+        return qw_autotune(self.handle, queries, K, cache_path, opts, stream)
 
     def hash(self, x, form: int = QW_FORM_FAST, stream=None):
         return qw_hash(self.handle, x, self.L * self.k, form, stream)

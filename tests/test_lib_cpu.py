@@ -40,15 +40,17 @@ def test_struct_layout_matches_c(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "qwlsh.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(qw_opts), sizeof(qw_stats),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(qw_opts), sizeof(qw_stats),"
         " sizeof(qw_index_info), offsetof(qw_stats, ms_stage), offsetof(qw_index_info, buckets),"
-        " offsetof(qw_index_info, has_count_model), offsetof(qw_index_info, probing));return 0;}\n")
+        " offsetof(qw_index_info, has_count_model), offsetof(qw_index_info, probing),"
+        " sizeof(qw_tune_result), offsetof(qw_tune_result, ms_default));return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(lib.qw_opts), ctypes.sizeof(lib.qw_stats), ctypes.sizeof(lib.qw_index_info),
             lib.qw_stats.ms_stage.offset, lib.qw_index_info.buckets.offset,
-            lib.qw_index_info.has_count_model.offset, lib.qw_index_info.probing.offset]
+            lib.qw_index_info.has_count_model.offset, lib.qw_index_info.probing.offset,
+            ctypes.sizeof(lib.qw_tune_result), lib.qw_tune_result.ms_default.offset]
     assert got == want
 
 
@@ -68,6 +70,7 @@ def test_validation_rejects_before_device_work(so):
     # null index
     assert so.qw_query_workload(None, None, 0, 10, None, None, None, None, None) == lib.QW_EINVAL
     assert so.qw_hash(None, None, 0, 0, None, None, None) == lib.QW_EINVAL
+    assert so.qw_autotune(None, None, 1, 1, None, b"/nonexistent/t.json", None, None) == lib.QW_EINVAL
     assert so.qw_get_index_info(None, None) == lib.QW_EINVAL
     assert so.qw_set_count_model(None, None, 0) == lib.QW_EINVAL
     assert so.qw_set_count_margin(None, 0.5) == lib.QW_EINVAL
