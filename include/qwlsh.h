@@ -209,11 +209,11 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
  * statistics.
  * Every workspace buffer (query hashes, bucket ranges, counters, the padded
  * query copy when d is not a multiple of 16 or `queries` is not 16-byte
- * aligned, the query-directed probing projections) comes from one static
+ * aligned, the query-directed probing moves) comes from one static
  * device array of 32 MiB per GPU, held until the process ends.  The call
  * allocates nothing -- no hipMalloc, no hipFree -- and grows no buffer of the
  * index.  Limits: the workspace of Q queries, about
- * Q * (4*L*k + 8*lists + 8 [+ 4*L with probing] [+ 8*L*k + T*L with
+ * Q * (4*L*k + 8*lists + 8 [+ 4*L with probing] [+ T*L with
  * query-directed probing] [+ d*elem when padded]) bytes plus alignment, must
  * fit 32 MiB, and each query's hash set must fit on-chip memory; otherwise
  * QW_EUNSUPPORTED, with the outputs untouched.

@@ -17,14 +17,17 @@ namespace qw {
 
 // ---------------------------------------------------------------- kernels
 
-// out[c][r] = in[r][c] for an r x c float matrix
-__global__ void transpose_f32_kernel(const float *__restrict__ in, int32_t rows, int32_t cols,
-                                     float *__restrict__ out)
+// The parameters in FP64, layer-major: out[l][e][j] = a[l * k + j][e] (a: the
+// zero-padded [nf_pad][dp] rows; L layers of k functions, dp elements).
+__global__ void params_f64_kernel(const float *__restrict__ a, int32_t L, int32_t k, int32_t dp,
+                                  double *__restrict__ out)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)rows * cols;
+    const int64_t total = (int64_t)L * k * dp;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = i / cols, c = i - r * cols;
-        out[c * rows + r] = in[i];
+        const int64_t f = i / dp, e = i - f * dp;  // function f = l * k + j
+        const int64_t l = f / k, j = f - l * k;
+        out[(l * dp + e) * k + j] = (double)a[i];
     }
 }
 
@@ -308,9 +311,9 @@ qw_status build_index(const void *data, int64_t n, int32_t d, int32_t dtype, con
     QW_TRY(ix->a32.ensure(sizeof(float) * (size_t)ix->nf_pad * dp));
     QW_HIP(hipMemsetAsync(ix->a32.p, 0, ix->a32.bytes, s));
     QW_TRY(launch_pad_rows(a, nf, d, dp, QW_F32, ix->a32.p, s));
-    QW_TRY(ix->a32t.ensure(sizeof(float) * (size_t)ix->nf_pad * dp));
-    transpose_f32_kernel<<<grid_of((int64_t)ix->nf_pad * dp), kBlock, 0, s>>>(
-        ix->a32.as<float>(), ix->nf_pad, dp, ix->a32t.as<float>());
+    QW_TRY(ix->a64l.ensure(sizeof(double) * (size_t)nf * dp));
+    params_f64_kernel<<<grid_of((int64_t)nf * dp), kBlock, 0, s>>>(ix->a32.as<float>(), L, k, dp,
+                                                                  ix->a64l.as<double>());
     QW_HIP(hipGetLastError());
     QW_TRY(ix->b32.ensure(sizeof(float) * nf));
     QW_HIP(hipMemcpyAsync(ix->b32.p, b, sizeof(float) * nf, hipMemcpyDeviceToDevice, s));

@@ -123,7 +123,7 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan, bool keys = false
     Workspace &w = ix->ws;
     auto ptrs = [&w]() {
         return std::vector<void *>{w.qpad.p, w.h.p, w.bstart.p, w.bsize.p, w.bmh.p, w.lsum.p,
-                                   w.lmh.p, w.yq.p, w.moves.p, w.pred.p,
+                                   w.lmh.p, w.moves.p, w.pred.p,
                                    w.feats.p, w.keys.p, w.keys2.p, w.vals.p, w.vals2.p,
                                    w.binoff.p, w.counters.p, w.ovf.p, w.gscratch.p, w.mlpout.p,
                                    w.order.p,
@@ -131,46 +131,64 @@ qw_status ensure_ws(qw_index *ix, int64_t Q, const Plan *plan, bool keys = false
                                    w.pkeys.p, w.fb.p};
     };
     const std::vector<void *> before = ptrs();
-    const size_t elem = ix->dtype == QW_U8 ? 1 : 4;
-    const int64_t q = std::max<int64_t>(Q, 1);
-    QW_TRY(w.qpad.ensure(elem * (size_t)q * ix->dp));
-    QW_TRY(w.h.ensure(sizeof(int32_t) * (size_t)q * ix->nf));
-    QW_TRY(w.bstart.ensure(sizeof(uint32_t) * (size_t)q * ix->nl));
-    QW_TRY(w.bsize.ensure(sizeof(uint32_t) * (size_t)q * ix->nl));
-    QW_TRY(w.bmh.ensure(sizeof(uint32_t) * (size_t)q * ix->nl));
-    if (ix->nprobe > 1) {
-        QW_TRY(w.lsum.ensure(sizeof(uint32_t) * (size_t)q * ix->L));
-        QW_TRY(w.lmh.ensure(sizeof(uint32_t) * (size_t)q * ix->L));
-    }
-    if (ix->probe_mode == 2) {
-        QW_TRY(w.yq.ensure(sizeof(double) * (size_t)q * ix->nf));
-        QW_TRY(w.moves.ensure((size_t)q * ix->L * (ix->nprobe - 1)));
-    }
-    QW_TRY(w.pred.ensure(sizeof(int32_t) * q));
-    QW_TRY(w.feats.ensure(sizeof(float) * (size_t)q * ix->L));
-    QW_TRY(w.mlpout.ensure(sizeof(float) * q));
-    QW_TRY(w.keys.ensure(sizeof(unsigned long long) * q));
-    QW_TRY(w.keys2.ensure(sizeof(unsigned long long) * q));
-    QW_TRY(w.vals.ensure(sizeof(int32_t) * q));
-    QW_TRY(w.vals2.ensure(sizeof(int32_t) * q));
-    QW_TRY(w.ovf.ensure(sizeof(int32_t) * q * (kQueueMerged + 1)));  // one queue per class + merged
-    QW_TRY(w.binoff.ensure(sizeof(unsigned long long) * 2 * kMaxClasses));
-    QW_TRY(w.order.ensure(sizeof(int32_t) * (size_t)kMaxClasses * q));  // per-class lists
-    QW_TRY(w.counters.ensure(sizeof(unsigned long long) * kC64 + sizeof(uint32_t) * kC32));
-    QW_TRY(w.hist.ensure(radix_sort_scratch_bytes(q)));
-    QW_TRY(w.scan.ensure(scan_scratch_bytes(q)));
-    QW_TRY(w.ucount.ensure(sizeof(uint32_t) * q));  // |C(q)|, written on every path
-    if (plan) {
-        const size_t g = (size_t)plan->grid_g * (size_t(1) << plan->cap_g) * 4;
-        QW_TRY(w.gscratch.ensure(g));
-        // one equal region per XCD, each with room for its share of the
-        // queries plus one chunk of items per dedup launch (at most ncls + 1)
-        const int64_t slack = (int64_t)kXcd * kXcdChunk * (plan->ncls + 1);
-        const int64_t cand_cap = std::max<int64_t>((q + slack) * kCandPerQuery, 1 << 20);
-        QW_TRY(w.coff.ensure(sizeof(unsigned long long) * q));
-        QW_TRY(w.flag.ensure(sizeof(uint32_t) * q));
-        if (keys) QW_TRY(w.pkeys.ensure(sizeof(unsigned long long) * cand_cap));
-        QW_TRY(w.fb.ensure(sizeof(int32_t) * q));
+    // two passes: the first adds up what the buffers must grow by and refuses
+    // a workload beyond the device's free memory before anything is
+    // allocated; the second grows them
+    size_t extra = 0;
+    bool dry = true;
+    auto grow = [&](DevBuf &b, size_t want) -> qw_status {
+        if (!dry) {
+            const qw_status rc = b.ensure(want);
+            if (rc != QW_OK) drop_graphs(ix);  // a buffer may have moved before the failure
+            return rc;
+        }
+        if (!b.p || want > b.bytes) extra += want - std::min(want, b.bytes) + 256;
+        return QW_OK;
+    };
+    for (int pass = 0; pass < 2; ++pass, dry = false) {
+        if (!dry) {
+            size_t free_b = 0, total_b = 0;
+            if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && extra > free_b) return QW_ENOMEM;
+            (void)hipGetLastError();
+        }
+        const size_t elem = ix->dtype == QW_U8 ? 1 : 4;
+        const int64_t q = std::max<int64_t>(Q, 1);
+        QW_TRY(grow(w.qpad, elem * (size_t)q * ix->dp));
+        QW_TRY(grow(w.h, sizeof(int32_t) * (size_t)q * ix->nf));
+        QW_TRY(grow(w.bstart, sizeof(uint32_t) * (size_t)q * ix->nl));
+        QW_TRY(grow(w.bsize, sizeof(uint32_t) * (size_t)q * ix->nl));
+        QW_TRY(grow(w.bmh, sizeof(uint32_t) * (size_t)q * ix->nl));
+        if (ix->nprobe > 1) {
+            QW_TRY(grow(w.lsum, sizeof(uint32_t) * (size_t)q * ix->L));
+            QW_TRY(grow(w.lmh, sizeof(uint32_t) * (size_t)q * ix->L));
+        }
+        if (ix->probe_mode == 2) QW_TRY(grow(w.moves, (size_t)q * ix->L * (ix->nprobe - 1)));
+        QW_TRY(grow(w.pred, sizeof(int32_t) * q));
+        QW_TRY(grow(w.feats, sizeof(float) * (size_t)q * ix->L));
+        QW_TRY(grow(w.mlpout, sizeof(float) * q));
+        QW_TRY(grow(w.keys, sizeof(unsigned long long) * q));
+        QW_TRY(grow(w.keys2, sizeof(unsigned long long) * q));
+        QW_TRY(grow(w.vals, sizeof(int32_t) * q));
+        QW_TRY(grow(w.vals2, sizeof(int32_t) * q));
+        QW_TRY(grow(w.ovf, sizeof(int32_t) * q * (kQueueMerged + 1)));  // one queue per class + merged
+        QW_TRY(grow(w.binoff, sizeof(unsigned long long) * 2 * kMaxClasses));
+        QW_TRY(grow(w.order, sizeof(int32_t) * (size_t)kMaxClasses * q));  // per-class lists
+        QW_TRY(grow(w.counters, sizeof(unsigned long long) * kC64 + sizeof(uint32_t) * kC32));
+        QW_TRY(grow(w.hist, radix_sort_scratch_bytes(q)));
+        QW_TRY(grow(w.scan, scan_scratch_bytes(q)));
+        QW_TRY(grow(w.ucount, sizeof(uint32_t) * q));  // |C(q)|, written on every path
+        if (plan) {
+            const size_t g = (size_t)plan->grid_g * (size_t(1) << plan->cap_g) * 4;
+            QW_TRY(grow(w.gscratch, g));
+            // one equal region per XCD, each with room for its share of the
+            // queries plus one chunk of items per dedup launch (at most ncls + 1)
+            const int64_t slack = (int64_t)kXcd * kXcdChunk * (plan->ncls + 1);
+            const int64_t cand_cap = std::max<int64_t>((q + slack) * kCandPerQuery, 1 << 20);
+            QW_TRY(grow(w.coff, sizeof(unsigned long long) * q));
+            QW_TRY(grow(w.flag, sizeof(uint32_t) * q));
+            if (keys) QW_TRY(grow(w.pkeys, sizeof(unsigned long long) * cand_cap));
+            QW_TRY(grow(w.fb, sizeof(int32_t) * q));
+        }
     }
     if (before != ptrs()) drop_graphs(ix);
     return QW_OK;
@@ -232,22 +250,25 @@ qw_status front(qw_index *ix, const void *queries, int64_t Q, int form, hipStrea
                 hipEvent_t *ev = nullptr, float *feats = nullptr, uint32_t *bmh = nullptr)
 {
     QW_TRY(stage_query_rows(ix, queries, Q, s));
-    QW_TRY(launch_hash(ix, ix->ws.qrows, Q, 0, ix->nf, form, ix->ws.h.as<int32_t>(), ix->nf,
-                       c64(ix) + C_RECOMP, s));
-    if (ev) QW_HIP(hipEventRecord(ev[1], s));
+    // query-directed probing chooses its moves from FP64 index-order
+    // projections, whose floors are the exact hash values: the fast form
+    // takes them from there and runs no other hashing
+    const bool moves_hash = ix->probe_mode == 2 && form == QW_FORM_FAST;
+    if (!moves_hash)
+        QW_TRY(launch_hash(ix, ix->ws.qrows, Q, 0, ix->nf, form, ix->ws.h.as<int32_t>(), ix->nf,
+                           c64(ix) + C_RECOMP, s));
     const uint8_t *moves = nullptr;
     if (ix->probe_mode == 2) {
-        QW_TRY(launch_probe_moves(ix, ix->ws.qrows, Q, ix->ws.yq.as<double>(),
-                                  ix->ws.moves.as<uint8_t>(), s));
+        QW_TRY(launch_probe_moves(ix, ix->ws.qrows, Q, ix->ws.moves.as<uint8_t>(),
+                                  moves_hash ? ix->ws.h.as<int32_t>() : nullptr, s));
         moves = ix->ws.moves.as<uint8_t>();
     }
+    if (ev) QW_HIP(hipEventRecord(ev[1], s));
+    const bool probed = ix->nprobe > 1;
     QW_TRY(launch_probe(ix, ix->ws.h.as<int32_t>(), Q, ix->ws.bstart.as<uint32_t>(),
-                        ix->ws.bsize.as<uint32_t>(), ix->nprobe == 1 ? feats : nullptr, bmh,
-                        moves, s));
-    if (ix->nprobe > 1)
-        QW_TRY(launch_layer_sums(ix->ws.bsize.as<uint32_t>(), bmh, Q, ix->L, ix->nprobe,
-                                 ix->ws.lsum.as<uint32_t>(), bmh ? ix->ws.lmh.as<uint32_t>() : nullptr,
-                                 feats, s));
+                        ix->ws.bsize.as<uint32_t>(), feats, bmh, moves,
+                        probed ? ix->ws.lsum.as<uint32_t>() : nullptr,
+                        probed && bmh ? ix->ws.lmh.as<uint32_t>() : nullptr, s));
     return QW_OK;
 }
 
@@ -692,10 +713,7 @@ bool carve_plain_ws(const qw_index *ix, int64_t Q, bool pad, unsigned char *base
     take(w.bstart, sizeof(uint32_t) * q * (size_t)ix->nl);
     take(w.bsize, sizeof(uint32_t) * q * (size_t)ix->nl);
     if (ix->nprobe > 1) take(w.lsum, sizeof(uint32_t) * q * (size_t)ix->L);
-    if (ix->probe_mode == 2) {
-        take(w.yq, sizeof(double) * q * (size_t)ix->nf);
-        take(w.moves, q * (size_t)ix->L * (size_t)(ix->nprobe - 1));
-    }
+    if (ix->probe_mode == 2) take(w.moves, q * (size_t)ix->L * (size_t)(ix->nprobe - 1));
     take(w.ucount, sizeof(uint32_t) * q);
     take(w.ovf, sizeof(int32_t) * q);
     return ok;

@@ -23,7 +23,13 @@ qw_status DevBuf::ensure(size_t want)
     if (!owned) return QW_EINTERNAL;  // a view never allocates
     release();
     if (want == 0) want = 16;
+    if (want > (SIZE_MAX >> 1)) return QW_ENOMEM;
     want = (want + 255) & ~size_t(255);
+    // beyond the device's free memory: refused here, whatever the allocator
+    // would do with it
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && want > free_b) return QW_ENOMEM;
+    (void)hipGetLastError();
     if (hipMalloc(&p, want) != hipSuccess) {
         (void)hipGetLastError();
         p = nullptr;

@@ -19,7 +19,7 @@ enum {
     D_WT = 8 /* per-wave counts, kBlock / 64 */, D_NEXT = 12, D_LCNT = 13, D_BAD = 14,
     D_BOUND = 16 /* u64 */, D_KTH = 18 /* u64 */, D_NSCAL = 20
 };
-constexpr int kRegIds = 16;  // ids per thread of the register-resident path
+constexpr int kRegIds = 12;  // ids per thread of the register-resident path
 
 __host__ __device__ inline size_t a16(size_t v) { return (v + 15) & ~size_t(15); }
 
@@ -456,7 +456,7 @@ __device__ inline void fused_topk(const DedupArgs &A, int64_t q, LaneTop t, cons
 // workgroup's atomic on one address), so neighbouring queries of the order --
 // grouped by candidate overlap -- share one XCD's L2.  Each workgroup fetches
 // its next item while the current one runs.  Queries with
-// at most kRegIds * kBlock
+// at most kRegIds * kBlock (12 x 256)
 // bucket entries in an LDS set keep their ids in registers from the load to
 // the write; larger ones (and the global-memory class, GLOB) go through the
 // set and read the unique ids back from it.

@@ -522,90 +522,102 @@ qw_status launch_hash(const qw_index *ix, const void *xpad, int64_t m, int32_t f
 }
 
 // ---------------------------------------------------------------- probe scores
-// Query-directed probing.  y[q][f] = (a_f.x_q + b_f) / w in FP64, index order
-// (each product of a float parameter and a uint8 or float input is exact in
-// FP64, so the fused multiply-add rounds like the separate steps).  One
-// thread per (query, group of kProjF functions): the lanes of a wave take
-// consecutive queries of one function group, so the parameters are uniform
-// (scalar loads from a32 [nf_pad][dp]), each query element is converted once
-// and feeds kProjF independent sums.
-constexpr int kProjF = 8;
+// Query-directed probing: each (query, layer)'s T moves.  The layer's k values
+// y_j = (a_j . x + b_j) / w are computed in FP64, index order, one rounding per
+// step (a product of a float parameter and a uint8 or float element is exact
+// in FP64, so the fused multiply-add rounds as the separate product and sum
+// do): the reference's own FP64 values.  Move 2j + s shifts hash value j by
+// -1 (s = 0, score f_j * f_j) or +1 (s = 1, score (1 - f_j) * (1 - f_j)),
+// f_j = y_j - floor(y_j), every operation rounded in FP64; the probes take the
+// smallest (score, move) in order, pass t the smallest above pick t - 1.  The
+// floors of the same values are the query's hash values, written too when
+// hout is given (the fast form then needs no other hashing of the queries).
+//
+// One thread per (query, layer); the lanes of a wave take consecutive queries
+// of one layer, so the parameters are uniform: scalar loads from a64l, the
+// parameters in FP64, [layer][element][function], one layer's values
+// contiguous.  Each lane converts a 16-element piece of its row once and
+// feeds the k sums; the next piece loads while the current one is used.
+// KM: k itself (KEXACT) or a bound on it (functions past k skipped).
 
-__device__ inline void load16(const uint8_t *p, double (&v)[16])
-{
-    const uint4 w = *reinterpret_cast<const uint4 *>(p);
-    const uint32_t u[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = (double)((u[i >> 2] >> (8 * (i & 3))) & 0xFFu);
-}
-__device__ inline void load16(const float *p, double (&v)[16])
-{
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const float4 w = reinterpret_cast<const float4 *>(p)[i];
-        v[4 * i] = (double)w.x;
-        v[4 * i + 1] = (double)w.y;
-        v[4 * i + 2] = (double)w.z;
-        v[4 * i + 3] = (double)w.w;
+template <typename E> struct Piece16;
+template <> struct Piece16<uint8_t> {
+    typedef uint4 V;
+    static __device__ V load(const uint8_t *p) { return *reinterpret_cast<const uint4 *>(p); }
+    static __device__ double at(const V &v, int i)
+    {
+        const uint32_t w = i < 4 ? v.x : i < 8 ? v.y : i < 12 ? v.z : v.w;
+        return (double)((w >> (8 * (i & 3))) & 0xFFu);
     }
-}
-
-template <typename T>
-__global__ __launch_bounds__(kBlock) void project_fp64_kernel(
-    const T *__restrict__ x, int64_t Q, int32_t dp, int32_t d, const float *__restrict__ a32,
-    const float *__restrict__ b, int32_t nf, double w, double *__restrict__ y)
-{
-    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int32_t f0 = blockIdx.y * kProjF;  // a32 has nf_pad >= f0 + kProjF zero-padded rows
-    if (q >= Q) return;
-    const T *xr = x + q * dp;  // dp: a multiple of 16 elements, zero padded past d
-    double acc[kProjF];
+};
+template <> struct Piece16<float> {
+    struct V { float4 p[4]; };
+    static __device__ V load(const float *p)
+    {
+        V v;
 #pragma unroll
-    for (int j = 0; j < kProjF; ++j) acc[j] = 0.0;
-    for (int32_t e0 = 0; e0 < d; e0 += 16) {
-        double xv[16];
-        load16(xr + e0, xv);
-        // the 16 x kProjF parameters of this step (uniform: scalar loads)
-        float av[kProjF][16];
-#pragma unroll
-        for (int j = 0; j < kProjF; ++j)
-#pragma unroll
-            for (int u = 0; u < 16; ++u) av[j][u] = a32[(int64_t)(f0 + j) * dp + e0 + u];
-#pragma unroll
-        for (int u = 0; u < 16; ++u)
-            if (e0 + u < d)  // uniform
-#pragma unroll
-                for (int j = 0; j < kProjF; ++j)
-                    acc[j] = __dadd_rn(acc[j], __dmul_rn((double)av[j][u], xv[u]));
+        for (int i = 0; i < 4; ++i) v.p[i] = reinterpret_cast<const float4 *>(p)[i];
+        return v;
     }
-#pragma unroll
-    for (int j = 0; j < kProjF; ++j)
-        if (f0 + j < nf) y[q * nf + f0 + j] = __dadd_rn(acc[j], (double)b[f0 + j]) / w;
-}
+    static __device__ double at(const V &v, int i)
+    {
+        const float4 &q = v.p[i >> 2];
+        return (double)((i & 3) == 0 ? q.x : (i & 3) == 1 ? q.y : (i & 3) == 2 ? q.z : q.w);
+    }
+};
 
-// One thread per (query, layer): the T one-step moves with the smallest
-// scores, in (score, move) order -- move 2j + s shifts hash value j by -1
-// (s = 0, score f_j * f_j) or +1 (s = 1, score (1 - f_j) * (1 - f_j)), with
-// f_j = y_j - floor(y_j), every operation rounded in FP64 as the scores are
-// defined.  Pass t takes the smallest (score, move) above the previous pick.
-__global__ __launch_bounds__(kBlock) void select_moves_kernel(
-    const double *__restrict__ y, int64_t Q, int32_t L, int32_t k, int32_t T,
-    uint8_t *__restrict__ moves)
+template <typename E, int KM, bool KEXACT>
+__global__ __launch_bounds__(kBlock) void probe_moves_kernel(
+    const E *__restrict__ x, int64_t Q, int32_t dp, const double *__restrict__ a64l,
+    const float *__restrict__ b, int32_t L, int32_t k, double w, int32_t T,
+    uint8_t *__restrict__ moves, int32_t *__restrict__ hout)
 {
 #pragma clang fp contract(off)
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= Q * L) return;
-    const double *yl = y + i * k;  // the layer's k values (nf = L * k per query)
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int32_t l = blockIdx.y;
+    const E *xr = x + (q < Q ? q : Q - 1) * dp;  // dp: a multiple of 16 elements, zero padded
+    const double *al = a64l + (int64_t)l * dp * k;  // element e, function j: al[e * k + j]
+    double acc[KM];
+#pragma unroll
+    for (int j = 0; j < KM; ++j) acc[j] = 0.0;
+    typename Piece16<E>::V cur = Piece16<E>::load(xr);
+    for (int32_t e0 = 0; e0 < dp; e0 += 16) {
+        // the next piece (the last one re-reads itself)
+        const typename Piece16<E>::V nxt = Piece16<E>::load(xr + (e0 + 16 < dp ? e0 + 16 : e0));
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const double xv = Piece16<E>::at(cur, u);
+            const double *ae = al + (int64_t)(e0 + u) * k;
+#pragma unroll
+            for (int j = 0; j < KM; ++j)
+                if (KEXACT || j < k)  // uniform
+                    acc[j] = __builtin_fma(xv, ae[j], acc[j]);
+        }
+        cur = nxt;
+    }
+    if (q >= Q) return;
+    double fr[KM];
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+        fr[j] = 0.0;
+        if (KEXACT || j < k) {
+            const double y = __ddiv_rn(__dadd_rn(acc[j], (double)b[l * k + j]), w);
+            fr[j] = y - floor(y);
+            // the reference's own value: its floor is the hash value itself
+            if (hout) hout[q * (L * k) + l * k + j] = floor_to_i32(y);
+        }
+    }
+    const int64_t ql = q * L + l;
     double ps = -1.0;
     int32_t pm = -1;
     for (int32_t t = 0; t < T; ++t) {
         double bs = INFINITY;
         int32_t bm = 2 * k;
-        for (int32_t j = 0; j < k; ++j) {
-            const double v = yl[j];
-            const double fr = v - floor(v);
-            const double up = 1.0 - fr;
-            const double s0 = fr * fr, s1 = up * up;
+#pragma unroll
+        for (int32_t j = 0; j < KM; ++j) {
+            if (!KEXACT && j >= k) continue;
+            const double up = 1.0 - fr[j];
+            const double s0 = fr[j] * fr[j], s1 = up * up;
             const int32_t m0 = 2 * j, m1 = 2 * j + 1;
             // candidates strictly after the previous pick in (score, move) order
             const bool e0 = s0 > ps || (s0 == ps && m0 > pm);
@@ -613,51 +625,79 @@ __global__ __launch_bounds__(kBlock) void select_moves_kernel(
             if (e0 && (s0 < bs || (s0 == bs && m0 < bm))) { bs = s0; bm = m0; }
             if (e1 && (s1 < bs || (s1 == bs && m1 < bm))) { bs = s1; bm = m1; }
         }
-        moves[i * T + t] = (uint8_t)bm;
+        moves[ql * T + t] = (uint8_t)bm;
         ps = bs;
         pm = bm;
     }
 }
 
-qw_status launch_probe_moves(const qw_index *ix, const void *xpad, int64_t Q, double *y,
-                             uint8_t *moves, hipStream_t s)
+template <typename E>
+void launch_probe_moves_t(const qw_index *ix, const E *x, int64_t Q, uint8_t *moves, int32_t *hout,
+                          hipStream_t s)
+{
+    const dim3 g((unsigned)ceil_div(Q, kBlock), (unsigned)ix->L);
+    const double *a = ix->a64l.as<double>();
+    const float *b = ix->b32.as<float>();
+    const int32_t T = ix->nprobe - 1;
+    const double w = (double)ix->w;
+#define QW_PM(KM, EX) probe_moves_kernel<E, KM, EX><<<g, kBlock, 0, s>>>(x, Q, ix->dp, a, b, ix->L, ix->k, w, T, moves, hout)
+    switch (ix->k) {
+    case 8: QW_PM(8, true); break;
+    case 10: QW_PM(10, true); break;
+    case 12: QW_PM(12, true); break;
+    case 16: QW_PM(16, true); break;
+    default:
+        if (ix->k < 8) QW_PM(8, false);
+        else if (ix->k < 16) QW_PM(16, false);
+        else QW_PM(kMaxK, false);
+    }
+#undef QW_PM
+}
+
+qw_status launch_probe_moves(const qw_index *ix, const void *xpad, int64_t Q, uint8_t *moves,
+                             int32_t *hout, hipStream_t s)
 {
     if (Q <= 0) return QW_OK;
-    const dim3 g((unsigned)ceil_div(Q, kBlock), (unsigned)ceil_div(ix->nf, kProjF));
+    if (ix->k > kMaxK || ix->nprobe - 1 > 2 * ix->k || !ix->a64l.p) return QW_EINTERNAL;
     if (ix->dtype == QW_U8)
-        project_fp64_kernel<uint8_t><<<g, kBlock, 0, s>>>((const uint8_t *)xpad, Q, ix->dp, ix->d,
-                                                          ix->a32.as<float>(), ix->b32.as<float>(),
-                                                          ix->nf, (double)ix->w, y);
+        launch_probe_moves_t<uint8_t>(ix, (const uint8_t *)xpad, Q, moves, hout, s);
     else
-        project_fp64_kernel<float><<<g, kBlock, 0, s>>>((const float *)xpad, Q, ix->dp, ix->d,
-                                                        ix->a32.as<float>(), ix->b32.as<float>(),
-                                                        ix->nf, (double)ix->w, y);
-    QW_HIP(hipGetLastError());
-    const int32_t T = ix->nprobe - 1;
-    select_moves_kernel<<<(unsigned)ceil_div(Q * ix->L, kBlock), kBlock, 0, s>>>(
-        y, Q, ix->L, ix->k, T, moves);
+        launch_probe_moves_t<float>(ix, (const float *)xpad, Q, moves, hout, s);
     QW_HIP(hipGetLastError());
     return QW_OK;
 }
 
 // ---------------------------------------------------------------- probe
-// One thread per (query, layer, probe): probe 0 is the query's own bucket;
-// with neighbour probing (P = 2k + 1) probe 1 + 2j + s moves hash value j by
-// -1 (s = 0) or +1 (s = 1), the buckets next to the query's in one coordinate
-// (the multi-probe variant summarised in Section 2); query-directed (moves
-// non-null, P = T + 1) probe 1 + t takes the layer's t-th chosen move.  The k values are packed
-// into the exact key (values outside the data's range cannot match any
-// bucket: a miss; such a key is never looked up), then the key is looked up
-// in the layer's open-addressing table.  Outputs are [Q][L][P]; bmh
-// (nullable) receives the bucket's min-hash (0xFFFFFFFF on a miss); feats
-// (nullable, P = 1 only) the count-model input log(1 + size).
+// One thread per (query, layer), for all of the layer's P probes: probe 0 is
+// the query's own bucket; with neighbour probing (P = 2k + 1) probe
+// 1 + 2j + s moves hash value j by -1 (s = 0) or +1 (s = 1), the buckets next
+// to the query's in one coordinate (the multi-probe variant summarised in
+// Section 2); query-directed (moves non-null, P = T + 1) probe 1 + t takes
+// the layer's t-th chosen move.  The k values are packed into the exact key
+// once; a probe replaces one field.  Values outside the data's range cannot
+// match any bucket: such a key is a miss and is never looked up.  Each key is
+// looked up in the layer's open-addressing table, kProbeBatch keys with their
+// first slots in flight together.  Outputs are [Q][L][P]; bmh (nullable)
+// receives the bucket's min-hash (0xFFFFFFFF on a miss).  Per layer [Q][L]
+// (each nullable): feats the count-model input log(1 + s) of the layer's size
+// s (summed over its probes), lsum s itself and lmh the minimum of its
+// probes' min-hashes.  KM: k itself (KEXACT) or a bound on it (functions past
+// k skipped).
+constexpr int kProbeBatch = 4;
+// linear probing, two slots (one 64-byte line) per round trip: at a load
+// factor of at most 1/2 most sequences, hits and misses, end within the first
+// pair
+constexpr uint32_t kProbeRound = 2;
+
+template <int KM, bool KEXACT>
 __global__ __launch_bounds__(kBlock) void probe_kernel(
     const int32_t *__restrict__ h, int64_t Q, int32_t L, int32_t k, int32_t P,
     const int32_t *__restrict__ hmin, const int32_t *__restrict__ hmax,
     const int32_t *__restrict__ shift, const TabEntry *__restrict__ tab,
     const long long *__restrict__ tab_off, const uint32_t *__restrict__ tab_mask,
     uint32_t *__restrict__ bstart, uint32_t *__restrict__ bsize, float *__restrict__ feats,
-    uint32_t *__restrict__ bmh, const uint8_t *__restrict__ moves)
+    uint32_t *__restrict__ bmh, const uint8_t *__restrict__ moves, uint32_t *__restrict__ lsum,
+    uint32_t *__restrict__ lmh)
 {
     // per-function constants (value range, bit offset in the key) staged in
     // LDS while the hash values load: one memory latency for both
@@ -669,86 +709,138 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(
         fconst[2 * nf + f] = shift[f];
     }
     const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool live = idx < Q * L * P;
-    const int64_t ql = live ? idx / P : 0;
-    const int32_t p = live ? (int32_t)(idx - ql * P) : 0;
+    const bool live = idx < Q * L;
+    const int64_t ql = live ? idx : 0;
     const int64_t q = ql / L;
     const int32_t l = (int32_t)(ql - q * L);
+    const int32_t *hl = h + q * nf + l * k;
     // the layer's k hash values, all loads issued before any is used
-    int32_t hv[kMaxK];
+    int32_t hv[KM];
 #pragma unroll
-    for (int32_t j = 0; j < kMaxK; ++j)
-        if (j < k) hv[j] = h[q * nf + l * k + j];
+    for (int32_t j = 0; j < KM; ++j)
+        if (KEXACT || j < k) hv[j] = hl[j];
+    const TabEntry *t = tab + tab_off[l];
+    const uint32_t mask = tab_mask[l];
     __syncthreads();
     if (!live) return;
-    bool valid = true;
-    if (p > 0) {  // neighbour probe: one value moved by one (a move past the int32 range: a miss)
-        // every neighbour (probe p is move p - 1), or the query's chosen moves
-        const int32_t mv = moves ? (int32_t)moves[ql * (P - 1) + (p - 1)] : p - 1;
-        const int32_t jp = mv >> 1, dlt = mv & 1 ? 1 : -1;
-#pragma unroll
-        for (int32_t j = 0; j < kMaxK; ++j)
-            if (j == jp) {
-                valid = dlt > 0 ? hv[j] != INT32_MAX : hv[j] != INT32_MIN;
-                hv[j] += valid ? dlt : 0;
-            }
-    }
+    // the base key from the fields in range; nbad fields out of range, the
+    // last of them badj
     uint64_t klo = 0, khi = 0;
+    int32_t nbad = 0, badj = -1;
 #pragma unroll
-    for (int32_t j = 0; j < kMaxK; ++j)
-        if (j < k) {
+    for (int32_t j = 0; j < KM; ++j)
+        if (KEXACT || j < k) {
             const int32_t f = l * k + j, lo = fconst[f];
-            valid = valid && hv[j] >= lo && hv[j] <= fconst[nf + f];
-            key_put(klo, khi, (uint64_t)((int64_t)hv[j] - (int64_t)lo), fconst[2 * nf + f]);
+            if (hv[j] >= lo && hv[j] <= fconst[nf + f]) {
+                key_put(klo, khi, (uint64_t)((int64_t)hv[j] - (int64_t)lo), fconst[2 * nf + f]);
+            } else {
+                ++nbad;
+                badj = j;
+            }
         }
-    uint32_t st = 0, sz = 0, mh = 0xFFFFFFFFu;
-    if (valid) {
-        // linear probing, two slots (one 64-byte line) per round trip: at a
-        // load factor of at most 1/2 most sequences, hits and misses, end
-        // within the first pair (four slots per round read twice the bytes:
-        // 0.22 vs 0.17 ms for 4.2 M neighbour probes)
-        constexpr uint32_t kProbeRound = 2;
-        const TabEntry *t = tab + tab_off[l];
-        const uint32_t mask = tab_mask[l];
-        uint32_t slot = (uint32_t)key_mix(klo, khi) & mask;
-        bool done = false;
-        for (uint32_t it = 0; it <= mask && !done; it += kProbeRound) {
-            TabEntry e[kProbeRound];
+    uint32_t lsz = 0, lm = 0xFFFFFFFFu;  // the layer's size sum and min-hash over its probes
+    for (int32_t p0 = 0; p0 < P; p0 += kProbeBatch) {
+        uint64_t kl[kProbeBatch], kh[kProbeBatch];
+        uint32_t slot[kProbeBatch];
+        bool look[kProbeBatch];
 #pragma unroll
-            for (uint32_t i = 0; i < kProbeRound; ++i) e[i] = t[(slot + i) & mask];
-#pragma unroll
-            for (uint32_t i = 0; i < kProbeRound; ++i) {
-                if (done) continue;
-                if (e[i].size == 0) {
-                    done = true;
-                } else if (e[i].klo == klo && e[i].khi == khi) {
-                    st = e[i].start;
-                    sz = e[i].size;
-                    mh = e[i].mh;
-                    done = true;
+        for (int b = 0; b < kProbeBatch; ++b) {
+            const int32_t p = p0 + b;
+            kl[b] = klo;
+            kh[b] = khi;
+            look[b] = false;
+            if (p >= P) continue;
+            if (p == 0) {
+                look[b] = nbad == 0;
+            } else {  // one value moved by one
+                const int32_t mv = moves ? (int32_t)moves[ql * (P - 1) + (p - 1)] : p - 1;
+                const int32_t j = mv >> 1, f = l * k + j;
+                const int32_t lo = fconst[f], hi = fconst[nf + f], sh = fconst[2 * nf + f];
+                const int64_t hj = (int64_t)hl[j];
+                const int64_t nv = hj + (mv & 1 ? 1 : -1);
+                const bool in_old = hj >= lo && hj <= hi;
+                look[b] = (nbad == 0 || (nbad == 1 && badj == j)) && nv >= lo && nv <= hi;
+                if (look[b]) {  // replace field j: the base holds it only when it was in range
+                    const uint64_t oldv = in_old ? (uint64_t)(hj - lo) : 0u;
+                    const uint64_t newv = (uint64_t)(nv - lo);
+                    if (sh < 64) kl[b] = kl[b] - (oldv << sh) + (newv << sh);
+                    else kh[b] = kh[b] - (oldv << (sh - 64)) + (newv << (sh - 64));
                 }
             }
-            slot = (slot + kProbeRound) & mask;
+        }
+        TabEntry e[kProbeBatch][kProbeRound];
+#pragma unroll
+        for (int b = 0; b < kProbeBatch; ++b) {
+            slot[b] = (uint32_t)key_mix(kl[b], kh[b]) & mask;
+            if (look[b])
+#pragma unroll
+                for (uint32_t i = 0; i < kProbeRound; ++i) e[b][i] = t[(slot[b] + i) & mask];
+        }
+#pragma unroll
+        for (int b = 0; b < kProbeBatch; ++b) {
+            const int32_t p = p0 + b;
+            if (p >= P) continue;
+            uint32_t st = 0, sz = 0, mh = 0xFFFFFFFFu;
+            if (look[b]) {
+                bool done = false;
+                for (uint32_t it = 0; !done; it += kProbeRound) {
+                    if (it > 0) {  // rare: the first pair held other keys
+                        if (it > mask) break;
+                        slot[b] = (slot[b] + kProbeRound) & mask;
+#pragma unroll
+                        for (uint32_t i = 0; i < kProbeRound; ++i) e[b][i] = t[(slot[b] + i) & mask];
+                    }
+#pragma unroll
+                    for (uint32_t i = 0; i < kProbeRound; ++i) {
+                        if (done) continue;
+                        if (e[b][i].size == 0) {
+                            done = true;
+                        } else if (e[b][i].klo == kl[b] && e[b][i].khi == kh[b]) {
+                            st = e[b][i].start;
+                            sz = e[b][i].size;
+                            mh = e[b][i].mh;
+                            done = true;
+                        }
+                    }
+                }
+            }
+            const int64_t o = ql * P + p;
+            bstart[o] = st;
+            bsize[o] = sz;
+            if (bmh) bmh[o] = mh;
+            lsz += sz;
+            lm = min(lm, mh);
         }
     }
-    bstart[idx] = st;
-    bsize[idx] = sz;
-    if (feats) feats[idx] = log1pf((float)sz);  // count-model input, f = log(1 + s)
-    if (bmh) bmh[idx] = mh;
+    if (feats) feats[ql] = log1pf((float)lsz);  // count-model input, f = log(1 + s)
+    if (lsum) lsum[ql] = lsz;
+    if (lmh) lmh[ql] = lm;
 }
 
 qw_status launch_probe(const qw_index *ix, const int32_t *h, int64_t Q, uint32_t *bstart,
                        uint32_t *bsize, float *feats, uint32_t *bmh, const uint8_t *moves,
-                       hipStream_t s)
+                       uint32_t *lsum, uint32_t *lmh, hipStream_t s)
 {
     if (Q <= 0) return QW_OK;
-    if (feats && ix->nprobe != 1) return QW_EINTERNAL;  // features of probed layers: layer sums
-    const int64_t total = Q * ix->nl;
+    if (ix->k > kMaxK) return QW_EINTERNAL;
+    const unsigned g = (unsigned)ceil_div(Q * ix->L, kBlock);
     const size_t lds = sizeof(int32_t) * 3 * (size_t)ix->nf;  // nf <= 64 * kMaxK: 24 KiB at most
-    probe_kernel<<<(unsigned)ceil_div(total, kBlock), kBlock, lds, s>>>(
-        h, Q, ix->L, ix->k, ix->nprobe, ix->hmin.as<int32_t>(), ix->hmax.as<int32_t>(),
-        ix->shift.as<int32_t>(), ix->tab.as<TabEntry>(), ix->tab_off.as<long long>(),
-        ix->tab_mask.as<uint32_t>(), bstart, bsize, feats, bmh, moves);
+#define QW_PR(KM, EX)                                                                            \
+    probe_kernel<KM, EX><<<g, kBlock, lds, s>>>(                                                  \
+        h, Q, ix->L, ix->k, ix->nprobe, ix->hmin.as<int32_t>(), ix->hmax.as<int32_t>(),          \
+        ix->shift.as<int32_t>(), ix->tab.as<TabEntry>(), ix->tab_off.as<long long>(),            \
+        ix->tab_mask.as<uint32_t>(), bstart, bsize, feats, bmh, moves, lsum, lmh)
+    switch (ix->k) {
+    case 8: QW_PR(8, true); break;
+    case 10: QW_PR(10, true); break;
+    case 12: QW_PR(12, true); break;
+    case 16: QW_PR(16, true); break;
+    default:
+        if (ix->k < 8) QW_PR(8, false);
+        else if (ix->k < 16) QW_PR(16, false);
+        else QW_PR(kMaxK, false);
+    }
+#undef QW_PR
     QW_HIP(hipGetLastError());
     return QW_OK;
 }

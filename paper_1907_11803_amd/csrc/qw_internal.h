@@ -129,7 +129,7 @@ __host__ __device__ inline uint32_t id_mix(uint32_t x)
 }
 
 struct Workspace {
-    DevBuf qpad, h, bstart, bsize, bmh, lsum, lmh, yq, moves, pred, feats, keys, keys2, vals,
+    DevBuf qpad, h, bstart, bsize, bmh, lsum, lmh, moves, pred, feats, keys, keys2, vals,
         vals2, hist, order, binoff, counters, ovf, gscratch, mlpout, scan;
     // flat pipeline
     DevBuf ucount, coff, flag, pkeys, fb;
@@ -187,7 +187,7 @@ struct qw_index {
     float w = 0.f;
     // hash parameters (device)
     qw::DevBuf a32;      // float [nf_pad][dp], zero padded
-    qw::DevBuf a32t;     // float [dp][nf_pad]: a32 transposed (FP64 query projections)
+    qw::DevBuf a64l;     // double [L][dp][k]: a32 in FP64, layer-major (query-directed probing)
     qw::DevBuf b32;      // float [nf]
     qw::DevBuf a_hi;     // _Float16 [nf_pad][dp]  (uint8 data, MFMA path)
     qw::DevBuf a_lo;     // _Float16 [nf_pad][dp]
@@ -266,15 +266,20 @@ qw_status launch_hash(const qw_index *ix, const void *xpad, int64_t m, int32_t f
                       int32_t form, int32_t *out, int32_t out_ld,
                       unsigned long long *recomputed, hipStream_t s);
 
-// Probe every (query, layer): bstart/bsize [Q][L] (bsize 0 = miss); feats
-// (nullable) log(1 + size); bmh (nullable) the bucket's min-hash.
+// Query-directed probing: each layer's T chosen moves [Q][L][T]
+// (T = nprobe - 1) from the FP64 projections of the query rows; hout
+// (nullable) receives their floors, the exact hash values [Q][L*k].
+qw_status launch_probe_moves(const qw_index *ix, const void *xpad, int64_t Q, uint8_t *moves,
+                             int32_t *hout, hipStream_t s);
+
+// Probe every list of every query: bstart/bsize [Q][L][P] (bsize 0 = miss);
+// bmh (nullable) the bucket's min-hash; moves (query-directed probing) each
+// layer's chosen moves.  Per layer [Q][L], each nullable: feats log(1 + s),
+// lsum s, lmh the min-hash over the layer's probes (s: the layer's size summed
+// over its probes).
 qw_status launch_probe(const qw_index *ix, const int32_t *h, int64_t Q, uint32_t *bstart,
                        uint32_t *bsize, float *feats, uint32_t *bmh, const uint8_t *moves,
-                       hipStream_t s);
-// Query-directed probing: FP64 projections y [Q][nf] of the query rows and
-// each layer's T chosen moves [Q][L][T] (T = nprobe - 1).
-qw_status launch_probe_moves(const qw_index *ix, const void *xpad, int64_t Q, double *y,
-                             uint8_t *moves, hipStream_t s);
+                       uint32_t *lsum, uint32_t *lmh, hipStream_t s);
 
 // Generic fills.
 qw_status launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t s);
@@ -379,10 +384,6 @@ qw_status launch_classify_bin(int64_t Q, int32_t L, int64_t n, const uint32_t *b
                               int32_t ncls, int32_t *order, unsigned long long *class_count,
                               uint32_t *done, unsigned long long *seg, hipStream_t s);
 qw_status launch_max_u32(const uint32_t *v, int64_t count, uint32_t *out, hipStream_t s);
-// Neighbour probing: per (query, layer) the sum of its P list sizes, the
-// smallest min-hash (lmh nullable) and log(1 + sum) (feats nullable).
-qw_status launch_layer_sums(const uint32_t *bsize, const uint32_t *bmh, int64_t Q, int32_t L,
-                            int32_t P, uint32_t *lsum, uint32_t *lmh, float *feats, hipStream_t s);
 qw_status launch_max_bucket_sum(const uint32_t *bsize, int64_t Q, int32_t L, uint32_t *out,
                                 hipStream_t s);
 qw_status launch_probe_stats(const uint32_t *bsize, int64_t count, unsigned long long *hits,

@@ -308,38 +308,6 @@ __global__ __launch_bounds__(kBlock) void probe_stats_kernel(const uint32_t *__r
     }
 }
 
-// Neighbour probing: the P lists of each (query, layer) reduced to one entry
-// per layer, the shape the schedule and the count model read: lsum = the sum
-// of the list sizes, lmh (nullable) = the smallest min-hash, feats (nullable)
-// = log(1 + lsum).
-__global__ __launch_bounds__(kBlock) void layer_sums_kernel(
-    const uint32_t *__restrict__ bsize, const uint32_t *__restrict__ bmh, int64_t QL, int32_t P,
-    uint32_t *__restrict__ lsum, uint32_t *__restrict__ lmh, float *__restrict__ feats)
-{
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < QL;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t s = 0, m = 0xFFFFFFFFu;
-        for (int32_t p = 0; p < P; ++p) {
-            s += bsize[i * P + p];
-            if (bmh) m = min(m, bmh[i * P + p]);
-        }
-        lsum[i] = s;
-        if (lmh) lmh[i] = m;
-        if (feats) feats[i] = log1pf((float)s);
-    }
-}
-
-qw_status launch_layer_sums(const uint32_t *bsize, const uint32_t *bmh, int64_t Q, int32_t L,
-                            int32_t P, uint32_t *lsum, uint32_t *lmh, float *feats, hipStream_t s)
-{
-    if (Q <= 0) return QW_OK;
-    const int64_t QL = Q * L;
-    const int g = (int)std::min<int64_t>(4096, ceil_div(QL, kBlock));
-    layer_sums_kernel<<<g, kBlock, 0, s>>>(bsize, bmh, QL, P, lsum, lmh, feats);
-    QW_HIP(hipGetLastError());
-    return QW_OK;
-}
-
 qw_status launch_probe_stats(const uint32_t *v, int64_t count, unsigned long long *nonzero,
                              unsigned long long *total, hipStream_t s)
 {

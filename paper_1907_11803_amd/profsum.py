@@ -55,6 +55,13 @@ def _csv(directory: str, suffix: str):
     return rows
 
 
+def _size(r, key: str) -> int:
+    """Grid or workgroup size of a row (kernel traces split it into X/Y/Z)."""
+    if key in r:
+        return int(r[key])
+    return int(r[key + "_X"]) * int(r.get(key + "_Y", 1) or 1) * int(r.get(key + "_Z", 1) or 1)
+
+
 def _short(name: str, width: int = 90) -> str:
     return name if len(name) <= width else name[: width - 3] + "..."
 
@@ -77,7 +84,7 @@ def cmd_trace(a):
     for tot, name, rs, ds in sorted(items, key=lambda t: -t[0]):
         r = rs[0]
         out.append(f"| `{_short(name)}` | {len(ds)} | {statistics.mean(ds):.2f} | {min(ds):.2f} | "
-                   f"{max(ds):.2f} | {tot:.1f} | {r.get('Workgroup_Size', '')} | "
+                   f"{max(ds):.2f} | {tot:.1f} | {_size(r, 'Workgroup_Size')} | "
                    f"{r.get('VGPR_Count', '')} | {r.get('Accum_VGPR_Count', '')} | "
                    f"{r.get('SGPR_Count', '')} | {r.get('LDS_Block_Size', '')} | "
                    f"{r.get('Scratch_Size', '')} |")
@@ -85,10 +92,20 @@ def cmd_trace(a):
         sel = [t for t in items if a.kernel in t[1]]
         if sel:
             _, name, rs, ds = sel[0]
-            grids = collections.Counter(int(r["Grid_Size"]) // max(1, int(r["Workgroup_Size"])) for r in rs)
+            grids = collections.Counter(_size(r, "Grid_Size") // max(1, _size(r, "Workgroup_Size")) for r in rs)
             out += ["", f"`{_short(name)}`: mean {statistics.mean(ds):.2f} us over {len(ds)} dispatches "
                     f"(median {statistics.median(ds):.2f}); workgroups per dispatch "
                     + ", ".join(f"{g} x{c}" for g, c in sorted(grids.items())) + "."]
+    stats = sorted(glob.glob(os.path.join(a.dir, "*kernel_stats.csv")))
+    if stats:
+        with open(stats[0], newline="") as f:
+            srows = list(csv.DictReader(f))
+        out += ["", f"rocprofv3 --stats summary (`{os.path.basename(stats[0])}`, first {min(15, len(srows))} "
+                "rows by total time):", "", "| kernel | calls | average us | min us | max us | % |",
+                "|---|---|---|---|---|---|"]
+        for r in srows[:15]:
+            out.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                       f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {r['Percentage']} |")
     with open(a.out, "w") as f:
         f.write("\n".join(out) + "\n")
     print(f"wrote {a.out}")
@@ -163,7 +180,7 @@ def cmd_counters(a):
             continue
         key = (r["Dispatch_Id"], r["Counter_Name"], r.get("Start_Timestamp", ""))
         per[key] += float(r["Counter_Value"])
-        meta[key] = (int(r["Grid_Size"]) // max(1, int(r["Workgroup_Size"])), r["Kernel_Name"])
+        meta[key] = (_size(r, "Grid_Size") // max(1, _size(r, "Workgroup_Size")), r["Kernel_Name"])
         names.add(r["Kernel_Name"])
     for key, v in per.items():
         grid, _ = meta[key]

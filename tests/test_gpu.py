@@ -205,6 +205,59 @@ def test_query_directed_probing_cfg1(cfg1, T):
             check_topk(ids, dist, ids_o, dist_o, True)
 
 
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+@pytest.mark.parametrize("k", [3, 5, 8, 10, 12, 13, 16, 20, 32])
+def test_query_directed_probing_every_k(dtype, k):
+    """The move selection for every function count (the kernel is built for
+    k = 8, 10, 12 and 16 exactly and for bounds of 8, 16 and 32 otherwise),
+    ragged rows, and T up to 2k moves: candidate lists and top K match the
+    oracle."""
+    d = 37 if dtype == "u8" else 21
+    # bucket widths giving about 100-800 candidates per query at T = 3
+    mult = {"u8": {3: 0.25, 5: 0.5, 16: 2, 20: 2, 32: 4},
+            "f32": {3: 0.5, 5: 1, 8: 2, 10: 2, 12: 4, 13: 4, 16: 4, 20: 4, 32: 8}}[dtype].get(k, 1)
+    w = (1500.0 if dtype == "u8" else 1.5) * mult
+    wl = synth.random_small(900 + k, 3000, d, 50, 3, k, w, dtype=dtype)
+    p = wl.params
+    ix = build(wl.data, p.a, p.b(), p.w)
+    for T in sorted({1, 3, 2 * k}):
+        ix.set_probing(2, T)
+        want = oracle.lsh_candidates(wl.data, wl.queries, p.a, p.b(), p.w, probes=2, probe_t=T)
+        for g, o in zip(ix.candidate_lists(dev(wl.queries)), want):
+            assert np.array_equal(g, o)
+        ids_o, dist_o, _ = oracle.lsh_query(wl.data, wl.queries, p.a, p.b(), p.w, wl.K, probes=2,
+                                            probe_t=T)
+        ids, dist = ix.query(dev(wl.queries), wl.K, lib.make_opts(sched=lib.QW_SCHED_SUM))
+        check_topk(ids, dist, ids_o, dist_o, dtype == "u8")
+    ix.close()
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_query_directed_probing_score_ties(dtype):
+    """Small integer parameters put projections on quarter steps, so scores
+    tie exactly (f = 1/2 scores both moves 1/4; equal fractions across
+    functions): ties are broken by move index as the oracle breaks them."""
+    L, k, d = 3, 5, 48
+    a, b, w = synth.boundary_params(31, L, k, d, w=4.0)
+    rng = np.random.default_rng(32)
+    x = rng.integers(0, 8, size=(2000, d), dtype=np.uint8)
+    qx = rng.integers(0, 8, size=(64, d), dtype=np.uint8)
+    if dtype == "f32":
+        x, qx = x.astype(np.float32), qx.astype(np.float32)
+    ix = build(x, a, b, w)
+    for T in (1, 2, 5, 2 * k):
+        ix.set_probing(2, T)
+        want = oracle.lsh_candidates(x, qx, a, b, w, probes=2, probe_t=T)
+        for form in FORMS:
+            ix_lists = ix.candidate_lists(dev(qx))
+            for g, o in zip(ix_lists, want):
+                assert np.array_equal(g, o)
+            ids_o, dist_o, _ = oracle.lsh_query(x, qx, a, b, w, 10, probes=2, probe_t=T)
+            ids, dist = ix.query(dev(qx), 10, lib.make_opts(form=form, sched=lib.QW_SCHED_SUM))
+            check_topk(ids, dist, ids_o, dist_o, dtype == "u8")
+    ix.close()
+
+
 def test_query_directed_probing_float():
     wl = synth.make_config(3, n=6000, Q=60, ncomp=30, w=4.0)
     p = wl.params
@@ -616,4 +669,66 @@ def test_dedup_option_validation(cfg1):
         with pytest.raises(lib.QwError) as e:
             ix.query(q, 10, lib.make_opts(**kw))
         assert e.value.status == lib.QW_EINVAL
+    ix.close()
+
+
+# ---------------------------------------------------------------- workload invariants and limits
+
+def test_query_permutation_invariance():
+    """Answers do not depend on where a query sits in the workload: a permuted
+    workload returns the permuted answers, bit for bit, in both forms, both
+    candidate kernels and both groupings (the schedule reorders queries by
+    size class and candidate overlap)."""
+    wl = synth.make_config(2, n=100_000, Q=3000, ncomp=100)
+    p = wl.params
+    w = 1000.0
+    ix = build(wl.data, p.a, p.b(w), w)
+    ix.train_count_model(dev(synth.training_queries(2, 5000, ncomp=100)), epochs=2, batch=1024,
+                         lr=2e-3, seed=1)
+    perm = np.random.default_rng(5).permutation(wl.Q)
+    q, qp = dev(wl.queries), dev(wl.queries[perm])
+    for probes in (0, 2):
+        if probes:
+            ix.set_probing(2, 2)
+        for o in (lib.make_opts(form=lib.QW_FORM_PLAIN_FP32),
+                  lib.make_opts(dedup=lib.QW_DEDUP_BLOCK, group=0),
+                  lib.make_opts(dedup=lib.QW_DEDUP_BLOCK, group=1),
+                  lib.make_opts(dedup=lib.QW_DEDUP_WAVE, group=0),
+                  lib.make_opts(dedup=lib.QW_DEDUP_WAVE, group=1, xchunk=16)):
+            ids, dist = ix.query(q, wl.K, o)
+            ids_p, dist_p = ix.query(qp, wl.K, o)
+            assert np.array_equal(ids.cpu().numpy()[perm], ids_p.cpu().numpy())
+            assert np.array_equal(dist.cpu().numpy()[perm], dist_p.cpu().numpy())
+    ix.close()
+
+
+def test_oversized_requests_give_enomem(cfg1):
+    """Requests beyond the device's memory are refused with QW_ENOMEM before
+    anything is allocated or read (the library checks the device's free memory
+    first), and the index keeps answering afterwards."""
+    import ctypes
+    so = lib.load()
+    # an index over 2^31 - 1 rows of 8192 floats (70 TB): refused before the data copy
+    a1 = torch.zeros((1, 1, 8192), dtype=torch.float32, device="cuda")
+    b1 = torch.zeros((1, 1), dtype=torch.float32, device="cuda")
+    small = torch.zeros((4, 8192), dtype=torch.float32, device="cuda")
+    out = ctypes.c_void_p()
+    rc = so.qw_build_index(small.data_ptr(), 2 ** 31 - 1, 8192, lib.QW_F32, a1.data_ptr(), b1.data_ptr(),
+                           1.0, 1, 1, None, None, ctypes.byref(out))
+    assert rc == lib.QW_ENOMEM and not out.value
+    # a workload of 2^31 - 1 queries (over a TB of workspace) on a small index
+    p = cfg1.params
+    ix = build(cfg1.data, p.a, p.b(), p.w)
+    q = dev(cfg1.queries)
+    ids = torch.full((4, cfg1.K), -7, dtype=torch.int32, device="cuda")
+    dist = torch.full_like(ids, -7)
+    for o in (lib.make_opts(), lib.make_opts(form=lib.QW_FORM_PLAIN_FP32)):
+        rc = so.qw_query_workload(ix.handle, q.data_ptr(), 2 ** 31 - 1, cfg1.K, ctypes.byref(o), None,
+                                  ids.data_ptr(), dist.data_ptr(), None)
+        assert rc == lib.QW_ENOMEM
+    torch.cuda.synchronize()
+    assert bool((ids == -7).all()) and bool((dist == -7).all())
+    ids_o, dist_o, _ = oracle.lsh_query(cfg1.data, cfg1.queries, p.a, p.b(), p.w, cfg1.K)
+    ids, dist = ix.query(q, cfg1.K)
+    check_topk(ids, dist, ids_o, dist_o, True)
     ix.close()
