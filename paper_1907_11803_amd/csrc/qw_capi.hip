@@ -250,6 +250,9 @@ qw_status front(qw_index *ix, const void *queries, int64_t Q, int form, hipStrea
                 hipEvent_t *ev = nullptr, float *feats = nullptr, uint32_t *bmh = nullptr)
 {
     QW_TRY(stage_query_rows(ix, queries, Q, s));
+    const bool probed = ix->nprobe > 1;
+    uint32_t *lsum = probed ? ix->ws.lsum.as<uint32_t>() : nullptr;
+    uint32_t *lmh = probed && bmh ? ix->ws.lmh.as<uint32_t>() : nullptr;
     // query-directed probing chooses its moves from FP64 index-order
     // projections, whose floors are the exact hash values: the fast form
     // takes them from there and runs no other hashing
@@ -264,11 +267,8 @@ qw_status front(qw_index *ix, const void *queries, int64_t Q, int form, hipStrea
         moves = ix->ws.moves.as<uint8_t>();
     }
     if (ev) QW_HIP(hipEventRecord(ev[1], s));
-    const bool probed = ix->nprobe > 1;
     QW_TRY(launch_probe(ix, ix->ws.h.as<int32_t>(), Q, ix->ws.bstart.as<uint32_t>(),
-                        ix->ws.bsize.as<uint32_t>(), feats, bmh, moves,
-                        probed ? ix->ws.lsum.as<uint32_t>() : nullptr,
-                        probed && bmh ? ix->ws.lmh.as<uint32_t>() : nullptr, s));
+                        ix->ws.bsize.as<uint32_t>(), feats, bmh, moves, lsum, lmh, s));
     return QW_OK;
 }
 

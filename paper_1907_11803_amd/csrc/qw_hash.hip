@@ -597,14 +597,26 @@ __global__ __launch_bounds__(kBlock) void probe_moves_kernel(
     }
     if (q >= Q) return;
     double fr[KM];
+    int32_t hv[KM];
 #pragma unroll
     for (int j = 0; j < KM; ++j) {
         fr[j] = 0.0;
+        hv[j] = 0;
         if (KEXACT || j < k) {
             const double y = __ddiv_rn(__dadd_rn(acc[j], (double)b[l * k + j]), w);
             fr[j] = y - floor(y);
-            // the reference's own value: its floor is the hash value itself
-            if (hout) hout[q * (L * k) + l * k + j] = floor_to_i32(y);
+            hv[j] = floor_to_i32(y);  // the reference's own value: its floor is the hash value
+        }
+    }
+    if (hout) {
+        int32_t *ho = hout + q * (L * k) + l * k;
+        if (KEXACT && KM % 2 == 0) {  // 8-byte aligned: (L k q + k l) is even
+#pragma unroll
+            for (int j = 0; j < KM; j += 2) *reinterpret_cast<int2 *>(ho + j) = int2{hv[j], hv[j + 1]};
+        } else {
+#pragma unroll
+            for (int j = 0; j < KM; ++j)
+                if (j < k) ho[j] = hv[j];
         }
     }
     const int64_t ql = q * L + l;
@@ -689,55 +701,18 @@ constexpr int kProbeBatch = 4;
 // pair
 constexpr uint32_t kProbeRound = 2;
 
-template <int KM, bool KEXACT>
-__global__ __launch_bounds__(kBlock) void probe_kernel(
-    const int32_t *__restrict__ h, int64_t Q, int32_t L, int32_t k, int32_t P,
-    const int32_t *__restrict__ hmin, const int32_t *__restrict__ hmax,
-    const int32_t *__restrict__ shift, const TabEntry *__restrict__ tab,
-    const long long *__restrict__ tab_off, const uint32_t *__restrict__ tab_mask,
-    uint32_t *__restrict__ bstart, uint32_t *__restrict__ bsize, float *__restrict__ feats,
-    uint32_t *__restrict__ bmh, const uint8_t *__restrict__ moves, uint32_t *__restrict__ lsum,
-    uint32_t *__restrict__ lmh)
+// Looks up the P probes of one (query, layer) and writes their outputs (see
+// probe_kernel).  klo/khi: the base key over the fields in range; nbad of
+// them out of range, the last badj.  field(j, lo, hi, sh, hj): function j's
+// value range, key offset and hash value; move(p): the move of probe p >= 1.
+template <class Field, class Move>
+__device__ inline void probe_layer(int32_t P, uint64_t klo, uint64_t khi, int32_t nbad,
+                                   int32_t badj, const TabEntry *__restrict__ t, uint32_t mask,
+                                   Field field, Move move, int64_t ql, uint32_t *__restrict__ bstart,
+                                   uint32_t *__restrict__ bsize, uint32_t *__restrict__ bmh,
+                                   float *__restrict__ feats, uint32_t *__restrict__ lsum,
+                                   uint32_t *__restrict__ lmh)
 {
-    // per-function constants (value range, bit offset in the key) staged in
-    // LDS while the hash values load: one memory latency for both
-    extern __shared__ int32_t fconst[];  // [3][nf]: hmin, hmax, shift
-    const int32_t nf = L * k;
-    for (int32_t f = threadIdx.x; f < nf; f += kBlock) {
-        fconst[f] = hmin[f];
-        fconst[nf + f] = hmax[f];
-        fconst[2 * nf + f] = shift[f];
-    }
-    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool live = idx < Q * L;
-    const int64_t ql = live ? idx : 0;
-    const int64_t q = ql / L;
-    const int32_t l = (int32_t)(ql - q * L);
-    const int32_t *hl = h + q * nf + l * k;
-    // the layer's k hash values, all loads issued before any is used
-    int32_t hv[KM];
-#pragma unroll
-    for (int32_t j = 0; j < KM; ++j)
-        if (KEXACT || j < k) hv[j] = hl[j];
-    const TabEntry *t = tab + tab_off[l];
-    const uint32_t mask = tab_mask[l];
-    __syncthreads();
-    if (!live) return;
-    // the base key from the fields in range; nbad fields out of range, the
-    // last of them badj
-    uint64_t klo = 0, khi = 0;
-    int32_t nbad = 0, badj = -1;
-#pragma unroll
-    for (int32_t j = 0; j < KM; ++j)
-        if (KEXACT || j < k) {
-            const int32_t f = l * k + j, lo = fconst[f];
-            if (hv[j] >= lo && hv[j] <= fconst[nf + f]) {
-                key_put(klo, khi, (uint64_t)((int64_t)hv[j] - (int64_t)lo), fconst[2 * nf + f]);
-            } else {
-                ++nbad;
-                badj = j;
-            }
-        }
     uint32_t lsz = 0, lm = 0xFFFFFFFFu;  // the layer's size sum and min-hash over its probes
     for (int32_t p0 = 0; p0 < P; p0 += kProbeBatch) {
         uint64_t kl[kProbeBatch], kh[kProbeBatch];
@@ -753,10 +728,11 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(
             if (p == 0) {
                 look[b] = nbad == 0;
             } else {  // one value moved by one
-                const int32_t mv = moves ? (int32_t)moves[ql * (P - 1) + (p - 1)] : p - 1;
-                const int32_t j = mv >> 1, f = l * k + j;
-                const int32_t lo = fconst[f], hi = fconst[nf + f], sh = fconst[2 * nf + f];
-                const int64_t hj = (int64_t)hl[j];
+                const int32_t mv = move(p);
+                const int32_t j = mv >> 1;
+                int32_t lo, hi, sh, hj32;
+                field(j, lo, hi, sh, hj32);
+                const int64_t hj = (int64_t)hj32;
                 const int64_t nv = hj + (mv & 1 ? 1 : -1);
                 const bool in_old = hj >= lo && hj <= hi;
                 look[b] = (nbad == 0 || (nbad == 1 && badj == j)) && nv >= lo && nv <= hi;
@@ -817,6 +793,67 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(
     if (lmh) lmh[ql] = lm;
 }
 
+template <int KM, bool KEXACT>
+__global__ __launch_bounds__(kBlock) void probe_kernel(
+    const int32_t *__restrict__ h, int64_t Q, int32_t L, int32_t k, int32_t P,
+    const int32_t *__restrict__ hmin, const int32_t *__restrict__ hmax,
+    const int32_t *__restrict__ shift, const TabEntry *__restrict__ tab,
+    const long long *__restrict__ tab_off, const uint32_t *__restrict__ tab_mask,
+    uint32_t *__restrict__ bstart, uint32_t *__restrict__ bsize, float *__restrict__ feats,
+    uint32_t *__restrict__ bmh, const uint8_t *__restrict__ moves, uint32_t *__restrict__ lsum,
+    uint32_t *__restrict__ lmh)
+{
+    // per-function constants (value range, bit offset in the key) staged in
+    // LDS while the hash values load: one memory latency for both
+    extern __shared__ int32_t fconst[];  // [3][nf]: hmin, hmax, shift
+    const int32_t nf = L * k;
+    for (int32_t f = threadIdx.x; f < nf; f += kBlock) {
+        fconst[f] = hmin[f];
+        fconst[nf + f] = hmax[f];
+        fconst[2 * nf + f] = shift[f];
+    }
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool live = idx < Q * L;
+    const int64_t ql = live ? idx : 0;
+    const int64_t q = ql / L;
+    const int32_t l = (int32_t)(ql - q * L);
+    const int32_t *hl = h + q * nf + l * k;
+    // the layer's k hash values, all loads issued before any is used
+    int32_t hv[KM];
+#pragma unroll
+    for (int32_t j = 0; j < KM; ++j)
+        if (KEXACT || j < k) hv[j] = hl[j];
+    const TabEntry *t = tab + tab_off[l];
+    const uint32_t mask = tab_mask[l];
+    __syncthreads();
+    if (!live) return;
+    // the base key from the fields in range; nbad fields out of range, the
+    // last of them badj
+    uint64_t klo = 0, khi = 0;
+    int32_t nbad = 0, badj = -1;
+#pragma unroll
+    for (int32_t j = 0; j < KM; ++j)
+        if (KEXACT || j < k) {
+            const int32_t f = l * k + j, lo = fconst[f];
+            if (hv[j] >= lo && hv[j] <= fconst[nf + f]) {
+                key_put(klo, khi, (uint64_t)((int64_t)hv[j] - (int64_t)lo), fconst[2 * nf + f]);
+            } else {
+                ++nbad;
+                badj = j;
+            }
+        }
+    auto field = [&](int32_t j, int32_t &lo, int32_t &hi, int32_t &sh, int32_t &hj) {
+        const int32_t f = l * k + j;
+        lo = fconst[f];
+        hi = fconst[nf + f];
+        sh = fconst[2 * nf + f];
+        hj = hl[j];
+    };
+    auto move = [&](int32_t p) { return moves ? (int32_t)moves[ql * (P - 1) + (p - 1)] : p - 1; };
+    probe_layer(P, klo, khi, nbad, badj, t, mask, field, move, ql, bstart, bsize, bmh, feats, lsum,
+                lmh);
+}
+
 qw_status launch_probe(const qw_index *ix, const int32_t *h, int64_t Q, uint32_t *bstart,
                        uint32_t *bsize, float *feats, uint32_t *bmh, const uint8_t *moves,
                        uint32_t *lsum, uint32_t *lmh, hipStream_t s)
@@ -844,5 +881,6 @@ qw_status launch_probe(const qw_index *ix, const int32_t *h, int64_t Q, uint32_t
     QW_HIP(hipGetLastError());
     return QW_OK;
 }
+
 
 }  // namespace qw
