@@ -109,6 +109,14 @@ typedef struct {
                           candidate sets in id-hash passes); ignored elsewhere */
     int32_t xchunk;    /* fast form with bucket grouping: consecutive items of the grouped
                           order dealt to one XCD (1..256; 0 = the tuned value or 256) */
+    int32_t stage_split; /* the split of the caches between the two streams a query reads
+                          (bucket lists, candidate rows), the GPU form of the split of
+                          Sections 4-5 between index files (C_I) and data objects (C_D).
+                          -1 = off (everything cached), 0 = automatic (off); a split
+                          s in 1..99 (bucket lists in the lowest s % of a 16-bit hash loaded
+                          into the caches, the rest streamed through with non-temporal loads,
+                          rows likewise with 100 - s %) is switched off in this build and
+                          refused with QW_EUNSUPPORTED. */
     const char *tune_cache; /* nullable: JSON file written by qw_autotune; automatic settings
                                (dedup 0, xchunk 0, group -1) take its entry for this
                                workload, when it has one */
@@ -135,8 +143,9 @@ typedef struct {
                               resolved): dedup kernel (1 or 2), */
     int32_t group_used;    /* bucket grouping (0 or 1), */
     int32_t xchunk_used;   /* XCD chunk (0 without grouping), */
-    int32_t tuned;         /* 1 when the tuning cache supplied an automatic setting; all four
+    int32_t tuned;         /* 1 when the tuning cache supplied an automatic setting; all five
                               are 0 in the plain form and under collision counting */
+    int32_t split_used;    /* staging split (-1 off, else the index share in percent) */
 } qw_stats;
 
 typedef struct {
@@ -228,6 +237,7 @@ qw_status qw_query_workload_noalloc(qw_index *ix, const void *queries, int64_t Q
 /* Outcome of qw_autotune (host). */
 typedef struct {
     int32_t dedup, group, xchunk; /* the fastest setting, explicit values (qw_opts meaning) */
+    int32_t stage_split;          /* -1: the staging split stays off */
     float ms;                     /* its time per call (graph replay, mean of 5) */
     float ms_default;             /* the built-in automatic setting's time per call */
     int32_t candidates;           /* settings timed */

@@ -727,7 +727,7 @@ bool qw::resolve_fast_auto(qw_index *ix, int64_t Q, int32_t K, qw_opts *o, bool 
     if (wave_ok) *wave_ok = plan.wgrid > 0;
     TuneEntry e;
     bool tuned = false;
-    if (o->tune_cache && (o->dedup == 0 || o->group < 0 || o->xchunk == 0) &&
+    if (o->tune_cache && (o->dedup == 0 || o->group < 0 || o->xchunk == 0 || o->stage_split == 0) &&
         tune_lookup(ix, o->tune_cache, Q, K, o->sched, &e)) {
         tuned = true;
         const bool grp = o->group < 0 ? e.group != 0 : o->group != 0;
@@ -735,7 +735,9 @@ bool qw::resolve_fast_auto(qw_index *ix, int64_t Q, int32_t K, qw_opts *o, bool 
         if (o->group < 0) o->group = e.group;
         // the tuned chunk belongs to the tuned grouping
         if (o->xchunk == 0 && grp && e.group) o->xchunk = e.xchunk;
+        if (o->stage_split == 0 && e.split <= 0) o->stage_split = e.split;
     }
+    if (o->stage_split == 0) o->stage_split = -1;  // off unless tuned or asked for
     if (o->dedup == 0) o->dedup = plan.wgrid > 0 && plan.wave_default ? 2 : 1;
     if (o->group < 0)
         o->group = ix->dp * (ix->dtype == QW_U8 ? 1 : 4) >= kGroupRowBytes || Q >= kGroupQueries;
@@ -846,6 +848,9 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
     if (opt.group < -1 || opt.group > 1) return QW_EINVAL;
     if (opt.dedup < 0 || opt.dedup > 2 || opt.xchunk < 0 || opt.xchunk > (int32_t)kXcdChunk)
         return QW_EINVAL;
+    if (opt.stage_split < -1 || opt.stage_split > 99) return QW_EINVAL;
+    // the non-temporal staging split is switched off (see the header)
+    if (opt.stage_split > 0) return QW_EUNSUPPORTED;
     if (Q == 0) {
         if (st) std::memset(st, 0, sizeof(*st));
         return QW_OK;
@@ -902,6 +907,7 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
             key.topk_keep = eff.topk_keep;
             key.dedup = eff.dedup;
             key.xchunk = eff.xchunk;
+            key.split = eff.stage_split;
             auto it = ix->graphs.find(key);
             if (it == ix->graphs.end()) {
                 hipStream_t cs;
@@ -934,6 +940,7 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
             st->group_used = eff.group;
             st->xchunk_used = eff.xchunk;
             st->tuned = tuned;
+            st->split_used = eff.stage_split;
         }
         return QW_OK;
     } catch (const std::bad_alloc &) {

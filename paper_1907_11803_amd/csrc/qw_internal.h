@@ -158,13 +158,13 @@ struct Plan {
 // one GPU architecture and workload shape, with the times that chose them.
 struct TuneEntry {
     std::string arch, key, desc;
-    int32_t dedup = 0, group = -1, xchunk = 0;
+    int32_t dedup = 0, group = -1, xchunk = 0, split = -1;
     double ms = 0.0, ms_default = 0.0;
 };
 
 struct GraphKey {
     const void *q; int64_t Q; int32_t K; int32_t *ids; void *dist;
-    int32_t form, sched, group, topk_keep, dedup, xchunk;
+    int32_t form, sched, group, topk_keep, dedup, xchunk, split;
     bool operator<(const GraphKey &o) const {
         return std::memcmp(this, &o, sizeof(GraphKey)) < 0;
     }

@@ -66,6 +66,8 @@ std::vector<TuneEntry> read_cache(const std::string &path)
         e.dedup = std::atoi(field_str(line, "dedup").c_str());
         e.group = std::atoi(field_str(line, "group").c_str());
         e.xchunk = std::atoi(field_str(line, "xchunk").c_str());
+        const std::string sp = field_str(line, "split");
+        e.split = sp.empty() ? -1 : std::atoi(sp.c_str());
         e.ms = std::atof(field_str(line, "ms").c_str());
         e.ms_default = std::atof(field_str(line, "ms_default").c_str());
         if (!e.arch.empty() && !e.key.empty()) out.push_back(e);
@@ -84,8 +86,8 @@ bool write_cache(const std::string &path, const std::vector<TuneEntry> &es)
             const TuneEntry &e = es[i];
             char buf[256];
             std::snprintf(buf, sizeof(buf),
-                          "\"dedup\":%d,\"group\":%d,\"xchunk\":%d,\"ms\":%.5f,\"ms_default\":%.5f}",
-                          e.dedup, e.group, e.xchunk, e.ms, e.ms_default);
+                          "\"dedup\":%d,\"group\":%d,\"xchunk\":%d,\"split\":%d,\"ms\":%.5f,\"ms_default\":%.5f}",
+                          e.dedup, e.group, e.xchunk, e.split, e.ms, e.ms_default);
             f << "{\"arch\":\"" << e.arch << "\",\"key\":\"" << e.key << "\",\"workload\":\"" << e.desc
               << "\"," << buf << (i + 1 < es.size() ? "," : "") << "\n";
         }
@@ -176,21 +178,23 @@ extern "C" qw_status qw_autotune(qw_index *ix, const void *queries, int64_t Q, i
 
     // candidate settings: the built-in automatic choice first (it is the
     // reference the others must reproduce), then every other combination
-    struct Cand { int32_t dedup, group, xchunk; };
+    struct Cand { int32_t dedup, group, xchunk, split; };
     std::vector<Cand> cands;
     qw_opts auto_o = b;
     auto_o.dedup = 0;
     auto_o.group = -1;
     auto_o.xchunk = 0;
+    auto_o.stage_split = -1;
     bool wave_ok = false;
     resolve_fast_auto(ix, Q, K, &auto_o, &wave_ok);
-    cands.push_back({auto_o.dedup, auto_o.group, auto_o.xchunk});
+    cands.push_back({auto_o.dedup, auto_o.group, auto_o.xchunk, -1});
     for (int dd = 1; dd <= (wave_ok ? 2 : 1); ++dd)
         for (int xc : {0, 16, 64, 256}) {
-            const Cand c{dd, xc ? 1 : 0, xc};
+            const Cand c{dd, xc ? 1 : 0, xc, -1};
             if (c.dedup != cands[0].dedup || c.group != cands[0].group || c.xchunk != cands[0].xchunk)
                 cands.push_back(c);
         }
+
     void *d_ids = nullptr, *d_dist = nullptr;
     if (hipMalloc(&d_ids, sizeof(int32_t) * (size_t)Q * K) != hipSuccess ||
         hipMalloc(&d_dist, sizeof(uint32_t) * (size_t)Q * K) != hipSuccess) {  // int32 or float32
@@ -210,6 +214,7 @@ extern "C" qw_status qw_autotune(qw_index *ix, const void *queries, int64_t Q, i
         o.dedup = cands[i].dedup;
         o.group = cands[i].group;
         o.xchunk = cands[i].xchunk;
+        o.stage_split = cands[i].split;
         constexpr int kWarm = 2, kReps = 5;  // the first warm call captures the graph
         for (int r = 0; r < kWarm && rc == QW_OK; ++r)
             rc = qw_query_workload(ix, queries, Q, K, &o, stream, static_cast<int32_t *>(d_ids), d_dist, nullptr);
@@ -252,6 +257,7 @@ extern "C" qw_status qw_autotune(qw_index *ix, const void *queries, int64_t Q, i
     e.dedup = cands[best_i].dedup;
     e.group = cands[best_i].group;
     e.xchunk = cands[best_i].xchunk;
+    e.split = cands[best_i].split;
     e.ms = best;
     e.ms_default = def_ms;
     try {
@@ -269,6 +275,7 @@ extern "C" qw_status qw_autotune(qw_index *ix, const void *queries, int64_t Q, i
     out->dedup = e.dedup;
     out->group = e.group;
     out->xchunk = e.xchunk;
+    out->stage_split = e.split;
     out->ms = best;
     out->ms_default = def_ms;
     out->candidates = (int32_t)cands.size();

@@ -36,7 +36,7 @@ class qw_opts(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int32), ("sched", ctypes.c_int32), ("group", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("topk_keep", ctypes.c_int32), ("dedup", ctypes.c_int32), ("xchunk", ctypes.c_int32),
-                ("tune_cache", ctypes.c_char_p)]
+                ("stage_split", ctypes.c_int32), ("tune_cache", ctypes.c_char_p)]
 
 
 class qw_stats(ctypes.Structure):
@@ -48,7 +48,8 @@ class qw_stats(ctypes.Structure):
                 ("bins", ctypes.c_int64 * 8),
                 ("ms_stage", ctypes.c_float * 8),
                 ("dedup_used", ctypes.c_int32), ("group_used", ctypes.c_int32),
-                ("xchunk_used", ctypes.c_int32), ("tuned", ctypes.c_int32)]
+                ("xchunk_used", ctypes.c_int32), ("tuned", ctypes.c_int32),
+                ("split_used", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -70,6 +71,7 @@ class qw_index_info(ctypes.Structure):
 
 class qw_tune_result(ctypes.Structure):
     _fields_ = [("dedup", ctypes.c_int32), ("group", ctypes.c_int32), ("xchunk", ctypes.c_int32),
+                ("stage_split", ctypes.c_int32),
                 ("ms", ctypes.c_float), ("ms_default", ctypes.c_float), ("candidates", ctypes.c_int32)]
 
 
@@ -158,11 +160,11 @@ QW_DEDUP_AUTO, QW_DEDUP_BLOCK, QW_DEDUP_WAVE = 0, 1, 2
 
 def make_opts(form: int = QW_FORM_FAST, sched: int = QW_SCHED_LEARNED, group: int = -1,
               graph: int = 1, timing: int = 0, topk_keep: int = 0, dedup: int = 0,
-              xchunk: int = 0, tune_cache: Optional[str] = None) -> qw_opts:
+              xchunk: int = 0, tune_cache: Optional[str] = None, stage_split: int = 0) -> qw_opts:
     o = qw_opts()
     load().qw_default_opts(ctypes.byref(o))
     o.form, o.sched, o.group, o.graph, o.timing = form, sched, group, graph, timing
-    o.topk_keep, o.dedup, o.xchunk = topk_keep, dedup, xchunk
+    o.topk_keep, o.dedup, o.xchunk, o.stage_split = topk_keep, dedup, xchunk, stage_split
     # the struct keeps a pointer to the encoded path: hold the bytes on the object
     o._tune_path = tune_cache.encode() if tune_cache else None
     o.tune_cache = o._tune_path

@@ -665,10 +665,14 @@ def test_dedup_option_validation(cfg1):
     p = cfg1.params
     ix = build(cfg1.data[:1000], p.a, p.b(), p.w)
     q = dev(cfg1.queries)
-    for kw in ({"dedup": 3}, {"dedup": -1}, {"xchunk": -1}, {"xchunk": 257}):
+    for kw in ({"dedup": 3}, {"dedup": -1}, {"xchunk": -1}, {"xchunk": 257}, {"stage_split": -2},
+               {"stage_split": 100}):
         with pytest.raises(lib.QwError) as e:
             ix.query(q, 10, lib.make_opts(**kw))
         assert e.value.status == lib.QW_EINVAL
+    with pytest.raises(lib.QwError) as e:  # the staging split is switched off
+        ix.query(q, 10, lib.make_opts(stage_split=50))
+    assert e.value.status == lib.QW_EUNSUPPORTED
     ix.close()
 
 
@@ -731,4 +735,36 @@ def test_oversized_requests_give_enomem(cfg1):
     ids_o, dist_o, _ = oracle.lsh_query(cfg1.data, cfg1.queries, p.a, p.b(), p.w, cfg1.K)
     ids, dist = ix.query(q, cfg1.K)
     check_topk(ids, dist, ids_o, dist_o, True)
+    ix.close()
+
+
+@pytest.mark.skip(reason="the non-temporal staging split faulted the GPU on its first run (memory "
+                         "fault during this test, cause not found by reading the code); its kernel "
+                         "path is switched off and split values are refused with QW_EUNSUPPORTED")
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_staging_split_keeps_results(dtype):
+    """The staging split (a share of the bucket lists and of the candidate rows
+    loaded non-temporally) changes only cache residency: every split, both
+    candidate kernels, both groupings and neighbour probing (more than 64
+    lists: the wide-list kernel) return the oracle's results."""
+    if dtype == "u8":
+        wl = synth.make_config(2, n=50_000, Q=500, ncomp=100)
+        w = 1000.0
+    else:
+        wl = synth.make_config(3, n=8000, Q=80, ncomp=40)
+        w = 4.0
+    p = wl.params
+    ix = build(wl.data, p.a, p.b(w), w)
+    q = dev(wl.queries)
+    for probes in (0, 1):
+        if probes:
+            ix.set_probing(1)
+        ids_o, dist_o, _ = oracle.lsh_query(wl.data, wl.queries, p.a, p.b(w), w, wl.K, probes=probes)
+        for split in (-1, 1, 50, 99):
+            for dedup in ((lib.QW_DEDUP_BLOCK, lib.QW_DEDUP_WAVE) if dtype == "u8" else (lib.QW_DEDUP_BLOCK,)):
+                for group in (0, 1):
+                    ids, dist, st = ix.query(q, wl.K, lib.make_opts(stage_split=split, dedup=dedup, group=group),
+                                             stats=True)
+                    assert st["split_used"] == split
+                    check_topk(ids, dist, ids_o, dist_o, dtype == "u8")
     ix.close()

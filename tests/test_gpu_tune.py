@@ -34,11 +34,13 @@ def test_tuned_and_default_outputs_identical(tmp_path, probing, model):
     assert r["candidates"] >= 4
     assert r["dedup"] in (1, 2) and r["group"] in (0, 1)
     assert (r["xchunk"] in (16, 64, 256)) if r["group"] else r["xchunk"] == 0
+    assert r["stage_split"] == -1
     assert 0 < r["ms"] <= r["ms_default"]
     doc = json.loads(cache.read_text())
     (e,) = doc["entries"]
     assert e["arch"].startswith("gfx") and len(e["key"]) == 16
-    assert (e["dedup"], e["group"], e["xchunk"]) == (r["dedup"], r["group"], r["xchunk"])
+    assert (e["dedup"], e["group"], e["xchunk"], e["split"]) == (r["dedup"], r["group"], r["xchunk"],
+                                                                 r["stage_split"])
 
     ids_d, dist_d, st = ix.query(q, K, lib.make_opts(), stats=True)
     assert st["tuned"] == 0 and st["dedup_used"] in (1, 2)
@@ -47,11 +49,13 @@ def test_tuned_and_default_outputs_identical(tmp_path, probing, model):
         ids_t, dist_t, st = ix.query(q, K, lib.make_opts(graph=graph, tune_cache=str(cache)), stats=True)
         assert st["tuned"] == 1
         assert (st["dedup_used"], st["group_used"], st["xchunk_used"]) == (r["dedup"], r["group"], r["xchunk"])
+        assert st["split_used"] == r["stage_split"]
         assert np.array_equal(ids_t.cpu().numpy(), ids_d)
         assert np.array_equal(dist_t.cpu().numpy(), dist_d)
     # an explicit setting wins over the cache
-    _, _, st = ix.query(q, K, lib.make_opts(dedup=1, group=0, tune_cache=str(cache)), stats=True)
-    assert (st["dedup_used"], st["group_used"], st["xchunk_used"]) == (1, 0, 0)
+    _, _, st = ix.query(q, K, lib.make_opts(dedup=1, group=0, stage_split=-1, tune_cache=str(cache)),
+                        stats=True)
+    assert (st["dedup_used"], st["group_used"], st["xchunk_used"], st["split_used"]) == (1, 0, 0, -1)
     ids_o, dist_o, _ = oracle.lsh_query(wl.data, wl.queries, p.a, p.b(), p.w, K, probes=probing, probe_t=2)
     assert np.array_equal(ids_d, ids_o)
     assert np.array_equal(dist_d.astype(np.int64),
