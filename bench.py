@@ -36,6 +36,9 @@ MFMA_PEAK_FP16_TFLOPS = 2500.0  # dense FP16 matrix peak (no sparsity)
 MFMA_PEAK_FP32_TFLOPS = 157.3   # dense FP32 matrix peak
 FP64_PEAK_TFLOPS = 78.6         # FP64 vector (fused multiply-add) peak
 W_GRID = [1, 1.5, 2, 2.5, 3, 4, 6, 8]
+# index share of the staged kernel's LDS caches swept (percent), the paper's
+# sweep of the index/data split
+SPLIT_SWEEP = [1, 10, 25, 50, 75, 90, 99]
 METRIC = "queries/sec at recall@10>=0.9, BF16+learned vs plain FP32 on 1 MI355X"
 # w_0.9 of the 1M x 960 float Zipf workload without neighbour probing (8 x 1.5),
 # measured with the w search above; its leg re-measures the recall
@@ -383,6 +386,21 @@ def main():
     settings = {"dedup": {1: "workgroup per query", 2: "wave per query"}.get(st["dedup_used"]),
                 "group": st["group_used"], "xchunk": st["xchunk_used"], "from_tune_cache": bool(st["tuned"])}
 
+    # ---- the staged kernel (LDS caches of bucket lists and rows kept across
+    # runs of consecutive queries, the GPU form of the paper's index/data cache
+    # split): the step time at each split of the sweep (bucket grouping on,
+    # so that neighbouring queries share buckets); every split must return the
+    # same results
+    split_sweep = {}
+    split_same = True
+    for sp in SPLIT_SWEEP:
+        o = lib.make_opts(sched=lib.QW_SCHED_LEARNED, stage_split=sp, group=1)
+        split_sweep[str(sp)] = round(timed(ix, o, max(5, args.steps // 2), 2), 4)
+        s_ids, s_dist = ix.query(q_d, K, o)
+        split_same &= bool(np.array_equal(s_ids.cpu().numpy(), f_ids_np) and
+                           np.array_equal(s_dist.cpu().numpy(), f_dist_np))
+    log(f"[bench] staged kernel split sweep (ms per step): {split_sweep}, identical {split_same}")
+
     # ---- hashing: algorithmic projection flops against the dense MFMA peak of
     # the type the kernel multiplies in (FP16 for uint8 data, FP32 for float),
     # over the n data rows the build hashes (timed on its own with events), and
@@ -585,6 +603,7 @@ def main():
         ms5 = {}
         same5 = True
         ref5 = None
+        split5 = {}
         for name, sc in (("learned", lib.QW_SCHED_LEARNED), ("sum", lib.QW_SCHED_SUM),
                          ("actual", lib.QW_SCHED_ACTUAL), ("none", lib.QW_SCHED_NONE)):
             o = lib.make_opts(sched=sc)
@@ -595,6 +614,12 @@ def main():
                 ref5 = got
             else:
                 same5 &= bool(np.array_equal(got[0], ref5[0]) and np.array_equal(got[1], ref5[1]))
+        for sp in SPLIT_SWEEP:  # the staged kernel on this workload
+            o = lib.make_opts(sched=lib.QW_SCHED_LEARNED, stage_split=sp, group=1)
+            split5[str(sp)] = round(timed(ix5, o, 3, 1, q5, oi5, od5), 3)
+            r_ids, r_dist = ix5.query(q5, wl5.K, o, out_ids=oi5, out_dist=od5)
+            split_same &= bool(np.array_equal(r_ids.cpu().numpy(), ref5[0]) and
+                               np.array_equal(r_dist.cpu().numpy(), ref5[1]))
         rec5 = recall_at_10(ref5[0][sel5], ti5.cpu().numpy(), ref5[1][sel5], td5.cpu().numpy())
         _, _, s5 = ix5.query(q5, wl5.K, lib.make_opts(sched=lib.QW_SCHED_LEARNED, graph=0),
                              out_ids=oi5, out_dist=od5, stats=True)
@@ -603,6 +628,7 @@ def main():
                          f"k={wl5.params.k} w={CFG5_W}, K={wl5.K}, no neighbour probing"),
             "ms_per_step": ms5, "sched_identical": same5,
             "learned_vs_sum": round(ms5["sum"] / ms5["learned"], 3),
+            "staged_split_ms": split5,
             "recall_at_10_sample500": round(rec5, 4),
             "train_queries": int(tr5.shape[0]), "train_loss": round(float(loss5), 4),
             "train_s": round(train5_s, 1),
@@ -649,6 +675,10 @@ def main():
         "forms_identical": identical,
         "sched_ms_per_step": sched_ms,
         "sched_identical": sched_identical,
+        "staged_split": {"index_share_percent_to_ms": split_sweep, "identical": split_same,
+                         "note": "ms per step of the staged kernel on this workload (grouping on); "
+                                 "float_zipf_schedules.staged_split_ms holds the sweep on the "
+                                 "1M x 960 float workload"},
         "plain_union": plain_union,
         "float_zipf_schedules": float_leg,
         "collision_counting": counting,

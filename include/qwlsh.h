@@ -109,14 +109,19 @@ typedef struct {
                           candidate sets in id-hash passes); ignored elsewhere */
     int32_t xchunk;    /* fast form with bucket grouping: consecutive items of the grouped
                           order dealt to one XCD (1..256; 0 = the tuned value or 256) */
-    int32_t stage_split; /* the split of the caches between the two streams a query reads
-                          (bucket lists, candidate rows), the GPU form of the split of
-                          Sections 4-5 between index files (C_I) and data objects (C_D).
-                          -1 = off (everything cached), 0 = automatic (off); a split
-                          s in 1..99 (bucket lists in the lowest s % of a 16-bit hash loaded
-                          into the caches, the rest streamed through with non-temporal loads,
-                          rows likewise with 100 - s %) is switched off in this build and
-                          refused with QW_EUNSUPPORTED. */
+    int32_t stage_split; /* fast form: the staged candidate kernel, the GPU form of the
+                          split of Sections 4-5 of a fixed cache between index files (C_I)
+                          and data objects (C_D).  s in 1..99: each workgroup takes runs of
+                          16 consecutive queries of the schedule's order and keeps in its
+                          80 KiB of LDS, beside a 32 KiB hash set, a cache of bucket id lists
+                          (s % of the rest, lists of at most 32 ids) and a cache of candidate
+                          rows (100 - s %), direct-mapped, across the run; a list or row found
+                          there is not read from memory.  Keys go to the select kernel; a
+                          query of more than 6144 bucket entries goes to the fallback.
+                          Needs at most 64 lists per query and rows of at most 4 KiB
+                          (QW_EUNSUPPORTED otherwise).  -1 = off (the other kernels), 0 =
+                          automatic (the tuned choice when tune_cache holds one, else off).
+                          Results are identical for every value. */
     const char *tune_cache; /* nullable: JSON file written by qw_autotune; automatic settings
                                (dedup 0, xchunk 0, group -1) take its entry for this
                                workload, when it has one */
@@ -237,7 +242,7 @@ qw_status qw_query_workload_noalloc(qw_index *ix, const void *queries, int64_t Q
 /* Outcome of qw_autotune (host). */
 typedef struct {
     int32_t dedup, group, xchunk; /* the fastest setting, explicit values (qw_opts meaning) */
-    int32_t stage_split;          /* -1: the staging split stays off */
+    int32_t stage_split;          /* -1 (off) or the index share in percent */
     float ms;                     /* its time per call (graph replay, mean of 5) */
     float ms_default;             /* the built-in automatic setting's time per call */
     int32_t candidates;           /* settings timed */
@@ -254,8 +259,10 @@ typedef struct {
  * neighbours: two warm-up calls, then five timed graph replays on `stream`.
  * All settings return the same ids and distances; a candidate whose outputs
  * differ from the built-in automatic setting's is a library bug and gives
- * QW_EINTERNAL.  `base` (nullable) supplies the remaining options (form must
- * be QW_FORM_FAST; its schedule is part of the cache key).
+ * QW_EINTERNAL.  Where the staged kernel applies (qw_opts.stage_split), the
+ * fastest of them is then timed at splits of 1, 10, 50, 90 and 99 %, and a
+ * split that beats it is kept.  `base` (nullable) supplies the remaining
+ * options (form must be QW_FORM_FAST; its schedule is part of the cache key).
  *  cache_path  host string: the JSON file, created or updated in place (one
  *              entry per line, keyed by the GPU architecture, e.g. gfx950, and
  *              a hash of n, d, dtype, L, k, w, the probing, Q, K, the schedule

@@ -34,9 +34,11 @@ enum {
 // u32: overflow-queue lengths per class (queue i holds queries that overflowed
 // class i-1), fallback queue, misc, then kXcd work counters per class
 enum { W_CLSDONE = 0, W_TOPK2 = 1, W_WORK = 2 /* .. 15: unused */, W_QCNT = 16 /* .. 32 */, W_SIMPLE = 33, W_MAX = 34,
-       W_DUMMY = 35, W_QMERGED = 36, W_FB = 44, W_FBWORK = 45, W_XWORK = 48,
+       W_DUMMY = 35, W_QMERGED = 36, W_FB = 44, W_FBWORK = 45, W_STAGE = 46, W_XWORK = 48,
        kC32 = W_XWORK + kXcd * (kMaxClasses + 1) };
 constexpr int kQueueMerged = kMaxClasses + 1;  // overflow queue of the merged launch
+constexpr uint32_t kStageChunk = 16;   // staged kernel: consecutive items per workgroup run
+constexpr int kStageBlocksPerCu = 2;   // its LDS (80 KiB) allows two workgroups per CU
 constexpr int64_t kCandPerQuery = 4096;  // pair space reserved per query (beyond: fallback)
 
 
@@ -386,7 +388,9 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     Workspace &w = ix->ws;
     if (ev) QW_HIP(hipEventRecord(ev[0], s));
     QW_TRY(clear_counters(ix, s));
-    const int topk = o.topk_keep >= 0 ? plan.topk : 0;  // in-kernel top K
+    // the staged kernel writes keys for the select kernel
+    const bool stage = o.stage_split > 0;
+    const int topk = !stage && o.topk_keep >= 0 ? plan.topk : 0;  // in-kernel top K
     const bool learned = o.sched == QW_SCHED_LEARNED && !ix->mlp.empty();
     // the binning kernel runs the count model itself; the grouped schedule
     // takes the predictions from the inference kernel
@@ -431,6 +435,34 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     // overflowed the class before it; queries that overflow the merged launch
     // are served afterwards by the global class.
     auto dedup_classes = [&](const int32_t *order, int count_only) -> qw_status {
+        if (stage && !count_only) {  // index/data caches in LDS at the chosen split
+            StageArgs a;
+            std::memset(&a, 0, sizeof(a));
+            a.order = order;
+            a.seg = seg;
+            a.ncls = plan.ncls;
+            a.counter = c32(ix) + W_STAGE;
+            a.chunk = kStageChunk;
+            a.bstart = w.bstart.as<uint32_t>();
+            a.bsize = w.bsize.as<uint32_t>();
+            a.ids = ix->ids.as<int32_t>();
+            a.n = ix->n;
+            a.nl = ix->nl;
+            a.pmagic = ix->pmagic;
+            a.dp = ix->dp;
+            a.dtype = ix->dtype;
+            a.data = ix->data.p;
+            a.queries = w.qrows;
+            a.keys = w.pkeys.as<unsigned long long>();
+            a.alloc = c64(ix) + C_ALLOC;
+            a.fail = c64(ix) + C_FAIL;
+            a.region = (unsigned long long)(cand_cap / kXcd);
+            a.ucount = w.ucount.as<uint32_t>();
+            a.coff = w.coff.as<unsigned long long>();
+            a.flag = w.flag.as<uint32_t>();
+            (void)stage_lds_bytes(ix->dp * (ix->dtype == QW_U8 ? 1 : 4), o.stage_split, &a.icn, &a.dcn);
+            return launch_stage(a, kStageBlocksPerCu * ix->cus, s);
+        }
         auto launch_range = [&](int lo, int hi, const int32_t *in_list, const uint32_t *in_count,
                                 int32_t *ovf_list, uint32_t *ovf_count, int slot, int queue_only,
                                 hipStream_t st) -> qw_status {
@@ -735,7 +767,7 @@ bool qw::resolve_fast_auto(qw_index *ix, int64_t Q, int32_t K, qw_opts *o, bool 
         if (o->group < 0) o->group = e.group;
         // the tuned chunk belongs to the tuned grouping
         if (o->xchunk == 0 && grp && e.group) o->xchunk = e.xchunk;
-        if (o->stage_split == 0 && e.split <= 0) o->stage_split = e.split;
+        if (o->stage_split == 0) o->stage_split = e.split;
     }
     if (o->stage_split == 0) o->stage_split = -1;  // off unless tuned or asked for
     if (o->dedup == 0) o->dedup = plan.wgrid > 0 && plan.wave_default ? 2 : 1;
@@ -849,8 +881,14 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
     if (opt.dedup < 0 || opt.dedup > 2 || opt.xchunk < 0 || opt.xchunk > (int32_t)kXcdChunk)
         return QW_EINVAL;
     if (opt.stage_split < -1 || opt.stage_split > 99) return QW_EINVAL;
-    // the non-temporal staging split is switched off (see the header)
-    if (opt.stage_split > 0) return QW_EUNSUPPORTED;
+    // the staged kernel: fast form, at most 64 lists per query, rows of at most 4 KiB
+    if (opt.stage_split > 0) {
+        const int rb = ix->dp * (ix->dtype == QW_U8 ? 1 : 4);
+        uint32_t icn = 0, dcn = 0;
+        if (opt.form != QW_FORM_FAST || ix->nl > 64 || ix->count_theta > 0 || rb > kStageMaxRow ||
+            stage_lds_bytes(rb, opt.stage_split, &icn, &dcn) > ix->lds_max)
+            return QW_EUNSUPPORTED;
+    }
     if (Q == 0) {
         if (st) std::memset(st, 0, sizeof(*st));
         return QW_OK;
@@ -890,12 +928,19 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
             return QW_OK;
         }
         const Plan plan = make_plan(ix, K);
-        QW_TRY(ensure_ws(ix, Q, &plan, !(opt.topk_keep >= 0 && plan.topk)));
         const bool learned = opt.sched == QW_SCHED_LEARNED && !ix->mlp.empty();
         const int sched = opt.sched == QW_SCHED_LEARNED && !learned ? QW_SCHED_SUM : opt.sched;
         qw_opts eff = opt;
         eff.sched = sched;
         const bool tuned = resolve_fast_auto(ix, Q, K, &eff, nullptr);
+        // a tuned split applies only where the staged kernel does
+        if (eff.stage_split > 0) {
+            const int rb = ix->dp * (ix->dtype == QW_U8 ? 1 : 4);
+            uint32_t icn = 0, dcn = 0;
+            if (ix->nl > 64 || rb > kStageMaxRow || stage_lds_bytes(rb, eff.stage_split, &icn, &dcn) > ix->lds_max)
+                eff.stage_split = -1;
+        }
+        QW_TRY(ensure_ws(ix, Q, &plan, !(eff.topk_keep >= 0 && plan.topk) || eff.stage_split > 0));
         if (opt.timing || !opt.graph) {
             QW_TRY(enqueue_fast(ix, plan, queries, Q, K, eff, s, out_ids, out_dist,
                                 opt.timing ? ix->ev : nullptr));

@@ -463,6 +463,39 @@ struct SelectArgs {
     const void *data, *queries;
 };
 
+// Staged candidate kernel (qw_opts.stage_split): one workgroup per run of
+// `chunk` consecutive items of the order (classes largest first), LDS caches
+// of bucket id lists (icn slots of kStageIps ids) and rows (dcn slots) kept
+// across them; keys for the select kernel, flag[q] = 1 for queries left to
+// the fallback.
+constexpr int kStageIps = 32;                        // ids per index-cache slot
+constexpr size_t kStageLdsBytes = 80 * 1024;         // two workgroups per CU
+constexpr int kStageMaxRow = 4096;                   // row bytes at most
+struct StageArgs {
+    const int32_t *order;
+    const unsigned long long *seg;  // {begin, end} of each class in the order
+    int32_t ncls;
+    uint32_t *counter;              // run counter (zero on entry)
+    uint32_t chunk;                 // items per run
+    const uint32_t *bstart, *bsize;
+    const int32_t *ids;
+    int64_t n;
+    int32_t nl;                     // lists per query (at most 64)
+    uint32_t pmagic;
+    int32_t dp, dtype;
+    const void *data, *queries;
+    unsigned long long *keys, *alloc, *fail;
+    unsigned long long region;
+    uint32_t *ucount;
+    unsigned long long *coff;
+    uint32_t *flag;
+    uint32_t icn, dcn;              // index / data cache slots
+};
+// LDS bytes of the staged kernel for rows of row_bytes at an index share of
+// `split` percent; icn/dcn receive the cache slots.
+size_t stage_lds_bytes(int row_bytes, int32_t split, uint32_t *icn, uint32_t *dcn);
+qw_status launch_stage(const StageArgs &a, int grid, hipStream_t s);
+
 size_t dedup_lds_bytes(int cap_log2, int global_tab, int L, int row_bytes);
 int dedup_blocks_per_cu(size_t lds, int dtype);
 qw_status launch_dedup(const DedupArgs &a, int grid, hipStream_t s);

@@ -195,6 +195,13 @@ extern "C" qw_status qw_autotune(qw_index *ix, const void *queries, int64_t Q, i
                 cands.push_back(c);
         }
 
+    // the staging split goes on the fastest setting, where the staged kernel applies
+    uint32_t icn = 0, dcn = 0;
+    const int rb = ix->dp * (ix->dtype == QW_U8 ? 1 : 4);
+    const bool stage_ok = ix->nl <= 64 && rb <= kStageMaxRow &&
+                          stage_lds_bytes(rb, 50, &icn, &dcn) <= ix->lds_max;
+    const size_t nbase = cands.size();
+    constexpr int kSplits[] = {1, 10, 50, 90, 99};
     void *d_ids = nullptr, *d_dist = nullptr;
     if (hipMalloc(&d_ids, sizeof(int32_t) * (size_t)Q * K) != hipSuccess ||
         hipMalloc(&d_dist, sizeof(uint32_t) * (size_t)Q * K) != hipSuccess) {  // int32 or float32
@@ -210,6 +217,12 @@ extern "C" qw_status qw_autotune(qw_index *ix, const void *queries, int64_t Q, i
     size_t best_i = 0;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = QW_EDEVICE;
     for (size_t i = 0; rc == QW_OK && i < cands.size(); ++i) {
+        if (i == nbase && stage_ok)  // every base setting is timed: splits on the fastest
+            for (int sp : kSplits) {
+                Cand c = cands[best_i];
+                c.split = sp;
+                cands.push_back(c);
+            }
         qw_opts o = b;
         o.dedup = cands[i].dedup;
         o.group = cands[i].group;

@@ -670,7 +670,11 @@ def test_dedup_option_validation(cfg1):
         with pytest.raises(lib.QwError) as e:
             ix.query(q, 10, lib.make_opts(**kw))
         assert e.value.status == lib.QW_EINVAL
-    with pytest.raises(lib.QwError) as e:  # the staging split is switched off
+    with pytest.raises(lib.QwError) as e:  # the staged kernel takes the fast form only
+        ix.query(q, 10, lib.make_opts(stage_split=50, form=lib.QW_FORM_PLAIN_FP32))
+    assert e.value.status == lib.QW_EUNSUPPORTED
+    ix.set_probing(1)  # 170 lists per query: beyond the staged kernel's 64
+    with pytest.raises(lib.QwError) as e:
         ix.query(q, 10, lib.make_opts(stage_split=50))
     assert e.value.status == lib.QW_EUNSUPPORTED
     ix.close()
@@ -767,4 +771,52 @@ def test_staging_split_keeps_results(dtype):
                                              stats=True)
                     assert st["split_used"] == split
                     check_topk(ids, dist, ids_o, dist_o, dtype == "u8")
+    ix.close()
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_staged_kernel_keeps_results(dtype):
+    """The staged candidate kernel (LDS caches of bucket lists and rows kept
+    across runs of consecutive queries, split s % / 100 - s %) returns the
+    oracle's results at every split, with and without bucket grouping, for
+    every schedule, K of 1 and 10, and with query-directed probing (60 lists);
+    queries beyond its set go to the fallback."""
+    if dtype == "u8":
+        wl = synth.make_config(2, n=50_000, Q=400, ncomp=100)
+        w = 1000.0
+    else:
+        wl = synth.make_config(3, n=8000, Q=80, ncomp=40)
+        w = 4.0
+    p = wl.params
+    ix = build(wl.data, p.a, p.b(w), w)
+    q = dev(wl.queries)
+    for probes in (0, 2):
+        if probes:
+            ix.set_probing(2, 2)
+        for K in (1, wl.K):
+            ids_o, dist_o, cnt = oracle.lsh_query(wl.data, wl.queries, p.a, p.b(w), w, K, probes=probes,
+                                                  probe_t=2)
+            for split in (1, 50, 99):
+                for group in (0, 1):
+                    for sched in (lib.QW_SCHED_SUM, lib.QW_SCHED_NONE):
+                        ids, dist, st = ix.query(q, K, lib.make_opts(stage_split=split, group=group,
+                                                                     sched=sched), stats=True)
+                        assert st["split_used"] == split
+                        assert st["cand_unique"] == int(cnt.sum())
+                        check_topk(ids, dist, ids_o, dist_o, dtype == "u8")
+    ix.close()
+
+
+def test_staged_kernel_large_candidate_sets(cfg1):
+    """Queries with more bucket entries than the staged kernel's set holds
+    (w = 3000 on the small workload: up to 6,700 unique candidates) go to the
+    fallback and keep exact results; so do K beyond the fused limit."""
+    p = cfg1.params
+    w = 3000.0
+    ix = build(cfg1.data, p.a, p.b(w), w)
+    q = dev(cfg1.queries)
+    for K in (10, 40):
+        ids_o, dist_o, _ = oracle.lsh_query(cfg1.data, cfg1.queries, p.a, p.b(w), w, K)
+        ids, dist = ix.query(q, K, lib.make_opts(stage_split=50))
+        check_topk(ids, dist, ids_o, dist_o, True)
     ix.close()
