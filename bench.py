@@ -621,14 +621,21 @@ def main():
             split_same &= bool(np.array_equal(r_ids.cpu().numpy(), ref5[0]) and
                                np.array_equal(r_dist.cpu().numpy(), ref5[1]))
         rec5 = recall_at_10(ref5[0][sel5], ti5.cpu().numpy(), ref5[1][sel5], td5.cpu().numpy())
-        _, _, s5 = ix5.query(q5, wl5.K, lib.make_opts(sched=lib.QW_SCHED_LEARNED, graph=0),
-                             out_ids=oi5, out_dist=od5, stats=True)
+        # the candidate kernel's roofline under the learned schedule (its stage
+        # time from the library's events; the stored counter traffic of the same
+        # workload when the kernel's sources still match)
+        stage5, s5 = stage_times(ix5, dict(sched=lib.QW_SCHED_LEARNED), nrep=3, queries=q5)
+        roof5 = candidate_roofline(s5, float(stage5[6]), wl5.Q, wl5.d, 4, wl5.K, False, 5, CFG5_W, 0, 0)
         float_leg = {
             "workload": (f"n={wl5.n} d={wl5.d} f32, Q={wl5.Q} Zipf queries, L={wl5.params.L} "
                          f"k={wl5.params.k} w={CFG5_W}, K={wl5.K}, no neighbour probing"),
             "ms_per_step": ms5, "sched_identical": same5,
             "learned_vs_sum": round(ms5["sum"] / ms5["learned"], 3),
             "staged_split_ms": split5,
+            "roofline": roof5,
+            "stage_ms": {"hash": round(float(stage5[0]), 4), "probe": round(float(stage5[1]), 4),
+                         "schedule": round(float(stage5[2]), 4), "dedup": round(float(stage5[6]), 4),
+                         "select": round(float(stage5[7]), 4), "total": round(float(stage5[5]), 4)},
             "recall_at_10_sample500": round(rec5, 4),
             "train_queries": int(tr5.shape[0]), "train_loss": round(float(loss5), 4),
             "train_s": round(train5_s, 1),
