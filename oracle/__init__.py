@@ -11,6 +11,9 @@ Modules:
                   loaded here through ctypes.
   mlp.py       -- FP64 forward/backward of the candidate-count regressor.
   collision.py -- the p-stable collision probability of Eq. (1).
+  ooc.py       -- the index and data caches of the out-of-core setting
+                  (Sections 4 and 5.1): IO counts of a workload answered in
+                  batches through a C_I / C_D split with MRU or LRU eviction.
 """
 from __future__ import annotations
 
