@@ -151,6 +151,13 @@ typedef struct {
     int32_t tuned;         /* 1 when the tuning cache supplied an automatic setting; all five
                               are 0 in the plain form and under collision counting */
     int32_t split_used;    /* staging split (-1 off, else the index share in percent) */
+    /* out-of-core mode (qw_set_out_of_core), this call's reads from host memory: */
+    int64_t ooc_index_files;   /* index files (bucket id lists) read into the index cache */
+    int64_t ooc_index_bytes;   /* their bytes (4 per id) */
+    int64_t ooc_data_objects;  /* data objects (rows) read into the data cache */
+    int64_t ooc_data_bytes;    /* their bytes (row_bytes each, the padded row) */
+    int64_t ooc_batches;       /* batches answered */
+    int64_t ooc_splits;        /* batches that did not fit the cache and were halved */
 } qw_stats;
 
 typedef struct {
@@ -169,6 +176,9 @@ typedef struct {
     int32_t count_extra;      /* qw_set_counting extra (v) */
     double mean_hit_bucket;   /* mean over layers of sum_b s_b^2 / n: the expected size of the
                                  bucket a data point falls in */
+    int32_t out_of_core;      /* 1 while qw_set_out_of_core is on */
+    int32_t reserved;
+    int64_t host_bytes;       /* pinned host memory held (the out-of-core lists and rows) */
 } qw_index_info;
 
 typedef struct qw_index qw_index;
@@ -424,6 +434,80 @@ qw_status qw_set_probing(qw_index *ix, int32_t mode, int32_t per_layer);
  * called while work on the index is in flight.
  */
 qw_status qw_set_counting(qw_index *ix, int32_t threshold, int32_t extra);
+
+/* ---- out-of-core mode -------------------------------------------------------
+ *
+ * Section 1.2 and Section 4: the index files and the data objects sit on
+ * external storage, and a cache C = C_I + C_D in memory holds some of them, C_I
+ * index files and C_D data objects.  Section 5.1: each part evicts by MRU, and
+ * C_I is either divided equally among the hash functions' layers (Strategy 1)
+ * or shared by all of them (Strategy 2).
+ * Here host memory is the storage and HBM is the cache.  An index file is one
+ * bucket's id list (4 bytes per id).  A data object is one point's padded
+ * row (dp elements).  The probe tables and hash parameters stay in HBM.
+ *
+ * The workload is answered in batches of consecutive queries.  Each batch:
+ *  1. reads its missing bucket lists into C_I;
+ *  2. reads its candidates' missing rows into C_D;
+ *  3. runs the plain form's union, verification and top-K from HBM alone.
+ * Eviction and IO counting follow the reading stated in the oracle's cache
+ * model; a batch of one query is the paper's query-at-a-time setting.
+ *  - An item's recency is its last use.  Query q uses its layer-l bucket at
+ *    q*L + l + 1, and a row of C(q) at q + 1; rows used last by the same query
+ *    are ordered by id.
+ *  - A batch evicts, outside its own needs, the most recently used items
+ *    first (QW_OOC_LRU: least recently used first), until its misses fit.
+ *  - A batch that does not fit is answered as two halves.
+ * Results are those of the in-core index (bit for bit).
+ */
+typedef enum { QW_OOC_MRU = 0, QW_OOC_LRU = 1 } qw_ooc_policy;
+
+typedef struct {
+    int64_t cache_bytes;    /* C, HBM bytes of the two caches; C_I = C * index_percent / 100
+                               (floor) holds floor(C_I / 4) ids, C_D = C - C_I holds
+                               floor(C_D / row_bytes) rows */
+    int32_t index_percent;  /* C_I's share, 1..99 */
+    int32_t strategy;       /* 1: C_I split equally among the L layers (floor(ids / L) ids
+                               each); 2: one C_I for all layers */
+    int32_t policy;         /* qw_ooc_policy */
+    int32_t batch;          /* queries per batch, >= 1 */
+    int32_t keep;           /* 0: every qw_query_workload call starts with empty caches (a
+                               workload on its own, as the paper measures); 1: the caches
+                               persist across calls */
+    int32_t reserved;       /* 0 */
+} qw_ooc_opts;
+
+/*
+ * Move the index's CSR ids ([L][n] int32) and data rows ([n][dp]) to pinned
+ * host memory, free their HBM copies, and give HBM to the two caches.
+ *  o       host; NULL moves everything back to HBM and frees the caches.
+ *  stream  used for the copies; synchronised before returning.
+ * Calling it again with new options keeps the host copies and rebuilds the
+ * caches empty.
+ *
+ * While the mode is on:
+ *  - qw_query_workload answers through the caches, whichever form it names:
+ *    the form's hashing, then the plain form's per-query kernel.  The
+ *    statistics' ooc_* fields count the reads.
+ *  - qw_hash and qw_bucket_sizes work as before.
+ *  - QW_EUNSUPPORTED from the calls that would read the data or the lists
+ *    outside the caches: qw_query_workload_noalloc, qw_candidate_counts,
+ *    qw_candidate_lists, qw_bruteforce_knn, qw_train_count_model and
+ *    qw_autotune; also from qw_set_probing / qw_set_counting with a mode
+ *    other than off, and from qw_opts.stage_split > 0.
+ *
+ * Errors:
+ *  - QW_EINVAL on bad options;
+ *  - QW_EUNSUPPORTED when probing or counting is on, or when C_I exceeds
+ *    2^31 - 1 ids;
+ *  - QW_ENOMEM when the caches or the pinned host copies cannot be allocated.
+ *    The index is then left as it was.
+ * A query workload returns QW_EUNSUPPORTED when one query's bucket lists or
+ * candidate rows do not fit their cache, or when its hash set does not fit
+ * on-chip memory.  The outputs of the queries before it are written; the rest
+ * are unspecified.
+ */
+qw_status qw_set_out_of_core(qw_index *ix, const qw_ooc_opts *o, void *stream);
 
 #ifdef __cplusplus
 }

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libqwlsh.so")
 ARCH = os.environ.get("QWLSH_ARCH", "gfx950")
 
 SOURCES = ["qw_common.hip", "qw_hash.hip", "qw_build.hip", "qw_verify.hip", "qw_dedup.hip", "qw_wdedup.hip",
-           "qw_select.hip", "qw_count.hip", "qw_sched.hip", "qw_mlp.hip", "qw_tune.hip", "qw_stage.hip", "qw_capi.hip"]
+           "qw_select.hip", "qw_count.hip", "qw_sched.hip", "qw_mlp.hip", "qw_tune.hip", "qw_stage.hip", "qw_ooc.hip", "qw_capi.hip"]
 
 CXXFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",

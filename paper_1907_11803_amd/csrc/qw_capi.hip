@@ -368,6 +368,32 @@ qw_status count_query(qw_index *ix, int64_t Q, int K, hipStream_t s, int32_t *ou
     return launch_count(a, Q, s);
 }
 
+// Out-of-core answer of Q probed queries: one hash-set size for all queries
+// (from the largest list total, read back: the call synchronises), then the
+// batches through the caches.  Refuses a set beyond on-chip memory.
+qw_status ooc_query(qw_index *ix, int64_t Q, int K, hipStream_t s, int32_t *out_ids,
+                    void *out_dist, OocIo *io, hipEvent_t ev_sched)
+{
+    uint32_t *mx = c32(ix) + W_MAX;
+    QW_TRY(launch_fill_u32(mx, 0u, 1, s));
+    QW_TRY(launch_max_bucket_sum(ix->ws.bsize.as<uint32_t>(), Q, ix->L, mx, s));
+    uint32_t maxsum = 0;
+    QW_HIP(hipMemcpyAsync(&maxsum, mx, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    QW_HIP(hipStreamSynchronize(s));
+    if (ev_sched) QW_HIP(hipEventRecord(ev_sched, s));
+    const uint64_t bound = std::min<uint64_t>(maxsum, (uint64_t)ix->n);
+    int cap = kCmin;
+    while ((3ull << cap) < 4 * bound) ++cap;  // load factor <= 3/4: never overflows
+    VerifyArgs a = base_args(ix, K, VM_TOPK);
+    const int buf = pow2_at_least(std::max(64, 2 * (K + verify_per_iter(ix->dp, ix->dtype))));
+    if (verify_lds_bytes(cap, buf, 0, ix->nl, ix->dp, ix->dtype) > ix->lds_max)
+        return QW_EUNSUPPORTED;
+    a.buf = (uint32_t)buf;
+    a.cap_log2 = (uint32_t)cap;
+    a.limit = (1u << cap) / 4 * 3;
+    return ooc_answer(ix, Q, a, ix->ws.qrows, out_ids, out_dist, s, io);
+}
+
 qw_status check_index(const qw_index *ix)
 {
     if (!ix) return QW_EINVAL;
@@ -862,6 +888,17 @@ qw_status qw_get_index_info(const qw_index *ix, qw_index_info *info)
     info->count_threshold = ix->count_theta;
     info->count_extra = ix->count_extra;
     info->mean_hit_bucket = ix->mean_hit_bucket;
+    info->out_of_core = ix->ooc ? 1 : 0;
+    info->host_bytes = ix->ooc ? (int64_t)ix->ooc->host_bytes : 0;
+    if (ix->ooc) {
+        const OocState &o = *ix->ooc;
+        for (const DevBuf *b : {&o.arena[0], &o.arena[1], &o.rows, &o.mkey, &o.msize, &o.mstamp,
+                                &o.moff, &o.mnoff, &o.mneed, &o.owner, &o.freel, &o.dir,
+                                &o.rstamp, &o.rneed, &o.missd, &o.copyl, &o.ckeys,
+                                &o.ckeys2, &o.cvals, &o.cvals2, &o.csz, &o.cscan, &o.sort_hist,
+                                &o.scan_tmp, &o.bstart2, &o.ctr})
+            info->device_bytes += (int64_t)b->bytes;
+    }
     return QW_OK;
 }
 
@@ -881,6 +918,7 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
     if (opt.dedup < 0 || opt.dedup > 2 || opt.xchunk < 0 || opt.xchunk > (int32_t)kXcdChunk)
         return QW_EINVAL;
     if (opt.stage_split < -1 || opt.stage_split > 99) return QW_EINVAL;
+    if (ix->ooc && opt.stage_split > 0) return QW_EUNSUPPORTED;
     // the staged kernel: fast form, at most 64 lists per query, rows of at most 4 KiB
     if (opt.stage_split > 0) {
         const int rb = ix->dp * (ix->dtype == QW_U8 ? 1 : 4);
@@ -896,6 +934,30 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
     hipStream_t s = S(stream);
     try {
         if (opt.timing) QW_TRY(ensure_events(ix));
+        if (ix->ooc) {  // out of core: either form's hashing, then batches through the caches
+            QW_TRY(ensure_ws(ix, Q, nullptr));
+            hipEvent_t *ev = opt.timing ? ix->ev : nullptr;
+            if (ev) QW_HIP(hipEventRecord(ev[0], s));
+            QW_TRY(clear_counters(ix, s));
+            QW_TRY(front(ix, queries, Q, opt.form, s, ev));
+            if (ev) QW_HIP(hipEventRecord(ev[2], s));
+            OocIo io;
+            QW_TRY(ooc_query(ix, Q, K, s, out_ids, out_dist, &io, ev ? ev[3] : nullptr));
+            if (ev) {
+                QW_HIP(hipEventRecord(ev[4], s));
+                QW_HIP(hipEventRecord(ev[5], s));
+            }
+            if (st) {
+                QW_TRY(fill_stats(ix, Q, s, st, ev, false));
+                st->ooc_index_files = io.index_files;
+                st->ooc_index_bytes = io.index_bytes;
+                st->ooc_data_objects = io.data_objects;
+                st->ooc_data_bytes = io.data_bytes;
+                st->ooc_batches = io.batches;
+                st->ooc_splits = io.splits;
+            }
+            return QW_OK;
+        }
         if (ix->count_theta > 0) {  // collision counting, either form's hashing
             QW_TRY(ensure_ws(ix, Q, nullptr));
             hipEvent_t *ev = opt.timing ? ix->ev : nullptr;
@@ -1001,6 +1063,7 @@ qw_status qw_query_workload_noalloc(qw_index *ix, const void *queries, int64_t Q
     QW_TRY(check_index(ix));
     QW_TRY(check_vectors(ix, queries, Q));
     if (K < 1 || K > kMaxTopK || (Q > 0 && (!out_ids || !out_dist))) return QW_EINVAL;
+    if (ix->ooc) return QW_EUNSUPPORTED;  // the lists and rows are in host memory
     if (Q == 0) return QW_OK;
     void *base = nullptr;
     QW_TRY(scratch_address(ix->device, &base));
@@ -1077,6 +1140,7 @@ qw_status qw_candidate_counts(qw_index *ix, const void *queries, int64_t Q, void
     QW_TRY(check_index(ix));
     QW_TRY(check_vectors(ix, queries, Q));
     if (Q > 0 && !out_counts) return QW_EINVAL;
+    if (ix->ooc) return QW_EUNSUPPORTED;
     if (Q == 0) return QW_OK;
     hipStream_t s = S(stream);
     QW_TRY(ensure_ws(ix, Q, nullptr));
@@ -1091,6 +1155,7 @@ qw_status qw_candidate_lists(qw_index *ix, const void *queries, int64_t Q, const
     QW_TRY(check_index(ix));
     QW_TRY(check_vectors(ix, queries, Q));
     if (Q > 0 && (!offsets || !out_ids)) return QW_EINVAL;
+    if (ix->ooc) return QW_EUNSUPPORTED;
     if (Q == 0) return QW_OK;
     hipStream_t s = S(stream);
     QW_TRY(ensure_ws(ix, Q, nullptr));
@@ -1106,6 +1171,7 @@ qw_status qw_bruteforce_knn(qw_index *ix, const void *queries, int64_t Q, int32_
     QW_TRY(check_index(ix));
     QW_TRY(check_vectors(ix, queries, Q));
     if (K < 1 || K > kMaxTopK || (Q > 0 && (!out_ids || !out_dist))) return QW_EINVAL;
+    if (ix->ooc) return QW_EUNSUPPORTED;
     if (Q == 0) return QW_OK;
     hipStream_t s = S(stream);
     QW_TRY(ensure_ws(ix, Q, nullptr));
@@ -1182,6 +1248,7 @@ qw_status qw_set_probing(qw_index *ix, int32_t mode, int32_t per_layer)
     QW_TRY(check_index(ix));
     if (mode < 0 || mode > 2) return QW_EINVAL;
     if (mode == 2 && (per_layer < 1 || per_layer > 2 * ix->k)) return QW_EINVAL;
+    if (ix->ooc && mode != 0) return QW_EUNSUPPORTED;  // out of core: each layer's own bucket
     const int32_t P = mode == 2 ? 1 + per_layer : (mode ? 2 * ix->k + 1 : 1);
     if ((int64_t)ix->L * P > kMaxLists) return QW_EUNSUPPORTED;
     uint32_t magic = 0;
@@ -1205,9 +1272,35 @@ qw_status qw_set_counting(qw_index *ix, int32_t threshold, int32_t extra)
 {
     QW_TRY(check_index(ix));
     if (threshold < 0 || threshold > ix->L || extra < 0 || extra > kMaxTopK) return QW_EINVAL;
+    if (ix->ooc && threshold != 0) return QW_EUNSUPPORTED;
     ix->count_theta = threshold;
     ix->count_extra = threshold ? extra : 0;
     return QW_OK;
+}
+
+qw_status qw_set_out_of_core(qw_index *ix, const qw_ooc_opts *o, void *stream)
+{
+    QW_TRY(check_index(ix));
+    hipStream_t s = S(stream);
+    try {
+        if (!o) {
+            if (!ix->ooc) return QW_OK;
+            drop_graphs(ix);
+            return ooc_disable(ix, s);
+        }
+        if (o->cache_bytes <= 0 || o->index_percent < 1 || o->index_percent > 99 ||
+            (o->strategy != 1 && o->strategy != 2) ||
+            (o->policy != QW_OOC_MRU && o->policy != QW_OOC_LRU) || o->batch < 1 ||
+            (o->keep != 0 && o->keep != 1) || o->reserved != 0)
+            return QW_EINVAL;
+        if (ix->nprobe != 1 || ix->count_theta > 0) return QW_EUNSUPPORTED;
+        drop_graphs(ix);  // captured graphs read the in-core lists and rows
+        return ooc_enable(ix, *o, s);
+    } catch (const std::bad_alloc &) {
+        return QW_ENOMEM;
+    } catch (...) {
+        return QW_EINTERNAL;
+    }
 }
 
 qw_status qw_get_count_model(const qw_index *ix, float *params, int32_t P)
@@ -1224,6 +1317,7 @@ qw_status qw_train_count_model(qw_index *ix, const void *train_queries, int64_t 
     QW_TRY(check_index(ix));
     QW_TRY(check_vectors(ix, train_queries, m));
     if (m < 1 || epochs < 1 || batch < 1 || !(lr > 0.f)) return QW_EINVAL;
+    if (ix->ooc) return QW_EUNSUPPORTED;  // the labels need the candidate sets
     hipStream_t s = S(stream);
     const int32_t L = ix->L, P = qw_mlp_param_count(L);
     const int32_t B = (int32_t)std::min<int64_t>(batch, m);

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -162,6 +163,48 @@ struct TuneEntry {
     double ms = 0.0, ms_default = 0.0;
 };
 
+// Out-of-core mode: the CSR ids and the padded rows in pinned host memory,
+// and the two HBM caches (bucket lists in C_I, rows in C_D) with their
+// bookkeeping.  Bucket records live in an open-addressing map keyed by the
+// bucket's position in the CSR (layer * n + start), never deleted, whose
+// capacity is at least twice the number of buckets.
+struct OocState {
+    qw_ooc_opts o{};
+    int32_t npools = 1;
+    int64_t cap_pool = 0;     // ids per C_I pool
+    int64_t ids_total = 0;    // npools * cap_pool: the arena
+    int64_t cap_rows = 0;     // rows in C_D
+    int64_t row_bytes = 0;
+    void *host_ids = nullptr, *host_rows = nullptr;  // pinned host copies
+    const void *dev_ids = nullptr, *dev_rows = nullptr;  // their device addresses
+    size_t host_bytes = 0;
+    int64_t mcap = 0;         // map slots (power of two)
+    DevBuf arena[2];          // C_I: resident lists, rebuilt into the other arena per batch
+    int cur = 0;
+    DevBuf mkey, msize, mstamp, moff, mnoff, mneed, mmiss;  // per map slot
+    DevBuf rows, owner;       // C_D: cap_rows rows and the id held by each slot (-1 free)
+    DevBuf dir, rstamp, rneed, rmiss;  // per point: slot (-1), last use, batch tags
+    DevBuf missd, ckeys, cvals, ckeys2, cvals2, csz, cscan, sort_hist, scan_tmp, copyl, freel,
+        bstart2, ctr;
+    int64_t cand_cap = 0;     // entries of the candidate lists
+    uint32_t tag = 0;         // batch attempt counter (tags are never reused)
+    int64_t rows_used = 0;    // resident rows (host mirror)
+    OocState() = default;
+    OocState(const OocState &) = delete;
+    OocState &operator=(const OocState &) = delete;
+    ~OocState()
+    {
+        if (host_ids) (void)hipHostFree(host_ids);
+        if (host_rows) (void)hipHostFree(host_rows);
+    }
+};
+
+// Reads of one out-of-core query call.
+struct OocIo {
+    int64_t index_files = 0, index_bytes = 0, data_objects = 0, data_bytes = 0, batches = 0,
+            splits = 0;
+};
+
 struct GraphKey {
     const void *q; int64_t Q; int32_t K; int32_t *ids; void *dist;
     int32_t form, sched, group, topk_keep, dedup, xchunk, split;
@@ -227,6 +270,8 @@ struct qw_index {
     // device's architecture name
     std::string tune_path, tune_arch;
     std::vector<qw::TuneEntry> tune_entries;
+    // out-of-core mode (null: data and lists in HBM)
+    std::unique_ptr<qw::OocState> ooc;
 
     qw_index() = default;
     qw_index(const qw_index &) = delete;
@@ -332,6 +377,8 @@ struct VerifyArgs {
     int32_t *out_counts;         // COUNT
     const long long *offsets;    // LIST
     uint32_t *ucount_out;        // nullable: |C(q)| of each answered query
+    const int32_t *row_slot;     // nullable: row of point id is data + row_slot[id] * row bytes
+                                 // (the out-of-core data cache); LDS hash sets only
 };
 
 // Collision counting (one workgroup per query; plain layer lists, no probing).
@@ -359,6 +406,20 @@ constexpr int64_t kCountMaxN = (int64_t(1) << 25) - 1;
 
 size_t verify_lds_bytes(int cap_log2, int buf, int global_tab, int L, int dp, int dtype);
 qw_status launch_verify(const VerifyArgs &a, int grid, hipStream_t s);
+
+// ---------------------------------------------------------------- out-of-core mode
+// Host copies and empty caches for options `o` (validated by the caller).
+qw_status ooc_enable(qw_index *ix, const qw_ooc_opts &o, hipStream_t s);
+// Everything back in HBM, caches freed.
+qw_status ooc_disable(qw_index *ix, hipStream_t s);
+// Empty both caches.
+qw_status ooc_reset(qw_index *ix, hipStream_t s);
+// Answer Q probed queries (ws.bstart / ws.bsize hold their buckets) in
+// batches through the caches.  `tmpl` carries the verify launch's settings
+// (mode, K, set size, buffers); the per-batch pointers are filled here.
+// out_dist_elem: bytes per distance.  Synchronises s per batch.
+qw_status ooc_answer(qw_index *ix, int64_t Q, const VerifyArgs &tmpl, const void *qrows,
+                     int32_t *out_ids, void *out_dist, hipStream_t s, OocIo *io);
 // Candidates processed per workgroup iteration (sizes the top-K buffer).
 int verify_per_iter(int dp, int dtype);
 // Resident workgroups per CU of the verify kernel with `lds` bytes of LDS.

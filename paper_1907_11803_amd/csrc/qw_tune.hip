@@ -164,6 +164,7 @@ extern "C" qw_status qw_autotune(qw_index *ix, const void *queries, int64_t Q, i
 {
     if (!ix || !queries || Q < 1 || K < 1 || K > kMaxTopK || !cache_path || !out) return QW_EINVAL;
     if (ix->count_theta > 0) return QW_EINVAL;  // collision counting has no fast-form settings
+    if (ix->ooc) return QW_EUNSUPPORTED;        // out of core: the plain form's kernel only
     int dev = -1;
     QW_HIP(hipGetDevice(&dev));
     if (dev != ix->device) return QW_EINVAL;

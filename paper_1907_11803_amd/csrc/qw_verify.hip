@@ -88,7 +88,8 @@ __device__ inline void entry_sentinel(TopF &e)
 // entries, keep K, update the admission threshold.  Whole workgroup.
 template <int DT>
 __device__ void topk_compact(typename TopT<DT>::type *buf, uint32_t *scal, int nbuf, int K,
-                             const void *data, int32_t dp, int32_t d, const float *qrow, float eps)
+                             const void *data, int32_t dp, int32_t d, const float *qrow, float eps,
+                             const int32_t *slot)
 {
     using E = typename TopT<DT>::type;
     __syncthreads();
@@ -96,7 +97,8 @@ __device__ void topk_compact(typename TopT<DT>::type *buf, uint32_t *scal, int n
     if constexpr (DT == QW_F32) {
         for (int e = threadIdx.x; e < n_e; e += kBlock) {
             if (buf[e].flag) {
-                const float *x = (const float *)data + (int64_t)buf[e].id * dp;
+                const int64_t r = slot ? (int64_t)slot[buf[e].id] : (int64_t)buf[e].id;
+                const float *x = (const float *)data + r * dp;
                 const double D = exact_dist_row(x, qrow, dp);
                 buf[e].pri = (unsigned long long)__double_as_longlong(D);
                 buf[e].flag = 0;
@@ -143,7 +145,8 @@ __device__ void topk_compact(typename TopT<DT>::type *buf, uint32_t *scal, int n
 
 // GLOB: the hash sets live in global scratch (one per workgroup) instead of
 // LDS; a compile-time choice so that LDS sets compile to LDS instructions.
-template <int DT, int UN, int PM, bool GLOB>
+// SLOT: rows are read through A.row_slot (the out-of-core data cache).
+template <int DT, int UN, int PM, bool GLOB, bool SLOT = false>
 __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
 {
     using E = typename TopT<DT>::type;
@@ -308,7 +311,8 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
             __syncthreads();
             if (bufcount > (int)A.buf - per_iter)
                 topk_compact<DT>(buf, scal, (int)A.buf, A.K, A.data, A.dp, A.d,
-                                 reinterpret_cast<const float *>(qrow_b), eps);
+                                 reinterpret_cast<const float *>(qrow_b), eps,
+                                 SLOT ? A.row_slot : nullptr);
             const uint32_t thr = scal[S_THR];
             uint32_t cid[UN];
             bool cv[UN];
@@ -316,6 +320,13 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
                 const uint32_t c = c0 + grp + (uint32_t)(NG * u);
                 cv[u] = c < U;
                 cid[u] = cv[u] ? (A.mode == VM_ALL ? c : tab[c]) : 0u;
+            }
+            uint32_t rid[UN];  // row index of each candidate in A.data
+            for (int u = 0; u < UN; ++u) {
+                rid[u] = SLOT && cv[u] ? (uint32_t)A.row_slot[cid[u]] : cid[u];
+                // every candidate's row is resident before the launch; a row
+                // that is not (slot -1) is never read
+                if (SLOT && (int32_t)rid[u] < 0) cv[u] = false;
             }
             uint32_t accu[UN];
             float accf[UN];
@@ -330,7 +341,7 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
                         const int part = j + G * (p0 + pp);
                         if (cv[u] && p0 + pp < P && part < parts) {
                             const uint4 *row = reinterpret_cast<const uint4 *>(
-                                (const unsigned char *)A.data + (int64_t)cid[u] * row_bytes);
+                                (const unsigned char *)A.data + (int64_t)rid[u] * row_bytes);
                             xv[u][pp] = row[part];
                         } else {
                             xv[u][pp] = make_uint4(0, 0, 0, 0);
@@ -397,7 +408,8 @@ __global__ __launch_bounds__(kBlock) void verify_kernel(VerifyArgs A)
             }
         }
         topk_compact<DT>(buf, scal, (int)A.buf, A.K, A.data, A.dp, A.d,
-                         reinterpret_cast<const float *>(qrow_b), eps);
+                         reinterpret_cast<const float *>(qrow_b), eps,
+                         SLOT ? A.row_slot : nullptr);
         const int keep = (int)scal[S_BUFCOUNT];
         for (int r = tid; r < A.K; r += kBlock) {
             const int64_t o = q * A.K + r;
@@ -465,6 +477,18 @@ qw_status launch_verify(const VerifyArgs &a, int grid, hipStream_t s)
                                         a.dtype);
     const bool small = one_part_per_lane(a.dp, a.dtype);
     const bool g = a.global_tab != 0;
+    if (a.row_slot) {  // out-of-core data cache: LDS sets only
+        if (g) return QW_EINVAL;
+        if (a.dtype == QW_U8) {
+            if (small) verify_kernel<QW_U8, 8, 1, false, true><<<grid, kBlock, lds, s>>>(a);
+            else verify_kernel<QW_U8, 2, 4, false, true><<<grid, kBlock, lds, s>>>(a);
+        } else {
+            if (small) verify_kernel<QW_F32, 8, 1, false, true><<<grid, kBlock, lds, s>>>(a);
+            else verify_kernel<QW_F32, 2, 4, false, true><<<grid, kBlock, lds, s>>>(a);
+        }
+        QW_HIP(hipGetLastError());
+        return QW_OK;
+    }
     if (a.dtype == QW_U8) {
         if (small && g) verify_kernel<QW_U8, 8, 1, true><<<grid, kBlock, lds, s>>>(a);
         else if (small) verify_kernel<QW_U8, 8, 1, false><<<grid, kBlock, lds, s>>>(a);

@@ -24,6 +24,7 @@ QW_U8, QW_F32 = 0, 1
 QW_FORM_PLAIN_FP32, QW_FORM_FAST = 0, 1
 QW_SCHED_SUM, QW_SCHED_LEARNED, QW_SCHED_ACTUAL, QW_SCHED_NONE = range(4)
 QW_MLP_HIDDEN = 64
+QW_OOC_MRU, QW_OOC_LRU = 0, 1
 
 
 class QwError(RuntimeError):
@@ -49,7 +50,10 @@ class qw_stats(ctypes.Structure):
                 ("ms_stage", ctypes.c_float * 8),
                 ("dedup_used", ctypes.c_int32), ("group_used", ctypes.c_int32),
                 ("xchunk_used", ctypes.c_int32), ("tuned", ctypes.c_int32),
-                ("split_used", ctypes.c_int32)]
+                ("split_used", ctypes.c_int32),
+                ("ooc_index_files", ctypes.c_int64), ("ooc_index_bytes", ctypes.c_int64),
+                ("ooc_data_objects", ctypes.c_int64), ("ooc_data_bytes", ctypes.c_int64),
+                ("ooc_batches", ctypes.c_int64), ("ooc_splits", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -66,7 +70,14 @@ class qw_index_info(ctypes.Structure):
                 ("has_count_model", ctypes.c_int32), ("count_margin", ctypes.c_float),
                 ("probing", ctypes.c_int32), ("probes_per_layer", ctypes.c_int32),
                 ("count_threshold", ctypes.c_int32), ("count_extra", ctypes.c_int32),
-                ("mean_hit_bucket", ctypes.c_double)]
+                ("mean_hit_bucket", ctypes.c_double), ("out_of_core", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("host_bytes", ctypes.c_int64)]
+
+
+class qw_ooc_opts(ctypes.Structure):
+    _fields_ = [("cache_bytes", ctypes.c_int64), ("index_percent", ctypes.c_int32),
+                ("strategy", ctypes.c_int32), ("policy", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("keep", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class qw_tune_result(ctypes.Structure):
@@ -101,6 +112,7 @@ SIGNATURES = {
     "qw_set_count_margin": (ctypes.c_int, [_P, ctypes.c_float]),
     "qw_set_probing": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
     "qw_set_counting": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
+    "qw_set_out_of_core": (ctypes.c_int, [_P, _P, _P]),
 }
 
 _lib = None
@@ -358,6 +370,18 @@ def qw_set_counting(ix, threshold: int, extra: int = 0):
     _check(load().qw_set_counting(ix, int(threshold), int(extra)), "qw_set_counting")
 
 
+def qw_set_out_of_core(ix, cache_bytes: Optional[int], index_percent: int = 50, strategy: int = 1,
+                       policy: int = QW_OOC_MRU, batch: int = 10000, keep: int = 0, stream=None):
+    """Out-of-core mode (cache_bytes None: back in core)."""
+    if cache_bytes is None:
+        _check(load().qw_set_out_of_core(ix, None, _stream(stream)), "qw_set_out_of_core")
+        return
+    o = qw_ooc_opts(cache_bytes=int(cache_bytes), index_percent=int(index_percent),
+                    strategy=int(strategy), policy=int(policy), batch=int(batch), keep=int(keep),
+                    reserved=0)
+    _check(load().qw_set_out_of_core(ix, ctypes.byref(o), _stream(stream)), "qw_set_out_of_core")
+
+
 def qw_get_count_model(ix, L: int) -> np.ndarray:
     p = np.empty(qw_mlp_param_count(L), dtype=np.float32)
     _check(load().qw_get_count_model(ix, ctypes.c_void_p(p.ctypes.data), p.size), "qw_get_count_model")
@@ -417,6 +441,11 @@ class Index:
         """Collision counting: threshold on the layers shared with the query
         (0: the plain union), at most K + extra points verified."""
         qw_set_counting(self.handle, threshold, extra)
+
+    def set_out_of_core(self, cache_bytes: Optional[int], **kw):
+        """Lists and rows to pinned host memory with an HBM cache of
+        cache_bytes split index_percent / the rest (None: back in HBM)."""
+        qw_set_out_of_core(self.handle, cache_bytes, **kw)
 
     def info(self) -> dict:
         return qw_get_index_info(self.handle)
