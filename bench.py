@@ -43,6 +43,11 @@ METRIC = "queries/sec at recall@10>=0.9, BF16+learned vs plain FP32 on 1 MI355X"
 # w_0.9 of the 1M x 960 float Zipf workload without neighbour probing (8 x 1.5),
 # measured with the w search above; its leg re-measures the recall
 CFG5_W = 12.0
+# out-of-core caches: about a third of what the 1M x 128 uint8 index keeps in
+# host memory (80 MB of lists + 128 MB of rows), and about a quarter of the
+# 1M x 960 float one (64 MB + 3.84 GB)
+OOC_CACHE_U8 = 64 << 20
+OOC_CACHE_F32 = 1 << 30
 
 
 def log(msg):
@@ -119,7 +124,11 @@ def candidate_roofline(st, kms, Q, d, elem, K, is_u8, config, w, probes, probe_t
             "traffic_frac": round(traffic / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if traffic and kms > 0 else None,
             "traffic_file": os.path.relpath(tfile, ROOT),
             "kernel_ms": round(kms, 4),
-            "kernel_algorithmic_bytes": int(kbytes)}
+            "kernel_algorithmic_bytes": int(kbytes),
+            # algorithmic bytes over counted bytes: rows that neighbouring queries
+            # share served from L2 or the Infinity Cache (above 1, `frac` measures
+            # that reuse, and `traffic_frac` is the HBM roofline fraction)
+            "reuse_factor": round(kbytes / traffic, 3) if traffic else None}
 
 
 def main():
@@ -159,6 +168,8 @@ def main():
                     help="skip the plain-union leg (no neighbour probing, its own w_0.9)")
     ap.add_argument("--no-float-leg", action="store_true",
                     help="skip the schedules on the 1M x 960 float Zipf workload")
+    ap.add_argument("--no-ooc-leg", action="store_true",
+                    help="skip the out-of-core split sweeps")
     ap.add_argument("--profile", action="store_true",
                     help="only the fast-form timed loop (for rocprofv3 runs): no tuning unless "
                          "--tune-cache names an existing file")
@@ -230,6 +241,74 @@ def main():
             _, _, s = index.query(queries, K, lib.make_opts(**kw, timing=1, graph=0), stats=True)
             stage += np.array(s["ms_stage"])
         return stage / nrep, s
+
+    def ooc_sweep(index, queries, Kq, cache_bytes, batch, ref, oi, od, reps=2, warm=True):
+        """Out of core (lists and rows in host memory, HBM as the cache C):
+        C_I's share of a fixed C swept over 1, 10, 20, ..., 90, 99 % as the
+        paper evaluates its split, Strategy 1 and MRU; every call starts with
+        empty caches (one workload, cold).  Then Strategy 2 and LRU at the
+        fastest share.  Results must equal the in-core answer `ref`."""
+        rows = []
+        same = True
+
+        def one(pct, strategy, policy):
+            nonlocal same
+            index.set_out_of_core(cache_bytes, index_percent=pct, strategy=strategy,
+                                  policy=policy, batch=batch)
+            try:
+                if warm:
+                    index.query(queries, Kq, out_ids=oi, out_dist=od)  # warm-up (allocations)
+                torch.cuda.synchronize()
+                t1 = time.time()
+                for _ in range(reps):
+                    _, _, so = index.query(queries, Kq, out_ids=oi, out_dist=od, stats=True)
+                torch.cuda.synchronize()
+                ms = (time.time() - t1) * 1e3 / reps
+                same &= bool(torch.equal(oi, ref[0]) and torch.equal(od, ref[1]))
+                io = so["ooc_index_bytes"] + so["ooc_data_bytes"]
+                return {"index_percent": pct, "strategy": strategy,
+                        "policy": "MRU" if policy == lib.QW_OOC_MRU else "LRU",
+                        "ms": round(ms, 2), "index_files": so["ooc_index_files"],
+                        "index_mb": round(so["ooc_index_bytes"] / 1e6, 2),
+                        "data_objects": so["ooc_data_objects"],
+                        "data_mb": round(so["ooc_data_bytes"] / 1e6, 2),
+                        "host_mb": round(io / 1e6, 2),
+                        "host_gbs": round(io / (ms * 1e-3) / 1e9, 2) if ms > 0 else None,
+                        "batches": so["ooc_batches"], "splits": so["ooc_splits"]}
+            except lib.QwError as e:  # a share too small for one query's lists or rows
+                return {"index_percent": pct, "strategy": strategy, "error": str(e)}
+
+        for pct in (1, 10, 20, 30, 40, 50, 60, 70, 80, 90, 99):
+            rows.append(one(pct, 1, lib.QW_OOC_MRU))
+            log(f"[bench] out of core C={cache_bytes >> 20} MiB: {rows[-1]}")
+        ok = [r for r in rows if "ms" in r]
+        best = min(ok, key=lambda r: r["ms"]) if ok else None
+        least_io = min(ok, key=lambda r: r["host_mb"]) if ok else None
+        extra = []
+        if best:
+            extra.append(one(best["index_percent"], 2, lib.QW_OOC_MRU))
+            extra.append(one(best["index_percent"], 1, lib.QW_OOC_LRU))
+        index.set_out_of_core(None)
+        return {"cache_mb": round(cache_bytes / 2**20, 1), "batch": batch, "sweep": rows,
+                "fastest_index_percent": best["index_percent"] if best else None,
+                "least_io_index_percent": least_io["index_percent"] if least_io else None,
+                "at_fastest_share": extra, "identical_to_in_core": same}
+
+    def h2d_rate():
+        """Pinned host to device copy rate (1 GiB, best of three)."""
+        hsrc = torch.empty(1 << 28, dtype=torch.float32).pin_memory()
+        ddst = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        best = 0.0
+        for _ in range(4):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ddst.copy_(hsrc, non_blocking=True)
+            e1.record()
+            torch.cuda.synchronize()
+            best = max(best, (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+        del hsrc, ddst
+        return round(best, 1)
 
     def tune(index, queries, kw):
         """Autotune the scheduling settings unless they are fixed; returns the
@@ -509,6 +588,7 @@ def main():
     # probing), at its own w_0.9 (searched from the headline's w upward), with
     # a count model trained the same way and its own tuning
     plain_union = None
+    ooc_u8 = None
     if args.probes and not args.no_union_leg:
         ugrid = [m * spec["w"] for m in W_GRID if m * spec["w"] >= w] if not args.w else [args.w]
         uw, uix, urec, _, utried, _ = search_w(0, 0, ugrid, tb)
@@ -532,6 +612,15 @@ def main():
                        "roofline": uroof}
         log(f"[bench] plain union w={uw}: {ums:.3f} ms/step, recall {urec:.4f}, "
             f"kernel frac {uroof['frac']}")
+        if not args.no_ooc_leg:
+            t1 = time.time()
+            oi_u = torch.empty_like(u_ids)
+            od_u = torch.empty_like(u_dist)
+            ooc_u8 = ooc_sweep(uix, q_d, K, OOC_CACHE_U8, 1000, (u_ids, u_dist), oi_u, od_u)
+            ooc_u8["workload"] = (f"n={wl.n} d={wl.d} u8, Q={wl.Q}, L={L} k={wl.params.k} w={uw}, "
+                                  f"lists {4 * L * wl.n / 1e6:.0f} MB + rows "
+                                  f"{wl.n * wl.d / 1e6:.0f} MB in host memory")
+            ooc_u8["sweep_s"] = round(time.time() - t1, 1)
         uix.close()
     del train_d
     torch.cuda.empty_cache()
@@ -582,6 +671,7 @@ def main():
     # varies most: learned sizing against the sum-of-buckets bound, the exact
     # count (an extra counting pass) and one size for all
     float_leg = None
+    ooc_f32 = None
     if args.config == 2 and not args.no_float_leg:
         t1 = time.time()
         wl5 = synth.make_config(5)
@@ -643,6 +733,19 @@ def main():
             "sum_of_buckets_per_query": s5["cand_total"] / wl5.Q,
         }
         log(f"[bench] float Zipf schedules: {ms5}, identical {same5}, recall {rec5:.4f}")
+        if not args.no_ooc_leg:
+            t1 = time.time()
+            ref5_d = (torch.from_numpy(ref5[0]).to(dev), torch.from_numpy(ref5[1]).to(dev))
+            # one cold pass per share: the passes take seconds, their allocations
+            # happen in qw_set_out_of_core
+            ooc_f32 = ooc_sweep(ix5, q5, wl5.K, OOC_CACHE_F32, 10000, ref5_d, oi5, od5, reps=1,
+                                warm=False)
+            ooc_f32["workload"] = (f"n={wl5.n} d={wl5.d} f32, Q={wl5.Q} Zipf, L={wl5.params.L} "
+                                   f"k={wl5.params.k} w={CFG5_W}, lists "
+                                   f"{4 * wl5.params.L * wl5.n / 1e6:.0f} MB + rows "
+                                   f"{wl5.n * wl5.d * 4 / 1e6:.0f} MB in host memory")
+            ooc_f32["sweep_s"] = round(time.time() - t1, 1)
+            del ref5_d
         ix5.close()
         del d5, q5
         torch.cuda.empty_cache()
@@ -688,6 +791,11 @@ def main():
                                  "1M x 960 float workload"},
         "plain_union": plain_union,
         "float_zipf_schedules": float_leg,
+        "out_of_core": ({"host_to_device_copy_gbs": h2d_rate(), "u8": ooc_u8, "f32": ooc_f32,
+                         "note": "index files and data objects in pinned host memory, HBM as the "
+                                 "cache; ms per cold workload pass; host_mb = bytes read over the "
+                                 "host link; host_to_device_copy_gbs = a pinned 1 GiB copy"}
+                        if (ooc_u8 or ooc_f32) else None),
         "collision_counting": counting,
         "stage_ms": {"hash": round(stage[0], 4), "probe": round(stage[1], 4),
                      "schedule": round(stage[2], 4), "dedup": round(stage[6], 4),

@@ -660,8 +660,11 @@ qw_status ooc_enable(qw_index *ix, const qw_ooc_opts &o, hipStream_t s)
                              (o.cache_bytes % 100) * o.index_percent / 100;
     const int64_t ids_total_raw = ci_bytes / 4;
     const int npools = o.strategy == 1 ? ix->L : 1;
-    const int64_t cap_pool = ids_total_raw / npools;
-    const int64_t cap_rows = (o.cache_bytes - ci_bytes) / row_bytes;
+    // a pool never holds more than its layers' n * (L / npools) ids and the
+    // data cache never more than n rows, so larger capacities change nothing
+    // and are not allocated
+    const int64_t cap_pool = std::min<int64_t>(ids_total_raw / npools, n * (ix->L / npools));
+    const int64_t cap_rows = std::min<int64_t>((o.cache_bytes - ci_bytes) / row_bytes, n);
     if (npools > kMaxPools) return QW_EUNSUPPORTED;
     if (cap_pool * npools > INT32_MAX || cap_rows > INT32_MAX) return QW_EUNSUPPORTED;
 

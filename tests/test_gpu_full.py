@@ -208,3 +208,52 @@ def test_cfg2_bucket_ids_full_size(w):
             del h
         del xd
     ix.close()
+
+
+@pytest.mark.timeout(400)
+def test_cfg2_full_out_of_core():
+    """1M x 128 uint8 at w = 1200 out of core (lists and rows in host memory):
+    every query's top K against the oracle with a 64 MiB cache (30 % for
+    lists, evictions and splits on), and with an unbounded cache every
+    distinct index file and data object read exactly once (counted here
+    independently with numpy from the oracle's hash values and candidates)."""
+    w = 1200.0
+    wl = synth.make_config(2)
+    p = wl.params
+    b = p.b(w)
+    bi = oracle.BuiltIndex(wl.data, p.a, b, w)
+    ids_o, dist_o, _ = bi.query(wl.queries, wl.K)
+    bi.close()
+    ix = lib.Index(dev(wl.data), dev(p.a), dev(b), w)
+    q = dev(wl.queries)
+    try:
+        ix.set_out_of_core(64 << 20, index_percent=30, strategy=1, batch=1000)
+        ids, dist, st = ix.query(q, wl.K, stats=True)
+        torch.cuda.synchronize()
+        compare(ids, dist, ids_o, dist_o, np.arange(wl.Q), True)
+        assert st["ooc_batches"] >= 10 and st["ooc_data_objects"] > 0
+        ix.set_out_of_core(512 << 20, index_percent=50, strategy=2, batch=2500)
+        ids, dist, st = ix.query(q, wl.K, stats=True)
+        torch.cuda.synchronize()
+        compare(ids, dist, ids_o, dist_o, np.arange(wl.Q), True)
+    finally:
+        ix.close()
+    L, k = p.L, p.k
+    hd = oracle.hash_points(wl.data, p.a, b, w).reshape(wl.n, L, k)
+    hq = oracle.hash_points(wl.queries, p.a, b, w).reshape(wl.Q, L, k)
+    files = nbytes = 0
+    for l in range(L):
+        vd = np.ascontiguousarray(hd[:, l, :]).view(np.dtype((np.void, 4 * k))).ravel()
+        vq = np.ascontiguousarray(hq[:, l, :]).view(np.dtype((np.void, 4 * k))).ravel()
+        keys, counts = np.unique(vd, return_counts=True)
+        uq = np.unique(vq)
+        pos = np.searchsorted(keys, uq)
+        pos = np.minimum(pos, keys.size - 1)
+        hit = keys[pos] == uq
+        files += int(hit.sum())
+        nbytes += 4 * int(counts[pos[hit]].sum())
+    cands = oracle.lsh_candidates(wl.data, wl.queries, p.a, b, w)
+    objs = np.unique(np.concatenate(cands)).size
+    assert st["ooc_index_files"] == files and st["ooc_index_bytes"] == nbytes
+    assert st["ooc_data_objects"] == objs and st["ooc_data_bytes"] == objs * 128
+    assert st["ooc_splits"] == 0 and st["ooc_batches"] == 4
