@@ -45,11 +45,11 @@ batch of one query is the paper's query-at-a-time setting):
     ceil(m / 2) queries and then the rest.  A failed single query is an
     error: the cache cannot hold one query's index files or candidates.
 
-parity unpinned: the paper prints no worked example of its cache, so the
-counts are pinned to what follows from the definitions.  These are
-compulsory reads with an unbounded cache, the textbook MRU and LRU sequences
-on a cyclic trace, LRU's inclusion property, and Strategy 1 as independent
-per-layer caches.
+The paper prints no worked example or per-query figure of its cache, so the
+counts are pinned to what the definitions fix: compulsory reads with an
+unbounded cache, the textbook MRU and LRU sequences on a cyclic trace, the
+inclusion property of both policies, Strategy 1 as independent per-layer
+caches, and hand-worked eviction, stamp and split cases (tests/test_oracle_ooc.py).
 """
 from __future__ import annotations
 

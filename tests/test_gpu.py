@@ -742,9 +742,11 @@ def test_oversized_requests_give_enomem(cfg1):
     ix.close()
 
 
-@pytest.mark.skip(reason="the non-temporal staging split faulted the GPU on its first run (memory "
-                         "fault during this test, cause not found by reading the code); its kernel "
-                         "path is switched off and split values are refused with QW_EUNSUPPORTED")
+@pytest.mark.skip(reason="the first staging split (a share of the candidate kernels' list and row "
+                         "loads made non-temporal) faulted the GPU on its first run (memory fault "
+                         "during this test, cause not found by reading the code); that kernel path "
+                         "was removed, and qw_opts.stage_split is now served by the staged LDS "
+                         "kernel, tested by test_staged_kernel_keeps_results")
 @pytest.mark.parametrize("dtype", ["u8", "f32"])
 def test_staging_split_keeps_results(dtype):
     """The staging split (a share of the bucket lists and of the candidate rows
