@@ -170,6 +170,8 @@ def main():
                     help="skip the schedules on the 1M x 960 float Zipf workload")
     ap.add_argument("--no-ooc-leg", action="store_true",
                     help="skip the out-of-core split sweeps")
+    ap.add_argument("--profile-ooc", type=int, default=None, metavar="PERCENT",
+                    help="with --profile: only --steps out-of-core passes at this index share")
     ap.add_argument("--profile", action="store_true",
                     help="only the fast-form timed loop (for rocprofv3 runs): no tuning unless "
                          "--tune-cache names an existing file")
@@ -363,6 +365,22 @@ def main():
     grid = [args.w] if args.w else [m * spec["w"] for m in W_GRID]
     tb = {}
     w, ix, rec, st0, tried, build_s = search_w(args.probes, args.probe_t, grid, tb)
+
+    if args.profile_ooc is not None:
+        # out-of-core passes only (for rocprofv3 runs): the index's lists and
+        # rows in host memory, the cache of the sweep at the given index share
+        cache = OOC_CACHE_U8 if is_u8 else OOC_CACHE_F32
+        ix.set_out_of_core(cache, index_percent=args.profile_ooc, strategy=1,
+                           batch=1000 if is_u8 else 10000)
+        t1 = time.time()
+        for _ in range(args.steps):
+            _, _, so = ix.query(q_d, K, out_ids=out_ids, out_dist=out_dist, stats=True)
+        torch.cuda.synchronize()
+        log(f"[bench] profile out of core: C={cache >> 20} MiB, index share {args.profile_ooc} %, "
+            f"{(time.time() - t1) * 1e3 / args.steps:.1f} ms per pass, "
+            f"index {so['ooc_index_bytes'] / 1e6:.1f} MB, data {so['ooc_data_bytes'] / 1e6:.1f} MB, "
+            f"batches {so['ooc_batches']}, splits {so['ooc_splits']}")
+        return
 
     # ---- learned count model, trained on the engine's own features
     t1 = time.time()
