@@ -473,7 +473,8 @@ typedef struct {
     int32_t batch;          /* queries per batch, >= 1 */
     int32_t keep;           /* 0: every qw_query_workload call starts with empty caches (a
                                workload on its own, as the paper measures); 1: the caches
-                               persist across calls */
+                               persist across calls, and a call's queries count as used
+                               after the previous call's */
     int32_t reserved;       /* 0 */
 } qw_ooc_opts;
 

@@ -189,6 +189,7 @@ struct OocState {
     int64_t cand_cap = 0;     // entries of the candidate lists
     uint32_t tag = 0;         // batch attempt counter (tags are never reused)
     int64_t rows_used = 0;    // resident rows (host mirror)
+    int64_t qbase = 0;        // queries answered since the caches were emptied (recency offset)
     OocState() = default;
     OocState(const OocState &) = delete;
     OocState &operator=(const OocState &) = delete;

@@ -23,7 +23,8 @@
 //  3. the plain form's per-query kernel (union, verification, top-K) reads
 //     the lists from the arena and the rows through the slot directory.
 // Recency: query q's layer-l bucket is used at q * L + l + 1, a row of C(q) at
-// q + 1; an item's stamp is its largest use.  The host reads a few counters
+// q + 1, q counting the queries answered since the caches were last emptied
+// (across calls when they persist); an item's stamp is its largest use.  The host reads a few counters
 // back after each marking step (misses, resident totals, candidates) to decide
 // whether the batch fits; a batch that does not fit is answered as two halves
 // (the index phase of a batch whose rows did not fit stays done).
@@ -573,8 +574,9 @@ qw_status run_batch(qw_index *ix, int64_t q0, int64_t nq, hipStream_t s, OocIo *
     io->index_bytes += 4 * (int64_t)miss_ids;
     uint32_t *bs2 = st.bstart2.as<uint32_t>();
     uint32_t *bz2 = bs2 + nql;  // resolved sizes
+    const int64_t uq0 = st.qbase + q0;  // recency of this batch's first query
     commit_index_kernel<<<grid_exact(nql), kOocBlock, 0, s>>>(
-        bs, bz, nql, L, n, q0, mkey, mask, st.mstamp.as<unsigned long long>(), moff, bs2, bz2);
+        bs, bz, nql, L, n, uq0, mkey, mask, st.mstamp.as<unsigned long long>(), moff, bs2, bz2);
     QW_HIP(hipGetLastError());
 
     // ---- data phase
@@ -621,7 +623,7 @@ qw_status run_batch(qw_index *ix, int64_t q0, int64_t nq, hipStream_t s, OocIo *
     io->data_objects += rmiss;
     io->data_bytes += rmiss * st.row_bytes;
     commit_rows_kernel<<<grid_for(nql, kOocBlock / 64), kOocBlock, 0, s>>>(
-        bs2, bz2, nql, L, q0, arena, st.rstamp.as<uint32_t>());
+        bs2, bz2, nql, L, uq0, arena, st.rstamp.as<uint32_t>());
     QW_HIP(hipGetLastError());
     return QW_OK;
 }
@@ -648,6 +650,7 @@ qw_status ooc_reset(qw_index *ix, hipStream_t s)
     QW_TRY(launch_fill_u32(st.owner.as<uint32_t>(), 0xFFFFFFFFu, st.cap_rows, s));
     QW_TRY(launch_fill_u64(st.ctr.as<unsigned long long>(), 0ull, O_WORDS, s));
     st.rows_used = 0;
+    st.qbase = 0;
     return QW_OK;
 }
 
@@ -817,6 +820,7 @@ qw_status ooc_answer(qw_index *ix, int64_t Q, const VerifyArgs &tmpl, const void
             ++io->batches;
         }
     }
+    st.qbase += Q;  // with persistent caches, the next call's queries come later
     return QW_OK;
 }
 

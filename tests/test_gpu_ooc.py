@@ -248,3 +248,27 @@ def test_refusals_and_limits(u8case):
         assert status(ix.query, q, 10) == lib.QW_EUNSUPPORTED
     finally:
         ix.close()
+
+
+def test_kept_caches_continue_the_workload(u8case):
+    """keep = 1: two calls of 150 queries read what one workload of 300 reads
+    in batches of 50 (recency continues across the calls), each call's share
+    as the oracle's model gives it."""
+    c = u8case
+    wl = c.wl
+    cache_bytes, pct = c.cache(0.3, 0.3, 1)
+    want_all = c.expected_io(cache_bytes, pct, 1, lib.QW_OOC_MRU, 50)
+    want_first = ooc.simulate(c.ineeds[:150], c.cands[:150], c.L, c.row_bytes, cache_bytes, pct,
+                              1, lib.QW_OOC_MRU, 50)
+    ix = lib.Index(dev(wl.data), dev(c.a), dev(c.b), c.w)
+    try:
+        ix.set_out_of_core(cache_bytes, index_percent=pct, strategy=1, batch=50, keep=1)
+        got = []
+        for lo, hi in ((0, 150), (150, 300)):
+            ids, dist, st = ix.query(dev(wl.queries[lo:hi]), wl.K, stats=True)
+            check_topk(ids, dist, c.ids[lo:hi], c.dist[lo:hi], True)
+            got.append(io_of(st))
+        assert got[0] == want_first
+        assert {k: got[0][k] + got[1][k] for k in got[0]} == want_all
+    finally:
+        ix.close()
