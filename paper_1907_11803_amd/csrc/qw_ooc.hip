@@ -40,7 +40,6 @@ namespace qw {
 namespace {
 
 constexpr unsigned long long kMapEmpty = ~0ull;
-constexpr unsigned long long kStampMax = (1ull << 58) - 1;
 constexpr int kMaxPools = 64;
 constexpr int kOocBlock = 256;
 constexpr int kOocGrid = 2048;  // grid-stride launches
@@ -92,18 +91,65 @@ __device__ inline int64_t map_slot(unsigned long long *key, unsigned long long m
     return -1;
 }
 
-// Position in a list that grows by one entry for every lane with `pred`: one
-// atomic per wave.  Called by every active lane of the wave.
-__device__ inline unsigned long long wave_append(unsigned long long *counter, bool pred)
+// The scans below give each block one contiguous range of the items, so a
+// block reserves the places of all its items with one atomic (one per wave
+// would serialise thousands of atomics on one address).
+constexpr int kScanGrid = 256;
+
+__device__ inline void block_range(int64_t N, int64_t *lo, int64_t *hi)
 {
-    const unsigned long long m = __ballot(pred);
-    if (m == 0ull) return 0ull;
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll((long long)m) - 1;
-    unsigned long long base = 0ull;
-    if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(m));
-    base = (unsigned long long)__shfl((long long)base, leader);
-    return base + (unsigned long long)__popcll(m & ((1ull << lane) - 1ull));
+    const int64_t per = (N + gridDim.x - 1) / gridDim.x;
+    *lo = (int64_t)blockIdx.x * per;
+    *hi = *lo + per < N ? *lo + per : N;
+    if (*lo > N) *lo = N;
+}
+
+// Whole block: the sum of v over its threads (barriers inside).
+__device__ inline unsigned long long block_sum(unsigned long long v, unsigned long long *red)
+{
+    for (int off = 32; off > 0; off >>= 1) v += (unsigned long long)__shfl_xor((long long)v, off);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    unsigned long long t = 0ull;
+    for (int w = 0; w < kOocBlock / 64; ++w) t += red[w];
+    return t;
+}
+
+// Order-preserving compaction of the items i of [lo, hi) with pred(i): pass
+// one counts them and reserves their places at *counter with one atomic,
+// pass two calls emit(place, i) with places increasing with i.  Whole block.
+template <class Pred, class Emit>
+__device__ inline void block_compact(int64_t lo, int64_t hi, unsigned long long *counter, Pred pred,
+                                     Emit emit)
+{
+    __shared__ unsigned long long red[kOocBlock / 64];
+    __shared__ unsigned long long bbase;
+    __shared__ uint32_t wc[kOocBlock / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    unsigned long long c = 0ull;
+    for (int64_t i = lo + tid; i < hi; i += kOocBlock) c += pred(i) ? 1ull : 0ull;
+    const unsigned long long tot = block_sum(c, red);
+    if (tid == 0) bbase = tot ? atomicAdd(counter, tot) : 0ull;
+    __syncthreads();
+    if (tot == 0ull) return;  // uniform
+    unsigned long long run = bbase;
+    const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    for (int64_t i0 = lo; i0 < hi; i0 += kOocBlock) {
+        const int64_t i = i0 + tid;
+        const bool p = i < hi && pred(i);
+        const unsigned long long m = __ballot(p);
+        if (lane == 0) wc[wid] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t before = 0, all = 0;
+        for (int w = 0; w < kOocBlock / 64; ++w) {
+            before += w < wid ? wc[w] : 0u;
+            all += wc[w];
+        }
+        __syncthreads();  // wc is rewritten next round
+        if (p) emit(run + before + (unsigned long long)__popcll(m & lt), i);
+        run += all;
+    }
 }
 
 // Index phase, marking: every (query, layer) of the batch with a non-empty
@@ -153,7 +199,7 @@ __global__ __launch_bounds__(kOocBlock) void mark_index_kernel(
 // first victim first.
 __global__ __launch_bounds__(kOocBlock) void index_cands_kernel(
     const unsigned long long *__restrict__ mkey, int64_t mcap, int64_t n, int32_t strategy,
-    int32_t policy, uint32_t tag, const uint32_t *__restrict__ msize,
+    int32_t policy, uint32_t tag, int32_t sbits, const uint32_t *__restrict__ msize,
     const unsigned long long *__restrict__ mstamp, const long long *__restrict__ moff,
     const uint32_t *__restrict__ mneed, unsigned long long *ckeys, int32_t *cvals,
     unsigned long long *ctr)
@@ -164,29 +210,22 @@ __global__ __launch_bounds__(kOocBlock) void index_cands_kernel(
         pcnt[threadIdx.x] = 0ull;
     }
     __syncthreads();
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < mcap; base += stride) {
-        const int64_t slot = base + threadIdx.x;
-        bool c = false;
-        unsigned long long key = 0ull;
-        int p = 0;
-        if (slot < mcap) {
-            const unsigned long long g = mkey[slot];
-            if (g != kMapEmpty && moff[slot] >= 0 && mneed[slot] != tag) {
-                c = true;
-                p = strategy == 1 ? (int)(g / (unsigned long long)n) : 0;
-                const unsigned long long st = mstamp[slot];
-                key = ((unsigned long long)p << 58) | (policy == QW_OOC_MRU ? kStampMax - st : st);
-            }
-        }
-        const unsigned long long o = wave_append(&ctr[O_ICAND], c);
-        if (c) {
-            ckeys[o] = key;
-            cvals[o] = (int32_t)slot;
-            atomicAdd(&pids[p], (unsigned long long)msize[slot]);
-            atomicAdd(&pcnt[p], 1ull);
-        }
-    }
+    int64_t lo, hi;
+    block_range(mcap, &lo, &hi);
+    const unsigned long long smax = (1ull << sbits) - 1ull;  // stamps below 2^sbits
+    auto cand = [&](int64_t slot) {
+        const unsigned long long g = mkey[slot];
+        return g != kMapEmpty && moff[slot] >= 0 && mneed[slot] != tag;
+    };
+    block_compact(lo, hi, &ctr[O_ICAND], cand, [&](unsigned long long o, int64_t slot) {
+        const unsigned long long g = mkey[slot];
+        const int p = strategy == 1 ? (int)(g / (unsigned long long)n) : 0;
+        const unsigned long long st = mstamp[slot];
+        ckeys[o] = ((unsigned long long)p << sbits) | (policy == QW_OOC_MRU ? smax - st : st);
+        cvals[o] = (int32_t)slot;
+        atomicAdd(&pids[p], (unsigned long long)msize[slot]);
+        atomicAdd(&pcnt[p], 1ull);
+    });
     __syncthreads();
     if (threadIdx.x < kMaxPools) {
         if (pids[threadIdx.x]) atomicAdd(&ctr[O_CIDS + threadIdx.x], pids[threadIdx.x]);
@@ -209,13 +248,13 @@ struct PoolCut {
 // Evict, in each pool, the shortest prefix of its sorted candidates whose
 // sizes cover the pool's deficit.
 __global__ void evict_index_kernel(const unsigned long long *__restrict__ ckeys,
-                                   const int32_t *__restrict__ cvals, int64_t count,
+                                   const int32_t *__restrict__ cvals, int64_t count, int32_t sbits,
                                    const unsigned long long *__restrict__ prefix, PoolCut cut,
                                    long long *moff)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    const int p = (int)(ckeys[i] >> 58);
+    const int p = (int)(ckeys[i] >> sbits);
     const long long d = cut.deficit[p];
     if (d <= 0) return;
     const unsigned long long before = prefix[i] - prefix[cut.start[p]];
@@ -223,44 +262,42 @@ __global__ void evict_index_kernel(const unsigned long long *__restrict__ ckeys,
 }
 
 // Arena rebuild, placement: every resident bucket and every miss of this
-// batch gets a place in its pool's region of the new arena.
+// batch gets a place in its pool's region of the new arena.  Each block
+// reserves its pools' ids and its copy-list entries once.
 __global__ __launch_bounds__(kOocBlock) void place_index_kernel(
     const unsigned long long *__restrict__ mkey, int64_t mcap, int64_t n, int32_t strategy,
     uint32_t tag, int64_t cap_pool, const uint32_t *__restrict__ msize,
     const long long *__restrict__ moff, const uint32_t *__restrict__ mneed, long long *mnoff,
     int32_t *copyl, unsigned long long *ctr)
 {
-    __shared__ unsigned long long lsum[kMaxPools], lbase[kMaxPools];
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < mcap; base += stride) {
-        if (threadIdx.x < kMaxPools) lsum[threadIdx.x] = 0ull;
-        __syncthreads();
-        const int64_t slot = base + threadIdx.x;
-        bool has = false;
-        int p = 0;
-        uint32_t s = 0;
-        unsigned long long local = 0ull;
-        if (slot < mcap) {
-            const unsigned long long g = mkey[slot];
-            if (g != kMapEmpty && (moff[slot] >= 0 || mneed[slot] == tag)) {
-                has = true;
-                p = strategy == 1 ? (int)(g / (unsigned long long)n) : 0;
-                s = msize[slot];
-                local = atomicAdd(&lsum[p], (unsigned long long)s);
-            }
-        }
-        __syncthreads();
-        if (threadIdx.x < kMaxPools && lsum[threadIdx.x])
-            lbase[threadIdx.x] = atomicAdd(&ctr[O_FILL + threadIdx.x], lsum[threadIdx.x]);
-        __syncthreads();
-        const unsigned long long o = wave_append(&ctr[O_COPY], has);
-        if (has) {
-            mnoff[slot] = (long long)((unsigned long long)p * (unsigned long long)cap_pool +
-                                      lbase[p] + local);
-            copyl[o] = (int32_t)slot;
-        }
-        __syncthreads();
+    __shared__ unsigned long long lsum[kMaxPools], lbase[kMaxPools], lrun[kMaxPools];
+    if (threadIdx.x < kMaxPools) {
+        lsum[threadIdx.x] = 0ull;
+        lrun[threadIdx.x] = 0ull;
     }
+    __syncthreads();
+    int64_t lo, hi;
+    block_range(mcap, &lo, &hi);
+    auto placed = [&](int64_t slot) {
+        const unsigned long long g = mkey[slot];
+        return g != kMapEmpty && (moff[slot] >= 0 || mneed[slot] == tag);
+    };
+    auto pool = [&](int64_t slot) {
+        return strategy == 1 ? (int)(mkey[slot] / (unsigned long long)n) : 0;
+    };
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kOocBlock)
+        if (placed(i)) atomicAdd(&lsum[pool(i)], (unsigned long long)msize[i]);
+    __syncthreads();
+    if (threadIdx.x < kMaxPools && lsum[threadIdx.x])
+        lbase[threadIdx.x] = atomicAdd(&ctr[O_FILL + threadIdx.x], lsum[threadIdx.x]);
+    __syncthreads();
+    block_compact(lo, hi, &ctr[O_COPY], placed, [&](unsigned long long o, int64_t slot) {
+        const int p = pool(slot);
+        const unsigned long long local = atomicAdd(&lrun[p], (unsigned long long)msize[slot]);
+        mnoff[slot] = (long long)((unsigned long long)p * (unsigned long long)cap_pool + lbase[p] +
+                                  local);
+        copyl[o] = (int32_t)slot;
+    });
 }
 
 // Arena rebuild, copy: one wave per placed bucket; survivors from the old
@@ -333,12 +370,11 @@ __global__ __launch_bounds__(kOocBlock) void commit_index_kernel(
     bsize2[i] = size;
 }
 
-// Data phase, marking: every id in the batch's lists is tagged as needed;
-// the first visitor of a row that is not resident lists it as a miss.
+// Data phase, marking: every id in the batch's lists is tagged as needed
+// (plain stores: every writer stores the same tag).
 __global__ __launch_bounds__(kOocBlock) void mark_rows_kernel(
     const uint32_t *__restrict__ bstart2, const uint32_t *__restrict__ bsize, int64_t nql,
-    const int32_t *__restrict__ arena, uint32_t tag, uint32_t *rneed,
-    const int32_t *__restrict__ dir, int32_t *missd, unsigned long long *ctr)
+    const int32_t *__restrict__ arena, uint32_t tag, uint32_t *rneed)
 {
     const int lane = threadIdx.x & 63;
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
@@ -346,46 +382,46 @@ __global__ __launch_bounds__(kOocBlock) void mark_rows_kernel(
          e += nw) {
         const uint32_t s = bsize[e];
         const int32_t *lst = arena + bstart2[e];
-        for (uint32_t j0 = 0; j0 < s; j0 += 64) {
-            const uint32_t j = j0 + (uint32_t)lane;
-            bool miss = false;
-            int32_t id = 0;
-            if (j < s) {
-                id = lst[j];
-                if (rneed[id] != tag && atomicExch(&rneed[id], tag) != tag) miss = dir[id] < 0;
-            }
-            const unsigned long long o = wave_append(&ctr[O_RMISS], miss);
-            if (miss) missd[o] = id;
-        }
+        for (uint32_t j = (uint32_t)lane; j < s; j += 64) rneed[lst[j]] = tag;
     }
+}
+
+// Data phase, misses: the tagged rows that are not resident, listed in runs
+// of increasing id (each block appends its range of ids in order), so rows
+// next to each other in host memory are read together.
+__global__ __launch_bounds__(kOocBlock) void miss_rows_kernel(const uint32_t *__restrict__ rneed,
+                                                              const int32_t *__restrict__ dir,
+                                                              int64_t n, uint32_t tag,
+                                                              int32_t *missd, unsigned long long *ctr)
+{
+    int64_t lo, hi;
+    block_range(n, &lo, &hi);
+    block_compact(
+        lo, hi, &ctr[O_RMISS], [&](int64_t id) { return rneed[id] == tag && dir[id] < 0; },
+        [&](unsigned long long o, int64_t id) { missd[o] = (int32_t)id; });
 }
 
 // Eviction candidates of the data cache: resident rows this batch does not
 // need, keyed (stamp, id) in recency order.
 __global__ __launch_bounds__(kOocBlock) void row_cands_kernel(
     const int32_t *__restrict__ owner, int64_t cap_rows, const uint32_t *__restrict__ rneed,
-    const uint32_t *__restrict__ rstamp, uint32_t tag, int32_t policy, unsigned long long *ckeys,
-    int32_t *cvals, unsigned long long *ctr)
+    const uint32_t *__restrict__ rstamp, uint32_t tag, int32_t policy, int32_t idbits,
+    int32_t kbits, unsigned long long *ckeys, int32_t *cvals, unsigned long long *ctr)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < cap_rows; base += stride) {
-        const int64_t slot = base + threadIdx.x;
-        bool c = false;
-        unsigned long long key = 0ull;
-        if (slot < cap_rows) {
-            const int32_t id = owner[slot];
-            if (id >= 0 && rneed[id] != tag) {
-                c = true;
-                key = ((unsigned long long)rstamp[id] << 32) | (uint32_t)id;
-                if (policy == QW_OOC_MRU) key = ~key;
-            }
-        }
-        const unsigned long long o = wave_append(&ctr[O_RCAND], c);
-        if (c) {
-            ckeys[o] = key;
-            cvals[o] = (int32_t)slot;
-        }
-    }
+    int64_t lo, hi;
+    block_range(cap_rows, &lo, &hi);
+    auto cand = [&](int64_t slot) {
+        const int32_t id = owner[slot];
+        return id >= 0 && rneed[id] != tag;
+    };
+    block_compact(lo, hi, &ctr[O_RCAND], cand, [&](unsigned long long o, int64_t slot) {
+        const int32_t id = owner[slot];
+        // (stamp, id) in kbits bits, ids below 2^idbits
+        unsigned long long key = ((unsigned long long)rstamp[id] << idbits) | (uint32_t)id;
+        if (policy == QW_OOC_MRU) key = ((1ull << kbits) - 1ull) - key;
+        ckeys[o] = key;
+        cvals[o] = (int32_t)slot;
+    });
 }
 
 __global__ void evict_rows_kernel(const int32_t *__restrict__ cvals, int64_t count,
@@ -402,13 +438,11 @@ __global__ __launch_bounds__(kOocBlock) void free_rows_kernel(const int32_t *__r
                                                               int64_t cap_rows, int32_t *freel,
                                                               unsigned long long *ctr)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < cap_rows; base += stride) {
-        const int64_t slot = base + threadIdx.x;
-        const bool f = slot < cap_rows && owner[slot] < 0;
-        const unsigned long long o = wave_append(&ctr[O_FREE], f);
-        if (f) freel[o] = (int32_t)slot;
-    }
+    int64_t lo, hi;
+    block_range(cap_rows, &lo, &hi);
+    block_compact(
+        lo, hi, &ctr[O_FREE], [&](int64_t slot) { return owner[slot] < 0; },
+        [&](unsigned long long o, int64_t slot) { freel[o] = (int32_t)slot; });
 }
 
 // Data phase, reads: one wave per missing row, from the host copy into a
@@ -478,11 +512,20 @@ qw_status read_ctr(OocState &st, std::vector<unsigned long long> &h, hipStream_t
     return QW_OK;
 }
 
-qw_status sort_cands(qw_index *ix, int64_t count, bool *alt, hipStream_t s)
+// Bits needed for values up to v.
+int bit_width(unsigned long long v)
+{
+    int b = 0;
+    while (b < 64 && (v >> b) != 0ull) ++b;
+    return b;
+}
+
+// Sort the candidate keys of `bits` low bits (8 per pass).
+qw_status sort_cands(qw_index *ix, int64_t count, int bits, bool *alt, hipStream_t s)
 {
     OocState &st = *ix->ooc;
-    return radix_sort_pairs(st.ckeys.as<unsigned long long>(), st.cvals.as<int32_t>(), count, 0, 64,
-                            st.ckeys2.as<unsigned long long>(), st.cvals2.as<int32_t>(),
+    return radix_sort_pairs(st.ckeys.as<unsigned long long>(), st.cvals.as<int32_t>(), count, 0,
+                            bits, st.ckeys2.as<unsigned long long>(), st.cvals2.as<int32_t>(),
                             st.sort_hist, s, alt);
 }
 
@@ -520,9 +563,14 @@ qw_status run_batch(qw_index *ix, int64_t q0, int64_t nq, hipStream_t s, OocIo *
         cut.deficit[p] = (long long)h[O_USED + p] + (long long)h[O_MISS + p] - st.cap_pool;
         any |= cut.deficit[p] > 0;
     }
+    // widths of the sort keys: bucket stamps up to (queries so far) * L, rows'
+    // stamps up to the queries so far, ids below n
+    const int64_t qnow = st.qbase + q0 + nq;
+    const int sbits = bit_width((unsigned long long)qnow * (unsigned long long)L);
+    const int pbits = bit_width((unsigned long long)(st.npools - 1));
     if (any) {
-        index_cands_kernel<<<grid_for(st.mcap, kOocBlock), kOocBlock, 0, s>>>(
-            mkey, st.mcap, n, st.o.strategy, st.o.policy, tag, st.msize.as<uint32_t>(),
+        index_cands_kernel<<<kScanGrid, kOocBlock, 0, s>>>(
+            mkey, st.mcap, n, st.o.strategy, st.o.policy, tag, sbits, st.msize.as<uint32_t>(),
             st.mstamp.as<unsigned long long>(), moff, st.mneed.as<uint32_t>(),
             st.ckeys.as<unsigned long long>(), st.cvals.as<int32_t>(), ctr);
         QW_HIP(hipGetLastError());
@@ -538,7 +586,7 @@ qw_status run_batch(qw_index *ix, int64_t q0, int64_t nq, hipStream_t s, OocIo *
         }
         const int64_t count = (int64_t)h[O_ICAND];
         bool alt = false;
-        QW_TRY(sort_cands(ix, count, &alt, s));
+        QW_TRY(sort_cands(ix, count, sbits + pbits, &alt, s));
         const unsigned long long *keys = alt ? st.ckeys2.as<unsigned long long>()
                                              : st.ckeys.as<unsigned long long>();
         const int32_t *vals = alt ? st.cvals2.as<int32_t>() : st.cvals.as<int32_t>();
@@ -549,14 +597,14 @@ qw_status run_batch(qw_index *ix, int64_t q0, int64_t nq, hipStream_t s, OocIo *
         QW_TRY(launch_scan_u32_to_u64(st.csz.as<uint32_t>(), count,
                                       st.cscan.as<unsigned long long>(), st.scan_tmp, s));
         evict_index_kernel<<<grid_exact(count), kOocBlock, 0, s>>>(
-            keys, vals, count, st.cscan.as<unsigned long long>(), cut, moff);
+            keys, vals, count, sbits, st.cscan.as<unsigned long long>(), cut, moff);
         QW_HIP(hipGetLastError());
     }
     const int64_t imiss = (int64_t)h[O_IMISS];
     if (imiss > 0) {
         int32_t *old_arena = st.arena[st.cur].as<int32_t>();
         int32_t *new_arena = st.arena[st.cur ^ 1].as<int32_t>();
-        place_index_kernel<<<grid_for(st.mcap, kOocBlock), kOocBlock, 0, s>>>(
+        place_index_kernel<<<kScanGrid, kOocBlock, 0, s>>>(
             mkey, st.mcap, n, st.o.strategy, tag, st.cap_pool, st.msize.as<uint32_t>(), moff,
             st.mneed.as<uint32_t>(), st.mnoff.as<long long>(), st.copyl.as<int32_t>(), ctr);
         QW_HIP(hipGetLastError());
@@ -583,17 +631,21 @@ qw_status run_batch(qw_index *ix, int64_t q0, int64_t nq, hipStream_t s, OocIo *
     const int32_t *arena = st.arena[st.cur].as<int32_t>();
     QW_TRY(launch_fill_u64(ctr + O_RMISS, 0ull, O_WORDS - O_RMISS, s));
     mark_rows_kernel<<<grid_for(nql, kOocBlock / 64), kOocBlock, 0, s>>>(
-        bs2, bz2, nql, arena, tag, st.rneed.as<uint32_t>(), st.dir.as<int32_t>(),
-        st.missd.as<int32_t>(), ctr);
+        bs2, bz2, nql, arena, tag, st.rneed.as<uint32_t>());
+    QW_HIP(hipGetLastError());
+    miss_rows_kernel<<<kScanGrid, kOocBlock, 0, s>>>(
+        st.rneed.as<uint32_t>(), st.dir.as<int32_t>(), n, tag, st.missd.as<int32_t>(), ctr);
     QW_HIP(hipGetLastError());
     QW_TRY(read_ctr(st, h, s));
     const int64_t rmiss = (int64_t)h[O_RMISS];
     const int64_t deficit = st.rows_used + rmiss - st.cap_rows;
     if (deficit > 0) {
-        row_cands_kernel<<<grid_for(st.cap_rows, kOocBlock), kOocBlock, 0, s>>>(
+        const int idbits = bit_width((unsigned long long)(n - 1));
+        const int kbits = idbits + bit_width((unsigned long long)qnow);
+        row_cands_kernel<<<kScanGrid, kOocBlock, 0, s>>>(
             st.owner.as<int32_t>(), st.cap_rows, st.rneed.as<uint32_t>(),
-            st.rstamp.as<uint32_t>(), tag, st.o.policy, st.ckeys.as<unsigned long long>(),
-            st.cvals.as<int32_t>(), ctr);
+            st.rstamp.as<uint32_t>(), tag, st.o.policy, idbits, kbits,
+            st.ckeys.as<unsigned long long>(), st.cvals.as<int32_t>(), ctr);
         QW_HIP(hipGetLastError());
         QW_TRY(read_ctr(st, h, s));
         const int64_t count = (int64_t)h[O_RCAND];
@@ -602,7 +654,7 @@ qw_status run_batch(qw_index *ix, int64_t q0, int64_t nq, hipStream_t s, OocIo *
             return QW_OK;
         }
         bool alt = false;
-        QW_TRY(sort_cands(ix, count, &alt, s));
+        QW_TRY(sort_cands(ix, count, kbits, &alt, s));
         const int32_t *vals = alt ? st.cvals2.as<int32_t>() : st.cvals.as<int32_t>();
         evict_rows_kernel<<<grid_exact(deficit), kOocBlock, 0, s>>>(vals, deficit,
                                                                     st.owner.as<int32_t>(),
@@ -610,7 +662,7 @@ qw_status run_batch(qw_index *ix, int64_t q0, int64_t nq, hipStream_t s, OocIo *
         QW_HIP(hipGetLastError());
     }
     if (rmiss > 0) {
-        free_rows_kernel<<<grid_for(st.cap_rows, kOocBlock), kOocBlock, 0, s>>>(
+        free_rows_kernel<<<kScanGrid, kOocBlock, 0, s>>>(
             st.owner.as<int32_t>(), st.cap_rows, st.freel.as<int32_t>(), ctr);
         QW_HIP(hipGetLastError());
         fill_rows_kernel<<<kOocGrid, kOocBlock, 0, s>>>(
