@@ -272,3 +272,29 @@ def test_kept_caches_continue_the_workload(u8case):
         assert {k: got[0][k] + got[1][k] for k in got[0]} == want_all
     finally:
         ix.close()
+
+
+def test_large_k_and_ragged_batches(f32case, u8case):
+    """K beyond the in-kernel top K (64: the FP64 re-rank of the float band
+    through the slot directory), a batch size that does not divide Q, and a
+    batch larger than Q: results and reads as the oracle gives them."""
+    c = f32case
+    wl = c.wl
+    ids_o, dist_o, _ = oracle.lsh_query(wl.data, wl.queries, c.a, c.b, c.w, 64)
+    cache_bytes, pct = c.cache(0.3, 0.3, 2)
+    want = c.expected_io(cache_bytes, pct, 2, lib.QW_OOC_MRU, 7)
+    ix = lib.Index(dev(wl.data), dev(c.a), dev(c.b), c.w)
+    try:
+        ix.set_out_of_core(cache_bytes, index_percent=pct, strategy=2, batch=7)
+        ids, dist, st = ix.query(dev(wl.queries), 64, stats=True)
+        check_topk(ids, dist, ids_o, dist_o, False)
+        assert io_of(st) == want
+    finally:
+        ix.close()
+    c = u8case
+    wl = c.wl
+    want = c.expected_io(1 << 30, 50, 1, lib.QW_OOC_LRU, 1000)
+    assert want["batches"] == 1
+    ids, dist, st = run_ooc(c, lib.QW_FORM_PLAIN_FP32, 1 << 30, 50, 1, lib.QW_OOC_LRU, 1000)
+    check_topk(ids, dist, c.ids, c.dist, True)
+    assert io_of(st) == want
