@@ -244,57 +244,51 @@ def main():
             stage += np.array(s["ms_stage"])
         return stage / nrep, s
 
-    def ooc_sweep(index, queries, Kq, cache_bytes, batch, ref, oi, od, reps=2, warm=True):
+    def ooc_sweep(index, queries, Kq, cache_bytes, batch, ref, oi, od):
         """Out of core (lists and rows in host memory, HBM as the cache C):
-        C_I's share of a fixed C swept over 1, 10, 20, ..., 90, 99 % as the
-        paper evaluates its split, Strategy 1 and MRU; every call starts with
-        empty caches (one workload, cold).  Then Strategy 2 and LRU at the
-        fastest share.  Results must equal the in-core answer `ref`."""
+        the library's tuner times C_I's share of a fixed C over 1, 10, 20,
+        ..., 90, 99 % (one cold workload pass each, Strategy 1, MRU) as the
+        paper evaluates its split, and leaves the index at the fastest; then
+        Strategy 2 and LRU at that share.  Results must equal the in-core
+        answer `ref`."""
+        t = index.autotune_ooc(queries, Kq, cache_bytes, strategy=1, policy=lib.QW_OOC_MRU,
+                               batch=batch)
         rows = []
-        same = True
-
-        def one(pct, strategy, policy):
-            nonlocal same
-            index.set_out_of_core(cache_bytes, index_percent=pct, strategy=strategy,
-                                  policy=policy, batch=batch)
-            try:
-                if warm:
-                    index.query(queries, Kq, out_ids=oi, out_dist=od)  # warm-up (allocations)
-                torch.cuda.synchronize()
-                t1 = time.time()
-                for _ in range(reps):
-                    _, _, so = index.query(queries, Kq, out_ids=oi, out_dist=od, stats=True)
-                torch.cuda.synchronize()
-                ms = (time.time() - t1) * 1e3 / reps
-                same &= bool(torch.equal(oi, ref[0]) and torch.equal(od, ref[1]))
-                io = so["ooc_index_bytes"] + so["ooc_data_bytes"]
-                return {"index_percent": pct, "strategy": strategy,
-                        "policy": "MRU" if policy == lib.QW_OOC_MRU else "LRU",
-                        "ms": round(ms, 2), "index_files": so["ooc_index_files"],
-                        "index_mb": round(so["ooc_index_bytes"] / 1e6, 2),
-                        "data_objects": so["ooc_data_objects"],
-                        "data_mb": round(so["ooc_data_bytes"] / 1e6, 2),
-                        "host_mb": round(io / 1e6, 2),
-                        "host_gbs": round(io / (ms * 1e-3) / 1e9, 2) if ms > 0 else None,
-                        "batches": so["ooc_batches"], "splits": so["ooc_splits"]}
-            except lib.QwError as e:  # a share too small for one query's lists or rows
-                return {"index_percent": pct, "strategy": strategy, "error": str(e)}
-
-        for pct in (1, 10, 20, 30, 40, 50, 60, 70, 80, 90, 99):
-            rows.append(one(pct, 1, lib.QW_OOC_MRU))
+        for sh in t["shares"]:
+            if sh["ms"] < 0:  # a share too small for one query's lists or rows
+                rows.append({"index_percent": sh["index_percent"], "refused": True})
+                continue
+            io = sh["index_bytes"] + sh["data_bytes"]
+            rows.append({"index_percent": sh["index_percent"], "ms": sh["ms"],
+                         "index_mb": round(sh["index_bytes"] / 1e6, 2),
+                         "data_mb": round(sh["data_bytes"] / 1e6, 2),
+                         "host_mb": round(io / 1e6, 2),
+                         "host_gbs": round(io / (sh["ms"] * 1e-3) / 1e9, 2),
+                         "batches": sh["batches"], "splits": sh["splits"]})
             log(f"[bench] out of core C={cache_bytes >> 20} MiB: {rows[-1]}")
+        index.query(queries, Kq, out_ids=oi, out_dist=od)  # at the chosen share
+        torch.cuda.synchronize()
+        same = bool(torch.equal(oi, ref[0]) and torch.equal(od, ref[1]))
+        best = t["index_percent"]
         ok = [r for r in rows if "ms" in r]
-        best = min(ok, key=lambda r: r["ms"]) if ok else None
-        least_io = min(ok, key=lambda r: r["host_mb"]) if ok else None
+        least_io = min(ok, key=lambda r: r["host_mb"])["index_percent"]
         extra = []
-        if best:
-            extra.append(one(best["index_percent"], 2, lib.QW_OOC_MRU))
-            extra.append(one(best["index_percent"], 1, lib.QW_OOC_LRU))
+        for strategy, policy in ((2, lib.QW_OOC_MRU), (1, lib.QW_OOC_LRU)):
+            index.set_out_of_core(cache_bytes, index_percent=best, strategy=strategy,
+                                  policy=policy, batch=batch)
+            t1 = time.time()
+            _, _, so = index.query(queries, Kq, out_ids=oi, out_dist=od, stats=True)
+            torch.cuda.synchronize()
+            same &= bool(torch.equal(oi, ref[0]) and torch.equal(od, ref[1]))
+            extra.append({"index_percent": best, "strategy": strategy,
+                          "policy": "MRU" if policy == lib.QW_OOC_MRU else "LRU",
+                          "ms": round((time.time() - t1) * 1e3, 2),
+                          "host_mb": round((so["ooc_index_bytes"] + so["ooc_data_bytes"]) / 1e6, 2)})
         index.set_out_of_core(None)
         return {"cache_mb": round(cache_bytes / 2**20, 1), "batch": batch, "sweep": rows,
-                "fastest_index_percent": best["index_percent"] if best else None,
-                "least_io_index_percent": least_io["index_percent"] if least_io else None,
-                "at_fastest_share": extra, "identical_to_in_core": same}
+                "fastest_index_percent": best, "least_io_index_percent": least_io,
+                "at_fastest_share": extra, "identical_to_in_core": same,
+                "tuner": "qw_autotune_ooc (Strategy 1, MRU)"}
 
     def h2d_rate():
         """Pinned host to device copy rate (1 GiB, best of three)."""
@@ -754,10 +748,7 @@ def main():
         if not args.no_ooc_leg:
             t1 = time.time()
             ref5_d = (torch.from_numpy(ref5[0]).to(dev), torch.from_numpy(ref5[1]).to(dev))
-            # one cold pass per share: the passes take seconds, their allocations
-            # happen in qw_set_out_of_core
-            ooc_f32 = ooc_sweep(ix5, q5, wl5.K, OOC_CACHE_F32, 10000, ref5_d, oi5, od5, reps=1,
-                                warm=False)
+            ooc_f32 = ooc_sweep(ix5, q5, wl5.K, OOC_CACHE_F32, 10000, ref5_d, oi5, od5)
             ooc_f32["workload"] = (f"n={wl5.n} d={wl5.d} f32, Q={wl5.Q} Zipf, L={wl5.params.L} "
                                    f"k={wl5.params.k} w={CFG5_W}, lists "
                                    f"{4 * wl5.params.L * wl5.n / 1e6:.0f} MB + rows "

@@ -177,7 +177,7 @@ typedef struct {
     double mean_hit_bucket;   /* mean over layers of sum_b s_b^2 / n: the expected size of the
                                  bucket a data point falls in */
     int32_t out_of_core;      /* 1 while qw_set_out_of_core is on */
-    int32_t reserved;
+    int32_t ooc_index_percent;  /* its index share (0 in core) */
     int64_t host_bytes;       /* pinned host memory held (the out-of-core lists and rows) */
 } qw_index_info;
 
@@ -509,6 +509,46 @@ typedef struct {
  * are unspecified.
  */
 qw_status qw_set_out_of_core(qw_index *ix, const qw_ooc_opts *o, void *stream);
+
+/* Outcome of qw_autotune_ooc (host). */
+typedef struct {
+    int32_t index_percent;     /* the fastest share; the index is left out of core at it */
+    int32_t shares;            /* shares timed: 11 */
+    int32_t percent[11];       /* 1, 10, 20, ..., 90, 99 */
+    float ms[11];              /* one cold workload pass; -1: the share cannot hold one query */
+    int64_t index_bytes[11];   /* bytes of index files read from host memory */
+    int64_t data_bytes[11];    /* bytes of data objects read from host memory */
+    int64_t batches[11];       /* batches answered */
+    int64_t splits[11];        /* batches halved */
+} qw_ooc_tune_result;
+
+/*
+ * Choose the index share of the out-of-core cache by measurement.  The paper
+ * evaluates its split against the best of eleven settings of C_I (1, 10, 20,
+ * ..., 90, 99 %, Section 6) and predicts it offline from the data's size and
+ * dimensionality (Sections 5.2 and 5.3).  Here each setting is timed on the
+ * workload itself.
+ *  queries  device, Q x d (the workload, or a sample of it).
+ *  K        1 <= K <= 1024.
+ *  base     host; the cache size, strategy, policy and batch to keep.  The
+ *           index share is ignored; keep applies to the final setting, and
+ *           every timed pass starts with empty caches.
+ *  out      host; every share's time and reads, and the fastest.
+ * Each share answers the workload once, cold (qw_set_out_of_core, then
+ * qw_query_workload), with the default query options.  The outputs of every
+ * share that fits must be identical; otherwise QW_EINTERNAL.  The index is
+ * then left out of core at the fastest share.  It may be in core or out of
+ * core on entry.
+ * Allocates two output buffers of Q*K*4 bytes and synchronises `stream`.
+ * Errors:
+ *  - QW_EINVAL on bad arguments;
+ *  - QW_EUNSUPPORTED when probing or counting is on, or when no share can
+ *    hold one query;
+ *  - QW_ENOMEM.
+ * After an error the index may be left out of core at one of the shares.
+ */
+qw_status qw_autotune_ooc(qw_index *ix, const void *queries, int64_t Q, int32_t K,
+                          const qw_ooc_opts *base, void *stream, qw_ooc_tune_result *out);
 
 #ifdef __cplusplus
 }

@@ -889,6 +889,7 @@ qw_status qw_get_index_info(const qw_index *ix, qw_index_info *info)
     info->count_extra = ix->count_extra;
     info->mean_hit_bucket = ix->mean_hit_bucket;
     info->out_of_core = ix->ooc ? 1 : 0;
+    info->ooc_index_percent = ix->ooc ? ix->ooc->o.index_percent : 0;
     info->host_bytes = ix->ooc ? (int64_t)ix->ooc->host_bytes : 0;
     if (ix->ooc) {
         const OocState &o = *ix->ooc;

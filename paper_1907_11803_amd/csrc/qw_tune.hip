@@ -295,3 +295,82 @@ extern "C" qw_status qw_autotune(qw_index *ix, const void *queries, int64_t Q, i
     out->candidates = (int32_t)cands.size();
     return QW_OK;
 }
+
+extern "C" qw_status qw_autotune_ooc(qw_index *ix, const void *queries, int64_t Q, int32_t K,
+                                     const qw_ooc_opts *base, void *stream,
+                                     qw_ooc_tune_result *out)
+{
+    if (!ix || !queries || Q < 1 || K < 1 || K > kMaxTopK || !base || !out) return QW_EINVAL;
+    int dev = -1;
+    QW_HIP(hipGetDevice(&dev));
+    if (dev != ix->device) return QW_EINVAL;
+    if (base->cache_bytes <= 0 || (base->strategy != 1 && base->strategy != 2) ||
+        (base->policy != QW_OOC_MRU && base->policy != QW_OOC_LRU) || base->batch < 1 ||
+        (base->keep != 0 && base->keep != 1) || base->reserved != 0)
+        return QW_EINVAL;
+    if (ix->nprobe != 1 || ix->count_theta > 0) return QW_EUNSUPPORTED;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    std::memset(out, 0, sizeof(*out));
+    constexpr int kShares[11] = {1, 10, 20, 30, 40, 50, 60, 70, 80, 90, 99};
+    void *d_ids = nullptr, *d_dist = nullptr;
+    if (hipMalloc(&d_ids, sizeof(int32_t) * (size_t)Q * K) != hipSuccess ||
+        hipMalloc(&d_dist, sizeof(uint32_t) * (size_t)Q * K) != hipSuccess) {  // int32 or float32
+        (void)hipGetLastError();
+        if (d_ids) (void)hipFree(d_ids);
+        return QW_ENOMEM;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    qw_status rc = QW_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = QW_EDEVICE;
+    std::vector<int32_t> ref_ids, ids((size_t)Q * K);
+    std::vector<uint32_t> ref_d, dist((size_t)Q * K);
+    int best = -1;
+    out->shares = 11;
+    for (int i = 0; rc == QW_OK && i < 11; ++i) {
+        qw_ooc_opts o = *base;
+        o.index_percent = kShares[i];
+        o.keep = 0;  // every pass starts cold
+        out->percent[i] = kShares[i];
+        out->ms[i] = -1.f;
+        rc = qw_set_out_of_core(ix, &o, stream);
+        if (rc != QW_OK) break;
+        qw_stats st;
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = QW_EDEVICE; break; }
+        const qw_status qr = qw_query_workload(ix, queries, Q, K, nullptr, stream,
+                                               static_cast<int32_t *>(d_ids), d_dist, &st);
+        if (qr == QW_EUNSUPPORTED) continue;  // the share cannot hold one query
+        if (qr != QW_OK) { rc = qr; break; }
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = QW_EDEVICE; break; }
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = QW_EDEVICE; break; }
+        if (hipMemcpy(ids.data(), d_ids, sizeof(int32_t) * ids.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(dist.data(), d_dist, sizeof(uint32_t) * dist.size(), hipMemcpyDeviceToHost) != hipSuccess) {
+            rc = QW_EDEVICE;
+            break;
+        }
+        if (best < 0) {
+            ref_ids = ids;
+            ref_d = dist;
+        } else if (ids != ref_ids || dist != ref_d) {  // caching changes no result
+            rc = QW_EINTERNAL;
+            break;
+        }
+        out->ms[i] = ms;
+        out->index_bytes[i] = st.ooc_index_bytes;
+        out->data_bytes[i] = st.ooc_data_bytes;
+        out->batches[i] = st.ooc_batches;
+        out->splits[i] = st.ooc_splits;
+        if (best < 0 || ms < out->ms[best]) best = i;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(d_ids);
+    (void)hipFree(d_dist);
+    if (rc != QW_OK) return rc;
+    if (best < 0) return QW_EUNSUPPORTED;
+    qw_ooc_opts o = *base;
+    o.index_percent = kShares[best];
+    out->index_percent = kShares[best];
+    return qw_set_out_of_core(ix, &o, stream);
+}
+

@@ -71,7 +71,14 @@ class qw_index_info(ctypes.Structure):
                 ("probing", ctypes.c_int32), ("probes_per_layer", ctypes.c_int32),
                 ("count_threshold", ctypes.c_int32), ("count_extra", ctypes.c_int32),
                 ("mean_hit_bucket", ctypes.c_double), ("out_of_core", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("host_bytes", ctypes.c_int64)]
+                ("ooc_index_percent", ctypes.c_int32), ("host_bytes", ctypes.c_int64)]
+
+
+class qw_ooc_tune_result(ctypes.Structure):
+    _fields_ = [("index_percent", ctypes.c_int32), ("shares", ctypes.c_int32),
+                ("percent", ctypes.c_int32 * 11), ("ms", ctypes.c_float * 11),
+                ("index_bytes", ctypes.c_int64 * 11), ("data_bytes", ctypes.c_int64 * 11),
+                ("batches", ctypes.c_int64 * 11), ("splits", ctypes.c_int64 * 11)]
 
 
 class qw_ooc_opts(ctypes.Structure):
@@ -113,6 +120,7 @@ SIGNATURES = {
     "qw_set_probing": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
     "qw_set_counting": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
     "qw_set_out_of_core": (ctypes.c_int, [_P, _P, _P]),
+    "qw_autotune_ooc": (ctypes.c_int, [_P, _P, _I64, _I32, _P, _P, _P]),
 }
 
 _lib = None
@@ -382,6 +390,23 @@ def qw_set_out_of_core(ix, cache_bytes: Optional[int], index_percent: int = 50, 
     _check(load().qw_set_out_of_core(ix, ctypes.byref(o), _stream(stream)), "qw_set_out_of_core")
 
 
+def qw_autotune_ooc(ix, queries: torch.Tensor, K: int, cache_bytes: int, strategy: int = 1,
+                    policy: int = QW_OOC_MRU, batch: int = 10000, keep: int = 0, stream=None) -> dict:
+    """Time the eleven index shares (1, 10, ..., 90, 99 %) of an out-of-core
+    cache on the workload; the index is left out of core at the fastest."""
+    queries = _dev(queries, (torch.uint8, torch.float32), "queries")
+    o = qw_ooc_opts(cache_bytes=int(cache_bytes), index_percent=0, strategy=int(strategy),
+                    policy=int(policy), batch=int(batch), keep=int(keep), reserved=0)
+    r = qw_ooc_tune_result()
+    _check(load().qw_autotune_ooc(ix, _ptr(queries), queries.shape[0], int(K), ctypes.byref(o),
+                                  _stream(stream), ctypes.byref(r)), "qw_autotune_ooc")
+    n = r.shares
+    return {"index_percent": r.index_percent,
+            "shares": [{"index_percent": r.percent[i], "ms": round(float(r.ms[i]), 3),
+                        "index_bytes": r.index_bytes[i], "data_bytes": r.data_bytes[i],
+                        "batches": r.batches[i], "splits": r.splits[i]} for i in range(n)]}
+
+
 def qw_get_count_model(ix, L: int) -> np.ndarray:
     p = np.empty(qw_mlp_param_count(L), dtype=np.float32)
     _check(load().qw_get_count_model(ix, ctypes.c_void_p(p.ctypes.data), p.size), "qw_get_count_model")
@@ -446,6 +471,9 @@ class Index:
         """Lists and rows to pinned host memory with an HBM cache of
         cache_bytes split index_percent / the rest (None: back in HBM)."""
         qw_set_out_of_core(self.handle, cache_bytes, **kw)
+
+    def autotune_ooc(self, queries, K, cache_bytes, **kw) -> dict:
+        return qw_autotune_ooc(self.handle, queries, K, cache_bytes, **kw)
 
     def info(self) -> dict:
         return qw_get_index_info(self.handle)

@@ -298,3 +298,36 @@ def test_large_k_and_ragged_batches(f32case, u8case):
     ids, dist, st = run_ooc(c, lib.QW_FORM_PLAIN_FP32, 1 << 30, 50, 1, lib.QW_OOC_LRU, 1000)
     check_topk(ids, dist, c.ids, c.dist, True)
     assert io_of(st) == want
+
+
+def test_autotune_picks_the_fastest_share(u8case):
+    """qw_autotune_ooc times the eleven index shares of a fixed cache: each
+    share's reads are the oracle's for that share (or the share is refused
+    where the oracle's model cannot hold one query), the fastest is chosen and
+    the index is left out of core at it, with the oracle's results."""
+    c = u8case
+    wl = c.wl
+    cache_bytes, _ = c.cache(0.3, 0.3, 2)
+    ix = lib.Index(dev(wl.data), dev(c.a), dev(c.b), c.w)
+    try:
+        r = ix.autotune_ooc(dev(wl.queries), wl.K, cache_bytes, strategy=2, batch=25)
+        fits = []
+        for sh in r["shares"]:
+            try:
+                want = c.expected_io(cache_bytes, sh["index_percent"], 2, lib.QW_OOC_MRU, 25)
+            except ooc.CacheTooSmall:
+                assert sh["ms"] < 0, sh
+                continue
+            assert sh["ms"] > 0
+            got = {"index_bytes": sh["index_bytes"], "data_bytes": sh["data_bytes"],
+                   "batches": sh["batches"], "splits": sh["splits"]}
+            assert got == {k: want[k] for k in got}, (sh["index_percent"], got, want)
+            fits.append(sh)
+        assert len(fits) >= 3
+        assert r["index_percent"] == min(fits, key=lambda x: x["ms"])["index_percent"]
+        info = ix.info()
+        assert info["out_of_core"] == 1 and info["ooc_index_percent"] == r["index_percent"]
+        ids, dist = ix.query(dev(wl.queries), wl.K)
+        check_topk(ids, dist, c.ids, c.dist, True)
+    finally:
+        ix.close()

@@ -40,13 +40,14 @@ def test_struct_layout_matches_c(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "qwlsh.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\","
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\","
         " sizeof(qw_opts), sizeof(qw_stats),"
         " sizeof(qw_index_info), offsetof(qw_stats, ms_stage), offsetof(qw_index_info, buckets),"
         " offsetof(qw_index_info, has_count_model), offsetof(qw_index_info, probing),"
         " sizeof(qw_tune_result), offsetof(qw_tune_result, ms_default),"
         " offsetof(qw_stats, ooc_index_files), offsetof(qw_stats, ooc_splits),"
-        " offsetof(qw_index_info, host_bytes), sizeof(qw_ooc_opts), offsetof(qw_ooc_opts, keep));"
+        " offsetof(qw_index_info, host_bytes), sizeof(qw_ooc_opts), offsetof(qw_ooc_opts, keep),"
+        " sizeof(qw_ooc_tune_result), offsetof(qw_ooc_tune_result, splits));"
         "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
@@ -57,7 +58,8 @@ def test_struct_layout_matches_c(tmp_path):
             ctypes.sizeof(lib.qw_tune_result), lib.qw_tune_result.ms_default.offset,
             lib.qw_stats.ooc_index_files.offset, lib.qw_stats.ooc_splits.offset,
             lib.qw_index_info.host_bytes.offset, ctypes.sizeof(lib.qw_ooc_opts),
-            lib.qw_ooc_opts.keep.offset]
+            lib.qw_ooc_opts.keep.offset, ctypes.sizeof(lib.qw_ooc_tune_result),
+            lib.qw_ooc_tune_result.splits.offset]
     assert got == want
 
 
@@ -84,6 +86,7 @@ def test_validation_rejects_before_device_work(so):
     assert so.qw_set_probing(None, 1, 0) == lib.QW_EINVAL
     assert so.qw_set_counting(None, 1, 0) == lib.QW_EINVAL
     assert so.qw_set_out_of_core(None, None, None) == lib.QW_EINVAL
+    assert so.qw_autotune_ooc(None, None, 1, 1, None, None, None) == lib.QW_EINVAL
     assert so.qw_mlp_loss_grad(None, 4, None, None, 1, None, None, None) == lib.QW_EINVAL
     so.qw_free_index(None)  # no-op
 
