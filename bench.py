@@ -469,6 +469,12 @@ def main():
         f"identical {sched_identical}")
 
     stage, st = stage_times(ix, {k: v for k, v in fast_kw.items() if k != "graph"})
+    # the plain form's stages: its hash-set size is read back to the host
+    # (one synchronisation) between probing and verification
+    pstage, _ = stage_times(ix, dict(form=lib.QW_FORM_PLAIN_FP32))
+    plain_stage = {"hash": round(float(pstage[0]), 4), "probe": round(float(pstage[1]), 4),
+                   "size_readback": round(float(pstage[2]), 4),
+                   "verify_topk": round(float(pstage[3]), 4), "total": round(float(pstage[5]), 4)}
     alg_bytes = (wl.Q * wl.d * elem + 8 * L * wl.Q + 4 * st["cand_total"] +
                  st["cand_unique"] * wl.d * elem + 8 * K * wl.Q)
     roof = candidate_roofline(st, float(stage[6]), wl.Q, wl.d, elem, K, is_u8, args.config, w,
@@ -812,6 +818,7 @@ def main():
         "recall_at_10": round(rec, 4),
         "autotune": autotune,
         "plain_fp32_qps": round(wl.Q / (ms_plain * 1e-3), 1),
+        "plain_fp32_stage_ms": plain_stage,
         "speedup_vs_plain_fp32": round(ms_plain / ms_fast, 3),
         "forms_identical": identical,
         "sched_ms_per_step": sched_ms,
