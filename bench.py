@@ -660,6 +660,24 @@ def main():
             ooc_u8["workload"] = (f"n={wl.n} d={wl.d} u8, Q={wl.Q}, L={L} k={wl.params.k} w={uw}, "
                                   f"lists {4 * L * wl.n / 1e6:.0f} MB + rows "
                                   f"{wl.n * wl.d / 1e6:.0f} MB in host memory")
+            # the paper's other two sweeps: the total cache size, and the
+            # number of queries in the workload; the tuner's choice for each
+            def choice(queries, cache):
+                try:
+                    t = uix.autotune_ooc(queries, K, cache, strategy=1, batch=1000)
+                except lib.QwError as e:  # no share holds one query
+                    uix.set_out_of_core(None)
+                    return {"error": str(e)}
+                best = next(x for x in t["shares"] if x["index_percent"] == t["index_percent"])
+                uix.set_out_of_core(None)
+                return {"fastest_index_percent": t["index_percent"], "ms": best["ms"],
+                        "host_mb": round((best["index_bytes"] + best["data_bytes"]) / 1e6, 2)}
+            ooc_u8["by_cache_mb"] = {str(c >> 20): choice(q_d, c)
+                                     for c in (16 << 20, 32 << 20, 128 << 20, 256 << 20)}
+            ooc_u8["by_queries"] = {str(nq): choice(q_d[:nq].contiguous(), OOC_CACHE_U8)
+                                    for nq in (1000, 3000)}
+            log(f"[bench] out of core by cache size: {ooc_u8['by_cache_mb']}; "
+                f"by workload size: {ooc_u8['by_queries']}")
             ooc_u8["sweep_s"] = round(time.time() - t1, 1)
         uix.close()
     del train_d
