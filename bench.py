@@ -532,6 +532,23 @@ def main():
         hb.append(e0.elapsed_time(e1))
     bms = min(hb)
     build_tflops = 2.0 * wl.d * L * wl.params.k * wl.n / (bms * 1e-3) / 1e12
+    # the matrix-core rate this GPU reaches in a large library GEMM of the
+    # same input type (torch.matmul, 8192^3, best of three): a measured peak
+    gdt = torch.float16 if is_u8 else torch.float32
+    ga = torch.randn(8192, 8192, device=dev, dtype=torch.float32).to(gdt)
+    gb = torch.randn(8192, 8192, device=dev, dtype=torch.float32).to(gdt)
+    torch.matmul(ga, gb)
+    gms = []
+    for _ in range(3):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        torch.matmul(ga, gb)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        gms.append(e0.elapsed_time(e1))
+    gemm_tflops = 2.0 * 8192 ** 3 / (min(gms) * 1e-3) / 1e12
+    del ga, gb
     hash_info = {"kernel": "hash_mfma_f16_kernel" if is_u8 else "hash_mfma_f32_kernel",
                  "peak_tflops": hash_peak,
                  "query_kernel": q_kernel, "query_peak_tflops": q_peak,
@@ -541,6 +558,8 @@ def main():
                  "build_rows": wl.n, "build_hash_ms": round(bms, 4),
                  "build_algorithmic_tflops": round(build_tflops, 2),
                  "build_frac": round(build_tflops / hash_peak, 5),
+                 "measured_gemm_tflops": round(gemm_tflops, 1),
+                 "build_frac_of_measured_gemm": round(build_tflops / gemm_tflops, 5),
                  "build_recompute_frac": round(brec / (wl.n * L * wl.params.k), 6),
                  "index_build_s": round(build_s, 3)}
     log(f"[bench] hashing: query {stage[0]:.4f} ms, build rows {bms:.3f} ms "
@@ -769,6 +788,13 @@ def main():
             split_same &= bool(np.array_equal(r_ids.cpu().numpy(), ref5[0]) and
                                np.array_equal(r_dist.cpu().numpy(), ref5[1]))
         rec5 = recall_at_10(ref5[0][sel5], ti5.cpu().numpy(), ref5[1][sel5], td5.cpu().numpy())
+        # the count model's error on the workload, log(1 + |C(q)|)
+        f5 = torch.log1p(ix5.bucket_sizes(q5).to(torch.float32)).contiguous()
+        p5 = lib.qw_mlp_predict_bf16(torch.from_numpy(ix5.get_count_model()).to(dev),
+                                     wl5.params.L, f5).cpu().numpy()
+        a5 = np.log1p(ix5.candidate_counts(q5).cpu().numpy().astype(np.float64))
+        mae5 = round(float(np.mean(np.abs(p5 - a5))), 4)
+        del f5
         # the candidate kernel's roofline under the learned schedule (its stage
         # time from the library's events; the stored counter traffic of the same
         # workload when the kernel's sources still match)
@@ -789,6 +815,8 @@ def main():
             "train_s": round(train5_s, 1),
             "unique_per_query": s5["cand_unique"] / wl5.Q,
             "sum_of_buckets_per_query": s5["cand_total"] / wl5.Q,
+            "mae_log": mae5,
+            "overflow_queries": s5["overflow"], "fallback_queries": s5["fallback"],
         }
         log(f"[bench] float Zipf schedules: {ms5}, identical {same5}, recall {rec5:.4f}")
         if not args.no_ooc_leg:
