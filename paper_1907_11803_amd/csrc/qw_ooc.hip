@@ -445,8 +445,9 @@ __global__ __launch_bounds__(kOocBlock) void free_rows_kernel(const int32_t *__r
         [&](unsigned long long o, int64_t slot) { freel[o] = (int32_t)slot; });
 }
 
-// Data phase, reads: one wave per missing row, from the host copy into a
-// free slot (the data IO).
+// Data phase, reads: from the host copy into free slots (the data IO).  A
+// wave takes 64 / parts rows at once when rows are short (so every lane
+// moves 16 bytes), else one row in 64-lane strides.
 __global__ __launch_bounds__(kOocBlock) void fill_rows_kernel(
     const int32_t *__restrict__ missd, const int32_t *__restrict__ freel,
     const unsigned long long *__restrict__ ctr, int64_t parts, const uint4 *__restrict__ host_rows,
@@ -455,16 +456,23 @@ __global__ __launch_bounds__(kOocBlock) void fill_rows_kernel(
     // the eviction leaves at least as many free slots as misses
     const int64_t count = (int64_t)min(ctr[O_RMISS], ctr[O_FREE]);
     const int lane = threadIdx.x & 63;
+    // rows per wave: a power of two with rpw * parts <= 64 (1 for long rows)
+    int rpw = 1;
+    while (rpw * 2 * parts <= 64) rpw *= 2;
+    const int lpr = 64 / rpw;  // lanes per row
+    const int r = lane / lpr, j0 = lane % lpr;
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x / 64);
-    for (int64_t e = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); e < count;
-         e += nw) {
+    for (int64_t e0 = ((int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * rpw;
+         e0 < count; e0 += nw * rpw) {
+        const int64_t e = e0 + r;
+        if (e >= count) continue;
         const int32_t id = missd[e];
         const int32_t slot = freel[e];
         if (slot < 0 || slot >= cap_rows) continue;
         const uint4 *src = host_rows + (int64_t)id * parts;
         uint4 *dst = rows + (int64_t)slot * parts;
-        for (int64_t j = lane; j < parts; j += 64) dst[j] = src[j];
-        if (lane == 0) {
+        for (int64_t j = j0; j < parts; j += lpr) dst[j] = src[j];
+        if (j0 == 0) {
             owner[slot] = id;
             dir[id] = slot;
         }
