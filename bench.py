@@ -38,7 +38,7 @@ FP64_PEAK_TFLOPS = 78.6         # FP64 vector (fused multiply-add) peak
 W_GRID = [1, 1.5, 2, 2.5, 3, 4, 6, 8]
 # index share of the staged kernel's LDS caches swept (percent), the paper's
 # sweep of the index/data split
-SPLIT_SWEEP = [1, 10, 25, 50, 75, 90, 99]
+SPLIT_SWEEP = [1, 10, 20, 30, 40, 50, 60, 70, 80, 90, 99]  # the eleven settings the paper sweeps
 METRIC = "queries/sec at recall@10>=0.9, BF16+learned vs plain FP32 on 1 MI355X"
 # w_0.9 of the 1M x 960 float Zipf workload without neighbour probing (8 x 1.5),
 # measured with the w search above; its leg re-measures the recall
