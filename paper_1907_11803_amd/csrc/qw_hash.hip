@@ -242,12 +242,25 @@ __device__ inline uint4 mask16(uint4 v, bool keep)
 // exact in FP16; products are exact in FP32.  v_mfma_f32_16x16x16f16, once for
 // a_hi and once for a_lo.  Three workgroups per CU (registers and LDS), so a
 // 10^4-query batch (628 workgroups) runs in one round.
+//
+// A workgroup takes 64 rows and `bpw` (at most 4) consecutive 64-function
+// tiles of them: all of a row's functions up to 256 when the row blocks alone
+// fill the GPU twice over.  Each tile's hash values go through LDS (the a_hi
+// staging buffer, free once the tile's last MFMA has read it) and leave as
+// whole 16-byte pieces of each row's 256-byte run, so a row's runs are written
+// together from one workgroup and its cache lines fill in one L2 instead of
+// arriving in pieces from workgroups far apart in the launch.  Guard-band
+// outputs are marked per lane and recomputed at the end, over the stored
+// tile values (inside the tile loop their FP64 registers would spill the
+// MFMA loop's).
+constexpr int kTileLd = 68;  // ints per staged output row: the four lane groups' rows land on distinct banks
+
 __global__ __launch_bounds__(kBlock, 3) void hash_mfma_f16_kernel(
     const uint8_t *__restrict__ x, int64_t m, int32_t dp, int32_t d,
     const _Float16 *__restrict__ ahi, const _Float16 *__restrict__ alo,
     const float *__restrict__ a32, const float *__restrict__ b, int32_t f0, int32_t nfun,
-    double w, const double *__restrict__ gbc, int32_t *__restrict__ out, int32_t out_ld,
-    unsigned long long *recomputed)
+    int32_t bpw, double w, const double *__restrict__ gbc, int32_t *__restrict__ out,
+    int32_t out_ld, unsigned long long *recomputed)
 {
     constexpr int KC = kKcF16;
     constexpr int XS = KC + 16;  // bytes per staged row of x
@@ -255,27 +268,25 @@ __global__ __launch_bounds__(kBlock, 3) void hash_mfma_f16_kernel(
     __shared__ __align__(16) uint8_t xs[64 * XS];
     __shared__ __align__(16) _Float16 hs[64 * AS];
     __shared__ __align__(16) _Float16 ls[64 * AS];
+    static_assert(sizeof(hs) >= sizeof(int32_t) * 64 * kTileLd, "the output tile reuses hs");
+    int32_t *tile = reinterpret_cast<int32_t *>(hs);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t rowb = (int64_t)blockIdx.x * 64;
     const int64_t row0 = rowb + wv * 16;
-    const int fbase = f0 + blockIdx.y * 64;
     const int r = lane & 15, kq = (lane >> 4) * 4;
-    // the epilogue's per-function constants, loaded up front (clamped to the
-    // launch's function range; out-of-range functions are never stored)
-    float bf[4], cw[4];
-#pragma unroll
-    for (int fb = 0; fb < 4; ++fb) {
-        const int f = min(fbase + fb * 16 + r, f0 + nfun - 1);
-        bf[fb] = b[f];
-        cw[fb] = band_coef(gbc[f], w);
-    }
+    const int blk0 = (int)blockIdx.y * bpw;
+    const int nblk = min((nfun + 63) / 64 - blk0, bpw);
+    const int nkc = (dp + KC - 1) / KC;
+    const bool vec = (out_ld & 3) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0;
     const float iw = (float)(1.0 / w);
     // staging registers: x = 64 rows x KC bytes (2 x 16 B per thread), a_hi and
     // a_lo = 64 functions x KC halves (4 x 16 B each); rows past m repeat row
     // m - 1; a piece past dp re-reads the row's last piece (every load is in
-    // bounds and none waits on a branch) and is stored as zeros
+    // bounds and none waits on a branch) and is stored as zeros.  Step t is
+    // chunk t % nkc of tile t / nkc.
     uint4 xr[2], hr[4], lr[4];
-    auto load_chunk = [&](int kc) {
+    auto load_step = [&](int t) {
+        const int kc = (t % nkc) * KC, fbase = f0 + (blk0 + t / nkc) * 64;
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const int e = tid + i * kBlock, row = e >> 3, k = kc + (e & 7) * 16;
@@ -307,65 +318,111 @@ __global__ __launch_bounds__(kBlock, 3) void hash_mfma_f16_kernel(
             *reinterpret_cast<uint4 *>(ls + o) = mask16(lr[i], keep);
         }
     };
-    floatx4_t acc_hi[4], acc_lo[4];
+    unsigned long long marks = 0;  // bit 16 bt + 4 fb + j: output (j, fb) of tile bt in the guard band
+    if (nblk > 0) load_step(0);
+    for (int bt = 0; bt < nblk; ++bt) {
+        const int fbase = f0 + (blk0 + bt) * 64;
+        // the tile's epilogue constants (clamped to the launch's function
+        // range; functions past it are never stored)
+        float bf[4], cw[4];
+        floatx4_t acc_hi[4], acc_lo[4];
 #pragma unroll
-    for (int fb = 0; fb < 4; ++fb) {
-        acc_hi[fb] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-        acc_lo[fb] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-    }
-    uint32_t xmax = 0;
-    load_chunk(0);
-    for (int kc = 0; kc < dp; kc += KC) {
-        __syncthreads();  // the previous chunk's reads are done
-        store_chunk(kc);
+        for (int fb = 0; fb < 4; ++fb) {
+            acc_hi[fb] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+            acc_lo[fb] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+            const int f = min(fbase + fb * 16 + r, f0 + nfun - 1);
+            bf[fb] = b[f];
+            cw[fb] = band_coef(gbc[f], w);
+        }
+        uint32_t xmax = 0;
+        for (int c = 0; c < nkc; ++c) {
+            const int kc = c * KC;
+            __syncthreads();  // the previous chunk's (or tile's) reads are done
+            store_chunk(kc);
+            __syncthreads();
+            // the next chunk (of this tile or the next) flies during this
+            // one's MFMAs and the epilogue
+            if (c + 1 < nkc || bt + 1 < nblk) load_step(bt * nkc + c + 1);
+            const int ns = (dp - kc < KC ? dp - kc : KC) / 16;
+#pragma unroll
+            for (int st = 0; st < KC / 16; ++st) {
+                if (st >= ns) break;
+                const uint32_t xv = *reinterpret_cast<const uint32_t *>(xs + (wv * 16 + r) * XS + st * 16 + kq);
+                half4_t ah[4], al[4];
+#pragma unroll
+                for (int fb = 0; fb < 4; ++fb) {
+                    const int o = (fb * 16 + r) * AS + st * 16 + kq;
+                    ah[fb] = *reinterpret_cast<const half4_t *>(hs + o);
+                    al[fb] = *reinterpret_cast<const half4_t *>(ls + o);
+                }
+                const uint32_t b0 = xv & 255u, b1 = (xv >> 8) & 255u, b2 = (xv >> 16) & 255u, b3 = xv >> 24;
+                xmax = max(xmax, max(max(b0, b1), max(b2, b3)));
+                const half4_t xh = {(_Float16)(float)b0, (_Float16)(float)b1, (_Float16)(float)b2,
+                                    (_Float16)(float)b3};
+#pragma unroll
+                for (int fb = 0; fb < 4; ++fb) {
+                    acc_hi[fb] = __builtin_amdgcn_mfma_f32_16x16x16f16(xh, ah[fb], acc_hi[fb], 0, 0, 0);
+                    acc_lo[fb] = __builtin_amdgcn_mfma_f32_16x16x16f16(xh, al[fb], acc_lo[fb], 0, 0, 0);
+                }
+            }
+        }
+        // ---- the tile's epilogue
+        xmax = max(xmax, (uint32_t)__shfl_xor((int)xmax, 16));
+        xmax = max(xmax, (uint32_t)__shfl_xor((int)xmax, 32));
+        float xm[4];
+        for (int j = 0; j < 4; ++j) xm[j] = (float)__shfl((int)xmax, (lane >> 4) * 4 + j);
+        // this lane's outputs: rows rl + j (j < 4), functions fbase + r + 16 fb;
+        // tile row tr + j
+        const int64_t rl = row0 + (lane >> 4) * 4;
+        const int tr = wv * 16 + (lane >> 4) * 4;
+        uint32_t pend = 0;
+        __syncthreads();  // every wave's MFMAs have read hs
+#pragma unroll
+        for (int fb = 0; fb < 4; ++fb) {
+            const int f = fbase + fb * 16 + r;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                int32_t h = 0;
+                if (rl + j < m && f < f0 + nfun &&
+                    !accept_fp32(acc_hi[fb][j] + acc_lo[fb][j], bf[fb], iw, cw[fb] * xm[j], h))
+                    pend |= 1u << (fb * 4 + j);
+                tile[(tr + j) * kTileLd + fb * 16 + r] = h;
+            }
+        }
+        marks |= (unsigned long long)pend << (16 * bt);
         __syncthreads();
-        if (kc + KC < dp) load_chunk(kc + KC);
-        const int ns = (dp - kc < KC ? dp - kc : KC) / 16;
+        // the tile's rows: 16 pieces of 4 values per row, row-major
+        const int nval = min(64, f0 + nfun - fbase);
 #pragma unroll
-        for (int st = 0; st < KC / 16; ++st) {
-            if (st >= ns) break;
-            const uint32_t xv = *reinterpret_cast<const uint32_t *>(xs + (wv * 16 + r) * XS + st * 16 + kq);
-            half4_t ah[4], al[4];
-#pragma unroll
-            for (int fb = 0; fb < 4; ++fb) {
-                const int o = (fb * 16 + r) * AS + st * 16 + kq;
-                ah[fb] = *reinterpret_cast<const half4_t *>(hs + o);
-                al[fb] = *reinterpret_cast<const half4_t *>(ls + o);
-            }
-            const uint32_t b0 = xv & 255u, b1 = (xv >> 8) & 255u, b2 = (xv >> 16) & 255u, b3 = xv >> 24;
-            xmax = max(xmax, max(max(b0, b1), max(b2, b3)));
-            const half4_t xh = {(_Float16)(float)b0, (_Float16)(float)b1, (_Float16)(float)b2,
-                                (_Float16)(float)b3};
-#pragma unroll
-            for (int fb = 0; fb < 4; ++fb) {
-                acc_hi[fb] = __builtin_amdgcn_mfma_f32_16x16x16f16(xh, ah[fb], acc_hi[fb], 0, 0, 0);
-                acc_lo[fb] = __builtin_amdgcn_mfma_f32_16x16x16f16(xh, al[fb], acc_lo[fb], 0, 0, 0);
+        for (int i = 0; i < 4; ++i) {
+            const int e = tid + i * kBlock, row = e >> 4, pc = (e & 15) * 4;
+            const int64_t gr = rowb + row;
+            if (gr >= m || pc >= nval) continue;
+            int32_t *dst = out + gr * out_ld + (fbase - f0) + pc;
+            const int32_t *src = tile + row * kTileLd + pc;
+            if (vec && pc + 4 <= nval) {
+                *reinterpret_cast<int4 *>(dst) = *reinterpret_cast<const int4 *>(src);
+            } else {
+                for (int q = 0; q < 4 && pc + q < nval; ++q) dst[q] = src[q];
             }
         }
     }
-    xmax = max(xmax, (uint32_t)__shfl_xor((int)xmax, 16));
-    xmax = max(xmax, (uint32_t)__shfl_xor((int)xmax, 32));
-    float xm[4];
-    for (int j = 0; j < 4; ++j) xm[j] = (float)__shfl((int)xmax, (lane >> 4) * 4 + j);
-    // this lane's outputs: rows rl + j (j < 4), functions fbase + r + 16 fb
+    // outputs inside the guard band: the FP64 index-order value, stored over
+    // the tile's value (the lanes of a wave recompute side by side; at the
+    // end, no other registers are live).  The barrier orders every tile store
+    // of the workgroup before these; a device-scope fence is not needed and
+    // would write back the L2.
+    __syncthreads();
     const int64_t rl = row0 + (lane >> 4) * 4;
-    uint32_t pend = 0;
-#pragma unroll
-    for (int fb = 0; fb < 4; ++fb) {
-        const int f = fbase + fb * 16 + r;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t row = rl + j;
-            if (row >= m || f >= f0 + nfun) continue;
-            int32_t h;
-            if (accept_fp32(acc_hi[fb][j] + acc_lo[fb][j], bf[fb], iw, cw[fb] * xm[j], h))
-                out[row * out_ld + (f - f0)] = h;
-            else
-                pend |= 1u << (fb * 4 + j);
-        }
-    }
     unsigned long long nre = 0;
-    recompute_marked<uint8_t>(pend, x, rl, 1, dp, d, a32, b, fbase + r, f0, w, out, out_ld, nre);
+    while (marks) {
+        const int o = __ffsll(marks) - 1;
+        marks &= marks - 1ull;
+        const int j = o & 3, f = f0 + (blk0 + (o >> 4)) * 64 + ((o >> 2) & 3) * 16 + r;
+        out[(rl + j) * out_ld + (f - f0)] =
+            hash_exact<uint8_t>(x + (rl + j) * dp, a32 + (int64_t)f * dp, d, b[f], w);
+        ++nre;
+    }
     if (recomputed && nre)
         atomicAdd(recomputed + (blockIdx.y * gridDim.x + blockIdx.x) % kRecompSlots, nre);
 }
@@ -503,9 +560,14 @@ qw_status launch_hash(const qw_index *ix, const void *xpad, int64_t m, int32_t f
                 (const float *)xpad, m, ix->dp, ix->d, ix->a32.as<float>(), ix->b32.as<float>(),
                 f0, nfun, w, ix->gb_plain.as<double>(), out, out_ld, recomputed);
     } else if (ix->dtype == QW_U8 && ix->fast_f16) {
-        hash_mfma_f16_kernel<<<grid, kBlock, 0, s>>>(
+        // every function tile of a row block in one workgroup when the row
+        // blocks alone give two rounds of the GPU's three workgroups per CU
+        const int nblk = (int)ceil_div(nfun, 64);
+        const int bpw = grid.x >= 6u * (unsigned)ix->cus ? std::min(nblk, 4) : 1;  // marks: 4 x 16 bits
+        const dim3 g16(grid.x, (unsigned)ceil_div(nblk, bpw));
+        hash_mfma_f16_kernel<<<g16, kBlock, 0, s>>>(
             (const uint8_t *)xpad, m, ix->dp, ix->d, ix->a_hi.as<_Float16>(),
-            ix->a_lo.as<_Float16>(), ix->a32.as<float>(), ix->b32.as<float>(), f0, nfun, w,
+            ix->a_lo.as<_Float16>(), ix->a32.as<float>(), ix->b32.as<float>(), f0, nfun, bpw, w,
             ix->gb_fast.as<double>(), out, out_ld, recomputed);
     } else if (ix->dtype == QW_F32) {
         hash_mfma_f32_kernel<<<grid, kBlock, 0, s>>>(

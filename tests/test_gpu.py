@@ -100,6 +100,24 @@ def test_hash_several_k_chunks(form, dtype, d):
         assert np.array_equal(h.cpu().numpy(), oracle.hash_points(x, p.a, p.b(), p.w))
 
 
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("L,k,d", [(19, 7, 40), (20, 8, 128), (64, 2, 24)])
+def test_hash_many_rows_several_function_tiles(form, L, k, d):
+    """Enough rows that the FP16 matrix-core kernel gives each workgroup several
+    64-function tiles of its rows (ragged last row block; 133, 160 and 128
+    functions per row: a ragged last tile, and row pitches that are and are
+    not a multiple of four values).  Parameters on bucket boundaries, so some
+    outputs take the FP64 recomputation in every tile."""
+    a, b, w = synth.boundary_params(31, L, k, d, w=4.0)
+    rng = np.random.default_rng(32)
+    x = rng.integers(0, 256, size=(100_003, d), dtype=np.uint8)
+    ix = build(x[:256], a, b, w, form)  # a small index: keys stay within 128 bits
+    h, rec = ix.hash(dev(x), form)
+    want = oracle.hash_points(x, a, b, w)
+    assert np.array_equal(h.cpu().numpy(), want)
+    assert rec > 0
+
+
 # ---------------------------------------------------------------- candidates
 
 @pytest.mark.parametrize("w", [400.0, 1200.0])
