@@ -173,6 +173,9 @@ def main():
                     help="skip the out-of-core split sweeps")
     ap.add_argument("--profile-ooc", type=int, default=None, metavar="PERCENT",
                     help="with --profile: only --steps out-of-core passes at this index share")
+    ap.add_argument("--profile-count", action="store_true",
+                    help="with --profile: only --steps collision-counting calls on the 64-layer "
+                         "index of the counting leg")
     ap.add_argument("--profile", action="store_true",
                     help="only the fast-form timed loop (for rocprofv3 runs): no tuning unless "
                          "--tune-cache names an existing file")
@@ -376,6 +379,20 @@ def main():
             f"{(time.time() - t1) * 1e3 / args.steps:.1f} ms per pass, "
             f"index {so['ooc_index_bytes'] / 1e6:.1f} MB, data {so['ooc_data_bytes'] / 1e6:.1f} MB, "
             f"batches {so['ooc_batches']}, splits {so['ooc_splits']}")
+        return
+
+    if args.profile_count:
+        # the collision-counting leg's calls only (for rocprofv3 runs)
+        theta = args.count_theta or 3
+        cL, cw = 64, 2.5 * spec["w"]
+        cp = synth.hash_params(2100 + args.config, cL, wl.params.k, wl.d, cw)
+        cix = lib.Index(data_d, torch.from_numpy(cp.a).to(dev), torch.from_numpy(cp.b()).to(dev),
+                        cw, form=lib.QW_FORM_FAST)
+        cix.set_counting(theta, args.count_v)
+        ms = timed(cix, lib.make_opts(form=lib.QW_FORM_FAST, graph=0), args.steps, args.warmup)
+        log(f"[bench] profile counting: theta {theta}, v {args.count_v}, L {cL}, w {cw}: "
+            f"{ms:.3f} ms/step")
+        cix.close()
         return
 
     # ---- learned count model, trained on the engine's own features

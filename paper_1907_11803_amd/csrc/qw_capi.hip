@@ -33,7 +33,7 @@ enum {
 };
 // u32: overflow-queue lengths per class (queue i holds queries that overflowed
 // class i-1), fallback queue, misc, then kXcd work counters per class
-enum { W_CLSDONE = 0, W_TOPK2 = 1, W_WORK = 2 /* .. 15: unused */, W_QCNT = 16 /* .. 32 */, W_SIMPLE = 33, W_MAX = 34,
+enum { W_CLSDONE = 0, W_TOPK2 = 1, W_WORK = 2 /* .. 5: counting split counts; .. 15 unused */, W_QCNT = 16 /* .. 32 */, W_SIMPLE = 33, W_MAX = 34,
        W_DUMMY = 35, W_QMERGED = 36, W_FB = 44, W_FBWORK = 45, W_STAGE = 46, W_XWORK = 48,
        kC32 = W_XWORK + kXcd * (kMaxClasses + 1) };
 constexpr int kQueueMerged = kMaxClasses + 1;  // overflow queue of the merged launch
@@ -335,16 +335,24 @@ qw_status count_query(qw_index *ix, int64_t Q, int K, hipStream_t s, int32_t *ou
 {
     if (ix->nprobe != 1 || (int64_t)K + ix->count_extra > kMaxTopK || ix->n >= kCountMaxN)
         return QW_EUNSUPPORTED;
-    uint32_t *mx = c32(ix) + W_MAX;
-    QW_TRY(launch_fill_u32(mx, 0u, 1, s));
-    QW_TRY(launch_max_bucket_sum(ix->ws.bsize.as<uint32_t>(), Q, ix->L, mx, s));
-    uint32_t maxsum = 0;
-    QW_HIP(hipMemcpyAsync(&maxsum, mx, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    // the queries split by their listed ids (the smaller sets let more
+    // workgroups share a CU); both lists' sizes and largest sums read back
+    uint32_t *cnt = c32(ix) + W_WORK;  // n0, n1, max0, max1
+    int32_t *list0 = ix->ws.order.as<int32_t>(), *list1 = list0 + Q;
+    QW_TRY(launch_fill_u32(cnt, 0u, 4, s));
+    QW_TRY(launch_count_split(ix->ws.bsize.as<uint32_t>(), Q, ix->L, kCountSmallListed, list0, list1,
+                              cnt, s));
+    uint32_t h[4] = {0, 0, 0, 0};
+    QW_HIP(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, s));
     QW_HIP(hipStreamSynchronize(s));
     if (ev_sched) QW_HIP(hipEventRecord(ev_sched, s));
-    if (maxsum > kCountMaxListed) return QW_EUNSUPPORTED;
-    int cap = 8;
-    while ((3ull << cap) < 4ull * maxsum) ++cap;  // load factor <= 3/4
+    if (h[0] + h[1] != (uint64_t)Q || h[2] > kCountSmallListed) return QW_EINTERNAL;
+    if (h[3] > kCountMaxListed) return QW_EUNSUPPORTED;
+    auto cap_for = [](uint32_t listed) {
+        int c = 8;
+        while ((3ull << c) < 4ull * listed) ++c;  // load factor <= 3/4
+        return c;
+    };
     CountArgs a;
     std::memset(&a, 0, sizeof(a));
     a.bstart = ix->ws.bstart.as<uint32_t>();
@@ -358,14 +366,30 @@ qw_status count_query(qw_index *ix, int64_t Q, int K, hipStream_t s, int32_t *ou
     a.ncap = (K + ix->count_extra + 1) & ~1;
     a.dtype = ix->dtype;
     a.dp = ix->dp;
-    a.cap_log2 = (uint32_t)cap;
     a.data = ix->data.p;
     a.queries = ix->ws.qrows;
     a.out_ids = out_ids;
     a.out_dist = out_dist;
     a.out_counts = ix->ws.ucount.as<uint32_t>();
-    if (cap > kCountMaxSetLog2 || count_lds_bytes(cap, a.ncap) > ix->lds_max) return QW_EUNSUPPORTED;
-    return launch_count(a, Q, s);
+    // the radix selects skip bytes no value reaches: ids are below n; a uint8
+    // squared distance is at most dp * 255^2; a float key's high word is that
+    // of a non-negative FP64 value (below 2^31)
+    auto top_byte = [](uint64_t bound) {  // 8 * floor(log2(bound) / 8)
+        int b = 0;
+        while (b < 24 && (bound >> (b + 8)) != 0) b += 8;
+        return b;
+    };
+    a.id_top = top_byte((uint64_t)std::max<int64_t>(1, ix->n - 1));
+    a.key_top = ix->dtype == QW_U8 ? top_byte((uint64_t)ix->dp * 65025ull) : 24;
+    const int cap0 = cap_for(h[2]), cap1 = cap_for(h[3]);
+    for (int c : {cap0, cap1})  // both checked before either writes an output
+        if (c > kCountMaxSetLog2 || count_lds_bytes(c, a.ncap) > ix->lds_max) return QW_EUNSUPPORTED;
+    a.cap_log2 = (uint32_t)cap0;
+    a.qlist = list0;
+    QW_TRY(launch_count(a, h[0], false, s));
+    a.cap_log2 = (uint32_t)cap1;
+    a.qlist = list1;
+    return launch_count(a, h[1], true, s);
 }
 
 // Out-of-core answer of Q probed queries: one hash-set size for all queries

@@ -8,7 +8,7 @@
 // One workgroup per query, all state in LDS:
 //   1. the query's L bucket lists go into an open-addressing set of 2^c slots,
 //      each holding an id (below 2^25 - 1) and its count (<= L <= 64) in one
-//      word, so two workgroups fit in a CU's LDS;
+//      word;
 //   2. a histogram of the counts >= theta gives the count c* at which the
 //      ranking crosses K + v: every id counted above c* is kept, and of the
 //      ids counted exactly c* the `need` smallest, found by a 4-pass radix
@@ -16,6 +16,11 @@
 //   3. the kept ids are verified (uint8: exact integer; float: the FP64
 //      rounded sequence of the plain path) and ranked by (distance, id) by
 //      counting, for each one, the kept ids before it.
+// Queries are split by their listed ids first: those with at most
+// kCountSmallListed (sets of at most 2^13 slots, 37 KB of LDS) run in
+// 512-thread workgroups, four to a CU; the rest in 1024-thread workgroups
+// with sets of up to 2^14 slots, two to a CU.  The kept ids' keys and the
+// survivors of the final selection reuse the set's LDS once it is read.
 #include "qw_dedup.h"
 #include "qw_dist.h"
 #include "qw_exact.h"
@@ -25,12 +30,16 @@ namespace qw {
 namespace {
 
 constexpr int kHistBins = kMaxL + 2;
-// Threads per workgroup (the largest): two workgroups share a CU's LDS, so
-// each brings sixteen waves to hide the latency of its LDS atomics and
-// dependent loads (measured: 256 threads 1.05 ms, 512 0.72 ms, 1024 0.61 ms
-// for 10K queries of 4,784 listed ids each).
-constexpr int kCountBlock = 1024;
+// Threads per workgroup: a query's phases are short and each waits on LDS
+// atomics or dependent loads, so a CU needs several queries in flight.
+// Two 1024-thread workgroups fill a CU's waves; four 512-thread ones do too
+// where their sets leave room (measured on 10K queries of 4,784 listed ids
+// each, two workgroups per CU: 256 threads 1.05 ms, 512 0.72 ms, 1024 0.61 ms).
+constexpr int kCountBlockSmall = 512, kCountBlockLarge = 1024;
 
+// The set (tab) is read until the kept ids are compacted into cid; the keys
+// of the kept ids (ckey) and the survivors of the final selection (surv) are
+// written after that, in the set's bytes.
 struct CountLayout {
     size_t tab, cid, ckey, surv, hist, radix, scal, total;
 };
@@ -38,12 +47,12 @@ struct CountLayout {
 __host__ __device__ inline CountLayout count_layout(int cap_log2, int ncap)
 {
     CountLayout o;
-    const size_t cap = size_t(1) << cap_log2;
+    const size_t set = size_t(4) << cap_log2, keys = size_t(ncap) * 12;
     o.tab = 0;
-    o.cid = o.tab + cap * 4;
-    o.ckey = o.cid + size_t(ncap) * 4;        // ncap even: 8-byte aligned
-    o.surv = o.ckey + size_t(ncap) * 8;
-    o.hist = o.surv + size_t(ncap) * 4;
+    o.ckey = 0;                               // 8-byte keys over the set
+    o.surv = size_t(ncap) * 8;                // then the survivors (ncap even)
+    o.cid = set > keys ? set : keys;
+    o.hist = o.cid + size_t(ncap) * 4;
     o.radix = o.hist + kHistBins * 4;
     o.scal = o.radix + 256 * 4;
     o.total = o.scal + 8 * 4;
@@ -71,12 +80,13 @@ __device__ inline uint32_t slot_count(uint32_t w) { return w >> kCountShift; }
 
 // Whole workgroup.  Among the items i < nitems with pred(i), the need-th
 // smallest of the 32-bit values val(i) (1 <= need <= that many items), one
-// byte per pass, most significant first: each pass counts the values that
+// byte per pass, most significant first from bit `top` + 7 (every value is
+// below 2^(top + 8); top a multiple of 8): each pass counts the values that
 // share the bytes chosen so far in 256 bins, and the first wave finds the bin
 // in which the count reaches the rank still wanted.
-template <typename Val, typename Pred>
+template <int B, typename Val, typename Pred>
 __device__ inline uint32_t block_select(uint32_t nitems, uint32_t need, Val val, Pred pred,
-                                        uint32_t *radix, uint32_t *scal)
+                                        uint32_t *radix, uint32_t *scal, int top)
 {
     const int tid = threadIdx.x;
     __syncthreads();  // earlier readers of scal are done
@@ -84,12 +94,12 @@ __device__ inline uint32_t block_select(uint32_t nitems, uint32_t need, Val val,
         scal[SC_PREFIX] = 0u;
         scal[SC_REM] = need;
     }
-    for (int shift = 24; shift >= 0; shift -= 8) {
-        for (int b = tid; b < 256; b += kCountBlock) radix[b] = 0u;
+    for (int shift = top; shift >= 0; shift -= 8) {
+        for (int b = tid; b < 256; b += B) radix[b] = 0u;
         __syncthreads();
         const uint32_t prefix = scal[SC_PREFIX];
-        const uint32_t hmask = shift == 24 ? 0u : (0xFFFFFFFFu << (shift + 8));
-        for (uint32_t i = tid; i < nitems; i += kCountBlock)
+        const uint32_t hmask = shift == top ? 0u : (0xFFFFFFFFu << (shift + 8));
+        for (uint32_t i = tid; i < nitems; i += B)
             if (pred(i)) {
                 const uint32_t v = val(i);
                 if ((v & hmask) == prefix) atomicAdd(&radix[(v >> shift) & 255u], 1u);
@@ -125,8 +135,8 @@ __device__ inline uint32_t block_select(uint32_t nitems, uint32_t need, Val val,
     return scal[SC_PREFIX];
 }
 
-template <int DT>
-__global__ __launch_bounds__(kCountBlock) void count_kernel(const CountArgs A)
+template <int DT, int B>
+__global__ __launch_bounds__(B) void count_kernel(const CountArgs A)
 {
     extern __shared__ __align__(16) uint8_t smem[];
     const CountLayout lay = count_layout((int)A.cap_log2, A.ncap);
@@ -140,7 +150,7 @@ __global__ __launch_bounds__(kCountBlock) void count_kernel(const CountArgs A)
 
     __shared__ uint32_t lpref[kMaxL + 1], lstart[kMaxL];
     const int tid = threadIdx.x;
-    const int64_t q = blockIdx.x;
+    const int64_t q = A.qlist ? (int64_t)A.qlist[blockIdx.x] : (int64_t)blockIdx.x;
 
     // list offsets: an exclusive prefix of the L list sizes over the first wave
     if (tid < 64) {
@@ -161,8 +171,8 @@ __global__ __launch_bounds__(kCountBlock) void count_kernel(const CountArgs A)
     while ((3u << c) < 4u * total && c < (int)A.cap_log2) ++c;
     const uint32_t cap = 1u << c, mask = cap - 1u;
 
-    for (uint32_t s = tid; s < cap; s += kCountBlock) tab[s] = 0u;
-    for (int s = tid; s < kHistBins; s += kCountBlock) hist[s] = 0u;
+    for (uint32_t s = tid; s < cap; s += B) tab[s] = 0u;
+    for (int s = tid; s < kHistBins; s += B) hist[s] = 0u;
     if (tid == 0) scal[SC_NCAND] = 0u;
     __syncthreads();
 
@@ -170,11 +180,11 @@ __global__ __launch_bounds__(kCountBlock) void count_kernel(const CountArgs A)
     // layer); kCountLoads positions of the concatenated lists per thread are
     // located (binary search over the prefix) and loaded together
     constexpr int kCountLoads = 4;
-    for (uint32_t base = 0; base < total; base += kCountLoads * kCountBlock) {
+    for (uint32_t base = 0; base < total; base += kCountLoads * B) {
         uint32_t id[kCountLoads];
 #pragma unroll
         for (int r = 0; r < kCountLoads; ++r) {
-            const uint32_t pos = base + (uint32_t)(r * kCountBlock + tid);
+            const uint32_t pos = base + (uint32_t)(r * B + tid);
             id[r] = kEmpty;
             if (pos < total) {
                 int lo = 0;  // largest layer with lpref <= pos (its list holds pos)
@@ -208,7 +218,7 @@ __global__ __launch_bounds__(kCountBlock) void count_kernel(const CountArgs A)
     __syncthreads();
 
     // 2. counts >= theta, the crossing count c* and how many ids it contributes
-    for (uint32_t s = tid; s < cap; s += kCountBlock)
+    for (uint32_t s = tid; s < cap; s += B)
         if (tab[s] != 0u) {
             const uint32_t k = slot_count(tab[s]);
             if (k >= (uint32_t)A.theta) atomicAdd(&hist[k], 1u);
@@ -235,25 +245,30 @@ __global__ __launch_bounds__(kCountBlock) void count_kernel(const CountArgs A)
     const uint32_t cstar = scal[SC_CSTAR];
     uint32_t last = 0xFFFFFFFFu;  // largest id kept among those counted c*
     if (scal[SC_NEED] < hist[cstar])  // the need-th smallest id counted exactly c*
-        last = block_select(
+        last = block_select<B>(
             cap, scal[SC_NEED], [&](uint32_t s) { return slot_id(tab[s]); },
-            [&](uint32_t s) { return tab[s] != 0u && slot_count(tab[s]) == cstar; }, radix, scal);
+            [&](uint32_t s) { return tab[s] != 0u && slot_count(tab[s]) == cstar; }, radix, scal,
+            A.id_top);
 
     // kept: counted above c*, or counted c* with an id up to `last`
-    for (uint32_t s = tid; s < cap; s += kCountBlock) {
-        const uint32_t w = tab[s];
-        if (w == 0u) continue;
+    // (one LDS atomic per wave and round, not one per kept id on one address)
+    for (uint32_t s0 = 0; s0 < cap; s0 += B) {
+        const uint32_t s = s0 + (uint32_t)tid;
+        const uint32_t w = s < cap ? tab[s] : 0u;
         const uint32_t id = slot_id(w), k = slot_count(w);
-        if (k > cstar || (k == cstar && id <= last)) {
-            const uint32_t at = atomicAdd(&scal[SC_NCAND], 1u);
-            cid[at] = id;
-        }
+        const bool keep = w != 0u && (k > cstar || (k == cstar && id <= last));
+        const unsigned long long m = __ballot(keep);
+        const int lane = tid & 63;
+        uint32_t at = 0;
+        if (lane == 0 && m) at = atomicAdd(&scal[SC_NCAND], (uint32_t)__popcll(m));
+        at = (uint32_t)__shfl((int)at, 0);
+        if (keep) cid[at + (uint32_t)__popcll(m & (lane ? (~0ull >> (64 - lane)) : 0ull))] = id;
     }
     __syncthreads();
     const int nc = (int)scal[SC_NCAND];
 
     // 3. verify the kept ids
-    for (int i = tid; i < nc; i += kCountBlock) {
+    for (int i = tid; i < nc; i += B) {
         const uint32_t id = cid[i];
         if constexpr (DT == QW_U8) {
             const uint4 *x = reinterpret_cast<const uint4 *>(static_cast<const uint8_t *>(A.data) +
@@ -284,18 +299,18 @@ __global__ __launch_bounds__(kCountBlock) void count_kernel(const CountArgs A)
     // does): a key with a larger high word is not in the top K
     uint32_t hbound = 0xFFFFFFFFu;
     if (nc > A.K)
-        hbound = block_select(
+        hbound = block_select<B>(
             (uint32_t)nc, (uint32_t)A.K, [&](uint32_t i) { return (uint32_t)(ckey[i] >> 32); },
-            [&](uint32_t) { return true; }, radix, scal);
+            [&](uint32_t) { return true; }, radix, scal, A.key_top);
     if (tid == 0) scal[SC_NSURV] = 0u;
     __syncthreads();
-    for (int i = tid; i < nc; i += kCountBlock)
+    for (int i = tid; i < nc; i += B)
         if ((uint32_t)(ckey[i] >> 32) <= hbound) surv[atomicAdd(&scal[SC_NSURV], 1u)] = (uint32_t)i;
     __syncthreads();
     const int ns = (int)scal[SC_NSURV];
     // rank of each survivor under (distance, id) among the survivors (at least
     // K of them; every key of the top K is one); the keys are distinct
-    for (int a = tid; a < ns; a += kCountBlock) {
+    for (int a = tid; a < ns; a += B) {
         const uint32_t i = surv[a];
         const uint64_t ki = ckey[i];
         const uint32_t ii = cid[i];
@@ -318,7 +333,7 @@ __global__ __launch_bounds__(kCountBlock) void count_kernel(const CountArgs A)
                 reinterpret_cast<float *>(A.out_dist)[o] = (float)__longlong_as_double((long long)ki);
         }
     }
-    for (int r = nc + tid; r < A.K; r += kCountBlock) {
+    for (int r = nc + tid; r < A.K; r += B) {
         const int64_t o = q * A.K + r;
         A.out_ids[o] = -1;
         if constexpr (DT == QW_U8)
@@ -333,18 +348,84 @@ __global__ __launch_bounds__(kCountBlock) void count_kernel(const CountArgs A)
 
 size_t count_lds_bytes(int cap_log2, int ncap) { return count_layout(cap_log2, ncap).total; }
 
-qw_status launch_count(const CountArgs &a, int64_t Q, hipStream_t s)
+// Per query, the sum of its L list lengths: class 0 when at most `limit`,
+// else class 1.  Appends the query to its class's list (one atomic per class
+// per workgroup; the lists' order is immaterial) and keeps each class's
+// largest sum.  cnt: [n0, n1, max0, max1], zeroed by the caller.
+__global__ __launch_bounds__(kBlock) void count_split_kernel(const uint32_t *__restrict__ bsize,
+                                                             int64_t Q, int32_t L, uint32_t limit,
+                                                             int32_t *__restrict__ list0,
+                                                             int32_t *__restrict__ list1,
+                                                             uint32_t *cnt)
+{
+    __shared__ uint32_t wc[2][kBlock / 64], wm[2][kBlock / 64], base[2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t q = (int64_t)blockIdx.x * kBlock + tid;
+    uint64_t t = 0;
+    if (q < Q)
+        for (int32_t l = 0; l < L; ++l) t += bsize[q * L + l];
+    const uint32_t tot = (uint32_t)min(t, (uint64_t)0xFFFFFFFFu);
+    const bool c1 = q < Q && tot > limit, c0 = q < Q && !c1;
+    const unsigned long long b0 = __ballot(c0), b1 = __ballot(c1);
+    const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    uint32_t m0 = c0 ? tot : 0u, m1 = c1 ? tot : 0u;
+    for (int off = 32; off > 0; off >>= 1) {
+        m0 = max(m0, (uint32_t)__shfl_xor((int)m0, off));
+        m1 = max(m1, (uint32_t)__shfl_xor((int)m1, off));
+    }
+    if (lane == 0) {
+        wc[0][wave] = (uint32_t)__popcll(b0);
+        wc[1][wave] = (uint32_t)__popcll(b1);
+        wm[0][wave] = m0;
+        wm[1][wave] = m1;
+    }
+    __syncthreads();
+    if (tid < 2) {
+        uint32_t n = 0, m = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            n += wc[tid][w];
+            m = max(m, wm[tid][w]);
+        }
+        base[tid] = n ? atomicAdd(&cnt[tid], n) : 0u;
+        if (m) atomicMax(&cnt[2 + tid], m);
+    }
+    __syncthreads();
+    uint32_t o0 = base[0], o1 = base[1];
+    for (int w = 0; w < wave; ++w) {
+        o0 += wc[0][w];
+        o1 += wc[1][w];
+    }
+    if (c0) list0[o0 + (uint32_t)__popcll(b0 & lt)] = (int32_t)q;
+    if (c1) list1[o1 + (uint32_t)__popcll(b1 & lt)] = (int32_t)q;
+}
+
+qw_status launch_count_split(const uint32_t *bsize, int64_t Q, int32_t L, uint32_t limit,
+                             int32_t *list0, int32_t *list1, uint32_t *cnt, hipStream_t s)
 {
     if (Q <= 0) return QW_OK;
+    if (Q > 0x7FFFFFFF) return QW_EINTERNAL;
+    count_split_kernel<<<(unsigned)ceil_div(Q, kBlock), kBlock, 0, s>>>(bsize, Q, L, limit, list0,
+                                                                       list1, cnt);
+    QW_HIP(hipGetLastError());
+    return QW_OK;
+}
+
+qw_status launch_count(const CountArgs &a, int64_t grid, bool large, hipStream_t s)
+{
+    if (grid <= 0) return QW_OK;
     if (a.L < 1 || a.L > kMaxL || a.theta < 1 || a.theta > a.L || a.K < 1 || a.extra < 0 ||
         a.K + a.extra > a.ncap || (a.ncap & 1) || a.cap_log2 < 4 || a.cap_log2 > 16 ||
-        Q > 0x7FFFFFFF)
+        grid > 0x7FFFFFFF)
         return QW_EINTERNAL;
     const size_t lds = count_lds_bytes((int)a.cap_log2, a.ncap);
-    if (a.dtype == QW_U8)
-        count_kernel<QW_U8><<<(unsigned)Q, kCountBlock, lds, s>>>(a);
-    else
-        count_kernel<QW_F32><<<(unsigned)Q, kCountBlock, lds, s>>>(a);
+    const unsigned g = (unsigned)grid;
+    if (a.dtype == QW_U8) {
+        if (large) count_kernel<QW_U8, kCountBlockLarge><<<g, kCountBlockLarge, lds, s>>>(a);
+        else count_kernel<QW_U8, kCountBlockSmall><<<g, kCountBlockSmall, lds, s>>>(a);
+    } else {
+        if (large) count_kernel<QW_F32, kCountBlockLarge><<<g, kCountBlockLarge, lds, s>>>(a);
+        else count_kernel<QW_F32, kCountBlockSmall><<<g, kCountBlockSmall, lds, s>>>(a);
+    }
     QW_HIP(hipGetLastError());
     return QW_OK;
 }

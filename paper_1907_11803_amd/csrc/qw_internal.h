@@ -395,12 +395,22 @@ struct CountArgs {
     int32_t *out_ids;                // [Q][K]
     void *out_dist;                  // [Q][K] int32 (uint8 data) or float
     uint32_t *out_counts;            // nullable: [Q] ids verified
+    const int32_t *qlist;            // nullable: workgroup b answers query qlist[b] (else b)
+    int32_t id_top, key_top;         // radix selects start at these bits (ids < 2^(id_top + 8),
+                                     // distance keys' high words < 2^(key_top + 8))
 };
 size_t count_lds_bytes(int cap_log2, int ncap);
-qw_status launch_count(const CountArgs &a, int64_t Q, hipStream_t s);
+// Splits the Q queries by the sum of their L list lengths (<= limit: list0,
+// else list1); cnt (zeroed, device): n0, n1, the largest sum of each list.
+qw_status launch_count_split(const uint32_t *bsize, int64_t Q, int32_t L, uint32_t limit,
+                             int32_t *list0, int32_t *list1, uint32_t *cnt, hipStream_t s);
+// `grid` workgroups of 512 threads (large: 1024).
+qw_status launch_count(const CountArgs &a, int64_t grid, bool large, hipStream_t s);
 // Largest sum of one query's L list lengths the counting set takes (3/4 of
-// the largest set, 2^14 slots).
+// the largest set, 2^14 slots); queries up to kCountSmallListed (3/4 of 2^13)
+// run in the smaller workgroups.
 constexpr uint32_t kCountMaxListed = 12288;
+constexpr uint32_t kCountSmallListed = 6144;
 constexpr int kCountMaxSetLog2 = 14;
 // Ids share a set word with their count (7 bits), so counting needs n below this.
 constexpr int64_t kCountMaxN = (int64_t(1) << 25) - 1;

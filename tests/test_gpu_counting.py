@@ -87,6 +87,24 @@ def test_counting_float():
     run_case(wl, 10.0, wl.K, [(2, 50), (1, 5), (4, 0)], False)
 
 
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_counting_small_and_large_workgroups(dtype):
+    """Listed-id totals on both sides of 6,144 (3/4 of a 2^13-slot set): the
+    smaller queries run in 512-thread workgroups, the larger ones in
+    1024-thread workgroups with a 2^14-slot set; no answer may depend on
+    which."""
+    if dtype == "u8":
+        wl, w = synth.make_config(1, L=32, k=1, w=55.0), 55.0
+    else:
+        wl, w = synth.make_config(3, n=12000, Q=60, ncomp=30, L=32, k=1, w=0.5), 0.5
+    p = wl.params
+    ix = lib.Index(dev(wl.data), dev(p.a), dev(p.b(w)), w)
+    tot = ix.bucket_sizes(dev(wl.queries)).to(torch.int64).sum(1).cpu().numpy()
+    ix.close()
+    assert (tot <= 6144).any() and (tot > 6144).any() and (tot <= 12288).all()
+    run_case(wl, w, wl.K, [(2, 50), (3, 0), (1, 1000)], dtype == "u8")
+
+
 def test_counting_limits_leave_outputs_untouched():
     """More than 12288 listed ids for some query (48 single-function layers at
     w = 60 list up to 12328), neighbour probing, K + v above 1024: the call
