@@ -238,7 +238,8 @@ qw_status qw_query_workload(qw_index *ix, const void *queries, int64_t Q, int32_
  * allocates nothing -- no hipMalloc, no hipFree -- and grows no buffer of the
  * index.  Limits: the workspace of Q queries, about
  * Q * (4*L*k + 8*lists + 8 [+ 4*L with probing] [+ T*L with
- * query-directed probing] [+ d*elem when padded]) bytes plus alignment, must
+ * query-directed probing] [+ 8 with collision counting] [+ d*elem when
+ * padded]) bytes plus alignment, must
  * fit 32 MiB, and each query's hash set must fit on-chip memory; otherwise
  * QW_EUNSUPPORTED, with the outputs untouched.
  * Every call on one GPU shares that GPU's array and overwrites it: calls that

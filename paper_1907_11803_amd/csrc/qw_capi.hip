@@ -338,6 +338,7 @@ qw_status count_query(qw_index *ix, int64_t Q, int K, hipStream_t s, int32_t *ou
     // the queries split by their listed ids (the smaller sets let more
     // workgroups share a CU); both lists' sizes and largest sums read back
     uint32_t *cnt = c32(ix) + W_WORK;  // n0, n1, max0, max1
+    if (!ix->ws.order.p || ix->ws.order.bytes < sizeof(int32_t) * 2 * (size_t)Q) return QW_EINTERNAL;
     int32_t *list0 = ix->ws.order.as<int32_t>(), *list1 = list0 + Q;
     QW_TRY(launch_fill_u32(cnt, 0u, 4, s));
     QW_TRY(launch_count_split(ix->ws.bsize.as<uint32_t>(), Q, ix->L, kCountSmallListed, list0, list1,
@@ -798,6 +799,7 @@ bool carve_plain_ws(const qw_index *ix, int64_t Q, bool pad, unsigned char *base
     if (ix->probe_mode == 2) take(w.moves, q * (size_t)ix->L * (size_t)(ix->nprobe - 1));
     take(w.ucount, sizeof(uint32_t) * q);
     take(w.ovf, sizeof(int32_t) * q);
+    if (ix->count_theta > 0) take(w.order, sizeof(int32_t) * 2 * q);  // counting's two query lists
     return ok;
 }
 
