@@ -408,14 +408,52 @@ __global__ __launch_bounds__(kBlock, 3) void hash_mfma_f16_kernel(
         }
     }
     // outputs inside the guard band: the FP64 index-order value, stored over
-    // the tile's value (the lanes of a wave recompute side by side; at the
-    // end, no other registers are live).  The barrier orders every tile store
-    // of the workgroup before these; a device-scope fence is not needed and
-    // would write back the L2.
+    // the tile's value.  The workgroup's marks are pooled in LDS (the a_lo
+    // staging buffer, free now) and dealt one per thread, so the recomputes
+    // of a workgroup take one FP64 sequence's latency rather than one per mark
+    // of its busiest lane; when they exceed the pool, each lane recomputes its
+    // own.  At the end no other registers are live.  The barriers order every
+    // tile store of the workgroup before these; a device-scope fence is not
+    // needed and would write back the L2.
+    constexpr uint32_t kPool = sizeof(ls) / sizeof(uint32_t);
+    uint32_t *pool = reinterpret_cast<uint32_t *>(ls);  // (tile row << 8) | function of the workgroup
+    __shared__ uint32_t wtot[kBlock / 64];
+    const uint32_t cnt = (uint32_t)__popcll(marks);
+    uint32_t incl = cnt;  // this lane's end within its wave's marks
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_up((int)incl, off);
+        if (lane >= off) incl += t;
+    }
+    if (lane == 63) wtot[wv] = incl;
     __syncthreads();
-    const int64_t rl = row0 + (lane >> 4) * 4;
+    uint32_t base = 0, total = 0;
+    for (int i = 0; i < kBlock / 64; ++i) {
+        const uint32_t t = wtot[i];
+        base += i < wv ? t : 0u;
+        total += t;
+    }
+    const bool pooled = total <= kPool;  // the same in every thread
+    const int tr = wv * 16 + (lane >> 4) * 4;
+    if (pooled) {
+        uint32_t e = base + incl - cnt;
+        while (marks) {
+            const int o = __ffsll(marks) - 1;
+            marks &= marks - 1ull;
+            pool[e++] = (uint32_t)(tr + (o & 3)) << 8 | (uint32_t)((o >> 4) * 64 + ((o >> 2) & 3) * 16 + r);
+        }
+    }
+    __syncthreads();
     unsigned long long nre = 0;
-    while (marks) {
+    const uint32_t np = pooled ? total : 0u;
+    for (uint32_t i = tid; i < np; i += kBlock) {
+        const uint32_t v = pool[i];
+        const int64_t row = rowb + (v >> 8);
+        const int f = f0 + blk0 * 64 + (int)(v & 255u);
+        out[row * out_ld + (f - f0)] = hash_exact<uint8_t>(x + row * dp, a32 + (int64_t)f * dp, d, b[f], w);
+        ++nre;
+    }
+    const int64_t rl = row0 + (lane >> 4) * 4;
+    while (marks) {  // not pooled: more marks than the pool holds
         const int o = __ffsll(marks) - 1;
         marks &= marks - 1ull;
         const int j = o & 3, f = f0 + (blk0 + (o >> 4)) * 64 + ((o >> 2) & 3) * 16 + r;
