@@ -248,8 +248,15 @@ const uint32_t *layer_mh(qw_index *ix)
 // stage rows -> hash -> probe for Q queries (counters must already be cleared);
 // feats (nullable) receives the count-model inputs log(1 + s_{q,l}) (s: the
 // layer's size), bmh (nullable) the buckets' min-hashes
+// Words of the counters buffer (zeroed at the start of every call).
+constexpr int64_t kCounterWords = (int64_t)(sizeof(unsigned long long) * kC64 + sizeof(uint32_t) * kC32) / 4;
+
+// clear_in_moves: the caller has not zeroed the counters; the query-directed
+// move kernel, the first kernel of this path to run, zeroes them (the fast
+// form with query-directed probing only).
 qw_status front(qw_index *ix, const void *queries, int64_t Q, int form, hipStream_t s,
-                hipEvent_t *ev = nullptr, float *feats = nullptr, uint32_t *bmh = nullptr)
+                hipEvent_t *ev = nullptr, float *feats = nullptr, uint32_t *bmh = nullptr,
+                bool clear_in_moves = false)
 {
     QW_TRY(stage_query_rows(ix, queries, Q, s));
     const bool probed = ix->nprobe > 1;
@@ -259,13 +266,16 @@ qw_status front(qw_index *ix, const void *queries, int64_t Q, int form, hipStrea
     // projections, whose floors are the exact hash values: the fast form
     // takes them from there and runs no other hashing
     const bool moves_hash = ix->probe_mode == 2 && form == QW_FORM_FAST;
+    if (clear_in_moves && !moves_hash) return QW_EINTERNAL;
     if (!moves_hash)
         QW_TRY(launch_hash(ix, ix->ws.qrows, Q, 0, ix->nf, form, ix->ws.h.as<int32_t>(), ix->nf,
                            c64(ix) + C_RECOMP, s));
     const uint8_t *moves = nullptr;
     if (ix->probe_mode == 2) {
         QW_TRY(launch_probe_moves(ix, ix->ws.qrows, Q, ix->ws.moves.as<uint8_t>(),
-                                  moves_hash ? ix->ws.h.as<int32_t>() : nullptr, s));
+                                  moves_hash ? ix->ws.h.as<int32_t>() : nullptr, s,
+                                  clear_in_moves ? ix->ws.counters.as<uint32_t>() : nullptr,
+                                  clear_in_moves ? (int32_t)kCounterWords : 0));
         moves = ix->ws.moves.as<uint8_t>();
     }
     if (ev) QW_HIP(hipEventRecord(ev[1], s));
@@ -276,8 +286,7 @@ qw_status front(qw_index *ix, const void *queries, int64_t Q, int form, hipStrea
 
 qw_status clear_counters(qw_index *ix, hipStream_t s)
 {
-    const int64_t words = (int64_t)(sizeof(unsigned long long) * kC64 + sizeof(uint32_t) * kC32) / 4;
-    return launch_fill_u32(ix->ws.counters.as<uint32_t>(), 0u, words, s);
+    return launch_fill_u32(ix->ws.counters.as<uint32_t>(), 0u, kCounterWords, s);
 }
 
 // One hash-set size for all queries (from the largest bound), one workgroup per
@@ -438,7 +447,10 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
 {
     Workspace &w = ix->ws;
     if (ev) QW_HIP(hipEventRecord(ev[0], s));
-    QW_TRY(clear_counters(ix, s));
+    // with query-directed probing the move kernel runs first and zeroes the
+    // counters itself (one launch fewer per call)
+    const bool clear_in_moves = ix->probe_mode == 2;
+    if (!clear_in_moves) QW_TRY(clear_counters(ix, s));
     // the staged kernel writes keys for the select kernel
     const bool stage = o.stage_split > 0;
     const int topk = !stage && o.topk_keep >= 0 ? plan.topk : 0;  // in-kernel top K
@@ -447,7 +459,7 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
     // takes the predictions from the inference kernel
     QW_TRY(front(ix, queries, Q, QW_FORM_FAST, s, ev,
                  learned && o.group ? w.feats.as<float>() : nullptr,
-                 o.group ? w.bmh.as<uint32_t>() : nullptr));
+                 o.group ? w.bmh.as<uint32_t>() : nullptr, clear_in_moves));
     if (ev) QW_HIP(hipEventRecord(ev[2], s));
     unsigned long long *seg = w.binoff.as<unsigned long long>();
     unsigned long long *ccount = c64(ix) + C_CLASS;

@@ -670,9 +670,14 @@ template <typename E, int KM, bool KEXACT>
 __global__ __launch_bounds__(kBlock) void probe_moves_kernel(
     const E *__restrict__ x, int64_t Q, int32_t dp, const double *__restrict__ a64l,
     const float *__restrict__ b, int32_t L, int32_t k, double w, int32_t T,
-    uint8_t *__restrict__ moves, int32_t *__restrict__ hout)
+    uint8_t *__restrict__ moves, int32_t *__restrict__ hout, uint32_t *__restrict__ clear,
+    int32_t nclear)
 {
 #pragma clang fp contract(off)
+    // the pipeline's counters, zeroed here instead of by a launch of their
+    // own (this kernel reads none of them; the kernels that do follow it)
+    if (clear && blockIdx.x == 0 && blockIdx.y == 0)
+        for (int32_t i = threadIdx.x; i < nclear; i += kBlock) clear[i] = 0u;
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int32_t l = blockIdx.y;
     const E *xr = x + (q < Q ? q : Q - 1) * dp;  // dp: a multiple of 16 elements, zero padded
@@ -745,14 +750,14 @@ __global__ __launch_bounds__(kBlock) void probe_moves_kernel(
 
 template <typename E>
 void launch_probe_moves_t(const qw_index *ix, const E *x, int64_t Q, uint8_t *moves, int32_t *hout,
-                          hipStream_t s)
+                          uint32_t *clear, int32_t nclear, hipStream_t s)
 {
     const dim3 g((unsigned)ceil_div(Q, kBlock), (unsigned)ix->L);
     const double *a = ix->a64l.as<double>();
     const float *b = ix->b32.as<float>();
     const int32_t T = ix->nprobe - 1;
     const double w = (double)ix->w;
-#define QW_PM(KM, EX) probe_moves_kernel<E, KM, EX><<<g, kBlock, 0, s>>>(x, Q, ix->dp, a, b, ix->L, ix->k, w, T, moves, hout)
+#define QW_PM(KM, EX) probe_moves_kernel<E, KM, EX><<<g, kBlock, 0, s>>>(x, Q, ix->dp, a, b, ix->L, ix->k, w, T, moves, hout, clear, nclear)
     switch (ix->k) {
     case 8: QW_PM(8, true); break;
     case 10: QW_PM(10, true); break;
@@ -767,14 +772,14 @@ void launch_probe_moves_t(const qw_index *ix, const E *x, int64_t Q, uint8_t *mo
 }
 
 qw_status launch_probe_moves(const qw_index *ix, const void *xpad, int64_t Q, uint8_t *moves,
-                             int32_t *hout, hipStream_t s)
+                             int32_t *hout, hipStream_t s, uint32_t *clear, int32_t nclear)
 {
-    if (Q <= 0) return QW_OK;
-    if (ix->k > kMaxK || ix->nprobe - 1 > 2 * ix->k || !ix->a64l.p) return QW_EINTERNAL;
+    if (Q <= 0) return clear ? launch_fill_u32(clear, 0u, nclear, s) : QW_OK;
+    if (ix->k > kMaxK || ix->nprobe - 1 > 2 * ix->k || !ix->a64l.p || nclear < 0) return QW_EINTERNAL;
     if (ix->dtype == QW_U8)
-        launch_probe_moves_t<uint8_t>(ix, (const uint8_t *)xpad, Q, moves, hout, s);
+        launch_probe_moves_t<uint8_t>(ix, (const uint8_t *)xpad, Q, moves, hout, clear, nclear, s);
     else
-        launch_probe_moves_t<float>(ix, (const float *)xpad, Q, moves, hout, s);
+        launch_probe_moves_t<float>(ix, (const float *)xpad, Q, moves, hout, clear, nclear, s);
     QW_HIP(hipGetLastError());
     return QW_OK;
 }

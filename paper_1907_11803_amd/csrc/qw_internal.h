@@ -314,9 +314,11 @@ qw_status launch_hash(const qw_index *ix, const void *xpad, int64_t m, int32_t f
 
 // Query-directed probing: each layer's T chosen moves [Q][L][T]
 // (T = nprobe - 1) from the FP64 projections of the query rows; hout
-// (nullable) receives their floors, the exact hash values [Q][L*k].
+// (nullable) receives their floors, the exact hash values [Q][L*k].  clear
+// (nullable): nclear words the kernel zeroes before any later kernel runs.
 qw_status launch_probe_moves(const qw_index *ix, const void *xpad, int64_t Q, uint8_t *moves,
-                             int32_t *hout, hipStream_t s);
+                             int32_t *hout, hipStream_t s, uint32_t *clear = nullptr,
+                             int32_t nclear = 0);
 
 // Probe every list of every query: bstart/bsize [Q][L][P] (bsize 0 = miss);
 // bmh (nullable) the bucket's min-hash; moves (query-directed probing) each
