@@ -526,9 +526,12 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
             (void)stage_lds_bytes(ix->dp * (ix->dtype == QW_U8 ? 1 : 4), o.stage_split, &a.icn, &a.dcn);
             return launch_stage(a, kStageBlocksPerCu * ix->cus, s);
         }
+        // gpart (global class only): 0 = the whole grid and scratch, 1 / 2 =
+        // the first / second half of them, so two global-class launches can
+        // run at once on disjoint sets
         auto launch_range = [&](int lo, int hi, const int32_t *in_list, const uint32_t *in_count,
                                 int32_t *ovf_list, uint32_t *ovf_count, int slot, int queue_only,
-                                hipStream_t st) -> qw_status {
+                                hipStream_t st, int gpart = 0) -> qw_status {
             DedupArgs a;
             std::memset(&a, 0, sizeof(a));
             a.order = order;
@@ -576,7 +579,10 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
                 a.cap_log2 = (uint32_t)plan.cap_g;
                 a.limit = (1u << plan.cap_g) / 4 * 3;
                 a.global_tab = 1;
-                a.gscratch = w.gscratch.as<uint32_t>();
+                const int half = plan.grid_g / 2;
+                a.gscratch = w.gscratch.as<uint32_t>() +
+                             (gpart == 2 ? (size_t)half << plan.cap_g : size_t(0));
+                if (gpart) return launch_dedup(a, gpart == 1 ? half : plan.grid_g - half, st);
             } else {
                 a.cap_log2 = (uint32_t)(kCmin + hi);  // LDS size; also the queue's class
                 a.limit = 0xFFFFFFFFu;                 // each set's own 3/4 bound
@@ -619,6 +625,11 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
         }
         const int merged = std::max(0, std::min(plan.cfloor - kCmin, plan.ncls - 2));
         const int glob = plan.ncls - 1;
+        // with two or more global-class workgroups, the side stream's global
+        // class and the merged launch's overflow each take half of them (and
+        // of their scratch sets), so the latter follows the merged launch on
+        // its own stream instead of waiting for the side stream first
+        const int gsplit = plan.grid_g >= 2 ? 1 : 0;
         QW_HIP(hipEventRecord(ix->fork[0], s));
         QW_HIP(hipStreamWaitEvent(ix->side, ix->fork[0], 0));
         for (int i = merged + 1; i < plan.ncls; ++i) {
@@ -626,15 +637,17 @@ qw_status enqueue_fast(qw_index *ix, const Plan &plan, const void *queries, int6
             QW_TRY(launch_range(i, i, first ? nullptr : queues + (int64_t)i * Q,
                                 first ? nullptr : c32(ix) + W_QCNT + i,
                                 queues + (int64_t)(i + 1) * Q, c32(ix) + W_QCNT + i + 1, i, 0,
-                                ix->side));
+                                ix->side, i == glob ? gsplit : 0));
         }
         QW_TRY(launch_range(0, merged, nullptr, nullptr, queues + (int64_t)kQueueMerged * Q,
                             c32(ix) + W_QMERGED, merged, 0, s));
         QW_HIP(hipEventRecord(ix->fork[1], ix->side));
-        QW_HIP(hipStreamWaitEvent(s, ix->fork[1], 0));
+        if (!gsplit) QW_HIP(hipStreamWaitEvent(s, ix->fork[1], 0));
         // overflow of the merged launch (usually none): the global class, queue only
         QW_TRY(launch_range(glob, glob, queues + (int64_t)kQueueMerged * Q, c32(ix) + W_QMERGED,
-                            queues + (int64_t)(glob + 1) * Q, c32(ix) + W_DUMMY, kMaxClasses, 1, s));
+                            queues + (int64_t)(glob + 1) * Q, c32(ix) + W_DUMMY, kMaxClasses, 1, s,
+                            gsplit ? 2 : 0));
+        if (gsplit) QW_HIP(hipStreamWaitEvent(s, ix->fork[1], 0));
         return QW_OK;
     };
     const int32_t *order = nullptr;

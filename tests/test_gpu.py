@@ -595,6 +595,38 @@ def test_learned_schedule_trains_and_keeps_results(cfg1):
     ixh.close()
 
 
+def test_global_memory_sets():
+    """Every one of 30,000 points a candidate of every query, more than the
+    largest on-chip set holds (3/4 of 2^15 slots): the workgroup kernel's
+    global-memory class answers them, both from its own segment (sizes from
+    the bucket-size bound) and from the overflow of the merged on-chip launch
+    (a count model that predicts no candidates); the wave kernel takes them in
+    id-hash passes."""
+    rng = np.random.default_rng(41)
+    n, d, Q, L, k = 30_000, 16, 40, 2, 2
+    data = rng.integers(0, 256, size=(n, d), dtype=np.uint8)
+    queries = rng.integers(0, 256, size=(Q, d), dtype=np.uint8)
+    a = synth.hash_params(42, L, k, d, 1e7).a
+    wh = 1e7
+    bh = np.full((L, k), wh / 2, dtype=np.float32)
+    ix = build(data, a, bh, wh)
+    ids_o, dist_o, cnt_o = oracle.lsh_query(data, queries, a, bh, wh, 10)
+    assert np.all(cnt_o == n)
+    q = dev(queries)
+    for dedup in (1, 2):
+        ids, dist, st = ix.query(q, 10, lib.make_opts(sched=lib.QW_SCHED_SUM, dedup=dedup),
+                                 stats=True)
+        check_topk(ids, dist, ids_o, dist_o, True)
+        assert st["cand_unique"] == n * Q
+    bad = np.zeros(lib.qw_mlp_param_count(L), np.float32)
+    bad[-1] = -5.0
+    ix.set_count_model(bad)
+    ids, dist, st = ix.query(q, 10, lib.make_opts(sched=lib.QW_SCHED_LEARNED, dedup=1), stats=True)
+    check_topk(ids, dist, ids_o, dist_o, True)
+    assert st["overflow"] >= Q
+    ix.close()
+
+
 # ---------------------------------------------------------------- errors
 
 def test_error_paths(cfg1):
