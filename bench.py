@@ -389,6 +389,14 @@ def main():
         cix = lib.Index(data_d, torch.from_numpy(cp.a).to(dev), torch.from_numpy(cp.b()).to(dev),
                         cw, form=lib.QW_FORM_FAST)
         cix.set_counting(theta, args.count_v)
+        # a plain device copy of known size (1 GiB read + 1 GiB written) to
+        # calibrate the HBM byte counters of a profiling run
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
         ms = timed(cix, lib.make_opts(form=lib.QW_FORM_FAST, graph=0), args.steps, args.warmup)
         log(f"[bench] profile counting: theta {theta}, v {args.count_v}, L {cL}, w {cw}: "
             f"{ms:.3f} ms/step")
@@ -637,6 +645,18 @@ def main():
                                 truth[1])
             ums = timed(cix, uopts, args.steps, args.warmup)
             cach = cbytes / (kms_c * 1e-3) / 1e9 if kms_c > 0 else None
+            # counted HBM bytes of the count kernels (both workgroup sizes), from
+            # two rocprofv3 passes of `bench.py --profile --profile-count`, while
+            # the kernel's sources are unchanged
+            from paper_1907_11803_amd.profsum import source_hash
+            ctraffic = None
+            csrc = ["qw_count.hip", "qw_dedup.h", "qw_dist.h", "qw_exact.h"]
+            ctfile = os.path.join(ROOT, "profiles", f"count_kernel_cfg{args.config}_64layers_traffic.json")
+            if os.path.exists(ctfile):
+                tj = json.load(open(ctfile))
+                if (tj.get("source") == source_hash(csrc) and
+                        abs(tj.get("w", -1) - cw) < 1e-9 and count_theta == 3 and args.count_v == 800):
+                    ctraffic = tj.get("bytes_per_launch")
             counting = {
                 "index": {"L": cL, "k": wl.params.k, "w": cw}, "theta": count_theta,
                 "v": args.count_v, "qps": round(wl.Q / (cms * 1e-3), 1),
@@ -647,7 +667,11 @@ def main():
                 "kernel": {"name": "count_kernel", "ms": round(kms_c, 4),
                            "algorithmic_bytes": int(cbytes),
                            "achieved_gbs": round(cach, 1) if cach else None,
-                           "frac": round(cach / HBM_PEAK_GBS, 4) if cach else None},
+                           "frac": round(cach / HBM_PEAK_GBS, 4) if cach else None,
+                           "traffic": ctraffic,
+                           "traffic_frac": (round(ctraffic / (kms_c * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                            if ctraffic and kms_c > 0 else None),
+                           "traffic_file": os.path.relpath(ctfile, ROOT)},
                 "union_same_index": {"qps": round(wl.Q / (ums * 1e-3), 1),
                                      "recall_at_10": round(urec, 4),
                                      "unique_per_query": ust["cand_unique"] / wl.Q,
