@@ -47,10 +47,13 @@ def check_oracle(ids, dist, ids_o, dist_o, is_u8):
         assert np.array_equal(d[fin], dist_o[fin].astype(np.float32))
 
 
-@pytest.mark.parametrize("case", ["u8", "u8_probing", "f32_padded", "u8_counting"])
+@pytest.mark.parametrize("case", ["u8", "u8_probing", "f32_padded", "u8_counting",
+                                  "u8_counting_both_sizes"])
 def test_noalloc_matches_query_workload_twice(case):
     if case == "f32_padded":  # d = 100: rows are padded into the scratch
         wl = synth.random_small(71, n=3000, d=100, Q=90, L=8, k=6, w=2.0, dtype="f32")
+    elif case == "u8_counting_both_sizes":  # listed totals on both sides of 6,144
+        wl = synth.make_config(1, L=32, k=1, w=55.0)
     else:
         wl = synth.make_config(1, w=1200.0)
     p = wl.params
@@ -60,7 +63,7 @@ def test_noalloc_matches_query_workload_twice(case):
     if case == "u8_probing":
         ix.set_probing(2, 3)
         probes, probe_t = 2, 3
-    if case == "u8_counting":
+    if case.startswith("u8_counting"):
         ix.set_counting(2, 40)
     K = wl.K
     # two calls in a row, the second with fewer queries: the scratch keeps the
@@ -70,7 +73,7 @@ def test_noalloc_matches_query_workload_twice(case):
         ids, dist = noalloc(ix, q, K, is_u8)
         ids_p, dist_p = plain(ix, q, K)
         assert torch.equal(ids, ids_p) and torch.equal(dist, dist_p)
-        if case == "u8_counting":
+        if case.startswith("u8_counting"):
             ids_o, dist_o, _ = oracle.lsh_query_counting(wl.data, wl.queries[rows], p.a, p.b(),
                                                          p.w, K, 2, 40)
         else:
