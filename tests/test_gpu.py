@@ -102,15 +102,16 @@ def test_hash_several_k_chunks(form, dtype, d):
 
 @pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("L,k,d,wb", [(19, 7, 40, 4.0), (20, 8, 128, 4.0), (64, 2, 24, 4.0),
-                                      (32, 8, 24, 2.0)])
+                                      (32, 8, 24, 2.0), (20, 8, 300, 4.0)])
 def test_hash_many_rows_several_function_tiles(form, L, k, d, wb):
     """Enough rows that the FP16 matrix-core kernel gives each workgroup several
     64-function tiles of its rows (ragged last row block; 133, 160, 128 and 256
     functions per row: a ragged last tile, and row pitches that are and are
-    not a multiple of four values).  Parameters on bucket boundaries, so some
-    outputs take the FP64 recomputation in every tile; at w = 2 about half of
-    a workgroup's 16,384 outputs do, more than its pooled recomputes hold, so
-    each lane recomputes its own."""
+    not a multiple of four values; d = 300 takes three staged chunks per
+    tile).  Parameters on bucket boundaries, so some outputs take the FP64
+    recomputation in every tile; at w = 2 about half of a workgroup's 16,384
+    outputs do, more than its pooled recomputes hold, so each lane
+    recomputes its own."""
     a, b, w = synth.boundary_params(31, L, k, d, w=wb)
     rng = np.random.default_rng(32)
     x = rng.integers(0, 256, size=(100_003, d), dtype=np.uint8)
